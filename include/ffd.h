@@ -1,0 +1,161 @@
+/*
+ * ffd.h -- C ABI of the MI355X (gfx950) discrete Frechet distance library.
+ *
+ * The library computes the discrete Frechet distance of Eiter and Mannila
+ * between polygonal curves p in R^{P x D} and q in R^{Q x D} (Meinert,
+ * "Walking Your Frog Fast in 4 LoC", arXiv 2404.05708, Sec. 2), i.e. M_PQ of
+ * the recurrence of Eq. (1)
+ *
+ *     M_ij = max{ min{ M_{i-1,j}, M_{i-1,j-1}, M_{i,j-1} }, d_ij },
+ *
+ * with the first row and column given by running maxima (Algorithms 3-5).
+ * It evaluates d_ij lazily, keeps O(Q) state per pair (Theorem 1) and never
+ * branches per cell.  Ground distances: Euclidean ||p_i - q_j||_2 and squared
+ * Euclidean (Sec. 4 names the Euclidean distance; Sec. 3 notes that the
+ * method makes no assumption about the metric).
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - Curves are row-major arrays of points: point i of a D-dimensional curve
+ *    is x[i*D .. i*D+D).  Indices in this header are 0-based.
+ *  - Coordinate, output and workspace pointers are DEVICE pointers (memory of
+ *    the context's GPU); offset arrays are HOST pointers (the host plans the
+ *    work from them).  The caller owns all of them; the library never frees
+ *    or keeps a caller pointer beyond the completion of the call's work on
+ *    `stream`, except an ffd_db, which refers to its database until
+ *    ffd_db_destroy.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous: results are valid once the stream has completed.
+ *  - Return value: FFD_OK or a negative FFD_E_* status.  All argument checks
+ *    happen on the host before anything is launched; a failed call launches
+ *    nothing and leaves the outputs untouched.  Device faults surface as
+ *    FFD_E_DEVICE from a later call that synchronises.
+ *  - Preconditions (documented, not checked): coordinates are finite; float
+ *    coordinates satisfy |x| < 1e18 so that squares do not overflow; int32
+ *    coordinates satisfy |x| < 2^24 so that every intermediate is exact.
+ *  - Float32 results agree with the exact real-number result to a relative
+ *    error of 2e-6 (each d_ij is evaluated in float32 in a fixed order; the
+ *    recurrence only selects values; the square root is taken once per pair
+ *    and correctly rounded).  Int32 results are exact.
+ *  - A context may be used by one host thread at a time.
+ */
+#ifndef FFD_H
+#define FFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FFD_OK 0
+#define FFD_E_INVALID (-1)     /* bad argument (NULL, empty curve, bad offsets ...) */
+#define FFD_E_UNSUPPORTED (-2) /* valid request outside what this build supports   */
+#define FFD_E_NOMEM (-3)       /* workspace or arena too small                      */
+#define FFD_E_DEVICE (-4)      /* HIP runtime error                                 */
+#define FFD_E_BUSY (-5)        /* serving: no free slot right now                   */
+#define FFD_E_TIMEOUT (-6)     /* serving: wait timed out                           */
+
+/* Ground distances (Sec. 2: f(p_i, q_j)). */
+#define FFD_EUCLIDEAN 0   /* ||p_i - q_j||_2                          */
+#define FFD_SQEUCLIDEAN 1 /* ||p_i - q_j||_2^2 (the only int metric)  */
+
+/* Largest supported dimension D. */
+#define FFD_MAX_DIM 4
+
+/* Operation codes for ffd_workspace_size. */
+#define FFD_OP_BATCH 0
+#define FFD_OP_CROSS 1
+
+typedef struct ffd_ctx ffd_ctx;
+
+/* Create a context on HIP device `device`.  The context owns host-side plans
+ * and launch settings only; it allocates no device memory.
+ * Errors: FFD_E_INVALID (out == NULL), FFD_E_DEVICE (no such device or the
+ * device is not gfx950). */
+int ffd_create(int device, ffd_ctx **out);
+void ffd_destroy(ffd_ctx *ctx);
+
+/* Create a planning-only context without a device, describing a GPU with
+ * `compute_units` CUs and `lds_per_block` bytes of LDS per workgroup.  It
+ * checks arguments and sizes workspaces exactly like a device context; every
+ * call that would launch work returns FFD_E_DEVICE after its checks pass.
+ * Errors: FFD_E_INVALID (out == NULL, compute_units < 1, lds_per_block <
+ * 16384). */
+int ffd_create_planner(int32_t compute_units, int64_t lds_per_block, ffd_ctx **out);
+
+/* Static text for a status code. */
+const char *ffd_strerror(int status);
+/* Text of the last error reported on this context ("" if none). */
+const char *ffd_last_error(const ffd_ctx *ctx);
+/* Library version string. */
+const char *ffd_version(void);
+
+/* One pair (Eq. (1), result M_PQ; Algorithm 5 / Algorithm 2 form).
+ *   p   [n * dim] float32, device;  q [m * dim] float32, device;
+ *   out [1] float32, device: delta_dF(p, q) under `metric`.
+ * Errors: FFD_E_INVALID for NULL pointers, n < 1, m < 1, dim < 1 or an
+ * unknown metric; FFD_E_UNSUPPORTED for dim > FFD_MAX_DIM. */
+int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
+                 int32_t dim, int32_t metric, float *out, void *stream);
+
+/* One pair with int32 coordinates and the squared Euclidean distance, exact:
+ *   out [1] int64, device.  metric must be FFD_SQEUCLIDEAN (else
+ *   FFD_E_UNSUPPORTED).  Other errors as ffd_distance. */
+int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m,
+                     int32_t dim, int32_t metric, int64_t *out, void *stream);
+
+/* Many independent pairs in one launch (Sec. 4: batches of curves; here
+ * each pair has its own lengths).
+ *   Pair k is (P[p_off[k] .. p_off[k+1]), Q[q_off[k] .. q_off[k+1])), offsets
+ *   in points, HOST int64 arrays of npairs + 1 entries starting at 0 and
+ *   strictly increasing (every curve has at least one point).
+ *   P, Q: device float32 coordinates; out [npairs] float32, device.
+ *   workspace: device memory of ws_bytes >= ffd_workspace_size(FFD_OP_BATCH).
+ *   Contents of the workspace are overwritten; it may be reused across calls
+ *   once the previous call on it has completed.
+ * npairs == 0 is a no-op.  Errors: FFD_E_INVALID (bad offsets, NULL, metric),
+ * FFD_E_UNSUPPORTED (dim), FFD_E_NOMEM (workspace too small). */
+int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q,
+              const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, float *out,
+              void *workspace, size_t ws_bytes, void *stream);
+
+/* Int32 version of ffd_batch: squared Euclidean, exact int64 out[npairs]. */
+int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
+                  const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric,
+                  int64_t *out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Query set x database set (Sec. 4: a batch of curves against a reference
+ * curve, generalised to many references):
+ *   out[i * ndb + k] = delta_dF(query i, database curve k), row-major,
+ *   out [nq * ndb] float32 device.  q_off [nq + 1] and db_off [ndb + 1] are
+ *   HOST offsets as in ffd_batch.  Errors as ffd_batch. */
+int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq,
+              const float *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
+              int32_t metric, float *out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Int32 version of ffd_cross: squared Euclidean, exact int64 out[nq * ndb]. */
+int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq,
+                  const int32_t *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
+                  int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
+                  void *stream);
+
+/* Device workspace needed by ffd_batch (op = FFD_OP_BATCH: a_off = p_off,
+ * na = npairs, b_off = q_off, nb = npairs) or ffd_cross (op = FFD_OP_CROSS:
+ * a_off = q_off, na = nq, b_off = db_off, nb = ndb).  Writes *bytes.
+ * Errors: FFD_E_INVALID for a bad op, NULL or bad offsets. */
+int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
+                       const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);
+
+/* Tuning knobs (0 = automatic).  rows_per_lane in {1, 2, 4, 8}: points of the
+ * row curve each GPU lane holds; waves_per_simd: resident waves per SIMD the
+ * batch planner targets.  Returns FFD_E_INVALID for values out of range. */
+int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFD_H */

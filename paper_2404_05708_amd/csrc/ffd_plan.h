@@ -1,0 +1,97 @@
+// Work description shared by the host planner (ffd_host.cpp) and the
+// kernels (ffd_kernels.hip).  Internal to the library.
+//
+// Execution model.  One wavefront (64 lanes) runs one "stream".  Lane l
+// holds R consecutive points (rows) of a row curve and, at step t, updates
+// column t - l of the recurrence of Eq. (1), so the 64 lanes sweep an
+// anti-diagonal wavefront.  Columns arrive as a stream: every task (one
+// band of 64*R rows against one column curve) contributes a separator
+// column followed by the column curve's points, so the lanes move from one
+// task to the next without draining.  A wave runs the tasks of its jobs back
+// to back; a job is one row curve against a contiguous range of column
+// curves, every column curve in turn, every band of the row curve in turn.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define FFD_HD inline
+#else
+#define FFD_HD __host__ __device__ inline
+#endif
+
+namespace ffd {
+
+constexpr int kWave = 64;            // lanes per wavefront
+constexpr int kGroup = 8;            // steps per unrolled group; task lengths are multiples
+constexpr int kRing = 256;           // column ring entries per wave (power of two)
+constexpr int kFill = 64;            // steps between ring refills (= one entry per lane)
+constexpr int kMinTask = 64;         // shortest task stream
+constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
+constexpr int kDescSlots = 8;        // task descriptors in flight per wave
+
+struct Job {           // 32 bytes, device-resident plan entry
+  int64_t out_base;    // output index of the first column curve of the job
+  int32_t row_sel;     // which coordinate array holds the row curve (0 or 1)
+  int32_t row_idx;     // index of the row curve in that array's offsets
+  int32_t col_sel;     // which array holds the column curves
+  int32_t col_first;   // first column curve
+  int32_t col_count;   // number of column curves
+  int32_t out_stride;  // output index step between consecutive column curves
+};
+
+// Bands of 64*R rows needed for a row curve of n points.
+FFD_HD int64_t bands_for(int64_t n, int R) { return (n + (int64_t)kWave * R - 1) / ((int64_t)kWave * R); }
+
+// Stream length of one task: separator + m columns, padded by repeating the
+// last column point up to the minimum length and to a multiple of kGroup.
+FFD_HD int64_t task_len(int64_t m, bool chained) {
+  int64_t L = 1 + m;
+  int64_t lo = chained ? kMinTaskChained : kMinTask;
+  if (L < lo) L = lo;
+  return (L + kGroup - 1) / kGroup * kGroup;
+}
+
+// LDS carve-up of one wave's region (byte offsets).  vsize is the byte size
+// of the value type (4: float32 path, 8: exact path with FP64 values).
+struct LdsLayout {
+  int ring;   // (kRing + kGroup) column points; the last kGroup mirror the first
+  int ghost;  // kGroup + 1 values: -inf, +inf, ... (top boundary of a first band)
+  int sink;   // kGroup values written when a band hands nothing on
+  int hand;   // hcap values: bottom row of the band above
+  int pst;    // two slots of 64 * R * D row coordinates (next task's rows)
+  int desc;   // kDescSlots task descriptors of 32 bytes
+  int total;
+};
+
+FFD_HD int align16(int x) { return (x + 15) & ~15; }
+FFD_HD int pad_dim(int D) { return D == 3 ? 4 : D; }
+
+FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
+  LdsLayout L;
+  int o = 0;
+  L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
+  L.ghost = o; o += (kGroup + 1) * vsize;
+  L.sink = o;  o += kGroup * vsize;
+  o = align16(o); L.hand = o; o += hcap * vsize;
+  o = align16(o); L.pst = o;  o += 2 * kWave * R * D * vsize;
+  o = align16(o); L.desc = o; o += kDescSlots * 32;
+  L.total = align16(o);
+  return L;
+}
+
+struct KernelArgs {
+  const void *X[2];          // coordinate arrays, device (float32 or int32)
+  const int64_t *off[2];     // curve offsets in points, device; unused in single-pair mode
+  const Job *jobs;           // device plan; nullptr = single-pair mode (inline below)
+  const int32_t *wave_jobs;  // [nwaves + 1]: jobs of wave w are [wave_jobs[w], wave_jobs[w+1])
+  void *out;                 // float32 or int64 results, device
+  int64_t inl_off[2][2];     // single-pair mode: curve 0 of each array is [off[s][0], off[s][1])
+  Job inl_job;               // single-pair mode job
+  int32_t nwaves;
+  int32_t metric;            // 0 Euclidean, 1 squared
+  int32_t hcap;              // hand-off row entries per wave (max chained task length)
+  int32_t lds_per_wave;      // bytes of LDS per wave
+  int32_t max_steps;         // upper bound of any wave's stream length (loop guard)
+};
+
+}  // namespace ffd

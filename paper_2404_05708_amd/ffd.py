@@ -1,0 +1,291 @@
+"""Thin Python binding of the C ABI in include/ffd.h (argument marshalling only).
+
+Every computation happens in the HIP library ``libffd.so``; this module only
+turns torch tensors (device memory, streams) and host offset arrays into the
+pointers the C functions take.  If the library is not built, importing the
+binding raises: there is no fallback path.
+
+Functions keep the C names: ``ffd_distance``, ``ffd_distance_i32``,
+``ffd_batch``, ``ffd_batch_i32``, ``ffd_cross``, ``ffd_cross_i32``,
+``ffd_workspace_size``, ``ffd_set_tuning``, ``ffd_create``,
+``ffd_destroy``.  ``Context`` is a small convenience wrapper around them.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffd.so")
+
+FFD_OK = 0
+FFD_E_INVALID = -1
+FFD_E_UNSUPPORTED = -2
+FFD_E_NOMEM = -3
+FFD_E_DEVICE = -4
+FFD_E_BUSY = -5
+FFD_E_TIMEOUT = -6
+FFD_EUCLIDEAN = 0
+FFD_SQEUCLIDEAN = 1
+FFD_OP_BATCH = 0
+FFD_OP_CROSS = 1
+FFD_MAX_DIM = 4
+
+EXPORTS = (
+    "ffd_create", "ffd_create_planner", "ffd_destroy", "ffd_strerror", "ffd_last_error", "ffd_version",
+    "ffd_distance", "ffd_distance_i32", "ffd_batch", "ffd_batch_i32", "ffd_cross",
+    "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning",
+)
+
+
+class FFDError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    sz = ctypes.c_size_t
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.ffd_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.ffd_create.restype = ctypes.c_int
+    lib.ffd_create_planner.argtypes = [i32, i64, ctypes.POINTER(vp)]
+    lib.ffd_create_planner.restype = ctypes.c_int
+    lib.ffd_destroy.argtypes = [vp]
+    lib.ffd_destroy.restype = None
+    lib.ffd_strerror.argtypes = [ctypes.c_int]
+    lib.ffd_strerror.restype = ctypes.c_char_p
+    lib.ffd_last_error.argtypes = [vp]
+    lib.ffd_last_error.restype = ctypes.c_char_p
+    lib.ffd_version.argtypes = []
+    lib.ffd_version.restype = ctypes.c_char_p
+    for name in ("ffd_distance", "ffd_distance_i32"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp, vp]
+        fn.restype = ctypes.c_int
+    for name in ("ffd_batch", "ffd_batch_i32"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, vp, vp, sz, vp]
+        fn.restype = ctypes.c_int
+    for name in ("ffd_cross", "ffd_cross_i32"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, vp, vp, sz, vp]
+        fn.restype = ctypes.c_int
+    lib.ffd_workspace_size.argtypes = [vp, i32, i64p, i64, i64p, i64, i32, ctypes.POINTER(sz)]
+    lib.ffd_workspace_size.restype = ctypes.c_int
+    lib.ffd_set_tuning.argtypes = [vp, i32, i32]
+    lib.ffd_set_tuning.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, ctx=None):
+    if rc != FFD_OK:
+        msg = lib.ffd_strerror(rc).decode()
+        if ctx:
+            detail = lib.ffd_last_error(ctx).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise FFDError(rc, msg)
+
+
+def _dev_ptr(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _curve(t, dtype, name):
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must have shape (points, dim)")
+    return t, _dev_ptr(t, dtype, name)
+
+
+def _offsets(off):
+    a = off.detach().cpu().numpy() if isinstance(off, torch.Tensor) else np.asarray(off)
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def ffd_version():
+    return lib.ffd_version().decode()
+
+
+def ffd_create(device=0):
+    h = ctypes.c_void_p()
+    _check(lib.ffd_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def ffd_create_planner(compute_units=256, lds_per_block=160 * 1024):
+    h = ctypes.c_void_p()
+    _check(lib.ffd_create_planner(int(compute_units), int(lds_per_block), ctypes.byref(h)))
+    return h
+
+
+def ffd_destroy(ctx):
+    lib.ffd_destroy(ctx)
+
+
+def ffd_set_tuning(ctx, rows_per_lane=0, waves_per_simd=0):
+    _check(lib.ffd_set_tuning(ctx, int(rows_per_lane), int(waves_per_simd)), ctx)
+
+
+def ffd_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
+    p, pp = _curve(p, torch.float32, "p")
+    q, qp = _curve(q, torch.float32, "q")
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("p and q must have the same dimension")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device=p.device)
+    _check(lib.ffd_distance(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
+                            _dev_ptr(out, torch.float32, "out"), _stream(stream)), ctx)
+    return out
+
+
+def ffd_distance_i32(ctx, p, q, metric=FFD_SQEUCLIDEAN, out=None, stream=None):
+    p, pp = _curve(p, torch.int32, "p")
+    q, qp = _curve(q, torch.int32, "q")
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("p and q must have the same dimension")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=p.device)
+    _check(lib.ffd_distance_i32(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
+                                _dev_ptr(out, torch.int64, "out"), _stream(stream)), ctx)
+    return out
+
+
+def ffd_workspace_size(ctx, op, a_off, b_off, dim):
+    a, ap = _offsets(a_off)
+    b, bp = _offsets(b_off)
+    n = ctypes.c_size_t()
+    _check(lib.ffd_workspace_size(ctx, int(op), ap, len(a) - 1, bp, len(b) - 1, int(dim),
+                                  ctypes.byref(n)), ctx)
+    return n.value
+
+
+def _workspace(ctx, op, a_off, b_off, dim, device, workspace):
+    if workspace is None:
+        nbytes = ffd_workspace_size(ctx, op, a_off, b_off, dim)
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+    return workspace, ctypes.c_void_p(workspace.data_ptr()), workspace.numel()
+
+
+def _batch(fn, dtype, odtype, ctx, P, p_off, Q, q_off, metric, out, workspace, stream):
+    P, Pp = _curve(P, dtype, "P")
+    Q, Qp = _curve(Q, dtype, "Q")
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    po, pop = _offsets(p_off)
+    qo, qop = _offsets(q_off)
+    npairs = len(po) - 1
+    if len(qo) - 1 != npairs:
+        raise ValueError("p_off and q_off must describe the same number of pairs")
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=odtype, device=P.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
+    _check(fn(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
+              _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)), ctx)
+    return out[:npairs]
+
+
+def ffd_batch(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, workspace=None, stream=None):
+    return _batch(lib.ffd_batch, torch.float32, torch.float32, ctx, P, p_off, Q, q_off, metric,
+                  out, workspace, stream)
+
+
+def ffd_batch_i32(ctx, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
+                  stream=None):
+    return _batch(lib.ffd_batch_i32, torch.int32, torch.int64, ctx, P, p_off, Q, q_off, metric,
+                  out, workspace, stream)
+
+
+def _cross(fn, dtype, odtype, ctx, Qs, q_off, DB, db_off, metric, out, workspace, stream):
+    Qs, Qp = _curve(Qs, dtype, "Qs")
+    DB, Dp = _curve(DB, dtype, "DB")
+    if Qs.shape[1] != DB.shape[1]:
+        raise ValueError("Qs and DB must have the same dimension")
+    qo, qop = _offsets(q_off)
+    do, dop = _offsets(db_off)
+    nq, ndb = len(qo) - 1, len(do) - 1
+    if out is None:
+        out = torch.empty(max(nq * ndb, 1), dtype=odtype, device=Qs.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
+    _check(fn(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
+              _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)), ctx)
+    return out[:nq * ndb].reshape(nq, ndb)
+
+
+def ffd_cross(ctx, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, out=None, workspace=None,
+              stream=None):
+    return _cross(lib.ffd_cross, torch.float32, torch.float32, ctx, Qs, q_off, DB, db_off, metric,
+                  out, workspace, stream)
+
+
+def ffd_cross_i32(ctx, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
+                  stream=None):
+    return _cross(lib.ffd_cross_i32, torch.int32, torch.int64, ctx, Qs, q_off, DB, db_off, metric,
+                  out, workspace, stream)
+
+
+class Context:
+    """Owns one ffd_ctx; methods call the functions above."""
+
+    def __init__(self, device=0):
+        self.device = device
+        self.handle = ffd_create(device)
+
+    def close(self):
+        if self.handle:
+            ffd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, rows_per_lane=0, waves_per_simd=0):
+        ffd_set_tuning(self.handle, rows_per_lane, waves_per_simd)
+
+    def distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_distance(self.handle, p, q, metric, **kw)
+
+    def distance_i32(self, p, q, **kw):
+        return ffd_distance_i32(self.handle, p, q, FFD_SQEUCLIDEAN, **kw)
+
+    def batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
+
+    def batch_i32(self, P, p_off, Q, q_off, **kw):
+        return ffd_batch_i32(self.handle, P, p_off, Q, q_off, FFD_SQEUCLIDEAN, **kw)
+
+    def cross(self, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_cross(self.handle, Qs, q_off, DB, db_off, metric, **kw)
+
+    def cross_i32(self, Qs, q_off, DB, db_off, **kw):
+        return ffd_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
+
+    def workspace_size(self, op, a_off, b_off, dim):
+        return ffd_workspace_size(self.handle, op, a_off, b_off, dim)

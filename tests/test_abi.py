@@ -1,0 +1,138 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/ffd.h declares, and a planning-only context validates arguments and
+sizes workspaces."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_05708_amd import ffd
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ffd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_functions()
+    assert "ffd_distance" in names and "ffd_batch" in names and "ffd_cross" in names
+    lib = ctypes.CDLL(ffd.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(ffd.EXPORTS)
+
+
+def test_version_and_status_text():
+    assert "gfx950" in ffd.ffd_version()
+    assert ffd.lib.ffd_strerror(ffd.FFD_E_INVALID).decode() == "invalid argument"
+    assert ffd.lib.ffd_strerror(12345).decode() == "unknown status"
+
+
+def test_create_without_gpu_reports_device_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except ImportError:
+        pass
+    h = ctypes.c_void_p()
+    assert ffd.lib.ffd_create(0, ctypes.byref(h)) == ffd.FFD_E_DEVICE
+    assert ffd.lib.ffd_create(0, None) == ffd.FFD_E_INVALID
+
+
+@pytest.fixture
+def planner():
+    h = ffd.ffd_create_planner(256, 160 * 1024)
+    yield h
+    ffd.ffd_destroy(h)
+
+
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail or the planner stops first
+
+
+def test_planner_create_validation():
+    h = ctypes.c_void_p()
+    assert ffd.lib.ffd_create_planner(0, 65536, ctypes.byref(h)) == ffd.FFD_E_INVALID
+    assert ffd.lib.ffd_create_planner(256, 1024, ctypes.byref(h)) == ffd.FFD_E_INVALID
+    assert ffd.lib.ffd_create_planner(256, 65536, None) == ffd.FFD_E_INVALID
+
+
+def test_distance_argument_checks(planner):
+    L = ffd.lib
+    ok = L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, 0, FAKE, None)
+    assert ok == ffd.FFD_E_DEVICE  # checks pass, then the planner refuses to launch
+    assert L.ffd_distance(planner, None, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 0, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, -1, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 0, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, 9, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 5, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_distance(None, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    # int32 coordinates: squared Euclidean only
+    assert L.ffd_distance_i32(planner, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_distance_i32(planner, FAKE, 5, FAKE, 7, 2, 1, FAKE, None) == ffd.FFD_E_DEVICE
+    assert "planning-only" in L.ffd_last_error(planner).decode()
+
+
+def test_batch_argument_checks(planner):
+    L = ffd.lib
+    good = np.array([0, 3, 5, 9], dtype=np.int64)
+    empty = np.array([0, 3, 3, 9], dtype=np.int64)
+    shifted = np.array([1, 3, 5, 9], dtype=np.int64)
+    ws = 1 << 20
+    args = lambda po, qo, n=3, metric=0, dim=2, out=FAKE, wsb=ws: L.ffd_batch(
+        planner, FAKE, _i64p(po), FAKE, _i64p(qo), n, dim, metric, out, FAKE, wsb, None)
+    assert args(good, good) == ffd.FFD_E_DEVICE
+    assert args(good, empty) == ffd.FFD_E_INVALID
+    assert args(shifted, good) == ffd.FFD_E_INVALID
+    assert args(good, good, metric=3) == ffd.FFD_E_INVALID
+    assert args(good, good, dim=9) == ffd.FFD_E_UNSUPPORTED
+    assert args(good, good, out=None) == ffd.FFD_E_INVALID
+    assert args(good, good, n=-1) == ffd.FFD_E_INVALID
+    assert args(good, good, n=0) == ffd.FFD_OK  # no-op
+    assert L.ffd_batch(planner, FAKE, None, FAKE, _i64p(good), 3, 2, 0, FAKE, FAKE, ws, None) == ffd.FFD_E_INVALID
+
+
+def test_cross_argument_checks(planner):
+    L = ffd.lib
+    qo = np.array([0, 4, 9], dtype=np.int64)
+    do = np.array([0, 2, 3, 8], dtype=np.int64)
+    bad = np.array([0, 2, 1, 8], dtype=np.int64)
+    assert L.ffd_cross(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(do), 3, 2, 0, FAKE, FAKE, 1 << 20, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_cross(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(bad), 3, 2, 0, FAKE, FAKE, 1 << 20, None) == ffd.FFD_E_INVALID
+    assert L.ffd_cross_i32(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(do), 3, 2, 0, FAKE, FAKE, 1 << 20, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_cross(planner, FAKE, _i64p(qo), 0, FAKE, _i64p(do), 3, 2, 0, FAKE, FAKE, 0, None) == ffd.FFD_OK
+
+
+def test_workspace_size_and_too_small_workspace(planner):
+    P, p_off, Q, q_off = workloads.random_pairs(3, 500, 1, 3000, dim=2)
+    need = ffd.ffd_workspace_size(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2)
+    # at least the plan entries and both offset arrays
+    assert need >= 500 * 32 + 2 * 501 * 8
+    L = ffd.lib
+    r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, need - 1, None)
+    assert r == ffd.FFD_E_DEVICE  # planner stops before the workspace check is reached on a device
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_workspace_size(planner, 7, p_off, q_off, 2)
+    Qs, qo, DB, do = workloads.cross_int(seed=1, nq=8, ndb=40, length=30)
+    assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_CROSS, qo, do, 2) > 0
+
+
+def test_set_tuning_validation(planner):
+    ffd.ffd_set_tuning(planner, 4, 2)
+    ffd.ffd_set_tuning(planner, 0, 0)
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_set_tuning(planner, 3, 1)
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_set_tuning(planner, 4, 99)

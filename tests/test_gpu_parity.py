@@ -1,0 +1,232 @@
+"""GPU parity: the HIP library through the C ABI against the CPU oracle.
+
+Bars: float32 results within a relative error of 2e-6 of the FP64 oracle
+(exactly 0 where the oracle is 0); int32 results bit-exact.  Where the
+float32 evaluation order is fixed (d2 = dx*dx, then fma(dk, dk, d2)), the GPU
+must also reproduce the float replica bit for bit: the recurrence only
+selects values, so any disagreement would mean a wrong cell was selected.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 2e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2404_05708_amd import ffd
+    c = ffd.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def rel_ok(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    return np.all(np.abs(got - want) <= TOL * np.abs(want))
+
+
+def test_dpp_lane_shift_semantics(ctx):
+    """A 64-lane single band exercises the wave-wide lane shift: rows of every
+    lane must see the row above, so any wrong neighbour changes the value."""
+    say("case: dpp shift, n=64*4, R=4")
+    rng = np.random.default_rng(5)
+    p = workloads.walk(rng, 256, 2)
+    q = workloads.walk(rng, 300, 2)
+    ctx.set_tuning(4, 0)
+    got = ctx.distance(dev(p), dev(q)).item()
+    ctx.set_tuning(0, 0)
+    assert got == oracle.dfd_f32_replica(p, q)
+
+
+def test_plain_pair_workload(ctx):
+    say("case: plain pair 512 x 384")
+    g = json.load(open(os.path.join(HERE, "golden", "expected.json")))["plain_pair"]
+    p, q = workloads.plain_pair()
+    got = ctx.distance(dev(p), dev(q)).item()
+    assert rel_ok(got, g["euclidean"])
+    assert got == oracle.dfd_f32_replica(p, q)
+    got_sq = ctx.distance(dev(p), dev(q), metric=1).item()
+    assert rel_ok(got_sq, g["sqeuclidean"])
+    assert got_sq == oracle.dfd_f32_replica(p, q, 1)
+
+
+@pytest.mark.parametrize("R", [0, 1, 2, 4, 8])
+def test_random_shapes_all_dims(ctx, R):
+    rng = np.random.default_rng(100 + R)
+    ctx.set_tuning(R, 0)
+    try:
+        for it in range(24):
+            D = int(rng.integers(1, 5))
+            n = int(rng.integers(1, 700))
+            m = int(rng.integers(1, 700))
+            metric = int(rng.integers(0, 2))
+            say(f"case: random R={R} it={it} n={n} m={m} D={D} metric={metric}")
+            p = workloads.walk(rng, n, D)
+            q = workloads.walk(rng, m, D)
+            got = ctx.distance(dev(p), dev(q), metric=metric).item()
+            assert got == oracle.dfd_f32_replica(p, q, metric), (n, m, D, metric)
+            assert rel_ok(got, oracle.dfd(p, q, metric, "rolling"))
+    finally:
+        ctx.set_tuning(0, 0)
+
+
+def test_edge_cases(ctx):
+    rng = np.random.default_rng(9)
+    for n, m in [(1, 1), (1, 5), (5, 1), (1, 700), (700, 1), (2, 2), (63, 65), (64, 64), (65, 63),
+                 (257, 3), (3, 1025)]:
+        say(f"case: edge n={n} m={m}")
+        p = workloads.walk(rng, n, 2)
+        q = workloads.walk(rng, m, 2)
+        got = ctx.distance(dev(p), dev(q)).item()
+        assert got == oracle.dfd_f32_replica(p, q)
+        assert rel_ok(got, oracle.dfd(p, q))
+    say("case: identical curves")
+    p = workloads.walk(rng, 333, 3)
+    assert ctx.distance(dev(p), dev(p)).item() == 0.0
+    say("case: translated copy")
+    q = workloads.paper_walk(rng, 200, 2)
+    assert ctx.distance(dev(q + np.float32([3, 4])), dev(q)).item() == 5.0
+
+
+def test_invariances_bit_exact(ctx):
+    rng = np.random.default_rng(10)
+    for it in range(6):
+        n, m = int(rng.integers(1, 900)), int(rng.integers(1, 900))
+        say(f"case: invariances n={n} m={m}")
+        p = workloads.walk(rng, n, 2)
+        q = workloads.walk(rng, m, 2)
+        d = ctx.distance(dev(p), dev(q)).item()
+        assert ctx.distance(dev(q), dev(p)).item() == d
+        assert ctx.distance(dev(p[::-1].copy()), dev(q[::-1].copy())).item() == d
+        pad = np.concatenate([p, np.repeat(p[-1:], 37, axis=0)])
+        assert ctx.distance(dev(pad), dev(q)).item() == d
+
+
+def test_paper_walks_are_bit_exact(ctx):
+    """{-1,0,1} walks: every float32 squared distance is an exact integer, so
+    the GPU result is the float32 rounding of the FP64 oracle."""
+    rng = np.random.default_rng(11)
+    for it in range(6):
+        n, m = int(rng.integers(1, 1024)), int(rng.integers(1, 1024))
+        say(f"case: paper walk n={n} m={m}")
+        p = workloads.paper_walk(rng, n)
+        q = workloads.paper_walk(rng, m)
+        assert ctx.distance(dev(p), dev(q)).item() == np.float32(oracle.dfd(p, q))
+
+
+def test_int_pairs_exact(ctx):
+    rng = np.random.default_rng(12)
+    for it in range(12):
+        D = int(rng.integers(1, 5))
+        n, m = int(rng.integers(1, 600)), int(rng.integers(1, 600))
+        say(f"case: int n={n} m={m} D={D}")
+        p = rng.integers(-(1 << 15), 1 << 15, size=(n, D), dtype=np.int32)
+        q = rng.integers(-(1 << 15), 1 << 15, size=(m, D), dtype=np.int32)
+        got = ctx.distance_i32(dev(p), dev(q)).item()
+        assert got == oracle.dfd_i32(p, q)
+
+
+def test_batch_small_and_ragged(ctx):
+    for seed, npairs, lo, hi in [(20, 50, 1, 300), (21, 200, 1, 80), (22, 30, 500, 2100)]:
+        say(f"case: batch seed={seed} npairs={npairs} lengths [{lo},{hi}]")
+        P, p_off, Q, q_off = workloads.random_pairs(seed, npairs, lo, hi, dim=2)
+        got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+        want = oracle.dfd_batch(P, p_off, Q, q_off, nthreads=8)
+        assert rel_ok(got, want)
+        for k in range(npairs):
+            assert got[k] == oracle.dfd_f32_replica(P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]])
+
+
+def test_batch_equals_plain_and_tuning_invariant(ctx):
+    P, p_off, Q, q_off = workloads.random_pairs(23, 40, 1, 1500, dim=3)
+    say("case: batch vs plain, 40 pairs D=3")
+    base = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    for k in range(40):
+        one = ctx.distance(dev(P[p_off[k]:p_off[k + 1]]), dev(Q[q_off[k]:q_off[k + 1]])).item()
+        assert one == base[k]
+    for R in (1, 2, 4, 8):
+        for W in (1, 2):
+            say(f"case: tuning R={R} W={W}")
+            ctx.set_tuning(R, W)
+            try:
+                got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+            finally:
+                ctx.set_tuning(0, 0)
+            np.testing.assert_array_equal(got, base)
+
+
+def test_batch_int_exact(ctx):
+    say("case: batch int")
+    P, p_off, Q, q_off = workloads.random_pairs(24, 60, 1, 700, dim=2, kind="int")
+    got = ctx.batch_i32(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.dfd_batch_i32(P, p_off, Q, q_off, nthreads=8))
+
+
+def test_cross_small(ctx):
+    say("case: cross float")
+    rng = np.random.default_rng(25)
+    Qs, qo = workloads.concat([workloads.walk(rng, int(rng.integers(1, 700)), 2) for _ in range(6)])
+    DB, do = workloads.concat([workloads.walk(rng, int(rng.integers(1, 400)), 2) for _ in range(37)])
+    got = ctx.cross(dev(Qs), qo, dev(DB), do).cpu().numpy()
+    want = oracle.dfd_cross(Qs, qo, DB, do, nthreads=8)
+    assert rel_ok(got, want)
+    say("case: cross int")
+    Qi, qoi, Di, doi = workloads.cross_int(seed=26, nq=7, ndb=50, length=97)
+    got = ctx.cross_i32(dev(Qi), qoi, dev(Di), doi).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.dfd_cross_i32(Qi, qoi, Di, doi, nthreads=8))
+
+
+def test_batched_workload_full_size_sampled(ctx):
+    """All 4096 pairs in the launch configuration the benchmark times;
+    sampled outputs against stored oracle values, all outputs against the
+    properties that hold at any size."""
+    say("case: batched workload 4096 pairs")
+    g = json.load(open(os.path.join(HERE, "golden", "expected.json")))["batched"]
+    P, p_off, Q, q_off = workloads.batched()
+    got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    idx = np.array(g["sample_index"])
+    assert rel_ok(got[idx], np.array(g["euclidean"]))
+    assert np.all(np.isfinite(got)) and np.all(got >= 0)
+    # end-point lower bound holds for every pair
+    for k in range(0, 4096, 7):
+        p0, p1 = P[p_off[k]], P[p_off[k + 1] - 1]
+        q0, q1 = Q[q_off[k]], Q[q_off[k + 1] - 1]
+        lb = max(np.linalg.norm(p0.astype(np.float64) - q0), np.linalg.norm(p1.astype(np.float64) - q1))
+        assert got[k] >= lb * (1 - TOL)
+    again = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    np.testing.assert_array_equal(got, again)
+
+
+def test_cross_int_workload_full_size_sampled(ctx):
+    say("case: cross int workload 1024 x 1024")
+    g = json.load(open(os.path.join(HERE, "golden", "expected.json")))["cross_int"]
+    Qs, qo, DB, do = workloads.cross_int()
+    got = ctx.cross_i32(dev(Qs), qo, dev(DB), do).cpu().numpy()
+    ii, kk = np.array(g["sample_i"]), np.array(g["sample_k"])
+    np.testing.assert_array_equal(got[ii, kk], np.array(g["sqeuclidean_int64"], dtype=np.int64))
+    # a full row computed by the oracle now
+    row = int(ii[0])
+    want = oracle.dfd_cross_i32(Qs, qo, DB, do, nthreads=16, rows=[row])[0]
+    np.testing.assert_array_equal(got[row], want)
