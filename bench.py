@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-pair comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-pairs", type=int, default=4096, help="pairs in the CPU oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     args = ap.parse_args()
@@ -73,6 +76,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.copy_probe:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # timed region: K steps, synchronised on both sides
     t0 = time.perf_counter()
@@ -91,6 +100,7 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    info = ctx.last_launch()
 
     # parity of the timed output against stored oracle values
     import json as _json
@@ -106,7 +116,8 @@ def main():
     roofline = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
         "unit": "TVALUop/s", "frac": achieved / PEAK_VALU, "traffic": None,
-        "kernel": "ffd::stream_kernel<4,2,float>", "kernel_ms": kern_ms,
+        "kernel": f"ffd::stream_kernel<{info['rows_per_lane']}, {dim}, float>", "kernel_ms": kern_ms,
+        "launch": info,
         "ops_per_cell": imin(dim), "cells_per_launch": cells,
     }
 
@@ -131,7 +142,7 @@ def main():
         import oracle
         cores = min(16, len(os.sched_getaffinity(0)))
         rng = np.random.default_rng(77)
-        sample = np.sort(rng.choice(npairs, size=512, replace=False))
+        sample = np.sort(rng.choice(npairs, size=args.cpu_pairs, replace=False))
         s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
         ps, pl = p_off[:-1][sample], np.diff(p_off)[sample]
         qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
@@ -141,7 +152,7 @@ def main():
         cw = time.perf_counter() - t2
         agree = bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))
         cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
-               "sample": f"512 of the 4096 pairs (seed 77), {s_cells} cells, FP64 rolling-row "
+               "sample": f"{args.cpu_pairs} of the 4096 pairs (seed 77), {s_cells} cells, FP64 rolling-row "
                          f"oracle, longest first on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": agree}
 

@@ -96,6 +96,9 @@ const char *ffd_version(void);
 /* One pair (Eq. (1), result M_PQ; Algorithm 5 / Algorithm 2 form).
  *   p   [n * dim] float32, device;  q [m * dim] float32, device;
  *   out [1] float32, device: delta_dF(p, q) under `metric`.
+ * A pair short enough for one wavefront needs no device memory; a long pair
+ * is split into bands over many wavefronts, using device scratch memory that
+ * the context allocates on first need and keeps until ffd_destroy.
  * Errors: FFD_E_INVALID for NULL pointers, n < 1, m < 1, dim < 1 or an
  * unknown metric; FFD_E_UNSUPPORTED for dim > FFD_MAX_DIM. */
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
@@ -153,6 +156,37 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
  * row curve each GPU lane holds; waves_per_simd: resident waves per SIMD the
  * batch planner targets.  Returns FFD_E_INVALID for values out of range. */
 int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd);
+
+/* Shape of the most recent launch on this context, for reporting and tuning.
+ * Fields are 0 if nothing has been launched.  Errors: FFD_E_INVALID (NULL). */
+typedef struct ffd_launch_info {
+  int32_t rows_per_lane;   /* points of the row curve per lane (R)          */
+  int32_t waves;           /* wavefronts launched                           */
+  int32_t waves_per_block; /* wavefronts per workgroup                      */
+  int32_t lds_per_wave;    /* bytes of LDS per wavefront                    */
+  int32_t exact;           /* 1: int32 path with FP64-exact values          */
+  int32_t dim;             /* D                                             */
+  int64_t stream_steps;    /* longest per-wave stream (steps)               */
+} ffd_launch_info;
+
+int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info);
+
+/* Error bits the most recent launch on this context raised on the device
+ * (waits for it to finish): bit 0 = a wavefront hit its step bound, bit 1 =
+ * a wavefront gave up waiting for a boundary row from another wavefront
+ * (possible only when other work occupies the GPU so long that the
+ * producing wavefront cannot start).  Results of such a launch are not
+ * valid.  0 for launches that use no workspace.
+ * Errors: FFD_E_INVALID (NULL), FFD_E_DEVICE. */
+int ffd_last_errors(ffd_ctx *ctx, int32_t *flags);
+
+/* How eagerly long pairs are split into bands that run on different
+ * wavefronts (their boundary rows pass through the workspace): a pair whose
+ * modelled work exceeds `share` times a wavefront's fair share of the launch
+ * is split; 0 = automatic (0.5), a negative value = split only when a pair's
+ * boundary row does not fit in LDS.  Results do not depend on the setting.
+ * Errors: FFD_E_INVALID (NaN or huge share). */
+int ffd_set_split(ffd_ctx *ctx, float share);
 
 #ifdef __cplusplus
 }

@@ -2,17 +2,27 @@
 //
 // Planning follows Sec. 4 of the paper (batches of curves, sorting by length
 // before batching) in the form that suits one wavefront per stream:
-//  * every pair is oriented so that the cheaper curve becomes the row curve
-//    (the distance is symmetric and the float evaluation is exactly
-//    symmetric, so both orientations give the same bits);
-//  * jobs are assigned to waves longest-first onto the least loaded wave
-//    (LPT), which is the "sort by length" rule applied to a fixed number of
-//    workers;
+//  * a "unit" is one row curve against a run of column curves (a pair of a
+//    batch, or a query against a chunk of the database); every pair is
+//    oriented so that the cheaper curve becomes the row curve (the distance
+//    is symmetric and the float evaluation is exactly symmetric, so both
+//    orientations give the same bits);
+//  * units much longer than a wave's fair share are split into their bands
+//    of 64*R rows, which run on different waves and hand their boundary rows
+//    on through global "links" (release/acquire progress flags);
+//  * tasks are placed by list scheduling: the highest-priority ready task
+//    (longest remaining chain; longest first otherwise, the paper's sort by
+//    length) goes to the wave that frees first.  A task that reads a link is
+//    placed after the task that writes it, and every wave runs its tasks in
+//    placement order, so the earliest unfinished task never waits: no
+//    deadlock, whatever the actual timing;
 //  * the plan (jobs, per-wave job ranges, curve offsets) is copied into the
 //    caller's workspace and reused while the offsets do not change.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -25,32 +35,64 @@
 
 namespace ffd {
 hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, hipStream_t st);
-}
+hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+}  // namespace ffd
 
 using ffd::Job;
 using ffd::KernelArgs;
 
-struct PlanCacheBase;
+namespace {
+
+// A planned launch.
+struct Plan {
+  int R = 4;
+  int nwaves = 0;
+  int wpb = 1;
+  int64_t hcap = 0;            // LDS hand-off entries per wave
+  int64_t max_steps = 0;       // longest stream of any wave
+  int64_t link_elems = 0;      // elements of all link buffers
+  int32_t nflags = 0;          // progress flags
+  double makespan = 0;         // modelled, in steps
+  std::vector<Job> jobs;       // grouped by wave, in placement order
+  std::vector<int32_t> wave_jobs;
+};
+
+struct PlanCache {
+  uint64_t key = 0;
+  Plan plan;
+  bool valid = false;
+};
+
+}  // namespace
 
 struct ffd_ctx {
   int device = 0;
   int cus = 0;
-  size_t lds_block_max = 0;
+  size_t lds_block_max = 0;   // LDS per workgroup the planner uses
+  size_t lds_cu = 0;          // LDS per compute unit
   int tune_R = 0;
   int tune_W = 0;
+  float split = 0.f;          // 0 auto, < 0 split only when needed, > 0 split above this share
+  uint32_t epoch = 0;
   std::string last_error;
   // plan most recently written to a workspace (skip the upload if unchanged)
   void *plan_ws = nullptr;
   uint64_t plan_ws_key = 0;
-  void *pinned = nullptr;  // staging buffer for plan uploads
+  void *pinned = nullptr;     // staging buffer for plan uploads
   size_t pinned_bytes = 0;
   hipEvent_t upload_done = nullptr;
-  PlanCacheBase *plans_ptr = nullptr;
+  PlanCache batch_plans, pair_plans;
+  void *scratch = nullptr;    // device workspace for long single pairs (owned)
+  size_t scratch_bytes = 0;
+  ffd_launch_info last{};
+  uint64_t *last_err = nullptr; // device error word of the last launch (workspace)
+  uint32_t last_epoch = 0;
+  hipStream_t last_stream = nullptr;
 };
 
 namespace {
 
-const char *kVersion = "ffd 0.1.0 (gfx950)";
+const char *kVersion = "ffd 0.2.0 (gfx950)";
 
 int fail(ffd_ctx *ctx, int code, const char *msg) {
   if (ctx) ctx->last_error = msg;
@@ -63,38 +105,14 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 }
 
 // Modelled VALU instructions per lane for one step with R rows per lane:
-// (2D + 2) per cell (D subtractions, one multiply, D-1 FMAs, min, min, max
-// with min3 fused as two) plus a few per step (lane shift, addressing).
+// (2D + 2) per cell (D subtractions, one multiply, D-1 FMAs, min3, max) plus
+// a few per step (lane shift, addressing).
 double step_cost(int R, int D) { return (double)R * (2 * D + 2) + 3.0; }
 
-struct Orient {
-  bool swap;        // true: row curve is the second curve
-  int64_t steps;    // stream steps of the job
-  int64_t hcap;     // hand-off entries needed (0 if a single band)
-};
-
-Orient orient_pair(int64_t n, int64_t m, int R, bool allow_swap) {
-  auto steps = [&](int64_t rows, int64_t cols, int64_t *hc) {
-    int64_t nb = ffd::bands_for(rows, R);
-    int64_t L = ffd::task_len(cols, nb > 1);
-    *hc = nb > 1 ? L : 0;
-    return nb * L;
-  };
-  Orient o{false, 0, 0};
-  int64_t h1, h2;
-  int64_t s1 = steps(n, m, &h1);
-  o.steps = s1;
-  o.hcap = h1;
-  if (allow_swap) {
-    int64_t s2 = steps(m, n, &h2);
-    if (s2 < s1 || (s2 == s1 && h2 < h1)) {
-      o.swap = true;
-      o.steps = s2;
-      o.hcap = h2;
-    }
-  }
-  return o;
-}
+// Steps a consumer band trails its producer: the boundary row is published
+// every kFill steps, fetched kFill to 3*kFill steps ahead of use, and the
+// producer's lane 63 trails its lane 0 by kWave steps.
+constexpr double kLinkLag = 6.0 * ffd::kFill;
 
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
   const unsigned char *b = (const unsigned char *)p;
@@ -129,202 +147,344 @@ int lds_bytes(int R, int D, bool exact, int64_t hcap) {
 
 const int kRs[4] = {1, 2, 4, 8};
 
-// A planned launch over jobs.
-struct Plan {
-  int R = 4;
-  int nwaves = 0;
-  int wpb = 1;
-  int64_t hcap = 0;
-  int64_t max_steps = 0;         // largest stream of any wave
-  std::vector<Job> jobs;         // grouped by wave
-  std::vector<int32_t> wave_jobs;
+// ---------------------------------------------------------------- units
+
+// One row curve against a run of column curves, all bands of the row curve.
+struct Unit {
+  int32_t row_sel, row_idx, col_sel, col_first, col_count, out_stride;
+  int64_t out_base;
+  int64_t nrows;
+  int32_t nb;      // bands
+  int64_t sumL;    // stream steps of one band over all column curves
+  int64_t maxL;    // longest task of the unit
+  double steps() const { return (double)nb * (double)sumL; }
 };
 
-// Assign jobs (with modelled costs) to nwaves waves, longest first onto the
-// least loaded wave, and lay them out grouped by wave.
-void lpt(std::vector<Job> &jobs, const std::vector<double> &cost, int nwaves, Plan &pl) {
-  std::vector<int64_t> order(jobs.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
-  using Item = std::pair<double, int>;
-  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-  for (int w = 0; w < nwaves; ++w) heap.push({0.0, w});
-  std::vector<int> owner(jobs.size());
-  std::vector<int32_t> count(nwaves, 0);
-  std::vector<double> load(nwaves, 0.0);
-  for (int64_t i : order) {
-    Item it = heap.top();
-    heap.pop();
-    owner[i] = it.second;
-    count[it.second]++;
-    load[it.second] += cost[i];
-    heap.push({it.first + cost[i], it.second});
+struct CurveSet {
+  const int64_t *off;
+  int64_t count;
+  int64_t len(int64_t k) const { return off[k + 1] - off[k]; }
+};
+
+// Units of a batch: pair k, oriented to the cheaper number of steps.
+void batch_units(const CurveSet &P, const CurveSet &Q, int R, std::vector<Unit> &units) {
+  units.resize(P.count);
+  for (int64_t k = 0; k < P.count; ++k) {
+    int64_t n = P.len(k), m = Q.len(k);
+    int64_t nb1 = ffd::bands_for(n, R), nb2 = ffd::bands_for(m, R);
+    int64_t L1 = ffd::task_len(m, nb1 > 1), L2 = ffd::task_len(n, nb2 > 1);
+    bool swap = nb2 * L2 < nb1 * L1;
+    Unit &u = units[k];
+    u.row_sel = swap ? 1 : 0;
+    u.col_sel = swap ? 0 : 1;
+    u.row_idx = u.col_first = (int32_t)k;
+    u.col_count = 1;
+    u.out_base = k;
+    u.out_stride = 1;
+    u.nrows = swap ? m : n;
+    u.nb = (int32_t)(swap ? nb2 : nb1);
+    u.sumL = u.maxL = swap ? L2 : L1;
   }
-  double mx = 0;
-  for (double x : load) mx = std::max(mx, x);
-  pl.max_steps = (int64_t)mx;
+}
+
+// Units of queries x database: query i against runs of consecutive database
+// curves of about `target` steps each.
+void cross_units(const CurveSet &Qs, const CurveSet &DB, int R, double target, std::vector<Unit> &units) {
+  units.clear();
+  for (int64_t i = 0; i < Qs.count; ++i) {
+    int64_t nb = ffd::bands_for(Qs.len(i), R);
+    int64_t k = 0;
+    while (k < DB.count) {
+      Unit u;
+      u.row_sel = 0;
+      u.row_idx = (int32_t)i;
+      u.col_sel = 1;
+      u.col_first = (int32_t)k;
+      u.out_base = i * DB.count + k;
+      u.out_stride = 1;
+      u.nrows = Qs.len(i);
+      u.nb = (int32_t)nb;
+      u.sumL = 0;
+      u.maxL = 0;
+      while (k < DB.count) {
+        int64_t L = ffd::task_len(DB.len(k), nb > 1);
+        if (u.sumL > 0 && (double)nb * (double)(u.sumL + L) > target) break;
+        u.sumL += L;
+        u.maxL = std::max(u.maxL, L);
+        ++k;
+      }
+      u.col_count = (int32_t)(k - u.col_first);
+      units.push_back(u);
+    }
+  }
+}
+
+// ------------------------------------------------------------- scheduling
+
+struct Task {
+  int32_t unit;
+  int32_t band_first, band_count;  // band_count 0: all bands
+  int32_t pred;                    // task writing this task's incoming link, -1 none
+  int32_t succ;                    // task reading this task's outgoing link, -1 none
+  double dur;                      // stream steps
+  double prio;                     // longest remaining chain (steps)
+};
+
+// List scheduling with precedence (see the file comment).  Fills
+// owner/order: the wave of every task and the tasks in placement order.
+// Returns the modelled makespan in steps.
+double list_schedule(const std::vector<Task> &tasks, int nwaves, std::vector<int> &owner,
+                     std::vector<int32_t> &order, std::vector<double> &wave_steps) {
+  const size_t nt = tasks.size();
+  owner.assign(nt, -1);
+  order.clear();
+  order.reserve(nt);
+  wave_steps.assign(nwaves, 0.0);
+  using WaveItem = std::pair<double, int>;  // free time, wave
+  std::priority_queue<WaveItem, std::vector<WaveItem>, std::greater<WaveItem>> waves;
+  for (int w = 0; w < nwaves; ++w) waves.push({0.0, w});
+  using Ready = std::pair<double, int32_t>;  // priority, task
+  std::priority_queue<Ready> avail;          // ready now, highest priority first
+  using Pending = std::pair<double, int32_t>;  // ready time, task
+  std::priority_queue<Pending, std::vector<Pending>, std::greater<Pending>> pending;
+  for (size_t i = 0; i < nt; ++i)
+    if (tasks[i].pred < 0) avail.push({tasks[i].prio, (int32_t)i});
+  double makespan = 0;
+  std::vector<double> start(nt, 0.0);
+  while (!avail.empty() || !pending.empty()) {
+    WaveItem w = waves.top();
+    waves.pop();
+    double now = w.first;
+    while (!pending.empty() && pending.top().first <= now) {
+      avail.push({tasks[pending.top().second].prio, pending.top().second});
+      pending.pop();
+    }
+    if (avail.empty()) {  // nothing ready yet: this wave idles until the next task is
+      now = pending.top().first;
+      avail.push({tasks[pending.top().second].prio, pending.top().second});
+      pending.pop();
+    }
+    int32_t t = avail.top().second;
+    avail.pop();
+    double st = now;
+    if (tasks[t].pred >= 0) st = std::max(st, start[tasks[t].pred] + kLinkLag);
+    start[t] = st;
+    owner[t] = w.second;
+    order.push_back(t);
+    wave_steps[w.second] += tasks[t].dur;
+    double fin = st + tasks[t].dur;
+    makespan = std::max(makespan, fin);
+    waves.push({fin, w.second});
+    if (tasks[t].succ >= 0) pending.push({st + kLinkLag, tasks[t].succ});
+  }
+  return makespan;
+}
+
+struct Resources {
+  int nwaves_max;   // waves resident at once
+  int wpb;          // waves per workgroup
+  int64_t hand_max; // longest LDS hand-off row
+};
+
+// Launch resources for R rows per lane and W waves per SIMD: every wave gets
+// an equal share of the CU's LDS, which bounds the LDS hand-off row; all
+// waves of the launch are resident at once (a wave waiting on a link may
+// only wait on a running wave).
+Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W) {
+  Resources r;
+  size_t per_wave = ctx->lds_cu / (size_t)(4 * W);
+  int vs = exact ? 8 : 4;
+  int fixed = lds_bytes(R, D, exact, 0);
+  int64_t hand = ((int64_t)per_wave - fixed - 16) / vs;
+  r.hand_max = hand > 0 ? hand : 0;
+  r.wpb = 4;
+  while (r.wpb > 1 && (size_t)r.wpb * per_wave > ctx->lds_block_max) r.wpb /= 2;
+  r.nwaves_max = ctx->cus * 4 * W;
+  if (ctx->device >= 0) {
+    // registers may allow fewer resident waves than the LDS share assumes
+    int blocks = 0;
+    size_t lds = (size_t)r.wpb * (size_t)lds_bytes(R, D, exact, r.hand_max);
+    if (ffd::occupancy_stream(exact, R, D, r.wpb, lds, &blocks) == hipSuccess && blocks > 0)
+      r.nwaves_max = std::min(r.nwaves_max, ctx->cus * blocks * r.wpb);
+  }
+  return r;
+}
+
+// Turn units into tasks (splitting the long ones), schedule them on nwaves
+// waves and lay the plan out.
+void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_share, int64_t hand_max,
+                Plan &pl) {
+  double total = 0;
+  for (const Unit &u : units) total += u.steps();
+  double fair = total / std::max(1, nwaves);
+  std::vector<Task> tasks;
+  tasks.reserve(units.size());
+  std::vector<char> split(units.size(), 0);
+  for (size_t i = 0; i < units.size(); ++i) {
+    const Unit &u = units[i];
+    bool need = u.nb > 1 && u.maxL > hand_max;
+    bool want = u.nb > 1 && split_share >= 0 && u.steps() > split_share * fair;
+    split[i] = need || want;
+    if (!split[i]) {
+      tasks.push_back({(int32_t)i, 0, 0, -1, -1, u.steps(), u.steps()});
+    } else {
+      int32_t first = (int32_t)tasks.size();
+      for (int32_t bnd = 0; bnd < u.nb; ++bnd) {
+        double chain = (double)(u.nb - 1 - bnd) * kLinkLag + (double)u.sumL;
+        tasks.push_back({(int32_t)i, bnd, 1, bnd > 0 ? first + bnd - 1 : -1,
+                         bnd + 1 < u.nb ? first + bnd + 1 : -1, (double)u.sumL, chain});
+      }
+    }
+  }
+  std::vector<int> owner;
+  std::vector<int32_t> order;
+  std::vector<double> wsteps;
+  pl.makespan = list_schedule(tasks, nwaves, owner, order, wsteps);
+  // links: one per band boundary of a split unit, sumL entries each
+  std::vector<int64_t> link_of(tasks.size(), -1);  // outgoing link element start
+  std::vector<int32_t> flag_of(tasks.size(), -1);
+  pl.link_elems = 0;
+  pl.nflags = 0;
+  for (size_t t = 0; t < tasks.size(); ++t) {
+    if (tasks[t].succ >= 0) {
+      link_of[t] = pl.link_elems;
+      flag_of[t] = pl.nflags++;
+      pl.link_elems += units[tasks[t].unit].sumL;
+    }
+  }
+  pl.hcap = 0;
+  for (size_t i = 0; i < units.size(); ++i)
+    if (!split[i] && units[i].nb > 1) pl.hcap = std::max(pl.hcap, units[i].maxL);
+  std::vector<int32_t> count(nwaves, 0);
+  for (int32_t t : order) count[owner[t]]++;
   pl.wave_jobs.assign(nwaves + 1, 0);
   for (int w = 0; w < nwaves; ++w) pl.wave_jobs[w + 1] = pl.wave_jobs[w] + count[w];
   std::vector<int32_t> fillp(pl.wave_jobs.begin(), pl.wave_jobs.end() - 1);
-  pl.jobs.resize(jobs.size());
-  for (int64_t i : order) pl.jobs[fillp[owner[i]]++] = jobs[i];
+  pl.jobs.resize(tasks.size());
+  for (int32_t t : order) {
+    const Task &tk = tasks[t];
+    const Unit &u = units[tk.unit];
+    Job jb;
+    jb.out_base = u.out_base;
+    jb.row_sel = u.row_sel;
+    jb.row_idx = u.row_idx;
+    jb.col_sel = u.col_sel;
+    jb.col_first = u.col_first;
+    jb.col_count = u.col_count;
+    jb.out_stride = u.out_stride;
+    jb.band_first = tk.band_first;
+    jb.band_count = tk.band_count;
+    jb.link_in = tk.pred >= 0 ? link_of[tk.pred] : -1;
+    jb.flag_in = tk.pred >= 0 ? flag_of[tk.pred] : -1;
+    jb.link_out = link_of[t];
+    jb.flag_out = flag_of[t];
+    pl.jobs[fillp[owner[t]]++] = jb;
+  }
+  double mx = 0;
+  for (double x : wsteps) mx = std::max(mx, x);
+  pl.max_steps = (int64_t)mx;
+  pl.nwaves = nwaves;
+  pl.R = R;
 }
 
-int waves_for(ffd_ctx *ctx, int W, size_t njobs) {
-  int nw = ctx->cus * 4 * W;
-  if ((size_t)nw > njobs) nw = (int)njobs;
-  return nw < 1 ? 1 : nw;
+double split_share(ffd_ctx *ctx) {
+  if (ctx->split == 0.f) return 0.5;
+  if (ctx->split < 0.f) return -1.0;
+  return ctx->split;
 }
 
-int choose_wpb(ffd_ctx *ctx, int lds_wave) {
-  int wpb = 4;
-  while (wpb > 1 && (size_t)lds_wave * wpb > ctx->lds_block_max) wpb /= 2;
-  return wpb;
+// Plan the units produced by `make(R, W, units)` for the R with the lowest
+// modelled makespan times per-step cost.
+template <typename MakeUnits>
+int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single, MakeUnits make, Plan &best) {
+  double best_cost = -1;
+  for (int R : kRs) {
+    if (ctx->tune_R && R != ctx->tune_R) continue;
+    Resources rs = resources(ctx, R, D, exact, W);
+    std::vector<Unit> units;
+    make(R, W, units);
+    size_t ntasks = 0;
+    for (const Unit &u : units) ntasks += (size_t)u.nb;  // tasks if every unit were split
+    int nwaves = rs.nwaves_max;
+    if ((size_t)nwaves > ntasks) nwaves = (int)std::max<size_t>(1, ntasks);
+    Plan pl;
+    build_plan(units, R, nwaves, share, rs.hand_max, pl);
+    if (single && pl.link_elems > 0) {
+      // a single pair: compare with the whole pair on one wave
+      Plan whole;
+      build_plan(units, R, 1, -1.0, rs.hand_max, whole);
+      if (whole.link_elems == 0 && whole.makespan <= pl.makespan) pl = std::move(whole);
+    }
+    pl.wpb = std::min(rs.wpb, pl.nwaves);
+    double cost = (pl.makespan + ffd::kWave) * step_cost(R, D);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = std::move(pl);
+    }
+  }
+  if (best_cost < 0) return fail(ctx, FFD_E_UNSUPPORTED, "no feasible launch shape");
+  return FFD_OK;
 }
 
-// Plan a batch of independent pairs.
-int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D,
+int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
+               Plan &pl) {
+  CurveSet P{p_off, npairs}, Q{q_off, npairs};
+  int W = ctx->tune_W > 0 ? ctx->tune_W : 2;
+  return plan_units(ctx, D, exact, W, split_share(ctx), false,
+                    [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl);
+}
+
+int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
                bool exact, Plan &pl) {
+  CurveSet Qs{q_off, nq}, DB{db_off, ndb};
   int W = ctx->tune_W > 0 ? ctx->tune_W : 2;
-  double best = -1;
-  int bestR = 4;
-  for (int R : kRs) {
-    if (ctx->tune_R && R != ctx->tune_R) continue;
-    double tot = 0;
-    int64_t hc = 0;
-    for (int64_t k = 0; k < npairs; ++k) {
-      Orient o = orient_pair(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], R, true);
-      tot += (double)o.steps * step_cost(R, D);
-      hc = std::max(hc, o.hcap);
-    }
-    if ((size_t)lds_bytes(R, D, exact, hc) > ctx->lds_block_max) continue;
-    if (best < 0 || tot < best) {
-      best = tot;
-      bestR = R;
-    }
-  }
-  if (best < 0) return fail(ctx, FFD_E_UNSUPPORTED, "curves too long for the LDS hand-off row");
-  pl.R = bestR;
-  std::vector<Job> jobs(npairs);
-  std::vector<double> cost(npairs);
-  pl.hcap = 0;
-  for (int64_t k = 0; k < npairs; ++k) {
-    Orient o = orient_pair(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], pl.R, true);
-    Job &jb = jobs[k];
-    jb.out_base = k;
-    jb.row_sel = o.swap ? 1 : 0;
-    jb.row_idx = (int32_t)k;
-    jb.col_sel = o.swap ? 0 : 1;
-    jb.col_first = (int32_t)k;
-    jb.col_count = 1;
-    jb.out_stride = 1;
-    cost[k] = (double)o.steps;  // exact stream length of the job
-    pl.hcap = std::max(pl.hcap, o.hcap);
-  }
-  pl.nwaves = waves_for(ctx, W, jobs.size());
-  pl.wpb = choose_wpb(ctx, lds_bytes(pl.R, D, exact, pl.hcap));
-  lpt(jobs, cost, pl.nwaves, pl);
-  return FFD_OK;
+  return plan_units(ctx, D, exact, W, split_share(ctx), false,
+                    [&](int R, int Wv, std::vector<Unit> &u) {
+                      // about eight units per wave
+                      double total = 0, cols = 0;
+                      for (int64_t k = 0; k < ndb; ++k) cols += (double)ffd::task_len(DB.len(k), false);
+                      for (int64_t i = 0; i < nq; ++i) total += (double)ffd::bands_for(Qs.len(i), R) * cols;
+                      double target = total / ((double)ctx->cus * 4 * Wv * 8.0);
+                      cross_units(Qs, DB, R, std::max(target, 1.0), u);
+                    },
+                    pl);
 }
 
-// Plan queries x database: job = one query against a run of database curves.
-int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb,
-               int D, bool exact, Plan &pl) {
-  int W = ctx->tune_W > 0 ? ctx->tune_W : 2;
-  int64_t dbmax = 0;
-  for (int64_t k = 0; k < ndb; ++k) dbmax = std::max(dbmax, db_off[k + 1] - db_off[k]);
-  double best = -1;
-  int bestR = 4;
-  for (int R : kRs) {
-    if (ctx->tune_R && R != ctx->tune_R) continue;
-    double tot = 0;
-    bool chained = false;
-    for (int64_t i = 0; i < nq; ++i) {
-      int64_t nb = ffd::bands_for(q_off[i + 1] - q_off[i], R);
-      chained |= nb > 1;
-      tot += (double)nb;
-    }
-    double cols = 0;
-    for (int64_t k = 0; k < ndb; ++k) cols += (double)ffd::task_len(db_off[k + 1] - db_off[k], chained);
-    tot *= cols * step_cost(R, D);
-    int64_t hc = chained ? ffd::task_len(dbmax, true) : 0;
-    if ((size_t)lds_bytes(R, D, exact, hc) > ctx->lds_block_max) continue;
-    if (best < 0 || tot < best) {
-      best = tot;
-      bestR = R;
-    }
-  }
-  if (best < 0) return fail(ctx, FFD_E_UNSUPPORTED, "database curves too long for the LDS hand-off row");
-  pl.R = bestR;
-  bool any_chained = false;
-  for (int64_t i = 0; i < nq; ++i) any_chained |= ffd::bands_for(q_off[i + 1] - q_off[i], pl.R) > 1;
-  pl.hcap = any_chained ? ffd::task_len(dbmax, true) : 0;
-  // total modelled steps -> chunk target so that each wave gets several jobs
-  int nw_full = ctx->cus * 4 * W;
-  std::vector<double> colcost(ndb);
-  for (int64_t k = 0; k < ndb; ++k) {
-    bool chained_any = any_chained;
-    colcost[k] = (double)ffd::task_len(db_off[k + 1] - db_off[k], chained_any);
-  }
-  double total = 0;
-  std::vector<double> qb(nq);
-  for (int64_t i = 0; i < nq; ++i) {
-    qb[i] = (double)ffd::bands_for(q_off[i + 1] - q_off[i], pl.R);
-    total += qb[i];
-  }
-  double colsum = 0;
-  for (double x : colcost) colsum += x;
-  total *= colsum;
-  double target = total / ((double)nw_full * 8.0);
-  std::vector<Job> jobs;
-  std::vector<double> cost;
-  for (int64_t i = 0; i < nq; ++i) {
-    int64_t k = 0;
-    while (k < ndb) {
-      int64_t k0 = k;
-      double c = 0;
-      while (k < ndb && (c == 0 || c + qb[i] * colcost[k] <= target)) {
-        c += qb[i] * colcost[k];
-        ++k;
-      }
-      Job jb;
-      jb.out_base = i * ndb + k0;
-      jb.row_sel = 0;
-      jb.row_idx = (int32_t)i;
-      jb.col_sel = 1;
-      jb.col_first = (int32_t)k0;
-      jb.col_count = (int32_t)(k - k0);
-      jb.out_stride = 1;
-      jobs.push_back(jb);
-      cost.push_back(c);
-    }
-  }
-  pl.nwaves = waves_for(ctx, W, jobs.size());
-  pl.wpb = choose_wpb(ctx, lds_bytes(pl.R, D, exact, pl.hcap));
-  lpt(jobs, cost, pl.nwaves, pl);
-  return FFD_OK;
+// One pair; a long pair is split into bands over waves when that pays.
+int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
+  int64_t off0[2] = {0, n}, off1[2] = {0, m};
+  CurveSet P{off0, 1}, Q{off1, 1};
+  int W = ctx->tune_W > 0 ? ctx->tune_W : 1;
+  double share = ctx->split < 0.f ? -1.0 : 0.0;
+  return plan_units(ctx, D, exact, W, share, true,
+                    [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl);
 }
+
+// ---------------------------------------------------------------- workspace
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t jobs, wj, off0, off1, total;
+  size_t jobs, wj, off0, off1, flags, err, links, total;
 };
 
-WsLayout ws_layout(size_t njobs, int nwaves, int64_t n0, int64_t n1) {
+WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
   WsLayout w;
   size_t o = 0;
-  w.jobs = o; o = al256(o + njobs * sizeof(Job));
-  w.wj = o;   o = al256(o + (size_t)(nwaves + 1) * sizeof(int32_t));
-  w.off0 = o; o = al256(o + (size_t)(n0 + 1) * sizeof(int64_t));
-  w.off1 = o; o = al256(o + (size_t)(n1 + 1) * sizeof(int64_t));
+  w.jobs = o;  o = al256(o + pl.jobs.size() * sizeof(Job));
+  w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
+  w.off0 = o;  o = al256(o + (size_t)(n0 + 1) * sizeof(int64_t));
+  w.off1 = o;  o = al256(o + (size_t)(n1 + 1) * sizeof(int64_t));
+  w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
+  w.err = o;   o = al256(o + sizeof(uint64_t));
+  w.links = o; o = al256(o + (size_t)pl.link_elems * (exact ? 8 : 4));
   w.total = o;
   return w;
 }
 
 int ensure_pinned(ffd_ctx *ctx, size_t bytes) {
   if (ctx->pinned_bytes >= bytes) {
-    // previous upload must have finished reading the staging buffer
+    // the previous upload must have finished reading the staging buffer
     if (ctx->upload_done) hipEventSynchronize(ctx->upload_done);
     return FFD_OK;
   }
@@ -340,23 +500,32 @@ int ensure_pinned(ffd_ctx *ctx, size_t bytes) {
   return FFD_OK;
 }
 
-// Run a planned launch: upload the plan into the workspace unless the same
-// plan is already there, then launch.
-int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const int64_t *off0,
-             int64_t n0, const void *X1, const int64_t *off1, int64_t n1, int D, bool exact,
-             int metric, void *out, void *ws, size_t ws_bytes, hipStream_t st) {
-  WsLayout wl = ws_layout(pl.jobs.size(), pl.nwaves, n0, n1);
+// Run a planned launch: upload the plan (jobs, job ranges, offsets, zeroed
+// flags and error word) into the workspace unless the same plan is already
+// there, then launch.  Flags carry the launch epoch, so a reused plan needs
+// no clearing.
+int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const int64_t *off0, int64_t n0,
+             const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
+             size_t ws_bytes, hipStream_t st) {
+  WsLayout wl = ws_layout(pl, n0, n1, exact);
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap), exact ? 1 : 0, D,
+                              pl.max_steps};
   if (!ws || ws_bytes < wl.total) return fail(ctx, FFD_E_NOMEM, "workspace too small (see ffd_workspace_size)");
+  if (pl.max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
+  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   unsigned char *w = (unsigned char *)ws;
   if (!(ctx->plan_ws == ws && ctx->plan_ws_key == key)) {
-    int rc = ensure_pinned(ctx, wl.total);
+    int rc = ensure_pinned(ctx, wl.links);
     if (rc) return rc;
     unsigned char *h = (unsigned char *)ctx->pinned;
     memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
     memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
     memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
     memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
-    hipError_t e = hipMemcpyAsync(w, h, wl.total, hipMemcpyHostToDevice, st);
+    memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
+    e = hipMemcpyAsync(w, h, wl.links, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync (plan)");
     if (!ctx->upload_done) {
       e = hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming);
@@ -379,18 +548,27 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.metric = metric;
   a.hcap = (int32_t)pl.hcap;
   a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap);
-  if (pl.max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
   a.max_steps = (int32_t)(pl.max_steps + 4 * ffd::kRing);
-  hipError_t e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, st);
+  a.epoch = ++ctx->epoch;
+  a.links = w + wl.links;
+  a.flags = (uint64_t *)(w + wl.flags);
+  a.err = (uint64_t *)(w + wl.err);
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
+  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+  ctx->last_err = a.err;
+  ctx->last_epoch = a.epoch;
+  ctx->last_stream = st;
   return FFD_OK;
 }
 
-uint64_t key_of(int op, int D, bool exact, int R, int W, const int64_t *a, int64_t na, const int64_t *b,
+uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b,
                 int64_t nb) {
   uint64_t h = 1469598103934665603ull;
-  int hdr[6] = {op, D, exact ? 1 : 0, R, W, 0};
+  int hdr[6] = {op, D, exact ? 1 : 0, ctx->tune_R, ctx->tune_W, 0};
+  float sp = ctx->split;
   h = fnv(h, hdr, sizeof hdr);
+  h = fnv(h, &sp, sizeof sp);
   h = fnv(h, &na, sizeof na);
   h = fnv(h, &nb, sizeof nb);
   h = fnv(h, a, (size_t)(na + 1) * sizeof(int64_t));
@@ -398,27 +576,20 @@ uint64_t key_of(int op, int D, bool exact, int R, int W, const int64_t *a, int64
   return h;
 }
 
-struct PlanCache {
-  uint64_t key = 0;
-  Plan plan;
-  bool valid = false;
-};
+constexpr int kOpPair = 100;  // internal plan kind of ffd_distance
 
-PlanCache &plans_of(ffd_ctx *ctx) {
-  if (!ctx->plans_ptr) ctx->plans_ptr = reinterpret_cast<PlanCacheBase *>(new PlanCache());
-  return *reinterpret_cast<PlanCache *>(ctx->plans_ptr);
-}
-
-int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na,
-                const int64_t *b_off, int64_t nb, int D, bool exact, const Plan **out, uint64_t &key) {
-  key = key_of(op, D, exact, ctx->tune_R, ctx->tune_W, a_off, na, b_off, nb);
+int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na, const int64_t *b_off,
+                int64_t nb, int D, bool exact, const Plan **out, uint64_t &key) {
+  key = key_of(ctx, op, D, exact, a_off, na, b_off, nb);
   if (pc.valid && pc.key == key) {
     *out = &pc.plan;
     return FFD_OK;
   }
   Plan pl;
-  int rc = op == FFD_OP_BATCH ? plan_batch(ctx, a_off, b_off, na, D, exact, pl)
-                              : plan_cross(ctx, a_off, na, b_off, nb, D, exact, pl);
+  int rc;
+  if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, D, exact, pl);
+  else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, D, exact, pl);
+  else rc = plan_pair(ctx, a_off[1], b_off[1], D, exact, pl);
   if (rc) return rc;
   pc.plan = std::move(pl);
   pc.key = key;
@@ -427,69 +598,68 @@ int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64
   return FFD_OK;
 }
 
-int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m, int32_t dim,
-                int32_t metric, void *out, hipStream_t st, bool exact) {
+int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m, int32_t dim, int32_t metric,
+                void *out, hipStream_t st, bool exact) {
   int rc = check_common(ctx, dim, metric, exact);
   if (rc) return rc;
   if (!p || !q || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
   if (n < 1 || m < 1) return fail(ctx, FFD_E_INVALID, "curves must have at least one point");
-  // choose R and orientation for one stream
-  double best = -1;
-  int bestR = 4;
-  Orient bestO{false, 0, 0};
-  for (int R : kRs) {
-    if (ctx->tune_R && R != ctx->tune_R) continue;
-    Orient o = orient_pair(n, m, R, true);
-    if ((size_t)lds_bytes(R, dim, exact, o.hcap) > ctx->lds_block_max) {
-      Orient o2 = orient_pair(n, m, R, false);
-      Orient o3 = orient_pair(m, n, R, false);
-      o3.swap = true;
-      if ((size_t)lds_bytes(R, dim, exact, o2.hcap) <= ctx->lds_block_max) o = o2;
-      else if ((size_t)lds_bytes(R, dim, exact, o3.hcap) <= ctx->lds_block_max) o = o3;
-      else continue;
-    }
-    double c = (double)(o.steps + ffd::kWave) * step_cost(R, dim);
-    if (best < 0 || c < best) {
-      best = c;
-      bestR = R;
-      bestO = o;
-    }
-  }
-  if (best < 0) return fail(ctx, FFD_E_UNSUPPORTED, "pair too long for the LDS hand-off row");
-  KernelArgs a;
-  memset(&a, 0, sizeof a);
-  a.X[0] = p;
-  a.X[1] = q;
-  a.inl_off[0][0] = 0;
-  a.inl_off[0][1] = n;
-  a.inl_off[1][0] = 0;
-  a.inl_off[1][1] = m;
-  a.jobs = nullptr;
-  a.inl_job.out_base = 0;
-  a.inl_job.row_sel = bestO.swap ? 1 : 0;
-  a.inl_job.row_idx = 0;
-  a.inl_job.col_sel = bestO.swap ? 0 : 1;
-  a.inl_job.col_first = 0;
-  a.inl_job.col_count = 1;
-  a.inl_job.out_stride = 1;
-  a.out = out;
-  a.nwaves = 1;
-  a.metric = metric;
-  a.hcap = (int32_t)bestO.hcap;
-  a.lds_per_wave = lds_bytes(bestR, dim, exact, bestO.hcap);
-  if (bestO.steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
-  a.max_steps = (int32_t)(bestO.steps + 4 * ffd::kRing);
+  int64_t off0[2] = {0, n}, off1[2] = {0, m};
+  const Plan *pl;
+  uint64_t key;
+  rc = cached_plan(ctx, ctx->pair_plans, kOpPair, off0, 1, off1, 1, dim, exact, &pl, key);
+  if (rc) return rc;
+  if (pl->max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
+  ctx->last = ffd_launch_info{pl->R, pl->nwaves, pl->wpb, lds_bytes(pl->R, dim, exact, pl->hcap), exact ? 1 : 0,
+                              dim, pl->max_steps};
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
-  e = ffd::launch_stream(exact, bestR, dim, a, 1, st);
-  if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
-  return FFD_OK;
+  if (pl->nwaves == 1 && pl->link_elems == 0) {
+    // one stream: the job travels in the kernel arguments, no device memory
+    KernelArgs a;
+    memset(&a, 0, sizeof a);
+    a.X[0] = p;
+    a.X[1] = q;
+    a.inl_off[0][0] = 0;
+    a.inl_off[0][1] = n;
+    a.inl_off[1][0] = 0;
+    a.inl_off[1][1] = m;
+    a.jobs = nullptr;
+    a.inl_job = pl->jobs[0];
+    a.out = out;
+    a.nwaves = 1;
+    a.metric = metric;
+    a.hcap = (int32_t)pl->hcap;
+    a.lds_per_wave = lds_bytes(pl->R, dim, exact, pl->hcap);
+    a.max_steps = (int32_t)(pl->max_steps + 4 * ffd::kRing);
+    a.epoch = ++ctx->epoch;
+    e = ffd::launch_stream(exact, pl->R, dim, a, 1, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+    ctx->last_err = nullptr;
+    return FFD_OK;
+  }
+  // bands split over waves: the plan and the links live in the context's scratch
+  WsLayout wl = ws_layout(*pl, 1, 1, exact);
+  if (ctx->scratch_bytes < wl.total) {
+    if (ctx->scratch) {
+      hipStreamSynchronize(st);
+      hipFree(ctx->scratch);
+      ctx->scratch = nullptr;
+      ctx->scratch_bytes = 0;
+      ctx->plan_ws = nullptr;
+    }
+    e = hipMalloc(&ctx->scratch, wl.total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc (scratch for a long pair)");
+    ctx->scratch_bytes = wl.total;
+  }
+  return run_plan(ctx, *pl, key, p, off0, 1, q, off1, 1, dim, exact, metric, out, ctx->scratch,
+                  ctx->scratch_bytes, st);
 }
 
 int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *Q, const int64_t *q_off,
-                 int64_t npairs, int32_t dim, int32_t metric, void *out, void *ws, size_t ws_bytes,
-                 hipStream_t st, bool exact) {
+                 int64_t npairs, int32_t dim, int32_t metric, void *out, void *ws, size_t ws_bytes, hipStream_t st,
+                 bool exact) {
   int rc = check_common(ctx, dim, metric, exact);
   if (rc) return rc;
   if (npairs < 0) return fail(ctx, FFD_E_INVALID, "npairs < 0");
@@ -500,11 +670,8 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   if ((rc = check_offsets(ctx, q_off, npairs, "q_off is NULL"))) return rc;
   const Plan *pl;
   uint64_t key;
-  rc = cached_plan(ctx, plans_of(ctx), FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
+  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
   if (rc) return rc;
-  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st);
 }
 
@@ -515,17 +682,15 @@ int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq,
   if (rc) return rc;
   if (nq < 0 || ndb < 0) return fail(ctx, FFD_E_INVALID, "negative count");
   if (nq == 0 || ndb == 0) return FFD_OK;
-  if (nq > INT32_MAX / 2 || ndb > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many curves");
+  if (nq > INT32_MAX / 2 || ndb > INT32_MAX / 2 || nq * ndb > ((int64_t)1 << 40))
+    return fail(ctx, FFD_E_UNSUPPORTED, "too many curves");
   if (!Qs || !DB || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
   if ((rc = check_offsets(ctx, q_off, nq, "q_off is NULL"))) return rc;
   if ((rc = check_offsets(ctx, db_off, ndb, "db_off is NULL"))) return rc;
   const Plan *pl;
   uint64_t key;
-  rc = cached_plan(ctx, plans_of(ctx), FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key);
+  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key);
   if (rc) return rc;
-  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st);
 }
 
@@ -563,6 +728,8 @@ int ffd_create(int device, ffd_ctx **out) {
   c->device = device;
   c->cus = prop.multiProcessorCount;
   c->lds_block_max = prop.sharedMemPerBlock < 65536 ? prop.sharedMemPerBlock : 65536;
+  c->lds_cu = prop.maxSharedMemoryPerMultiProcessor > 0 ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+  c->epoch = (uint32_t)std::chrono::steady_clock::now().time_since_epoch().count() | 1u;
   *out = c;
   return FFD_OK;
 }
@@ -575,7 +742,9 @@ int ffd_create_planner(int32_t compute_units, int64_t lds_per_block, ffd_ctx **o
   if (!c) return FFD_E_NOMEM;
   c->device = -1;
   c->cus = compute_units;
-  c->lds_block_max = (size_t)lds_per_block;
+  c->lds_block_max = (size_t)std::min<int64_t>(lds_per_block, 65536);
+  c->lds_cu = (size_t)lds_per_block;
+  c->epoch = 1;
   *out = c;
   return FFD_OK;
 }
@@ -587,14 +756,35 @@ void ffd_destroy(ffd_ctx *ctx) {
     hipEventDestroy(ctx->upload_done);
   }
   if (ctx->pinned) hipHostFree(ctx->pinned);
-
+  if (ctx->scratch) {
+    hipDeviceSynchronize();
+    hipFree(ctx->scratch);
+  }
   delete ctx;
+}
+
+int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info) {
+  if (!ctx || !info) return FFD_E_INVALID;
+  *info = ctx->last;
+  return FFD_OK;
+}
+
+int ffd_last_errors(ffd_ctx *ctx, int32_t *flags) {
+  if (!ctx || !flags) return FFD_E_INVALID;
+  *flags = 0;
+  if (!ctx->last_err) return FFD_OK;
+  hipError_t e = hipStreamSynchronize(ctx->last_stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  uint64_t word = 0;
+  e = hipMemcpy(&word, ctx->last_err, sizeof word, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy (error word)");
+  if ((uint32_t)(word >> 32) == ctx->last_epoch) *flags = (int32_t)(uint32_t)word;
+  return FFD_OK;
 }
 
 int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd) {
   if (!ctx) return FFD_E_INVALID;
-  if (rows_per_lane != 0 && rows_per_lane != 1 && rows_per_lane != 2 && rows_per_lane != 4 &&
-      rows_per_lane != 8)
+  if (rows_per_lane != 0 && rows_per_lane != 1 && rows_per_lane != 2 && rows_per_lane != 4 && rows_per_lane != 8)
     return fail(ctx, FFD_E_INVALID, "rows_per_lane must be 0, 1, 2, 4 or 8");
   if (waves_per_simd < 0 || waves_per_simd > 8) return fail(ctx, FFD_E_INVALID, "waves_per_simd must be 0..8");
   ctx->tune_R = rows_per_lane;
@@ -602,8 +792,15 @@ int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd) 
   return FFD_OK;
 }
 
-int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim,
-                 int32_t metric, float *out, void *stream) {
+int ffd_set_split(ffd_ctx *ctx, float share) {
+  if (!ctx) return FFD_E_INVALID;
+  if (!(share == share) || share > 1e6f) return fail(ctx, FFD_E_INVALID, "share must be a finite number");
+  ctx->split = share;
+  return FFD_OK;
+}
+
+int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim, int32_t metric,
+                 float *out, void *stream) {
   return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
 }
 
@@ -615,15 +812,15 @@ int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q
 int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
               int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
               void *stream) {
-  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes,
-                      (hipStream_t)stream, false);
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
+                      false);
 }
 
-int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
-                  const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, int64_t *out,
-                  void *workspace, size_t ws_bytes, void *stream) {
-  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes,
-                      (hipStream_t)stream, true);
+int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
+                  int64_t npairs, int32_t dim, int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
+                  void *stream) {
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
+                      true);
 }
 
 int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, const float *DB,
@@ -634,14 +831,14 @@ int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, c
 }
 
 int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
-                  const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int64_t *out,
-                  void *workspace, size_t ws_bytes, void *stream) {
+                  const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int64_t *out, void *workspace,
+                  size_t ws_bytes, void *stream) {
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
                       (hipStream_t)stream, true);
 }
 
-int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off,
-                       int64_t nb, int32_t dim, size_t *bytes) {
+int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
+                       int32_t dim, size_t *bytes) {
   if (!ctx || !bytes) return FFD_E_INVALID;
   if (op != FFD_OP_BATCH && op != FFD_OP_CROSS) return fail(ctx, FFD_E_INVALID, "unknown op");
   if (dim < 1) return fail(ctx, FFD_E_INVALID, "dim must be >= 1");
@@ -661,7 +858,7 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
     rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, dim, ex == 1, &pl, key);
     if (rc == FFD_E_UNSUPPORTED) continue;
     if (rc) return rc;
-    worst = std::max(worst, ws_layout(pl->jobs.size(), pl->nwaves, na, nb).total);
+    worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
   }
   if (worst == 0) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;

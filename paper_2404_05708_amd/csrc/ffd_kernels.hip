@@ -82,16 +82,23 @@ struct Num<double> {
   }
 };
 
-// Task descriptor kept in LDS (32 bytes).
+// Task descriptor kept in LDS (64 bytes).
+enum : int32_t { kHinGhost = 0, kHinHand = 1, kHinLink = 2 };   // where lane 0's row above comes from
+enum : int32_t { kHoutSink = 0, kHoutHand = 1, kHoutLink = 2 }; // where lane 63's bottom row goes
 struct Desc {
-  int32_t S;          // stream position of the separator
-  int32_t L;          // stream length
-  int32_t ghost;      // 1: lane 0 reads the top boundary, 0: the hand-off row
-  int32_t hand_out;   // 1: lane 63 writes the hand-off row for the next task
+  int32_t S;           // stream position of the separator
+  int32_t L;           // stream length
+  int32_t hin, hout;   // boundary modes
   int32_t out_lo, out_hi;  // result index, -1 = none
-  int32_t drain;      // 1: padding task after the last job
+  int32_t drain;       // 1: padding task after the last job
+  int32_t flag_in, flag_out;
+  int32_t rel_in;      // entries of the incoming link before this task's row
+  int32_t rel_out;     // entries of the outgoing link before this task's row
   int32_t pad;
+  int64_t link_in;     // element of this task's incoming boundary row (x = 0)
+  int64_t link_out;    // element of this task's outgoing boundary row
 };
+static_assert(sizeof(Desc) == 64, "descriptor size");
 
 __device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int64_t uni64(int64_t x) {
@@ -99,6 +106,10 @@ __device__ __forceinline__ int64_t uni64(int64_t x) {
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+
+// Bound of a link wait: s_sleep 2 is about 128 clocks, so about 2^29 clocks
+// (a quarter of a second) before the wait is abandoned and reported.
+constexpr int kSpinLimit = 1 << 22;
 
 template <int R, int D, typename V>
 struct Stream {
@@ -117,20 +128,27 @@ struct Stream {
   // ---- fill cursor: enumerates tasks (job, column curve, band) --------------
   int32_t j, jend;          // job range of this wave
   int32_t c, b, nb;         // column curve within the job, band, bands of the row curve
-  int32_t row_sel, col_sel, col_first, col_count, out_stride;
-  int64_t row_off, n, out_base;
+  int32_t b_first, b_end;   // band range of the job
+  int32_t row_sel, col_sel, col_first, col_count, out_stride, flag_in, flag_out;
+  int64_t row_off, n, out_base, link_in, link_out, link_rel;
   bool exhausted;
   int32_t next_id;          // id of the next task to create
   // task covering the current fill chunk start, and the one after it
-  int32_t cS, cL, cdrain, ccol_sel; int64_t ccol_off, cm;
-  int32_t xS, xL, xdrain, xcol_sel; int64_t xcol_off, xm;
+  struct FillTask {
+    int32_t S, L, drain, col_sel, hin, flag_in, rel;
+    int64_t col_off, m, link_in;
+  };
+  FillTask cur, nxt;
   bool has_next;
   // per-lane prefetch registers
   C qbuf[D];
   bool qsep;
+  V hbuf;
+  int32_t hslot;            // stream position of an incoming link value (-1: none)
   C ptmp[R][D];
   bool ptmp_pending;
   int32_t ptmp_slot;
+  int32_t err;
 
   __device__ Stream(const KernelArgs &args, int lane_, unsigned char *b_) : a(args), lane(lane_), base(b_) {}
 
@@ -138,8 +156,10 @@ struct Stream {
   __device__ V *ghost() const { return reinterpret_cast<V *>(base + lay.ghost); }
   __device__ V *sink() const { return reinterpret_cast<V *>(base + lay.sink); }
   __device__ V *hand() const { return reinterpret_cast<V *>(base + lay.hand); }
+  __device__ V *lring() const { return reinterpret_cast<V *>(base + lay.lring); }
   __device__ V *pst(int slot) const { return reinterpret_cast<V *>(base + lay.pst) + slot * (kWave * R * D); }
   __device__ Desc *desc(int id) const { return reinterpret_cast<Desc *>(base + lay.desc) + (id & (kDescSlots - 1)); }
+  __device__ V *links() const { return static_cast<V *>(a.links); }
 
   // Kernel-argument arrays are only indexed with selects: a dynamic index
   // would make the compiler copy the arguments to scratch memory.
@@ -156,7 +176,7 @@ struct Stream {
   }
 
   __device__ void load_job(int32_t jj) {
-    int32_t ri;
+    int32_t ri, bf, bc;
     if (a.jobs) {
       const Job *jb = a.jobs + jj;
       row_sel = uni(jb->row_sel);
@@ -166,6 +186,12 @@ struct Stream {
       col_count = uni(jb->col_count);
       out_stride = uni(jb->out_stride);
       out_base = uni64(jb->out_base);
+      link_in = uni64(jb->link_in);
+      link_out = uni64(jb->link_out);
+      bf = uni(jb->band_first);
+      bc = uni(jb->band_count);
+      flag_in = uni(jb->flag_in);
+      flag_out = uni(jb->flag_out);
     } else {
       row_sel = a.inl_job.row_sel;
       ri = a.inl_job.row_idx;
@@ -174,42 +200,61 @@ struct Stream {
       col_count = a.inl_job.col_count;
       out_stride = a.inl_job.out_stride;
       out_base = a.inl_job.out_base;
+      link_in = a.inl_job.link_in;
+      link_out = a.inl_job.link_out;
+      bf = a.inl_job.band_first;
+      bc = a.inl_job.band_count;
+      flag_in = a.inl_job.flag_in;
+      flag_out = a.inl_job.flag_out;
     }
     row_off = uni64(curve_off(row_sel, ri));
     n = uni64(curve_off(row_sel, ri + 1)) - row_off;
     nb = (int32_t)bands_for(n, R);
+    b_first = bf;
+    b_end = bc > 0 && bf + bc < nb ? bf + bc : nb;
     c = 0;
-    b = 0;
+    b = b_first;
+    link_rel = 0;
   }
 
-  // Create the next task in stream order starting at position S.  Writes its
-  // descriptor, issues the loads of its band rows into ptmp, and returns its
-  // stream parameters through the output references.
-  __device__ void make_task(int32_t S, int32_t &L, int32_t &drain, int32_t &csel, int64_t &coff,
-                            int64_t &m) {
+  // Create the next task in stream order starting at position S: write its
+  // descriptor, issue the loads of its band rows into ptmp, return its
+  // stream parameters.
+  __device__ void make_task(int32_t S, FillTask &t) {
     int32_t id = next_id++;
     Desc d;
     d.S = S;
     d.pad = 0;
+    d.rel_in = d.rel_out = 0;
+    t.S = S;
+    t.rel = 0;
     if (exhausted) {
-      L = kMinTask;
-      drain = 1;
-      csel = 0;
-      coff = 0;
-      m = 1;
-      d.L = L; d.ghost = 1; d.hand_out = 0; d.out_lo = -1; d.out_hi = -1; d.drain = 1;
+      t.L = kMinTask; t.drain = 1; t.col_sel = 0; t.col_off = 0; t.m = 1;
+      t.hin = kHinGhost; t.flag_in = -1; t.link_in = 0;
+      d.L = t.L; d.hin = kHinGhost; d.hout = kHoutSink; d.out_lo = -1; d.out_hi = -1; d.drain = 1;
+      d.flag_in = -1; d.flag_out = -1; d.link_in = 0; d.link_out = 0;
     } else {
       int32_t k = col_first + c;
-      coff = uni64(curve_off(col_sel, k));
-      m = uni64(curve_off(col_sel, k + 1)) - coff;
-      csel = col_sel;
-      bool chained = nb > 1;
-      L = (int32_t)task_len(m, chained);
-      drain = 0;
+      t.col_off = uni64(curve_off(col_sel, k));
+      t.m = uni64(curve_off(col_sel, k + 1)) - t.col_off;
+      t.col_sel = col_sel;
+      t.L = (int32_t)task_len(t.m, nb > 1);
+      t.drain = 0;
       int64_t oi = (b == nb - 1) ? out_base + (int64_t)c * out_stride : -1;
-      d.L = L; d.ghost = b == 0; d.hand_out = b + 1 < nb; d.drain = 0;
+      int32_t hin = b == 0 ? kHinGhost : (b == b_first ? kHinLink : kHinHand);
+      int32_t hout = b == nb - 1 ? kHoutSink : (b + 1 == b_end ? kHoutLink : kHoutHand);
+      t.hin = hin;
+      t.flag_in = flag_in;
+      t.link_in = link_in + link_rel;
+      t.rel = (int32_t)link_rel;
+      d.rel_in = d.rel_out = (int32_t)link_rel;
+      d.L = t.L; d.hin = hin; d.hout = hout; d.drain = 0;
       d.out_lo = (int32_t)(uint32_t)(uint64_t)oi;
       d.out_hi = (int32_t)(uint32_t)((uint64_t)oi >> 32);
+      d.flag_in = flag_in;
+      d.flag_out = flag_out;
+      d.link_in = link_in + link_rel;
+      d.link_out = link_out + link_rel;
       // band rows of this lane, clamped to the last point (repetition is exact)
       const C *X = coords(row_sel);
       int64_t r0 = (int64_t)b * kWave * R + (int64_t)lane * R;
@@ -223,8 +268,9 @@ struct Stream {
       ptmp_pending = true;
       ptmp_slot = id & 1;
       // advance: next band, next column curve, next job
-      if (++b == nb) {
-        b = 0;
+      if (++b == b_end) {
+        b = b_first;
+        link_rel += t.L;
         if (++c == col_count) {
           if (++j == jend) exhausted = true;
           else load_job(j);
@@ -234,28 +280,51 @@ struct Stream {
     if (lane == 0) *desc(id) = d;
   }
 
-  // Issue the global loads of ring entries [t, t + 64): one per lane.
-  __device__ void fill_load(int32_t t) {
-    while (cS + cL <= t) {
-      if (!has_next) {
-        make_task(cS + cL, xL, xdrain, xcol_sel, xcol_off, xm);
-        xS = cS + cL;
+  // Wait until the link flag reports at least `need` entries of this launch.
+  __device__ void wait_link(int32_t flag, uint32_t need) {
+    uint64_t want = flag_word(a.epoch, need);
+    uint64_t *f = a.flags + flag;
+    for (int it = 0;; ++it) {
+      uint64_t v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint32_t)(v >> 32) == a.epoch && v >= want) break;
+      if (it == kSpinLimit) {
+        err |= 2;
+        break;
       }
-      cS = xS; cL = xL; cdrain = xdrain; ccol_sel = xcol_sel; ccol_off = xcol_off; cm = xm;
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+
+  // Issue the global loads of ring entries [t, t + 64): one per lane, plus
+  // the incoming boundary values of tasks whose band above ran on another
+  // wave (after waiting for them to be published).
+  __device__ void fill_load(int32_t t) {
+    while (cur.S + cur.L <= t) {
+      if (!has_next) make_task(cur.S + cur.L, nxt);
+      cur = nxt;
       has_next = false;
     }
-    if (cS + cL < t + kFill && !has_next) {
-      xS = cS + cL;
-      make_task(xS, xL, xdrain, xcol_sel, xcol_off, xm);
+    if (cur.S + cur.L < t + kFill && !has_next) {
+      make_task(cur.S + cur.L, nxt);
       has_next = true;
     }
+    if (cur.hin == kHinLink) {
+      int32_t hi = t + kFill - cur.S;
+      wait_link(cur.flag_in, (uint32_t)(cur.rel + (hi < cur.L ? hi : cur.L)));
+    }
+    if (has_next && nxt.hin == kHinLink) {
+      int32_t hi = t + kFill - nxt.S;
+      if (hi > 0) wait_link(nxt.flag_in, (uint32_t)(nxt.rel + (hi < nxt.L ? hi : nxt.L)));
+    }
     int32_t tau = t + lane;
-    bool nxt = tau >= cS + cL;
-    int32_t x = tau - (nxt ? xS : cS);
-    int64_t m = nxt ? xm : cm;
-    int64_t co = nxt ? xcol_off : ccol_off;
-    int32_t sel = nxt ? xcol_sel : ccol_sel;
-    bool drain = nxt ? xdrain : cdrain;
+    bool in_next = tau >= cur.S + cur.L;
+    int32_t x = tau - (in_next ? nxt.S : cur.S);
+    int64_t m = in_next ? nxt.m : cur.m;
+    int64_t co = in_next ? nxt.col_off : cur.col_off;
+    int32_t sel = in_next ? nxt.col_sel : cur.col_sel;
+    bool drain = in_next ? nxt.drain : cur.drain;
+    bool glink = (in_next ? nxt.hin : cur.hin) == kHinLink;
+    int64_t lk = in_next ? nxt.link_in : cur.link_in;
     qsep = drain || x == 0;
     int64_t idx = x - 1;
     if (idx > m - 1) idx = m - 1;
@@ -265,10 +334,12 @@ struct Stream {
     const C *pt = X + (co + idx) * D;
 #pragma unroll
     for (int k2 = 0; k2 < D; ++k2) qbuf[k2] = pt[k2];
+    hslot = glink ? tau : -1;  // the link ring is indexed by stream position
+    if (glink) hbuf = __hip_atomic_load(links() + lk + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
   // Write the entries loaded by the previous fill_load (for positions
-  // [t, t + 64)) and any pending band rows.
+  // [t, t + 64)), incoming boundary values and any pending band rows.
   __device__ void fill_write(int32_t t) {
     Pt e;
 #pragma unroll
@@ -276,6 +347,11 @@ struct Stream {
     int slot = (t + lane) & (kRing - 1);
     ring()[slot] = e;
     if (slot < kGroup) ring()[slot + kRing] = e;
+    if (hslot >= 0) {
+      int ls = hslot & (kLinkRing - 1);
+      lring()[ls] = hbuf;
+      if (ls < kGroup) lring()[ls + kLinkRing] = hbuf;
+    }
     if (ptmp_pending) {
       V *dst = pst(ptmp_slot) + lane * (R * D);
 #pragma unroll
@@ -286,34 +362,64 @@ struct Stream {
     }
   }
 
-  template <bool WINDOW>
-  __device__ __forceinline__ void group(int32_t t0, int32_t win0, const V *hin, V *hout,
-                                        V (&p)[R][D], const V (&pn)[R][D], V (&Mp)[R], V &upPrev,
-                                        V &res) {
-    const Pt *qr = ring() + ((t0 - lane) & (kRing - 1));
+  // Column points and top-boundary values of one group of kGroup steps,
+  // read from LDS one group ahead of their use.
+  struct GroupIn {
+    Pt q[kGroup];
+    V h[kGroup];
+  };
+
+  __device__ __forceinline__ void load_group(int32_t t, const V *hin, GroupIn &g) const {
+    const Pt *qr = ring() + ((t - lane) & (kRing - 1));
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
-      Pt q = qr[u];
-      V h = hin[u];
+      g.q[u] = qr[u];
+      g.h[u] = hin[u];
+    }
+  }
+
+  // Row state of the lane: the R rows it holds, the rows of the next task,
+  // the left neighbours (previous column) and the previous top value.
+  V p[R][D], pn[R][D], Mp[R];
+  V upPrev;
+  // lane-0 cursor (task containing the group being loaded) and window start
+  int32_t id0, S0, L0, g0, win0, win_cur;
+  // lane-63 cursor: task containing column t0 - 64
+  int32_t id63, S63, L63, hout63, flag63, rel63;
+  int64_t out63, link63;
+
+  template <bool WINDOW, bool LINK>
+  __device__ __forceinline__ void group(int32_t t0, int32_t win, const GroupIn &g, V *hout, V *lout,
+                                        V &res) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
       V bottom = Mp[R - 1];
-      if (lane == kWave - 1) hout[u] = bottom;
+      if (lane == kWave - 1) {
+        hout[u] = bottom;
+        // link rows cross XCDs, whose L2 caches are not coherent with each
+        // other: store and load them at agent scope (coherent point)
+        if (LINK) __hip_atomic_store(lout + u, bottom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (u == kGroup - 1) res = bottom;
       if (WINDOW) {
-        bool sw = lane == t0 + u - win0;
+        bool sw = lane == t0 + u - win;
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int k2 = 0; k2 < D; ++k2) p[r][k2] = sw ? pn[r][k2] : p[r][k2];
       }
-      V up = N::shift_in(h, bottom);
+      V up = N::shift_in(g.h[u], bottom);
+#ifdef FFD_DEBUG_HIN
+      if (lane == 0) static_cast<float *>(a.out)[1 + dbg_wave * 4096 + ((t0 + u) & 4095)] = (float)g.h[u];
+#endif
       V dd[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        V t = p[r][0] - q.c[0];
+        V t = p[r][0] - g.q[u].c[0];
         V s = t * t;
 #pragma unroll
         for (int k2 = 1; k2 < D; ++k2) {
-          V w = p[r][k2] - q.c[k2];
+          V w = p[r][k2] - g.q[u].c[k2];
           s = N::fma(w, w, s);
         }
         dd[r] = s;
@@ -330,7 +436,102 @@ struct Stream {
     }
   }
 
+  // Address of lane 0's top-boundary values for the group starting at t.
+  // The byte offset is formed with integer selects: a chain of pointer
+  // returns here was compiled (ROCm 7.2) into code that read the address
+  // from an undefined register on the link path.
+  __device__ __forceinline__ const V *hin_at(int32_t t) const {
+    int32_t og = lay.ghost + (t == S0 ? 0 : (int32_t)sizeof(V));
+    int32_t oh = lay.hand + (t - S0) * (int32_t)sizeof(V);
+    int32_t ol = lay.lring + (t & (kLinkRing - 1)) * (int32_t)sizeof(V);
+    int32_t off = g0 == kHinGhost ? og : (g0 == kHinHand ? oh : ol);
+    return reinterpret_cast<const V *>(base + off);
+  }
+
+  // Advance lane 0's cursor to the group starting at t; at a task start,
+  // read the task's rows (pn) for the switch window.
+  __device__ __forceinline__ void lane0_to(int32_t t) {
+    if (t == S0 + L0) {
+      ++id0;
+      Desc d = *desc(id0);
+      S0 = uni(d.S);
+      L0 = uni(d.L);
+      g0 = uni(d.hin);
+      win0 = t;
+      const V *src = pst(id0 & 1) + lane * (R * D);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) pn[r][k2] = src[r * D + k2];
+    }
+  }
+
+  // Publish that the first `count` entries of lane 63's outgoing link row
+  // are in global memory (release: the stores above become visible first).
+  __device__ __forceinline__ void publish(int32_t count) {
+    if (lane == 0)
+      __hip_atomic_store(a.flags + flag63, flag_word(a.epoch, (uint32_t)(rel63 + count)),
+                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  // One group: refill the ring, move the lane-63 cursor, prefetch the next
+  // group into `nxt`, compute this group from `cur`.  Returns false when the
+  // stream has ended.
+  __device__ __forceinline__ bool step(int32_t t0, const GroupIn &curg, GroupIn &nxtg) {
+    if (t0 > a.max_steps) {  // guard: the plan bounds every stream's length
+      err |= 1;
+      return false;
+    }
+    if ((t0 & (kFill - 1)) == 0) {
+      if (hout63 == kHoutLink) {
+        int32_t done = t0 - kWave - S63;  // columns of lane 63's task already stored
+        if (done > 0) publish(done < L63 ? done : L63);
+      }
+      fill_write(t0 + kFill);
+      fill_load(t0 + 2 * kFill);
+    }
+    if (t0 - kWave == S63 + L63) {
+      if (hout63 == kHoutLink) publish(L63);
+      ++id63;
+      Desc d = *desc(id63);
+      if (uni(d.drain)) return false;
+      S63 = uni(d.S);
+      L63 = uni(d.L);
+      hout63 = uni(d.hout);
+      flag63 = uni(d.flag_out);
+      rel63 = uni(d.rel_out);
+      link63 = uni64(d.link_out);
+      out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
+    }
+    int32_t x63 = t0 - kWave - S63;
+    int32_t hoff = hout63 == kHoutHand ? lay.hand + x63 * (int32_t)sizeof(V) : lay.sink;
+    V *hout = reinterpret_cast<V *>(base + hoff);
+    V *lout = links() + link63 + x63;
+    int32_t win = win_cur;
+    lane0_to(t0 + kGroup);
+    load_group(t0 + kGroup, hin_at(t0 + kGroup), nxtg);
+    win_cur = win0;
+    V res;
+    bool window = t0 < win + kWave;
+    if (hout63 == kHoutLink) {
+      if (window) group<true, true>(t0, win, curg, hout, lout, res);
+      else group<false, true>(t0, win, curg, hout, lout, res);
+    } else {
+      if (window) group<true, false>(t0, win, curg, hout, lout, res);
+      else group<false, false>(t0, win, curg, hout, lout, res);
+    }
+    if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
+      N::store(a.out, out63, res, a.metric);
+    return true;
+  }
+
+#ifdef FFD_DEBUG_HIN
+  int32_t dbg_wave;
+#endif
   __device__ void run(int32_t wave) {
+#ifdef FFD_DEBUG_HIN
+    dbg_wave = wave;
+#endif
     lay = lds_layout(R, D, (int)sizeof(V), a.hcap);
     if (a.jobs) {
       j = uni(a.wave_jobs[wave]);
@@ -340,10 +541,12 @@ struct Stream {
       jend = wave == 0 ? 1 : 0;
     }
     if (j >= jend) return;
+    err = 0;
     exhausted = false;
     next_id = 0;
     has_next = false;
     ptmp_pending = false;
+    hslot = -1;
     load_job(j);
 
     // constant LDS: top boundary and ring entries before the stream start;
@@ -357,67 +560,42 @@ struct Stream {
       ring()[kRing - kWave + lane] = e;  // positions -64 .. -1
     }
     // first task and the first two ring chunks
-    cS = 0;
-    make_task(0, cL, cdrain, ccol_sel, ccol_off, cm);
+    make_task(0, cur);
     fill_load(0);
+#ifdef FFD_DEBUG_HIN
+    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + lane] = (float)hbuf;
+    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + 64 + lane] = (float)hslot;
+#endif
     fill_write(0);
+#ifdef FFD_DEBUG_HIN
+    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + 128 + lane] = (float)lring()[lane];
+#endif
     fill_load(kFill);
 
-    V p[R][D], pn[R][D], Mp[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       Mp[r] = N::inf();
 #pragma unroll
       for (int k2 = 0; k2 < D; ++k2) p[r][k2] = V(0);
     }
-    V upPrev = N::inf();
+    upPrev = N::inf();
+    id0 = -1; S0 = 0; L0 = 0; g0 = kHinGhost; win0 = 0;
+    id63 = -1; S63 = -kWave; L63 = kWave; hout63 = kHoutSink; flag63 = -1; rel63 = 0; out63 = -1;
+    link63 = 0;
 
-    // lane-0 cursor: task containing the group's first step
-    int32_t id0 = -1, S0 = 0, L0 = 0, g0 = 1, win0 = 0;
-    // lane-63 cursor: task containing column t0 - 64 (starts in a pseudo-task)
-    int32_t id63 = -1, S63 = -kWave, L63 = kWave, hand63 = 0;
-    int64_t out63 = -1;
-
-    for (int32_t t0 = 0;; t0 += kGroup) {
-      if (t0 > a.max_steps) break;  // guard: the plan bounds every stream's length
-      if ((t0 & (kFill - 1)) == 0) {
-        fill_write(t0 + kFill);
-        fill_load(t0 + 2 * kFill);
-      }
-      if (t0 - kWave == S63 + L63) {
-        ++id63;
-        Desc d = *desc(id63);
-        if (uni(d.drain)) break;
-        S63 = uni(d.S);
-        L63 = uni(d.L);
-        hand63 = uni(d.hand_out);
-        out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
-      }
-      bool window = false;
-      if (t0 == S0 + L0) {
-        ++id0;
-        Desc d = *desc(id0);
-        S0 = uni(d.S);
-        L0 = uni(d.L);
-        g0 = uni(d.ghost);
-        win0 = t0;
-        const V *src = pst(id0 & 1) + lane * (R * D);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int k2 = 0; k2 < D; ++k2) pn[r][k2] = src[r * D + k2];
-      }
-      window = t0 < win0 + kWave;
-      const V *hin = g0 ? ghost() + (t0 == S0 ? 0 : 1) : hand() + (t0 - S0);
-      V *hout = hand63 ? hand() + (t0 - kWave - S63) : sink();
-      V res;
-      if (window)
-        group<true>(t0, win0, hin, hout, p, pn, Mp, upPrev, res);
-      else
-        group<false>(t0, win0, hin, hout, p, pn, Mp, upPrev, res);
-      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
-        N::store(a.out, out63, res, a.metric);
+    GroupIn A, B;
+    lane0_to(0);
+    win_cur = win0;
+    load_group(0, hin_at(0), A);
+    for (int32_t t0 = 0;;) {
+      if (!step(t0, A, B)) break;
+      t0 += kGroup;
+      if (!step(t0, B, A)) break;
+      t0 += kGroup;
     }
+    if (err && lane == 0 && a.err)
+      atomicMax(reinterpret_cast<unsigned long long *>(a.err),
+                (unsigned long long)flag_word(a.epoch, (uint32_t)err));
   }
 };
 
@@ -466,6 +644,38 @@ static hipError_t launch_r(int R, int D, const KernelArgs &a, int wpb, hipStream
 
 hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, hipStream_t st) {
   return exact ? launch_r<double>(R, D, a, wpb, st) : launch_r<float>(R, D, a, wpb, st);
+}
+
+template <int R, int D, typename V>
+static hipError_t occ_t(int wpb, size_t lds, int *blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, stream_kernel<R, D, V>, wpb * kWave, lds);
+}
+
+template <int R, typename V>
+static hipError_t occ_d(int D, int wpb, size_t lds, int *blocks) {
+  switch (D) {
+    case 1: return occ_t<R, 1, V>(wpb, lds, blocks);
+    case 2: return occ_t<R, 2, V>(wpb, lds, blocks);
+    case 3: return occ_t<R, 3, V>(wpb, lds, blocks);
+    case 4: return occ_t<R, 4, V>(wpb, lds, blocks);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename V>
+static hipError_t occ_r(int R, int D, int wpb, size_t lds, int *blocks) {
+  switch (R) {
+    case 1: return occ_d<1, V>(D, wpb, lds, blocks);
+    case 2: return occ_d<2, V>(D, wpb, lds, blocks);
+    case 4: return occ_d<4, V>(D, wpb, lds, blocks);
+    case 8: return occ_d<8, V>(D, wpb, lds, blocks);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Workgroups of `wpb` waves using `lds` bytes that one CU holds at once.
+hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu) {
+  return exact ? occ_r<double>(R, D, wpb, lds, blocks_per_cu) : occ_r<float>(R, D, wpb, lds, blocks_per_cu);
 }
 
 }  // namespace ffd

@@ -9,7 +9,13 @@
 // column followed by the column curve's points, so the lanes move from one
 // task to the next without draining.  A wave runs the tasks of its jobs back
 // to back; a job is one row curve against a contiguous range of column
-// curves, every column curve in turn, every band of the row curve in turn.
+// curves, every column curve in turn, a range of bands of the row curve in
+// turn.  Consecutive bands on one wave hand the bottom row of one band to
+// the next through LDS; when the bands of a row curve are split over
+// several waves, the last band of one wave's range writes its bottom row to
+// a link buffer in global memory and publishes its progress with a release
+// store, and the wave holding the next band reads it after an acquire load
+// (a "link").
 #pragma once
 #include <stdint.h>
 
@@ -25,19 +31,30 @@ constexpr int kWave = 64;            // lanes per wavefront
 constexpr int kGroup = 8;            // steps per unrolled group; task lengths are multiples
 constexpr int kRing = 256;           // column ring entries per wave (power of two)
 constexpr int kFill = 64;            // steps between ring refills (= one entry per lane)
-constexpr int kMinTask = 64;         // shortest task stream
+constexpr int kMinTask = 72;         // shortest task stream (> 64: a task's rows are read one group early)
 constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
 constexpr int kDescSlots = 8;        // task descriptors in flight per wave
+constexpr int kLinkRing = 256;       // LDS ring for boundary rows arriving over a link
 
-struct Job {           // 32 bytes, device-resident plan entry
+struct Job {           // 64 bytes, device-resident plan entry
   int64_t out_base;    // output index of the first column curve of the job
+  int64_t link_in;     // first element of the incoming link buffer (-1: none)
+  int64_t link_out;    // first element of the outgoing link buffer (-1: none)
   int32_t row_sel;     // which coordinate array holds the row curve (0 or 1)
   int32_t row_idx;     // index of the row curve in that array's offsets
   int32_t col_sel;     // which array holds the column curves
   int32_t col_first;   // first column curve
   int32_t col_count;   // number of column curves
   int32_t out_stride;  // output index step between consecutive column curves
+  int32_t band_first;  // bands [band_first, band_first + band_count) of the row curve
+  int32_t band_count;  // (band_count <= 0: all bands from band_first on)
+  int32_t flag_in;     // progress flag of the incoming link (-1: none)
+  int32_t flag_out;    // progress flag of the outgoing link (-1: none)
 };
+
+// Progress flags hold (epoch << 32) | entries published; the epoch changes
+// with every launch, so flags never need clearing.
+FFD_HD uint64_t flag_word(uint32_t epoch, uint32_t count) { return ((uint64_t)epoch << 32) | count; }
 
 // Bands of 64*R rows needed for a row curve of n points.
 FFD_HD int64_t bands_for(int64_t n, int R) { return (n + (int64_t)kWave * R - 1) / ((int64_t)kWave * R); }
@@ -57,9 +74,10 @@ struct LdsLayout {
   int ring;   // (kRing + kGroup) column points; the last kGroup mirror the first
   int ghost;  // kGroup + 1 values: -inf, +inf, ... (top boundary of a first band)
   int sink;   // kGroup values written when a band hands nothing on
-  int hand;   // hcap values: bottom row of the band above
+  int hand;   // hcap values: bottom row of the band above (same wave)
+  int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
   int pst;    // two slots of 64 * R * D row coordinates (next task's rows)
-  int desc;   // kDescSlots task descriptors of 32 bytes
+  int desc;   // kDescSlots task descriptors of 64 bytes
   int total;
 };
 
@@ -73,8 +91,9 @@ FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
   L.ghost = o; o += (kGroup + 1) * vsize;
   L.sink = o;  o += kGroup * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
+  o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;
   o = align16(o); L.pst = o;  o += 2 * kWave * R * D * vsize;
-  o = align16(o); L.desc = o; o += kDescSlots * 32;
+  o = align16(o); L.desc = o; o += kDescSlots * 64;
   L.total = align16(o);
   return L;
 }
@@ -92,6 +111,15 @@ struct KernelArgs {
   int32_t hcap;              // hand-off row entries per wave (max chained task length)
   int32_t lds_per_wave;      // bytes of LDS per wave
   int32_t max_steps;         // upper bound of any wave's stream length (loop guard)
+  uint32_t epoch;            // launch number, tags progress flags
+  void *links;               // link buffers (value type of the path), device
+  uint64_t *flags;           // progress flags, device
+  uint64_t *err;             // error word (epoch << 32 | bits): bit 0 loop guard hit,
+                             // bit 1 link wait abandoned; the largest word of a launch wins
 };
+
+// A link buffer holds the boundary rows of a job's column curves back to
+// back; the row of column curve c starts at the sum of task_len(m, true) over
+// the job's earlier column curves.
 
 }  // namespace ffd

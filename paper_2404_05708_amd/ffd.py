@@ -16,7 +16,9 @@ import os
 import numpy as np
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libffd.so")
+# FFD_LIBRARY may name another build of the same library (e.g. a debug build)
+LIB_PATH = os.environ.get("FFD_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "libffd.so")
 
 FFD_OK = 0
 FFD_E_INVALID = -1
@@ -34,8 +36,18 @@ FFD_MAX_DIM = 4
 EXPORTS = (
     "ffd_create", "ffd_create_planner", "ffd_destroy", "ffd_strerror", "ffd_last_error", "ffd_version",
     "ffd_distance", "ffd_distance_i32", "ffd_batch", "ffd_batch_i32", "ffd_cross",
-    "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning",
+    "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
 )
+
+
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("lds_per_wave", ctypes.c_int32),
+                ("exact", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("stream_steps", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class FFDError(RuntimeError):
@@ -81,6 +93,12 @@ def _load():
     lib.ffd_workspace_size.restype = ctypes.c_int
     lib.ffd_set_tuning.argtypes = [vp, i32, i32]
     lib.ffd_set_tuning.restype = ctypes.c_int
+    lib.ffd_last_errors.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.ffd_last_errors.restype = ctypes.c_int
+    lib.ffd_set_split.argtypes = [vp, ctypes.c_float]
+    lib.ffd_set_split.restype = ctypes.c_int
+    lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
+    lib.ffd_last_launch.restype = ctypes.c_int
     return lib
 
 
@@ -149,6 +167,22 @@ def ffd_destroy(ctx):
 
 def ffd_set_tuning(ctx, rows_per_lane=0, waves_per_simd=0):
     _check(lib.ffd_set_tuning(ctx, int(rows_per_lane), int(waves_per_simd)), ctx)
+
+
+def ffd_last_errors(ctx):
+    v = ctypes.c_int32()
+    _check(lib.ffd_last_errors(ctx, ctypes.byref(v)), ctx)
+    return v.value
+
+
+def ffd_set_split(ctx, share=0.0):
+    _check(lib.ffd_set_split(ctx, float(share)), ctx)
+
+
+def ffd_last_launch(ctx):
+    info = LaunchInfo()
+    _check(lib.ffd_last_launch(ctx, ctypes.byref(info)), ctx)
+    return info.as_dict()
 
 
 def ffd_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
@@ -268,6 +302,15 @@ class Context:
 
     def set_tuning(self, rows_per_lane=0, waves_per_simd=0):
         ffd_set_tuning(self.handle, rows_per_lane, waves_per_simd)
+
+    def last_errors(self):
+        return ffd_last_errors(self.handle)
+
+    def set_split(self, share=0.0):
+        ffd_set_split(self.handle, share)
+
+    def last_launch(self):
+        return ffd_last_launch(self.handle)
 
     def distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
         return ffd_distance(self.handle, p, q, metric, **kw)

@@ -230,3 +230,54 @@ def test_cross_int_workload_full_size_sampled(ctx):
     row = int(ii[0])
     want = oracle.dfd_cross_i32(Qs, qo, DB, do, nthreads=16, rows=[row])[0]
     np.testing.assert_array_equal(got[row], want)
+
+
+def test_split_bands_bit_identical(ctx):
+    """Bands split over waves (boundary rows through global links) give the
+    same bits as the unsplit plan, in batch, cross and single-pair form."""
+    P, p_off, Q, q_off = workloads.random_pairs(40, 60, 1, 2500, dim=2)
+    say("case: split batch, 60 pairs up to 2500")
+    ctx.set_split(-1.0)
+    base = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    for R in (1, 2, 4, 8):
+        say(f"case: split every multi-band pair, R={R}")
+        ctx.set_tuning(R, 0)
+        ctx.set_split(1e-9)
+        try:
+            got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+        finally:
+            ctx.set_split(0.0)
+            ctx.set_tuning(0, 0)
+        np.testing.assert_array_equal(got, base)
+    want = oracle.dfd_batch(P, p_off, Q, q_off, nthreads=8)
+    assert rel_ok(base, want)
+    say("case: split cross int")
+    Qi, qoi, Di, doi = workloads.cross_int(seed=41, nq=3, ndb=20, length=700)
+    ctx.set_tuning(1, 0)
+    ctx.set_split(1e-9)
+    try:
+        got = ctx.cross_i32(dev(Qi), qoi, dev(Di), doi).cpu().numpy()
+    finally:
+        ctx.set_split(0.0)
+        ctx.set_tuning(0, 0)
+    np.testing.assert_array_equal(got, oracle.dfd_cross_i32(Qi, qoi, Di, doi, nthreads=8))
+
+
+def test_long_curves_force_split(ctx):
+    """Column curves longer than a wave's LDS hand-off row must be split."""
+    rng = np.random.default_rng(42)
+    for n, m, R in [(300, 6000, 1), (700, 9000, 2), (5000, 5000, 0), (64 * 8 * 3 + 5, 3000, 8)]:
+        say(f"case: long pair n={n} m={m} R={R}")
+        p = workloads.walk(rng, n, 2)
+        q = workloads.walk(rng, m, 2)
+        ctx.set_tuning(R, 0)
+        try:
+            got = ctx.distance(dev(p), dev(q)).item()
+            info = ctx.last_launch()
+            gotb = ctx.batch(dev(p), [0, n], dev(q), [0, m]).item()
+        finally:
+            ctx.set_tuning(0, 0)
+        say(f"  launch {info}")
+        assert got == gotb
+        assert got == oracle.dfd_f32_replica(p, q)
+        assert rel_ok(got, oracle.dfd(p, q, 0, "rolling"))
