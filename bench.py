@@ -46,6 +46,8 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--split", type=float, default=0.0,
+                    help="band splitting: 0 auto, < 0 only when needed, > 0 above this share of a wave's load")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -65,6 +67,7 @@ def main():
     Qd = torch.from_numpy(Q).to(dev)
     ctx = ffd.Context(0)
     ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
+    ctx.set_split(args.split)
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     out = torch.empty(npairs, dtype=torch.float32, device=dev)
@@ -101,6 +104,7 @@ def main():
     torch.cuda.synchronize()
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     info = ctx.last_launch()
+    launch_errors = ctx.last_errors()
 
     # parity of the timed output against stored oracle values
     import json as _json
@@ -163,7 +167,7 @@ def main():
         "config": {"workload": "batched: 4096 pairs, n and m uniform in [64, 2048], 2-D float32 "
                                "random walks, q = p resampled + N(0, 0.1^2), Euclidean (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
-        "parity": {"tolerance": TOL, "sampled_ok": parity_ok},
+        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": launch_errors},
         "roofline": roofline, "plain": plain, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -12,9 +12,10 @@
 //    on through global "links" (release/acquire progress flags);
 //  * tasks are placed by list scheduling: the highest-priority ready task
 //    (longest remaining chain; longest first otherwise, the paper's sort by
-//    length) goes to the wave that frees first.  A task that reads a link is
-//    placed after the task that writes it, and every wave runs its tasks in
-//    placement order, so the earliest unfinished task never waits: no
+//    length) goes to the wave that frees first.  A band that reads a link
+//    starts, in its wave's stream, at least kLinkLag steps after the band
+//    that writes it starts in its own (idle jobs pad the stream where
+//    needed), so every wait is for a strictly earlier stream position: no
 //    deadlock, whatever the actual timing;
 //  * the plan (jobs, per-wave job ranges, curve offsets) is copied into the
 //    caller's workspace and reused while the offsets do not change.
@@ -34,7 +35,7 @@
 #include "ffd_plan.h"
 
 namespace ffd {
-hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, hipStream_t st);
+hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
 hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 }  // namespace ffd
 
@@ -109,9 +110,13 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // a few per step (lane shift, addressing).
 double step_cost(int R, int D) { return (double)R * (2 * D + 2) + 3.0; }
 
-// Steps a consumer band trails its producer: the boundary row is published
-// every kFill steps, fetched kFill to 3*kFill steps ahead of use, and the
-// producer's lane 63 trails its lane 0 by kWave steps.
+// Stream steps a consumer band starts after its producer band.  At its
+// refill at step t the consumer waits for the entries of its chunk
+// [t + 2 kFill, t + 3 kFill), i.e. up to t + 3 kFill - S_consumer; the
+// producer publishes at its refill at step t' the t' - kWave - S_producer
+// columns its lane 63 has finished.  The wait therefore ends once the
+// producer reaches t' = t + 3 kFill + kWave - lag: with lag = 6 kFill that is
+// t - 2 kFill, strictly before the waiting wave's own position.
 constexpr double kLinkLag = 6.0 * ffd::kFill;
 
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
@@ -292,13 +297,17 @@ struct Resources {
 // only wait on a running wave).
 Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W) {
   Resources r;
-  size_t per_wave = ctx->lds_cu / (size_t)(4 * W);
+  r.wpb = 4;
+  while (r.wpb > 1 && (size_t)r.wpb * (ctx->lds_cu / (size_t)(4 * W)) > ctx->lds_block_max) r.wpb /= 2;
+  // LDS is allocated to workgroups in granules; a block's share is rounded
+  // down to 1 KiB so that 4W/wpb blocks surely fit one CU's LDS at once
+  size_t blocks_per_cu = (size_t)std::max(1, 4 * W / r.wpb);
+  size_t block_lds = ctx->lds_cu / blocks_per_cu / 1024 * 1024;
+  size_t per_wave = block_lds / (size_t)r.wpb / 16 * 16;
   int vs = exact ? 8 : 4;
   int fixed = lds_bytes(R, D, exact, 0);
   int64_t hand = ((int64_t)per_wave - fixed - 16) / vs;
   r.hand_max = hand > 0 ? hand : 0;
-  r.wpb = 4;
-  while (r.wpb > 1 && (size_t)r.wpb * per_wave > ctx->lds_block_max) r.wpb /= 2;
   r.nwaves_max = ctx->cus * 4 * W;
   if (ctx->device >= 0) {
     // registers may allow fewer resident waves than the LDS share assumes
@@ -355,16 +364,46 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
   pl.hcap = 0;
   for (size_t i = 0; i < units.size(); ++i)
     if (!split[i] && units[i].nb > 1) pl.hcap = std::max(pl.hcap, units[i].maxL);
+  // Stream positions.  A wave runs its tasks back to back, so a task starts
+  // at the sum of the stream lengths before it on its wave, whatever idle
+  // time the model gave it.  Every consumer band must start at least
+  // kLinkLag stream steps after its producer band: then each wait is for a
+  // position strictly earlier than the waiting wave's own, so no set of
+  // waves can wait on each other in a cycle.  Where the positions do not
+  // give that, an idle job pads the consumer's stream.
+  std::vector<double> spos(tasks.size(), 0.0), wpos(nwaves, 0.0);
+  std::vector<int64_t> idle(tasks.size(), 0);
+  for (int32_t t : order) {
+    int w = owner[t];
+    double s = wpos[w];
+    if (tasks[t].pred >= 0 && s < spos[tasks[t].pred] + kLinkLag) {
+      int64_t gap = (int64_t)std::ceil(spos[tasks[t].pred] + kLinkLag - s);
+      gap = std::max<int64_t>(gap, ffd::kMinTask);
+      gap = (gap + ffd::kGroup - 1) / ffd::kGroup * ffd::kGroup;
+      idle[t] = gap;
+      s += (double)gap;
+    }
+    spos[t] = s;
+    wpos[w] = s + tasks[t].dur;
+  }
   std::vector<int32_t> count(nwaves, 0);
-  for (int32_t t : order) count[owner[t]]++;
+  for (int32_t t : order) count[owner[t]] += idle[t] > 0 ? 2 : 1;
   pl.wave_jobs.assign(nwaves + 1, 0);
   for (int w = 0; w < nwaves; ++w) pl.wave_jobs[w + 1] = pl.wave_jobs[w] + count[w];
   std::vector<int32_t> fillp(pl.wave_jobs.begin(), pl.wave_jobs.end() - 1);
-  pl.jobs.resize(tasks.size());
+  pl.jobs.resize(pl.wave_jobs[nwaves]);
   for (int32_t t : order) {
     const Task &tk = tasks[t];
     const Unit &u = units[tk.unit];
     Job jb;
+    if (idle[t] > 0) {
+      memset(&jb, 0, sizeof jb);
+      jb.row_sel = ffd::kRowIdle;
+      jb.col_count = (int32_t)idle[t];
+      jb.link_in = jb.link_out = -1;
+      jb.flag_in = jb.flag_out = -1;
+      pl.jobs[fillp[owner[t]]++] = jb;
+    }
     jb.out_base = u.out_base;
     jb.row_sel = u.row_sel;
     jb.row_idx = u.row_idx;
@@ -381,14 +420,18 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
     pl.jobs[fillp[owner[t]]++] = jb;
   }
   double mx = 0;
-  for (double x : wsteps) mx = std::max(mx, x);
+  for (double x : wpos) mx = std::max(mx, x);
   pl.max_steps = (int64_t)mx;
   pl.nwaves = nwaves;
   pl.R = R;
 }
 
+// Batched and cross launches split a unit into bands over several waves
+// only when its boundary row does not fit the wave's LDS: many independent
+// units already fill the GPU, and cross-wave links cost waiting time that
+// the balance they buy does not repay (measured on the 4096-pair workload).
 double split_share(ffd_ctx *ctx) {
-  if (ctx->split == 0.f) return 0.5;
+  if (ctx->split == 0.f) return -1.0;
   if (ctx->split < 0.f) return -1.0;
   return ctx->split;
 }
@@ -554,7 +597,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.flags = (uint64_t *)(w + wl.flags);
   a.err = (uint64_t *)(w + wl.err);
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
-  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, st);
+  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.nflags > 0, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
@@ -634,7 +677,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
     a.lds_per_wave = lds_bytes(pl->R, dim, exact, pl->hcap);
     a.max_steps = (int32_t)(pl->max_steps + 4 * ffd::kRing);
     a.epoch = ++ctx->epoch;
-    e = ffd::launch_stream(exact, pl->R, dim, a, 1, st);
+    e = ffd::launch_stream(exact, pl->R, dim, a, 1, false, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     ctx->last_err = nullptr;
     return FFD_OK;
@@ -643,7 +686,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
   WsLayout wl = ws_layout(*pl, 1, 1, exact);
   if (ctx->scratch_bytes < wl.total) {
     if (ctx->scratch) {
-      hipStreamSynchronize(st);
+      hipDeviceSynchronize();  // launches on any stream may still use it
       hipFree(ctx->scratch);
       ctx->scratch = nullptr;
       ctx->scratch_bytes = 0;

@@ -126,28 +126,28 @@ struct Stream {
   unsigned char *base;  // this wave's LDS region
 
   // ---- fill cursor: enumerates tasks (job, column curve, band) --------------
-  int32_t j, jend;          // job range of this wave
-  int32_t c, b, nb;         // column curve within the job, band, bands of the row curve
-  int32_t b_first, b_end;   // band range of the job
-  int32_t row_sel, col_sel, col_first, col_count, out_stride, flag_in, flag_out;
-  int64_t row_off, n, out_base, link_in, link_out, link_rel;
-  bool exhausted;
-  int32_t next_id;          // id of the next task to create
-  // task covering the current fill chunk start, and the one after it
+  // Task covering a fill chunk start, or the one after it.
   struct FillTask {
-    int32_t S, L, drain, col_sel, hin, flag_in, rel;
+    int32_t S, L, drain, col_sel, hin, flag_in, rel, pad;
     int64_t col_off, m, link_in;
   };
-  FillTask cur, nxt;
-  bool has_next;
+  // Everything the refill needs; it lives in LDS between refills (every
+  // kFill steps) so that it occupies no registers in the hot loop.
+  struct FillState {
+    int32_t j, jend;          // job range of this wave
+    int32_t c, b, nb;         // column curve within the job, band, bands of the row curve
+    int32_t b_first, b_end;   // band range of the job
+    int32_t row_sel, col_sel, col_first, col_count, out_stride, flag_in, flag_out;
+    int32_t exhausted, next_id, has_next, ptmp_pending, ptmp_slot, idle;
+    int64_t row_off, n, out_base, link_in, link_out, link_rel;
+    FillTask cur, nxt;
+  };
   // per-lane prefetch registers
   C qbuf[D];
   bool qsep;
   V hbuf;
   int32_t hslot;            // stream position of an incoming link value (-1: none)
   C ptmp[R][D];
-  bool ptmp_pending;
-  int32_t ptmp_slot;
   int32_t err;
 
   __device__ Stream(const KernelArgs &args, int lane_, unsigned char *b_) : a(args), lane(lane_), base(b_) {}
@@ -159,6 +159,7 @@ struct Stream {
   __device__ V *lring() const { return reinterpret_cast<V *>(base + lay.lring); }
   __device__ V *pst(int slot) const { return reinterpret_cast<V *>(base + lay.pst) + slot * (kWave * R * D); }
   __device__ Desc *desc(int id) const { return reinterpret_cast<Desc *>(base + lay.desc) + (id & (kDescSlots - 1)); }
+  __device__ FillState *fstate() const { return reinterpret_cast<FillState *>(base + lay.fill); }
   __device__ V *links() const { return static_cast<V *>(a.links); }
 
   // Kernel-argument arrays are only indexed with selects: a dynamic index
@@ -175,105 +176,147 @@ struct Stream {
     return (sel ? a.off[1] : a.off[0])[idx];
   }
 
-  __device__ void load_job(int32_t jj) {
+  __device__ static void uni_task(FillTask &t) {
+    t.S = uni(t.S); t.L = uni(t.L); t.drain = uni(t.drain); t.col_sel = uni(t.col_sel);
+    t.hin = uni(t.hin); t.flag_in = uni(t.flag_in); t.rel = uni(t.rel);
+    t.col_off = uni64(t.col_off); t.m = uni64(t.m); t.link_in = uni64(t.link_in);
+  }
+
+  // Read the refill state from LDS (the same values in every lane).
+  __device__ void load_state(FillState &f) const {
+    f = *fstate();
+    f.j = uni(f.j); f.jend = uni(f.jend); f.c = uni(f.c); f.b = uni(f.b); f.nb = uni(f.nb);
+    f.b_first = uni(f.b_first); f.b_end = uni(f.b_end); f.row_sel = uni(f.row_sel);
+    f.col_sel = uni(f.col_sel); f.col_first = uni(f.col_first); f.col_count = uni(f.col_count);
+    f.out_stride = uni(f.out_stride); f.flag_in = uni(f.flag_in); f.flag_out = uni(f.flag_out);
+    f.exhausted = uni(f.exhausted); f.next_id = uni(f.next_id); f.has_next = uni(f.has_next);
+    f.ptmp_pending = uni(f.ptmp_pending); f.ptmp_slot = uni(f.ptmp_slot); f.idle = uni(f.idle);
+    f.row_off = uni64(f.row_off); f.n = uni64(f.n); f.out_base = uni64(f.out_base);
+    f.link_in = uni64(f.link_in); f.link_out = uni64(f.link_out); f.link_rel = uni64(f.link_rel);
+    uni_task(f.cur);
+    uni_task(f.nxt);
+  }
+
+  __device__ void store_state(const FillState &f) const {
+    if (lane == 0) *fstate() = f;
+  }
+
+  __device__ void load_job(FillState &f, int32_t jj) const {
     int32_t ri, bf, bc;
     if (a.jobs) {
       const Job *jb = a.jobs + jj;
-      row_sel = uni(jb->row_sel);
+      f.row_sel = uni(jb->row_sel);
       ri = uni(jb->row_idx);
-      col_sel = uni(jb->col_sel);
-      col_first = uni(jb->col_first);
-      col_count = uni(jb->col_count);
-      out_stride = uni(jb->out_stride);
-      out_base = uni64(jb->out_base);
-      link_in = uni64(jb->link_in);
-      link_out = uni64(jb->link_out);
+      f.col_sel = uni(jb->col_sel);
+      f.col_first = uni(jb->col_first);
+      f.col_count = uni(jb->col_count);
+      f.out_stride = uni(jb->out_stride);
+      f.out_base = uni64(jb->out_base);
+      f.link_in = uni64(jb->link_in);
+      f.link_out = uni64(jb->link_out);
       bf = uni(jb->band_first);
       bc = uni(jb->band_count);
-      flag_in = uni(jb->flag_in);
-      flag_out = uni(jb->flag_out);
+      f.flag_in = uni(jb->flag_in);
+      f.flag_out = uni(jb->flag_out);
     } else {
-      row_sel = a.inl_job.row_sel;
+      f.row_sel = a.inl_job.row_sel;
       ri = a.inl_job.row_idx;
-      col_sel = a.inl_job.col_sel;
-      col_first = a.inl_job.col_first;
-      col_count = a.inl_job.col_count;
-      out_stride = a.inl_job.out_stride;
-      out_base = a.inl_job.out_base;
-      link_in = a.inl_job.link_in;
-      link_out = a.inl_job.link_out;
+      f.col_sel = a.inl_job.col_sel;
+      f.col_first = a.inl_job.col_first;
+      f.col_count = a.inl_job.col_count;
+      f.out_stride = a.inl_job.out_stride;
+      f.out_base = a.inl_job.out_base;
+      f.link_in = a.inl_job.link_in;
+      f.link_out = a.inl_job.link_out;
       bf = a.inl_job.band_first;
       bc = a.inl_job.band_count;
-      flag_in = a.inl_job.flag_in;
-      flag_out = a.inl_job.flag_out;
+      f.flag_in = a.inl_job.flag_in;
+      f.flag_out = a.inl_job.flag_out;
     }
-    row_off = uni64(curve_off(row_sel, ri));
-    n = uni64(curve_off(row_sel, ri + 1)) - row_off;
-    nb = (int32_t)bands_for(n, R);
-    b_first = bf;
-    b_end = bc > 0 && bf + bc < nb ? bf + bc : nb;
-    c = 0;
-    b = b_first;
-    link_rel = 0;
+    f.c = 0;
+    f.link_rel = 0;
+    if (f.row_sel == kRowIdle) {  // padding: col_count steps of separators
+      f.idle = f.col_count;
+      f.nb = 1;
+      f.b_first = f.b = 0;
+      f.b_end = 1;
+      f.col_count = 1;
+      return;
+    }
+    f.idle = 0;
+    f.row_off = uni64(curve_off(f.row_sel, ri));
+    f.n = uni64(curve_off(f.row_sel, ri + 1)) - f.row_off;
+    f.nb = (int32_t)bands_for(f.n, R);
+    f.b_first = bf;
+    f.b_end = bc > 0 && bf + bc < f.nb ? bf + bc : f.nb;
+    f.b = f.b_first;
   }
 
   // Create the next task in stream order starting at position S: write its
   // descriptor, issue the loads of its band rows into ptmp, return its
   // stream parameters.
-  __device__ void make_task(int32_t S, FillTask &t) {
-    int32_t id = next_id++;
+  __device__ void make_task(FillState &f, int32_t S, FillTask &t) {
+    int32_t id = f.next_id++;
     Desc d;
     d.S = S;
     d.pad = 0;
     d.rel_in = d.rel_out = 0;
     t.S = S;
     t.rel = 0;
-    if (exhausted) {
-      t.L = kMinTask; t.drain = 1; t.col_sel = 0; t.col_off = 0; t.m = 1;
+    t.pad = 0;
+    if (f.exhausted || f.idle) {
+      // separators only: after the last job (drain: the stream ends), or an
+      // idle job (the stream goes on)
+      t.L = f.exhausted ? kMinTask : f.idle; t.drain = 1; t.col_sel = 0; t.col_off = 0; t.m = 1;
       t.hin = kHinGhost; t.flag_in = -1; t.link_in = 0;
-      d.L = t.L; d.hin = kHinGhost; d.hout = kHoutSink; d.out_lo = -1; d.out_hi = -1; d.drain = 1;
+      d.L = t.L; d.hin = kHinGhost; d.hout = kHoutSink; d.out_lo = -1; d.out_hi = -1; d.drain = f.exhausted;
       d.flag_in = -1; d.flag_out = -1; d.link_in = 0; d.link_out = 0;
+      if (!f.exhausted) {
+        if (++f.j == f.jend) f.exhausted = 1;
+        else load_job(f, f.j);
+      }
     } else {
-      int32_t k = col_first + c;
-      t.col_off = uni64(curve_off(col_sel, k));
-      t.m = uni64(curve_off(col_sel, k + 1)) - t.col_off;
-      t.col_sel = col_sel;
-      t.L = (int32_t)task_len(t.m, nb > 1);
+      int32_t k = f.col_first + f.c;
+      t.col_off = uni64(curve_off(f.col_sel, k));
+      t.m = uni64(curve_off(f.col_sel, k + 1)) - t.col_off;
+      t.col_sel = f.col_sel;
+      t.L = (int32_t)task_len(t.m, f.nb > 1);
       t.drain = 0;
-      int64_t oi = (b == nb - 1) ? out_base + (int64_t)c * out_stride : -1;
-      int32_t hin = b == 0 ? kHinGhost : (b == b_first ? kHinLink : kHinHand);
-      int32_t hout = b == nb - 1 ? kHoutSink : (b + 1 == b_end ? kHoutLink : kHoutHand);
+      int32_t b = f.b, nb = f.nb;
+      int64_t oi = (b == nb - 1) ? f.out_base + (int64_t)f.c * f.out_stride : -1;
+      int32_t hin = b == 0 ? kHinGhost : (b == f.b_first ? kHinLink : kHinHand);
+      int32_t hout = b == nb - 1 ? kHoutSink : (b + 1 == f.b_end ? kHoutLink : kHoutHand);
       t.hin = hin;
-      t.flag_in = flag_in;
-      t.link_in = link_in + link_rel;
-      t.rel = (int32_t)link_rel;
-      d.rel_in = d.rel_out = (int32_t)link_rel;
+      t.flag_in = f.flag_in;
+      t.link_in = f.link_in + f.link_rel;
+      t.rel = (int32_t)f.link_rel;
+      d.rel_in = d.rel_out = (int32_t)f.link_rel;
       d.L = t.L; d.hin = hin; d.hout = hout; d.drain = 0;
       d.out_lo = (int32_t)(uint32_t)(uint64_t)oi;
       d.out_hi = (int32_t)(uint32_t)((uint64_t)oi >> 32);
-      d.flag_in = flag_in;
-      d.flag_out = flag_out;
-      d.link_in = link_in + link_rel;
-      d.link_out = link_out + link_rel;
+      d.flag_in = f.flag_in;
+      d.flag_out = f.flag_out;
+      d.link_in = f.link_in + f.link_rel;
+      d.link_out = f.link_out + f.link_rel;
       // band rows of this lane, clamped to the last point (repetition is exact)
-      const C *X = coords(row_sel);
+      const C *X = coords(f.row_sel);
       int64_t r0 = (int64_t)b * kWave * R + (int64_t)lane * R;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        int64_t ri = r0 + r < n ? r0 + r : n - 1;
-        const C *pt = X + (row_off + ri) * D;
+        int64_t ri = r0 + r < f.n ? r0 + r : f.n - 1;
+        const C *pt = X + (f.row_off + ri) * D;
 #pragma unroll
         for (int k2 = 0; k2 < D; ++k2) ptmp[r][k2] = pt[k2];
       }
-      ptmp_pending = true;
-      ptmp_slot = id & 1;
+      f.ptmp_pending = 1;
+      f.ptmp_slot = id & 1;
       // advance: next band, next column curve, next job
-      if (++b == b_end) {
-        b = b_first;
-        link_rel += t.L;
-        if (++c == col_count) {
-          if (++j == jend) exhausted = true;
-          else load_job(j);
+      if (++f.b == f.b_end) {
+        f.b = f.b_first;
+        f.link_rel += t.L;
+        if (++f.c == f.col_count) {
+          if (++f.j == f.jend) f.exhausted = 1;
+          else load_job(f, f.j);
         }
       }
     }
@@ -281,11 +324,12 @@ struct Stream {
   }
 
   // Wait until the link flag reports at least `need` entries of this launch.
+  // Relaxed polling; one acquire fence once the entries are there.
   __device__ void wait_link(int32_t flag, uint32_t need) {
     uint64_t want = flag_word(a.epoch, need);
-    uint64_t *f = a.flags + flag;
+    uint64_t *fl = a.flags + flag;
     for (int it = 0;; ++it) {
-      uint64_t v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t v = __hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((uint32_t)(v >> 32) == a.epoch && v >= want) break;
       if (it == kSpinLimit) {
         err |= 2;
@@ -293,26 +337,28 @@ struct Stream {
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
 
   // Issue the global loads of ring entries [t, t + 64): one per lane, plus
   // the incoming boundary values of tasks whose band above ran on another
   // wave (after waiting for them to be published).
-  __device__ void fill_load(int32_t t) {
-    while (cur.S + cur.L <= t) {
-      if (!has_next) make_task(cur.S + cur.L, nxt);
-      cur = nxt;
-      has_next = false;
+  __device__ void fill_load(FillState &f, int32_t t) {
+    while (f.cur.S + f.cur.L <= t) {
+      if (!f.has_next) make_task(f, f.cur.S + f.cur.L, f.nxt);
+      f.cur = f.nxt;
+      f.has_next = 0;
     }
-    if (cur.S + cur.L < t + kFill && !has_next) {
-      make_task(cur.S + cur.L, nxt);
-      has_next = true;
+    if (f.cur.S + f.cur.L < t + kFill && !f.has_next) {
+      make_task(f, f.cur.S + f.cur.L, f.nxt);
+      f.has_next = 1;
     }
+    const FillTask &cur = f.cur, &nxt = f.nxt;
     if (cur.hin == kHinLink) {
       int32_t hi = t + kFill - cur.S;
       wait_link(cur.flag_in, (uint32_t)(cur.rel + (hi < cur.L ? hi : cur.L)));
     }
-    if (has_next && nxt.hin == kHinLink) {
+    if (f.has_next && nxt.hin == kHinLink) {
       int32_t hi = t + kFill - nxt.S;
       if (hi > 0) wait_link(nxt.flag_in, (uint32_t)(nxt.rel + (hi < nxt.L ? hi : nxt.L)));
     }
@@ -340,7 +386,7 @@ struct Stream {
 
   // Write the entries loaded by the previous fill_load (for positions
   // [t, t + 64)), incoming boundary values and any pending band rows.
-  __device__ void fill_write(int32_t t) {
+  __device__ void fill_write(FillState &f, int32_t t) {
     Pt e;
 #pragma unroll
     for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : N::cvt(qbuf[k2])) : V(0);
@@ -352,14 +398,25 @@ struct Stream {
       lring()[ls] = hbuf;
       if (ls < kGroup) lring()[ls + kLinkRing] = hbuf;
     }
-    if (ptmp_pending) {
-      V *dst = pst(ptmp_slot) + lane * (R * D);
+    if (f.ptmp_pending) {
+      V *dst = pst(f.ptmp_slot) + lane * (R * D);
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int k2 = 0; k2 < D; ++k2) dst[r * D + k2] = N::cvt(ptmp[r][k2]);
-      ptmp_pending = false;
+      f.ptmp_pending = 0;
     }
+  }
+
+  static_assert(sizeof(FillState) <= kFillStateBytes, "refill state does not fit its LDS slot");
+
+  // One refill: write the chunk loaded last time, load the next one.
+  __device__ __forceinline__ void refill(int32_t t0) {
+    FillState f;
+    load_state(f);
+    fill_write(f, t0 + kFill);
+    fill_load(f, t0 + 2 * kFill);
+    store_state(f);
   }
 
   // Column points and top-boundary values of one group of kGroup steps,
@@ -388,20 +445,25 @@ struct Stream {
   int32_t id63, S63, L63, hout63, flag63, rel63;
   int64_t out63, link63;
 
-  template <bool WINDOW, bool LINK>
-  __device__ __forceinline__ void group(int32_t t0, int32_t win, const GroupIn &g, V *hout, V *lout,
-                                        V &res) {
+  // One code path for every group: the row switch of a task window and the
+  // link store are uniform branches, so the hot registers stay where they
+  // are (code variants of the group made the compiler shuffle them at every
+  // merge).
+  __device__ __forceinline__ void group(int32_t t0, int32_t win, bool window, bool link, const GroupIn &g,
+                                        V *hout, V *lout, V &res) {
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       V bottom = Mp[R - 1];
-      if (lane == kWave - 1) {
-        hout[u] = bottom;
-        // link rows cross XCDs, whose L2 caches are not coherent with each
-        // other: store and load them at agent scope (coherent point)
-        if (LINK) __hip_atomic_store(lout + u, bottom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // every lane stores (no exec-mask change in the hot loop); only lane
+      // 63's address can be the hand-off row, the others land in the sink
+      hout[u] = bottom;
+      // link rows cross XCDs, whose L2 caches are not coherent with each
+      // other: store and load them at agent scope (coherent point)
+      if (link) {
+        if (lane == kWave - 1) __hip_atomic_store(lout + u, bottom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (u == kGroup - 1) res = bottom;
-      if (WINDOW) {
+      if (window) {
         bool sw = lane == t0 + u - win;
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -477,7 +539,7 @@ struct Stream {
   // One group: refill the ring, move the lane-63 cursor, prefetch the next
   // group into `nxt`, compute this group from `cur`.  Returns false when the
   // stream has ended.
-  __device__ __forceinline__ bool step(int32_t t0, const GroupIn &curg, GroupIn &nxtg) {
+  __device__ __forceinline__ bool step(int32_t t0) {
     if (t0 > a.max_steps) {  // guard: the plan bounds every stream's length
       err |= 1;
       return false;
@@ -487,8 +549,7 @@ struct Stream {
         int32_t done = t0 - kWave - S63;  // columns of lane 63's task already stored
         if (done > 0) publish(done < L63 ? done : L63);
       }
-      fill_write(t0 + kFill);
-      fill_load(t0 + 2 * kFill);
+      refill(t0);
     }
     if (t0 - kWave == S63 + L63) {
       if (hout63 == kHoutLink) publish(L63);
@@ -504,22 +565,15 @@ struct Stream {
       out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
     }
     int32_t x63 = t0 - kWave - S63;
-    int32_t hoff = hout63 == kHoutHand ? lay.hand + x63 * (int32_t)sizeof(V) : lay.sink;
+    int32_t hoff = lane == kWave - 1 && hout63 == kHoutHand ? lay.hand + x63 * (int32_t)sizeof(V)
+                                                             : lay.sink + lane * (int32_t)sizeof(V);
     V *hout = reinterpret_cast<V *>(base + hoff);
     V *lout = links() + link63 + x63;
-    int32_t win = win_cur;
-    lane0_to(t0 + kGroup);
-    load_group(t0 + kGroup, hin_at(t0 + kGroup), nxtg);
-    win_cur = win0;
+    lane0_to(t0);
+    GroupIn g;
+    load_group(t0, hin_at(t0), g);
     V res;
-    bool window = t0 < win + kWave;
-    if (hout63 == kHoutLink) {
-      if (window) group<true, true>(t0, win, curg, hout, lout, res);
-      else group<false, true>(t0, win, curg, hout, lout, res);
-    } else {
-      if (window) group<true, false>(t0, win, curg, hout, lout, res);
-      else group<false, false>(t0, win, curg, hout, lout, res);
-    }
+    group(t0, win0, t0 < win0 + kWave, hout63 == kHoutLink, g, hout, lout, res);
     if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
       N::store(a.out, out63, res, a.metric);
     return true;
@@ -533,21 +587,17 @@ struct Stream {
     dbg_wave = wave;
 #endif
     lay = lds_layout(R, D, (int)sizeof(V), a.hcap);
+    int32_t j0, j1;
     if (a.jobs) {
-      j = uni(a.wave_jobs[wave]);
-      jend = uni(a.wave_jobs[wave + 1]);
+      j0 = uni(a.wave_jobs[wave]);
+      j1 = uni(a.wave_jobs[wave + 1]);
     } else {
-      j = 0;
-      jend = wave == 0 ? 1 : 0;
+      j0 = 0;
+      j1 = wave == 0 ? 1 : 0;
     }
-    if (j >= jend) return;
+    if (j0 >= j1) return;
     err = 0;
-    exhausted = false;
-    next_id = 0;
-    has_next = false;
-    ptmp_pending = false;
     hslot = -1;
-    load_job(j);
 
     // constant LDS: top boundary and ring entries before the stream start;
     // row staging starts as zeros so that no lane ever reads uninitialised LDS
@@ -560,17 +610,22 @@ struct Stream {
       ring()[kRing - kWave + lane] = e;  // positions -64 .. -1
     }
     // first task and the first two ring chunks
-    make_task(0, cur);
-    fill_load(0);
-#ifdef FFD_DEBUG_HIN
-    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + lane] = (float)hbuf;
-    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + 64 + lane] = (float)hslot;
-#endif
-    fill_write(0);
-#ifdef FFD_DEBUG_HIN
-    static_cast<float *>(a.out)[1 + 16 * 4096 + dbg_wave * 256 + 128 + lane] = (float)lring()[lane];
-#endif
-    fill_load(kFill);
+    {
+      FillState f;
+      f.j = j0;
+      f.jend = j1;
+      f.exhausted = 0;
+      f.next_id = 0;
+      f.has_next = 0;
+      f.ptmp_pending = 0;
+      f.ptmp_slot = 0;
+      load_job(f, j0);
+      make_task(f, 0, f.cur);
+      fill_load(f, 0);
+      fill_write(f, 0);
+      fill_load(f, kFill);
+      store_state(f);
+    }
 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -583,16 +638,8 @@ struct Stream {
     id63 = -1; S63 = -kWave; L63 = kWave; hout63 = kHoutSink; flag63 = -1; rel63 = 0; out63 = -1;
     link63 = 0;
 
-    GroupIn A, B;
-    lane0_to(0);
-    win_cur = win0;
-    load_group(0, hin_at(0), A);
-    for (int32_t t0 = 0;;) {
-      if (!step(t0, A, B)) break;
-      t0 += kGroup;
-      if (!step(t0, B, A)) break;
-      t0 += kGroup;
-    }
+    for (int32_t t0 = 0;; t0 += kGroup)
+      if (!step(t0)) break;
     if (err && lane == 0 && a.err)
       atomicMax(reinterpret_cast<unsigned long long *>(a.err),
                 (unsigned long long)flag_word(a.epoch, (uint32_t)err));
@@ -612,38 +659,48 @@ __global__ __launch_bounds__(256) void stream_kernel(KernelArgs a) {
 
 // ------------------------------------------------------------------ launcher
 
+// A launch whose waves wait on each other (boundary rows over links) is
+// cooperative: the runtime then either makes every workgroup resident at
+// once or refuses the launch, so a waiting wave never waits for a wave that
+// cannot start.
 template <int R, int D, typename V>
-static hipError_t launch_t(const KernelArgs &a, int waves_per_block, hipStream_t st) {
+static hipError_t launch_t(const KernelArgs &a, int waves_per_block, bool coop, hipStream_t st) {
   int blocks = (a.nwaves + waves_per_block - 1) / waves_per_block;
   size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  if (coop) {
+    KernelArgs copy = a;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&stream_kernel<R, D, V>), dim3(blocks),
+                                      dim3(waves_per_block * kWave), args, (unsigned)lds, st);
+  }
   hipLaunchKernelGGL((stream_kernel<R, D, V>), dim3(blocks), dim3(waves_per_block * kWave), lds, st, a);
   return hipGetLastError();
 }
 
 template <int R, typename V>
-static hipError_t launch_d(int D, const KernelArgs &a, int wpb, hipStream_t st) {
+static hipError_t launch_d(int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
   switch (D) {
-    case 1: return launch_t<R, 1, V>(a, wpb, st);
-    case 2: return launch_t<R, 2, V>(a, wpb, st);
-    case 3: return launch_t<R, 3, V>(a, wpb, st);
-    case 4: return launch_t<R, 4, V>(a, wpb, st);
+    case 1: return launch_t<R, 1, V>(a, wpb, coop, st);
+    case 2: return launch_t<R, 2, V>(a, wpb, coop, st);
+    case 3: return launch_t<R, 3, V>(a, wpb, coop, st);
+    case 4: return launch_t<R, 4, V>(a, wpb, coop, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename V>
-static hipError_t launch_r(int R, int D, const KernelArgs &a, int wpb, hipStream_t st) {
+static hipError_t launch_r(int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
   switch (R) {
-    case 1: return launch_d<1, V>(D, a, wpb, st);
-    case 2: return launch_d<2, V>(D, a, wpb, st);
-    case 4: return launch_d<4, V>(D, a, wpb, st);
-    case 8: return launch_d<8, V>(D, a, wpb, st);
+    case 1: return launch_d<1, V>(D, a, wpb, coop, st);
+    case 2: return launch_d<2, V>(D, a, wpb, coop, st);
+    case 4: return launch_d<4, V>(D, a, wpb, coop, st);
+    case 8: return launch_d<8, V>(D, a, wpb, coop, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, hipStream_t st) {
-  return exact ? launch_r<double>(R, D, a, wpb, st) : launch_r<float>(R, D, a, wpb, st);
+hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
+  return exact ? launch_r<double>(R, D, a, wpb, coop, st) : launch_r<float>(R, D, a, wpb, coop, st);
 }
 
 template <int R, int D, typename V>

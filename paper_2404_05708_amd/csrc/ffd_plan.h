@@ -35,12 +35,17 @@ constexpr int kMinTask = 72;         // shortest task stream (> 64: a task's row
 constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
 constexpr int kDescSlots = 8;        // task descriptors in flight per wave
 constexpr int kLinkRing = 256;       // LDS ring for boundary rows arriving over a link
+constexpr int kFillStateBytes = 256; // per-wave refill state kept in LDS
+
+// A job whose row_sel is kRowIdle computes nothing for col_count stream
+// steps (padding that keeps a consumer band far enough behind its producer).
+constexpr int32_t kRowIdle = 2;
 
 struct Job {           // 64 bytes, device-resident plan entry
   int64_t out_base;    // output index of the first column curve of the job
   int64_t link_in;     // first element of the incoming link buffer (-1: none)
   int64_t link_out;    // first element of the outgoing link buffer (-1: none)
-  int32_t row_sel;     // which coordinate array holds the row curve (0 or 1)
+  int32_t row_sel;     // which coordinate array holds the row curve (0 or 1), or kRowIdle
   int32_t row_idx;     // index of the row curve in that array's offsets
   int32_t col_sel;     // which array holds the column curves
   int32_t col_first;   // first column curve
@@ -73,11 +78,12 @@ FFD_HD int64_t task_len(int64_t m, bool chained) {
 struct LdsLayout {
   int ring;   // (kRing + kGroup) column points; the last kGroup mirror the first
   int ghost;  // kGroup + 1 values: -inf, +inf, ... (top boundary of a first band)
-  int sink;   // kGroup values written when a band hands nothing on
+  int sink;   // kWave + kGroup values: bottom-row stores that hand nothing on
   int hand;   // hcap values: bottom row of the band above (same wave)
   int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
   int pst;    // two slots of 64 * R * D row coordinates (next task's rows)
   int desc;   // kDescSlots task descriptors of 64 bytes
+  int fill;   // refill state of the wave (kFillStateBytes)
   int total;
 };
 
@@ -89,11 +95,12 @@ FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
   int o = 0;
   L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
   L.ghost = o; o += (kGroup + 1) * vsize;
-  L.sink = o;  o += kGroup * vsize;
+  L.sink = o;  o += (kWave + kGroup) * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
   o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;
   o = align16(o); L.pst = o;  o += 2 * kWave * R * D * vsize;
   o = align16(o); L.desc = o; o += kDescSlots * 64;
+  o = align16(o); L.fill = o; o += kFillStateBytes;
   L.total = align16(o);
   return L;
 }

@@ -245,6 +245,7 @@ def test_split_bands_bit_identical(ctx):
         ctx.set_split(1e-9)
         try:
             got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+            assert ctx.last_errors() == 0
         finally:
             ctx.set_split(0.0)
             ctx.set_tuning(0, 0)
@@ -261,6 +262,32 @@ def test_split_bands_bit_identical(ctx):
         ctx.set_split(0.0)
         ctx.set_tuning(0, 0)
     np.testing.assert_array_equal(got, oracle.dfd_cross_i32(Qi, qoi, Di, doi, nthreads=8))
+
+
+def test_split_with_many_waves_per_simd(ctx):
+    """Many split pairs mixed with unsplit ones on 3 and 4 waves per SIMD
+    (small LDS shares force most multi-band pairs to split): no wave gives
+    up waiting and the bits equal the unsplit plan's."""
+    P, p_off, Q, q_off = workloads.random_pairs(43, 1500, 64, 2048, dim=2)
+    ctx.set_split(-1.0)
+    ctx.set_tuning(8, 2)
+    try:
+        base = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    finally:
+        ctx.set_tuning(0, 0)
+        ctx.set_split(0.0)
+    for W, share in [(3, -1.0), (4, -1.0), (2, 0.5), (3, 0.25)]:
+        say(f"case: 1500 pairs, R=8 W={W} split={share}")
+        ctx.set_tuning(8, W)
+        ctx.set_split(share)
+        try:
+            got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+            errs = ctx.last_errors()
+        finally:
+            ctx.set_tuning(0, 0)
+            ctx.set_split(0.0)
+        assert errs == 0
+        np.testing.assert_array_equal(got, base)
 
 
 def test_long_curves_force_split(ctx):
