@@ -1,15 +1,21 @@
-"""Benchmark: DP cells/s of the batched discrete Frechet distance on one GPU.
+"""Benchmark: DP cells/s of the discrete Frechet distance on one GPU.
 
-Workload (synthetic, seeded; see workloads.batched): 4096 independent pairs,
-lengths n, m uniform in [64, 2048], 2-D float32 random walks, q = p resampled
-at rate m/n plus N(0, 0.1^2) noise, Euclidean ground distance.  One step is
-one ffd_batch call over all 4096 pairs with the inputs already resident in
-device memory.  Cells are algorithmic (sum of n*m; padding not counted).
+Default workload (the headline line): 4096 independent pairs, lengths n, m
+uniform in [64, 2048], 2-D float32 random walks, q = p resampled at rate m/n
+plus N(0, 0.1^2) noise, Euclidean ground distance (workloads.batched).  One
+step is one ffd_batch call over all 4096 pairs with the inputs already
+resident in device memory.  Cells are algorithmic (sum of n*m; padding is
+not counted).
+
+--workload selects the other configurations:
+  plain  one 512 x 384 2-D pair through ffd_distance (one launch per step)
+  large  one 131072 x 131072 3-D pair through ffd_distance
+  cross  1024 x 1024 curves of 256 int32 2-D points through ffd_cross_i32
+         (squared Euclidean, int64 results, bit-exact)
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (VALU issue rate: the path has no contraction and moves O(n+m) bytes per
-pair), the same pairs through the one-pair entry point (plain), and the CPU
-oracle timed on a bounded sample of the same workload.
+pair), and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -25,117 +31,104 @@ sys.path.insert(0, ROOT)
 METRIC = "DP cells/s (batched vs plain, 1 GPU) at stated tol; p50/p99 latency at fixed QPS"
 TOL = 2e-6
 # MI355X: 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz = 3.93e13 VALU lane-ops/s
+# (FP32 without packed math, and FP64: both 16 lanes per SIMD per clock)
 PEAK_VALU = 256 * 4 * 16 * 2.4e9
 
 
-def imin(dim):
+def imin(dim, exact=False):
     """Algorithmic VALU lane-ops per cell without packed FP32: D subtractions,
-    one multiply and D-1 FMAs for the squared distance, then min3 and max."""
-    return 2 * dim + 2
+    one multiply and D-1 FMAs for the squared distance, then the selection:
+    min3 and max in FP32; FP64 has no three-input min, so two mins and a max."""
+    return 2 * dim + (3 if exact else 2)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-pair comparison")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-pairs", type=int, default=4096, help="pairs in the CPU oracle sample")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 256 MiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--rows-per-lane", type=int, default=0)
-    ap.add_argument("--waves-per-simd", type=int, default=0)
-    ap.add_argument("--split", type=float, default=0.0,
-                    help="band splitting: 0 auto, < 0 only when needed, > 0 above this share of a wave's load")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the work shards by pairs across GPUs, see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+def time_steps(step, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    sync()
+    return (time.perf_counter() - t0) / steps
 
-    import torch
+
+def kernel_ms(torch, step, steps, stream):
+    """Average duration of one step's launch, from HIP events recorded on the
+    stream the kernel runs on."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def roofline(info, cells, kms, dim, exact):
+    ops = cells * imin(dim, exact)
+    achieved = ops / (kms / 1e3)
+    vt = "double" if exact else "float"
+    return {
+        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
+        "unit": "TVALUop/s", "frac": achieved / PEAK_VALU, "traffic": None,
+        "kernel": f"ffd::stream_kernel<{info['rows_per_lane']}, {dim}, {vt}>", "kernel_ms": kms,
+        "launch": info, "ops_per_cell": imin(dim, exact), "cells_per_launch": cells,
+    }
+
+
+def golden():
+    return json.load(open(os.path.join(ROOT, "tests", "golden", "expected.json")))
+
+
+def cpu_cores():
+    return min(16, len(os.sched_getaffinity(0)))
+
+
+# ------------------------------------------------------------------ workloads
+
+def run_batched(args, torch, ffd, ctx, dev, stream):
     import workloads
-    from paper_2404_05708_amd import ffd
-
-    dev = torch.device("cuda:0")
     P, p_off, Q, q_off = workloads.batched()
     npairs = len(p_off) - 1
     cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
     dim = P.shape[1]
     Pd = torch.from_numpy(P).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    ctx = ffd.Context(0)
-    ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
-    ctx.set_split(args.split)
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     out = torch.empty(npairs, dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
 
     def step():
         ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
     if args.copy_probe:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    # timed region: K steps, synchronised on both sides
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-
-    # kernel-only duration with HIP events on the launch stream
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
     info = ctx.last_launch()
-    launch_errors = ctx.last_errors()
-
-    # parity of the timed output against stored oracle values
-    import json as _json
-    g = _json.load(open(os.path.join(ROOT, "tests", "golden", "expected.json")))["batched"]
+    errs = ctx.last_errors()
+    g = golden()["batched"]
     res = out.cpu().numpy()
     idx = np.array(g["sample_index"])
     want = np.array(g["euclidean"])
     parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
 
-    value = cells / (ms_per_step / 1e3)
-    ops = cells * imin(dim)
-    achieved = ops / (kern_ms / 1e3)
-    roofline = {
-        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
-        "unit": "TVALUop/s", "frac": achieved / PEAK_VALU, "traffic": None,
-        "kernel": f"ffd::stream_kernel<{info['rows_per_lane']}, {dim}, float>", "kernel_ms": kern_ms,
-        "launch": info,
-        "ops_per_cell": imin(dim), "cells_per_launch": cells,
-    }
-
     plain = None
     if not args.no_plain:
-        torch.cuda.synchronize()
         pp = [(Pd[p_off[k]:p_off[k + 1]], Qd[q_off[k]:q_off[k + 1]]) for k in range(npairs)]
         outs = torch.empty(npairs, dtype=torch.float32, device=dev)
         for k in range(8):
-            ctx.distance(pp[k][0], pp[k][1], out=outs[k:k + 1])
+            ctx.distance(pp[k][0], pp[k][1], out=outs[k:k + 1], stream=stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(npairs):
-            ctx.distance(pp[k][0], pp[k][1], out=outs[k:k + 1])
+            ctx.distance(pp[k][0], pp[k][1], out=outs[k:k + 1], stream=stream)
         torch.cuda.synchronize()
         pw = time.perf_counter() - t1
         plain = {"cells_per_s": cells / pw, "ms": pw * 1e3,
@@ -144,7 +137,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        cores = min(16, len(os.sched_getaffinity(0)))
+        cores = cpu_cores()
         rng = np.random.default_rng(77)
         sample = np.sort(rng.choice(npairs, size=args.cpu_pairs, replace=False))
         s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
@@ -159,17 +152,169 @@ def main():
                "sample": f"{args.cpu_pairs} of the 4096 pairs (seed 77), {s_cells} cells, FP64 rolling-row "
                          f"oracle, longest first on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": agree}
-
-    line = {
-        "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+    return {
+        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
         "config": {"workload": "batched: 4096 pairs, n and m uniform in [64, 2048], 2-D float32 "
                                "random walks, q = p resampled + N(0, 0.1^2), Euclidean (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
-        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": launch_errors},
-        "roofline": roofline, "plain": plain, "cpu_baseline": cpu,
+        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, dim, False), "plain": plain, "cpu_baseline": cpu,
     }
+
+
+def run_pair(args, torch, ffd, ctx, dev, stream, which):
+    import workloads
+    if which == "plain":
+        p, q = workloads.plain_pair()
+        want = golden()["plain_pair"]["euclidean"]
+        desc = "plain: one pair, n=512, m=384, 2-D float32 random walks, Euclidean (seed 1)"
+    else:
+        p, q = workloads.large_pair()
+        want = golden()["large_pair"]["euclidean"]
+        desc = "large: one pair, n=m=131072, 3-D float32 random walks, Euclidean (seed 3)"
+    n, m, dim = p.shape[0], q.shape[0], p.shape[1]
+    cells = n * m
+    pd = torch.from_numpy(p).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    out = torch.empty(1, dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.distance(pd, qd, out=out, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    errs = ctx.last_errors()
+    got = out.item()
+    parity_ok = abs(got - want) <= TOL * want
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        if which == "plain":
+            reps = 50
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                v = oracle.dfd(p, q, oracle.EUCLIDEAN, "rolling")
+            cw = (time.perf_counter() - t0) / reps
+            cpu = {"value": cells / cw, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                   "sample": f"the whole pair, FP64 rolling-row oracle, mean of {reps} runs, one thread",
+                   "latency_ms": cw * 1e3, "gpu_matches": bool(abs(got - v) <= TOL * v)}
+        else:
+            k = args.cpu_block
+            t0 = time.perf_counter()
+            oracle.dfd(p[:k], q[:k], oracle.EUCLIDEAN, "rolling")
+            cw = time.perf_counter() - t0
+            cpu = {"value": k * k / cw, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                   "sample": f"leading {k} x {k} points of both curves ({k * k} cells), FP64 rolling-row "
+                             f"oracle, one thread (one pair has no parallelism across pairs), {cw:.2f} s"}
+    return {
+        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
+        "config": {"workload": desc, "npairs": 1, "cells": cells, "global_batch": 1},
+        "parity": {"tolerance": TOL, "ok": bool(parity_ok), "got": got, "oracle": want,
+                   "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, dim, False), "cpu_baseline": cpu,
+    }
+
+
+def run_cross(args, torch, ffd, ctx, dev, stream):
+    import workloads
+    Qs, qo, DB, dbo = workloads.cross_int()
+    nq, ndb, dim = len(qo) - 1, len(dbo) - 1, Qs.shape[1]
+    cells = int(np.sum(np.diff(qo))) * int(np.sum(np.diff(dbo)))
+    Qd = torch.from_numpy(Qs).to(dev)
+    Dd = torch.from_numpy(DB).to(dev)
+    nbytes = ctx.workspace_size(ffd.FFD_OP_CROSS, qo, dbo, dim)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.empty(nq * ndb, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.cross_i32(Qd, qo, Dd, dbo, out=out, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    errs = ctx.last_errors()
+    g = golden()["cross_int"]
+    res = out.cpu().numpy().reshape(nq, ndb)
+    got = res[np.array(g["sample_i"]), np.array(g["sample_k"])]
+    parity_ok = bool(np.array_equal(got, np.array(g["sqeuclidean_int64"], dtype=np.int64)))
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = cpu_cores()
+        rows = np.arange(args.cpu_queries)
+        sq = np.concatenate([Qs[qo[i]:qo[i + 1]] for i in rows])
+        so = np.concatenate([[0], np.cumsum(np.diff(qo)[rows])]).astype(np.int64)
+        t0 = time.perf_counter()
+        vals = oracle.dfd_cross_i32(sq, so, DB, dbo, nthreads=cores)
+        cw = time.perf_counter() - t0
+        s_cells = int(np.sum(np.diff(so))) * int(np.sum(np.diff(dbo)))
+        cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {args.cpu_queries} queries x all 1024 database curves ({s_cells} cells), "
+                         f"int64 exact oracle on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.array_equal(vals.reshape(len(rows), ndb), res[rows]))}
+    return {
+        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f64",
+        "config": {"workload": "cross: 1024 queries x 1024 database curves of 256 points, 2-D int32 "
+                               "uniform in [-2^15, 2^15), squared Euclidean, int64 results (seed 4)",
+                   "npairs": nq * ndb, "cells": cells, "global_batch": nq * ndb},
+        "parity": {"exact": True, "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, dim, True), "cpu_baseline": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross"], default="batched")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-pair comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-pairs", type=int, default=4096, help="pairs in the CPU oracle sample (batched)")
+    ap.add_argument("--cpu-block", type=int, default=32768,
+                    help="leading points per curve timed on the CPU (large)")
+    ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU oracle sample (cross)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--rows-per-lane", type=int, default=0)
+    ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--split", type=float, default=0.0,
+                    help="band splitting: 0 auto, < 0 only when needed, > 0 above this share of a wave's load")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the work shards by pairs across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_05708_amd import ffd
+
+    dev = torch.device("cuda:0")
+    ctx = ffd.Context(0)
+    ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
+    ctx.set_split(args.split)
+    stream = torch.cuda.current_stream()
+    if args.workload == "batched":
+        r = run_batched(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "cross":
+        r = run_cross(args, torch, ffd, ctx, dev, stream)
+    else:
+        r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
+    }
+    for k in ("config", "parity", "roofline", "plain", "cpu_baseline"):
+        if k in r:
+            line[k] = r[k]
     print(json.dumps(line), flush=True)
     ctx.close()
 

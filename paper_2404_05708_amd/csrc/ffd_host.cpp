@@ -105,10 +105,18 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
   return FFD_E_DEVICE;
 }
 
-// Modelled VALU instructions per lane for one step with R rows per lane:
-// (2D + 2) per cell (D subtractions, one multiply, D-1 FMAs, min3, max) plus
-// a few per step (lane shift, addressing).
-double step_cost(int R, int D) { return (double)R * (2 * D + 2) + 3.0; }
+// Modelled shader clocks of one stream step of a wave with R rows per lane.
+// A step issues I VALU instructions per wave: (2D + 2) per cell (D
+// subtractions, one multiply, D-1 FMAs, min3, max; FP64 needs two mins) and
+// about 8 per step (lane shift, LDS stores, bookkeeping).  A wave alone on
+// its SIMD issues about one instruction per 5 clocks and its serial chain
+// (lane shift, then a min3 and a max per row) takes about 12 + 17 R clocks;
+// waves sharing a SIMD share its wave64 issue slots of 4 clocks.
+double step_clocks(int R, int D, bool exact, double waves_per_simd) {
+  double I = (double)R * (2 * D + (exact ? 3 : 2)) + 8.0;
+  double shared = std::max(1.0, waves_per_simd) * I * 4.0;
+  return std::max(shared, std::max(I * 5.0, 12.0 + 17.0 * R));
+}
 
 // Stream steps a consumer band starts after its producer band.  At its
 // refill at step t the consumer waits for the entries of its chunk
@@ -437,7 +445,7 @@ double split_share(ffd_ctx *ctx) {
 }
 
 // Plan the units produced by `make(R, W, units)` for the R with the lowest
-// modelled makespan times per-step cost.
+// modelled stream length times per-step clocks.
 template <typename MakeUnits>
 int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single, MakeUnits make, Plan &best) {
   double best_cost = -1;
@@ -456,10 +464,11 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
       // a single pair: compare with the whole pair on one wave
       Plan whole;
       build_plan(units, R, 1, -1.0, rs.hand_max, whole);
-      if (whole.link_elems == 0 && whole.makespan <= pl.makespan) pl = std::move(whole);
+      if (whole.link_elems == 0 && whole.max_steps <= pl.max_steps) pl = std::move(whole);
     }
     pl.wpb = std::min(rs.wpb, pl.nwaves);
-    double cost = (pl.makespan + ffd::kWave) * step_cost(R, D);
+    double wps = std::ceil((double)pl.nwaves / (4.0 * ctx->cus));
+    double cost = ((double)pl.max_steps + ffd::kWave) * step_clocks(R, D, exact, wps);
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;
       best = std::move(pl);
