@@ -64,13 +64,37 @@ def kernel_ms(torch, step, steps, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def roofline(info, cells, kms, dim, exact):
+def profiled_traffic(profile):
+    """HBM bytes per launch recorded in a committed rocprofv3 summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
+    kernel source differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0].strip() in (
+                "kernel_source_sha256", "plan_header_sha256", "* traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k.strip().lstrip("* ")] = v.split()[0]
+    src = {"kernel_source_sha256": "paper_2404_05708_amd/csrc/ffd_kernels.hip",
+           "plan_header_sha256": "paper_2404_05708_amd/csrc/ffd_plan.h"}
+    for key, rel in src.items():
+        digest = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
+        if fields.get(key) != digest:
+            return None
+    return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
+
+
+def roofline(info, cells, kms, dim, exact, profile=None):
     ops = cells * imin(dim, exact)
     achieved = ops / (kms / 1e3)
     vt = "double" if exact else "float"
     return {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
-        "unit": "TVALUop/s", "frac": achieved / PEAK_VALU, "traffic": None,
+        "unit": "TVALUop/s", "frac": achieved / PEAK_VALU,
+        "traffic": profiled_traffic(profile) if profile else None,
         "kernel": f"ffd::stream_kernel<{info['rows_per_lane']}, {dim}, {vt}>", "kernel_ms": kms,
         "launch": info, "ops_per_cell": imin(dim, exact), "cells_per_launch": cells,
     }
@@ -158,7 +182,8 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
                                "random walks, q = p resampled + N(0, 0.1^2), Euclidean (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": errs},
-        "roofline": roofline(info, cells, kms, dim, False), "plain": plain, "cpu_baseline": cpu,
+        "roofline": roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md"),
+        "plain": plain, "cpu_baseline": cpu,
     }
 
 
