@@ -9,7 +9,9 @@
 //    orientations give the same bits);
 //  * units much longer than a wave's fair share are split into their bands
 //    of 64*R rows, which run on different waves and hand their boundary rows
-//    on through global "links" (release/acquire progress flags);
+//    on through global "links" (release/acquire progress flags); a unit
+//    whose boundary row does not fit a wave's LDS keeps its bands on one
+//    wave, in order, chained through links in the same way;
 //  * tasks are placed by list scheduling: the highest-priority ready task
 //    (longest remaining chain; longest first otherwise, the paper's sort by
 //    length) goes to the wave that frees first.  A band that reads a link
@@ -31,67 +33,12 @@
 #include <string>
 #include <vector>
 
-#include "ffd.h"
-#include "ffd_plan.h"
-
-namespace ffd {
-hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
-hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
-}  // namespace ffd
+#include "ffd_internal.h"
 
 using ffd::Job;
 using ffd::KernelArgs;
 
-namespace {
-
-// A planned launch.
-struct Plan {
-  int R = 4;
-  int nwaves = 0;
-  int wpb = 1;
-  int64_t hcap = 0;            // LDS hand-off entries per wave
-  int64_t max_steps = 0;       // longest stream of any wave
-  int64_t link_elems = 0;      // elements of all link buffers
-  int32_t nflags = 0;          // progress flags
-  double makespan = 0;         // modelled, in steps
-  std::vector<Job> jobs;       // grouped by wave, in placement order
-  std::vector<int32_t> wave_jobs;
-};
-
-struct PlanCache {
-  uint64_t key = 0;
-  Plan plan;
-  bool valid = false;
-};
-
-}  // namespace
-
-struct ffd_ctx {
-  int device = 0;
-  int cus = 0;
-  size_t lds_block_max = 0;   // LDS per workgroup the planner uses
-  size_t lds_cu = 0;          // LDS per compute unit
-  int tune_R = 0;
-  int tune_W = 0;
-  float split = 0.f;          // 0 auto, < 0 split only when needed, > 0 split above this share
-  uint32_t epoch = 0;
-  std::string last_error;
-  // plan most recently written to a workspace (skip the upload if unchanged)
-  void *plan_ws = nullptr;
-  uint64_t plan_ws_key = 0;
-  void *pinned = nullptr;     // staging buffer for plan uploads
-  size_t pinned_bytes = 0;
-  hipEvent_t upload_done = nullptr;
-  PlanCache batch_plans, pair_plans;
-  void *scratch = nullptr;    // device workspace for long single pairs (owned)
-  size_t scratch_bytes = 0;
-  ffd_launch_info last{};
-  uint64_t *last_err = nullptr; // device error word of the last launch (workspace)
-  uint32_t last_epoch = 0;
-  hipStream_t last_stream = nullptr;
-};
-
-namespace {
+namespace ffdi {
 
 const char *kVersion = "ffd 0.2.0 (gfx950)";
 
@@ -241,7 +188,16 @@ struct Task {
   int32_t succ;                    // task reading this task's outgoing link, -1 none
   double dur;                      // stream steps
   double prio;                     // longest remaining chain (steps)
+  int64_t chain_gap = 0;           // self-chained unit: idle steps between its bands, -1 not one
 };
+
+// Idle steps a band must wait after the previous band of its unit on the
+// same wave when the boundary row goes through global memory.
+int64_t self_gap(int64_t sumL) {
+  if ((double)sumL >= kLinkLag) return 0;
+  int64_t gap = std::max<int64_t>((int64_t)std::ceil(kLinkLag - (double)sumL), ffd::kMinTask);
+  return (gap + ffd::kGroup - 1) / ffd::kGroup * ffd::kGroup;
+}
 
 // List scheduling with precedence (see the file comment).  Fills
 // owner/order: the wave of every task and the tasks in placement order.
@@ -293,11 +249,6 @@ double list_schedule(const std::vector<Task> &tasks, int nwaves, std::vector<int
   return makespan;
 }
 
-struct Resources {
-  int nwaves_max;   // waves resident at once
-  int wpb;          // waves per workgroup
-  int64_t hand_max; // longest LDS hand-off row
-};
 
 // Launch resources for R rows per lane and W waves per SIMD: every wave gets
 // an equal share of the CU's LDS, which bounds the LDS hand-off row; all
@@ -317,13 +268,21 @@ Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W) {
   int64_t hand = ((int64_t)per_wave - fixed - 16) / vs;
   r.hand_max = hand > 0 ? hand : 0;
   r.nwaves_max = ctx->cus * 4 * W;
+  size_t lds = (size_t)r.wpb * (size_t)lds_bytes(R, D, exact, r.hand_max);
   if (ctx->device >= 0) {
     // registers may allow fewer resident waves than the LDS share assumes
     int blocks = 0;
-    size_t lds = (size_t)r.wpb * (size_t)lds_bytes(R, D, exact, r.hand_max);
     if (ffd::occupancy_stream(exact, R, D, r.wpb, lds, &blocks) == hipSuccess && blocks > 0)
       r.nwaves_max = std::min(r.nwaves_max, ctx->cus * blocks * r.wpb);
   }
+  // A launch whose waves wait on other waves needs every wave resident.
+  // Count a workgroup's LDS in whole 4 KiB units (no coarser allocation
+  // granule is assumed): a full CU at 3 workgroups of 53 KB did not hold
+  // all of them at once in measurements, although the occupancy query said
+  // it would.
+  size_t rounded = (lds + 4095) / 4096 * 4096;
+  int fit = (int)std::min<size_t>(blocks_per_cu, ctx->lds_cu / std::max<size_t>(rounded, 1));
+  r.nwaves_coop = std::min(r.nwaves_max, ctx->cus * std::max(fit, 1) * r.wpb);
   return r;
 }
 
@@ -336,20 +295,28 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
   double fair = total / std::max(1, nwaves);
   std::vector<Task> tasks;
   tasks.reserve(units.size());
-  std::vector<char> split(units.size(), 0);
+  std::vector<char> split(units.size(), 0);  // 1: bands on several waves, 2: chained on one wave
+  pl.coop = false;
   for (size_t i = 0; i < units.size(); ++i) {
     const Unit &u = units[i];
     bool need = u.nb > 1 && u.maxL > hand_max;
     bool want = u.nb > 1 && split_share >= 0 && u.steps() > split_share * fair;
-    split[i] = need || want;
-    if (!split[i]) {
-      tasks.push_back({(int32_t)i, 0, 0, -1, -1, u.steps(), u.steps()});
+    split[i] = want ? 1 : (need ? 2 : 0);
+    if (split[i] == 0) {
+      tasks.push_back({(int32_t)i, 0, 0, -1, -1, u.steps(), u.steps(), -1});
+    } else if (split[i] == 2) {
+      // the boundary row does not fit the LDS hand-off: the bands stay on
+      // one wave in order and hand their rows on through global links
+      int64_t gap = self_gap(u.sumL);
+      double dur = u.steps() + (double)(u.nb - 1) * (double)gap;
+      tasks.push_back({(int32_t)i, 0, 0, -1, -1, dur, dur, gap});
     } else {
+      pl.coop = true;
       int32_t first = (int32_t)tasks.size();
       for (int32_t bnd = 0; bnd < u.nb; ++bnd) {
         double chain = (double)(u.nb - 1 - bnd) * kLinkLag + (double)u.sumL;
         tasks.push_back({(int32_t)i, bnd, 1, bnd > 0 ? first + bnd - 1 : -1,
-                         bnd + 1 < u.nb ? first + bnd + 1 : -1, (double)u.sumL, chain});
+                         bnd + 1 < u.nb ? first + bnd + 1 : -1, (double)u.sumL, chain, -1});
       }
     }
   }
@@ -363,10 +330,19 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
   pl.link_elems = 0;
   pl.nflags = 0;
   for (size_t t = 0; t < tasks.size(); ++t) {
+    const Unit &u = units[tasks[t].unit];
     if (tasks[t].succ >= 0) {
       link_of[t] = pl.link_elems;
       flag_of[t] = pl.nflags++;
-      pl.link_elems += units[tasks[t].unit].sumL;
+      pl.link_elems += u.sumL;
+    } else if (tasks[t].chain_gap >= 0) {
+      // one boundary row, rewritten in place by every band (a band reads
+      // each entry, into LDS, well before it overwrites it), and one flag
+      // per band boundary (each flag's count only grows)
+      link_of[t] = pl.link_elems;
+      flag_of[t] = pl.nflags;
+      pl.nflags += u.nb - 1;
+      pl.link_elems += u.sumL;
     }
   }
   pl.hcap = 0;
@@ -395,7 +371,11 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
     wpos[w] = s + tasks[t].dur;
   }
   std::vector<int32_t> count(nwaves, 0);
-  for (int32_t t : order) count[owner[t]] += idle[t] > 0 ? 2 : 1;
+  for (int32_t t : order) {
+    const Task &tk = tasks[t];
+    int32_t nbands = tk.chain_gap >= 0 ? units[tk.unit].nb : 1;
+    count[owner[t]] += (idle[t] > 0 ? 1 : 0) + nbands + (tk.chain_gap > 0 ? nbands - 1 : 0);
+  }
   pl.wave_jobs.assign(nwaves + 1, 0);
   for (int w = 0; w < nwaves; ++w) pl.wave_jobs[w + 1] = pl.wave_jobs[w] + count[w];
   std::vector<int32_t> fillp(pl.wave_jobs.begin(), pl.wave_jobs.end() - 1);
@@ -419,13 +399,36 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
     jb.col_first = u.col_first;
     jb.col_count = u.col_count;
     jb.out_stride = u.out_stride;
-    jb.band_first = tk.band_first;
-    jb.band_count = tk.band_count;
-    jb.link_in = tk.pred >= 0 ? link_of[tk.pred] : -1;
-    jb.flag_in = tk.pred >= 0 ? flag_of[tk.pred] : -1;
-    jb.link_out = link_of[t];
-    jb.flag_out = flag_of[t];
-    pl.jobs[fillp[owner[t]]++] = jb;
+    if (tk.chain_gap < 0) {
+      jb.band_first = tk.band_first;
+      jb.band_count = tk.band_count;
+      jb.link_in = tk.pred >= 0 ? link_of[tk.pred] : -1;
+      jb.flag_in = tk.pred >= 0 ? flag_of[tk.pred] : -1;
+      jb.link_out = link_of[t];
+      jb.flag_out = flag_of[t];
+      pl.jobs[fillp[owner[t]]++] = jb;
+      continue;
+    }
+    // self-chained unit: one job per band, each band after an idle job
+    // where the bands are too short to keep kLinkLag apart
+    for (int32_t b = 0; b < u.nb; ++b) {
+      if (b > 0 && tk.chain_gap > 0) {
+        Job idle_job;
+        memset(&idle_job, 0, sizeof idle_job);
+        idle_job.row_sel = ffd::kRowIdle;
+        idle_job.col_count = (int32_t)tk.chain_gap;
+        idle_job.link_in = idle_job.link_out = -1;
+        idle_job.flag_in = idle_job.flag_out = -1;
+        pl.jobs[fillp[owner[t]]++] = idle_job;
+      }
+      jb.band_first = b;
+      jb.band_count = 1;
+      jb.link_in = b > 0 ? link_of[t] : -1;
+      jb.flag_in = b > 0 ? flag_of[t] + b - 1 : -1;
+      jb.link_out = b + 1 < u.nb ? link_of[t] : -1;
+      jb.flag_out = b + 1 < u.nb ? flag_of[t] + b : -1;
+      pl.jobs[fillp[owner[t]]++] = jb;
+    }
   }
   double mx = 0;
   for (double x : wpos) mx = std::max(mx, x);
@@ -460,6 +463,11 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
     if ((size_t)nwaves > ntasks) nwaves = (int)std::max<size_t>(1, ntasks);
     Plan pl;
     build_plan(units, R, nwaves, share, rs.hand_max, pl);
+    if (pl.coop && pl.nwaves > rs.nwaves_coop) {
+      Plan fewer;
+      build_plan(units, R, rs.nwaves_coop, share, rs.hand_max, fewer);
+      pl = std::move(fewer);
+    }
     if (single && pl.link_elems > 0) {
       // a single pair: compare with the whole pair on one wave
       Plan whole;
@@ -606,7 +614,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.flags = (uint64_t *)(w + wl.flags);
   a.err = (uint64_t *)(w + wl.err);
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
-  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.nflags > 0, st);
+  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
@@ -746,7 +754,9 @@ int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq,
   return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st);
 }
 
-}  // namespace
+}  // namespace ffdi
+
+using namespace ffdi;
 
 extern "C" {
 

@@ -1,0 +1,99 @@
+// Internal declarations shared by the host files of the library (planner,
+// launcher and the serving loop).  Not part of the C ABI.
+#ifndef FFD_INTERNAL_H
+#define FFD_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ffd.h"
+#include "ffd_plan.h"
+
+namespace ffd {
+hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
+hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+}  // namespace ffd
+
+namespace ffdi {
+
+using ffd::Job;
+using ffd::KernelArgs;
+
+
+// A planned launch.
+struct Plan {
+  int R = 4;
+  int nwaves = 0;
+  int wpb = 1;
+  int64_t hcap = 0;            // LDS hand-off entries per wave
+  int64_t max_steps = 0;       // longest stream of any wave
+  int64_t link_elems = 0;      // elements of all link buffers
+  int32_t nflags = 0;          // progress flags
+  bool coop = false;           // some link joins two waves: cooperative launch
+  double makespan = 0;         // modelled, in steps
+  std::vector<Job> jobs;       // grouped by wave, in placement order
+  std::vector<int32_t> wave_jobs;
+};
+
+struct PlanCache {
+  uint64_t key = 0;
+  Plan plan;
+  bool valid = false;
+};
+
+}  // namespace ffdi
+
+struct ffd_ctx {
+  int device = 0;
+  int cus = 0;
+  size_t lds_block_max = 0;   // LDS per workgroup the planner uses
+  size_t lds_cu = 0;          // LDS per compute unit
+  int tune_R = 0;
+  int tune_W = 0;
+  float split = 0.f;          // 0 auto, < 0 split only when needed, > 0 split above this share
+  uint32_t epoch = 0;
+  std::string last_error;
+  // plan most recently written to a workspace (skip the upload if unchanged)
+  void *plan_ws = nullptr;
+  uint64_t plan_ws_key = 0;
+  void *pinned = nullptr;     // staging buffer for plan uploads
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  ffdi::PlanCache batch_plans, pair_plans;
+  void *scratch = nullptr;    // device workspace for long single pairs (owned)
+  size_t scratch_bytes = 0;
+  ffd_launch_info last{};
+  uint64_t *last_err = nullptr; // device error word of the last launch (workspace)
+  uint32_t last_epoch = 0;
+  hipStream_t last_stream = nullptr;
+};
+
+
+namespace ffdi {
+
+int fail(ffd_ctx *ctx, int code, const char *msg);
+int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what);
+int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *name);
+int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact);
+int lds_bytes(int R, int D, bool exact, int64_t hcap);
+int64_t self_gap(int64_t sumL);
+
+struct Resources {
+  int nwaves_max;   // waves resident at once
+  int nwaves_coop;  // waves surely resident at once (cooperative launches)
+  int wpb;          // waves per workgroup
+  int64_t hand_max; // longest LDS hand-off row
+};
+Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W);
+
+int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
+               bool exact, Plan &pl);
+int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq, const void *DB,
+                 const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, void *out, void *ws,
+                 size_t ws_bytes, hipStream_t st, bool exact);
+
+}  // namespace ffdi
+
+#endif  // FFD_INTERNAL_H
