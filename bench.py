@@ -12,6 +12,8 @@ not counted).
   large  one 131072 x 131072 3-D pair through ffd_distance
   cross  1024 x 1024 curves of 256 int32 2-D points through ffd_cross_i32
          (squared Euclidean, int64 results, bit-exact)
+  serving  Poisson-arrival queries against a resident 10,000-curve database
+         through the ffd_server calls: p50/p99 latency at a fixed rate
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (VALU issue rate: the path has no contraction and moves O(n+m) bytes per
@@ -294,12 +296,115 @@ def run_cross(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_serving(args, torch, ffd, ctx, dev, stream):
+    """Queries against the resident 10,000-curve database: a closed-loop
+    burst measures the saturation rate S, then Poisson arrivals at a fixed
+    rate (default 0.5 S) give the latency percentiles and cells/s."""
+    import queue
+    import threading
+
+    import workloads
+    DB, dbo = workloads.serving_db()
+    db_points = int(dbo[-1])
+    DBd = torch.from_numpy(DB).to(dev)
+    db = ffd.Database(ctx, DBd, dbo)
+    srv = ffd.Server(db, max_slots=args.slots, max_query=8192)
+    nwarm, nsat, nopen = 16, args.sat_requests, args.requests
+    qs = workloads.serving_queries(count=nwarm + nsat + nopen)
+    for q in qs[:nwarm]:
+        srv.wait(srv.submit(q))
+    # saturation: every request submitted at once
+    sat = qs[nwarm:nwarm + nsat]
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(q) for q in sat]
+    for t in tickets:
+        srv.wait(t)
+    sat_s = time.perf_counter() - t0
+    sat_qps = nsat / sat_s
+    sat_cells = sum(len(q) for q in sat) * db_points / sat_s
+    sat_stats = srv.stats()
+    # open loop at a fixed rate
+    rate = args.qps if args.qps > 0 else 0.5 * sat_qps
+    arrivals = workloads.poisson_arrivals(count=nopen, rate=rate)
+    load = qs[nwarm + nsat:]
+    results = {}
+    pend = queue.Queue()
+
+    def collect():
+        while True:
+            item = pend.get()
+            if item is None:
+                return
+            i, t = item
+            results[i] = srv.wait(t)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    for i, ta in enumerate(arrivals):
+        while True:
+            dt = t0 + ta - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.0005))
+        pend.put((i, srv.submit(load[i])))
+    pend.put(None)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    errs = st["failed"]
+
+    # parity of two served results against the oracle
+    import oracle
+    pick = [0, 1]
+    sq, so = workloads.concat([load[i] for i in pick])
+    cores = cpu_cores()
+    t2 = time.perf_counter()
+    want = oracle.dfd_cross(sq, so, DB, dbo, oracle.EUCLIDEAN, nthreads=cores)
+    cw = time.perf_counter() - t2
+    parity_ok = bool(all(np.all(np.abs(results[i] - want[r]) <= TOL * want[r]) for r, i in enumerate(pick)))
+    s_cells = int(np.sum(np.diff(so))) * db_points
+    cpu = None if args.no_cpu else {
+        "value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+        "sample": f"2 of the open-loop queries ({int(np.sum(np.diff(so)))} points) against all 10,000 "
+                  f"database curves ({s_cells} cells), FP64 rolling-row oracle on {cores} threads, {cw:.2f} s"}
+    srv.close()
+    db.close()
+    cells_open = st["cells_per_s"]
+    info = {"rows_per_lane": 8, "waves": st["waves"], "requests_per_launch": st["requests_per_launch"]}
+    return {
+        "value": cells_open, "ms_per_step": st["mean_ms"], "dtype": "f32",
+        "config": {"workload": "serving: Poisson arrivals, each a query against a resident database of 10,000 "
+                               "curves; lengths log-normal (median 300, sigma 1, clipped to [32, 8192]), 2-D "
+                               "float32 random walks, Euclidean (seeds 5, 6, 7)",
+                   "requests": nopen, "db_points": db_points, "global_batch": nopen},
+        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "failed_requests": errs},
+        "serving": {"qps_target": rate, "qps_achieved": st["qps"], "p50_ms": st["p50_ms"],
+                    "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+                    "deferred": st["deferred"], "open_loop_wall_s": wall,
+                    "saturation": {"requests": nsat, "qps": sat_qps, "cells_per_s": sat_cells,
+                                   "p50_ms": sat_stats["p50_ms"], "p99_ms": sat_stats["p99_ms"]},
+                    "max_slots": args.slots},
+        "roofline": {"bound": "alu", "achieved": sat_cells * imin(2) / 1e12, "peak": PEAK_VALU / 1e12,
+                     "unit": "TVALUop/s", "frac": sat_cells * imin(2) / PEAK_VALU, "traffic": None,
+                     "kernel": "ffd::stream_kernel<8, 2, float>", "kernel_ms": None, "launch": info,
+                     "basis": "saturation cells/s over the closed-loop burst (host overhead included)"},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving"], default="batched")
+    ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
+    ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
+    ap.add_argument("--qps", type=float, default=0.0, help="open-loop arrival rate; 0 = half the saturation rate")
+    ap.add_argument("--slots", type=int, default=16, help="requests in flight (serving)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-pair comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-pairs", type=int, default=4096, help="pairs in the CPU oracle sample (batched)")
@@ -330,6 +435,8 @@ def main():
         r = run_batched(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "cross":
         r = run_cross(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "serving":
+        r = run_serving(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {
@@ -337,7 +444,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "roofline", "plain", "cpu_baseline"):
+    for k in ("config", "parity", "serving", "roofline", "plain", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     print(json.dumps(line), flush=True)

@@ -191,6 +191,76 @@ int ffd_last_errors(ffd_ctx *ctx, int32_t *flags);
  * Errors: FFD_E_INVALID (NaN or huge share). */
 int ffd_set_split(ffd_ctx *ctx, float share);
 
+/* ------------------------------------------------------------ serving ---
+ * Queries against a device-resident database of curves (the batched form
+ * of Sec. 4 against one reference curve, turned around: one query against
+ * every database curve).  Requests are submitted from the host at any time;
+ * a worker thread admits them into launches as soon as a launch slot and
+ * its arena region are free, so requests that arrive while others run on
+ * the GPU join the next launch and their work overlaps on the device
+ * (continuous batching).  Each result equals, bit for bit, what ffd_cross
+ * gives for the same query and database, whatever else runs with it. */
+typedef struct ffd_db ffd_db;
+typedef struct ffd_server ffd_server;
+
+/* A database of ndb float32 curves: DB[db_off[k]*dim .. db_off[k+1]*dim) is
+ * curve k (device pointer, kept referenced until ffd_db_destroy; db_off is a
+ * host array, copied).  The database must outlive every server made from
+ * it and must not change while a server exists.
+ * Errors: FFD_E_INVALID (NULL, ndb < 1, bad offsets or dim), FFD_E_UNSUPPORTED
+ * (dim > FFD_MAX_DIM). */
+int ffd_db_create(ffd_ctx *ctx, const float *DB, const int64_t *db_off, int64_t ndb, int32_t dim, ffd_db **out);
+void ffd_db_destroy(ffd_db *db);
+
+/* Device bytes of the arena a server needs: a reordered copy of the
+ * database plus the regions of its launch slots, sized for max_slots
+ * requests in flight and queries of up to max_query points.
+ * Errors: FFD_E_INVALID (NULL, max_slots outside 1..4096, max_query outside
+ * 1..2^20). */
+int ffd_server_arena_size(ffd_db *db, int32_t max_slots, int64_t max_query, size_t *bytes);
+
+/* Start a server on the database's context device.  `arena` is caller
+ * device memory of arena_bytes >= ffd_server_arena_size(...); it stays in
+ * use until ffd_server_destroy.  The server owns a worker thread, four HIP
+ * streams and pinned host staging buffers.
+ * Errors: FFD_E_INVALID, FFD_E_NOMEM (arena too small), FFD_E_DEVICE. */
+int ffd_server_create(ffd_db *db, void *arena, size_t arena_bytes, int32_t max_slots, int64_t max_query,
+                      ffd_server **out);
+/* Waits for every submitted request, then stops the worker. */
+void ffd_server_destroy(ffd_server *s);
+
+/* Submit one query: q is a HOST array of n*dim floats (copied before the
+ * call returns); out is a HOST array of ndb floats that receives
+ * delta(query, database curve k) in out[k] and must stay valid until the
+ * request is collected by ffd_server_poll or ffd_server_wait.  Returns at
+ * once with a ticket.  Thread-safe.
+ * Errors: FFD_E_INVALID (NULL, n < 1, unknown metric), FFD_E_UNSUPPORTED
+ * (n > max_query). */
+int ffd_server_submit(ffd_server *s, const float *q, int64_t n, int32_t metric, float *out, uint64_t *ticket);
+/* *done = 1 once the request has finished; the ticket is then collected
+ * and the request's status returned (FFD_OK or FFD_E_DEVICE).  Thread-safe.
+ * Errors: FFD_E_INVALID (unknown or collected ticket). */
+int ffd_server_poll(ffd_server *s, uint64_t ticket, int32_t *done);
+/* Block until the request has finished (timeout_us < 0: no limit), then
+ * collect it.  Thread-safe.
+ * Errors: FFD_E_TIMEOUT, FFD_E_INVALID (unknown ticket), FFD_E_DEVICE. */
+int ffd_server_wait(ffd_server *s, uint64_t ticket, int64_t timeout_us);
+
+typedef struct ffd_server_stats {
+  int64_t submitted, completed, failed;
+  int64_t deferred;     /* submissions that found no free launch slot */
+  int64_t queued;       /* waiting for a launch slot now */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit-to-result latency */
+  double qps;           /* completed requests per second, first submit to last result */
+  double cells_per_s;   /* DP cells of completed requests per second, same span */
+  int32_t requests_per_launch, waves;
+} ffd_server_stats;
+
+/* Statistics since creation or the last reset.  Thread-safe. */
+int ffd_server_get_stats(ffd_server *s, ffd_server_stats *out);
+int ffd_server_reset_stats(ffd_server *s);
+const char *ffd_server_last_error(const ffd_server *s);
+
 #ifdef __cplusplus
 }
 #endif

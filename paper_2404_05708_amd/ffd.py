@@ -37,6 +37,9 @@ EXPORTS = (
     "ffd_create", "ffd_create_planner", "ffd_destroy", "ffd_strerror", "ffd_last_error", "ffd_version",
     "ffd_distance", "ffd_distance_i32", "ffd_batch", "ffd_batch_i32", "ffd_cross",
     "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
+    "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
+    "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
+    "ffd_server_last_error",
 )
 
 
@@ -45,6 +48,17 @@ class LaunchInfo(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("lds_per_wave", ctypes.c_int32),
                 ("exact", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("stream_steps", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("deferred", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("qps", ctypes.c_double), ("cells_per_s", ctypes.c_double),
+                ("requests_per_launch", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -99,6 +113,29 @@ def _load():
     lib.ffd_set_split.restype = ctypes.c_int
     lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
     lib.ffd_last_launch.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.ffd_db_create.argtypes = [vp, vp, i64p, i64, i32, ctypes.POINTER(vp)]
+    lib.ffd_db_create.restype = ctypes.c_int
+    lib.ffd_db_destroy.argtypes = [vp]
+    lib.ffd_db_destroy.restype = None
+    lib.ffd_server_arena_size.argtypes = [vp, i32, i64, ctypes.POINTER(sz)]
+    lib.ffd_server_arena_size.restype = ctypes.c_int
+    lib.ffd_server_create.argtypes = [vp, vp, sz, i32, i64, ctypes.POINTER(vp)]
+    lib.ffd_server_create.restype = ctypes.c_int
+    lib.ffd_server_destroy.argtypes = [vp]
+    lib.ffd_server_destroy.restype = None
+    lib.ffd_server_submit.argtypes = [vp, vp, i64, i32, vp, u64p]
+    lib.ffd_server_submit.restype = ctypes.c_int
+    lib.ffd_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+    lib.ffd_server_poll.restype = ctypes.c_int
+    lib.ffd_server_wait.argtypes = [vp, ctypes.c_uint64, i64]
+    lib.ffd_server_wait.restype = ctypes.c_int
+    lib.ffd_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.ffd_server_get_stats.restype = ctypes.c_int
+    lib.ffd_server_reset_stats.argtypes = [vp]
+    lib.ffd_server_reset_stats.restype = ctypes.c_int
+    lib.ffd_server_last_error.argtypes = [vp]
+    lib.ffd_server_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -332,3 +369,89 @@ class Context:
 
     def workspace_size(self, op, a_off, b_off, dim):
         return ffd_workspace_size(self.handle, op, a_off, b_off, dim)
+
+
+# ------------------------------------------------------------------ serving
+
+class Database:
+    """A device-resident database of float32 curves (ffd_db).  Keeps the
+    coordinate tensor alive for as long as the handle exists."""
+
+    def __init__(self, ctx, DB, db_off):
+        DB, Dp = _curve(DB, torch.float32, "DB")
+        do, dop = _offsets(db_off)
+        self.ctx = ctx
+        self.tensor = DB
+        self.offsets = do
+        self.ndb = len(do) - 1
+        self.dim = DB.shape[1]
+        h = ctypes.c_void_p()
+        _check(lib.ffd_db_create(ctx.handle, Dp, dop, self.ndb, self.dim, ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib.ffd_db_destroy(self.handle)
+            self.handle = None
+
+
+class Server:
+    """Continuous-batching query server over a Database (ffd_server).  The
+    arena is a torch tensor on the database's device."""
+
+    def __init__(self, db, max_slots=8, max_query=8192):
+        self.db = db
+        n = ctypes.c_size_t()
+        _check(lib.ffd_server_arena_size(db.handle, int(max_slots), int(max_query), ctypes.byref(n)),
+               db.ctx.handle)
+        self.arena = torch.empty(max(n.value, 1), dtype=torch.uint8, device=db.tensor.device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(lib.ffd_server_create(db.handle, ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                     int(max_slots), int(max_query), ctypes.byref(h)), db.ctx.handle)
+        self.handle = h
+        self._live = {}  # ticket -> (query copy, result array) kept alive until collected
+
+    def _check(self, rc):
+        if rc != FFD_OK:
+            raise FFDError(rc, f"{lib.ffd_strerror(rc).decode()}: {lib.ffd_server_last_error(self.handle).decode()}")
+
+    def submit(self, q, metric=FFD_EUCLIDEAN):
+        """Submit a (n, dim) float32 host array; returns a ticket."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        if q.ndim == 1:
+            q = q.reshape(-1, 1)
+        if q.shape[1] != self.db.dim:
+            raise ValueError("query dimension differs from the database's")
+        out = np.empty(self.db.ndb, dtype=np.float32)
+        t = ctypes.c_uint64()
+        self._check(lib.ffd_server_submit(self.handle, q.ctypes.data_as(ctypes.c_void_p), q.shape[0],
+                                          int(metric), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
+        self._live[t.value] = (q, out)
+        return t.value
+
+    def poll(self, ticket):
+        """The result array once the request has finished, else None."""
+        done = ctypes.c_int32()
+        self._check(lib.ffd_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done)))
+        if not done.value:
+            return None
+        return self._live.pop(ticket)[1]
+
+    def wait(self, ticket, timeout_us=-1):
+        self._check(lib.ffd_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us)))
+        return self._live.pop(ticket)[1]
+
+    def stats(self):
+        st = ServerStats()
+        self._check(lib.ffd_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        self._check(lib.ffd_server_reset_stats(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.ffd_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()

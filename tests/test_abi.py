@@ -136,3 +136,34 @@ def test_set_tuning_validation(planner):
         ffd.ffd_set_tuning(planner, 3, 1)
     with pytest.raises(ffd.FFDError):
         ffd.ffd_set_tuning(planner, 4, 99)
+
+
+def test_serving_database_and_arena(planner):
+    L = ffd.lib
+    DB, dbo = workloads.serving_db(seed=9, count=300)
+    db = ctypes.c_void_p()
+    assert L.ffd_db_create(planner, FAKE, _i64p(dbo), 300, 2, ctypes.byref(db)) == ffd.FFD_OK
+    try:
+        bad = dbo.copy()
+        bad[5] = bad[4]
+        h = ctypes.c_void_p()
+        assert L.ffd_db_create(planner, FAKE, _i64p(bad), 300, 2, ctypes.byref(h)) == ffd.FFD_E_INVALID
+        assert L.ffd_db_create(planner, None, _i64p(dbo), 300, 2, ctypes.byref(h)) == ffd.FFD_E_INVALID
+        assert L.ffd_db_create(planner, FAKE, _i64p(dbo), 300, 9, ctypes.byref(h)) == ffd.FFD_E_UNSUPPORTED
+        n = ctypes.c_size_t()
+        assert L.ffd_server_arena_size(db, 8, 8192, ctypes.byref(n)) == ffd.FFD_OK
+        # the reordered database, the queries of 8 requests and their results at least
+        assert n.value >= dbo[-1] * 2 * 4 + 8 * 8192 * 2 * 4 + 8 * 300 * 4
+        small = ctypes.c_size_t()
+        assert L.ffd_server_arena_size(db, 1, 100, ctypes.byref(small)) == ffd.FFD_OK
+        assert small.value < n.value
+        assert L.ffd_server_arena_size(db, 0, 100, ctypes.byref(small)) == ffd.FFD_E_INVALID
+        assert L.ffd_server_arena_size(db, 8, 0, ctypes.byref(small)) == ffd.FFD_E_INVALID
+        s = ctypes.c_void_p()
+        assert L.ffd_server_create(db, FAKE, n.value - 1, 8, 8192, ctypes.byref(s)) == ffd.FFD_E_NOMEM
+        assert L.ffd_server_create(db, FAKE, n.value, 8, 8192, ctypes.byref(s)) == ffd.FFD_E_DEVICE
+        assert L.ffd_server_create(db, None, n.value, 8, 8192, ctypes.byref(s)) == ffd.FFD_E_INVALID
+        t = ctypes.c_uint64()
+        assert L.ffd_server_submit(None, FAKE, 5, 0, FAKE, ctypes.byref(t)) == ffd.FFD_E_INVALID
+    finally:
+        L.ffd_db_destroy(db)

@@ -1,0 +1,119 @@
+"""GPU serving: queries against a resident database with continuous batching.
+
+Each query's distances to every database curve must be the same, bit for
+bit, when the query runs alone and when it runs mixed with others admitted
+into the same or overlapping launches; they must equal ffd_cross on the
+same inputs bit for bit, and the FP64 oracle within a relative 2e-6.
+"""
+import sys
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def served(gpu):
+    from paper_2404_05708_amd import ffd
+    ctx = ffd.Context(0)
+    # a smaller database with the serving length law, plus long curves so
+    # that long queries need boundary rows that do not fit LDS
+    DB, dbo = workloads.serving_db(seed=51, count=1500)
+    rng = np.random.default_rng(52)
+    extra = [workloads.walk(rng, L, 2) for L in (3000, 5000, 8192)]
+    parts = [DB[dbo[k]:dbo[k + 1]] for k in range(len(dbo) - 1)] + extra
+    DB, dbo = workloads.concat(parts)
+    DBd = torch.from_numpy(DB).to("cuda:0")
+    db = ffd.Database(ctx, DBd, dbo)
+    srv = ffd.Server(db, max_slots=8, max_query=8192)
+    yield ffd, ctx, DB, dbo, DBd, srv
+    srv.close()
+    db.close()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def queries():
+    qs = workloads.serving_queries(seed=53, count=10)
+    rng = np.random.default_rng(54)
+    qs.append(workloads.walk(rng, 2600, 2))   # several bands, long database curves
+    qs.append(workloads.walk(rng, 40, 2))
+    return qs
+
+
+def test_alone_equals_mix_equals_cross(served):
+    ffd, ctx, DB, dbo, DBd, srv = served
+    qs = queries()
+    say(f"case: serving, {len(qs)} queries alone, db {len(dbo) - 1} curves")
+    alone = []
+    for q in qs:
+        alone.append(srv.wait(srv.submit(q)).copy())
+    say("case: serving, all queries at once")
+    tickets = [srv.submit(q) for q in qs]
+    mix = [srv.wait(t).copy() for t in tickets]
+    for a, b in zip(alone, mix):
+        np.testing.assert_array_equal(a, b)
+    say("case: serving, mixed from two threads")
+    res = {}
+
+    def client(idx):
+        for i in idx:
+            res[i] = srv.wait(srv.submit(qs[i])).copy()
+    th = [threading.Thread(target=client, args=(range(j, len(qs), 2),)) for j in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for i in range(len(qs)):
+        np.testing.assert_array_equal(res[i], alone[i])
+    say("case: serving vs ffd_cross")
+    Qs, qo = workloads.concat(qs)
+    cross = ctx.cross(torch.from_numpy(Qs).to("cuda:0"), qo, DBd, dbo).cpu().numpy()
+    for i in range(len(qs)):
+        np.testing.assert_array_equal(alone[i], cross[i])
+    say("case: serving vs oracle")
+    pick = [0, len(qs) - 2, len(qs) - 1]
+    sq, so = workloads.concat([qs[i] for i in pick])
+    want = oracle.dfd_cross(sq, so, DB, dbo, oracle.EUCLIDEAN, nthreads=8)
+    for r, i in enumerate(pick):
+        got = alone[i].astype(np.float64)
+        assert np.all(np.abs(got - want[r]) <= TOL * np.abs(want[r]))
+
+
+def test_metrics_and_stats(served):
+    ffd, ctx, DB, dbo, DBd, srv = served
+    q = queries()[3]
+    srv.reset_stats()
+    e = srv.wait(srv.submit(q, ffd.FFD_EUCLIDEAN)).astype(np.float64)
+    s = srv.wait(srv.submit(q, ffd.FFD_SQEUCLIDEAN)).astype(np.float64)
+    assert np.all(np.abs(s - e * e) <= 4 * TOL * s + 1e-30)
+    st = srv.stats()
+    assert st["completed"] == 2 and st["failed"] == 0
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+
+
+def test_poll_and_errors(served):
+    ffd, ctx, DB, dbo, DBd, srv = served
+    q = queries()[0]
+    t = srv.submit(q)
+    while srv.poll(t) is None:
+        pass
+    with pytest.raises(ffd.FFDError):
+        srv.poll(t)  # collected
+    with pytest.raises(ffd.FFDError):
+        srv.submit(np.zeros((9000, 2), dtype=np.float32))  # longer than max_query
+    with pytest.raises(ffd.FFDError):
+        srv.submit(np.zeros((0, 2), dtype=np.float32))
