@@ -449,8 +449,10 @@ struct Stream {
   // link store are uniform branches, so the hot registers stay where they
   // are (code variants of the group made the compiler shuffle them at every
   // merge).
+  template <bool PLAIN>
   __device__ __forceinline__ void group(int32_t t0, int32_t win, bool window, bool link, const GroupIn &g,
                                         V *hout, V *lout, V &res) {
+    if (PLAIN) window = link = false;
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       V bottom = Mp[R - 1];
@@ -573,7 +575,9 @@ struct Stream {
     GroupIn g;
     load_group(t0, hin_at(t0), g);
     V res;
-    group(t0, win0, t0 < win0 + kWave, hout63 == kHoutLink, g, hout, lout, res);
+    bool window = t0 < win0 + kWave, link = hout63 == kHoutLink;
+    if (!window && !link) group<true>(t0, win0, false, false, g, hout, lout, res);
+    else group<false>(t0, win0, window, link, g, hout, lout, res);
     if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
       N::store(a.out, out63, res, a.metric);
     return true;

@@ -28,10 +28,11 @@
 namespace ffd {
 
 constexpr int kWave = 64;            // lanes per wavefront
-constexpr int kGroup = 8;            // steps per unrolled group; task lengths are multiples
+constexpr int kGroup = 16;           // steps per unrolled group; task lengths are multiples
 constexpr int kRing = 256;           // column ring entries per wave (power of two)
 constexpr int kFill = 64;            // steps between ring refills (= one entry per lane)
-constexpr int kMinTask = 72;         // shortest task stream (> 64: a task's rows are read one group early)
+constexpr int kMinTask = 80;         // shortest task stream: >= kWave + kGroup, so the next band reads a
+                                     // hand-off entry a group after lane 63 wrote it
 constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
 constexpr int kDescSlots = 8;        // task descriptors in flight per wave
 constexpr int kLinkRing = 256;       // LDS ring for boundary rows arriving over a link
