@@ -183,11 +183,12 @@ int ffd_last_errors(ffd_ctx *ctx, int32_t *flags);
 /* How eagerly long pairs are split into bands that run on different
  * wavefronts (their boundary rows pass through the workspace): a pair whose
  * modelled work exceeds `share` times a wavefront's fair share of the launch
- * is split; a negative value = split only when a pair's boundary row does not
- * fit in LDS; 0 = automatic: ffd_batch and ffd_cross split only when needed,
- * ffd_distance splits a long pair whenever the model says it pays.  A launch
- * with split pairs is cooperative (all its workgroups resident at once).
- * Results do not depend on the setting.
+ * is split; a negative value = never (a pair whose boundary row does not fit
+ * in LDS then keeps its bands on one wavefront, chained through the
+ * workspace); 0 = automatic: share 1.25 for ffd_batch and ffd_cross, and
+ * ffd_distance splits a long pair whenever the model says it pays.  A
+ * launch with split pairs is cooperative (all its workgroups resident at
+ * once).  Results do not depend on the setting.
  * Errors: FFD_E_INVALID (NaN or huge share). */
 int ffd_set_split(ffd_ctx *ctx, float share);
 

@@ -438,11 +438,13 @@ void build_plan(const std::vector<Unit> &units, int R, int nwaves, double split_
 }
 
 // Batched and cross launches split a unit into bands over several waves
-// only when its boundary row does not fit the wave's LDS: many independent
-// units already fill the GPU, and cross-wave links cost waiting time that
-// the balance they buy does not repay (measured on the 4096-pair workload).
+// when it is longer than 1.25 times a wave's fair share of the launch: a
+// unit that long would otherwise set the launch's makespan, while splitting
+// shorter units costs more in link lag and waiting than the balance gains
+// (measured on the 4096-pair workload: 1.07 ms at 1.25, 1.10 ms at 1.0,
+// 1.16 ms at 1.5, 1.23 ms without splitting).
 double split_share(ffd_ctx *ctx) {
-  if (ctx->split == 0.f) return -1.0;
+  if (ctx->split == 0.f) return 1.25;
   if (ctx->split < 0.f) return -1.0;
   return ctx->split;
 }

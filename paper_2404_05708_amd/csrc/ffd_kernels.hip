@@ -111,6 +111,9 @@ __device__ __forceinline__ int64_t uni64(int64_t x) {
 // (a quarter of a second) before the wait is abandoned and reported.
 constexpr int kSpinLimit = 1 << 22;
 
+// s_waitcnt operand (gfx9 encoding) that waits for vmcnt = 0 only.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <int R, int D, typename V>
 struct Stream {
   using N = Num<V>;
@@ -324,7 +327,8 @@ struct Stream {
   }
 
   // Wait until the link flag reports at least `need` entries of this launch.
-  // Relaxed polling; one acquire fence once the entries are there.
+  // Agent-scope polling of the count; the row itself is then read with
+  // agent-scope loads (see flush_links).
   __device__ void wait_link(int32_t flag, uint32_t need) {
     uint64_t want = flag_word(a.epoch, need);
     uint64_t *fl = a.flags + flag;
@@ -337,7 +341,9 @@ struct Stream {
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the row is read with agent-scope loads issued after this point (the
+    // exit depends on the loaded count); keep the compiler from moving them
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
 
   // Issue the global loads of ring entries [t, t + 64): one per lane, plus
@@ -450,20 +456,16 @@ struct Stream {
   // are (code variants of the group made the compiler shuffle them at every
   // merge).
   template <bool PLAIN>
-  __device__ __forceinline__ void group(int32_t t0, int32_t win, bool window, bool link, const GroupIn &g,
-                                        V *hout, V *lout, V &res) {
-    if (PLAIN) window = link = false;
+  __device__ __forceinline__ void group(int32_t t0, int32_t win, bool window, const GroupIn &g, V *hout,
+                                        V &res) {
+    if (PLAIN) window = false;
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       V bottom = Mp[R - 1];
       // every lane stores (no exec-mask change in the hot loop); only lane
-      // 63's address can be the hand-off row, the others land in the sink
+      // 63's address can be the hand-off row or the link staging ring, the
+      // others land in the sink
       hout[u] = bottom;
-      // link rows cross XCDs, whose L2 caches are not coherent with each
-      // other: store and load them at agent scope (coherent point)
-      if (link) {
-        if (lane == kWave - 1) __hip_atomic_store(lout + u, bottom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
       if (u == kGroup - 1) res = bottom;
       if (window) {
         bool sw = lane == t0 + u - win;
@@ -530,12 +532,60 @@ struct Stream {
     }
   }
 
-  // Publish that the first `count` entries of lane 63's outgoing link row
-  // are in global memory (release: the stores above become visible first).
-  __device__ __forceinline__ void publish(int32_t count) {
-    if (lane == 0)
-      __hip_atomic_store(a.flags + flag63, flag_word(a.epoch, (uint32_t)(rel63 + count)),
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __device__ V *lstage() const { return reinterpret_cast<V *>(base + lay.lstage); }
+
+  // Store the outgoing boundary-row entries of stream positions
+  // [lo, lo + kWave) from the LDS staging ring to their link buffers -- one
+  // coalesced store per lane every kFill steps instead of a store per step
+  // -- and publish how many entries of each link row are in memory.  The
+  // positions must belong to lane 63's current task (id63), the one before
+  // it, or later tasks whose entries are not staged yet (skipped).
+  //
+  // The row's stores are agent-scope stores, which go through to the
+  // device's coherence point; once the wave's stores have completed
+  // (vmcnt 0) an agent-scope store of the count is ordered after them for
+  // any reader that loads the count and then the row at agent scope.  No
+  // L2 write-back is needed: nothing a reader depends on is dirty in this
+  // XCD's L2.
+  __device__ void flush_links(int32_t lo) {
+    int32_t p = lo + lane;
+    bool have_prev = id63 > 0;
+    int32_t pS = 0, pL = 0, phout = kHoutSink, pflag = -1, prel = 0;
+    int64_t plink = 0;
+    if (have_prev) {
+      const Desc *d = desc(id63 - 1);
+      pS = uni(d->S);
+      pL = uni(d->L);
+      phout = uni(d->hout);
+      pflag = uni(d->flag_out);
+      prel = uni(d->rel_out);
+      plink = uni64(d->link_out);
+    }
+    bool in_cur = p >= S63;
+    int32_t x = p - (in_cur ? S63 : pS);
+    bool stage = in_cur ? (hout63 == kHoutLink && x < L63) : (have_prev && phout == kHoutLink && p >= pS);
+    int64_t lk = in_cur ? link63 : plink;
+    if (stage) {
+      V v = lstage()[p & (kLinkRing - 1)];
+      __hip_atomic_store(links() + lk + x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool pub_prev = have_prev && phout == kHoutLink && pS + pL > lo;
+    bool pub_cur = hout63 == kHoutLink && lo + kWave > S63;
+    if (pub_prev || pub_cur) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) {
+        if (pub_prev)
+          __hip_atomic_store(a.flags + pflag, flag_word(a.epoch, (uint32_t)(prel + pL)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        if (pub_cur) {
+          int32_t done = lo + kWave - S63;
+          __hip_atomic_store(a.flags + flag63, flag_word(a.epoch, (uint32_t)(rel63 + (done < L63 ? done : L63))),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
   }
 
   // One group: refill the ring, move the lane-63 cursor, prefetch the next
@@ -547,17 +597,20 @@ struct Stream {
       return false;
     }
     if ((t0 & (kFill - 1)) == 0) {
-      if (hout63 == kHoutLink) {
-        int32_t done = t0 - kWave - S63;  // columns of lane 63's task already stored
-        if (done > 0) publish(done < L63 ? done : L63);
-      }
+      // entries of positions [t0 - 2 kWave, t0 - kWave) were staged during
+      // the last kWave steps
+      flush_links(t0 - 2 * kWave);
       refill(t0);
     }
     if (t0 - kWave == S63 + L63) {
-      if (hout63 == kHoutLink) publish(L63);
+      Desc d = *desc(id63 + 1);
+      if (uni(d.drain)) {
+        // end of the stream: store what is still staged (positions from
+        // the last flush to the end of lane 63's last task)
+        flush_links((t0 & ~(kFill - 1)) - kWave);
+        return false;
+      }
       ++id63;
-      Desc d = *desc(id63);
-      if (uni(d.drain)) return false;
       S63 = uni(d.S);
       L63 = uni(d.L);
       hout63 = uni(d.hout);
@@ -567,17 +620,20 @@ struct Stream {
       out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
     }
     int32_t x63 = t0 - kWave - S63;
-    int32_t hoff = lane == kWave - 1 && hout63 == kHoutHand ? lay.hand + x63 * (int32_t)sizeof(V)
-                                                             : lay.sink + lane * (int32_t)sizeof(V);
+    // lane 63's bottom row: the hand-off row, the link staging ring (by
+    // stream position; a group never wraps it), or the sink
+    int32_t hoff = lay.sink + lane * (int32_t)sizeof(V);
+    if (lane == kWave - 1 && hout63 == kHoutHand) hoff = lay.hand + x63 * (int32_t)sizeof(V);
+    if (lane == kWave - 1 && hout63 == kHoutLink)
+      hoff = lay.lstage + ((t0 - kWave) & (kLinkRing - 1)) * (int32_t)sizeof(V);
     V *hout = reinterpret_cast<V *>(base + hoff);
-    V *lout = links() + link63 + x63;
     lane0_to(t0);
     GroupIn g;
     load_group(t0, hin_at(t0), g);
     V res;
-    bool window = t0 < win0 + kWave, link = hout63 == kHoutLink;
-    if (!window && !link) group<true>(t0, win0, false, false, g, hout, lout, res);
-    else group<false>(t0, win0, window, link, g, hout, lout, res);
+    bool window = t0 < win0 + kWave;
+    if (!window) group<true>(t0, win0, false, g, hout, res);
+    else group<false>(t0, win0, window, g, hout, res);
     if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
       N::store(a.out, out63, res, a.metric);
     return true;

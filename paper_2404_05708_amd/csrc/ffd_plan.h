@@ -34,7 +34,7 @@ constexpr int kFill = 64;            // steps between ring refills (= one entry 
 constexpr int kMinTask = 80;         // shortest task stream: >= kWave + kGroup, so the next band reads a
                                      // hand-off entry a group after lane 63 wrote it
 constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
-constexpr int kDescSlots = 8;        // task descriptors in flight per wave
+constexpr int kDescSlots = 16;       // task descriptors in flight per wave
 constexpr int kLinkRing = 256;       // LDS ring for boundary rows arriving over a link
 constexpr int kFillStateBytes = 256; // per-wave refill state kept in LDS
 
@@ -82,6 +82,7 @@ struct LdsLayout {
   int sink;   // kWave + kGroup values: bottom-row stores that hand nothing on
   int hand;   // hcap values: bottom row of the band above (same wave)
   int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
+  int lstage; // kLinkRing values: outgoing boundary row, by stream position, until it is stored
   int pst;    // two slots of 64 * R * D row coordinates (next task's rows)
   int desc;   // kDescSlots task descriptors of 64 bytes
   int fill;   // refill state of the wave (kFillStateBytes)
@@ -99,6 +100,7 @@ FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
   L.sink = o;  o += (kWave + kGroup) * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
   o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;
+  o = align16(o); L.lstage = o; o += kLinkRing * vsize;
   o = align16(o); L.pst = o;  o += 2 * kWave * R * D * vsize;
   o = align16(o); L.desc = o; o += kDescSlots * 64;
   o = align16(o); L.fill = o; o += kFillStateBytes;
