@@ -122,7 +122,10 @@ def test_workspace_size_and_too_small_workspace(planner):
     assert need >= 500 * 32 + 2 * 501 * 8
     L = ffd.lib
     r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, need - 1, None)
-    assert r == ffd.FFD_E_DEVICE  # planner stops before the workspace check is reached on a device
+    assert r == ffd.FFD_E_NOMEM
+    # with enough workspace the checks pass and the planning-only context refuses to launch
+    r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, need, None)
+    assert r == ffd.FFD_E_DEVICE
     with pytest.raises(ffd.FFDError):
         ffd.ffd_workspace_size(planner, 7, p_off, q_off, 2)
     Qs, qo, DB, do = workloads.cross_int(seed=1, nq=8, ndb=40, length=30)
