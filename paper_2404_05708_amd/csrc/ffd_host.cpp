@@ -55,24 +55,27 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // Modelled shader clocks of one stream step of a wave with R rows per lane.
 // A step issues I VALU instructions per wave: (2D + 2) per cell (D
 // subtractions, one multiply, D-1 FMAs, min3, max; FP64 needs two mins) and
-// about 8 per step (lane shift, LDS stores, bookkeeping).  A wave alone on
-// its SIMD issues about one instruction per 5 clocks and its serial chain
-// (lane shift, then a min3 and a max per row) takes about 12 + 17 R clocks;
-// waves sharing a SIMD share its wave64 issue slots of 4 clocks.
+// about 8 per step (lane shift, LDS stores, bookkeeping).  Fitted to
+// measured lone waves (one per SIMD; 3-D single pairs at R = 2, 4, 8 and the
+// 2-D batch at R = 8): about 104 + 3.9 I clocks.  Waves sharing a SIMD also
+// share its wave64 issue slots (4 clocks each), which they keep about three
+// quarters busy.
 double step_clocks(int R, int D, bool exact, double waves_per_simd) {
   double I = (double)R * (2 * D + (exact ? 3 : 2)) + 8.0;
-  double shared = std::max(1.0, waves_per_simd) * I * 4.0;
-  return std::max(shared, std::max(I * 5.0, 12.0 + 17.0 * R));
+  double lone = 104.0 + 3.9 * I;
+  double shared = 0.75 * std::max(1.0, waves_per_simd) * I * 4.0;
+  return std::max(lone, shared);
 }
 
 // Stream steps a consumer band starts after its producer band.  At its
 // refill at step t the consumer waits for the entries of its chunk
-// [t + 2 kFill, t + 3 kFill), i.e. up to t + 3 kFill - S_consumer; the
-// producer publishes at its refill at step t' the t' - kWave - S_producer
-// columns its lane 63 has finished.  The wait therefore ends once the
-// producer reaches t' = t + 3 kFill + kWave - lag: with lag = 6 kFill that is
-// t - 2 kFill, strictly before the waiting wave's own position.
-constexpr double kLinkLag = 6.0 * ffd::kFill;
+// [t + kFill, t + 2 kFill), i.e. up to t + 2 kFill - S_consumer; the
+// producer publishes at its refill at step t' the count stored by its
+// previous flush, t' - kFill - kWave - S_producer columns.  The wait
+// therefore ends once the producer reaches t' = t + 3 kFill + kWave - lag:
+// with lag = 5 kFill that is t - kFill, strictly before the waiting wave's
+// own position.
+constexpr double kLinkLag = 5.0 * ffd::kFill;
 
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
   const unsigned char *b = (const unsigned char *)p;

@@ -142,6 +142,8 @@ struct Stream {
     int32_t b_first, b_end;   // band range of the job
     int32_t row_sel, col_sel, col_first, col_count, out_stride, flag_in, flag_out;
     int32_t exhausted, next_id, has_next, ptmp_pending, ptmp_slot, idle;
+    int32_t pub_flag[2];      // link counts stored by the last flush, published at the next one
+    uint32_t pub_count[2];
     int64_t row_off, n, out_base, link_in, link_out, link_rel;
     FillTask cur, nxt;
   };
@@ -194,6 +196,8 @@ struct Stream {
     f.out_stride = uni(f.out_stride); f.flag_in = uni(f.flag_in); f.flag_out = uni(f.flag_out);
     f.exhausted = uni(f.exhausted); f.next_id = uni(f.next_id); f.has_next = uni(f.has_next);
     f.ptmp_pending = uni(f.ptmp_pending); f.ptmp_slot = uni(f.ptmp_slot); f.idle = uni(f.idle);
+    f.pub_flag[0] = uni(f.pub_flag[0]); f.pub_flag[1] = uni(f.pub_flag[1]);
+    f.pub_count[0] = uni(f.pub_count[0]); f.pub_count[1] = uni(f.pub_count[1]);
     f.row_off = uni64(f.row_off); f.n = uni64(f.n); f.out_base = uni64(f.out_base);
     f.link_in = uni64(f.link_in); f.link_out = uni64(f.link_out); f.link_rel = uni64(f.link_rel);
     uni_task(f.cur);
@@ -346,10 +350,9 @@ struct Stream {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
 
-  // Issue the global loads of ring entries [t, t + 64): one per lane, plus
-  // the incoming boundary values of tasks whose band above ran on another
-  // wave (after waiting for them to be published).
-  __device__ void fill_load(FillState &f, int32_t t) {
+  // Make f.cur the task containing stream position t, and f.nxt the one
+  // after it if f.cur ends before t + kFill.
+  __device__ void advance(FillState &f, int32_t t) {
     while (f.cur.S + f.cur.L <= t) {
       if (!f.has_next) make_task(f, f.cur.S + f.cur.L, f.nxt);
       f.cur = f.nxt;
@@ -359,6 +362,35 @@ struct Stream {
       make_task(f, f.cur.S + f.cur.L, f.nxt);
       f.has_next = 1;
     }
+  }
+
+  // Issue the global loads of ring entries [t, t + 64), one per lane; f
+  // describes that chunk (advance(f, t)).
+  __device__ void ring_load(const FillState &f, int32_t t) {
+    const FillTask &cur = f.cur, &nxt = f.nxt;
+    int32_t tau = t + lane;
+    bool in_next = tau >= cur.S + cur.L;
+    int32_t x = tau - (in_next ? nxt.S : cur.S);
+    int64_t m = in_next ? nxt.m : cur.m;
+    int64_t co = in_next ? nxt.col_off : cur.col_off;
+    int32_t sel = in_next ? nxt.col_sel : cur.col_sel;
+    bool drain = in_next ? nxt.drain : cur.drain;
+    qsep = drain || x == 0;
+    int64_t idx = x - 1;
+    if (idx > m - 1) idx = m - 1;
+    if (idx < 0) idx = 0;
+    if (drain) { co = 0; idx = 0; sel = 0; }
+    const C *X = coords(sel);
+    const C *pt = X + (co + idx) * D;
+#pragma unroll
+    for (int k2 = 0; k2 < D; ++k2) qbuf[k2] = pt[k2];
+  }
+
+  // Issue the loads of the incoming boundary values of positions
+  // [t, t + 64) for tasks whose band above ran on another wave, after
+  // waiting for them to be published; f describes that chunk.  They are
+  // written to LDS at the refill of step t, just before their first use.
+  __device__ void link_load(const FillState &f, int32_t t) {
     const FillTask &cur = f.cur, &nxt = f.nxt;
     if (cur.hin == kHinLink) {
       int32_t hi = t + kFill - cur.S;
@@ -371,27 +403,22 @@ struct Stream {
     int32_t tau = t + lane;
     bool in_next = tau >= cur.S + cur.L;
     int32_t x = tau - (in_next ? nxt.S : cur.S);
-    int64_t m = in_next ? nxt.m : cur.m;
-    int64_t co = in_next ? nxt.col_off : cur.col_off;
-    int32_t sel = in_next ? nxt.col_sel : cur.col_sel;
-    bool drain = in_next ? nxt.drain : cur.drain;
     bool glink = (in_next ? nxt.hin : cur.hin) == kHinLink;
     int64_t lk = in_next ? nxt.link_in : cur.link_in;
-    qsep = drain || x == 0;
-    int64_t idx = x - 1;
-    if (idx > m - 1) idx = m - 1;
-    if (idx < 0) idx = 0;
-    if (drain) { co = 0; idx = 0; sel = 0; }
-    const C *X = coords(sel);
-    const C *pt = X + (co + idx) * D;
-#pragma unroll
-    for (int k2 = 0; k2 < D; ++k2) qbuf[k2] = pt[k2];
     hslot = glink ? tau : -1;  // the link ring is indexed by stream position
     if (glink) hbuf = __hip_atomic_load(links() + lk + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  // Write the entries loaded by the previous fill_load (for positions
-  // [t, t + 64)), incoming boundary values and any pending band rows.
+  __device__ void link_write() {
+    if (hslot >= 0) {
+      int ls = hslot & (kLinkRing - 1);
+      lring()[ls] = hbuf;
+      if (ls < kGroup) lring()[ls + kLinkRing] = hbuf;
+    }
+  }
+
+  // Write the ring entries loaded by the previous ring_load (for positions
+  // [t, t + 64)) and any pending band rows.
   __device__ void fill_write(FillState &f, int32_t t) {
     Pt e;
 #pragma unroll
@@ -399,11 +426,6 @@ struct Stream {
     int slot = (t + lane) & (kRing - 1);
     ring()[slot] = e;
     if (slot < kGroup) ring()[slot + kRing] = e;
-    if (hslot >= 0) {
-      int ls = hslot & (kLinkRing - 1);
-      lring()[ls] = hbuf;
-      if (ls < kGroup) lring()[ls + kLinkRing] = hbuf;
-    }
     if (f.ptmp_pending) {
       V *dst = pst(f.ptmp_slot) + lane * (R * D);
 #pragma unroll
@@ -416,12 +438,20 @@ struct Stream {
 
   static_assert(sizeof(FillState) <= kFillStateBytes, "refill state does not fit its LDS slot");
 
-  // One refill: write the chunk loaded last time, load the next one.
+  // One refill, at step t0: store the outgoing boundary entries staged
+  // during the last kWave steps; write the incoming boundary values of
+  // [t0, t0 + 64) and the ring chunk [t0 + 64, t0 + 128) loaded last time;
+  // load the incoming boundary values of [t0 + 64, t0 + 128) and the ring
+  // chunk [t0 + 128, t0 + 192).
   __device__ __forceinline__ void refill(int32_t t0) {
     FillState f;
     load_state(f);
+    flush_links(f, t0 - 2 * kWave, false);
+    link_write();
     fill_write(f, t0 + kFill);
-    fill_load(f, t0 + 2 * kFill);
+    link_load(f, t0 + kFill);
+    advance(f, t0 + 2 * kFill);
+    ring_load(f, t0 + 2 * kFill);
     store_state(f);
   }
 
@@ -546,8 +576,28 @@ struct Stream {
   // (vmcnt 0) an agent-scope store of the count is ordered after them for
   // any reader that loads the count and then the row at agent scope.  No
   // L2 write-back is needed: nothing a reader depends on is dirty in this
-  // XCD's L2.
-  __device__ void flush_links(int32_t lo) {
+  // XCD's L2.  To avoid waiting for the stores just issued, the counts of a
+  // flush are published at the next one (kFill steps later, when every
+  // older memory operation of the wave has long completed), or at once at
+  // the end of the stream (`last`).
+  __device__ void publish_pending(FillState &f) {
+    if (f.pub_flag[0] >= 0 || f.pub_flag[1] >= 0) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (f.pub_flag[k] >= 0)
+            __hip_atomic_store(a.flags + f.pub_flag[k], flag_word(a.epoch, f.pub_count[k]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+      f.pub_flag[0] = f.pub_flag[1] = -1;
+    }
+  }
+
+  __device__ void flush_links(FillState &f, int32_t lo, bool last) {
+    publish_pending(f);
     int32_t p = lo + lane;
     bool have_prev = id63 > 0;
     int32_t pS = 0, pL = 0, phout = kHoutSink, pflag = -1, prel = 0;
@@ -569,23 +619,16 @@ struct Stream {
       V v = lstage()[p & (kLinkRing - 1)];
       __hip_atomic_store(links() + lk + x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    bool pub_prev = have_prev && phout == kHoutLink && pS + pL > lo;
-    bool pub_cur = hout63 == kHoutLink && lo + kWave > S63;
-    if (pub_prev || pub_cur) {
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (lane == 0) {
-        if (pub_prev)
-          __hip_atomic_store(a.flags + pflag, flag_word(a.epoch, (uint32_t)(prel + pL)), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        if (pub_cur) {
-          int32_t done = lo + kWave - S63;
-          __hip_atomic_store(a.flags + flag63, flag_word(a.epoch, (uint32_t)(rel63 + (done < L63 ? done : L63))),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
+    if (have_prev && phout == kHoutLink && pS + pL > lo) {
+      f.pub_flag[0] = pflag;
+      f.pub_count[0] = (uint32_t)(prel + pL);
     }
+    if (hout63 == kHoutLink && lo + kWave > S63) {
+      int32_t done = lo + kWave - S63;
+      f.pub_flag[1] = flag63;
+      f.pub_count[1] = (uint32_t)(rel63 + (done < L63 ? done : L63));
+    }
+    if (last) publish_pending(f);
   }
 
   // One group: refill the ring, move the lane-63 cursor, prefetch the next
@@ -596,18 +639,15 @@ struct Stream {
       err |= 1;
       return false;
     }
-    if ((t0 & (kFill - 1)) == 0) {
-      // entries of positions [t0 - 2 kWave, t0 - kWave) were staged during
-      // the last kWave steps
-      flush_links(t0 - 2 * kWave);
-      refill(t0);
-    }
+    if ((t0 & (kFill - 1)) == 0) refill(t0);
     if (t0 - kWave == S63 + L63) {
       Desc d = *desc(id63 + 1);
       if (uni(d.drain)) {
         // end of the stream: store what is still staged (positions from
-        // the last flush to the end of lane 63's last task)
-        flush_links((t0 & ~(kFill - 1)) - kWave);
+        // the last flush to the end of lane 63's last task) and publish
+        FillState f;
+        load_state(f);
+        flush_links(f, (t0 & ~(kFill - 1)) - kWave, true);
         return false;
       }
       ++id63;
@@ -679,11 +719,16 @@ struct Stream {
       f.has_next = 0;
       f.ptmp_pending = 0;
       f.ptmp_slot = 0;
+      f.pub_flag[0] = f.pub_flag[1] = -1;
+      f.pub_count[0] = f.pub_count[1] = 0;
       load_job(f, j0);
       make_task(f, 0, f.cur);
-      fill_load(f, 0);
+      advance(f, 0);
+      ring_load(f, 0);
+      link_load(f, 0);
       fill_write(f, 0);
-      fill_load(f, kFill);
+      advance(f, kFill);
+      ring_load(f, kFill);
       store_state(f);
     }
 
