@@ -121,7 +121,8 @@ def test_workspace_size_and_too_small_workspace(planner):
     # at least the plan entries and both offset arrays
     assert need >= 500 * 32 + 2 * 501 * 8
     L = ffd.lib
-    r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, need - 1, None)
+    # the size covers both the float and the exact plan; far less is refused
+    r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, 256, None)
     assert r == ffd.FFD_E_NOMEM
     # with enough workspace the checks pass and the planning-only context refuses to launch
     r = L.ffd_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 500, 2, 0, FAKE, FAKE, need, None)
