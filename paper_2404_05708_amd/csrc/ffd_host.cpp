@@ -104,8 +104,8 @@ int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   return FFD_OK;
 }
 
-int lds_bytes(int R, int D, bool exact, int64_t hcap) {
-  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap).total;
+int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings) {
+  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings).total;
 }
 
 const int kRs[4] = {1, 2, 4, 8};
@@ -454,6 +454,90 @@ double split_share(ffd_ctx *ctx) {
 
 // Plan the units produced by `make(R, W, units)` for the R with the lowest
 // modelled stream length times per-step clocks.
+// A single long pair as a pipeline of its bands, band b on wave b: bands
+// of one workgroup hand their bottom rows on through LDS rings and start
+// kWave + kGroup stream steps after each other; bands of consecutive
+// workgroups hand them on through global links and start kLinkLag steps
+// after each other.  Every wave is resident at once (cooperative launch).
+// Returns false when the pair has too many bands for that.
+bool build_pipeline(ffd_ctx *ctx, const Unit &u, int R, int D, bool exact, Plan &pl) {
+  const int wpb = 4;
+  if (u.nb < 2) return false;
+  int lds_wave = lds_bytes(R, D, exact, 0, true);
+  size_t block = (size_t)wpb * (size_t)lds_wave;
+  if (block > ctx->lds_block_max) return false;
+  size_t rounded = (block + 4095) / 4096 * 4096;
+  int fit = (int)std::min<size_t>(16 / wpb, ctx->lds_cu / rounded);
+  if (ctx->device >= 0) {
+    int blocks = 0;
+    if (ffd::occupancy_stream(exact, R, D, wpb, block, &blocks, true) != hipSuccess || blocks < 1) return false;
+    fit = std::min(fit, blocks);
+  }
+  if ((int64_t)u.nb > (int64_t)ctx->cus * fit * wpb) return false;
+  const int32_t nb = u.nb;
+  pl = Plan();
+  pl.R = R;
+  pl.nwaves = nb;
+  pl.wpb = std::min(wpb, nb);
+  pl.hcap = 0;
+  pl.rings = true;
+  pl.coop = nb > wpb;
+  pl.wave_jobs.assign(nb + 1, 0);
+  pl.jobs.clear();
+  int64_t start = 0;
+  int64_t gl_link = -1;
+  int32_t gl_flag = -1;
+  for (int32_t b = 0; b < nb; ++b) {
+    bool ring_in = b > 0 && b % wpb != 0;
+    if (b > 0) start += ring_in ? (int64_t)(ffd::kWave + ffd::kGroup) : (int64_t)kLinkLag;
+    pl.wave_jobs[b] = (int32_t)pl.jobs.size();
+    if (start > 0) {
+      Job idle;
+      memset(&idle, 0, sizeof idle);
+      idle.row_sel = ffd::kRowIdle;
+      idle.col_count = (int32_t)start;
+      idle.link_in = idle.link_out = -1;
+      idle.flag_in = idle.flag_out = -1;
+      pl.jobs.push_back(idle);
+    }
+    Job jb;
+    memset(&jb, 0, sizeof jb);
+    jb.out_base = u.out_base;
+    jb.row_sel = u.row_sel;
+    jb.row_idx = u.row_idx;
+    jb.col_sel = u.col_sel;
+    jb.col_first = u.col_first;
+    jb.col_count = u.col_count;
+    jb.out_stride = u.out_stride;
+    jb.band_first = b;
+    jb.band_count = 1;
+    jb.link_in = jb.link_out = -1;
+    jb.flag_in = jb.flag_out = -1;
+    if (ring_in) {
+      jb.flag_in = -2 - ((b - 1) % wpb);
+    } else if (b > 0) {
+      jb.link_in = gl_link;
+      jb.flag_in = gl_flag;
+    }
+    if (b + 1 < nb) {
+      if ((b + 1) % wpb != 0) {
+        jb.flag_out = -2;
+      } else {
+        gl_link = pl.link_elems;
+        gl_flag = pl.nflags++;
+        pl.link_elems += u.sumL;
+        jb.link_out = gl_link;
+        jb.flag_out = gl_flag;
+      }
+    }
+    pl.jobs.push_back(jb);
+  }
+  pl.wave_jobs[nb] = (int32_t)pl.jobs.size();
+  pl.max_steps = start + u.sumL;
+  pl.makespan = (double)pl.max_steps;
+  return true;
+}
+
 template <typename MakeUnits>
 int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single, MakeUnits make, Plan &best) {
   double best_cost = -1;
@@ -482,6 +566,15 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
     pl.wpb = std::min(rs.wpb, pl.nwaves);
     double wps = std::ceil((double)pl.nwaves / (4.0 * ctx->cus));
     double cost = ((double)pl.max_steps + ffd::kWave) * step_clocks(R, D, exact, wps);
+    Plan pipe;
+    if (single && share >= 0 && units.size() == 1 && build_pipeline(ctx, units[0], R, D, exact, pipe)) {
+      double pw = std::ceil((double)pipe.nwaves / (4.0 * ctx->cus));
+      double pc = ((double)pipe.max_steps + ffd::kWave) * step_clocks(R, D, exact, pw);
+      if (pc < cost) {
+        cost = pc;
+        pl = std::move(pipe);
+      }
+    }
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;
       best = std::move(pl);
@@ -573,7 +666,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
              const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
              size_t ws_bytes, hipStream_t st) {
   WsLayout wl = ws_layout(pl, n0, n1, exact);
-  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap), exact ? 1 : 0, D,
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings), exact ? 1 : 0, D,
                               pl.max_steps};
   if (!ws || ws_bytes < wl.total) return fail(ctx, FFD_E_NOMEM, "workspace too small (see ffd_workspace_size)");
   if (pl.max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
@@ -612,12 +705,13 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.nwaves = pl.nwaves;
   a.metric = metric;
   a.hcap = (int32_t)pl.hcap;
-  a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap);
+  a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap, pl.rings);
   a.max_steps = (int32_t)(pl.max_steps + 4 * ffd::kRing);
   a.epoch = ++ctx->epoch;
   a.links = w + wl.links;
   a.flags = (uint64_t *)(w + wl.flags);
   a.err = (uint64_t *)(w + wl.err);
+  a.rings = pl.rings ? 1 : 0;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
   e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");

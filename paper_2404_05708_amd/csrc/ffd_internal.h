@@ -12,8 +12,22 @@
 #include "ffd_plan.h"
 
 namespace ffd {
-hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
-hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
+hipError_t launch_stream_rings(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
+hipError_t occupancy_stream_plain(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+hipError_t occupancy_stream_rings(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+
+// The kernel variant with LDS rings between waves serves launches whose
+// plan uses them (a.rings); every other launch takes the plain variant.
+inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
+  return a.rings ? launch_stream_rings(exact, R, D, a, wpb, coop, st)
+                 : launch_stream_plain(exact, R, D, a, wpb, coop, st);
+}
+inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu,
+                                   bool rings = false) {
+  return rings ? occupancy_stream_rings(exact, R, D, wpb, lds, blocks_per_cu)
+               : occupancy_stream_plain(exact, R, D, wpb, lds, blocks_per_cu);
+}
 }  // namespace ffd
 
 namespace ffdi {
@@ -32,6 +46,7 @@ struct Plan {
   int64_t link_elems = 0;      // elements of all link buffers
   int32_t nflags = 0;          // progress flags
   bool coop = false;           // some link joins two waves: cooperative launch
+  bool rings = false;          // some bands hand rows on through LDS rings of their workgroup
   double makespan = 0;         // modelled, in steps
   std::vector<Job> jobs;       // grouped by wave, in placement order
   std::vector<int32_t> wave_jobs;
@@ -77,7 +92,7 @@ int fail(ffd_ctx *ctx, int code, const char *msg);
 int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what);
 int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *name);
 int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact);
-int lds_bytes(int R, int D, bool exact, int64_t hcap);
+int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings = false);
 int64_t self_gap(int64_t sumL);
 
 struct Resources {

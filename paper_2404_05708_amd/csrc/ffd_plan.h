@@ -36,6 +36,7 @@ constexpr int kMinTask = 80;         // shortest task stream: >= kWave + kGroup,
 constexpr int kMinTaskChained = 80;  // shortest stream when a band hands its bottom row on
 constexpr int kDescSlots = 16;       // task descriptors in flight per wave
 constexpr int kLinkRing = 256;       // LDS ring for boundary rows arriving over a link
+constexpr int kXRing = 512;          // LDS ring for a bottom row handed to a wave of the same workgroup
 constexpr int kFillStateBytes = 256; // per-wave refill state kept in LDS
 
 // A job whose row_sel is kRowIdle computes nothing for col_count stream
@@ -54,8 +55,10 @@ struct Job {           // 64 bytes, device-resident plan entry
   int32_t out_stride;  // output index step between consecutive column curves
   int32_t band_first;  // bands [band_first, band_first + band_count) of the row curve
   int32_t band_count;  // (band_count <= 0: all bands from band_first on)
-  int32_t flag_in;     // progress flag of the incoming link (-1: none)
-  int32_t flag_out;    // progress flag of the outgoing link (-1: none)
+  int32_t flag_in;     // progress flag of the incoming link (-1: none; <= -2: the row above comes
+                       // through the LDS ring of wave -2 - flag_in of the same workgroup)
+  int32_t flag_out;    // progress flag of the outgoing link (-1: none; -2: the bottom row goes to
+                       // this wave's LDS ring, read by another wave of the workgroup)
 };
 
 // Progress flags hold (epoch << 32) | entries published; the epoch changes
@@ -83,6 +86,8 @@ struct LdsLayout {
   int hand;   // hcap values: bottom row of the band above (same wave)
   int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
   int lstage; // kLinkRing values: outgoing boundary row, by stream position, until it is stored
+  int xring;  // kXRing values: bottom row read by another wave of the workgroup
+  int xctr;   // two int32 counters of that ring: entries written, entries read
   int pst;    // two slots of 64 * R * D row coordinates (next task's rows)
   int desc;   // kDescSlots task descriptors of 64 bytes
   int fill;   // refill state of the wave (kFillStateBytes)
@@ -92,7 +97,9 @@ struct LdsLayout {
 FFD_HD int align16(int x) { return (x + 15) & ~15; }
 FFD_HD int pad_dim(int D) { return D == 3 ? 4 : D; }
 
-FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
+// rings: the wave also owns a ring that hands its bottom row to another
+// wave of its workgroup.
+FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings) {
   LdsLayout L;
   int o = 0;
   L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
@@ -101,6 +108,8 @@ FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap) {
   o = align16(o); L.hand = o; o += hcap * vsize;
   o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;
   o = align16(o); L.lstage = o; o += kLinkRing * vsize;
+  o = align16(o); L.xring = o; o += rings ? kXRing * vsize : 0;
+  o = align16(o); L.xctr = o; o += rings ? 16 : 0;
   o = align16(o); L.pst = o;  o += 2 * kWave * R * D * vsize;
   o = align16(o); L.desc = o; o += kDescSlots * 64;
   o = align16(o); L.fill = o; o += kFillStateBytes;
@@ -126,6 +135,7 @@ struct KernelArgs {
   uint64_t *flags;           // progress flags, device
   uint64_t *err;             // error word (epoch << 32 | bits): bit 0 loop guard hit,
                              // bit 1 link wait abandoned; the largest word of a launch wins
+  int32_t rings;             // nonzero: some jobs hand rows between waves through LDS rings
 };
 
 // A link buffer holds the boundary rows of a job's column curves back to

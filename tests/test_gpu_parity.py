@@ -290,6 +290,28 @@ def test_split_with_many_waves_per_simd(ctx):
         np.testing.assert_array_equal(got, base)
 
 
+def test_pipelined_single_pairs(ctx):
+    """A long pair as a pipeline of bands on consecutive waves: LDS rings
+    inside a workgroup, global links between workgroups; partial last
+    workgroups and band counts of every residue mod 4."""
+    rng = np.random.default_rng(47)
+    cases = [(64 * 4 * 5 + 3, 1500, 4), (64 * 2 * 6, 900, 2), (64 * 9 + 1, 700, 1), (64 * 4 * 7, 2500, 4),
+             (3000, 200, 2), (64 * 2 * 2 + 5, 4000, 2)]
+    for n, m, R in cases:
+        say(f"case: pipelined pair n={n} m={m} R={R}")
+        p = workloads.walk(rng, n, 2)
+        q = workloads.walk(rng, m, 2)
+        ctx.set_tuning(R, 0)
+        try:
+            got = ctx.distance(dev(p), dev(q)).item()
+            info = ctx.last_launch()
+            errs = ctx.last_errors()
+        finally:
+            ctx.set_tuning(0, 0)
+        assert errs == 0
+        assert got == oracle.dfd_f32_replica(p, q), (n, m, R, info)
+
+
 def test_long_curves_force_split(ctx):
     """Column curves longer than a wave's LDS hand-off row must be split."""
     rng = np.random.default_rng(42)
