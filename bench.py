@@ -127,6 +127,9 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     def step():
         ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
 
+    tuning = None
+    if args.autotune:
+        tuning = ctx.autotune_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
     for _ in range(args.warmup):
         step()
     if args.copy_probe:
@@ -184,6 +187,7 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
                                "random walks, q = p resampled + N(0, 0.1^2), Euclidean (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "autotune": tuning,
         "roofline": roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md"),
         "plain": plain, "cpu_baseline": cpu,
     }
@@ -415,6 +419,8 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch shapes once before the warm-up (batched) and use the fastest")
     ap.add_argument("--split", type=float, default=0.0,
                     help="band splitting: 0 auto, < 0 only when needed, > 0 above this share of a wave's load")
     args = ap.parse_args()
@@ -444,7 +450,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "serving", "roofline", "plain", "cpu_baseline"):
+    for k in ("config", "parity", "autotune", "serving", "roofline", "plain", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     print(json.dumps(line), flush=True)

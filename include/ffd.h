@@ -192,6 +192,31 @@ int ffd_last_errors(ffd_ctx *ctx, int32_t *flags);
  * Errors: FFD_E_INVALID (NaN or huge share). */
 int ffd_set_split(ffd_ctx *ctx, float share);
 
+/* ----------------------------------------------------------- autotune --- */
+typedef struct ffd_tuning {
+  int32_t rows_per_lane;   /* chosen launch shape */
+  int32_t waves_per_simd;
+  float split;             /* band-split share (see ffd_set_split) */
+  float ms;                /* kernel time of the chosen shape */
+  float ms_planner;        /* kernel time of the planner's own choice */
+  int32_t tried;           /* shapes timed */
+} ffd_tuning;
+
+/* Time the launch shapes the planner can produce for this request (rows per
+ * lane 2, 4, 8; one or two waves per SIMD; band-split shares) on the given
+ * data, on `stream`, and keep the fastest: later ffd_batch (ffd_cross)
+ * calls with the same offsets, dim and coordinate type, made while the
+ * context's tuning and split settings are automatic, use it.  Arguments as
+ * for ffd_batch (ffd_cross); `out` receives the results; shapes whose
+ * workspace exceeds ws_bytes are skipped.  Synchronises the stream.
+ * Errors: as ffd_batch (ffd_cross). */
+int ffd_autotune_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                       int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
+                       void *stream, ffd_tuning *best);
+int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, const float *DB,
+                       const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out,
+                       void *workspace, size_t ws_bytes, void *stream, ffd_tuning *best);
+
 /* ------------------------------------------------------------ serving ---
  * Queries against a device-resident database of curves (the batched form
  * of Sec. 4 against one reference curve, turned around: one query against

@@ -721,11 +721,13 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   return FFD_OK;
 }
 
+// Key of a request: offsets, op, dim, type and, unless `base`, the tuning
+// and split settings (a plan depends on all of them).
 uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b,
-                int64_t nb) {
+                int64_t nb, bool base = false) {
   uint64_t h = 1469598103934665603ull;
-  int hdr[6] = {op, D, exact ? 1 : 0, ctx->tune_R, ctx->tune_W, 0};
-  float sp = ctx->split;
+  int hdr[6] = {op, D, exact ? 1 : 0, base ? 0 : ctx->tune_R, base ? 0 : ctx->tune_W, 0};
+  float sp = base ? 0.f : ctx->split;
   h = fnv(h, hdr, sizeof hdr);
   h = fnv(h, &sp, sizeof sp);
   h = fnv(h, &na, sizeof na);
@@ -736,6 +738,32 @@ uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64
 }
 
 constexpr int kOpPair = 100;  // internal plan kind of ffd_distance
+
+// With automatic settings, a launch shape the autotuner chose for this
+// request replaces the model's choice for the duration of the call.
+struct TunedScope {
+  ffd_ctx *ctx;
+  int R, W;
+  float split;
+  bool active = false;
+  TunedScope(ffd_ctx *c, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb)
+      : ctx(c), R(c->tune_R), W(c->tune_W), split(c->split) {
+    if (c->tune_R || c->tune_W || c->split != 0.f || c->tuned.empty()) return;
+    auto it = c->tuned.find(key_of(c, op, D, exact, a, na, b, nb, true));
+    if (it == c->tuned.end()) return;
+    c->tune_R = it->second.rows_per_lane;
+    c->tune_W = it->second.waves_per_simd;
+    c->split = it->second.split;
+    active = true;
+  }
+  ~TunedScope() {
+    if (active) {
+      ctx->tune_R = R;
+      ctx->tune_W = W;
+      ctx->split = split;
+    }
+  }
+};
 
 int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na, const int64_t *b_off,
                 int64_t nb, int D, bool exact, const Plan **out, uint64_t &key) {
@@ -827,6 +855,7 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   if (!P || !Q || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
   if ((rc = check_offsets(ctx, p_off, npairs, "p_off is NULL"))) return rc;
   if ((rc = check_offsets(ctx, q_off, npairs, "q_off is NULL"))) return rc;
+  TunedScope tuned(ctx, FFD_OP_BATCH, dim, exact, p_off, npairs, q_off, npairs);
   const Plan *pl;
   uint64_t key;
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
@@ -846,11 +875,86 @@ int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq,
   if (!Qs || !DB || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
   if ((rc = check_offsets(ctx, q_off, nq, "q_off is NULL"))) return rc;
   if ((rc = check_offsets(ctx, db_off, ndb, "db_off is NULL"))) return rc;
+  TunedScope tuned(ctx, FFD_OP_CROSS, dim, exact, q_off, nq, db_off, ndb);
   const Plan *pl;
   uint64_t key;
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key);
   if (rc) return rc;
   return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st);
+}
+
+// Time one launch of `call` (already planned and uploaded by a first call)
+// between two events on the stream; < 0 when the shape cannot run.
+template <typename Call>
+float time_shape(ffd_ctx *ctx, hipStream_t st, Call call) {
+  if (call() != FFD_OK) return -1.f;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return -1.f;
+  }
+  float best = -1.f;
+  for (int rep = 0; rep < 2; ++rep) {
+    hipEventRecord(e0, st);
+    int rc = call();
+    hipEventRecord(e1, st);
+    float ms = -1.f;
+    if (rc == FFD_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      best = best < 0 || ms < best ? ms : best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  int32_t flags = 0;
+  if (ffd_last_errors(ctx, &flags) != FFD_OK || flags != 0) return -1.f;
+  return best;
+}
+
+// Try the launch shapes and keep the fastest for this request.
+template <typename Call>
+int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb,
+             hipStream_t st, Call call, ffd_tuning *best_out) {
+  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
+  int R0 = ctx->tune_R, W0 = ctx->tune_W;
+  float S0 = ctx->split;
+  uint64_t base = key_of(ctx, op, D, exact, a, na, b, nb, true);
+  ctx->tuned.erase(base);
+  ffd_tuning best{0, 0, 0.f, -1.f, -1.f, 0};
+  ctx->tune_R = ctx->tune_W = 0;
+  ctx->split = 0.f;
+  best.ms_planner = time_shape(ctx, st, call);
+  const int Rs[3] = {2, 4, 8};
+  const int Ws[2] = {1, 2};
+  const float Ss[5] = {-1.f, 1.0f, 1.25f, 1.5f, 2.0f};
+  for (int R : Rs)
+    for (int W : Ws)
+      for (float sp : Ss) {
+        ctx->tune_R = R;
+        ctx->tune_W = W;
+        ctx->split = sp;
+        float ms = time_shape(ctx, st, call);
+        best.tried++;
+        if (ms > 0 && (best.ms < 0 || ms < best.ms)) {
+          best.ms = ms;
+          best.rows_per_lane = R;
+          best.waves_per_simd = W;
+          best.split = sp;
+        }
+      }
+  ctx->tune_R = R0;
+  ctx->tune_W = W0;
+  ctx->split = S0;
+  if (best.ms < 0) return fail(ctx, FFD_E_UNSUPPORTED, "no launch shape could run");
+  if (best.ms_planner > 0 && best.ms_planner <= best.ms) {
+    // the planner's own choice is as fast: keep using the model
+    best.rows_per_lane = best.waves_per_simd = 0;
+    best.split = 0.f;
+    best.ms = best.ms_planner;
+  } else {
+    ctx->tuned[base] = best;
+  }
+  if (best_out) *best_out = best;
+  return FFD_OK;
 }
 
 }  // namespace ffdi
@@ -1024,6 +1128,38 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   if (worst == 0) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;
   return FFD_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int ffd_autotune_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                       int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
+                       void *stream, ffd_tuning *best) {
+  if (!ctx) return FFD_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, st, false);
+  if (rc) return rc;  // argument errors, before any tuning
+  if (npairs == 0) return FFD_OK;
+  return autotune(ctx, FFD_OP_BATCH, dim, false, p_off, npairs, q_off, npairs, st,
+                  [&] { return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes,
+                                            st, false); },
+                  best);
+}
+
+int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, const float *DB,
+                       const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out,
+                       void *workspace, size_t ws_bytes, void *stream, ffd_tuning *best) {
+  if (!ctx) return FFD_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes, st, false);
+  if (rc) return rc;
+  if (nq == 0 || ndb == 0) return FFD_OK;
+  return autotune(ctx, FFD_OP_CROSS, dim, false, q_off, nq, db_off, ndb, st,
+                  [&] { return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace,
+                                            ws_bytes, st, false); },
+                  best);
 }
 
 }  // extern "C"

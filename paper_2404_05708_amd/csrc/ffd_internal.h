@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "ffd.h"
@@ -77,6 +78,8 @@ struct ffd_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t upload_done = nullptr;
   ffdi::PlanCache batch_plans, pair_plans;
+  // launch shapes chosen by the autotuner, by request (offsets, op, dim, type)
+  std::unordered_map<uint64_t, ffd_tuning> tuned;
   void *scratch = nullptr;    // device workspace for long single pairs (owned)
   size_t scratch_bytes = 0;
   ffd_launch_info last{};

@@ -39,7 +39,7 @@ EXPORTS = (
     "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
     "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
-    "ffd_server_last_error",
+    "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
 )
 
 
@@ -48,6 +48,14 @@ class LaunchInfo(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("lds_per_wave", ctypes.c_int32),
                 ("exact", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("stream_steps", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("split", ctypes.c_float),
+                ("ms", ctypes.c_float), ("ms_planner", ctypes.c_float), ("tried", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -113,6 +121,11 @@ def _load():
     lib.ffd_set_split.restype = ctypes.c_int
     lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
     lib.ffd_last_launch.restype = ctypes.c_int
+    lib.ffd_autotune_batch.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, vp, vp, sz, vp, ctypes.POINTER(Tuning)]
+    lib.ffd_autotune_batch.restype = ctypes.c_int
+    lib.ffd_autotune_cross.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, vp, vp, sz, vp,
+                                       ctypes.POINTER(Tuning)]
+    lib.ffd_autotune_cross.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.ffd_db_create.argtypes = [vp, vp, i64p, i64, i32, ctypes.POINTER(vp)]
     lib.ffd_db_create.restype = ctypes.c_int
@@ -319,6 +332,40 @@ def ffd_cross_i32(ctx, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, out=None, 
                   out, workspace, stream)
 
 
+def ffd_autotune_batch(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, workspace=None, stream=None):
+    """Time the launch shapes on this batch and keep the fastest for its offsets."""
+    P, Pp = _curve(P, torch.float32, "P")
+    Q, Qp = _curve(Q, torch.float32, "Q")
+    po, pop = _offsets(p_off)
+    qo, qop = _offsets(q_off)
+    npairs = len(po) - 1
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=torch.float32, device=P.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
+    t = Tuning()
+    _check(lib.ffd_autotune_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
+                                  _dev_ptr(out, torch.float32, "out"), wsp, wsn, _stream(stream),
+                                  ctypes.byref(t)), ctx)
+    return t.as_dict()
+
+
+def ffd_autotune_cross(ctx, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, out=None, workspace=None, stream=None):
+    """Time the launch shapes on this query set x database and keep the fastest."""
+    Qs, Qp = _curve(Qs, torch.float32, "Qs")
+    DB, Dp = _curve(DB, torch.float32, "DB")
+    qo, qop = _offsets(q_off)
+    do, dop = _offsets(db_off)
+    nq, ndb = len(qo) - 1, len(do) - 1
+    if out is None:
+        out = torch.empty(max(nq * ndb, 1), dtype=torch.float32, device=Qs.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
+    t = Tuning()
+    _check(lib.ffd_autotune_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
+                                  _dev_ptr(out, torch.float32, "out"), wsp, wsn, _stream(stream),
+                                  ctypes.byref(t)), ctx)
+    return t.as_dict()
+
+
 class Context:
     """Owns one ffd_ctx; methods call the functions above."""
 
@@ -366,6 +413,12 @@ class Context:
 
     def cross_i32(self, Qs, q_off, DB, db_off, **kw):
         return ffd_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
+
+    def autotune_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_autotune_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
+
+    def autotune_cross(self, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_autotune_cross(self.handle, Qs, q_off, DB, db_off, metric, **kw)
 
     def workspace_size(self, op, a_off, b_off, dim):
         return ffd_workspace_size(self.handle, op, a_off, b_off, dim)

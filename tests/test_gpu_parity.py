@@ -330,3 +330,23 @@ def test_long_curves_force_split(ctx):
         assert got == gotb
         assert got == oracle.dfd_f32_replica(p, q)
         assert rel_ok(got, oracle.dfd(p, q, 0, "rolling"))
+
+
+def test_autotune_keeps_results_and_uses_the_chosen_shape(ctx):
+    """The autotuner only changes launch shapes: the results stay bit for
+    bit, and later calls with the same offsets run the chosen shape."""
+    P, p_off, Q, q_off = workloads.random_pairs(61, 300, 64, 1500, dim=2)
+    say("case: autotune batch, 300 pairs")
+    base = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    t = ctx.autotune_batch(dev(P), p_off, dev(Q), q_off)
+    assert t["tried"] > 0 and t["ms"] > 0
+    got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    np.testing.assert_array_equal(got, base)
+    if t["rows_per_lane"]:
+        assert ctx.last_launch()["rows_per_lane"] == t["rows_per_lane"]
+    say("case: autotune cross, 6 x 300")
+    Qs, qo = workloads.concat([P[p_off[i]:p_off[i + 1]] for i in range(6)])
+    DB, do = workloads.concat([Q[q_off[i]:q_off[i + 1]] for i in range(300)])
+    cbase = ctx.cross(dev(Qs), qo, dev(DB), do).cpu().numpy()
+    ctx.autotune_cross(dev(Qs), qo, dev(DB), do)
+    np.testing.assert_array_equal(ctx.cross(dev(Qs), qo, dev(DB), do).cpu().numpy(), cbase)
