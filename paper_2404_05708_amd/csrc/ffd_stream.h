@@ -195,20 +195,16 @@ struct Stream {
   }
 
   // Read the refill state from LDS (the same values in every lane).
+  // Read the refill state from LDS.  Every lane reads the same values;
+  // only the fields that steer control flow are made scalar (the rest stay
+  // in vector registers, which keeps the scalar register file from spilling).
   __device__ void load_state(FillState &f) const {
     f = *fstate();
-    f.j = uni(f.j); f.jend = uni(f.jend); f.c = uni(f.c); f.b = uni(f.b); f.nb = uni(f.nb);
-    f.b_first = uni(f.b_first); f.b_end = uni(f.b_end); f.row_sel = uni(f.row_sel);
-    f.col_sel = uni(f.col_sel); f.col_first = uni(f.col_first); f.col_count = uni(f.col_count);
-    f.out_stride = uni(f.out_stride); f.flag_in = uni(f.flag_in); f.flag_out = uni(f.flag_out);
-    f.exhausted = uni(f.exhausted); f.next_id = uni(f.next_id); f.has_next = uni(f.has_next);
-    f.ptmp_pending = uni(f.ptmp_pending); f.ptmp_slot = uni(f.ptmp_slot); f.idle = uni(f.idle);
+    f.exhausted = uni(f.exhausted); f.has_next = uni(f.has_next); f.idle = uni(f.idle);
+    f.ptmp_pending = uni(f.ptmp_pending);
     f.pub_flag[0] = uni(f.pub_flag[0]); f.pub_flag[1] = uni(f.pub_flag[1]);
-    f.pub_count[0] = uni(f.pub_count[0]); f.pub_count[1] = uni(f.pub_count[1]);
-    f.row_off = uni64(f.row_off); f.n = uni64(f.n); f.out_base = uni64(f.out_base);
-    f.link_in = uni64(f.link_in); f.link_out = uni64(f.link_out); f.link_rel = uni64(f.link_rel);
-    uni_task(f.cur);
-    uni_task(f.nxt);
+    f.cur.S = uni(f.cur.S); f.cur.L = uni(f.cur.L); f.cur.hin = uni(f.cur.hin);
+    f.nxt.S = uni(f.nxt.S); f.nxt.L = uni(f.nxt.L); f.nxt.hin = uni(f.nxt.hin);
   }
 
   __device__ void store_state(const FillState &f) const {
