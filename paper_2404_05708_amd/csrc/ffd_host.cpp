@@ -708,8 +708,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap, pl.rings);
   a.max_steps = (int32_t)(pl.max_steps + 4 * ffd::kRing);
   a.epoch = ++ctx->epoch;
-  a.links = w + wl.links;
-  a.flags = (uint64_t *)(w + wl.flags);
+  a.links = pl.nflags > 0 ? w + wl.links : nullptr;  // no links: the kernel skips their bookkeeping
+  a.flags = pl.nflags > 0 ? (uint64_t *)(w + wl.flags) : nullptr;
   a.err = (uint64_t *)(w + wl.err);
   a.rings = pl.rings ? 1 : 0;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};

@@ -454,7 +454,7 @@ struct Stream {
   __device__ __forceinline__ void refill(int32_t t0) {
     FillState f;
     load_state(f);
-    flush_links(f, t0 - 2 * kWave, false);
+    if (a.flags) flush_links(f, t0 - 2 * kWave, false);  // launches without links skip it
     link_write();
     fill_write(f, t0 + kFill);
     link_load(f, t0 + kFill);
@@ -674,9 +674,11 @@ struct Stream {
       if (uni(d.drain)) {
         // end of the stream: store what is still staged (positions from
         // the last flush to the end of lane 63's last task) and publish
-        FillState f;
-        load_state(f);
-        flush_links(f, (t0 & ~(kFill - 1)) - kWave, true);
+        if (a.flags) {
+          FillState f;
+          load_state(f);
+          flush_links(f, (t0 & ~(kFill - 1)) - kWave, true);
+        }
         return false;
       }
       ++id63;
