@@ -80,7 +80,7 @@ def profiled_traffic(profile):
                 "kernel_source_sha256", "plan_header_sha256", "* traffic_bytes_per_launch"):
             k, v = line.split(":", 1)
             fields[k.strip().lstrip("* ")] = v.split()[0]
-    src = {"kernel_source_sha256": "paper_2404_05708_amd/csrc/ffd_kernels.hip",
+    src = {"kernel_source_sha256": "paper_2404_05708_amd/csrc/ffd_stream.h",
            "plan_header_sha256": "paper_2404_05708_amd/csrc/ffd_plan.h"}
     for key, rel in src.items():
         digest = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()

@@ -38,6 +38,17 @@
  *    recurrence only selects values; the square root is taken once per pair
  *    and correctly rounded).  Int32 results are exact.
  *  - A context may be used by one host thread at a time.
+ *  - Graph capture: ffd_distance, ffd_batch and ffd_cross (and their int32
+ *    forms) may be recorded into a hipGraph by stream capture once the same
+ *    call (same offsets, dimension, type, tuning and workspace) has run
+ *    outside the capture: the plan is then already in the workspace, or in
+ *    the context's scratch for a single long pair, and the recorded work is
+ *    a small kernel that clears the launch's progress flags followed by the
+ *    distance kernel.  Otherwise the call returns FFD_E_UNSUPPORTED and
+ *    records nothing.  The workspace then belongs to the graph: a later call
+ *    outside it with other offsets on the same workspace replaces the plan
+ *    the replays read.  Replays of one graph must not overlap each other.
+ *    The autotuner and the serving calls cannot be captured.
  */
 #ifndef FFD_H
 #define FFD_H

@@ -658,6 +658,14 @@ int ensure_pinned(ffd_ctx *ctx, size_t bytes) {
   return FFD_OK;
 }
 
+// Whether work submitted to `st` is being recorded into a graph.
+hipError_t capturing_on(hipStream_t st, bool &capturing) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  capturing = cs != hipStreamCaptureStatusNone;
+  return e;
+}
+
 // Run a planned launch: upload the plan (jobs, job ranges, offsets, zeroed
 // flags and error word) into the workspace unless the same plan is already
 // there, then launch.  Flags carry the launch epoch, so a reused plan needs
@@ -673,8 +681,15 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  bool capturing = false;
+  e = capturing_on(st, capturing);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
   unsigned char *w = (unsigned char *)ws;
   if (!(ctx->plan_ws == ws && ctx->plan_ws_key == key)) {
+    if (capturing)
+      return fail(ctx, FFD_E_UNSUPPORTED,
+                  "a launch recorded into a graph needs its plan in the workspace: make the same call once "
+                  "outside the capture first");
     int rc = ensure_pinned(ctx, wl.links);
     if (rc) return rc;
     unsigned char *h = (unsigned char *)ctx->pinned;
@@ -692,6 +707,12 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
     hipEventRecord(ctx->upload_done, st);
     ctx->plan_ws = ws;
     ctx->plan_ws_key = key;
+  }
+  if (capturing) {
+    // every replay runs with the epoch recorded here: clear the flags and
+    // the error word at the start of each replay instead
+    e = ffd::clear_words((uint64_t *)(w + wl.flags), (int64_t)((wl.links - wl.flags) / sizeof(uint64_t)), st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "flag clearing launch");
   }
   KernelArgs a;
   memset(&a, 0, sizeof a);
@@ -829,6 +850,13 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
   // bands split over waves: the plan and the links live in the context's scratch
   WsLayout wl = ws_layout(*pl, 1, 1, exact);
   if (ctx->scratch_bytes < wl.total) {
+    bool capturing = false;
+    e = capturing_on(st, capturing);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
+    if (capturing)
+      return fail(ctx, FFD_E_UNSUPPORTED,
+                  "a long pair recorded into a graph needs the context's scratch: make the same call once "
+                  "outside the capture first");
     if (ctx->scratch) {
       hipDeviceSynchronize();  // launches on any stream may still use it
       hipFree(ctx->scratch);
@@ -915,6 +943,10 @@ template <typename Call>
 int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb,
              hipStream_t st, Call call, ffd_tuning *best_out) {
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
+  bool capturing = false;
+  hipError_t ce = capturing_on(st, capturing);
+  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamIsCapturing");
+  if (capturing) return fail(ctx, FFD_E_UNSUPPORTED, "the autotuner times launches and cannot be captured");
   int R0 = ctx->tune_R, W0 = ctx->tune_W;
   float S0 = ctx->split;
   uint64_t base = key_of(ctx, op, D, exact, a, na, b, nb, true);

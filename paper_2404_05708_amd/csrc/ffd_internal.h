@@ -17,6 +17,7 @@ hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, in
 hipError_t launch_stream_rings(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
 hipError_t occupancy_stream_plain(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 hipError_t occupancy_stream_rings(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 
 // The kernel variant with LDS rings between waves serves launches whose
 // plan uses them (a.rings); every other launch takes the plain variant.

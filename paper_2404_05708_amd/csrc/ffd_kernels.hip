@@ -90,4 +90,18 @@ hipError_t FFD_OCC_NAME(bool exact, int R, int D, int wpb, size_t lds, int *bloc
   return exact ? occ_r<double>(R, D, wpb, lds, blocks_per_cu) : occ_r<float>(R, D, wpb, lds, blocks_per_cu);
 }
 
+// Zero n 64-bit words (progress flags and the error word of a launch that
+// is recorded into a graph: its replays share one epoch, so each replay
+// starts from cleared flags).  A kernel, not a memset node.
+__global__ void clear_words_kernel(uint64_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 }  // namespace ffd
