@@ -14,7 +14,11 @@ Contents
 * ``brute.py``: minimum over all monotone couplings (the Eiter--Mannila
   definition the paper builds on in Sec. 2), pure Python, tiny inputs only.
 * ``paper_forms.py``: the paper's branch-free forms (Algorithms 2, 4 and 5
-  with the scan and fold operators of Appendix A) in FP64 numpy.
+  with the scan and fold operators of Appendix A) in FP64 numpy, and the
+  DTW algorithm of Appendix B (Algorithm B.1) in the same style.
+* DTW (Appendix B): the table recurrence with the outer max replaced by a
+  sum, M_ij = min{M_{i-1,j}, M_{i-1,j-1}, M_{i,j-1}} + d_ij, in FP64, exact
+  int64, and a float32 replica (``dtw_*``).
 
 Inputs are float32 (widened exactly to FP64 inside) or int32 arrays of shape
 (n, D), row-major.  Metric 0 = Euclidean (sqrt of the sum of squares per
@@ -63,6 +67,16 @@ def _load():
         lib.ffdo_pairs.restype = ci
         lib.ffdo_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, i64p, ci, i64p]
         lib.ffdo_pairs_i32.restype = ci
+        lib.ffdo_dtw.argtypes = [f32p, i64, f32p, i64, ci, ci, f64p]
+        lib.ffdo_dtw.restype = ci
+        lib.ffdo_dtw_i32.argtypes = [i32p, i64, i32p, i64, ci, i64p]
+        lib.ffdo_dtw_i32.restype = ci
+        lib.ffdo_dtw_f32_replica.argtypes = [f32p, i64, f32p, i64, ci, ci, f32p]
+        lib.ffdo_dtw_f32_replica.restype = ci
+        lib.ffdo_dtw_pairs.argtypes = [f32p, i64p, i64p, f32p, i64p, i64p, i64, ci, ci, i64p, ci, f64p]
+        lib.ffdo_dtw_pairs.restype = ci
+        lib.ffdo_dtw_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, i64p, ci, i64p]
+        lib.ffdo_dtw_pairs_i32.restype = ci
         lib.ffdo_now.argtypes = []
         lib.ffdo_now.restype = ctypes.c_double
         _lib = lib
@@ -179,12 +193,54 @@ def dfd_f32_replica(p, q, metric=EUCLIDEAN):
     return np.float32(out.value)
 
 
+def dtw(p, q, metric=EUCLIDEAN):
+    """DTW (Appendix B) of two float32 curves in FP64; EUCLIDEAN takes the
+    square root in every cell."""
+    lib = _load()
+    p = _curve_f32(p)
+    q = _curve_f32(q)
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("dimension mismatch")
+    out = ctypes.c_double()
+    _check(lib.ffdo_dtw(_ptr(p, ctypes.c_float), p.shape[0], _ptr(q, ctypes.c_float), q.shape[0],
+                        p.shape[1], int(metric), ctypes.byref(out)), "dtw")
+    return out.value
+
+
+def dtw_i32(p, q):
+    """Exact squared-Euclidean DTW of int32 curves (int64)."""
+    lib = _load()
+    p = _curve_i32(p)
+    q = _curve_i32(q)
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("dimension mismatch")
+    out = ctypes.c_int64()
+    _check(lib.ffdo_dtw_i32(_ptr(p, ctypes.c_int32), p.shape[0], _ptr(q, ctypes.c_int32),
+                            q.shape[0], p.shape[1], ctypes.byref(out)), "dtw_i32")
+    return int(out.value)
+
+
+def dtw_f32_replica(p, q, metric=EUCLIDEAN):
+    """Float32 DTW replica: cell d2 as in dfd_f32_replica, a correctly
+    rounded float32 sqrt per cell for Euclidean, v = min(...) + d in float32."""
+    lib = _load()
+    p = _curve_f32(p)
+    q = _curve_f32(q)
+    out = ctypes.c_float()
+    _check(lib.ffdo_dtw_f32_replica(_ptr(p, ctypes.c_float), p.shape[0], _ptr(q, ctypes.c_float),
+                                    q.shape[0], p.shape[1], int(metric), ctypes.byref(out)),
+           "dtw_f32_replica")
+    return np.float32(out.value)
+
+
 def _i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
-def dfd_pairs(P, p_start, p_len, Q, q_start, q_len, metric=EUCLIDEAN, nthreads=1, order=None):
-    """Many float32 pairs on a thread pool; returns FP64 distances."""
+def dfd_pairs(P, p_start, p_len, Q, q_start, q_len, metric=EUCLIDEAN, nthreads=1, order=None,
+              measure="dfd"):
+    """Many float32 pairs on a thread pool; returns FP64 distances
+    (measure "dfd" or "dtw")."""
     lib = _load()
     P = _curve_f32(P)
     Q = _curve_f32(Q)
@@ -195,15 +251,17 @@ def dfd_pairs(P, p_start, p_len, Q, q_start, q_len, metric=EUCLIDEAN, nthreads=1
     if order is not None:
         order = _i64(order)
         ordp = _ptr(order, ctypes.c_int64)
-    _check(lib.ffdo_pairs(_ptr(P, ctypes.c_float), _ptr(ps, ctypes.c_int64),
-                          _ptr(pl, ctypes.c_int64), _ptr(Q, ctypes.c_float),
-                          _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n, P.shape[1],
-                          int(metric), ordp, int(nthreads), _ptr(out, ctypes.c_double)), "pairs")
+    fn = lib.ffdo_dtw_pairs if measure == "dtw" else lib.ffdo_pairs
+    _check(fn(_ptr(P, ctypes.c_float), _ptr(ps, ctypes.c_int64),
+              _ptr(pl, ctypes.c_int64), _ptr(Q, ctypes.c_float),
+              _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n, P.shape[1],
+              int(metric), ordp, int(nthreads), _ptr(out, ctypes.c_double)), "pairs")
     return out
 
 
-def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None):
-    """Many int32 pairs on a thread pool; returns exact int64 squared distances."""
+def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None, measure="dfd"):
+    """Many int32 pairs on a thread pool; returns exact int64 squared distances
+    (measure "dfd" or "dtw")."""
     lib = _load()
     P = _curve_i32(P)
     Q = _curve_i32(Q)
@@ -214,10 +272,11 @@ def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None):
     if order is not None:
         order = _i64(order)
         ordp = _ptr(order, ctypes.c_int64)
-    _check(lib.ffdo_pairs_i32(_ptr(P, ctypes.c_int32), _ptr(ps, ctypes.c_int64),
-                              _ptr(pl, ctypes.c_int64), _ptr(Q, ctypes.c_int32),
-                              _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n, P.shape[1],
-                              ordp, int(nthreads), _ptr(out, ctypes.c_int64)), "pairs_i32")
+    fn = lib.ffdo_dtw_pairs_i32 if measure == "dtw" else lib.ffdo_pairs_i32
+    _check(fn(_ptr(P, ctypes.c_int32), _ptr(ps, ctypes.c_int64),
+              _ptr(pl, ctypes.c_int64), _ptr(Q, ctypes.c_int32),
+              _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n, P.shape[1],
+                  ordp, int(nthreads), _ptr(out, ctypes.c_int64)), "pairs_i32")
     return out
 
 
@@ -257,6 +316,30 @@ def dfd_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
 def dfd_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None):
     ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
     return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads).reshape(nr, ndb)
+
+
+def dtw_batch(P, p_off, Q, q_off, metric=EUCLIDEAN, nthreads=1, order=None):
+    p_off = _i64(p_off)
+    q_off = _i64(q_off)
+    return dfd_pairs(P, p_off[:-1], np.diff(p_off), Q, q_off[:-1], np.diff(q_off), metric,
+                     nthreads, order, measure="dtw")
+
+
+def dtw_batch_i32(P, p_off, Q, q_off, nthreads=1, order=None):
+    p_off = _i64(p_off)
+    q_off = _i64(q_off)
+    return dfd_pairs_i32(P, p_off[:-1], np.diff(p_off), Q, q_off[:-1], np.diff(q_off),
+                         nthreads, order, measure="dtw")
+
+
+def dtw_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
+    ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
+    return dfd_pairs(Qs, ps, pl, DB, qs, ql, metric, nthreads, measure="dtw").reshape(nr, ndb)
+
+
+def dtw_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None):
+    ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
+    return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads, measure="dtw").reshape(nr, ndb)
 
 
 def now():

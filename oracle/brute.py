@@ -7,6 +7,9 @@ sequence of index pairs that starts at (1, 1), ends at (P, Q) and advances by
 (1, 0), (0, 1) or (1, 1) at every step.  This module enumerates every
 coupling explicitly; it is exponential and meant for P, Q <= 7 (at most
 Delannoy(6, 6) = 8989 couplings).
+
+DTW (Appendix B) over the same couplings takes the sum of the ground
+distances along a coupling instead of the largest one.
 """
 import numpy as np
 
@@ -72,6 +75,28 @@ def brute_from_matrix(d):
         if best is None or worst < best:
             best = worst
     return best
+
+
+def brute_dtw_from_matrix(d):
+    """min over couplings of the sum along the coupling, added in path order
+    (rounding is monotone, so this equals the table recurrence bit for bit)."""
+    P, Q = len(d), len(d[0])
+    best = None
+    for c in couplings(P, Q):
+        total = d[0][0]
+        for i, j in c[1:]:
+            total = total + d[i][j]
+        if best is None or total < best:
+            best = total
+    return best
+
+
+def brute_dtw(p, q, squared=False):
+    return float(brute_dtw_from_matrix(ground_matrix(p, q, squared).tolist()))
+
+
+def brute_dtw_int(p, q):
+    return int(brute_dtw_from_matrix(ground_matrix_int(p, q).tolist()))
 
 
 def brute(p, q, squared=False):

@@ -27,6 +27,14 @@
  * A separate "float replica" (ffdo_f32_replica) evaluates the distance with
  * the fixed float32 expression documented below and runs the recurrence in
  * float32; it exists only for a bit-exactness check of the GPU's FP32 path.
+ *
+ * Dynamic time warping (Appendix B, Algorithm B.1): the same table
+ * with the outer max replaced by a sum,
+ *   M_ij = min{M_{i-1,j}, M_{i-1,j-1}, M_{i,j-1}} + d_ij,  DTW = M_PQ,
+ * whose first row is the running sum of d_1j (the +-scan of the DTW
+ * algorithm) and whose first column is the running sum of d_i1.  Here the
+ * ground distance enters the sum per cell, so EUCLIDEAN takes a square root
+ * in every cell (ffdo_dtw_*).
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -321,6 +329,74 @@ int ffdo_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, 
     return rc;
 }
 
+/* ------------------------------------------- dynamic time warping (App. B) */
+
+/* Rows i-1 and i of the DTW table: the DFD recurrence with max{., d}
+ * replaced by . + d. */
+static int dtw_rolling_f64(const float *p, int64_t n, const float *q, int64_t m, int dim,
+                           int metric, double *out, double *prev, double *cur)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            double d = cell_f64(p + i * dim, q + j * dim, dim, metric);
+            double v;
+            if (i == 0 && j == 0) v = d;
+            else if (i > 0 && j == 0) v = prev[0] + d;
+            else if (i == 0 && j > 0) v = cur[j - 1] + d;
+            else v = dmin(dmin(prev[j], prev[j - 1]), cur[j - 1]) + d;
+            cur[j] = v;
+        }
+        double *t = prev; prev = cur; cur = t;
+    }
+    *out = prev[m - 1];
+    return FFDO_OK;
+}
+
+static int dtw_rolling_i64(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim,
+                           int64_t *out, int64_t *prev, int64_t *cur)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            int64_t d = cell_i64(p + i * dim, q + j * dim, dim);
+            int64_t v;
+            if (i == 0 && j == 0) v = d;
+            else if (i > 0 && j == 0) v = prev[0] + d;
+            else if (i == 0 && j > 0) v = cur[j - 1] + d;
+            else v = imin(imin(prev[j], prev[j - 1]), cur[j - 1]) + d;
+            cur[j] = v;
+        }
+        int64_t *t = prev; prev = cur; cur = t;
+    }
+    *out = prev[m - 1];
+    return FFDO_OK;
+}
+
+/* DTW of two float32 curves in FP64. */
+int ffdo_dtw(const float *p, int64_t n, const float *q, int64_t m, int dim, int metric,
+             double *out)
+{
+    int rc = check_args(p, n, q, m, dim, metric, out);
+    if (rc) return rc;
+    double *buf = (double *)malloc((size_t)(2 * m) * sizeof(double));
+    if (!buf) return FFDO_ENOMEM;
+    rc = dtw_rolling_f64(p, n, q, m, dim, metric, out, buf, buf + m);
+    free(buf);
+    return rc;
+}
+
+/* Squared-Euclidean DTW of int32 curves, exact int64 (the caller keeps the
+ * sums below 2^63). */
+int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int64_t *out)
+{
+    int rc = check_args(p, n, q, m, dim, FFDO_SQEUCLIDEAN, out);
+    if (rc) return rc;
+    int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
+    if (!buf) return FFDO_ENOMEM;
+    rc = dtw_rolling_i64(p, n, q, m, dim, out, buf, buf + m);
+    free(buf);
+    return rc;
+}
+
 /* ----------------------------------------------------------- float replica */
 
 /* Float32 replica of one fixed evaluation order: d2 = dx*dx, then
@@ -365,6 +441,37 @@ int ffdo_f32_replica(const float *p, int64_t n, const float *q, int64_t m, int d
     return FFDO_OK;
 }
 
+/* Float32 replica of DTW in one fixed order: the cell distance as above,
+ * then (EUCLIDEAN) its correctly rounded float32 square root, then
+ * v = fminf(fminf(...)) + d in float32.  Minima are exact, so only the
+ * order of the additions along the selected path matters, and that order is
+ * fixed by the recurrence. */
+int ffdo_dtw_f32_replica(const float *p, int64_t n, const float *q, int64_t m, int dim,
+                         int metric, float *out)
+{
+    int rc = check_args(p, n, q, m, dim, metric, out);
+    if (rc) return rc;
+    float *buf = (float *)malloc((size_t)(2 * m) * sizeof(float));
+    if (!buf) return FFDO_ENOMEM;
+    float *prev = buf, *cur = buf + m;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            float d = cell_f32_replica(p + i * dim, q + j * dim, dim);
+            if (metric == FFDO_EUCLIDEAN) d = sqrtf(d);
+            float v;
+            if (i == 0 && j == 0) v = d;
+            else if (i > 0 && j == 0) v = prev[0] + d;
+            else if (i == 0 && j > 0) v = cur[j - 1] + d;
+            else v = fminf(fminf(prev[j], prev[j - 1]), cur[j - 1]) + d;
+            cur[j] = v;
+        }
+        float *t = prev; prev = cur; cur = t;
+    }
+    *out = prev[m - 1];
+    free(buf);
+    return FFDO_OK;
+}
+
 /* ------------------------------------------------ many pairs on a thread pool */
 
 /* Pair k is P[p_start[k] .. p_start[k]+p_len[k]) against
@@ -378,6 +485,7 @@ struct pool_ctx {
     const int64_t *order;
     int64_t npairs;
     int dim, metric, is_int;
+    int dtw;               /* 0: discrete Frechet distance, 1: DTW */
     void *out;
     int64_t next;
     pthread_mutex_t mu;
@@ -408,13 +516,15 @@ static void *pool_worker(void *arg)
         if (c->is_int) {
             const int32_t *P = (const int32_t *)c->P, *Q = (const int32_t *)c->Q;
             int64_t *b = (int64_t *)buf;
-            rolling_i64(P + c->p_start[k] * c->dim, n, Q + c->q_start[k] * c->dim, m, c->dim,
-                        (int64_t *)c->out + k, b, b + m);
+            (c->dtw ? dtw_rolling_i64 : rolling_i64)(P + c->p_start[k] * c->dim, n,
+                                                     Q + c->q_start[k] * c->dim, m, c->dim,
+                                                     (int64_t *)c->out + k, b, b + m);
         } else {
             const float *P = (const float *)c->P, *Q = (const float *)c->Q;
             double *b = (double *)buf;
-            rolling_f64(P + c->p_start[k] * c->dim, n, Q + c->q_start[k] * c->dim, m, c->dim,
-                        c->metric, (double *)c->out + k, b, b + m);
+            (c->dtw ? dtw_rolling_f64 : rolling_f64)(P + c->p_start[k] * c->dim, n,
+                                                     Q + c->q_start[k] * c->dim, m, c->dim,
+                                                     c->metric, (double *)c->out + k, b, b + m);
         }
     }
     free(buf);
@@ -447,9 +557,9 @@ static int pool_args(const void *P, const void *Q, const int64_t *ps, const int6
     return FFDO_OK;
 }
 
-int ffdo_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, const float *Q,
-               const int64_t *q_start, const int64_t *q_len, int64_t npairs, int dim,
-               int metric, const int64_t *order, int nthreads, double *out)
+static int pairs_f32(const float *P, const int64_t *p_start, const int64_t *p_len, const float *Q,
+                     const int64_t *q_start, const int64_t *q_len, int64_t npairs, int dim,
+                     int metric, const int64_t *order, int nthreads, double *out, int dtw)
 {
     int rc = pool_args(P, Q, p_start, p_len, q_start, q_len, npairs, dim, out);
     if (rc) return rc;
@@ -458,13 +568,14 @@ int ffdo_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, con
     memset(&c, 0, sizeof c);
     c.P = P; c.Q = Q; c.p_start = p_start; c.p_len = p_len; c.q_start = q_start;
     c.q_len = q_len; c.order = order; c.npairs = npairs; c.dim = dim; c.metric = metric;
-    c.is_int = 0; c.out = out;
+    c.is_int = 0; c.dtw = dtw; c.out = out;
     return run_pool(&c, nthreads);
 }
 
-int ffdo_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
-                   const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
-                   int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+static int pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
+                     const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
+                     int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out,
+                     int dtw)
 {
     int rc = pool_args(P, Q, p_start, p_len, q_start, q_len, npairs, dim, out);
     if (rc) return rc;
@@ -472,8 +583,38 @@ int ffdo_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_le
     memset(&c, 0, sizeof c);
     c.P = P; c.Q = Q; c.p_start = p_start; c.p_len = p_len; c.q_start = q_start;
     c.q_len = q_len; c.order = order; c.npairs = npairs; c.dim = dim;
-    c.metric = FFDO_SQEUCLIDEAN; c.is_int = 1; c.out = out;
+    c.metric = FFDO_SQEUCLIDEAN; c.is_int = 1; c.dtw = dtw; c.out = out;
     return run_pool(&c, nthreads);
+}
+
+int ffdo_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, const float *Q,
+               const int64_t *q_start, const int64_t *q_len, int64_t npairs, int dim,
+               int metric, const int64_t *order, int nthreads, double *out)
+{
+    return pairs_f32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, metric, order, nthreads,
+                     out, 0);
+}
+
+int ffdo_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
+                   const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
+                   int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+{
+    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, order, nthreads, out, 0);
+}
+
+int ffdo_dtw_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, const float *Q,
+                   const int64_t *q_start, const int64_t *q_len, int64_t npairs, int dim,
+                   int metric, const int64_t *order, int nthreads, double *out)
+{
+    return pairs_f32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, metric, order, nthreads,
+                     out, 1);
+}
+
+int ffdo_dtw_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
+                       const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
+                       int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+{
+    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, order, nthreads, out, 1);
 }
 
 /* Seconds on the monotonic clock, for the CPU-baseline timer. */

@@ -15,6 +15,11 @@ Written from the descriptions in Sec. 3 and Appendix A of Meinert,
 * ``inplace``: Algorithm 4, which overwrites d: running maxima of the first
   column and row, then Eq. (1) over the interior.
 * ``linear``: Algorithm 5, one row v of length Q.
+* ``dtw``: the DTW algorithm of Appendix B (Algorithm B.1).  The first row is
+  the +-scan of d_1; ``dtw_next`` applies the same shifted minimum and then
+  a scan of ``dtw_min(a, x) = min(a, x1) + x2`` seeded with a_1 + x_1.  The
+  printed return line lacks the closing "last element" bracket that
+  Algorithm 2 has; it is read as the last element of the final row.
 
 The vector assignment "a_{2..Q} <- min(a_{1..Q-1}, a_{2..Q})" is read as a
 simultaneous assignment (right-hand side evaluated before any element is
@@ -98,6 +103,30 @@ def linear(p, q, f, sequential_shift=False):
         for j in range(1, Q):
             v[j] = max(min(v[j - 1], v[j]), f(p[i], q[j]))
     return v[Q - 1]
+
+
+def dtw_min(a, x):
+    return min(a, x[0]) + x[1]
+
+
+def dtw_rows(d, sequential_shift=False):
+    """Every row of Algorithm B.1's iteration (a scan in place of the final
+    fold): row i is M_i of the DTW table."""
+    d = [list(map(float, row)) for row in np.asarray(d).tolist()] if hasattr(d, "tolist") else d
+
+    def nxt(a, x):
+        a = _shift_min(a, sequential_shift)
+        pairs = list(zip(a[1:], x[1:]))
+        return scan(dtw_min, a[0] + x[0], pairs)
+
+    first = scan1(lambda s, x: s + x, d[0])
+    return scan(nxt, first, d[1:])
+
+
+def dtw(d, sequential_shift=False):
+    """Algorithm B.1 on a distance matrix d (P x Q): the last element of the
+    final row."""
+    return dtw_rows(d, sequential_shift)[-1][-1]
 
 
 def euclid_f64(a, b):
