@@ -89,7 +89,7 @@ def profiled_traffic(profile):
     return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
 
 
-def roofline(info, cells, kms, dim, exact, profile=None):
+def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel", suffix=""):
     ops = cells * imin(dim, exact)
     achieved = ops / (kms / 1e3)
     vt = "double" if exact else "float"
@@ -97,7 +97,7 @@ def roofline(info, cells, kms, dim, exact, profile=None):
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
         "unit": "TVALUop/s", "frac": achieved / PEAK_VALU,
         "traffic": profiled_traffic(profile) if profile else None,
-        "kernel": f"ffd::stream_kernel<{info['rows_per_lane']}, {dim}, {vt}>", "kernel_ms": kms,
+        "kernel": f"ffd::{family}<{info['rows_per_lane']}, {dim}, {vt}{suffix}>", "kernel_ms": kms,
         "launch": info, "ops_per_cell": imin(dim, exact), "cells_per_launch": cells,
     }
 
@@ -190,6 +190,67 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
         "autotune": tuning,
         "roofline": roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md"),
         "plain": plain, "cpu_baseline": cpu,
+    }
+
+
+def run_dtw(args, torch, ffd, ctx, dev, stream):
+    """DTW (Appendix B) with squared Euclidean cells on the batched workload."""
+    import workloads
+    P, p_off, Q, q_off = workloads.batched()
+    npairs = len(p_off) - 1
+    cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
+    dim = P.shape[1]
+    Pd = torch.from_numpy(P).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.empty(npairs, dtype=torch.float32, device=dev)
+    metric = ffd.FFD_SQEUCLIDEAN
+
+    def step():
+        ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=metric, out=out, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    errs = ctx.last_errors()
+    g = golden()["dtw_batched"]
+    res = out.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    want = np.array(g["sqeuclidean"])
+    n_s, m_s = np.diff(p_off)[idx], np.diff(q_off)[idx]
+    bound = (n_s + m_s + dim + 2) * 2.0 ** -24 * 1.01
+    parity_ok = bool(np.all(np.abs(res[idx] - want) <= bound * want))
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = cpu_cores()
+        rng = np.random.default_rng(77)
+        sample = np.sort(rng.choice(npairs, size=args.cpu_pairs, replace=False))
+        s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
+        ps, pl = p_off[:-1][sample], np.diff(p_off)[sample]
+        qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
+        order = np.argsort(-(pl * ql))
+        t2 = time.perf_counter()
+        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.SQEUCLIDEAN, cores, order, measure="dtw")
+        cw = time.perf_counter() - t2
+        b2 = (pl + ql + dim + 2) * 2.0 ** -24 * 1.01
+        cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"{args.cpu_pairs} of the 4096 pairs (seed 77), {s_cells} cells, FP64 rolling-row "
+                         f"DTW oracle, longest first on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= b2 * vals))}
+    return {
+        "metric": "dtw_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
+        "config": {"workload": "dtw: DTW (Appendix B) with squared Euclidean cells on the batched pairs: "
+                               "4096 pairs, n and m uniform in [64, 2048], 2-D float32 random walks (seed 2)",
+                   "npairs": npairs, "cells": cells, "global_batch": npairs},
+        "parity": {"tolerance": "(n + m + D + 2) 2^-24 relative", "sampled_ok": parity_ok,
+                   "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, dim, False, family="dtw_kernel", suffix=", 1"),
+        "cpu_baseline": cpu,
     }
 
 
@@ -404,7 +465,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw"],
+                    default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
     ap.add_argument("--qps", type=float, default=0.0, help="open-loop arrival rate; 0 = half the saturation rate")
@@ -443,10 +505,12 @@ def main():
         r = run_cross(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "serving":
         r = run_serving(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "dtw":
+        r = run_dtw(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {
-        "metric": METRIC, "value": r["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "metric": r.get("metric", METRIC), "value": r["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }

@@ -156,9 +156,43 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
                   int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
                   void *stream);
 
+/* Dynamic time warping (Appendix B, Algorithm B.1): the recurrence of Eq. (1)
+ * with the outer max replaced by a sum,
+ *     M_ij = min{ M_{i-1,j}, M_{i-1,j-1}, M_{i,j-1} } + d_ij,   DTW = M_PQ,
+ * whose first row and column are running sums of d.  Each call takes the
+ * arguments of its Frechet counterpart (ffd_distance, ffd_batch, ffd_cross
+ * and their int32 forms) with the same layouts, ownership, workspace sizes
+ * (ffd_workspace_size covers both) and errors.  The ground distance is
+ * summed per cell, so FFD_EUCLIDEAN takes the hardware float32 square root
+ * (within 1 ulp) in every cell and FFD_SQEUCLIDEAN sums squared distances;
+ * the result is the sum itself.  Float32 results agree with the exact
+ * result to a relative error of (n + m + D + 3) 2^-24 (each cell carries at
+ * most D + 3 rounding errors, the sum along the selected coupling one per
+ * addition), for cells whose squared distance is not below 2^-126.  Int32
+ * calls (squared Euclidean only) are exact while the sums stay below 2^53
+ * (for example |x| < 2^15 and n + m < 2^19). */
+int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
+                     int32_t dim, int32_t metric, float *out, void *stream);
+int ffd_dtw_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q,
+                         int64_t m, int32_t dim, int32_t metric, int64_t *out, void *stream);
+int ffd_dtw_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q,
+                  const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, float *out,
+                  void *workspace, size_t ws_bytes, void *stream);
+int ffd_dtw_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
+                      const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric,
+                      int64_t *out, void *workspace, size_t ws_bytes, void *stream);
+int ffd_dtw_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq,
+                  const float *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
+                  int32_t metric, float *out, void *workspace, size_t ws_bytes, void *stream);
+int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq,
+                      const int32_t *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
+                      int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
+                      void *stream);
+
 /* Device workspace needed by ffd_batch (op = FFD_OP_BATCH: a_off = p_off,
  * na = npairs, b_off = q_off, nb = npairs) or ffd_cross (op = FFD_OP_CROSS:
- * a_off = q_off, na = nq, b_off = db_off, nb = ndb).  Writes *bytes.
+ * a_off = q_off, na = nq, b_off = db_off, nb = ndb), and by their int32 and
+ * DTW forms: the size covers all of them.  Writes *bytes.
  * Errors: FFD_E_INVALID for a bad op, NULL or bad offsets. */
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                        const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);

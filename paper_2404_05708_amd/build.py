@@ -24,7 +24,8 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["ffd_kernels.hip", "ffd_kernels_rings.hip", "ffd_host.cpp", "ffd_server.cpp"]
+SOURCES = ["ffd_kernels.hip", "ffd_kernels_rings.hip", "ffd_kernels_dtw.hip", "ffd_kernels_dtw_euc.hip",
+           "ffd_host.cpp", "ffd_server.cpp"]
 
 
 def _compile(src):

@@ -59,9 +59,10 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // measured lone waves (one per SIMD; 3-D single pairs at R = 2, 4, 8 and the
 // 2-D batch at R = 8): about 104 + 3.9 I clocks.  Waves sharing a SIMD also
 // share its wave64 issue slots (4 clocks each), which they keep about three
-// quarters busy.
-double step_clocks(int R, int D, bool exact, double waves_per_simd) {
-  double I = (double)R * (2 * D + (exact ? 3 : 2)) + 8.0;
+// quarters busy.  DTW with Euclidean cells (measure 2) adds a square root
+// per cell, a quarter-rate instruction (4 issue slots).
+double step_clocks(int R, int D, bool exact, double waves_per_simd, int measure = 0) {
+  double I = (double)R * (2 * D + (exact ? 3 : 2) + (measure == 2 ? 4 : 0)) + 8.0;
   double lone = 104.0 + 3.9 * I;
   double shared = 0.75 * std::max(1.0, waves_per_simd) * I * 4.0;
   return std::max(lone, shared);
@@ -104,8 +105,8 @@ int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   return FFD_OK;
 }
 
-int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings) {
-  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings).total;
+int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings, int measure) {
+  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, measure != 0).total;
 }
 
 const int kRs[4] = {1, 2, 4, 8};
@@ -267,15 +268,15 @@ Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W) {
   size_t block_lds = ctx->lds_cu / blocks_per_cu / 1024 * 1024;
   size_t per_wave = block_lds / (size_t)r.wpb / 16 * 16;
   int vs = exact ? 8 : 4;
-  int fixed = lds_bytes(R, D, exact, 0);
+  int fixed = lds_bytes(R, D, exact, 0, false, ctx->measure);
   int64_t hand = ((int64_t)per_wave - fixed - 16) / vs;
   r.hand_max = hand > 0 ? hand : 0;
   r.nwaves_max = ctx->cus * 4 * W;
-  size_t lds = (size_t)r.wpb * (size_t)lds_bytes(R, D, exact, r.hand_max);
+  size_t lds = (size_t)r.wpb * (size_t)lds_bytes(R, D, exact, r.hand_max, false, ctx->measure);
   if (ctx->device >= 0) {
     // registers may allow fewer resident waves than the LDS share assumes
     int blocks = 0;
-    if (ffd::occupancy_stream(exact, R, D, r.wpb, lds, &blocks) == hipSuccess && blocks > 0)
+    if (ffd::occupancy_stream(exact, R, D, r.wpb, lds, &blocks, false, ctx->measure) == hipSuccess && blocks > 0)
       r.nwaves_max = std::min(r.nwaves_max, ctx->cus * blocks * r.wpb);
   }
   // A launch whose waves wait on other waves needs every wave resident.
@@ -565,9 +566,10 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
     }
     pl.wpb = std::min(rs.wpb, pl.nwaves);
     double wps = std::ceil((double)pl.nwaves / (4.0 * ctx->cus));
-    double cost = ((double)pl.max_steps + ffd::kWave) * step_clocks(R, D, exact, wps);
+    double cost = ((double)pl.max_steps + ffd::kWave) * step_clocks(R, D, exact, wps, ctx->measure);
     Plan pipe;
-    if (single && share >= 0 && units.size() == 1 && build_pipeline(ctx, units[0], R, D, exact, pipe)) {
+    if (single && share >= 0 && units.size() == 1 && ctx->measure == 0 &&
+        build_pipeline(ctx, units[0], R, D, exact, pipe)) {
       double pw = std::ceil((double)pipe.nwaves / (4.0 * ctx->cus));
       double pc = ((double)pipe.max_steps + ffd::kWave) * step_clocks(R, D, exact, pw);
       if (pc < cost) {
@@ -674,8 +676,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
              const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
              size_t ws_bytes, hipStream_t st) {
   WsLayout wl = ws_layout(pl, n0, n1, exact);
-  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings), exact ? 1 : 0, D,
-                              pl.max_steps};
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings, ctx->measure),
+                              exact ? 1 : 0, D, pl.max_steps};
   if (!ws || ws_bytes < wl.total) return fail(ctx, FFD_E_NOMEM, "workspace too small (see ffd_workspace_size)");
   if (pl.max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
@@ -726,7 +728,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.nwaves = pl.nwaves;
   a.metric = metric;
   a.hcap = (int32_t)pl.hcap;
-  a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap, pl.rings);
+  a.lds_per_wave = lds_bytes(pl.R, D, exact, pl.hcap, pl.rings, ctx->measure);
   a.max_steps = (int32_t)(pl.max_steps + 4 * ffd::kRing);
   a.epoch = ++ctx->epoch;
   a.links = pl.nflags > 0 ? w + wl.links : nullptr;  // no links: the kernel skips their bookkeeping
@@ -734,7 +736,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   a.err = (uint64_t *)(w + wl.err);
   a.rings = pl.rings ? 1 : 0;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
-  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st);
+  e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st, ctx->measure);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
@@ -747,7 +749,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
 uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b,
                 int64_t nb, bool base = false) {
   uint64_t h = 1469598103934665603ull;
-  int hdr[6] = {op, D, exact ? 1 : 0, base ? 0 : ctx->tune_R, base ? 0 : ctx->tune_W, 0};
+  int hdr[6] = {op, D, exact ? 1 : 0, base ? 0 : ctx->tune_R, base ? 0 : ctx->tune_W, ctx->measure};
   float sp = base ? 0.f : ctx->split;
   h = fnv(h, hdr, sizeof hdr);
   h = fnv(h, &sp, sizeof sp);
@@ -759,6 +761,15 @@ uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64
 }
 
 constexpr int kOpPair = 100;  // internal plan kind of ffd_distance
+
+// The measure of the call in progress (0 Frechet, 1 DTW of squared cells, 2
+// DTW of Euclidean cells), read by the planner and the launcher.
+struct MeasureScope {
+  ffd_ctx *ctx;
+  int saved;
+  MeasureScope(ffd_ctx *c, int m) : ctx(c), saved(c->measure) { c->measure = m; }
+  ~MeasureScope() { ctx->measure = saved; }
+};
 
 // With automatic settings, a launch shape the autotuner chose for this
 // request replaces the model's choice for the duration of the call.
@@ -818,7 +829,8 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
   rc = cached_plan(ctx, ctx->pair_plans, kOpPair, off0, 1, off1, 1, dim, exact, &pl, key);
   if (rc) return rc;
   if (pl->max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
-  ctx->last = ffd_launch_info{pl->R, pl->nwaves, pl->wpb, lds_bytes(pl->R, dim, exact, pl->hcap), exact ? 1 : 0,
+  ctx->last = ffd_launch_info{pl->R, pl->nwaves, pl->wpb, lds_bytes(pl->R, dim, exact, pl->hcap, false, ctx->measure),
+                              exact ? 1 : 0,
                               dim, pl->max_steps};
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipError_t e = hipSetDevice(ctx->device);
@@ -839,10 +851,10 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
     a.nwaves = 1;
     a.metric = metric;
     a.hcap = (int32_t)pl->hcap;
-    a.lds_per_wave = lds_bytes(pl->R, dim, exact, pl->hcap);
+    a.lds_per_wave = lds_bytes(pl->R, dim, exact, pl->hcap, false, ctx->measure);
     a.max_steps = (int32_t)(pl->max_steps + 4 * ffd::kRing);
     a.epoch = ++ctx->epoch;
-    e = ffd::launch_stream(exact, pl->R, dim, a, 1, false, st);
+    e = ffd::launch_stream(exact, pl->R, dim, a, 1, false, st, ctx->measure);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     ctx->last_err = nullptr;
     return FFD_OK;
@@ -1134,6 +1146,60 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
                       (hipStream_t)stream, true);
 }
 
+// Dynamic time warping (Appendix B): the same calls with measure 1 (squared
+// Euclidean cells, also every int32 call) or 2 (Euclidean cells).
+static int dtw_measure(int32_t metric, bool exact) { return exact || metric == FFD_SQEUCLIDEAN ? 1 : 2; }
+
+int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim,
+                     int32_t metric, float *out, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, false));
+  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
+}
+
+int ffd_dtw_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
+                         int32_t metric, int64_t *out, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, true));
+  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, true);
+}
+
+int ffd_dtw_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                  int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
+                  void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, false));
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
+                      false);
+}
+
+int ffd_dtw_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
+                      int64_t npairs, int32_t dim, int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
+                      void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, true));
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
+                      true);
+}
+
+int ffd_dtw_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, const float *DB,
+                  const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out, void *workspace,
+                  size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, false));
+  return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
+                      (hipStream_t)stream, false);
+}
+
+int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
+                      const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int64_t *out, void *workspace,
+                      size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, dtw_measure(metric, true));
+  return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
+                      (hipStream_t)stream, true);
+}
+
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
                        int32_t dim, size_t *bytes) {
   if (!ctx || !bytes) return FFD_E_INVALID;
@@ -1147,16 +1213,20 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   int rc;
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
+  // one size for every path: float and int32 coordinates, Frechet and DTW
   size_t worst = 0;
-  for (int ex = 0; ex < 2; ++ex) {
-    const Plan *pl;
-    uint64_t key;
-    PlanCache tmp;
-    rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, dim, ex == 1, &pl, key);
-    if (rc == FFD_E_UNSUPPORTED) continue;
-    if (rc) return rc;
-    worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
-  }
+  for (int ms = 0; ms < 3; ++ms)
+    for (int ex = 0; ex < 2; ++ex) {
+      if (ms == 2 && ex == 1) continue;  // int32 DTW has squared cells only
+      MeasureScope scope(ctx, ms);
+      const Plan *pl;
+      uint64_t key;
+      PlanCache tmp;
+      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, dim, ex == 1, &pl, key);
+      if (rc == FFD_E_UNSUPPORTED) continue;
+      if (rc) return rc;
+      worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
+    }
   if (worst == 0) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;
   return FFD_OK;

@@ -17,16 +17,27 @@ hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, in
 hipError_t launch_stream_rings(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
 hipError_t occupancy_stream_plain(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 hipError_t occupancy_stream_rings(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+hipError_t launch_dtw_sq(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
+hipError_t launch_dtw_euc(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
+hipError_t occupancy_dtw_sq(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+hipError_t occupancy_dtw_euc(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 
 // The kernel variant with LDS rings between waves serves launches whose
 // plan uses them (a.rings); every other launch takes the plain variant.
-inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
+// `measure`: 0 discrete Frechet distance, 1 DTW of squared Euclidean cells,
+// 2 DTW of Euclidean cells (DTW plans never use rings).
+inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
+                                int measure = 0) {
+  if (measure == 1) return launch_dtw_sq(exact, R, D, a, wpb, coop, st);
+  if (measure == 2) return launch_dtw_euc(exact, R, D, a, wpb, coop, st);
   return a.rings ? launch_stream_rings(exact, R, D, a, wpb, coop, st)
                  : launch_stream_plain(exact, R, D, a, wpb, coop, st);
 }
 inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu,
-                                   bool rings = false) {
+                                   bool rings = false, int measure = 0) {
+  if (measure == 1) return occupancy_dtw_sq(exact, R, D, wpb, lds, blocks_per_cu);
+  if (measure == 2) return occupancy_dtw_euc(exact, R, D, wpb, lds, blocks_per_cu);
   return rings ? occupancy_stream_rings(exact, R, D, wpb, lds, blocks_per_cu)
                : occupancy_stream_plain(exact, R, D, wpb, lds, blocks_per_cu);
 }
@@ -70,6 +81,7 @@ struct ffd_ctx {
   int tune_R = 0;
   int tune_W = 0;
   float split = 0.f;          // 0 auto, < 0 split only when needed, > 0 split above this share
+  int measure = 0;            // of the call in progress: 0 Frechet, 1 DTW squared, 2 DTW Euclidean
   uint32_t epoch = 0;
   std::string last_error;
   // plan most recently written to a workspace (skip the upload if unchanged)
@@ -96,7 +108,7 @@ int fail(ffd_ctx *ctx, int code, const char *msg);
 int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what);
 int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *name);
 int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact);
-int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings = false);
+int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings = false, int measure = 0);
 int64_t self_gap(int64_t sumL);
 
 struct Resources {

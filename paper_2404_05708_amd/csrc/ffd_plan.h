@@ -81,7 +81,8 @@ FFD_HD int64_t task_len(int64_t m, bool chained) {
 // of the value type (4: float32 path, 8: exact path with FP64 values).
 struct LdsLayout {
   int ring;   // (kRing + kGroup) column points; the last kGroup mirror the first
-  int ghost;  // kGroup + 1 values: -inf, +inf, ... (top boundary of a first band)
+  int ghost;  // top boundary of a first band: kGroup + 1 values -inf, +inf, ...; DTW:
+              // 2 kGroup + 1 values, +inf except 0 in the middle
   int sink;   // kWave + kGroup values: bottom-row stores that hand nothing on
   int hand;   // hcap values: bottom row of the band above (same wave)
   int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
@@ -98,12 +99,12 @@ FFD_HD int align16(int x) { return (x + 15) & ~15; }
 FFD_HD int pad_dim(int D) { return D == 3 ? 4 : D; }
 
 // rings: the wave also owns a ring that hands its bottom row to another
-// wave of its workgroup.
-FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings) {
+// wave of its workgroup.  dtw: the layout of the DTW kernels.
+FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings, bool dtw = false) {
   LdsLayout L;
   int o = 0;
   L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
-  L.ghost = o; o += (kGroup + 1) * vsize;
+  L.ghost = o; o += (dtw ? 2 * kGroup + 1 : kGroup + 1) * vsize;
   L.sink = o;  o += (kWave + kGroup) * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
   o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;

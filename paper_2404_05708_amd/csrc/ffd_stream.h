@@ -27,6 +27,16 @@
 //    end repeat its last column point: repeating points does not change the
 //    distance (Sec. 4, footnote), so padding is exact.
 //
+// Dynamic time warping (Appendix B, Algorithm B.1) runs on the same sweep with
+// the outer max replaced by a sum, M_ij = min{...} + d_ij (OP = 1: squared
+// Euclidean cells, OP = 2: Euclidean cells, the hardware square root per
+// cell).  Sums are not selections, so padding is no longer exact: a DTW
+// task puts its separator columns first and its m real columns last (the
+// top-boundary corner, 0 for DTW, sits at the last separator), and the
+// result M_{n-1,m-1} is taken from the lane holding row n-1 at the moment
+// it switches to the next task, when its registers still hold the last
+// column of the old one.
+//
 // The squared distance is evaluated as d2 = dx*dx, then d2 = fma(dk, dk, d2)
 // for k >= 1, in the value type; the recurrence runs on d2 and the Euclidean
 // result is the correctly rounded square root of the selected d2 (min and
@@ -63,6 +73,12 @@ struct Num<float> {
     float r = metric == 0 ? (float)__builtin_sqrt((double)v) : v;
     static_cast<float *>(out)[idx] = r;
   }
+  // the hardware square root (v_sqrt_f32, within 1 ulp); the correctly
+  // rounded library form costs about 16 more instructions per cell
+  __device__ static __forceinline__ float sqrt_cell(float x) { return __builtin_amdgcn_sqrtf(x); }
+  __device__ static __forceinline__ void store_value(void *out, int64_t idx, float v) {
+    static_cast<float *>(out)[idx] = v;
+  }
 };
 
 template <>
@@ -83,6 +99,10 @@ struct Num<double> {
   __device__ static __forceinline__ void store(void *out, int64_t idx, double v, int) {
     static_cast<int64_t *>(out)[idx] = (int64_t)v;
   }
+  __device__ static __forceinline__ double sqrt_cell(double x) { return __builtin_sqrt(x); }
+  __device__ static __forceinline__ void store_value(void *out, int64_t idx, double v) {
+    static_cast<int64_t *>(out)[idx] = (int64_t)v;
+  }
 };
 
 // Task descriptor kept in LDS (64 bytes).
@@ -95,7 +115,9 @@ struct Desc {
   int32_t L;           // stream length
   int32_t hin, hout;   // boundary modes
   int32_t out_lo, out_hi;  // result index, -1 = none
-  int32_t drain;       // 1: padding task after the last job
+  int32_t drain;       // bit 0: padding task after the last job; DTW also packs the
+                       // register (bits 1-3) and lane (bits 4-9) of the curve's last
+                       // row in this band and the separator count (bits 10+)
   int32_t flag_in, flag_out;
   int32_t rel_in;      // entries of the incoming link before this task's row
   int32_t rel_out;     // entries of the outgoing link before this task's row
@@ -119,8 +141,11 @@ constexpr int kSpinLimit = 1 << 22;
 // s_waitcnt operand (gfx9 encoding) that waits for vmcnt = 0 only.
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-template <int R, int D, typename V, bool RINGS>
+// OP: 0 discrete Frechet distance, 1 DTW of squared Euclidean cells, 2 DTW
+// of Euclidean cells.
+template <int R, int D, typename V, bool RINGS, int OP = 0>
 struct Stream {
+  static constexpr bool DTW = OP != 0;
   using N = Num<V>;
   using C = typename N::Coord;
   static constexpr int DP = D == 3 ? 4 : D;
@@ -307,6 +332,12 @@ struct Stream {
       t.rel = (int32_t)f.link_rel;
       d.rel_in = d.rel_out = (int32_t)f.link_rel;
       d.L = t.L; d.hin = hin; d.hout = hout; d.drain = 0;
+      if constexpr (DTW) {
+        // separators first, real columns last; the last row's lane and register
+        int64_t last = f.n - 1 - (int64_t)b * kWave * R;
+        int32_t lr = last < kWave * R ? (int32_t)last : kWave * R - 1;
+        d.drain = ((lr % R) << 1) | ((lr / R) << 4) | ((int32_t)(t.L - t.m) << 10);
+      }
       d.out_lo = (int32_t)(uint32_t)(uint64_t)oi;
       d.out_hi = (int32_t)(uint32_t)((uint64_t)oi >> 32);
       d.flag_in = f.flag_in;
@@ -383,8 +414,14 @@ struct Stream {
     int64_t co = in_next ? nxt.col_off : cur.col_off;
     int32_t sel = in_next ? nxt.col_sel : cur.col_sel;
     bool drain = in_next ? nxt.drain : cur.drain;
-    qsep = drain || x == 0;
     int64_t idx = x - 1;
+    if constexpr (DTW) {
+      int64_t npre = (in_next ? nxt.L : cur.L) - m;
+      qsep = drain || x < npre;
+      idx = x - npre;
+    } else {
+      qsep = drain || x == 0;
+    }
     if (idx > m - 1) idx = m - 1;
     if (idx < 0) idx = 0;
     if (drain) { co = 0; idx = 0; sel = 0; }
@@ -485,6 +522,9 @@ struct Stream {
   V upPrev;
   // lane-0 cursor (task containing the group being loaded) and window start
   int32_t id0, S0, L0, g0, src0, win0, win_cur;
+  int32_t pre0;  // DTW: separator columns of lane 0's task
+  int32_t rc63, ls63;  // DTW: register and lane of the last row of lane 63's task
+  V cap;         // DTW: this lane's value of the last column, taken at its task switch
   // lane-63 cursor: task containing column t0 - 64
   int32_t id63, S63, L63, hout63, flag63, rel63;
   int64_t out63, link63;
@@ -495,7 +535,7 @@ struct Stream {
   // merge).
   template <bool PLAIN>
   __device__ __forceinline__ void group(int32_t t0, int32_t win, bool window, const GroupIn &g, V *hout,
-                                        V &res) {
+                                        V &res, int32_t rc) {
     if (PLAIN) window = false;
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
@@ -507,6 +547,13 @@ struct Stream {
       if (u == kGroup - 1) res = bottom;
       if (window) {
         bool sw = lane == t0 + u - win;
+        if constexpr (DTW) {
+          // the lane leaves the old task: its registers hold that task's last column
+          V sel = Mp[0];
+#pragma unroll
+          for (int r = 1; r < R; ++r) sel = rc == r ? Mp[r] : sel;
+          cap = sw ? sel : cap;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -526,12 +573,15 @@ struct Stream {
           V w = p[r][k2] - g.q[u].c[k2];
           s = N::fma(w, w, s);
         }
+        if constexpr (OP == 2) s = N::sqrt_cell(s);
         dd[r] = s;
       }
       V above = up, diag = upPrev;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        V v = N::mx(N::mn(N::mn(above, diag), Mp[r]), dd[r]);
+        V v;
+        if constexpr (DTW) v = N::mn(N::mn(above, diag), Mp[r]) + dd[r];
+        else v = N::mx(N::mn(N::mn(above, diag), Mp[r]), dd[r]);
         diag = Mp[r];
         above = v;
         Mp[r] = v;
@@ -546,6 +596,12 @@ struct Stream {
   // from an undefined register on the link path.
   __device__ __forceinline__ const V *hin_at(int32_t t) const {
     int32_t og = lay.ghost + (t == S0 ? 0 : (int32_t)sizeof(V));
+    if constexpr (DTW) {
+      // ghost = [+inf x kGroup, 0, +inf x kGroup]; the corner sits at the
+      // task's last separator column c
+      int32_t c = S0 + pre0 - 1;
+      og = lay.ghost + (c >= t && c < t + kGroup ? kGroup - (c - t) : 0) * (int32_t)sizeof(V);
+    }
     int32_t oh = lay.hand + (t - S0) * (int32_t)sizeof(V);
     int32_t ol = lay.lring + (t & (kLinkRing - 1)) * (int32_t)sizeof(V);
     int32_t off = g0 == kHinGhost ? og : (g0 == kHinHand ? oh : ol);
@@ -564,6 +620,7 @@ struct Stream {
       L0 = uni(d.L);
       g0 = uni(d.hin);
       src0 = uni(d.src);
+      if constexpr (DTW) pre0 = uni(d.drain) >> 10;
       win0 = t;
       const V *src = pst(id0 & 1) + lane * (R * D);
 #pragma unroll
@@ -671,7 +728,7 @@ struct Stream {
     if ((t0 & (kFill - 1)) == 0) refill(t0);
     if (t0 - kWave == S63 + L63) {
       Desc d = *desc(id63 + 1);
-      if (uni(d.drain)) {
+      if (uni(d.drain) & (DTW ? 1 : -1)) {
         // end of the stream: store what is still staged (positions from
         // the last flush to the end of lane 63's last task) and publish
         if (a.flags) {
@@ -689,6 +746,10 @@ struct Stream {
       rel63 = uni(d.rel_out);
       link63 = uni64(d.link_out);
       out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
+      if constexpr (DTW) {
+        rc63 = (uni(d.drain) >> 1) & 7;
+        ls63 = (uni(d.drain) >> 4) & 63;
+      }
     }
     int32_t x63 = t0 - kWave - S63;
     // lane 63's bottom row: the hand-off row, the link staging ring (by
@@ -717,13 +778,17 @@ struct Stream {
     }
     V res;
     bool window = t0 < win0 + kWave;
-    if (!window) group<true>(t0, win0, false, g, hout, res);
-    else group<false>(t0, win0, window, g, hout, res);
+    if (!window) group<true>(t0, win0, false, g, hout, res, rc63);
+    else group<false>(t0, win0, window, g, hout, res, rc63);
     if (RINGS && hout63 == kHoutRing && lane == 0)
       __hip_atomic_store(xctr(wib), x63 + kGroup < L63 ? x63 + kGroup : L63, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
-      N::store(a.out, out63, res, a.metric);
+    if constexpr (DTW) {
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
+    } else {
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
+        N::store(a.out, out63, res, a.metric);
+    }
     return true;
   }
 
@@ -734,7 +799,7 @@ struct Stream {
 #ifdef FFD_DEBUG_HIN
     dbg_wave = wave;
 #endif
-    lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS);
+    lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS, DTW);
     int32_t j0, j1;
     if (a.jobs) {
       j0 = uni(a.wave_jobs[wave]);
@@ -749,7 +814,11 @@ struct Stream {
 
     // constant LDS: top boundary and ring entries before the stream start;
     // row staging starts as zeros so that no lane ever reads uninitialised LDS
-    for (int i = lane; i <= kGroup; i += kWave) ghost()[i] = i == 0 ? -N::inf() : N::inf();
+    if constexpr (DTW) {
+      for (int i = lane; i <= 2 * kGroup; i += kWave) ghost()[i] = i == kGroup ? V(0) : N::inf();
+    } else {
+      for (int i = lane; i <= kGroup; i += kWave) ghost()[i] = i == 0 ? -N::inf() : N::inf();
+    }
     for (int i = lane; i < 2 * kWave * R * D; i += kWave) pst(0)[i] = V(0);
     {
       Pt e;
@@ -790,6 +859,7 @@ struct Stream {
     id0 = -1; S0 = 0; L0 = 0; g0 = kHinGhost; src0 = 0; win0 = 0;
     id63 = -1; S63 = -kWave; L63 = kWave; hout63 = kHoutSink; flag63 = -1; rel63 = 0; out63 = -1;
     link63 = 0;
+    pre0 = 1; rc63 = 0; ls63 = kWave - 1; cap = V(0);
 
     for (int32_t t0 = 0;; t0 += kGroup)
       if (!step(t0)) break;
@@ -815,6 +885,19 @@ __global__ __launch_bounds__(256) void stream_kernel(KernelArgs a) {
   }
   if (wave >= a.nwaves) return;
   Stream<R, D, V, RINGS> s(a, lane, wib, smem + wib * a.lds_per_wave);
+  s.run(wave);
+}
+
+// Dynamic time warping (OP 1: squared Euclidean cells, 2: Euclidean cells)
+// on the same sweep; its plans never use LDS rings between waves.
+template <int R, int D, typename V, int OP>
+__global__ __launch_bounds__(256) void dtw_kernel(KernelArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int lane = threadIdx.x & (kWave - 1);
+  int wib = threadIdx.x / kWave;
+  int wave = blockIdx.x * (blockDim.x / kWave) + wib;
+  if (wave >= a.nwaves) return;
+  Stream<R, D, V, false, OP> s(a, lane, wib, smem + wib * a.lds_per_wave);
   s.run(wave);
 }
 

@@ -40,6 +40,8 @@ EXPORTS = (
     "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
+    "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
+    "ffd_dtw_cross_i32",
 )
 
 
@@ -99,15 +101,15 @@ def _load():
     lib.ffd_last_error.restype = ctypes.c_char_p
     lib.ffd_version.argtypes = []
     lib.ffd_version.restype = ctypes.c_char_p
-    for name in ("ffd_distance", "ffd_distance_i32"):
+    for name in ("ffd_distance", "ffd_distance_i32", "ffd_dtw_distance", "ffd_dtw_distance_i32"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, i64, vp, i64, i32, i32, vp, vp]
         fn.restype = ctypes.c_int
-    for name in ("ffd_batch", "ffd_batch_i32"):
+    for name in ("ffd_batch", "ffd_batch_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, vp, vp, sz, vp]
         fn.restype = ctypes.c_int
-    for name in ("ffd_cross", "ffd_cross_i32"):
+    for name in ("ffd_cross", "ffd_cross_i32", "ffd_dtw_cross", "ffd_dtw_cross_i32"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, vp, vp, sz, vp]
         fn.restype = ctypes.c_int
@@ -235,28 +237,32 @@ def ffd_last_launch(ctx):
     return info.as_dict()
 
 
-def ffd_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
-    p, pp = _curve(p, torch.float32, "p")
-    q, qp = _curve(q, torch.float32, "q")
+def _pair(fn, dtype, odtype, ctx, p, q, metric, out, stream):
+    p, pp = _curve(p, dtype, "p")
+    q, qp = _curve(q, dtype, "q")
     if p.shape[1] != q.shape[1]:
         raise ValueError("p and q must have the same dimension")
     if out is None:
-        out = torch.empty(1, dtype=torch.float32, device=p.device)
-    _check(lib.ffd_distance(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
-                            _dev_ptr(out, torch.float32, "out"), _stream(stream)), ctx)
+        out = torch.empty(1, dtype=odtype, device=p.device)
+    _check(fn(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
+              _dev_ptr(out, odtype, "out"), _stream(stream)), ctx)
     return out
+
+
+def ffd_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
+    return _pair(lib.ffd_distance, torch.float32, torch.float32, ctx, p, q, metric, out, stream)
 
 
 def ffd_distance_i32(ctx, p, q, metric=FFD_SQEUCLIDEAN, out=None, stream=None):
-    p, pp = _curve(p, torch.int32, "p")
-    q, qp = _curve(q, torch.int32, "q")
-    if p.shape[1] != q.shape[1]:
-        raise ValueError("p and q must have the same dimension")
-    if out is None:
-        out = torch.empty(1, dtype=torch.int64, device=p.device)
-    _check(lib.ffd_distance_i32(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
-                                _dev_ptr(out, torch.int64, "out"), _stream(stream)), ctx)
-    return out
+    return _pair(lib.ffd_distance_i32, torch.int32, torch.int64, ctx, p, q, metric, out, stream)
+
+
+def ffd_dtw_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
+    return _pair(lib.ffd_dtw_distance, torch.float32, torch.float32, ctx, p, q, metric, out, stream)
+
+
+def ffd_dtw_distance_i32(ctx, p, q, metric=FFD_SQEUCLIDEAN, out=None, stream=None):
+    return _pair(lib.ffd_dtw_distance_i32, torch.int32, torch.int64, ctx, p, q, metric, out, stream)
 
 
 def ffd_workspace_size(ctx, op, a_off, b_off, dim):
@@ -304,6 +310,17 @@ def ffd_batch_i32(ctx, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, out=None, wor
                   out, workspace, stream)
 
 
+def ffd_dtw_batch(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, workspace=None, stream=None):
+    return _batch(lib.ffd_dtw_batch, torch.float32, torch.float32, ctx, P, p_off, Q, q_off, metric,
+                  out, workspace, stream)
+
+
+def ffd_dtw_batch_i32(ctx, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
+                      stream=None):
+    return _batch(lib.ffd_dtw_batch_i32, torch.int32, torch.int64, ctx, P, p_off, Q, q_off, metric,
+                  out, workspace, stream)
+
+
 def _cross(fn, dtype, odtype, ctx, Qs, q_off, DB, db_off, metric, out, workspace, stream):
     Qs, Qp = _curve(Qs, dtype, "Qs")
     DB, Dp = _curve(DB, dtype, "DB")
@@ -329,6 +346,18 @@ def ffd_cross(ctx, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, out=None, worksp
 def ffd_cross_i32(ctx, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
                   stream=None):
     return _cross(lib.ffd_cross_i32, torch.int32, torch.int64, ctx, Qs, q_off, DB, db_off, metric,
+                  out, workspace, stream)
+
+
+def ffd_dtw_cross(ctx, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, out=None, workspace=None,
+                  stream=None):
+    return _cross(lib.ffd_dtw_cross, torch.float32, torch.float32, ctx, Qs, q_off, DB, db_off, metric,
+                  out, workspace, stream)
+
+
+def ffd_dtw_cross_i32(ctx, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
+                      stream=None):
+    return _cross(lib.ffd_dtw_cross_i32, torch.int32, torch.int64, ctx, Qs, q_off, DB, db_off, metric,
                   out, workspace, stream)
 
 
@@ -413,6 +442,24 @@ class Context:
 
     def cross_i32(self, Qs, q_off, DB, db_off, **kw):
         return ffd_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
+
+    def dtw_distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_dtw_distance(self.handle, p, q, metric, **kw)
+
+    def dtw_distance_i32(self, p, q, **kw):
+        return ffd_dtw_distance_i32(self.handle, p, q, FFD_SQEUCLIDEAN, **kw)
+
+    def dtw_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_dtw_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
+
+    def dtw_batch_i32(self, P, p_off, Q, q_off, **kw):
+        return ffd_dtw_batch_i32(self.handle, P, p_off, Q, q_off, FFD_SQEUCLIDEAN, **kw)
+
+    def dtw_cross(self, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_dtw_cross(self.handle, Qs, q_off, DB, db_off, metric, **kw)
+
+    def dtw_cross_i32(self, Qs, q_off, DB, db_off, **kw):
+        return ffd_dtw_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
 
     def autotune_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_autotune_batch(self.handle, P, p_off, Q, q_off, metric, **kw)

@@ -57,6 +57,14 @@ def main():
         "euclidean": [float(v) for v in vals],
     }
 
+    # DTW (Appendix B) of squared Euclidean cells on the same pairs
+    dvals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.SQEUCLIDEAN, nthreads, measure="dtw")
+    out["dtw_batched"] = {
+        "workload": "batched(seed=2) as above, DTW with squared Euclidean cells",
+        "sample_index": [int(i) for i in idx],
+        "sqeuclidean": [float(v) for v in dvals],
+    }
+
     Qs, qo, DB, dbo = workloads.cross_int()
     rng = np.random.default_rng(1002)
     ii = rng.integers(0, len(qo) - 1, size=256)

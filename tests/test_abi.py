@@ -133,6 +133,42 @@ def test_workspace_size_and_too_small_workspace(planner):
     assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_CROSS, qo, do, 2) > 0
 
 
+def test_dtw_argument_checks_and_workspace(planner):
+    """The DTW calls take their Frechet counterparts' arguments and checks;
+    ffd_workspace_size covers their plans too."""
+    L = ffd.lib
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, 1, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_distance(planner, None, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 0, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, 7, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_distance(None, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, 1, FAKE, None) == ffd.FFD_E_DEVICE
+    good = np.array([0, 3, 5, 9], dtype=np.int64)
+    empty = np.array([0, 3, 3, 9], dtype=np.int64)
+    assert L.ffd_dtw_batch(planner, FAKE, _i64p(good), FAKE, _i64p(good), 3, 2, 0, FAKE, FAKE, 1 << 20,
+                           None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_batch(planner, FAKE, _i64p(good), FAKE, _i64p(empty), 3, 2, 0, FAKE, FAKE, 1 << 20,
+                           None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_batch_i32(planner, FAKE, _i64p(good), FAKE, _i64p(good), 3, 2, 0, FAKE, FAKE, 1 << 20,
+                               None) == ffd.FFD_E_UNSUPPORTED
+    qo = np.array([0, 4, 9], dtype=np.int64)
+    do = np.array([0, 2, 3, 8], dtype=np.int64)
+    assert L.ffd_dtw_cross(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(do), 3, 2, 1, FAKE, FAKE, 1 << 20,
+                           None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_cross_i32(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(do), 3, 2, 1, FAKE, FAKE, 1 << 20,
+                               None) == ffd.FFD_E_DEVICE
+    # long curves whose boundary rows do not fit LDS need link buffers in both measures
+    P, p_off, Q, q_off = workloads.random_pairs(4, 60, 1, 9000, dim=2)
+    need = ffd.ffd_workspace_size(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2)
+    for fn in (L.ffd_batch, L.ffd_dtw_batch):
+        assert fn(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 60, 2, 0, FAKE, FAKE, need,
+                  None) == ffd.FFD_E_DEVICE
+        assert fn(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 60, 2, 0, FAKE, FAKE, 256,
+                  None) == ffd.FFD_E_NOMEM
+
+
 def test_set_tuning_validation(planner):
     ffd.ffd_set_tuning(planner, 4, 2)
     ffd.ffd_set_tuning(planner, 0, 0)
