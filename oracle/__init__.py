@@ -22,7 +22,8 @@ Contents
 
 Inputs are float32 (widened exactly to FP64 inside) or int32 arrays of shape
 (n, D), row-major.  Metric 0 = Euclidean (sqrt of the sum of squares per
-cell), 1 = squared Euclidean.
+cell), 1 = squared Euclidean, 2 = Manhattan (sum of |p_k - q_k|), 3 =
+Chebyshev (max of |p_k - q_k|); int32 inputs take 1, 2 or 3.
 """
 import ctypes
 import os
@@ -33,6 +34,8 @@ from .build_oracle import LIB as _LIB_PATH, build as _build
 
 EUCLIDEAN = 0
 SQEUCLIDEAN = 1
+MANHATTAN = 2
+CHEBYSHEV = 3
 
 _lib = None
 
@@ -59,23 +62,23 @@ def _load():
         lib.ffdo_rolling_state.restype = ci
         lib.ffdo_rolling_resume.argtypes = [f32p, i64, i64, f32p, i64, ci, ci, f64p, f64p]
         lib.ffdo_rolling_resume.restype = ci
-        lib.ffdo_i32.argtypes = [i32p, i64, i32p, i64, ci, i64p]
+        lib.ffdo_i32.argtypes = [i32p, i64, i32p, i64, ci, ci, i64p]
         lib.ffdo_i32.restype = ci
         lib.ffdo_f32_replica.argtypes = [f32p, i64, f32p, i64, ci, ci, f32p]
         lib.ffdo_f32_replica.restype = ci
         lib.ffdo_pairs.argtypes = [f32p, i64p, i64p, f32p, i64p, i64p, i64, ci, ci, i64p, ci, f64p]
         lib.ffdo_pairs.restype = ci
-        lib.ffdo_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, i64p, ci, i64p]
+        lib.ffdo_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, ci, i64p, ci, i64p]
         lib.ffdo_pairs_i32.restype = ci
         lib.ffdo_dtw.argtypes = [f32p, i64, f32p, i64, ci, ci, f64p]
         lib.ffdo_dtw.restype = ci
-        lib.ffdo_dtw_i32.argtypes = [i32p, i64, i32p, i64, ci, i64p]
+        lib.ffdo_dtw_i32.argtypes = [i32p, i64, i32p, i64, ci, ci, i64p]
         lib.ffdo_dtw_i32.restype = ci
         lib.ffdo_dtw_f32_replica.argtypes = [f32p, i64, f32p, i64, ci, ci, f32p]
         lib.ffdo_dtw_f32_replica.restype = ci
         lib.ffdo_dtw_pairs.argtypes = [f32p, i64p, i64p, f32p, i64p, i64p, i64, ci, ci, i64p, ci, f64p]
         lib.ffdo_dtw_pairs.restype = ci
-        lib.ffdo_dtw_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, i64p, ci, i64p]
+        lib.ffdo_dtw_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, ci, i64p, ci, i64p]
         lib.ffdo_dtw_pairs_i32.restype = ci
         lib.ffdo_now.argtypes = []
         lib.ffdo_now.restype = ctypes.c_double
@@ -167,8 +170,8 @@ def rolling_resume(p, row0, q, row, metric=EUCLIDEAN):
     return out.value
 
 
-def dfd_i32(p, q):
-    """Exact squared-Euclidean discrete Frechet distance of int32 curves (int64)."""
+def dfd_i32(p, q, metric=SQEUCLIDEAN):
+    """Exact discrete Frechet distance of int32 curves (int64); metric 1, 2 or 3."""
     lib = _load()
     p = _curve_i32(p)
     q = _curve_i32(q)
@@ -176,7 +179,7 @@ def dfd_i32(p, q):
         raise ValueError("dimension mismatch")
     out = ctypes.c_int64()
     _check(lib.ffdo_i32(_ptr(p, ctypes.c_int32), p.shape[0], _ptr(q, ctypes.c_int32),
-                        q.shape[0], p.shape[1], ctypes.byref(out)), "i32")
+                        q.shape[0], p.shape[1], int(metric), ctypes.byref(out)), "i32")
     return int(out.value)
 
 
@@ -207,8 +210,8 @@ def dtw(p, q, metric=EUCLIDEAN):
     return out.value
 
 
-def dtw_i32(p, q):
-    """Exact squared-Euclidean DTW of int32 curves (int64)."""
+def dtw_i32(p, q, metric=SQEUCLIDEAN):
+    """Exact DTW of int32 curves (int64); metric 1, 2 or 3."""
     lib = _load()
     p = _curve_i32(p)
     q = _curve_i32(q)
@@ -216,7 +219,7 @@ def dtw_i32(p, q):
         raise ValueError("dimension mismatch")
     out = ctypes.c_int64()
     _check(lib.ffdo_dtw_i32(_ptr(p, ctypes.c_int32), p.shape[0], _ptr(q, ctypes.c_int32),
-                            q.shape[0], p.shape[1], ctypes.byref(out)), "dtw_i32")
+                            q.shape[0], p.shape[1], int(metric), ctypes.byref(out)), "dtw_i32")
     return int(out.value)
 
 
@@ -259,7 +262,8 @@ def dfd_pairs(P, p_start, p_len, Q, q_start, q_len, metric=EUCLIDEAN, nthreads=1
     return out
 
 
-def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None, measure="dfd"):
+def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None, measure="dfd",
+                  metric=SQEUCLIDEAN):
     """Many int32 pairs on a thread pool; returns exact int64 squared distances
     (measure "dfd" or "dtw")."""
     lib = _load()
@@ -276,7 +280,7 @@ def dfd_pairs_i32(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None, 
     _check(fn(_ptr(P, ctypes.c_int32), _ptr(ps, ctypes.c_int64),
               _ptr(pl, ctypes.c_int64), _ptr(Q, ctypes.c_int32),
               _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n, P.shape[1],
-                  ordp, int(nthreads), _ptr(out, ctypes.c_int64)), "pairs_i32")
+              int(metric), ordp, int(nthreads), _ptr(out, ctypes.c_int64)), "pairs_i32")
     return out
 
 
@@ -288,11 +292,11 @@ def dfd_batch(P, p_off, Q, q_off, metric=EUCLIDEAN, nthreads=1, order=None):
                      nthreads, order)
 
 
-def dfd_batch_i32(P, p_off, Q, q_off, nthreads=1, order=None):
+def dfd_batch_i32(P, p_off, Q, q_off, nthreads=1, order=None, metric=SQEUCLIDEAN):
     p_off = _i64(p_off)
     q_off = _i64(q_off)
     return dfd_pairs_i32(P, p_off[:-1], np.diff(p_off), Q, q_off[:-1], np.diff(q_off),
-                         nthreads, order)
+                         nthreads, order, metric=metric)
 
 
 def _cross_index(q_off, db_off, rows=None):
@@ -313,9 +317,9 @@ def dfd_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
     return dfd_pairs(Qs, ps, pl, DB, qs, ql, metric, nthreads).reshape(nr, ndb)
 
 
-def dfd_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None):
+def dfd_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None, metric=SQEUCLIDEAN):
     ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
-    return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads).reshape(nr, ndb)
+    return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads, metric=metric).reshape(nr, ndb)
 
 
 def dtw_batch(P, p_off, Q, q_off, metric=EUCLIDEAN, nthreads=1, order=None):
@@ -325,11 +329,11 @@ def dtw_batch(P, p_off, Q, q_off, metric=EUCLIDEAN, nthreads=1, order=None):
                      nthreads, order, measure="dtw")
 
 
-def dtw_batch_i32(P, p_off, Q, q_off, nthreads=1, order=None):
+def dtw_batch_i32(P, p_off, Q, q_off, nthreads=1, order=None, metric=SQEUCLIDEAN):
     p_off = _i64(p_off)
     q_off = _i64(q_off)
     return dfd_pairs_i32(P, p_off[:-1], np.diff(p_off), Q, q_off[:-1], np.diff(q_off),
-                         nthreads, order, measure="dtw")
+                         nthreads, order, measure="dtw", metric=metric)
 
 
 def dtw_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
@@ -337,9 +341,9 @@ def dtw_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
     return dfd_pairs(Qs, ps, pl, DB, qs, ql, metric, nthreads, measure="dtw").reshape(nr, ndb)
 
 
-def dtw_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None):
+def dtw_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None, metric=SQEUCLIDEAN):
     ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
-    return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads, measure="dtw").reshape(nr, ndb)
+    return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads, measure="dtw", metric=metric).reshape(nr, ndb)
 
 
 def now():

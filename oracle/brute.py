@@ -14,12 +14,15 @@ distances along a coupling instead of the largest one.
 import numpy as np
 
 
-def ground_matrix(p, q, squared=False):
+def ground_matrix(p, q, squared=False, metric=None):
     """d_ij = ||p_i - q_j|| in FP64 from the given coordinates (exact widening).
 
     The sum runs over coordinates in order, one term at a time, which is the
-    same evaluation order as the C oracle.
+    same evaluation order as the C oracle.  metric (overrides `squared`):
+    0 Euclidean, 1 squared Euclidean, 2 Manhattan, 3 Chebyshev.
     """
+    if metric is None:
+        metric = 1 if squared else 0
     p = np.asarray(p, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     if p.ndim == 1:
@@ -29,12 +32,18 @@ def ground_matrix(p, q, squared=False):
     s = np.zeros((p.shape[0], q.shape[0]), dtype=np.float64)
     for k in range(p.shape[1]):
         t = p[:, None, k] - q[None, :, k]
-        s = s + t * t
-    return s if squared else np.sqrt(s)
+        if metric == 2:
+            s = s + np.abs(t)
+        elif metric == 3:
+            s = np.maximum(s, np.abs(t))
+        else:
+            s = s + t * t
+    return np.sqrt(s) if metric == 0 else s
 
 
-def ground_matrix_int(p, q):
-    """Exact int64 squared distances of integer points."""
+def ground_matrix_int(p, q, metric=1):
+    """Exact int64 distances of integer points: 1 squared Euclidean, 2
+    Manhattan, 3 Chebyshev."""
     p = np.asarray(p, dtype=np.int64)
     q = np.asarray(q, dtype=np.int64)
     if p.ndim == 1:
@@ -44,7 +53,12 @@ def ground_matrix_int(p, q):
     s = np.zeros((p.shape[0], q.shape[0]), dtype=np.int64)
     for k in range(p.shape[1]):
         t = p[:, None, k] - q[None, :, k]
-        s = s + t * t
+        if metric == 2:
+            s = s + np.abs(t)
+        elif metric == 3:
+            s = np.maximum(s, np.abs(t))
+        else:
+            s = s + t * t
     return s
 
 
@@ -91,20 +105,20 @@ def brute_dtw_from_matrix(d):
     return best
 
 
-def brute_dtw(p, q, squared=False):
-    return float(brute_dtw_from_matrix(ground_matrix(p, q, squared).tolist()))
+def brute_dtw(p, q, squared=False, metric=None):
+    return float(brute_dtw_from_matrix(ground_matrix(p, q, squared, metric).tolist()))
 
 
-def brute_dtw_int(p, q):
-    return int(brute_dtw_from_matrix(ground_matrix_int(p, q).tolist()))
+def brute_dtw_int(p, q, metric=1):
+    return int(brute_dtw_from_matrix(ground_matrix_int(p, q, metric).tolist()))
 
 
-def brute(p, q, squared=False):
-    return float(brute_from_matrix(ground_matrix(p, q, squared).tolist()))
+def brute(p, q, squared=False, metric=None):
+    return float(brute_from_matrix(ground_matrix(p, q, squared, metric).tolist()))
 
 
-def brute_int(p, q):
-    return int(brute_from_matrix(ground_matrix_int(p, q).tolist()))
+def brute_int(p, q, metric=1):
+    return int(brute_from_matrix(ground_matrix_int(p, q, metric).tolist()))
 
 
 def delannoy(a, b):

@@ -20,8 +20,10 @@
  *
  * Arithmetic: FP64 for float inputs (each float32 coordinate widened
  * exactly); the EUCLIDEAN ground distance is sqrt(sum (p_k - q_k)^2) per
- * cell, SQEUCLIDEAN the plain sum of squares.  Integer inputs use exact
- * int64 squared distances and int64 min/max.  Built without fast-math and
+ * cell, SQEUCLIDEAN the plain sum of squares, MANHATTAN sum |p_k - q_k|,
+ * CHEBYSHEV max_k |p_k - q_k| (Sec. 3: the method assumes nothing about the
+ * ground distance).  Integer inputs use exact int64 distances (squared,
+ * Manhattan or Chebyshev) and int64 min/max.  Built without fast-math and
  * without FP contraction so that every operation is the one written here.
  *
  * A separate "float replica" (ffdo_f32_replica) evaluates the distance with
@@ -50,6 +52,8 @@
 
 #define FFDO_EUCLIDEAN 0
 #define FFDO_SQEUCLIDEAN 1
+#define FFDO_MANHATTAN 2
+#define FFDO_CHEBYSHEV 3
 
 /* ---------------------------------------------------------------- ground distance */
 
@@ -59,18 +63,24 @@ static double cell_f64(const float *pi, const float *qj, int dim, int metric)
     double s = 0.0;
     for (int k = 0; k < dim; ++k) {
         double t = (double)pi[k] - (double)qj[k];
-        s += t * t;
+        if (metric == FFDO_MANHATTAN) s += fabs(t);
+        else if (metric == FFDO_CHEBYSHEV) s = fabs(t) > s ? fabs(t) : s;
+        else s += t * t;
     }
     return metric == FFDO_EUCLIDEAN ? sqrt(s) : s;
 }
 
-/* Exact squared Euclidean distance of integer points. */
-static int64_t cell_i64(const int32_t *pi, const int32_t *qj, int dim)
+/* Exact distance of integer points: squared Euclidean, Manhattan or
+ * Chebyshev. */
+static int64_t cell_i64(const int32_t *pi, const int32_t *qj, int dim, int metric)
 {
     int64_t s = 0;
     for (int k = 0; k < dim; ++k) {
         int64_t t = (int64_t)pi[k] - (int64_t)qj[k];
-        s += t * t;
+        int64_t a = t < 0 ? -t : t;
+        if (metric == FFDO_MANHATTAN) s += a;
+        else if (metric == FFDO_CHEBYSHEV) s = a > s ? a : s;
+        else s += t * t;
     }
     return s;
 }
@@ -85,7 +95,7 @@ static int check_args(const void *p, int64_t n, const void *q, int64_t m, int di
 {
     if (!p || !q || !out) return FFDO_EINVAL;
     if (n < 1 || m < 1 || dim < 1) return FFDO_EINVAL;
-    if (metric != FFDO_EUCLIDEAN && metric != FFDO_SQEUCLIDEAN) return FFDO_EINVAL;
+    if (metric < FFDO_EUCLIDEAN || metric > FFDO_CHEBYSHEV) return FFDO_EINVAL;
     return FFDO_OK;
 }
 
@@ -299,11 +309,11 @@ int ffdo_rolling_resume(const float *p, int64_t row0, int64_t n, const float *q,
 /* ------------------------------------------------------ exact integer version */
 
 static int rolling_i64(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim,
-                       int64_t *out, int64_t *prev, int64_t *cur)
+                       int metric, int64_t *out, int64_t *prev, int64_t *cur)
 {
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j < m; ++j) {
-            int64_t d = cell_i64(p + i * dim, q + j * dim, dim);
+            int64_t d = cell_i64(p + i * dim, q + j * dim, dim, metric);
             int64_t v;
             if (i == 0 && j == 0) v = d;
             else if (i > 0 && j == 0) v = imax(prev[0], d);
@@ -317,14 +327,16 @@ static int rolling_i64(const int32_t *p, int64_t n, const int32_t *q, int64_t m,
     return FFDO_OK;
 }
 
-/* Squared-Euclidean discrete Frechet distance of int32 curves, exact int64. */
-int ffdo_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int64_t *out)
+/* Discrete Frechet distance of int32 curves, exact int64; metric is
+ * SQEUCLIDEAN, MANHATTAN or CHEBYSHEV. */
+int ffdo_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int metric, int64_t *out)
 {
-    int rc = check_args(p, n, q, m, dim, FFDO_SQEUCLIDEAN, out);
+    int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
+    if (metric == FFDO_EUCLIDEAN) return FFDO_EINVAL;
     int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
     if (!buf) return FFDO_ENOMEM;
-    rc = rolling_i64(p, n, q, m, dim, out, buf, buf + m);
+    rc = rolling_i64(p, n, q, m, dim, metric, out, buf, buf + m);
     free(buf);
     return rc;
 }
@@ -353,11 +365,11 @@ static int dtw_rolling_f64(const float *p, int64_t n, const float *q, int64_t m,
 }
 
 static int dtw_rolling_i64(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim,
-                           int64_t *out, int64_t *prev, int64_t *cur)
+                           int metric, int64_t *out, int64_t *prev, int64_t *cur)
 {
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j < m; ++j) {
-            int64_t d = cell_i64(p + i * dim, q + j * dim, dim);
+            int64_t d = cell_i64(p + i * dim, q + j * dim, dim, metric);
             int64_t v;
             if (i == 0 && j == 0) v = d;
             else if (i > 0 && j == 0) v = prev[0] + d;
@@ -384,15 +396,16 @@ int ffdo_dtw(const float *p, int64_t n, const float *q, int64_t m, int dim, int 
     return rc;
 }
 
-/* Squared-Euclidean DTW of int32 curves, exact int64 (the caller keeps the
- * sums below 2^63). */
-int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int64_t *out)
+/* DTW of int32 curves, exact int64 (the caller keeps the sums below
+ * 2^63); metric is SQEUCLIDEAN, MANHATTAN or CHEBYSHEV. */
+int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int metric, int64_t *out)
 {
-    int rc = check_args(p, n, q, m, dim, FFDO_SQEUCLIDEAN, out);
+    int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
+    if (metric == FFDO_EUCLIDEAN) return FFDO_EINVAL;
     int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
     if (!buf) return FFDO_ENOMEM;
-    rc = dtw_rolling_i64(p, n, q, m, dim, out, buf, buf + m);
+    rc = dtw_rolling_i64(p, n, q, m, dim, metric, out, buf, buf + m);
     free(buf);
     return rc;
 }
@@ -404,9 +417,18 @@ int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int d
  * EUCLIDEAN one correctly rounded square root of the selected d2 at the end
  * (min and max commute with the monotone square root).  Used only to check
  * that a float32 implementation of that order selects the same cell. */
-static float cell_f32_replica(const float *pi, const float *qj, int dim)
+static float cell_f32_replica(const float *pi, const float *qj, int dim, int metric)
 {
     float dx = pi[0] - qj[0];
+    if (metric == FFDO_MANHATTAN || metric == FFDO_CHEBYSHEV) {
+        /* s = |dx|, then s = s + |dk| (Manhattan) or max(s, |dk|) */
+        float a = fabsf(dx);
+        for (int k = 1; k < dim; ++k) {
+            float t = fabsf(pi[k] - qj[k]);
+            a = metric == FFDO_MANHATTAN ? a + t : fmaxf(a, t);
+        }
+        return a;
+    }
     float s = dx * dx;
     for (int k = 1; k < dim; ++k) {
         float t = pi[k] - qj[k];
@@ -425,7 +447,7 @@ int ffdo_f32_replica(const float *p, int64_t n, const float *q, int64_t m, int d
     float *prev = buf, *cur = buf + m;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j < m; ++j) {
-            float d = cell_f32_replica(p + i * dim, q + j * dim, dim);
+            float d = cell_f32_replica(p + i * dim, q + j * dim, dim, metric);
             float v;
             if (i == 0 && j == 0) v = d;
             else if (i > 0 && j == 0) v = fmaxf(prev[0], d);
@@ -456,7 +478,7 @@ int ffdo_dtw_f32_replica(const float *p, int64_t n, const float *q, int64_t m, i
     float *prev = buf, *cur = buf + m;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j < m; ++j) {
-            float d = cell_f32_replica(p + i * dim, q + j * dim, dim);
+            float d = cell_f32_replica(p + i * dim, q + j * dim, dim, metric);
             if (metric == FFDO_EUCLIDEAN) d = sqrtf(d);
             float v;
             if (i == 0 && j == 0) v = d;
@@ -518,7 +540,7 @@ static void *pool_worker(void *arg)
             int64_t *b = (int64_t *)buf;
             (c->dtw ? dtw_rolling_i64 : rolling_i64)(P + c->p_start[k] * c->dim, n,
                                                      Q + c->q_start[k] * c->dim, m, c->dim,
-                                                     (int64_t *)c->out + k, b, b + m);
+                                                     c->metric, (int64_t *)c->out + k, b, b + m);
         } else {
             const float *P = (const float *)c->P, *Q = (const float *)c->Q;
             double *b = (double *)buf;
@@ -563,7 +585,7 @@ static int pairs_f32(const float *P, const int64_t *p_start, const int64_t *p_le
 {
     int rc = pool_args(P, Q, p_start, p_len, q_start, q_len, npairs, dim, out);
     if (rc) return rc;
-    if (metric != FFDO_EUCLIDEAN && metric != FFDO_SQEUCLIDEAN) return FFDO_EINVAL;
+    if (metric < FFDO_EUCLIDEAN || metric > FFDO_CHEBYSHEV) return FFDO_EINVAL;
     struct pool_ctx c;
     memset(&c, 0, sizeof c);
     c.P = P; c.Q = Q; c.p_start = p_start; c.p_len = p_len; c.q_start = q_start;
@@ -574,16 +596,17 @@ static int pairs_f32(const float *P, const int64_t *p_start, const int64_t *p_le
 
 static int pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
                      const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
-                     int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out,
-                     int dtw)
+                     int64_t npairs, int dim, int metric, const int64_t *order, int nthreads,
+                     int64_t *out, int dtw)
 {
     int rc = pool_args(P, Q, p_start, p_len, q_start, q_len, npairs, dim, out);
     if (rc) return rc;
+    if (metric < FFDO_SQEUCLIDEAN || metric > FFDO_CHEBYSHEV) return FFDO_EINVAL;
     struct pool_ctx c;
     memset(&c, 0, sizeof c);
     c.P = P; c.Q = Q; c.p_start = p_start; c.p_len = p_len; c.q_start = q_start;
     c.q_len = q_len; c.order = order; c.npairs = npairs; c.dim = dim;
-    c.metric = FFDO_SQEUCLIDEAN; c.is_int = 1; c.dtw = dtw; c.out = out;
+    c.metric = metric; c.is_int = 1; c.dtw = dtw; c.out = out;
     return run_pool(&c, nthreads);
 }
 
@@ -597,9 +620,10 @@ int ffdo_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, con
 
 int ffdo_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
                    const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
-                   int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+                   int64_t npairs, int dim, int metric, const int64_t *order, int nthreads,
+                   int64_t *out)
 {
-    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, order, nthreads, out, 0);
+    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, metric, order, nthreads, out, 0);
 }
 
 int ffdo_dtw_pairs(const float *P, const int64_t *p_start, const int64_t *p_len, const float *Q,
@@ -612,9 +636,10 @@ int ffdo_dtw_pairs(const float *P, const int64_t *p_start, const int64_t *p_len,
 
 int ffdo_dtw_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
                        const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
-                       int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+                       int64_t npairs, int dim, int metric, const int64_t *order, int nthreads,
+                       int64_t *out)
 {
-    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, order, nthreads, out, 1);
+    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, metric, order, nthreads, out, 1);
 }
 
 /* Seconds on the monotonic clock, for the CPU-baseline timer. */
