@@ -37,11 +37,19 @@ TOL = 2e-6
 PEAK_VALU = 256 * 4 * 16 * 2.4e9
 
 
-def imin(dim, exact=False):
+def imin(dim, exact=False, cell="euclidean"):
     """Algorithmic VALU lane-ops per cell without packed FP32: D subtractions,
     one multiply and D-1 FMAs for the squared distance, then the selection:
-    min3 and max in FP32; FP64 has no three-input min, so two mins and a max."""
-    return 2 * dim + (3 if exact else 2)
+    min3 and max in FP32; FP64 has no three-input min, so two mins and a max.
+    Manhattan cells: D subtractions and D-1 additions (absolute values are
+    free source modifiers); Chebyshev: D subtractions and ceil((D-1)/2)
+    three-input maxima.  DTW replaces the max by an add (same count)."""
+    sel = 3 if exact else 2
+    if cell == "manhattan":
+        return 2 * dim - 1 + sel
+    if cell == "chebyshev":
+        return dim + dim // 2 + sel
+    return 2 * dim + sel
 
 
 def time_steps(step, steps, sync):
@@ -89,8 +97,8 @@ def profiled_traffic(profile):
     return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
 
 
-def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel", suffix=""):
-    ops = cells * imin(dim, exact)
+def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel", suffix="", cell="euclidean"):
+    ops = cells * imin(dim, exact, cell)
     achieved = ops / (kms / 1e3)
     vt = "double" if exact else "float"
     return {
@@ -98,7 +106,7 @@ def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel",
         "unit": "TVALUop/s", "frac": achieved / PEAK_VALU,
         "traffic": profiled_traffic(profile) if profile else None,
         "kernel": f"ffd::{family}<{info['rows_per_lane']}, {dim}, {vt}{suffix}>", "kernel_ms": kms,
-        "launch": info, "ops_per_cell": imin(dim, exact), "cells_per_launch": cells,
+        "launch": info, "ops_per_cell": imin(dim, exact, cell), "cells_per_launch": cells,
     }
 
 
@@ -123,13 +131,15 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     out = torch.empty(npairs, dtype=torch.float32, device=dev)
+    metric = {"euclidean": ffd.FFD_EUCLIDEAN, "manhattan": ffd.FFD_MANHATTAN,
+              "chebyshev": ffd.FFD_CHEBYSHEV}[args.metric]
 
     def step():
-        ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+        ctx.batch(Pd, p_off, Qd, q_off, metric=metric, out=out, workspace=ws, stream=stream)
 
     tuning = None
     if args.autotune:
-        tuning = ctx.autotune_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+        tuning = ctx.autotune_batch(Pd, p_off, Qd, q_off, metric=metric, out=out, workspace=ws, stream=stream)
     for _ in range(args.warmup):
         step()
     if args.copy_probe:
@@ -142,14 +152,14 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     kms = kernel_ms(torch, step, args.steps, stream)
     info = ctx.last_launch()
     errs = ctx.last_errors()
-    g = golden()["batched"]
+    g = golden()["batched" if args.metric == "euclidean" else "batched_" + args.metric]
     res = out.cpu().numpy()
     idx = np.array(g["sample_index"])
-    want = np.array(g["euclidean"])
+    want = np.array(g[args.metric])
     parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
 
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and args.metric == "euclidean":
         pp = [(Pd[p_off[k]:p_off[k + 1]], Qd[q_off[k]:q_off[k + 1]]) for k in range(npairs)]
         outs = torch.empty(npairs, dtype=torch.float32, device=dev)
         for k in range(8):
@@ -174,7 +184,7 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
         qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
         order = np.argsort(-(pl * ql))
         t2 = time.perf_counter()
-        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.EUCLIDEAN, cores, order)
+        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, metric, cores, order)
         cw = time.perf_counter() - t2
         agree = bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))
         cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
@@ -184,11 +194,14 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     return {
         "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
         "config": {"workload": "batched: 4096 pairs, n and m uniform in [64, 2048], 2-D float32 "
-                               "random walks, q = p resampled + N(0, 0.1^2), Euclidean (seed 2)",
+                               f"random walks, q = p resampled + N(0, 0.1^2), {args.metric.capitalize()} (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": errs},
         "autotune": tuning,
-        "roofline": roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md"),
+        "roofline": (roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md")
+                     if args.metric == "euclidean" else
+                     roofline(info, cells, kms, dim, False, family="op_kernel",
+                              suffix=", 4" if args.metric == "manhattan" else ", 6", cell=args.metric)),
         "plain": plain, "cpu_baseline": cpu,
     }
 
@@ -249,7 +262,7 @@ def run_dtw(args, torch, ffd, ctx, dev, stream):
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": "(n + m + D + 2) 2^-24 relative", "sampled_ok": parity_ok,
                    "launch_error_flags": errs},
-        "roofline": roofline(info, cells, kms, dim, False, family="dtw_kernel", suffix=", 1"),
+        "roofline": roofline(info, cells, kms, dim, False, family="op_kernel", suffix=", 1"),
         "cpu_baseline": cpu,
     }
 
@@ -479,6 +492,8 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU oracle sample (cross)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--metric", choices=["euclidean", "manhattan", "chebyshev"], default="euclidean",
+                    help="ground distance of the batched workload")
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",

@@ -33,10 +33,11 @@
  *  - Preconditions (documented, not checked): coordinates are finite; float
  *    coordinates satisfy |x| < 1e18 so that squares do not overflow; int32
  *    coordinates satisfy |x| < 2^24 so that every intermediate is exact.
- *  - Float32 results agree with the exact real-number result to a relative
- *    error of 2e-6 (each d_ij is evaluated in float32 in a fixed order; the
- *    recurrence only selects values; the square root is taken once per pair
- *    and correctly rounded).  Int32 results are exact.
+ *  - Float32 results of the Frechet calls agree with the exact real-number
+ *    result to a relative error of 2e-6 (each d_ij is evaluated in float32
+ *    in a fixed order, with at most 2 D - 1 roundings; the recurrence only
+ *    selects values; for FFD_EUCLIDEAN the square root is taken once per
+ *    pair and correctly rounded).  Int32 results are exact.
  *  - A context may be used by one host thread at a time.
  *  - Graph capture: ffd_distance, ffd_batch and ffd_cross (and their int32
  *    forms) may be recorded into a hipGraph by stream capture once the same
@@ -69,9 +70,13 @@ extern "C" {
 #define FFD_E_BUSY (-5)        /* serving: no free slot right now                   */
 #define FFD_E_TIMEOUT (-6)     /* serving: wait timed out                           */
 
-/* Ground distances (Sec. 2: f(p_i, q_j)). */
+/* Ground distances (Sec. 2: f(p_i, q_j); Sec. 3: the method makes no
+ * assumption about it).  int32 calls take every metric but FFD_EUCLIDEAN;
+ * the serving calls take FFD_EUCLIDEAN and FFD_SQEUCLIDEAN. */
 #define FFD_EUCLIDEAN 0   /* ||p_i - q_j||_2                          */
-#define FFD_SQEUCLIDEAN 1 /* ||p_i - q_j||_2^2 (the only int metric)  */
+#define FFD_SQEUCLIDEAN 1 /* ||p_i - q_j||_2^2                        */
+#define FFD_MANHATTAN 2   /* sum_k |p_ik - q_jk|                      */
+#define FFD_CHEBYSHEV 3   /* max_k |p_ik - q_jk|                      */
 
 /* Largest supported dimension D. */
 #define FFD_MAX_DIM 4
@@ -115,8 +120,8 @@ const char *ffd_version(void);
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
                  int32_t dim, int32_t metric, float *out, void *stream);
 
-/* One pair with int32 coordinates and the squared Euclidean distance, exact:
- *   out [1] int64, device.  metric must be FFD_SQEUCLIDEAN (else
+/* One pair with int32 coordinates, exact: out [1] int64, device.  metric is
+ *   FFD_SQEUCLIDEAN, FFD_MANHATTAN or FFD_CHEBYSHEV (FFD_EUCLIDEAN:
  *   FFD_E_UNSUPPORTED).  Other errors as ffd_distance. */
 int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m,
                      int32_t dim, int32_t metric, int64_t *out, void *stream);
@@ -136,7 +141,8 @@ int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q
               const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, float *out,
               void *workspace, size_t ws_bytes, void *stream);
 
-/* Int32 version of ffd_batch: squared Euclidean, exact int64 out[npairs]. */
+/* Int32 version of ffd_batch: exact int64 out[npairs]; metrics as
+ * ffd_distance_i32. */
 int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
                   const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric,
                   int64_t *out, void *workspace, size_t ws_bytes, void *stream);
@@ -150,7 +156,8 @@ int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq,
               const float *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
               int32_t metric, float *out, void *workspace, size_t ws_bytes, void *stream);
 
-/* Int32 version of ffd_cross: squared Euclidean, exact int64 out[nq * ndb]. */
+/* Int32 version of ffd_cross: exact int64 out[nq * ndb]; metrics as
+ * ffd_distance_i32. */
 int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq,
                   const int32_t *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
                   int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
@@ -164,12 +171,13 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
  * and their int32 forms) with the same layouts, ownership, workspace sizes
  * (ffd_workspace_size covers both) and errors.  The ground distance is
  * summed per cell, so FFD_EUCLIDEAN takes the hardware float32 square root
- * (within 1 ulp) in every cell and FFD_SQEUCLIDEAN sums squared distances;
- * the result is the sum itself.  Float32 results agree with the exact
- * result to a relative error of (n + m + D + 3) 2^-24 (each cell carries at
- * most D + 3 rounding errors, the sum along the selected coupling one per
- * addition), for cells whose squared distance is not below 2^-126.  Int32
- * calls (squared Euclidean only) are exact while the sums stay below 2^53
+ * (within 1 ulp) in every cell, FFD_SQEUCLIDEAN sums squared distances and
+ * FFD_MANHATTAN / FFD_CHEBYSHEV their cell distances; the result is the sum
+ * itself.  Float32 results agree with the exact result to a relative error
+ * of (n + m + 2 D + 2) 2^-24 (each cell carries at most 2 D + 1 rounding
+ * errors, the sum along the selected coupling one per addition), for
+ * Euclidean cells whose squared distance is not below 2^-126.  Int32 calls
+ * (every metric but FFD_EUCLIDEAN) are exact while the sums stay below 2^53
  * (for example |x| < 2^15 and n + m < 2^19). */
 int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
                      int32_t dim, int32_t metric, float *out, void *stream);

@@ -24,13 +24,19 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["ffd_kernels.hip", "ffd_kernels_rings.hip", "ffd_kernels_dtw.hip", "ffd_kernels_dtw_euc.hip",
-           "ffd_host.cpp", "ffd_server.cpp"]
+# (source, preprocessor definitions): ffd_kernels_op.hip is compiled once
+# per measure / ground distance (OP = measure + 2 * cell)
+SOURCES = [("ffd_kernels.hip", {}), ("ffd_kernels_rings.hip", {})] + \
+          [("ffd_kernels_op.hip", {"FFD_OP": op}) for op in (1, 3, 4, 5, 6, 7)] + \
+          [("ffd_host.cpp", {}), ("ffd_server.cpp", {})]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item):
+    src, defs = item
+    tag = "".join(f"_{k}{v}" for k, v in defs.items())
+    obj = os.path.join(BUILD, src + tag + ".o")
+    cmd = [HIPCC] + COMMON + [f"-D{k}={v}" for k, v in defs.items()] + \
+        ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -40,7 +46,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
+    with ThreadPoolExecutor(min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

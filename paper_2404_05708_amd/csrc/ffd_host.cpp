@@ -59,10 +59,14 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // measured lone waves (one per SIMD; 3-D single pairs at R = 2, 4, 8 and the
 // 2-D batch at R = 8): about 104 + 3.9 I clocks.  Waves sharing a SIMD also
 // share its wave64 issue slots (4 clocks each), which they keep about three
-// quarters busy.  DTW with Euclidean cells (measure 2) adds a square root
-// per cell, a quarter-rate instruction (4 issue slots).
-double step_clocks(int R, int D, bool exact, double waves_per_simd, int measure = 0) {
-  double I = (double)R * (2 * D + (exact ? 3 : 2) + (measure == 2 ? 4 : 0)) + 8.0;
+// quarters busy.  Other kernels (op = measure + 2 * cell): Euclidean cells
+// add a square root per cell, a quarter-rate instruction (4 issue slots);
+// Manhattan and Chebyshev cells take D subtractions and D - 1 additions or
+// maxima with free absolute values, one instruction less.
+double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
+  int cell = op >> 1;
+  double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell >= 2 ? 1 : 0);
+  double I = (double)R * per_cell + 8.0;
   double lone = 104.0 + 3.9 * I;
   double shared = 0.75 * std::max(1.0, waves_per_simd) * I * 4.0;
   return std::max(lone, shared);
@@ -98,15 +102,15 @@ int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *n
 int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   if (!ctx) return FFD_E_INVALID;
   if (dim < 1) return fail(ctx, FFD_E_INVALID, "dim must be >= 1");
-  if (metric != FFD_EUCLIDEAN && metric != FFD_SQEUCLIDEAN) return fail(ctx, FFD_E_INVALID, "unknown metric");
+  if (metric < FFD_EUCLIDEAN || metric > FFD_CHEBYSHEV) return fail(ctx, FFD_E_INVALID, "unknown metric");
   if (dim > FFD_MAX_DIM) return fail(ctx, FFD_E_UNSUPPORTED, "dim exceeds FFD_MAX_DIM");
-  if (exact && metric != FFD_SQEUCLIDEAN)
-    return fail(ctx, FFD_E_UNSUPPORTED, "int32 coordinates support the squared Euclidean metric only");
+  if (exact && metric == FFD_EUCLIDEAN)
+    return fail(ctx, FFD_E_UNSUPPORTED, "int32 coordinates take the squared Euclidean, Manhattan or Chebyshev metric");
   return FFD_OK;
 }
 
 int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings, int measure) {
-  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, measure != 0).total;
+  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, (measure & 1) != 0).total;
 }
 
 const int kRs[4] = {1, 2, 4, 8};
@@ -1108,19 +1112,33 @@ int ffd_set_split(ffd_ctx *ctx, float share) {
   return FFD_OK;
 }
 
+// Kernel op of a call: measure (0 Frechet, 1 DTW) + 2 * cell, where the
+// cell is 0 squared Euclidean (the Frechet kernel also serves Euclidean: one
+// root per pair), 1 Euclidean per cell (DTW), 2 Manhattan, 3 Chebyshev.
+static int op_of(bool dtw, int32_t metric) {
+  int cell = metric == FFD_MANHATTAN ? 2 : metric == FFD_CHEBYSHEV ? 3 : (dtw && metric == FFD_EUCLIDEAN ? 1 : 0);
+  return (dtw ? 1 : 0) + 2 * cell;
+}
+
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim, int32_t metric,
                  float *out, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
 }
 
 int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
                      int32_t metric, int64_t *out, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, true);
 }
 
 int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
               int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
               void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
                       false);
 }
@@ -1128,6 +1146,8 @@ int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q
 int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
                   int64_t npairs, int32_t dim, int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
                   void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
                       true);
 }
@@ -1135,6 +1155,8 @@ int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const in
 int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, const float *DB,
               const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out, void *workspace,
               size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
                       (hipStream_t)stream, false);
 }
@@ -1142,25 +1164,25 @@ int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, c
 int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
                   const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int64_t *out, void *workspace,
                   size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, op_of(false, metric));
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
                       (hipStream_t)stream, true);
 }
 
-// Dynamic time warping (Appendix B): the same calls with measure 1 (squared
-// Euclidean cells, also every int32 call) or 2 (Euclidean cells).
-static int dtw_measure(int32_t metric, bool exact) { return exact || metric == FFD_SQEUCLIDEAN ? 1 : 2; }
+// Dynamic time warping (Appendix B): the same calls with the DTW kernels.
 
 int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim,
                      int32_t metric, float *out, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, false));
+  MeasureScope scope(ctx, op_of(true, metric));
   return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
 }
 
 int ffd_dtw_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
                          int32_t metric, int64_t *out, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, true));
+  MeasureScope scope(ctx, op_of(true, metric));
   return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, true);
 }
 
@@ -1168,7 +1190,7 @@ int ffd_dtw_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const floa
                   int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
                   void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, false));
+  MeasureScope scope(ctx, op_of(true, metric));
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
                       false);
 }
@@ -1177,7 +1199,7 @@ int ffd_dtw_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, cons
                       int64_t npairs, int32_t dim, int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
                       void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, true));
+  MeasureScope scope(ctx, op_of(true, metric));
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
                       true);
 }
@@ -1186,7 +1208,7 @@ int ffd_dtw_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t n
                   const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out, void *workspace,
                   size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, false));
+  MeasureScope scope(ctx, op_of(true, metric));
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
                       (hipStream_t)stream, false);
 }
@@ -1195,7 +1217,7 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
                       const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int64_t *out, void *workspace,
                       size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, dtw_measure(metric, true));
+  MeasureScope scope(ctx, op_of(true, metric));
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
                       (hipStream_t)stream, true);
 }
@@ -1213,11 +1235,12 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   int rc;
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
-  // one size for every path: float and int32 coordinates, Frechet and DTW
+  // one size for every path: float and int32 coordinates, every measure and
+  // ground distance (kernel ops 0, 1, 3, ..., 7)
   size_t worst = 0;
-  for (int ms = 0; ms < 3; ++ms)
+  for (int ms = 0; ms < 8; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
-      if (ms == 2 && ex == 1) continue;  // int32 DTW has squared cells only
+      if (ms == 2 || (ms == 3 && ex == 1)) continue;  // no such kernel
       MeasureScope scope(ctx, ms);
       const Plan *pl;
       uint64_t key;

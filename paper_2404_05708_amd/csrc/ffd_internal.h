@@ -17,29 +17,51 @@ hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, in
 hipError_t launch_stream_rings(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
 hipError_t occupancy_stream_plain(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 hipError_t occupancy_stream_rings(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
-hipError_t launch_dtw_sq(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
-hipError_t launch_dtw_euc(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
-hipError_t occupancy_dtw_sq(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
-hipError_t occupancy_dtw_euc(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+#define FFD_DECLARE_OP(n)                                                                                   \
+  hipError_t launch_op_##n(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st); \
+  hipError_t occupancy_op_##n(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+FFD_DECLARE_OP(1)
+FFD_DECLARE_OP(3)
+FFD_DECLARE_OP(4)
+FFD_DECLARE_OP(5)
+FFD_DECLARE_OP(6)
+FFD_DECLARE_OP(7)
+#undef FFD_DECLARE_OP
 hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 
 // The kernel variant with LDS rings between waves serves launches whose
 // plan uses them (a.rings); every other launch takes the plain variant.
-// `measure`: 0 discrete Frechet distance, 1 DTW of squared Euclidean cells,
-// 2 DTW of Euclidean cells (DTW plans never use rings).
+// `op` = measure + 2 * cell (measure 0 Frechet, 1 DTW; cell 0 squared
+// Euclidean, 1 Euclidean per cell, 2 Manhattan, 3 Chebyshev).  Op 0 is the
+// Frechet kernel on squared cells (with or without LDS rings); every other
+// op has its own kernel family and never uses rings.
 inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
-                                int measure = 0) {
-  if (measure == 1) return launch_dtw_sq(exact, R, D, a, wpb, coop, st);
-  if (measure == 2) return launch_dtw_euc(exact, R, D, a, wpb, coop, st);
-  return a.rings ? launch_stream_rings(exact, R, D, a, wpb, coop, st)
-                 : launch_stream_plain(exact, R, D, a, wpb, coop, st);
+                                int op = 0) {
+  switch (op) {
+    case 0: return a.rings ? launch_stream_rings(exact, R, D, a, wpb, coop, st)
+                           : launch_stream_plain(exact, R, D, a, wpb, coop, st);
+    case 1: return launch_op_1(exact, R, D, a, wpb, coop, st);
+    case 3: return launch_op_3(exact, R, D, a, wpb, coop, st);
+    case 4: return launch_op_4(exact, R, D, a, wpb, coop, st);
+    case 5: return launch_op_5(exact, R, D, a, wpb, coop, st);
+    case 6: return launch_op_6(exact, R, D, a, wpb, coop, st);
+    case 7: return launch_op_7(exact, R, D, a, wpb, coop, st);
+  }
+  return hipErrorInvalidValue;
 }
 inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu,
-                                   bool rings = false, int measure = 0) {
-  if (measure == 1) return occupancy_dtw_sq(exact, R, D, wpb, lds, blocks_per_cu);
-  if (measure == 2) return occupancy_dtw_euc(exact, R, D, wpb, lds, blocks_per_cu);
-  return rings ? occupancy_stream_rings(exact, R, D, wpb, lds, blocks_per_cu)
-               : occupancy_stream_plain(exact, R, D, wpb, lds, blocks_per_cu);
+                                   bool rings = false, int op = 0) {
+  switch (op) {
+    case 0: return rings ? occupancy_stream_rings(exact, R, D, wpb, lds, blocks_per_cu)
+                         : occupancy_stream_plain(exact, R, D, wpb, lds, blocks_per_cu);
+    case 1: return occupancy_op_1(exact, R, D, wpb, lds, blocks_per_cu);
+    case 3: return occupancy_op_3(exact, R, D, wpb, lds, blocks_per_cu);
+    case 4: return occupancy_op_4(exact, R, D, wpb, lds, blocks_per_cu);
+    case 5: return occupancy_op_5(exact, R, D, wpb, lds, blocks_per_cu);
+    case 6: return occupancy_op_6(exact, R, D, wpb, lds, blocks_per_cu);
+    case 7: return occupancy_op_7(exact, R, D, wpb, lds, blocks_per_cu);
+  }
+  return hipErrorInvalidValue;
 }
 }  // namespace ffd
 
@@ -81,7 +103,7 @@ struct ffd_ctx {
   int tune_R = 0;
   int tune_W = 0;
   float split = 0.f;          // 0 auto, < 0 split only when needed, > 0 split above this share
-  int measure = 0;            // of the call in progress: 0 Frechet, 1 DTW squared, 2 DTW Euclidean
+  int measure = 0;            // kernel op of the call in progress (measure + 2 * cell, see launch_stream)
   uint32_t epoch = 0;
   std::string last_error;
   // plan most recently written to a workspace (skip the upload if unchanged)

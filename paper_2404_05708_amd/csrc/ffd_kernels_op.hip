@@ -1,0 +1,36 @@
+// Kernels of one measure / ground distance (OP = measure + 2 * cell, see
+// ffd_stream.h) other than the Frechet distance on squared Euclidean cells.
+// This unit is compiled once per OP (-DFFD_OP=...), in parallel: 1 DTW of
+// squared Euclidean cells, 3 DTW of Euclidean cells (float32 only), 4
+// Frechet on Manhattan cells, 5 DTW on Manhattan cells, 6 Frechet on
+// Chebyshev cells, 7 DTW on Chebyshev cells.
+#include "ffd_launch.h"
+
+#ifndef FFD_OP
+#error "compile with -DFFD_OP=<op>"
+#endif
+
+#define FFD_CAT2(a, b) a##b
+#define FFD_CAT(a, b) FFD_CAT2(a, b)
+
+namespace ffd {
+
+namespace {
+struct OpSel {
+  // int32 coordinates (exact FP64 values) for every op but Euclidean cells
+  static constexpr bool kExact = FFD_OP != 3;
+  template <int R, int D, typename V>
+  static auto kernel() { return &op_kernel<R, D, V, FFD_OP>; }
+};
+}  // namespace
+
+hipError_t FFD_CAT(launch_op_, FFD_OP)(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop,
+                                       hipStream_t st) {
+  return Launcher<OpSel>::launch(exact, R, D, a, wpb, coop, st);
+}
+
+hipError_t FFD_CAT(occupancy_op_, FFD_OP)(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu) {
+  return Launcher<OpSel>::occupancy(exact, R, D, wpb, lds, blocks_per_cu);
+}
+
+}  // namespace ffd

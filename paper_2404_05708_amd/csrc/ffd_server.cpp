@@ -569,6 +569,8 @@ int ffd_server_submit(ffd_server *s, const float *q, int64_t n, int32_t metric, 
   if (!s || !q || !out || !ticket) return FFD_E_INVALID;
   if (n < 1) return sfail(s, FFD_E_INVALID, "query must have at least one point");
   if (n > s->max_query) return sfail(s, FFD_E_UNSUPPORTED, "query longer than the server's max_query");
+  if (metric == FFD_MANHATTAN || metric == FFD_CHEBYSHEV)
+    return sfail(s, FFD_E_UNSUPPORTED, "serving takes the Euclidean and squared Euclidean metrics");
   if (metric != FFD_EUCLIDEAN && metric != FFD_SQEUCLIDEAN) return sfail(s, FFD_E_INVALID, "unknown metric");
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return FFD_E_NOMEM;

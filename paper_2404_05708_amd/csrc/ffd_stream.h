@@ -27,10 +27,14 @@
 //    end repeat its last column point: repeating points does not change the
 //    distance (Sec. 4, footnote), so padding is exact.
 //
-// Dynamic time warping (Appendix B, Algorithm B.1) runs on the same sweep with
-// the outer max replaced by a sum, M_ij = min{...} + d_ij (OP = 1: squared
-// Euclidean cells, OP = 2: Euclidean cells, the hardware square root per
-// cell).  Sums are not selections, so padding is no longer exact: a DTW
+// Other ground distances (Sec. 3: the method assumes nothing about it) and
+// dynamic time warping (Appendix B, Algorithm B.1: the outer max replaced by
+// a sum, M_ij = min{...} + d_ij) run on the same sweep; the template
+// argument OP = measure + 2 * cell selects them: measure 0 Frechet, 1 DTW;
+// cell 0 squared Euclidean, 1 Euclidean (the hardware square root per cell,
+// DTW only: the Frechet kernel takes one root per pair), 2 Manhattan
+// (sum of |dk|), 3 Chebyshev (max of |dk|).  Sums are not selections, so
+// padding is no longer exact: a DTW
 // task puts its separator columns first and its m real columns last (the
 // top-boundary corner, 0 for DTW, sits at the last separator), and the
 // result M_{n-1,m-1} is taken from the lane holding row n-1 at the moment
@@ -63,6 +67,7 @@ struct Num<float> {
   __device__ static __forceinline__ float mn(float a, float b) { return __builtin_fminf(a, b); }
   __device__ static __forceinline__ float mx(float a, float b) { return __builtin_fmaxf(a, b); }
   __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+  __device__ static __forceinline__ float abs(float a) { return __builtin_fabsf(a); }
   // Lane l receives src of lane l-1; lane 0 keeps `old`.
   __device__ static __forceinline__ float shift_in(float old, float src) {
     int r = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, src),
@@ -89,6 +94,7 @@ struct Num<double> {
   __device__ static __forceinline__ double mn(double a, double b) { return __builtin_fmin(a, b); }
   __device__ static __forceinline__ double mx(double a, double b) { return __builtin_fmax(a, b); }
   __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+  __device__ static __forceinline__ double abs(double a) { return __builtin_fabs(a); }
   __device__ static __forceinline__ double shift_in(double old, double src) {
     uint64_t o = __builtin_bit_cast(uint64_t, old), s = __builtin_bit_cast(uint64_t, src);
     int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)s, 0x138, 0xf, 0xf, false);
@@ -141,11 +147,12 @@ constexpr int kSpinLimit = 1 << 22;
 // s_waitcnt operand (gfx9 encoding) that waits for vmcnt = 0 only.
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-// OP: 0 discrete Frechet distance, 1 DTW of squared Euclidean cells, 2 DTW
-// of Euclidean cells.
+// OP = measure + 2 * cell (measure 0 Frechet, 1 DTW; cell 0 squared
+// Euclidean, 1 Euclidean, 2 Manhattan, 3 Chebyshev).
 template <int R, int D, typename V, bool RINGS, int OP = 0>
 struct Stream {
-  static constexpr bool DTW = OP != 0;
+  static constexpr bool DTW = (OP & 1) != 0;
+  static constexpr int CELL = OP >> 1;
   using N = Num<V>;
   using C = typename N::Coord;
   static constexpr int DP = D == 3 ? 4 : D;
@@ -567,13 +574,24 @@ struct Stream {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         V t = p[r][0] - g.q[u].c[0];
-        V s = t * t;
+        V s;
+        if constexpr (CELL >= 2) {
+          // Manhattan: s = |d0| + |d1| + ...; Chebyshev: max of |dk|
+          s = N::abs(t);
 #pragma unroll
-        for (int k2 = 1; k2 < D; ++k2) {
-          V w = p[r][k2] - g.q[u].c[k2];
-          s = N::fma(w, w, s);
+          for (int k2 = 1; k2 < D; ++k2) {
+            V w = N::abs(p[r][k2] - g.q[u].c[k2]);
+            s = CELL == 2 ? s + w : N::mx(s, w);
+          }
+        } else {
+          s = t * t;
+#pragma unroll
+          for (int k2 = 1; k2 < D; ++k2) {
+            V w = p[r][k2] - g.q[u].c[k2];
+            s = N::fma(w, w, s);
+          }
+          if constexpr (CELL == 1) s = N::sqrt_cell(s);
         }
-        if constexpr (OP == 2) s = N::sqrt_cell(s);
         dd[r] = s;
       }
       V above = up, diag = upPrev;
@@ -785,6 +803,8 @@ struct Stream {
                          __HIP_MEMORY_SCOPE_WORKGROUP);
     if constexpr (DTW) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
+    } else if constexpr (CELL != 0) {
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) N::store_value(a.out, out63, res);
     } else {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
         N::store(a.out, out63, res, a.metric);
@@ -888,10 +908,10 @@ __global__ __launch_bounds__(256) void stream_kernel(KernelArgs a) {
   s.run(wave);
 }
 
-// Dynamic time warping (OP 1: squared Euclidean cells, 2: Euclidean cells)
-// on the same sweep; its plans never use LDS rings between waves.
+// The other measures and ground distances (OP as for Stream, OP != 0) on the
+// same sweep; their plans never use LDS rings between waves.
 template <int R, int D, typename V, int OP>
-__global__ __launch_bounds__(256) void dtw_kernel(KernelArgs a) {
+__global__ __launch_bounds__(256) void op_kernel(KernelArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   int lane = threadIdx.x & (kWave - 1);
   int wib = threadIdx.x / kWave;

@@ -29,6 +29,8 @@ FFD_E_BUSY = -5
 FFD_E_TIMEOUT = -6
 FFD_EUCLIDEAN = 0
 FFD_SQEUCLIDEAN = 1
+FFD_MANHATTAN = 2
+FFD_CHEBYSHEV = 3
 FFD_OP_BATCH = 0
 FFD_OP_CROSS = 1
 FFD_MAX_DIM = 4
@@ -428,38 +430,38 @@ class Context:
     def distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
         return ffd_distance(self.handle, p, q, metric, **kw)
 
-    def distance_i32(self, p, q, **kw):
-        return ffd_distance_i32(self.handle, p, q, FFD_SQEUCLIDEAN, **kw)
+    def distance_i32(self, p, q, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_distance_i32(self.handle, p, q, metric, **kw)
 
     def batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
 
-    def batch_i32(self, P, p_off, Q, q_off, **kw):
-        return ffd_batch_i32(self.handle, P, p_off, Q, q_off, FFD_SQEUCLIDEAN, **kw)
+    def batch_i32(self, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_batch_i32(self.handle, P, p_off, Q, q_off, metric, **kw)
 
     def cross(self, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_cross(self.handle, Qs, q_off, DB, db_off, metric, **kw)
 
-    def cross_i32(self, Qs, q_off, DB, db_off, **kw):
-        return ffd_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
+    def cross_i32(self, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_cross_i32(self.handle, Qs, q_off, DB, db_off, metric, **kw)
 
     def dtw_distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
         return ffd_dtw_distance(self.handle, p, q, metric, **kw)
 
-    def dtw_distance_i32(self, p, q, **kw):
-        return ffd_dtw_distance_i32(self.handle, p, q, FFD_SQEUCLIDEAN, **kw)
+    def dtw_distance_i32(self, p, q, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_dtw_distance_i32(self.handle, p, q, metric, **kw)
 
     def dtw_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_dtw_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
 
-    def dtw_batch_i32(self, P, p_off, Q, q_off, **kw):
-        return ffd_dtw_batch_i32(self.handle, P, p_off, Q, q_off, FFD_SQEUCLIDEAN, **kw)
+    def dtw_batch_i32(self, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_dtw_batch_i32(self.handle, P, p_off, Q, q_off, metric, **kw)
 
     def dtw_cross(self, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_dtw_cross(self.handle, Qs, q_off, DB, db_off, metric, **kw)
 
-    def dtw_cross_i32(self, Qs, q_off, DB, db_off, **kw):
-        return ffd_dtw_cross_i32(self.handle, Qs, q_off, DB, db_off, FFD_SQEUCLIDEAN, **kw)
+    def dtw_cross_i32(self, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, **kw):
+        return ffd_dtw_cross_i32(self.handle, Qs, q_off, DB, db_off, metric, **kw)
 
     def autotune_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_autotune_batch(self.handle, P, p_off, Q, q_off, metric, **kw)

@@ -57,6 +57,15 @@ def main():
         "euclidean": [float(v) for v in vals],
     }
 
+    # the same pairs under the Manhattan and Chebyshev ground distances
+    for name, metric in (("manhattan", oracle.MANHATTAN), ("chebyshev", oracle.CHEBYSHEV)):
+        mv = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, metric, nthreads)
+        out["batched_" + name] = {
+            "workload": f"batched(seed=2) as above, {name} ground distance",
+            "sample_index": [int(i) for i in idx],
+            name: [float(v) for v in mv],
+        }
+
     # DTW (Appendix B) of squared Euclidean cells on the same pairs
     dvals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.SQEUCLIDEAN, nthreads, measure="dtw")
     out["dtw_batched"] = {

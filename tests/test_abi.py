@@ -96,7 +96,7 @@ def test_batch_argument_checks(planner):
     assert args(good, good) == ffd.FFD_E_DEVICE
     assert args(good, empty) == ffd.FFD_E_INVALID
     assert args(shifted, good) == ffd.FFD_E_INVALID
-    assert args(good, good, metric=3) == ffd.FFD_E_INVALID
+    assert args(good, good, metric=7) == ffd.FFD_E_INVALID
     assert args(good, good, dim=9) == ffd.FFD_E_UNSUPPORTED
     assert args(good, good, out=None) == ffd.FFD_E_INVALID
     assert args(good, good, n=-1) == ffd.FFD_E_INVALID
@@ -167,6 +167,18 @@ def test_dtw_argument_checks_and_workspace(planner):
                   None) == ffd.FFD_E_DEVICE
         assert fn(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 60, 2, 0, FAKE, FAKE, 256,
                   None) == ffd.FFD_E_NOMEM
+
+
+def test_metric_checks(planner):
+    L = ffd.lib
+    for metric in (ffd.FFD_MANHATTAN, ffd.FFD_CHEBYSHEV):
+        assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, metric, FAKE, None) == ffd.FFD_E_DEVICE
+        assert L.ffd_distance_i32(planner, FAKE, 5, FAKE, 7, 2, metric, FAKE, None) == ffd.FFD_E_DEVICE
+        assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, metric, FAKE, None) == ffd.FFD_E_DEVICE
+        assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, metric, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, 4, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, -1, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, ffd.FFD_EUCLIDEAN, FAKE, None) == ffd.FFD_E_UNSUPPORTED
 
 
 def test_set_tuning_validation(planner):

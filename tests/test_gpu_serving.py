@@ -117,3 +117,6 @@ def test_poll_and_errors(served):
         srv.submit(np.zeros((9000, 2), dtype=np.float32))  # longer than max_query
     with pytest.raises(ffd.FFDError):
         srv.submit(np.zeros((0, 2), dtype=np.float32))
+    with pytest.raises(ffd.FFDError) as ei:
+        srv.submit(q, ffd.FFD_MANHATTAN)  # serving takes the Euclidean metrics only
+    assert ei.value.status == ffd.FFD_E_UNSUPPORTED
