@@ -205,6 +205,56 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                        const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);
 
+/* Introspection (tests and tools): the plan that a call would launch.
+ *   op: FFD_OP_BATCH (a_off = p_off, b_off = q_off, na = nb = npairs),
+ *   FFD_OP_CROSS (a_off = q_off, b_off = db_off) or FFD_OP_PAIR (a_off =
+ *   {0, n}, b_off = {0, m}, na = nb = 1: ffd_distance); dtw selects the DTW
+ *   calls; metric and exact (int32 coordinates) as in the calls.  HOST
+ *   arrays only; nothing is launched, and a planning-only context works.
+ *   *summary receives the launch shape; jobs (ffd_plan_job[jobs_cap], may be
+ *   NULL) receives the job table grouped by wave, wave_jobs (int32
+ *   [waves + 1], may be NULL) the first job of each wave.  Stream positions
+ *   follow from the jobs: each job runs its column curves in order, each
+ *   column curve's bands in order; a task lasts 1 + m steps (a separator
+ *   and m columns) rounded up to a multiple of 16 and to at least 80; an
+ *   idle job (row_sel 2) lasts col_count steps.
+ * Errors: as ffd_batch / ffd_cross / ffd_distance; FFD_E_NOMEM when jobs_cap
+ * or the wave_jobs array is too small (the summary is filled first). */
+#define FFD_OP_PAIR 2
+typedef struct ffd_plan_summary {
+  int32_t rows_per_lane;   /* R                                              */
+  int32_t waves;           /* wavefronts                                     */
+  int32_t waves_per_block; /* wavefronts per workgroup                       */
+  int32_t cooperative;     /* 1: waves wait on each other (global links)     */
+  int32_t rings;           /* 1: bands hand rows on through LDS rings        */
+  int32_t flags;           /* progress flags (global links)                  */
+  int64_t link_elems;      /* elements of all link buffers                   */
+  int64_t stream_steps;    /* longest stream of any wave                     */
+  int64_t jobs;            /* entries of the job table                       */
+} ffd_plan_summary;
+typedef struct ffd_plan_job { /* 64 bytes */
+  int64_t out_base;   /* output index of the first column curve              */
+  int64_t link_in;    /* first element of the incoming boundary rows          */
+  int64_t link_out;   /* first element of the outgoing boundary rows          */
+  int32_t row_sel;    /* 0: row curve from the first set (P, queries), 1:
+                         from the second (Q, database), 2: idle job           */
+  int32_t row_idx;    /* row curve index                                      */
+  int32_t col_sel;    /* set of the column curves                             */
+  int32_t col_first;  /* first column curve                                   */
+  int32_t col_count;  /* column curves (idle job: steps)                      */
+  int32_t out_stride; /* output index step between column curves            */
+  int32_t band_first; /* bands [band_first, band_first + band_count) of 64 R  */
+  int32_t band_count; /* rows (<= 0: to the last band)                        */
+  int32_t flag_in;    /* flag of the incoming link; -1 none; <= -2: LDS ring
+                         of wave (-2 - flag_in) of the same workgroup         */
+  int32_t flag_out;   /* flag of the outgoing link; -1 none; -2: LDS ring     */
+} ffd_plan_job;
+int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
+                      const int64_t *b_off, int64_t nb, int32_t dim, int32_t exact,
+                      int32_t dtw, int32_t metric, ffd_plan_summary *summary,
+                      ffd_plan_job *jobs, int64_t jobs_cap, int32_t *wave_jobs,
+                      int64_t wave_jobs_cap);
+
 /* Tuning knobs (0 = automatic).  rows_per_lane in {1, 2, 4, 8}: points of the
  * row curve each GPU lane holds; waves_per_simd: resident waves per SIMD the
  * batch planner targets.  Returns FFD_E_INVALID for values out of range. */

@@ -1222,6 +1222,46 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
                       (hipStream_t)stream, true);
 }
 
+static_assert(sizeof(ffd_plan_job) == sizeof(Job), "plan job layout");
+
+int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
+                      int32_t dim, int32_t exact, int32_t dtw, int32_t metric, ffd_plan_summary *summary,
+                      ffd_plan_job *jobs, int64_t jobs_cap, int32_t *wave_jobs, int64_t wave_jobs_cap) {
+  if (!ctx || !summary) return FFD_E_INVALID;
+  int rc = check_common(ctx, dim, metric, exact != 0);
+  if (rc) return rc;
+  if (op != FFD_OP_BATCH && op != FFD_OP_CROSS && op != FFD_OP_PAIR) return fail(ctx, FFD_E_INVALID, "unknown op");
+  if (na < 1 || nb < 1) return fail(ctx, FFD_E_INVALID, "nothing to plan");
+  if ((op == FFD_OP_BATCH || op == FFD_OP_PAIR) && na != nb) return fail(ctx, FFD_E_INVALID, "na != nb");
+  if (op == FFD_OP_PAIR && na != 1) return fail(ctx, FFD_E_INVALID, "a pair has one curve per side");
+  if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
+  if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
+  MeasureScope scope(ctx, op_of(dtw != 0, metric));
+  Plan pl;
+  if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, dim, exact != 0, pl);
+  else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, dim, exact != 0, pl);
+  else rc = plan_pair(ctx, a_off[1], b_off[1], dim, exact != 0, pl);
+  if (rc) return rc;
+  summary->rows_per_lane = pl.R;
+  summary->waves = pl.nwaves;
+  summary->waves_per_block = pl.wpb;
+  summary->cooperative = pl.coop ? 1 : 0;
+  summary->rings = pl.rings ? 1 : 0;
+  summary->flags = pl.nflags;
+  summary->link_elems = pl.link_elems;
+  summary->stream_steps = pl.max_steps;
+  summary->jobs = (int64_t)pl.jobs.size();
+  if (jobs) {
+    if (jobs_cap < (int64_t)pl.jobs.size()) return fail(ctx, FFD_E_NOMEM, "jobs_cap too small");
+    memcpy(jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
+  }
+  if (wave_jobs) {
+    if (wave_jobs_cap < (int64_t)pl.wave_jobs.size()) return fail(ctx, FFD_E_NOMEM, "wave_jobs too small");
+    memcpy(wave_jobs, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
+  }
+  return FFD_OK;
+}
+
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
                        int32_t dim, size_t *bytes) {
   if (!ctx || !bytes) return FFD_E_INVALID;

@@ -33,6 +33,7 @@ FFD_MANHATTAN = 2
 FFD_CHEBYSHEV = 3
 FFD_OP_BATCH = 0
 FFD_OP_CROSS = 1
+FFD_OP_PAIR = 2
 FFD_MAX_DIM = 4
 
 EXPORTS = (
@@ -43,7 +44,7 @@ EXPORTS = (
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
-    "ffd_dtw_cross_i32",
+    "ffd_dtw_cross_i32", "ffd_plan_describe",
 )
 
 
@@ -55,6 +56,23 @@ class LaunchInfo(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PlanSummary(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("cooperative", ctypes.c_int32),
+                ("rings", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("link_elems", ctypes.c_int64), ("stream_steps", ctypes.c_int64), ("jobs", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# one entry of a plan's job table (ffd_plan_job, 64 bytes)
+PLAN_JOB = np.dtype([("out_base", "<i8"), ("link_in", "<i8"), ("link_out", "<i8"), ("row_sel", "<i4"),
+                     ("row_idx", "<i4"), ("col_sel", "<i4"), ("col_first", "<i4"), ("col_count", "<i4"),
+                     ("out_stride", "<i4"), ("band_first", "<i4"), ("band_count", "<i4"), ("flag_in", "<i4"),
+                     ("flag_out", "<i4")])
 
 
 class Tuning(ctypes.Structure):
@@ -125,6 +143,9 @@ def _load():
     lib.ffd_set_split.restype = ctypes.c_int
     lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
     lib.ffd_last_launch.restype = ctypes.c_int
+    lib.ffd_plan_describe.argtypes = [vp, i32, i64p, i64, i64p, i64, i32, i32, i32, i32,
+                                      ctypes.POINTER(PlanSummary), vp, i64, vp, i64]
+    lib.ffd_plan_describe.restype = ctypes.c_int
     lib.ffd_autotune_batch.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, vp, vp, sz, vp, ctypes.POINTER(Tuning)]
     lib.ffd_autotune_batch.restype = ctypes.c_int
     lib.ffd_autotune_cross.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, vp, vp, sz, vp,
@@ -265,6 +286,22 @@ def ffd_dtw_distance(ctx, p, q, metric=FFD_EUCLIDEAN, out=None, stream=None):
 
 def ffd_dtw_distance_i32(ctx, p, q, metric=FFD_SQEUCLIDEAN, out=None, stream=None):
     return _pair(lib.ffd_dtw_distance_i32, torch.int32, torch.int64, ctx, p, q, metric, out, stream)
+
+
+def ffd_plan_describe(ctx, op, a_off, b_off, dim, exact=False, dtw=False, metric=FFD_EUCLIDEAN):
+    """The plan a call would launch: (summary dict, job table as a PLAN_JOB
+    array, first job of each wave as int32[waves + 1]).  Host-only."""
+    ao, aop = _offsets(a_off)
+    bo, bop = _offsets(b_off)
+    sm = PlanSummary()
+    args = (ctx, int(op), aop, len(ao) - 1, bop, len(bo) - 1, int(dim), int(bool(exact)), int(bool(dtw)),
+            int(metric), ctypes.byref(sm))
+    _check(lib.ffd_plan_describe(*args, None, 0, None, 0), ctx)
+    jobs = np.zeros(sm.jobs, dtype=PLAN_JOB)
+    wj = np.zeros(sm.waves + 1, dtype=np.int32)
+    _check(lib.ffd_plan_describe(*args, ctypes.c_void_p(jobs.ctypes.data), len(jobs),
+                                 ctypes.c_void_p(wj.ctypes.data), len(wj)), ctx)
+    return sm.as_dict(), jobs, wj
 
 
 def ffd_workspace_size(ctx, op, a_off, b_off, dim):

@@ -1,0 +1,131 @@
+"""Launch plans replayed on the CPU by the schedule simulator (no GPU).
+
+A planning-only context (256 CUs, 160 KB of LDS per CU) builds the plans
+the library would launch for the benchmark workloads, for forced band
+splitting, other launch shapes, long curves whose boundary rows do not fit
+LDS, cross requests, single long pairs (the LDS-ring pipeline) and the DTW
+and Manhattan kernels; tests/plan_sim.py checks coverage, output indices,
+hand-off adjacency, link and ring lags (deadlock freedom) and buffer bounds.
+"""
+import numpy as np
+import pytest
+
+from paper_2404_05708_amd import ffd
+import plan_sim
+import workloads
+
+
+@pytest.fixture
+def planner():
+    h = ffd.ffd_create_planner(256, 160 * 1024)
+    yield h
+    ffd.ffd_destroy(h)
+
+
+def batch_case(h, p_off, q_off, dim=2, **kw):
+    sm, jobs, wj = ffd.ffd_plan_describe(h, ffd.FFD_OP_BATCH, p_off, q_off, dim, **kw)
+    plan_sim.check(sm, jobs, wj, (np.asarray(p_off), np.asarray(q_off)), range(len(p_off) - 1))
+    return sm
+
+
+def test_batched_workload_plan(planner):
+    P, p_off, Q, q_off = workloads.batched()
+    sm = batch_case(planner, p_off, q_off)
+    assert sm["rows_per_lane"] == 8 and sm["waves"] == 2048 and sm["cooperative"] == 1
+
+
+@pytest.mark.parametrize("R,W", [(1, 0), (2, 0), (4, 0), (8, 0), (8, 3), (4, 4)])
+def test_forced_split_and_launch_shapes(planner, R, W):
+    P, p_off, Q, q_off = workloads.random_pairs(400 + R, 300, 1, 2500, dim=2)
+    ffd.ffd_set_tuning(planner, R, W)
+    try:
+        batch_case(planner, p_off, q_off)
+        ffd.ffd_set_split(planner, 1e-9)
+        sm = batch_case(planner, p_off, q_off)
+        assert sm["flags"] > 0
+    finally:
+        ffd.ffd_set_split(planner, 0.0)
+        ffd.ffd_set_tuning(planner, 0, 0)
+
+
+def test_long_curves_chain_through_links(planner):
+    # column curves longer than a wave's LDS hand-off row: bands chain
+    # through global links, split or in place on one wave
+    P, p_off, Q, q_off = workloads.random_pairs(410, 120, 1, 9000, dim=2)
+    sm = batch_case(planner, p_off, q_off)
+    assert sm["flags"] > 0
+    ffd.ffd_set_split(planner, -1.0)
+    try:
+        batch_case(planner, p_off, q_off)
+    finally:
+        ffd.ffd_set_split(planner, 0.0)
+
+
+def test_cross_plans(planner):
+    Qs, qo, DB, do = workloads.cross_int()
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, qo, do, 2, exact=True, metric=1)
+    nq, ndb = len(qo) - 1, len(do) - 1
+    plan_sim.check(sm, jobs, wj, (qo, do), range(nq * ndb))
+    rng = np.random.default_rng(411)
+    qo2 = np.concatenate([[0], np.cumsum(rng.integers(1, 3000, size=20))]).astype(np.int64)
+    do2 = np.concatenate([[0], np.cumsum(rng.integers(1, 9000, size=60))]).astype(np.int64)
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, qo2, do2, 3)
+    plan_sim.check(sm, jobs, wj, (qo2, do2), range(20 * 60))
+
+
+@pytest.mark.parametrize("n,m,dim", [(131072, 131072, 3), (512, 384, 2), (5000, 5000, 2), (64 * 4 * 7, 2500, 2)])
+def test_single_pairs(planner, n, m, dim):
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, n], [0, m], dim)
+    plan_sim.check(sm, jobs, wj, (np.array([0, n]), np.array([0, m])), [0])
+    if n == 131072:
+        assert sm["rings"] == 1 and sm["waves"] == 512
+
+
+@pytest.mark.parametrize("dtw,metric", [(True, 1), (True, 0), (False, 2), (True, 3)])
+def test_other_kernels(planner, dtw, metric):
+    P, p_off, Q, q_off = workloads.random_pairs(412, 200, 1, 6000, dim=2)
+    sm = batch_case(planner, p_off, q_off, dtw=dtw, metric=metric)
+    assert sm["rings"] == 0
+    smp, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 40000], [0, 30000], 2, dtw=dtw,
+                                          metric=metric)
+    plan_sim.check(smp, jobs, wj, (np.array([0, 40000]), np.array([0, 30000])), [0])
+    assert smp["rings"] == 0
+
+
+def test_simulator_catches_a_broken_plan(planner):
+    """Planted mistakes in a copy of a real plan (CPU only): a link consumer
+    moved closer to its producer, a dropped band, a duplicated output."""
+    P, p_off, Q, q_off = workloads.random_pairs(413, 200, 1, 2500, dim=2)
+    ffd.ffd_set_tuning(planner, 2, 0)
+    ffd.ffd_set_split(planner, 1e-9)
+    try:
+        sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2)
+    finally:
+        ffd.ffd_set_split(planner, 0.0)
+        ffd.ffd_set_tuning(planner, 0, 0)
+    offs = (np.asarray(p_off), np.asarray(q_off))
+    plan_sim.check(sm, jobs, wj, offs, range(len(p_off) - 1))
+    # 1: shorten the idle padding in front of a link consumer
+    idle = np.nonzero((jobs["row_sel"] == 2) & (jobs["col_count"] >= 16))[0]
+    assert len(idle) > 0
+    bad = jobs.copy()
+    bad["col_count"][idle[0]] -= 16
+    sm2 = dict(sm)
+    tasks, ends = plan_sim.replay(sm2, bad, wj, offs)
+    sm2["stream_steps"] = max(ends)
+    with pytest.raises(AssertionError):
+        plan_sim.check(sm2, bad, wj, offs, range(len(p_off) - 1))
+    # 2: a job that drops its last band
+    multi = np.nonzero((jobs["row_sel"] != 2) & (jobs["band_count"] > 1))[0]
+    if len(multi):
+        bad = jobs.copy()
+        bad["band_count"][multi[0]] -= 1
+        with pytest.raises(AssertionError):
+            plan_sim.check(sm, bad, wj, offs, range(len(p_off) - 1))
+    # 3: two pairs writing one output
+    tasks, _ = plan_sim.replay(sm, jobs, wj, offs)
+    writers = sorted({t["job"] for t in tasks if t["out"] is not None})
+    bad = jobs.copy()
+    bad["out_base"][writers[1]] = bad["out_base"][writers[0]]
+    with pytest.raises(AssertionError):
+        plan_sim.check(sm, bad, wj, offs, range(len(p_off) - 1))
