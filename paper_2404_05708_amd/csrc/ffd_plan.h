@@ -68,24 +68,25 @@ FFD_HD uint64_t flag_word(uint32_t epoch, uint32_t count) { return ((uint64_t)ep
 // Bands of 64*R rows needed for a row curve of n points.
 FFD_HD int64_t bands_for(int64_t n, int R) { return (n + (int64_t)kWave * R - 1) / ((int64_t)kWave * R); }
 
-// Stream length of one task: separator + m columns, padded by repeating the
-// last column point up to the minimum length and to a multiple of kGroup.
+// Stream length of one task: at least kGroup separator columns, then the m
+// columns, rounded up to a multiple of kGroup and to the minimum length (the
+// separators come first so that a 16-lane block of the wave can take the
+// task's rows at a group boundary, while its columns are still separators).
 FFD_HD int64_t task_len(int64_t m, bool chained) {
-  int64_t L = 1 + m;
+  int64_t L = (m + kGroup + kGroup - 1) / kGroup * kGroup;
   int64_t lo = chained ? kMinTaskChained : kMinTask;
-  if (L < lo) L = lo;
-  return (L + kGroup - 1) / kGroup * kGroup;
+  return L < lo ? lo : L;
 }
 
 // LDS carve-up of one wave's region (byte offsets).  vsize is the byte size
 // of the value type (4: float32 path, 8: exact path with FP64 values).
 struct LdsLayout {
   int ring;   // (kRing + kGroup) column points; the last kGroup mirror the first
-  int ghost;  // top boundary of a first band: kGroup + 1 values -inf, +inf, ...; DTW:
-              // 2 kGroup + 1 values, +inf except 0 in the middle
+  int ghost;  // top boundary of a first band: 2 kGroup + 1 values, +inf except the
+              // corner in the middle (-inf for the Frechet distance, 0 for DTW)
   int sink;   // kWave + kGroup values: bottom-row stores that hand nothing on
   int hand;   // hcap values: bottom row of the band above (same wave)
-  int lring;  // kLinkRing + kGroup values: boundary row arriving over a link
+  int lring;  // kLinkRing values: boundary row arriving over a link
   int lstage; // kLinkRing values: outgoing boundary row, by stream position, until it is stored
   int xring;  // kXRing values: bottom row read by another wave of the workgroup
   int xctr;   // two int32 counters of that ring: entries written, entries read
@@ -104,10 +105,11 @@ FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings, bool 
   LdsLayout L;
   int o = 0;
   L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
-  L.ghost = o; o += (dtw ? 2 * kGroup + 1 : kGroup + 1) * vsize;
+  L.ghost = o; o += (2 * kGroup + 1) * vsize;
+  (void)dtw;
   L.sink = o;  o += (kWave + kGroup) * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
-  o = align16(o); L.lring = o; o += (kLinkRing + kGroup) * vsize;
+  o = align16(o); L.lring = o; o += kLinkRing * vsize;
   o = align16(o); L.lstage = o; o += kLinkRing * vsize;
   o = align16(o); L.xring = o; o += rings ? kXRing * vsize : 0;
   o = align16(o); L.xctr = o; o += rings ? 16 : 0;

@@ -17,15 +17,19 @@
 //    (written by lane 63 earlier in the same stream) or the top boundary;
 //  * column points stream through a 256-entry LDS ring that the wave refills
 //    every 64 steps, one entry per lane, from global memory;
-//  * every task starts with a separator column whose point is +inf in every
-//    coordinate, so d = +inf in that column for every row: this resets the
-//    left neighbours to +inf (the boundary M_{i,0} = +inf) without a branch,
-//    and a -inf entry of the top boundary at the separator gives the corner
-//    M_{0,0} = -inf, which makes Eq. (1) produce the first row and column
-//    (running maxima, Algorithms 3-5) by itself;
-//  * rows past the end of a curve repeat its last point and columns past the
-//    end repeat its last column point: repeating points does not change the
-//    distance (Sec. 4, footnote), so padding is exact.
+//  * every task starts with at least 16 separator columns whose point is
+//    +inf in every coordinate, so d = +inf there for every row: this resets
+//    the left neighbours to +inf (the boundary M_{i,0} = +inf) without a
+//    branch, and a -inf entry of the top boundary at the last separator
+//    gives the corner M_{0,0} = -inf, which makes Eq. (1) produce the first
+//    row and column (running maxima, Algorithms 3-5) by itself; the task's
+//    m columns follow and end the task;
+//  * a lane must use the new task's rows from its first real column on;
+//    while its columns are separators the rows do not matter, so the lanes
+//    take them in 16-lane blocks at group boundaries (block k at the start
+//    of the (k+1)-th group of the task), with no per-step select;
+//  * rows past the end of a curve repeat its last point: repeating points
+//    does not change the distance (Sec. 4, footnote), so padding is exact.
 //
 // Other ground distances (Sec. 3: the method assumes nothing about it) and
 // dynamic time warping (Appendix B, Algorithm B.1: the outer max replaced by
@@ -34,12 +38,10 @@
 // cell 0 squared Euclidean, 1 Euclidean (the hardware square root per cell,
 // DTW only: the Frechet kernel takes one root per pair), 2 Manhattan
 // (sum of |dk|), 3 Chebyshev (max of |dk|).  Sums are not selections, so
-// padding is no longer exact: a DTW
-// task puts its separator columns first and its m real columns last (the
-// top-boundary corner, 0 for DTW, sits at the last separator), and the
-// result M_{n-1,m-1} is taken from the lane holding row n-1 at the moment
-// it switches to the next task, when its registers still hold the last
-// column of the old one.
+// row padding is no longer exact: the DTW
+// corner is 0, and the result M_{n-1,m-1} is taken from the lane holding row
+// n-1 at the moment it enters the next task, when its registers still hold
+// the last column of the old one.
 //
 // The squared distance is evaluated as d2 = dx*dx, then d2 = fma(dk, dk, d2)
 // for k >= 1, in the value type; the recurrence runs on d2 and the Euclidean
@@ -338,9 +340,9 @@ struct Stream {
       t.link_in = f.link_in + f.link_rel;
       t.rel = (int32_t)f.link_rel;
       d.rel_in = d.rel_out = (int32_t)f.link_rel;
-      d.L = t.L; d.hin = hin; d.hout = hout; d.drain = 0;
-      if constexpr (DTW) {
-        // separators first, real columns last; the last row's lane and register
+      d.L = t.L; d.hin = hin; d.hout = hout;
+      {
+        // separator count; the register and lane of the curve's last row (DTW)
         int64_t last = f.n - 1 - (int64_t)b * kWave * R;
         int32_t lr = last < kWave * R ? (int32_t)last : kWave * R - 1;
         d.drain = ((lr % R) << 1) | ((lr / R) << 4) | ((int32_t)(t.L - t.m) << 10);
@@ -421,14 +423,9 @@ struct Stream {
     int64_t co = in_next ? nxt.col_off : cur.col_off;
     int32_t sel = in_next ? nxt.col_sel : cur.col_sel;
     bool drain = in_next ? nxt.drain : cur.drain;
-    int64_t idx = x - 1;
-    if constexpr (DTW) {
-      int64_t npre = (in_next ? nxt.L : cur.L) - m;
-      qsep = drain || x < npre;
-      idx = x - npre;
-    } else {
-      qsep = drain || x == 0;
-    }
+    int64_t npre = (in_next ? nxt.L : cur.L) - m;
+    qsep = drain || x < npre;
+    int64_t idx = x - npre;
     if (idx > m - 1) idx = m - 1;
     if (idx < 0) idx = 0;
     if (drain) { co = 0; idx = 0; sel = 0; }
@@ -464,8 +461,7 @@ struct Stream {
   __device__ void link_write() {
     if (hslot >= 0) {
       int ls = hslot & (kLinkRing - 1);
-      lring()[ls] = hbuf;
-      if (ls < kGroup) lring()[ls + kLinkRing] = hbuf;
+      lring()[ls] = hbuf;  // read a group at a time from a group-aligned position: no wrap
     }
   }
 
@@ -529,7 +525,7 @@ struct Stream {
   V upPrev;
   // lane-0 cursor (task containing the group being loaded) and window start
   int32_t id0, S0, L0, g0, src0, win0, win_cur;
-  int32_t pre0;  // DTW: separator columns of lane 0's task
+  int32_t pre0;  // separator columns of lane 0's task
   int32_t rc63, ls63;  // DTW: register and lane of the last row of lane 63's task
   V cap;         // DTW: this lane's value of the last column, taken at its task switch
   // lane-63 cursor: task containing column t0 - 64
@@ -552,15 +548,15 @@ struct Stream {
       // others land in the sink
       hout[u] = bottom;
       if (u == kGroup - 1) res = bottom;
-      if (window) {
+      if (DTW && window) {
+        // the lane enters the new task: its registers hold the old task's
+        // last column (the result of DTW is taken here), and it takes the
+        // new task's rows
         bool sw = lane == t0 + u - win;
-        if constexpr (DTW) {
-          // the lane leaves the old task: its registers hold that task's last column
-          V sel = Mp[0];
+        V sel = Mp[0];
 #pragma unroll
-          for (int r = 1; r < R; ++r) sel = rc == r ? Mp[r] : sel;
-          cap = sw ? sel : cap;
-        }
+        for (int r = 1; r < R; ++r) sel = rc == r ? Mp[r] : sel;
+        cap = sw ? sel : cap;
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -613,13 +609,10 @@ struct Stream {
   // returns here was compiled (ROCm 7.2) into code that read the address
   // from an undefined register on the link path.
   __device__ __forceinline__ const V *hin_at(int32_t t) const {
-    int32_t og = lay.ghost + (t == S0 ? 0 : (int32_t)sizeof(V));
-    if constexpr (DTW) {
-      // ghost = [+inf x kGroup, 0, +inf x kGroup]; the corner sits at the
-      // task's last separator column c
-      int32_t c = S0 + pre0 - 1;
-      og = lay.ghost + (c >= t && c < t + kGroup ? kGroup - (c - t) : 0) * (int32_t)sizeof(V);
-    }
+    // ghost = [+inf x kGroup, corner, +inf x kGroup]; the corner sits at
+    // the task's last separator column c
+    int32_t c = S0 + pre0 - 1;
+    int32_t og = lay.ghost + (c >= t && c < t + kGroup ? kGroup - (c - t) : 0) * (int32_t)sizeof(V);
     int32_t oh = lay.hand + (t - S0) * (int32_t)sizeof(V);
     int32_t ol = lay.lring + (t & (kLinkRing - 1)) * (int32_t)sizeof(V);
     int32_t off = g0 == kHinGhost ? og : (g0 == kHinHand ? oh : ol);
@@ -638,7 +631,7 @@ struct Stream {
       L0 = uni(d.L);
       g0 = uni(d.hin);
       src0 = uni(d.src);
-      if constexpr (DTW) pre0 = uni(d.drain) >> 10;
+      pre0 = uni(d.drain) >> 10;
       win0 = t;
       const V *src = pst(id0 & 1) + lane * (R * D);
 #pragma unroll
@@ -746,7 +739,7 @@ struct Stream {
     if ((t0 & (kFill - 1)) == 0) refill(t0);
     if (t0 - kWave == S63 + L63) {
       Desc d = *desc(id63 + 1);
-      if (uni(d.drain) & (DTW ? 1 : -1)) {
+      if (uni(d.drain) & 1) {
         // end of the stream: store what is still staged (positions from
         // the last flush to the end of lane 63's last task) and publish
         if (a.flags) {
@@ -795,7 +788,19 @@ struct Stream {
       load_group(t0, hin_at(t0), g);
     }
     V res;
-    bool window = t0 < win0 + kWave;
+    // Frechet: 16-lane block k takes the task's rows at the start of group
+    // k + 1 of the task: its lanes are then on separator columns 1 .. 16 (a
+    // task has at least 16), so no real column of either task sees the
+    // wrong rows.  (DTW switches per lane in the window groups, where it
+    // also takes its result.)
+    if (!DTW && t0 > win0 && t0 <= win0 + kWave) {
+      bool take = (lane >> 4) == ((t0 - win0) >> 4) - 1;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) p[r][k2] = take ? pn[r][k2] : p[r][k2];
+    }
+    bool window = DTW && t0 < win0 + kWave;
     if (!window) group<true>(t0, win0, false, g, hout, res, rc63);
     else group<false>(t0, win0, window, g, hout, res, rc63);
     if (RINGS && hout63 == kHoutRing && lane == 0)
@@ -834,11 +839,7 @@ struct Stream {
 
     // constant LDS: top boundary and ring entries before the stream start;
     // row staging starts as zeros so that no lane ever reads uninitialised LDS
-    if constexpr (DTW) {
-      for (int i = lane; i <= 2 * kGroup; i += kWave) ghost()[i] = i == kGroup ? V(0) : N::inf();
-    } else {
-      for (int i = lane; i <= kGroup; i += kWave) ghost()[i] = i == 0 ? -N::inf() : N::inf();
-    }
+    for (int i = lane; i <= 2 * kGroup; i += kWave) ghost()[i] = i == kGroup ? (DTW ? V(0) : -N::inf()) : N::inf();
     for (int i = lane; i < 2 * kWave * R * D; i += kWave) pst(0)[i] = V(0);
     {
       Pt e;

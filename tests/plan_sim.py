@@ -2,9 +2,9 @@
 
 Replays a plan (from ffd_plan_describe) the way the kernel walks it: each
 wave runs its jobs in order; a job runs its column curves in order and, for
-each, its bands in order; a task lasts task_len(m) stream steps (a
-separator and m columns, at least 80, a multiple of 16), an idle job its
-step count.  From that replay it checks, without a GPU, the properties the
+each, its bands in order; a task lasts task_len(m) stream steps (at least
+16 separators and m columns, at least 80, a multiple of 16), an idle job
+its step count.  From that replay it checks, without a GPU, the properties the
 kernel relies on:
 
 * every (row curve, column curve) pair runs each of its bands exactly once,
@@ -33,8 +33,8 @@ ROW_IDLE = 2
 
 
 def task_len(m):
-    L = max(1 + m, KMIN)
-    return (L + KGROUP - 1) // KGROUP * KGROUP
+    # at least 16 separator columns, then the m columns, in whole groups
+    return max((m + 2 * KGROUP - 1) // KGROUP * KGROUP, KMIN)
 
 
 def curve_len(offs, sel, idx):
