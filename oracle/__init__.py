@@ -80,6 +80,10 @@ def _load():
         lib.ffdo_dtw_pairs.restype = ci
         lib.ffdo_dtw_pairs_i32.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, ci, i64p, ci, i64p]
         lib.ffdo_dtw_pairs_i32.restype = ci
+        lib.ffdo_lev.argtypes = [i32p, i64, i32p, i64, ci, i64p]
+        lib.ffdo_lev.restype = ci
+        lib.ffdo_lev_pairs.argtypes = [i32p, i64p, i64p, i32p, i64p, i64p, i64, ci, i64p, ci, i64p]
+        lib.ffdo_lev_pairs.restype = ci
         lib.ffdo_now.argtypes = []
         lib.ffdo_now.restype = ctypes.c_double
         _lib = lib
@@ -236,6 +240,20 @@ def dtw_f32_replica(p, q, metric=EUCLIDEAN):
     return np.float32(out.value)
 
 
+def lev(p, q):
+    """Levenshtein distance (Appendix B) of two int32 symbol sequences of
+    shape (n, D) (a symbol is equal to another when every coordinate is)."""
+    lib = _load()
+    p = _curve_i32(p)
+    q = _curve_i32(q)
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("dimension mismatch")
+    out = ctypes.c_int64()
+    _check(lib.ffdo_lev(_ptr(p, ctypes.c_int32), p.shape[0], _ptr(q, ctypes.c_int32), q.shape[0],
+                        p.shape[1], ctypes.byref(out)), "lev")
+    return int(out.value)
+
+
 def _i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
@@ -344,6 +362,34 @@ def dtw_cross(Qs, q_off, DB, db_off, metric=EUCLIDEAN, nthreads=1, rows=None):
 def dtw_cross_i32(Qs, q_off, DB, db_off, nthreads=1, rows=None, metric=SQEUCLIDEAN):
     ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
     return dfd_pairs_i32(Qs, ps, pl, DB, qs, ql, nthreads, measure="dtw", metric=metric).reshape(nr, ndb)
+
+
+def lev_pairs(P, p_start, p_len, Q, q_start, q_len, nthreads=1, order=None):
+    lib = _load()
+    P = _curve_i32(P)
+    Q = _curve_i32(Q)
+    ps, pl, qs, ql = _i64(p_start), _i64(p_len), _i64(q_start), _i64(q_len)
+    n = ps.shape[0]
+    out = np.empty(n, dtype=np.int64)
+    ordp = None
+    if order is not None:
+        order = _i64(order)
+        ordp = _ptr(order, ctypes.c_int64)
+    _check(lib.ffdo_lev_pairs(_ptr(P, ctypes.c_int32), _ptr(ps, ctypes.c_int64), _ptr(pl, ctypes.c_int64),
+                              _ptr(Q, ctypes.c_int32), _ptr(qs, ctypes.c_int64), _ptr(ql, ctypes.c_int64), n,
+                              P.shape[1], ordp, int(nthreads), _ptr(out, ctypes.c_int64)), "lev_pairs")
+    return out
+
+
+def lev_batch(P, p_off, Q, q_off, nthreads=1, order=None):
+    p_off = _i64(p_off)
+    q_off = _i64(q_off)
+    return lev_pairs(P, p_off[:-1], np.diff(p_off), Q, q_off[:-1], np.diff(q_off), nthreads, order)
+
+
+def lev_cross(Qs, q_off, DB, db_off, nthreads=1, rows=None):
+    ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
+    return lev_pairs(Qs, ps, pl, DB, qs, ql, nthreads).reshape(nr, ndb)
 
 
 def now():

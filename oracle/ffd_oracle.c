@@ -37,6 +37,13 @@
  * algorithm) and whose first column is the running sum of d_i1.  Here the
  * ground distance enters the sum per cell, so EUCLIDEAN takes a square root
  * in every cell (ffdo_dtw_*).
+ *
+ * Levenshtein distance (Appendix B, Algorithm B.2) of two symbol sequences
+ * (int32 points, equal when every coordinate is equal): the table
+ *   M_ij = min{M_{i-1,j} + 1, M_{i,j-1} + 1, M_{i-1,j-1} + [p_i != q_j]}
+ * with the boundary M_{-1,j} = j + 1, M_{i,-1} = i + 1, M_{-1,-1} = 0
+ * (0-based; the algorithm's index vectors read as 0-based), result M_PQ
+ * (ffdo_lev_*).
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -410,6 +417,46 @@ int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int d
     return rc;
 }
 
+/* ---------------------------------------- Levenshtein distance (App. B) */
+
+static int sym_ne(const int32_t *pi, const int32_t *qj, int dim)
+{
+    for (int k = 0; k < dim; ++k)
+        if (pi[k] != qj[k]) return 1;
+    return 0;
+}
+
+/* Rows i-1 and i of the Levenshtein table. */
+static int lev_rolling(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim,
+                       int64_t *out, int64_t *prev, int64_t *cur)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            int64_t d = sym_ne(p + i * dim, q + j * dim, dim);
+            int64_t up = i > 0 ? prev[j] : j + 1;         /* M_{i-1,j}   */
+            int64_t left = j > 0 ? cur[j - 1] : i + 1;    /* M_{i,j-1}   */
+            int64_t diag = i > 0 ? (j > 0 ? prev[j - 1] : i) : j; /* M_{i-1,j-1} */
+            cur[j] = imin(imin(up + 1, left + 1), diag + d);
+        }
+        int64_t *t = prev; prev = cur; cur = t;
+    }
+    *out = prev[m - 1];
+    return FFDO_OK;
+}
+
+/* Levenshtein distance of two int32 symbol sequences (dim coordinates per
+ * symbol). */
+int ffdo_lev(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, int64_t *out)
+{
+    int rc = check_args(p, n, q, m, dim, FFDO_SQEUCLIDEAN, out);
+    if (rc) return rc;
+    int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
+    if (!buf) return FFDO_ENOMEM;
+    rc = lev_rolling(p, n, q, m, dim, out, buf, buf + m);
+    free(buf);
+    return rc;
+}
+
 /* ----------------------------------------------------------- float replica */
 
 /* Float32 replica of one fixed evaluation order: d2 = dx*dx, then
@@ -507,7 +554,7 @@ struct pool_ctx {
     const int64_t *order;
     int64_t npairs;
     int dim, metric, is_int;
-    int dtw;               /* 0: discrete Frechet distance, 1: DTW */
+    int dtw;               /* 0: discrete Frechet distance, 1: DTW, 2: Levenshtein (int) */
     void *out;
     int64_t next;
     pthread_mutex_t mu;
@@ -538,9 +585,13 @@ static void *pool_worker(void *arg)
         if (c->is_int) {
             const int32_t *P = (const int32_t *)c->P, *Q = (const int32_t *)c->Q;
             int64_t *b = (int64_t *)buf;
-            (c->dtw ? dtw_rolling_i64 : rolling_i64)(P + c->p_start[k] * c->dim, n,
-                                                     Q + c->q_start[k] * c->dim, m, c->dim,
-                                                     c->metric, (int64_t *)c->out + k, b, b + m);
+            if (c->dtw == 2)
+                lev_rolling(P + c->p_start[k] * c->dim, n, Q + c->q_start[k] * c->dim, m, c->dim,
+                            (int64_t *)c->out + k, b, b + m);
+            else
+                (c->dtw ? dtw_rolling_i64 : rolling_i64)(P + c->p_start[k] * c->dim, n,
+                                                         Q + c->q_start[k] * c->dim, m, c->dim,
+                                                         c->metric, (int64_t *)c->out + k, b, b + m);
         } else {
             const float *P = (const float *)c->P, *Q = (const float *)c->Q;
             double *b = (double *)buf;
@@ -632,6 +683,14 @@ int ffdo_dtw_pairs(const float *P, const int64_t *p_start, const int64_t *p_len,
 {
     return pairs_f32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, metric, order, nthreads,
                      out, 1);
+}
+
+int ffdo_lev_pairs(const int32_t *P, const int64_t *p_start, const int64_t *p_len,
+                   const int32_t *Q, const int64_t *q_start, const int64_t *q_len,
+                   int64_t npairs, int dim, const int64_t *order, int nthreads, int64_t *out)
+{
+    return pairs_i32(P, p_start, p_len, Q, q_start, q_len, npairs, dim, FFDO_SQEUCLIDEAN, order, nthreads,
+                     out, 2);
 }
 
 int ffdo_dtw_pairs_i32(const int32_t *P, const int64_t *p_start, const int64_t *p_len,

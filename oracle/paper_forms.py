@@ -20,6 +20,8 @@ Written from the descriptions in Sec. 3 and Appendix A of Meinert,
   a scan of ``dtw_min(a, x) = min(a, x1) + x2`` seeded with a_1 + x_1.  The
   printed return line lacks the closing "last element" bracket that
   Algorithm 2 has; it is read as the last element of the final row.
+* ``levenshtein``: Algorithm B.2 (edit distance of symbol sequences), with
+  its index vectors read 0-based.
 
 The vector assignment "a_{2..Q} <- min(a_{1..Q-1}, a_{2..Q})" is read as a
 simultaneous assignment (right-hand side evaluated before any element is
@@ -127,6 +129,34 @@ def dtw(d, sequential_shift=False):
     """Algorithm B.1 on a distance matrix d (P x Q): the last element of the
     final row."""
     return dtw_rows(d, sequential_shift)[-1][-1]
+
+
+def levenshtein(d, one_based=False):
+    """Algorithm B.2 on the matrix d_ij = [p_i != q_j] (P x Q).
+
+    levenshtein_min(a, x) = min(a + 1, x); the first row is the same-type
+    scan of levenshtein_min over iota_{1..Q} + d_1; every later row i applies
+    the shifted update a_{2..Q} <- min(a_{1..Q-1} + x_{2..Q}, a_{2..Q} + 1)
+    (simultaneous) and a scan seeded with min(iota_i + x_1, a_1 + 1).  The
+    index vectors are read 0-based (iota_{1..Q} = 0 .. Q-1 for the first
+    row, iota_{2..P} = 1 .. P-1 for the later ones); one_based=True takes
+    the other reading, which tests show to be wrong."""
+    d = [list(map(int, row)) for row in np.asarray(d).tolist()]
+    P, Q = len(d), len(d[0])
+    off = 1 if one_based else 0
+    iota_q = [j + off for j in range(Q)]
+    iota_p = [i + off for i in range(1, P)]
+
+    def lmin(a, x):
+        return min(a + 1, x)
+
+    def nxt(a, ix):
+        i, x = ix
+        b = [a[0]] + [min(a[j - 1] + x[j], a[j] + 1) for j in range(1, len(a))]
+        return scan(lmin, min(i + x[0], b[0] + 1), b[1:])
+
+    first = scan1(lmin, [iota_q[j] + d[0][j] for j in range(Q)])
+    return fold(nxt, first, list(zip(iota_p, d[1:])))[-1]
 
 
 def euclid_f64(a, b):
