@@ -45,6 +45,9 @@ def imin(dim, exact=False, cell="euclidean"):
     free source modifiers); Chebyshev: D subtractions and ceil((D-1)/2)
     three-input maxima.  DTW replaces the max by an add (same count)."""
     sel = 3 if exact else 2
+    if cell == "levenshtein":
+        # a compare and a select per symbol value, then min, +1, +d, min
+        return 2 * dim + 4
     if cell == "manhattan":
         return 2 * dim - 1 + sel
     if cell == "chebyshev":
@@ -267,6 +270,58 @@ def run_dtw(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_levenshtein(args, torch, ffd, ctx, dev, stream):
+    """Levenshtein distance (Appendix B) on 4096 pairs of 4-letter int32
+    symbol sequences with the batched lengths."""
+    import workloads
+    P, p_off, Q, q_off = workloads.symbol_pairs()
+    npairs = len(p_off) - 1
+    cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
+    Pd = torch.from_numpy(P).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    ws = torch.empty(ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(npairs, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.levenshtein_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    errs = ctx.last_errors()
+    g = golden()["levenshtein"]
+    res = out.cpu().numpy()
+    parity_ok = bool(np.array_equal(res[np.array(g["sample_index"])], np.array(g["levenshtein"], dtype=np.int64)))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = cpu_cores()
+        rng = np.random.default_rng(77)
+        sample = np.sort(rng.choice(npairs, size=args.cpu_pairs, replace=False))
+        s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
+        ps, pl = p_off[:-1][sample], np.diff(p_off)[sample]
+        qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
+        order = np.argsort(-(pl * ql))
+        t2 = time.perf_counter()
+        vals = oracle.lev_pairs(P, ps, pl, Q, qs, ql, cores, order)
+        cw = time.perf_counter() - t2
+        cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"{args.cpu_pairs} of the 4096 pairs (seed 77), {s_cells} cells, int64 rolling-row "
+                         f"Levenshtein oracle, longest first on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.array_equal(vals, res[sample]))}
+    return {
+        "metric": "levenshtein_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f64",
+        "config": {"workload": "levenshtein: 4096 pairs of int32 symbol sequences over 4 letters, lengths "
+                               "uniform in [64, 2048], q = p resampled with 10% redrawn (seed 8)",
+                   "npairs": npairs, "cells": cells, "global_batch": npairs},
+        "parity": {"exact": True, "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, 1, True, family="op_kernel", suffix=", 8", cell="levenshtein"),
+        "cpu_baseline": cpu,
+    }
+
+
 def run_pair(args, torch, ffd, ctx, dev, stream, which):
     import workloads
     if which == "plain":
@@ -478,7 +533,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw"],
+    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
@@ -522,6 +577,8 @@ def main():
         r = run_serving(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "dtw":
         r = run_dtw(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "levenshtein":
+        r = run_levenshtein(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {

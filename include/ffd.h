@@ -197,10 +197,29 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
                       int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,
                       void *stream);
 
+/* Levenshtein distance (Appendix B, Algorithm B.2) of sequences of int32
+ * symbols (a symbol is `dim` int32 values; two symbols are equal when every
+ * value is): the minimum number of insertions, deletions and substitutions,
+ * the recurrence
+ *     M_ij = min{ M_{i-1,j} + 1, M_{i,j-1} + 1, M_{i-1,j-1} + [p_i != q_j] }
+ * with M_{-1,j} = j + 1, M_{i,-1} = i + 1, M_{-1,-1} = 0 (0-based; the
+ * algorithm's index vectors read 0-based), result M_PQ, exact int64.  The
+ * calls take the arguments of ffd_distance_i32, ffd_batch_i32 and
+ * ffd_cross_i32 without the metric, with the same layouts, workspace sizes
+ * and errors. */
+int ffd_levenshtein_distance(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q,
+                             int64_t m, int32_t dim, int64_t *out, void *stream);
+int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off,
+                          const int32_t *Q, const int64_t *q_off, int64_t npairs, int32_t dim,
+                          int64_t *out, void *workspace, size_t ws_bytes, void *stream);
+int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq,
+                          const int32_t *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
+                          int64_t *out, void *workspace, size_t ws_bytes, void *stream);
+
 /* Device workspace needed by ffd_batch (op = FFD_OP_BATCH: a_off = p_off,
  * na = npairs, b_off = q_off, nb = npairs) or ffd_cross (op = FFD_OP_CROSS:
  * a_off = q_off, na = nq, b_off = db_off, nb = ndb), and by their int32 and
- * DTW forms: the size covers all of them.  Writes *bytes.
+ * DTW and Levenshtein forms: the size covers all of them.  Writes *bytes.
  * Errors: FFD_E_INVALID for a bad op, NULL or bad offsets. */
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                        const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);
@@ -208,8 +227,9 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
 /* Introspection (tests and tools): the plan that a call would launch.
  *   op: FFD_OP_BATCH (a_off = p_off, b_off = q_off, na = nb = npairs),
  *   FFD_OP_CROSS (a_off = q_off, b_off = db_off) or FFD_OP_PAIR (a_off =
- *   {0, n}, b_off = {0, m}, na = nb = 1: ffd_distance); dtw selects the DTW
- *   calls; metric and exact (int32 coordinates) as in the calls.  HOST
+ *   {0, n}, b_off = {0, m}, na = nb = 1: ffd_distance); measure 0 for the
+ *   Frechet calls, 1 for DTW, 2 for Levenshtein (exact = 1); metric and
+ *   exact (int32 coordinates) as in the calls.  HOST
  *   arrays only; nothing is launched, and a planning-only context works.
  *   *summary receives the launch shape; jobs (ffd_plan_job[jobs_cap], may be
  *   NULL) receives the job table grouped by wave, wave_jobs (int32
@@ -251,7 +271,7 @@ typedef struct ffd_plan_job { /* 64 bytes */
 } ffd_plan_job;
 int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                       const int64_t *b_off, int64_t nb, int32_t dim, int32_t exact,
-                      int32_t dtw, int32_t metric, ffd_plan_summary *summary,
+                      int32_t measure, int32_t metric, ffd_plan_summary *summary,
                       ffd_plan_job *jobs, int64_t jobs_cap, int32_t *wave_jobs,
                       int64_t wave_jobs_cap);
 

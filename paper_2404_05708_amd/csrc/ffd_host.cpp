@@ -66,6 +66,7 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
   int cell = op >> 1;
   double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell >= 2 ? 1 : 0);
+  if (op == 8) per_cell = 3 * D + 4;  // Levenshtein: a compare and a 64-bit select per coordinate, 4 FP64 ops
   double I = (double)R * per_cell + 8.0;
   double lone = 104.0 + 3.9 * I;
   double shared = 0.75 * std::max(1.0, waves_per_simd) * I * 4.0;
@@ -1170,6 +1171,33 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
                       (hipStream_t)stream, true);
 }
 
+// Levenshtein distance (Appendix B, Algorithm B.2) of int32 symbol
+// sequences: the same calls with the Levenshtein kernels (kernel op 8).
+int ffd_levenshtein_distance(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
+                             int64_t *out, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, 8);
+  return pair_common(ctx, p, n, q, m, dim, FFD_SQEUCLIDEAN, out, (hipStream_t)stream, true);
+}
+
+int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
+                          const int64_t *q_off, int64_t npairs, int32_t dim, int64_t *out, void *workspace,
+                          size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, 8);
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
+                      (hipStream_t)stream, true);
+}
+
+int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
+                          const int64_t *db_off, int64_t ndb, int32_t dim, int64_t *out, void *workspace,
+                          size_t ws_bytes, void *stream) {
+  if (!ctx) return FFD_E_INVALID;
+  MeasureScope scope(ctx, 8);
+  return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
+                      (hipStream_t)stream, true);
+}
+
 // Dynamic time warping (Appendix B): the same calls with the DTW kernels.
 
 int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim,
@@ -1225,7 +1253,7 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
 static_assert(sizeof(ffd_plan_job) == sizeof(Job), "plan job layout");
 
 int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
-                      int32_t dim, int32_t exact, int32_t dtw, int32_t metric, ffd_plan_summary *summary,
+                      int32_t dim, int32_t exact, int32_t measure, int32_t metric, ffd_plan_summary *summary,
                       ffd_plan_job *jobs, int64_t jobs_cap, int32_t *wave_jobs, int64_t wave_jobs_cap) {
   if (!ctx || !summary) return FFD_E_INVALID;
   int rc = check_common(ctx, dim, metric, exact != 0);
@@ -1236,7 +1264,9 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   if (op == FFD_OP_PAIR && na != 1) return fail(ctx, FFD_E_INVALID, "a pair has one curve per side");
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
-  MeasureScope scope(ctx, op_of(dtw != 0, metric));
+  if (measure < 0 || measure > 2) return fail(ctx, FFD_E_INVALID, "unknown measure");
+  if (measure == 2 && !exact) return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein takes int32 symbols");
+  MeasureScope scope(ctx, measure == 2 ? 8 : op_of(measure == 1, metric));
   Plan pl;
   if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, dim, exact != 0, pl);
   else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, dim, exact != 0, pl);
@@ -1278,9 +1308,9 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   // one size for every path: float and int32 coordinates, every measure and
   // ground distance (kernel ops 0, 1, 3, ..., 7)
   size_t worst = 0;
-  for (int ms = 0; ms < 8; ++ms)
+  for (int ms = 0; ms < 9; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
-      if (ms == 2 || (ms == 3 && ex == 1)) continue;  // no such kernel
+      if (ms == 2 || (ms == 3 && ex == 1) || (ms == 8 && ex == 0)) continue;  // no such kernel
       MeasureScope scope(ctx, ms);
       const Plan *pl;
       uint64_t key;

@@ -26,13 +26,15 @@ FFD_DECLARE_OP(4)
 FFD_DECLARE_OP(5)
 FFD_DECLARE_OP(6)
 FFD_DECLARE_OP(7)
+FFD_DECLARE_OP(8)
 #undef FFD_DECLARE_OP
 hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 
 // The kernel variant with LDS rings between waves serves launches whose
 // plan uses them (a.rings); every other launch takes the plain variant.
 // `op` = measure + 2 * cell (measure 0 Frechet, 1 DTW; cell 0 squared
-// Euclidean, 1 Euclidean per cell, 2 Manhattan, 3 Chebyshev).  Op 0 is the
+// Euclidean, 1 Euclidean per cell, 2 Manhattan, 3 Chebyshev); op 8 is the
+// Levenshtein distance (int32 symbols).  Op 0 is the
 // Frechet kernel on squared cells (with or without LDS rings); every other
 // op has its own kernel family and never uses rings.
 inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
@@ -46,6 +48,7 @@ inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, i
     case 5: return launch_op_5(exact, R, D, a, wpb, coop, st);
     case 6: return launch_op_6(exact, R, D, a, wpb, coop, st);
     case 7: return launch_op_7(exact, R, D, a, wpb, coop, st);
+    case 8: return launch_op_8(exact, R, D, a, wpb, coop, st);
   }
   return hipErrorInvalidValue;
 }
@@ -60,6 +63,7 @@ inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds
     case 5: return occupancy_op_5(exact, R, D, wpb, lds, blocks_per_cu);
     case 6: return occupancy_op_6(exact, R, D, wpb, lds, blocks_per_cu);
     case 7: return occupancy_op_7(exact, R, D, wpb, lds, blocks_per_cu);
+    case 8: return occupancy_op_8(exact, R, D, wpb, lds, blocks_per_cu);
   }
   return hipErrorInvalidValue;
 }

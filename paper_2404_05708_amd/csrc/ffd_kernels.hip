@@ -8,6 +8,7 @@ namespace ffd {
 namespace {
 struct PlainSel {
   static constexpr bool kExact = true;
+  static constexpr bool kFloat = true;
   template <int R, int D, typename V>
   static auto kernel() { return &stream_kernel<R, D, V, false>; }
 };

@@ -3,7 +3,8 @@
 // This unit is compiled once per OP (-DFFD_OP=...), in parallel: 1 DTW of
 // squared Euclidean cells, 3 DTW of Euclidean cells (float32 only), 4
 // Frechet on Manhattan cells, 5 DTW on Manhattan cells, 6 Frechet on
-// Chebyshev cells, 7 DTW on Chebyshev cells.
+// Chebyshev cells, 7 DTW on Chebyshev cells, 8 Levenshtein (int32 symbols
+// only).
 #include "ffd_launch.h"
 
 #ifndef FFD_OP
@@ -17,8 +18,10 @@ namespace ffd {
 
 namespace {
 struct OpSel {
-  // int32 coordinates (exact FP64 values) for every op but Euclidean cells
+  // int32 coordinates (exact FP64 values) for every op but Euclidean cells;
+  // float32 coordinates for every op but Levenshtein
   static constexpr bool kExact = FFD_OP != 3;
+  static constexpr bool kFloat = FFD_OP != 8;
   template <int R, int D, typename V>
   static auto kernel() { return &op_kernel<R, D, V, FFD_OP>; }
 };

@@ -64,7 +64,8 @@ struct Launcher {
     } else {
       if (exact) return hipErrorInvalidValue;
     }
-    return launch_v<float>(R, D, a, wpb, coop, st);
+    if constexpr (Sel::kFloat) return launch_v<float>(R, D, a, wpb, coop, st);
+    return hipErrorInvalidValue;
   }
 
   // Workgroups of `wpb` waves using `lds` bytes that one CU holds at once.
@@ -74,7 +75,8 @@ struct Launcher {
     } else {
       if (exact) return hipErrorInvalidValue;
     }
-    return occ_v<float>(R, D, wpb, lds, blocks);
+    if constexpr (Sel::kFloat) return occ_v<float>(R, D, wpb, lds, blocks);
+    return hipErrorInvalidValue;
   }
 };
 

@@ -37,11 +37,15 @@
 // argument OP = measure + 2 * cell selects them: measure 0 Frechet, 1 DTW;
 // cell 0 squared Euclidean, 1 Euclidean (the hardware square root per cell,
 // DTW only: the Frechet kernel takes one root per pair), 2 Manhattan
-// (sum of |dk|), 3 Chebyshev (max of |dk|).  Sums are not selections, so
-// row padding is no longer exact: the DTW
-// corner is 0, and the result M_{n-1,m-1} is taken from the lane holding row
-// n-1 at the moment it enters the next task, when its registers still hold
-// the last column of the old one.
+// (sum of |dk|), 3 Chebyshev (max of |dk|); OP 8 is the Levenshtein
+// distance of int32 symbol sequences (Appendix B, Algorithm B.2).  Sums are
+// not selections, so row padding is no longer exact: the DTW corner is 0,
+// and the result M_{n-1,m-1} is taken from the lane holding row n-1 at the
+// moment it enters the next task, when its registers still hold the last
+// column of the old one.  Levenshtein also sets the new task's first
+// (separator) column to its boundary M_{i,-1} = i + 1 at that moment; the
+// recurrence keeps it through the other separators, and lane 0's top
+// boundary is the ramp M_{-1,j} = j + 1 after a 0 corner.
 //
 // The squared distance is evaluated as d2 = dx*dx, then d2 = fma(dk, dk, d2)
 // for k >= 1, in the value type; the recurrence runs on d2 and the Euclidean
@@ -123,9 +127,10 @@ struct Desc {
   int32_t L;           // stream length
   int32_t hin, hout;   // boundary modes
   int32_t out_lo, out_hi;  // result index, -1 = none
-  int32_t drain;       // bit 0: padding task after the last job; DTW also packs the
-                       // register (bits 1-3) and lane (bits 4-9) of the curve's last
-                       // row in this band and the separator count (bits 10+)
+  int32_t drain;       // bit 0: padding task after the last job; bits 1-3 and 4-9: the
+                       // register and lane of the curve's last row in this band;
+                       // bits 10-16: the separator count; bits 17+: the band
+                       // (Levenshtein only)
   int32_t flag_in, flag_out;
   int32_t rel_in;      // entries of the incoming link before this task's row
   int32_t rel_out;     // entries of the outgoing link before this task's row
@@ -155,6 +160,11 @@ template <int R, int D, typename V, bool RINGS, int OP = 0>
 struct Stream {
   static constexpr bool DTW = (OP & 1) != 0;
   static constexpr int CELL = OP >> 1;
+  // OP 8: Levenshtein distance of int32 symbol sequences (cell 4:
+  // [p_i != q_j]; M_ij = min{M_{i-1,j} + 1, M_{i,j-1} + 1, M_{i-1,j-1} + d_ij})
+  static constexpr bool LEV = OP == 8;
+  // the result is taken from the lane of the curve's last row at its switch
+  static constexpr bool CAP = DTW || LEV;
   using N = Num<V>;
   using C = typename N::Coord;
   static constexpr int DP = D == 3 ? 4 : D;
@@ -342,10 +352,11 @@ struct Stream {
       d.rel_in = d.rel_out = (int32_t)f.link_rel;
       d.L = t.L; d.hin = hin; d.hout = hout;
       {
-        // separator count; the register and lane of the curve's last row (DTW)
+        // separator count; the register and lane of the curve's last row
+        // (DTW, Levenshtein); the band (Levenshtein)
         int64_t last = f.n - 1 - (int64_t)b * kWave * R;
         int32_t lr = last < kWave * R ? (int32_t)last : kWave * R - 1;
-        d.drain = ((lr % R) << 1) | ((lr / R) << 4) | ((int32_t)(t.L - t.m) << 10);
+        d.drain = ((lr % R) << 1) | ((lr / R) << 4) | ((int32_t)(t.L - t.m) << 10) | (LEV ? b << 17 : 0);
       }
       d.out_lo = (int32_t)(uint32_t)(uint64_t)oi;
       d.out_hi = (int32_t)(uint32_t)((uint64_t)oi >> 32);
@@ -526,6 +537,7 @@ struct Stream {
   // lane-0 cursor (task containing the group being loaded) and window start
   int32_t id0, S0, L0, g0, src0, win0, win_cur;
   int32_t pre0;  // separator columns of lane 0's task
+  V bnd0;        // Levenshtein: boundary value M_{i,-1} = i + 1 of this lane's first row in lane 0's task
   int32_t rc63, ls63;  // DTW: register and lane of the last row of lane 63's task
   V cap;         // DTW: this lane's value of the last column, taken at its task switch
   // lane-63 cursor: task containing column t0 - 64
@@ -548,11 +560,12 @@ struct Stream {
       // others land in the sink
       hout[u] = bottom;
       if (u == kGroup - 1) res = bottom;
-      if (DTW && window) {
+      bool sw = false;
+      if (CAP && window) {
         // the lane enters the new task: its registers hold the old task's
-        // last column (the result of DTW is taken here), and it takes the
-        // new task's rows
-        bool sw = lane == t0 + u - win;
+        // last column (the result of DTW or Levenshtein is taken here), and
+        // it takes the new task's rows
+        sw = lane == t0 + u - win;
         V sel = Mp[0];
 #pragma unroll
         for (int r = 1; r < R; ++r) sel = rc == r ? Mp[r] : sel;
@@ -588,17 +601,31 @@ struct Stream {
           }
           if constexpr (CELL == 1) s = N::sqrt_cell(s);
         }
+        if constexpr (LEV) {
+          // d = [p_i != q_j] (separators: 1)
+          s = V(0);
+#pragma unroll
+          for (int k2 = 0; k2 < D; ++k2) s = p[r][k2] != g.q[u].c[k2] ? V(1) : s;
+        }
         dd[r] = s;
       }
       V above = up, diag = upPrev;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         V v;
-        if constexpr (DTW) v = N::mn(N::mn(above, diag), Mp[r]) + dd[r];
+        if constexpr (LEV) v = N::mn(N::mn(above, Mp[r]) + V(1), diag + dd[r]);
+        else if constexpr (DTW) v = N::mn(N::mn(above, diag), Mp[r]) + dd[r];
         else v = N::mx(N::mn(N::mn(above, diag), Mp[r]), dd[r]);
         diag = Mp[r];
         above = v;
         Mp[r] = v;
+      }
+      if (LEV && window) {
+        // the new task's first (separator) column holds the boundary
+        // M_{i,-1} = i + 1; the recurrence keeps it through the other
+        // separators (above = i, diagonal = i, d = 1)
+#pragma unroll
+        for (int r = 0; r < R; ++r) Mp[r] = sw ? bnd0 + V(r) : Mp[r];
       }
       upPrev = up;
     }
@@ -613,6 +640,7 @@ struct Stream {
     // the task's last separator column c
     int32_t c = S0 + pre0 - 1;
     int32_t og = lay.ghost + (c >= t && c < t + kGroup ? kGroup - (c - t) : 0) * (int32_t)sizeof(V);
+    if constexpr (LEV) og = lay.ghost;  // the ramp written for this group
     int32_t oh = lay.hand + (t - S0) * (int32_t)sizeof(V);
     int32_t ol = lay.lring + (t & (kLinkRing - 1)) * (int32_t)sizeof(V);
     int32_t off = g0 == kHinGhost ? og : (g0 == kHinHand ? oh : ol);
@@ -631,7 +659,8 @@ struct Stream {
       L0 = uni(d.L);
       g0 = uni(d.hin);
       src0 = uni(d.src);
-      pre0 = uni(d.drain) >> 10;
+      pre0 = LEV ? (uni(d.drain) >> 10) & 127 : uni(d.drain) >> 10;  // the band bits are Levenshtein's only
+      if constexpr (LEV) bnd0 = V((int64_t)(uni(d.drain) >> 17) * (kWave * R) + lane * R + 1);
       win0 = t;
       const V *src = pst(id0 & 1) + lane * (R * D);
 #pragma unroll
@@ -757,7 +786,7 @@ struct Stream {
       rel63 = uni(d.rel_out);
       link63 = uni64(d.link_out);
       out63 = (int64_t)(((uint64_t)(uint32_t)uni(d.out_hi) << 32) | (uint32_t)uni(d.out_lo));
-      if constexpr (DTW) {
+      if constexpr (CAP) {
         rc63 = (uni(d.drain) >> 1) & 7;
         ls63 = (uni(d.drain) >> 4) & 63;
       }
@@ -776,6 +805,11 @@ struct Stream {
     if (RINGS && hout63 == kHoutRing) wait_ctr(xctr(wib) + 1, x63 + kGroup - kXRing);
     V *hout = reinterpret_cast<V *>(base + hoff);
     lane0_to(t0);
+    if (LEV && g0 == kHinGhost && lane < kGroup) {
+      // Levenshtein top boundary: 0 over the separators, then M_{-1,j} = j + 1
+      int32_t j1 = t0 + lane - S0 - pre0 + 1;
+      ghost()[lane] = V(j1 > 0 ? j1 : 0);
+    }
     GroupIn g;
     if (RINGS && g0 == kHinRing) {
       // the producing wave must have written this group's entries; once
@@ -791,22 +825,22 @@ struct Stream {
     // Frechet: 16-lane block k takes the task's rows at the start of group
     // k + 1 of the task: its lanes are then on separator columns 1 .. 16 (a
     // task has at least 16), so no real column of either task sees the
-    // wrong rows.  (DTW switches per lane in the window groups, where it
-    // also takes its result.)
-    if (!DTW && t0 > win0 && t0 <= win0 + kWave) {
+    // wrong rows.  (DTW and Levenshtein switch per lane in the window
+    // groups, where they also take their result.)
+    if (!CAP && t0 > win0 && t0 <= win0 + kWave) {
       bool take = (lane >> 4) == ((t0 - win0) >> 4) - 1;
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int k2 = 0; k2 < D; ++k2) p[r][k2] = take ? pn[r][k2] : p[r][k2];
     }
-    bool window = DTW && t0 < win0 + kWave;
+    bool window = CAP && t0 < win0 + kWave;
     if (!window) group<true>(t0, win0, false, g, hout, res, rc63);
     else group<false>(t0, win0, window, g, hout, res, rc63);
     if (RINGS && hout63 == kHoutRing && lane == 0)
       __hip_atomic_store(xctr(wib), x63 + kGroup < L63 ? x63 + kGroup : L63, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    if constexpr (DTW) {
+    if constexpr (CAP) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
     } else if constexpr (CELL != 0) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) N::store_value(a.out, out63, res);
@@ -880,7 +914,7 @@ struct Stream {
     id0 = -1; S0 = 0; L0 = 0; g0 = kHinGhost; src0 = 0; win0 = 0;
     id63 = -1; S63 = -kWave; L63 = kWave; hout63 = kHoutSink; flag63 = -1; rel63 = 0; out63 = -1;
     link63 = 0;
-    pre0 = 1; rc63 = 0; ls63 = kWave - 1; cap = V(0);
+    pre0 = 1; rc63 = 0; ls63 = kWave - 1; cap = V(0); bnd0 = V(1);
 
     for (int32_t t0 = 0;; t0 += kGroup)
       if (!step(t0)) break;

@@ -44,7 +44,8 @@ EXPORTS = (
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
-    "ffd_dtw_cross_i32", "ffd_plan_describe",
+    "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
+    "ffd_levenshtein_cross",
 )
 
 
@@ -143,6 +144,12 @@ def _load():
     lib.ffd_set_split.restype = ctypes.c_int
     lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
     lib.ffd_last_launch.restype = ctypes.c_int
+    lib.ffd_levenshtein_distance.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+    lib.ffd_levenshtein_distance.restype = ctypes.c_int
+    lib.ffd_levenshtein_batch.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, vp, vp, sz, vp]
+    lib.ffd_levenshtein_batch.restype = ctypes.c_int
+    lib.ffd_levenshtein_cross.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, vp, vp, sz, vp]
+    lib.ffd_levenshtein_cross.restype = ctypes.c_int
     lib.ffd_plan_describe.argtypes = [vp, i32, i64p, i64, i64p, i64, i32, i32, i32, i32,
                                       ctypes.POINTER(PlanSummary), vp, i64, vp, i64]
     lib.ffd_plan_describe.restype = ctypes.c_int
@@ -288,13 +295,61 @@ def ffd_dtw_distance_i32(ctx, p, q, metric=FFD_SQEUCLIDEAN, out=None, stream=Non
     return _pair(lib.ffd_dtw_distance_i32, torch.int32, torch.int64, ctx, p, q, metric, out, stream)
 
 
-def ffd_plan_describe(ctx, op, a_off, b_off, dim, exact=False, dtw=False, metric=FFD_EUCLIDEAN):
+def ffd_levenshtein_distance(ctx, p, q, out=None, stream=None):
+    p, pp = _curve(p, torch.int32, "p")
+    q, qp = _curve(q, torch.int32, "q")
+    if p.shape[1] != q.shape[1]:
+        raise ValueError("p and q must have the same dimension")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=p.device)
+    _check(lib.ffd_levenshtein_distance(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1],
+                                        _dev_ptr(out, torch.int64, "out"), _stream(stream)), ctx)
+    return out
+
+
+def ffd_levenshtein_batch(ctx, P, p_off, Q, q_off, out=None, workspace=None, stream=None):
+    P, Pp = _curve(P, torch.int32, "P")
+    Q, Qp = _curve(Q, torch.int32, "Q")
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    po, pop = _offsets(p_off)
+    qo, qop = _offsets(q_off)
+    npairs = len(po) - 1
+    if len(qo) - 1 != npairs:
+        raise ValueError("p_off and q_off must describe the same number of pairs")
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=torch.int64, device=P.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
+    _check(lib.ffd_levenshtein_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], _dev_ptr(out, torch.int64, "out"),
+                                     wsp, wsn, _stream(stream)), ctx)
+    return out[:npairs]
+
+
+def ffd_levenshtein_cross(ctx, Qs, q_off, DB, db_off, out=None, workspace=None, stream=None):
+    Qs, Qp = _curve(Qs, torch.int32, "Qs")
+    DB, Dp = _curve(DB, torch.int32, "DB")
+    if Qs.shape[1] != DB.shape[1]:
+        raise ValueError("Qs and DB must have the same dimension")
+    qo, qop = _offsets(q_off)
+    do, dop = _offsets(db_off)
+    nq, ndb = len(qo) - 1, len(do) - 1
+    if out is None:
+        out = torch.empty(max(nq * ndb, 1), dtype=torch.int64, device=Qs.device)
+    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
+    _check(lib.ffd_levenshtein_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1],
+                                     _dev_ptr(out, torch.int64, "out"), wsp, wsn, _stream(stream)), ctx)
+    return out[:nq * ndb].reshape(nq, ndb)
+
+
+def ffd_plan_describe(ctx, op, a_off, b_off, dim, exact=False, dtw=False, metric=FFD_EUCLIDEAN,
+                      levenshtein=False):
     """The plan a call would launch: (summary dict, job table as a PLAN_JOB
     array, first job of each wave as int32[waves + 1]).  Host-only."""
+    measure = 2 if levenshtein else (1 if dtw else 0)
     ao, aop = _offsets(a_off)
     bo, bop = _offsets(b_off)
     sm = PlanSummary()
-    args = (ctx, int(op), aop, len(ao) - 1, bop, len(bo) - 1, int(dim), int(bool(exact)), int(bool(dtw)),
+    args = (ctx, int(op), aop, len(ao) - 1, bop, len(bo) - 1, int(dim), int(bool(exact)), measure,
             int(metric), ctypes.byref(sm))
     _check(lib.ffd_plan_describe(*args, None, 0, None, 0), ctx)
     jobs = np.zeros(sm.jobs, dtype=PLAN_JOB)
@@ -499,6 +554,15 @@ class Context:
 
     def dtw_cross_i32(self, Qs, q_off, DB, db_off, metric=FFD_SQEUCLIDEAN, **kw):
         return ffd_dtw_cross_i32(self.handle, Qs, q_off, DB, db_off, metric, **kw)
+
+    def levenshtein(self, p, q, **kw):
+        return ffd_levenshtein_distance(self.handle, p, q, **kw)
+
+    def levenshtein_batch(self, P, p_off, Q, q_off, **kw):
+        return ffd_levenshtein_batch(self.handle, P, p_off, Q, q_off, **kw)
+
+    def levenshtein_cross(self, Qs, q_off, DB, db_off, **kw):
+        return ffd_levenshtein_cross(self.handle, Qs, q_off, DB, db_off, **kw)
 
     def autotune_batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_autotune_batch(self.handle, P, p_off, Q, q_off, metric, **kw)

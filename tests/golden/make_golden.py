@@ -74,6 +74,18 @@ def main():
         "sqeuclidean": [float(v) for v in dvals],
     }
 
+    # Levenshtein (Appendix B) on the symbol-sequence workload
+    SP, spo, SQ, sqo = workloads.symbol_pairs()
+    rng = np.random.default_rng(1003)
+    sidx = sample_indices(rng, 60, len(spo) - 1)
+    lv = oracle.lev_pairs(SP, spo[:-1][sidx], np.diff(spo)[sidx], SQ, sqo[:-1][sidx], np.diff(sqo)[sidx],
+                          nthreads)
+    out["levenshtein"] = {
+        "workload": "symbol_pairs(seed=8): 4096 pairs of 4-letter int32 sequences, lengths in [64, 2048]",
+        "sample_index": [int(i) for i in sidx],
+        "levenshtein": [int(v) for v in lv],
+    }
+
     Qs, qo, DB, dbo = workloads.cross_int()
     rng = np.random.default_rng(1002)
     ii = rng.integers(0, len(qo) - 1, size=256)

@@ -181,6 +181,24 @@ def test_metric_checks(planner):
     assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, ffd.FFD_EUCLIDEAN, FAKE, None) == ffd.FFD_E_UNSUPPORTED
 
 
+def test_levenshtein_argument_checks(planner):
+    L = ffd.lib
+    assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_levenshtein_distance(planner, None, 5, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_levenshtein_distance(planner, FAKE, 0, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 5, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    good = np.array([0, 3, 5, 9], dtype=np.int64)
+    assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(good), FAKE, _i64p(good), 3, 1, FAKE, FAKE, 1 << 20,
+                                   None) == ffd.FFD_E_DEVICE
+    qo = np.array([0, 4, 9], dtype=np.int64)
+    assert L.ffd_levenshtein_cross(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(good), 3, 1, FAKE, FAKE, 1 << 20,
+                                   None) == ffd.FFD_E_DEVICE
+    P, p_off, Q, q_off = workloads.random_pairs(5, 60, 1, 9000, dim=1)
+    need = ffd.ffd_workspace_size(planner, ffd.FFD_OP_BATCH, p_off, q_off, 1)
+    assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 60, 1, FAKE, FAKE, need,
+                                   None) == ffd.FFD_E_DEVICE
+
+
 def test_set_tuning_validation(planner):
     ffd.ffd_set_tuning(planner, 4, 2)
     ffd.ffd_set_tuning(planner, 0, 0)

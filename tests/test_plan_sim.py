@@ -81,13 +81,14 @@ def test_single_pairs(planner, n, m, dim):
         assert sm["rings"] == 1 and sm["waves"] == 512
 
 
-@pytest.mark.parametrize("dtw,metric", [(True, 1), (True, 0), (False, 2), (True, 3)])
-def test_other_kernels(planner, dtw, metric):
+@pytest.mark.parametrize("dtw,metric,lev", [(True, 1, False), (True, 0, False), (False, 2, False),
+                                            (True, 3, False), (False, 1, True)])
+def test_other_kernels(planner, dtw, metric, lev):
     P, p_off, Q, q_off = workloads.random_pairs(412, 200, 1, 6000, dim=2)
-    sm = batch_case(planner, p_off, q_off, dtw=dtw, metric=metric)
+    sm = batch_case(planner, p_off, q_off, dtw=dtw, metric=metric, exact=lev, levenshtein=lev)
     assert sm["rings"] == 0
     smp, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 40000], [0, 30000], 2, dtw=dtw,
-                                          metric=metric)
+                                          metric=metric, exact=lev, levenshtein=lev)
     plan_sim.check(smp, jobs, wj, (np.array([0, 40000]), np.array([0, 30000])), [0])
     assert smp["rings"] == 0
 

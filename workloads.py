@@ -18,6 +18,10 @@ Workloads (the shapes of the benchmark configurations):
   sigma 1 in natural log, clipped to [32, 8192]), seeds 5, 6, 7.
 * ``paper_walk``     the paper's random walk with steps uniform in
                      {-1, 0, +1} per coordinate (Sec. 4 experiments).
+* ``symbol_pairs``   4096 pairs of int32 symbol sequences over a 4-letter
+                     alphabet with the batched lengths; q is p resampled to
+                     length m with 10% of its symbols redrawn, seed 8
+                     (Levenshtein distance, Appendix B).
 
 A random walk is the cumulative sum of i.i.d. N(0, 1) steps in FP64 (the
 first point is the first step), rounded once to float32.
@@ -27,7 +31,7 @@ import numpy as np
 __all__ = [
     "walk", "paper_walk", "plain_pair", "batched", "large_pair", "cross_int",
     "lognormal_lengths", "serving_db", "serving_queries", "poisson_arrivals",
-    "random_pairs", "concat",
+    "random_pairs", "concat", "symbol_pairs",
 ]
 
 
@@ -159,6 +163,30 @@ def random_pairs(seed, npairs, lo, hi, dim=2, kind="walk"):
             qs.append(rng.integers(-(1 << 15), 1 << 15, size=(int(m[k]), dim), dtype=np.int32))
         else:
             raise ValueError(kind)
+    P, p_off = concat(ps)
+    Q, q_off = concat(qs)
+    return P, p_off, Q, q_off
+
+
+def symbol_pairs(seed=8, npairs=4096, lo=64, hi=2048, alphabet=4, redraw=0.1):
+    """Draw order: n[npairs], m[npairs] uniform in [lo, hi]; then per pair:
+    p (n symbols uniform in [0, alphabet)), the resampling of p to m symbols
+    (index floor(j * n / m)), a redraw mask (Bernoulli(redraw), m values) and
+    the redrawn symbols (m values).  Returns int32 P, p_off, Q, q_off with
+    one coordinate per symbol."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(lo, hi + 1, size=npairs)
+    m = rng.integers(lo, hi + 1, size=npairs)
+    ps, qs = [], []
+    for k in range(npairs):
+        p = rng.integers(0, alphabet, size=int(n[k]))
+        idx = (np.arange(int(m[k])) * int(n[k])) // int(m[k])
+        q = p[idx].copy()
+        mask = rng.random(int(m[k])) < redraw
+        new = rng.integers(0, alphabet, size=int(m[k]))
+        q[mask] = new[mask]
+        ps.append(p.astype(np.int32).reshape(-1, 1))
+        qs.append(q.astype(np.int32).reshape(-1, 1))
     P, p_off = concat(ps)
     Q, q_off = concat(qs)
     return P, p_off, Q, q_off
