@@ -14,6 +14,10 @@ not counted).
          (squared Euclidean, int64 results, bit-exact)
   serving  Poisson-arrival queries against a resident 10,000-curve database
          through the ffd_server calls: p50/p99 latency at a fixed rate
+  dtw    DTW (Appendix B) with squared Euclidean cells on the batched pairs
+  levenshtein  Levenshtein distance (Appendix B) of 4096 int32 symbol pairs
+  geo    4096 pairs of (latitude, longitude) walks on the sphere under the
+         great-circle distance (metric FFD_HAVERSINE)
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (VALU issue rate: the path has no contraction and moves O(n+m) bytes per
@@ -322,6 +326,62 @@ def run_levenshtein(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_geo(args, torch, ffd, ctx, dev, stream):
+    """The Frechet distance under the great-circle ground distance on 4096
+    pairs of (latitude, longitude) walks on the sphere with the batched
+    lengths; the kernel runs on FP64 unit vectors (D = 3)."""
+    import workloads
+    P, p_off, Q, q_off = workloads.geo_pairs()
+    npairs = len(p_off) - 1
+    cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
+    Pd = torch.from_numpy(P).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    ws = torch.empty(ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, 2), dtype=torch.uint8, device=dev)
+    out = torch.empty(npairs, dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_HAVERSINE, out=out, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    errs = ctx.last_errors()
+    g = golden()["batched_haversine"]
+    res = out.cpu().numpy()
+    want = np.array(g["haversine"])
+    parity_ok = bool(np.all(np.abs(res[np.array(g["sample_index"])] - want) <= TOL * want + 1e-12))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = cpu_cores()
+        nsample = min(args.cpu_pairs, 1024)
+        rng = np.random.default_rng(77)
+        sample = np.sort(rng.choice(npairs, size=nsample, replace=False))
+        s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
+        ps, pl = p_off[:-1][sample], np.diff(p_off)[sample]
+        qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
+        order = np.argsort(-(pl * ql))
+        t2 = time.perf_counter()
+        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.HAVERSINE, cores, order)
+        cw = time.perf_counter() - t2
+        cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"{nsample} of the 4096 pairs (seed 77), {s_cells} cells, FP64 haversine rolling-row "
+                         f"oracle, longest first on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals + 1e-12))}
+    return {
+        "metric": "geo_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f64",
+        "config": {"workload": "geo: 4096 pairs of (latitude, longitude) random walks on the sphere, steps "
+                               "N(0, (2e-3 rad)^2), n and m uniform in [64, 2048], q = p resampled + "
+                               "N(0, (2e-4 rad)^2), great-circle distance (seed 9)",
+                   "npairs": npairs, "cells": cells, "global_batch": npairs},
+        "parity": {"tolerance": "2e-6 relative + 1e-12 rad", "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, 3, True, family="op_kernel", suffix=", 10"),
+        "cpu_baseline": cpu,
+    }
+
+
 def run_pair(args, torch, ffd, ctx, dev, stream, which):
     import workloads
     if which == "plain":
@@ -533,7 +593,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein"],
+    ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
+                                           "geo"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
@@ -579,6 +640,8 @@ def main():
         r = run_dtw(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "levenshtein":
         r = run_levenshtein(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "geo":
+        r = run_geo(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {

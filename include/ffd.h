@@ -71,12 +71,23 @@ extern "C" {
 #define FFD_E_TIMEOUT (-6)     /* serving: wait timed out                           */
 
 /* Ground distances (Sec. 2: f(p_i, q_j); Sec. 3: the method makes no
- * assumption about it).  int32 calls take every metric but FFD_EUCLIDEAN;
- * the serving calls take FFD_EUCLIDEAN and FFD_SQEUCLIDEAN. */
+ * assumption about it).  int32 calls take every metric but FFD_EUCLIDEAN
+ * and FFD_HAVERSINE; the serving calls take FFD_EUCLIDEAN and
+ * FFD_SQEUCLIDEAN.
+ * FFD_HAVERSINE is the great-circle distance on the unit sphere (the
+ * central angle, in radians; multiply by the sphere's radius for a length)
+ * between points given as (latitude, longitude) in radians, dim = 2.  Only
+ * the float32 Frechet calls (ffd_distance, ffd_batch, ffd_cross and their
+ * autotuners) take it; the DTW calls return FFD_E_UNSUPPORTED.  Internally
+ * each point becomes its FP64 unit vector, the sweep runs on squared chord
+ * lengths (the angle 2 asin(chord / 2) increases with the chord, so Eq. (1)
+ * selects the same cells) and the angle is computed once per pair in FP64;
+ * ffd_last_launch then reports dim 3 and the FP64 value type. */
 #define FFD_EUCLIDEAN 0   /* ||p_i - q_j||_2                          */
 #define FFD_SQEUCLIDEAN 1 /* ||p_i - q_j||_2^2                        */
 #define FFD_MANHATTAN 2   /* sum_k |p_ik - q_jk|                      */
 #define FFD_CHEBYSHEV 3   /* max_k |p_ik - q_jk|                      */
+#define FFD_HAVERSINE 4   /* central angle of (lat, lon) points       */
 
 /* Largest supported dimension D. */
 #define FFD_MAX_DIM 4
@@ -115,14 +126,15 @@ const char *ffd_version(void);
  * A pair short enough for one wavefront needs no device memory; a long pair
  * is split into bands over many wavefronts, using device scratch memory that
  * the context allocates on first need and keeps until ffd_destroy.
- * Errors: FFD_E_INVALID for NULL pointers, n < 1, m < 1, dim < 1 or an
- * unknown metric; FFD_E_UNSUPPORTED for dim > FFD_MAX_DIM. */
+ * Errors: FFD_E_INVALID for NULL pointers, n < 1, m < 1, dim < 1, an
+ * unknown metric or FFD_HAVERSINE with dim != 2; FFD_E_UNSUPPORTED for
+ * dim > FFD_MAX_DIM. */
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
                  int32_t dim, int32_t metric, float *out, void *stream);
 
 /* One pair with int32 coordinates, exact: out [1] int64, device.  metric is
- *   FFD_SQEUCLIDEAN, FFD_MANHATTAN or FFD_CHEBYSHEV (FFD_EUCLIDEAN:
- *   FFD_E_UNSUPPORTED).  Other errors as ffd_distance. */
+ *   FFD_SQEUCLIDEAN, FFD_MANHATTAN or FFD_CHEBYSHEV (FFD_EUCLIDEAN and
+ *   FFD_HAVERSINE: FFD_E_UNSUPPORTED).  Other errors as ffd_distance. */
 int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m,
                      int32_t dim, int32_t metric, int64_t *out, void *stream);
 
@@ -228,16 +240,17 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
  *   op: FFD_OP_BATCH (a_off = p_off, b_off = q_off, na = nb = npairs),
  *   FFD_OP_CROSS (a_off = q_off, b_off = db_off) or FFD_OP_PAIR (a_off =
  *   {0, n}, b_off = {0, m}, na = nb = 1: ffd_distance); measure 0 for the
- *   Frechet calls, 1 for DTW, 2 for Levenshtein (exact = 1); metric and
- *   exact (int32 coordinates) as in the calls.  HOST
+ *   Frechet calls, 1 for DTW, 2 for Levenshtein (exact = 1); metric,
+ *   dim and exact (int32 coordinates) as in the calls (FFD_HAVERSINE:
+ *   dim 2, exact 0, measure 0).  HOST
  *   arrays only; nothing is launched, and a planning-only context works.
  *   *summary receives the launch shape; jobs (ffd_plan_job[jobs_cap], may be
  *   NULL) receives the job table grouped by wave, wave_jobs (int32
  *   [waves + 1], may be NULL) the first job of each wave.  Stream positions
  *   follow from the jobs: each job runs its column curves in order, each
- *   column curve's bands in order; a task lasts 1 + m steps (a separator
- *   and m columns) rounded up to a multiple of 16 and to at least 80; an
- *   idle job (row_sel 2) lasts col_count steps.
+ *   column curve's bands in order; a task lasts 16 + m steps (at least 16
+ *   separators, then the m columns) rounded up to a multiple of 16 and to
+ *   at least 80; an idle job (row_sel 2) lasts col_count steps.
  * Errors: as ffd_batch / ffd_cross / ffd_distance; FFD_E_NOMEM when jobs_cap
  * or the wave_jobs array is too small (the summary is filled first). */
 #define FFD_OP_PAIR 2

@@ -36,6 +36,7 @@ EUCLIDEAN = 0
 SQEUCLIDEAN = 1
 MANHATTAN = 2
 CHEBYSHEV = 3
+HAVERSINE = 4  # (latitude, longitude) in radians, dim 2; float inputs only
 
 _lib = None
 

@@ -26,6 +26,11 @@
  * Manhattan or Chebyshev) and int64 min/max.  Built without fast-math and
  * without FP contraction so that every operation is the one written here.
  *
+ * HAVERSINE is the great-circle distance on the unit sphere between points
+ * given as (latitude, longitude) in radians (dim 2): the central angle
+ *   theta = 2 asin( sqrt( sin^2(dlat / 2) + cos lat_1 cos lat_2 sin^2(dlon / 2) ) ),
+ * the haversine formula, evaluated per cell in FP64 (float inputs only).
+ *
  * A separate "float replica" (ffdo_f32_replica) evaluates the distance with
  * the fixed float32 expression documented below and runs the recurrence in
  * float32; it exists only for a bit-exactness check of the GPU's FP32 path.
@@ -61,12 +66,26 @@
 #define FFDO_SQEUCLIDEAN 1
 #define FFDO_MANHATTAN 2
 #define FFDO_CHEBYSHEV 3
+#define FFDO_HAVERSINE 4
 
 /* ---------------------------------------------------------------- ground distance */
+
+/* Central angle between two (latitude, longitude) points in radians, by
+ * the haversine formula; the haversine is clamped at 1 against rounding. */
+static double haversine_f64(const float *a, const float *b)
+{
+    double lat1 = a[0], lon1 = a[1], lat2 = b[0], lon2 = b[1];
+    double sa = sin(0.5 * (lat2 - lat1));
+    double sb = sin(0.5 * (lon2 - lon1));
+    double h = sa * sa + cos(lat1) * cos(lat2) * (sb * sb);
+    if (h > 1.0) h = 1.0;
+    return 2.0 * asin(sqrt(h));
+}
 
 /* d(p_i, q_j) in FP64 from float32 coordinates (Sec. 2, f(p_i, q_j)). */
 static double cell_f64(const float *pi, const float *qj, int dim, int metric)
 {
+    if (metric == FFDO_HAVERSINE) return haversine_f64(pi, qj);
     double s = 0.0;
     for (int k = 0; k < dim; ++k) {
         double t = (double)pi[k] - (double)qj[k];
@@ -102,7 +121,8 @@ static int check_args(const void *p, int64_t n, const void *q, int64_t m, int di
 {
     if (!p || !q || !out) return FFDO_EINVAL;
     if (n < 1 || m < 1 || dim < 1) return FFDO_EINVAL;
-    if (metric < FFDO_EUCLIDEAN || metric > FFDO_CHEBYSHEV) return FFDO_EINVAL;
+    if (metric < FFDO_EUCLIDEAN || metric > FFDO_HAVERSINE) return FFDO_EINVAL;
+    if (metric == FFDO_HAVERSINE && dim != 2) return FFDO_EINVAL;
     return FFDO_OK;
 }
 
@@ -340,7 +360,7 @@ int ffdo_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int dim, 
 {
     int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
-    if (metric == FFDO_EUCLIDEAN) return FFDO_EINVAL;
+    if (metric == FFDO_EUCLIDEAN || metric == FFDO_HAVERSINE) return FFDO_EINVAL;
     int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
     if (!buf) return FFDO_ENOMEM;
     rc = rolling_i64(p, n, q, m, dim, metric, out, buf, buf + m);
@@ -409,7 +429,7 @@ int ffdo_dtw_i32(const int32_t *p, int64_t n, const int32_t *q, int64_t m, int d
 {
     int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
-    if (metric == FFDO_EUCLIDEAN) return FFDO_EINVAL;
+    if (metric == FFDO_EUCLIDEAN || metric == FFDO_HAVERSINE) return FFDO_EINVAL;
     int64_t *buf = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
     if (!buf) return FFDO_ENOMEM;
     rc = dtw_rolling_i64(p, n, q, m, dim, metric, out, buf, buf + m);
@@ -489,6 +509,7 @@ int ffdo_f32_replica(const float *p, int64_t n, const float *q, int64_t m, int d
 {
     int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
+    if (metric == FFDO_HAVERSINE) return FFDO_EINVAL;
     float *buf = (float *)malloc((size_t)(2 * m) * sizeof(float));
     if (!buf) return FFDO_ENOMEM;
     float *prev = buf, *cur = buf + m;
@@ -520,6 +541,7 @@ int ffdo_dtw_f32_replica(const float *p, int64_t n, const float *q, int64_t m, i
 {
     int rc = check_args(p, n, q, m, dim, metric, out);
     if (rc) return rc;
+    if (metric == FFDO_HAVERSINE) return FFDO_EINVAL;
     float *buf = (float *)malloc((size_t)(2 * m) * sizeof(float));
     if (!buf) return FFDO_ENOMEM;
     float *prev = buf, *cur = buf + m;
@@ -636,7 +658,8 @@ static int pairs_f32(const float *P, const int64_t *p_start, const int64_t *p_le
 {
     int rc = pool_args(P, Q, p_start, p_len, q_start, q_len, npairs, dim, out);
     if (rc) return rc;
-    if (metric < FFDO_EUCLIDEAN || metric > FFDO_CHEBYSHEV) return FFDO_EINVAL;
+    if (metric < FFDO_EUCLIDEAN || metric > FFDO_HAVERSINE) return FFDO_EINVAL;
+    if (metric == FFDO_HAVERSINE && dim != 2) return FFDO_EINVAL;
     struct pool_ctx c;
     memset(&c, 0, sizeof c);
     c.P = P; c.Q = Q; c.p_start = p_start; c.p_len = p_len; c.q_start = q_start;

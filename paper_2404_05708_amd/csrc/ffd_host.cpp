@@ -62,10 +62,11 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // quarters busy.  Other kernels (op = measure + 2 * cell): Euclidean cells
 // add a square root per cell, a quarter-rate instruction (4 issue slots);
 // Manhattan and Chebyshev cells take D subtractions and D - 1 additions or
-// maxima with free absolute values, one instruction less.
+// maxima with free absolute values, one instruction less; great-circle
+// cells (op 10) are FP64 squared chords of unit vectors (D = 3).
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
   int cell = op >> 1;
-  double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell >= 2 ? 1 : 0);
+  double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell == 2 || cell == 3 ? 1 : 0);
   if (op == 8) per_cell = 3 * D + 4;  // Levenshtein: a compare and a 64-bit select per coordinate, 4 FP64 ops
   double I = (double)R * per_cell + 8.0;
   double lone = 104.0 + 3.9 * I;
@@ -100,11 +101,18 @@ int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *n
   return FFD_OK;
 }
 
+// kernel op of the Frechet distance on great-circle cells
+constexpr int kOpGeo = 10;
+
 int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   if (!ctx) return FFD_E_INVALID;
   if (dim < 1) return fail(ctx, FFD_E_INVALID, "dim must be >= 1");
-  if (metric < FFD_EUCLIDEAN || metric > FFD_CHEBYSHEV) return fail(ctx, FFD_E_INVALID, "unknown metric");
+  if (metric < FFD_EUCLIDEAN || metric > FFD_HAVERSINE) return fail(ctx, FFD_E_INVALID, "unknown metric");
   if (dim > FFD_MAX_DIM) return fail(ctx, FFD_E_UNSUPPORTED, "dim exceeds FFD_MAX_DIM");
+  // great-circle requests arrive here with the kernel's shape (geo_shape)
+  if (metric == FFD_HAVERSINE && ctx->measure != kOpGeo)
+    return fail(ctx, FFD_E_UNSUPPORTED, "the great-circle distance is available for the Frechet distance of float32 "
+                                        "curves");
   if (exact && metric == FFD_EUCLIDEAN)
     return fail(ctx, FFD_E_UNSUPPORTED, "int32 coordinates take the squared Euclidean, Manhattan or Chebyshev metric");
   return FFD_OK;
@@ -1116,16 +1124,32 @@ int ffd_set_split(ffd_ctx *ctx, float share) {
 // Kernel op of a call: measure (0 Frechet, 1 DTW) + 2 * cell, where the
 // cell is 0 squared Euclidean (the Frechet kernel also serves Euclidean: one
 // root per pair), 1 Euclidean per cell (DTW), 2 Manhattan, 3 Chebyshev.
-static int op_of(bool dtw, int32_t metric) {
+// Kernel op of a call; `geo` marks the float32 Frechet calls, the only ones
+// that take FFD_HAVERSINE (elsewhere check_common refuses it).
+static int op_of(bool dtw, int32_t metric, bool geo = false) {
+  if (metric == FFD_HAVERSINE) return geo && !dtw ? kOpGeo : 0;
   int cell = metric == FFD_MANHATTAN ? 2 : metric == FFD_CHEBYSHEV ? 3 : (dtw && metric == FFD_EUCLIDEAN ? 1 : 0);
   return (dtw ? 1 : 0) + 2 * cell;
+}
+
+// Great-circle calls take (latitude, longitude) points and run the FP64
+// unit-vector kernel: dim 2 of the call becomes the kernel's D = 3 and its
+// value type FP64 (`exact`); the coordinates stay float32.
+static int geo_shape(ffd_ctx *ctx, int32_t metric, int32_t &dim, bool &exact) {
+  if (metric != FFD_HAVERSINE) return FFD_OK;
+  if (dim != 2) return fail(ctx, FFD_E_INVALID, "great-circle curves take (latitude, longitude) points: dim must be 2");
+  dim = 3;
+  exact = true;
+  return FFD_OK;
 }
 
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim, int32_t metric,
                  float *out, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(false, metric));
-  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
+  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, exact);
 }
 
 int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
@@ -1139,9 +1163,11 @@ int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q
               int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
               void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(false, metric));
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
-                      false);
+                      exact);
 }
 
 int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
@@ -1157,9 +1183,11 @@ int ffd_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t nq, c
               const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out, void *workspace,
               size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(false, metric));
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
-                      (hipStream_t)stream, false);
+                      (hipStream_t)stream, exact);
 }
 
 int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
@@ -1256,21 +1284,23 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
                       int32_t dim, int32_t exact, int32_t measure, int32_t metric, ffd_plan_summary *summary,
                       ffd_plan_job *jobs, int64_t jobs_cap, int32_t *wave_jobs, int64_t wave_jobs_cap) {
   if (!ctx || !summary) return FFD_E_INVALID;
-  int rc = check_common(ctx, dim, metric, exact != 0);
+  if (measure < 0 || measure > 2) return fail(ctx, FFD_E_INVALID, "unknown measure");
+  if (measure == 2 && !exact) return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein takes int32 symbols");
+  MeasureScope scope(ctx, measure == 2 ? 8 : op_of(measure == 1, metric, exact == 0));
+  bool ex = exact != 0;
+  int rc = geo_shape(ctx, metric, dim, ex);
   if (rc) return rc;
+  if ((rc = check_common(ctx, dim, metric, ex))) return rc;
   if (op != FFD_OP_BATCH && op != FFD_OP_CROSS && op != FFD_OP_PAIR) return fail(ctx, FFD_E_INVALID, "unknown op");
   if (na < 1 || nb < 1) return fail(ctx, FFD_E_INVALID, "nothing to plan");
   if ((op == FFD_OP_BATCH || op == FFD_OP_PAIR) && na != nb) return fail(ctx, FFD_E_INVALID, "na != nb");
   if (op == FFD_OP_PAIR && na != 1) return fail(ctx, FFD_E_INVALID, "a pair has one curve per side");
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
-  if (measure < 0 || measure > 2) return fail(ctx, FFD_E_INVALID, "unknown measure");
-  if (measure == 2 && !exact) return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein takes int32 symbols");
-  MeasureScope scope(ctx, measure == 2 ? 8 : op_of(measure == 1, metric));
   Plan pl;
-  if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, dim, exact != 0, pl);
-  else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, dim, exact != 0, pl);
-  else rc = plan_pair(ctx, a_off[1], b_off[1], dim, exact != 0, pl);
+  if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, dim, ex, pl);
+  else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, dim, ex, pl);
+  else rc = plan_pair(ctx, a_off[1], b_off[1], dim, ex, pl);
   if (rc) return rc;
   summary->rows_per_lane = pl.R;
   summary->waves = pl.nwaves;
@@ -1306,16 +1336,17 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
   // one size for every path: float and int32 coordinates, every measure and
-  // ground distance (kernel ops 0, 1, 3, ..., 7)
+  // ground distance (kernel ops 0, 1, 3, ..., 8, and 10 for 2-D curves)
   size_t worst = 0;
-  for (int ms = 0; ms < 9; ++ms)
+  for (int ms = 0; ms <= kOpGeo; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
-      if (ms == 2 || (ms == 3 && ex == 1) || (ms == 8 && ex == 0)) continue;  // no such kernel
+      if (ms == 2 || ms == 9 || (ms == 3 && ex == 1) || (ms == 8 && ex == 0)) continue;  // no such kernel
+      if (ms == kOpGeo && (ex == 0 || dim != 2)) continue;  // FP64 on (latitude, longitude) only
       MeasureScope scope(ctx, ms);
       const Plan *pl;
       uint64_t key;
       PlanCache tmp;
-      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, dim, ex == 1, &pl, key);
+      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, ms == kOpGeo ? 3 : dim, ex == 1, &pl, key);
       if (rc == FFD_E_UNSUPPORTED) continue;
       if (rc) return rc;
       worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
@@ -1334,12 +1365,16 @@ int ffd_autotune_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const
                        void *stream, ffd_tuning *best) {
   if (!ctx) return FFD_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
-  int rc = batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, st, false);
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  int rc = geo_shape(ctx, metric, dim, exact);
+  if (rc) return rc;
+  rc = batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, st, exact);
   if (rc) return rc;  // argument errors, before any tuning
   if (npairs == 0) return FFD_OK;
-  return autotune(ctx, FFD_OP_BATCH, dim, false, p_off, npairs, q_off, npairs, st,
+  return autotune(ctx, FFD_OP_BATCH, dim, exact, p_off, npairs, q_off, npairs, st,
                   [&] { return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes,
-                                            st, false); },
+                                            st, exact); },
                   best);
 }
 
@@ -1348,12 +1383,16 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
                        void *workspace, size_t ws_bytes, void *stream, ffd_tuning *best) {
   if (!ctx) return FFD_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
-  int rc = cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes, st, false);
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  int rc = geo_shape(ctx, metric, dim, exact);
+  if (rc) return rc;
+  rc = cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes, st, exact);
   if (rc) return rc;
   if (nq == 0 || ndb == 0) return FFD_OK;
-  return autotune(ctx, FFD_OP_CROSS, dim, false, q_off, nq, db_off, ndb, st,
+  return autotune(ctx, FFD_OP_CROSS, dim, exact, q_off, nq, db_off, ndb, st,
                   [&] { return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace,
-                                            ws_bytes, st, false); },
+                                            ws_bytes, st, exact); },
                   best);
 }
 

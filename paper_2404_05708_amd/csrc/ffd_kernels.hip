@@ -9,6 +9,7 @@ namespace {
 struct PlainSel {
   static constexpr bool kExact = true;
   static constexpr bool kFloat = true;
+  static constexpr int kOnlyD = 0;
   template <int R, int D, typename V>
   static auto kernel() { return &stream_kernel<R, D, V, false>; }
 };

@@ -1,7 +1,8 @@
 // Launch and occupancy helpers shared by the kernel translation units.  Each
 // unit instantiates one kernel family (a selector `Sel` whose
 // `Sel::kernel<R, D, V>()` names the kernel for a launch shape) for every
-// shape R in {1, 2, 4, 8}, D in {1, ..., 4}, and the value types it supports.
+// shape R in {1, 2, 4, 8}, D in {1, ..., 4} (only D = Sel::kOnlyD when that
+// is not 0), and the value types it supports.
 #ifndef FFD_LAUNCH_H
 #define FFD_LAUNCH_H
 
@@ -22,18 +23,27 @@ struct Launcher {
   // that cannot start.
   template <int R, int D, typename V>
   static hipError_t one(const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
-    const void *k = reinterpret_cast<const void *>(Sel::template kernel<R, D, V>());
-    unsigned blocks = (unsigned)((a.nwaves + wpb - 1) / wpb);
-    unsigned lds = (unsigned)((size_t)a.lds_per_wave * wpb);
-    KernelArgs copy = a;
-    void *args[] = {&copy};
-    if (coop) return hipLaunchCooperativeKernel(k, dim3(blocks), dim3(wpb * kWave), args, lds, st);
-    return hipLaunchKernel(k, dim3(blocks), dim3(wpb * kWave), args, lds, st);
+    if constexpr (Sel::kOnlyD != 0 && D != Sel::kOnlyD) {
+      return hipErrorInvalidValue;
+    } else {
+      const void *k = reinterpret_cast<const void *>(Sel::template kernel<R, D, V>());
+      unsigned blocks = (unsigned)((a.nwaves + wpb - 1) / wpb);
+      unsigned lds = (unsigned)((size_t)a.lds_per_wave * wpb);
+      KernelArgs copy = a;
+      void *args[] = {&copy};
+      if (coop) return hipLaunchCooperativeKernel(k, dim3(blocks), dim3(wpb * kWave), args, lds, st);
+      return hipLaunchKernel(k, dim3(blocks), dim3(wpb * kWave), args, lds, st);
+    }
   }
 
   template <int R, int D, typename V>
   static hipError_t occ(int wpb, size_t lds, int *blocks) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, Sel::template kernel<R, D, V>(), wpb * kWave, lds);
+    if constexpr (Sel::kOnlyD != 0 && D != Sel::kOnlyD) {
+      return hipErrorInvalidValue;
+    } else {
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, Sel::template kernel<R, D, V>(), wpb * kWave,
+                                                          lds);
+    }
   }
 
   template <typename V>

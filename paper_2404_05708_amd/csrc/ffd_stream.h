@@ -38,7 +38,9 @@
 // cell 0 squared Euclidean, 1 Euclidean (the hardware square root per cell,
 // DTW only: the Frechet kernel takes one root per pair), 2 Manhattan
 // (sum of |dk|), 3 Chebyshev (max of |dk|); OP 8 is the Levenshtein
-// distance of int32 symbol sequences (Appendix B, Algorithm B.2).  Sums are
+// distance of int32 symbol sequences (Appendix B, Algorithm B.2); OP 10 is
+// the Frechet distance of curves on the sphere under the great-circle
+// distance (see Stream::HAV).  Sums are
 // not selections, so row padding is no longer exact: the DTW corner is 0,
 // and the result M_{n-1,m-1} is taken from the lane holding row n-1 at the
 // moment it enters the next task, when its registers still hold the last
@@ -57,6 +59,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "ffd_plan.h"
 
@@ -165,8 +169,18 @@ struct Stream {
   static constexpr bool LEV = OP == 8;
   // the result is taken from the lane of the curve's last row at its switch
   static constexpr bool CAP = DTW || LEV;
+  // OP 10: points are (latitude, longitude) in radians, float32, and the
+  // ground distance is the central angle between them.  Each point becomes
+  // its FP64 unit vector u = (cos lat cos lon, cos lat sin lon, sin lat)
+  // when it is staged in LDS (once per band row and once per ring entry),
+  // and the sweep runs on the squared chord |u - v|^2 with D = 3: the angle
+  // 2 asin(|u - v| / 2) is an increasing function of it, so the selections
+  // of Eq. (1) pick the same cells, and the angle is taken once per pair.
+  static constexpr bool HAV = OP == 10;
+  static constexpr int DI = HAV ? 2 : D;  // input values per point
   using N = Num<V>;
-  using C = typename N::Coord;
+  using C = std::conditional_t<HAV, float, typename N::Coord>;
+  static_assert(!HAV || (D == 3 && sizeof(V) == 8), "great-circle sweeps run on FP64 unit vectors");
   static constexpr int DP = D == 3 ? 4 : D;
   struct alignas(sizeof(V) * DP) Pt {
     V c[DP];
@@ -198,11 +212,11 @@ struct Stream {
     FillTask cur, nxt;
   };
   // per-lane prefetch registers
-  C qbuf[D];
+  C qbuf[DI];
   bool qsep;
   V hbuf;
   int32_t hslot;            // stream position of an incoming link value (-1: none)
-  C ptmp[R][D];
+  C ptmp[R][DI];
   int32_t err;
 
   __device__ Stream(const KernelArgs &args, int lane_, int wib_, unsigned char *b_)
@@ -370,9 +384,9 @@ struct Stream {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int64_t ri = r0 + r < f.n ? r0 + r : f.n - 1;
-        const C *pt = X + (f.row_off + ri) * D;
+        const C *pt = X + (f.row_off + ri) * DI;
 #pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) ptmp[r][k2] = pt[k2];
+        for (int k2 = 0; k2 < DI; ++k2) ptmp[r][k2] = pt[k2];
       }
       f.ptmp_pending = 1;
       f.ptmp_slot = id & 1;
@@ -441,9 +455,9 @@ struct Stream {
     if (idx < 0) idx = 0;
     if (drain) { co = 0; idx = 0; sel = 0; }
     const C *X = coords(sel);
-    const C *pt = X + (co + idx) * D;
+    const C *pt = X + (co + idx) * DI;
 #pragma unroll
-    for (int k2 = 0; k2 < D; ++k2) qbuf[k2] = pt[k2];
+    for (int k2 = 0; k2 < DI; ++k2) qbuf[k2] = pt[k2];
   }
 
   // Issue the loads of the incoming boundary values of positions
@@ -478,19 +492,41 @@ struct Stream {
 
   // Write the ring entries loaded by the previous ring_load (for positions
   // [t, t + 64)) and any pending band rows.
+  // HAV: the unit vector of a (latitude, longitude) point, in FP64.
+  __device__ static __forceinline__ void stage(const C *in, V *out) {
+    double sf, cf, sl, cl;
+    sincos((double)in[0], &sf, &cf);
+    sincos((double)in[1], &sl, &cl);
+    out[0] = cf * cl;
+    out[1] = cf * sl;
+    out[2] = sf;
+  }
+
   __device__ void fill_write(FillState &f, int32_t t) {
     Pt e;
+    if constexpr (HAV) {
+      V u[D];
+      stage(qbuf, u);
 #pragma unroll
-    for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : N::cvt(qbuf[k2])) : V(0);
+      for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : u[k2]) : V(0);
+    } else {
+#pragma unroll
+      for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : N::cvt(qbuf[k2])) : V(0);
+    }
     int slot = (t + lane) & (kRing - 1);
     ring()[slot] = e;
     if (slot < kGroup) ring()[slot + kRing] = e;
     if (f.ptmp_pending) {
       V *dst = pst(f.ptmp_slot) + lane * (R * D);
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+      for (int r = 0; r < R; ++r) {
+        if constexpr (HAV) {
+          stage(ptmp[r], dst + r * D);
+        } else {
 #pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) dst[r * D + k2] = N::cvt(ptmp[r][k2]);
+          for (int k2 = 0; k2 < D; ++k2) dst[r * D + k2] = N::cvt(ptmp[r][k2]);
+        }
+      }
       f.ptmp_pending = 0;
     }
   }
@@ -584,7 +620,7 @@ struct Stream {
       for (int r = 0; r < R; ++r) {
         V t = p[r][0] - g.q[u].c[0];
         V s;
-        if constexpr (CELL >= 2) {
+        if constexpr (CELL >= 2 && !HAV) {
           // Manhattan: s = |d0| + |d1| + ...; Chebyshev: max of |dk|
           s = N::abs(t);
 #pragma unroll
@@ -842,6 +878,13 @@ struct Stream {
                          __HIP_MEMORY_SCOPE_WORKGROUP);
     if constexpr (CAP) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
+    } else if constexpr (HAV) {
+      // the central angle of the selected squared chord, in FP64, rounded
+      // once to FP32 (the chord is clamped at the diameter)
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) {
+        double h = 0.5 * __builtin_sqrt((double)res);
+        static_cast<float *>(a.out)[out63] = (float)(2.0 * asin(h < 1.0 ? h : 1.0));
+      }
     } else if constexpr (CELL != 0) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) N::store_value(a.out, out63, res);
     } else {

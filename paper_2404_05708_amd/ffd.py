@@ -31,6 +31,7 @@ FFD_EUCLIDEAN = 0
 FFD_SQEUCLIDEAN = 1
 FFD_MANHATTAN = 2
 FFD_CHEBYSHEV = 3
+FFD_HAVERSINE = 4  # (latitude, longitude) in radians, dim 2; float32 Frechet calls only
 FFD_OP_BATCH = 0
 FFD_OP_CROSS = 1
 FFD_OP_PAIR = 2

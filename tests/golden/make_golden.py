@@ -74,6 +74,22 @@ def main():
         "sqeuclidean": [float(v) for v in dvals],
     }
 
+    # great-circle distances on the sphere workload
+    GP, gpo, GQ, gqo = workloads.geo_pairs()
+    rng = np.random.default_rng(1004)
+    gcells = np.diff(gpo) * np.diff(gqo)
+    gidx = sample_indices(rng, 60, len(gpo) - 1)
+    gidx = sorted(set(gidx) | {int(np.argmax(gcells)), int(np.argmin(gcells))})
+    gv = oracle.dfd_pairs(GP, gpo[:-1][gidx], np.diff(gpo)[gidx], GQ, gqo[:-1][gidx], np.diff(gqo)[gidx],
+                          oracle.HAVERSINE, nthreads)
+    out["batched_haversine"] = {
+        "workload": "geo_pairs(seed=9): 4096 pairs of (latitude, longitude) walks on the sphere, lengths in "
+                    "[64, 2048], great-circle distance (radians)",
+        "total_cells": int(gcells.sum()),
+        "sample_index": [int(i) for i in gidx],
+        "haversine": [float(v) for v in gv],
+    }
+
     # Levenshtein (Appendix B) on the symbol-sequence workload
     SP, spo, SQ, sqo = workloads.symbol_pairs()
     rng = np.random.default_rng(1003)

@@ -3,8 +3,8 @@
 A planning-only context (256 CUs, 160 KB of LDS per CU) builds the plans
 the library would launch for the benchmark workloads, for forced band
 splitting, other launch shapes, long curves whose boundary rows do not fit
-LDS, cross requests, single long pairs (the LDS-ring pipeline) and the DTW
-and Manhattan kernels; tests/plan_sim.py checks coverage, output indices,
+LDS, cross requests, single long pairs (the LDS-ring pipeline) and the DTW,
+Manhattan, Chebyshev, Levenshtein and great-circle kernels; tests/plan_sim.py checks coverage, output indices,
 hand-off adjacency, link and ring lags (deadlock freedom) and buffer bounds.
 """
 import numpy as np
@@ -82,7 +82,7 @@ def test_single_pairs(planner, n, m, dim):
 
 
 @pytest.mark.parametrize("dtw,metric,lev", [(True, 1, False), (True, 0, False), (False, 2, False),
-                                            (True, 3, False), (False, 1, True)])
+                                            (True, 3, False), (False, 1, True), (False, 4, False)])
 def test_other_kernels(planner, dtw, metric, lev):
     P, p_off, Q, q_off = workloads.random_pairs(412, 200, 1, 6000, dim=2)
     sm = batch_case(planner, p_off, q_off, dtw=dtw, metric=metric, exact=lev, levenshtein=lev)

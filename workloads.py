@@ -168,6 +168,55 @@ def random_pairs(seed, npairs, lo, hi, dim=2, kind="walk"):
     return P, p_off, Q, q_off
 
 
+def _wrap(lon):
+    """Longitude to [-pi, pi)."""
+    return (lon + np.pi) % (2.0 * np.pi) - np.pi
+
+
+def geo_walk(rng, n, step, pole_margin=1e-4):
+    """A random walk on the sphere as (latitude, unwrapped longitude) in FP64
+    radians.  Draw order: z uniform in [-1, 1) (latitude asin z, so the start
+    is uniform on the sphere), the start longitude uniform in [-pi, pi), then
+    the n - 1 steps (n - 1 x 2, N(0, step^2)): latitude steps are taken as
+    drawn and clipped to pole_margin from the poles, longitude steps are
+    divided by the cosine of the new latitude (about `step` radians east or
+    west)."""
+    lat0 = np.arcsin(rng.uniform(-1.0, 1.0))
+    lon0 = rng.uniform(-np.pi, np.pi)
+    d = rng.standard_normal((n - 1, 2)) * step
+    lim = np.pi / 2 - pole_margin
+    lat = np.clip(lat0 + np.concatenate([[0.0], np.cumsum(d[:, 0])]), -lim, lim)
+    lon = lon0 + np.concatenate([[0.0], np.cumsum(d[:, 1] / np.cos(lat[1:]))])
+    return np.stack([lat, lon], axis=1)
+
+
+def geo_pairs(seed=9, npairs=4096, lo=64, hi=2048, step=2e-3, noise=0.1):
+    """Pairs of curves on the sphere, (latitude, longitude) in radians,
+    float32, for the great-circle ground distance.  Draw order: n[npairs],
+    m[npairs] uniform in [lo, hi]; then per pair: the geo_walk of p (n
+    points), then the q noise (m x 2, N(0, (noise * step)^2)).  q is p
+    resampled at m points (linear interpolation of latitude and unwrapped
+    longitude, endpoints kept) plus the noise; latitudes are clipped to 1e-4
+    from the poles and longitudes wrapped to [-pi, pi), so curves cross the
+    antimeridian.  Returns P, p_off, Q, q_off with 2 coordinates per point."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(lo, hi + 1, size=npairs)
+    m = rng.integers(lo, hi + 1, size=npairs)
+    lim = np.pi / 2 - 1e-4
+    ps, qs = [], []
+    for k in range(npairs):
+        p64 = geo_walk(rng, int(n[k]), step)
+        q64 = _resample(p64, int(m[k])) + (noise * step) * rng.standard_normal((int(m[k]), 2))
+        for c in (p64, q64):
+            c[:, 0] = np.clip(c[:, 0], -lim, lim)
+            c[:, 1] = _wrap(c[:, 1])
+        ps.append(p64.astype(np.float32))
+        qs.append(q64.astype(np.float32))
+    P, p_off = concat(ps)
+    Q, q_off = concat(qs)
+    return P, p_off, Q, q_off
+
+
 def symbol_pairs(seed=8, npairs=4096, lo=64, hi=2048, alphabet=4, redraw=0.1):
     """Draw order: n[npairs], m[npairs] uniform in [lo, hi]; then per pair:
     p (n symbols uniform in [0, alphabet)), the resampling of p to m symbols
