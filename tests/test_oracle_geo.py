@@ -1,7 +1,7 @@
 """Pins for the great-circle ground distance of the CPU oracle (no GPU).
 
-Sec. 3 of the paper leaves the ground distance open and motivates
-trajectories on the globe; the oracle's FFDO_HAVERSINE cell is the central
+Sec. 3 of the paper leaves the ground distance open and Sec. 2 motivates
+vessel trajectories; the oracle's FFDO_HAVERSINE cell is the central
 angle between (latitude, longitude) points in radians, by the haversine
 formula in FP64.  It is tied here to things other than itself:
 
