@@ -18,6 +18,9 @@ not counted).
   levenshtein  Levenshtein distance (Appendix B) of 4096 int32 symbol pairs
   geo    4096 pairs of (latitude, longitude) walks on the sphere under the
          great-circle distance (metric FFD_HAVERSINE)
+  knn    k = 10 nearest curves of queries in the serving database
+         (ffd_knn: bounds, threshold, early-abandoning sweep) against a
+         full scan
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (VALU issue rate: the path has no contraction and moves O(n+m) bytes per
@@ -382,6 +385,67 @@ def run_geo(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_knn(args, torch, ffd, ctx, dev, stream):
+    """k = 10 nearest curves of queries in the resident 10,000-curve database
+    (the serving workload) through ffd_knn (endpoint bounds, a threshold
+    from 128 exact distances, early-abandoning sweep), against a full scan
+    (ffd_cross of the query with every curve, then the 10 smallest)."""
+    import workloads
+    K = 10
+    DB, dbo = workloads.serving_db()
+    db_points = int(dbo[-1])
+    DBd = torch.from_numpy(DB).to(dev)
+    qs = workloads.serving_queries(count=args.warmup + args.steps)
+    qd = [torch.from_numpy(q).to(dev) for q in qs]
+    ws = torch.empty(max(ctx.workspace_size(ffd.FFD_OP_CROSS, [0, len(q)], dbo, 2) for q in qs),
+                     dtype=torch.uint8, device=dev)
+    full = torch.empty(len(dbo) - 1, dtype=torch.float32, device=dev)
+    for i in range(args.warmup):
+        ctx.knn(qd[i], DBd, dbo, K, stream=stream)
+        ctx.cross(qd[i], [0, len(qs[i])], DBd, dbo, out=full, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    timed = range(args.warmup, args.warmup + args.steps)
+    cells = sum(len(qs[i]) for i in timed) * db_points
+    t0 = time.perf_counter()
+    res = [ctx.knn(qd[i], DBd, dbo, K, stream=stream) for i in timed]
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    counts = ctx.last_search()
+    t1 = time.perf_counter()
+    scans = []
+    for i in timed:
+        ctx.cross(qd[i], [0, len(qs[i])], DBd, dbo, out=full, workspace=ws, stream=stream)
+        d = full.cpu()
+        scans.append(torch.topk(d, K, largest=False, sorted=True))
+    torch.cuda.synchronize()
+    scan_sec = (time.perf_counter() - t1) / args.steps
+    same = all(torch.equal(r[1].cpu(), s.values) for r, s in zip(res, scans))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = cpu_cores()
+        i = args.warmup
+        t2 = time.perf_counter()
+        vals = oracle.dfd_cross(qs[i], [0, len(qs[i])], DB, dbo, oracle.EUCLIDEAN, cores)[0]
+        cw = time.perf_counter() - t2
+        o_i, o_d = oracle.knn(vals, K)
+        cpu = {"value": 1.0 / cw, "unit": "queries/s", "cores": cores, "kind": "oracle",
+               "sample": f"one query ({len(qs[i])} points) against all 10,000 curves, FP64 rolling-row oracle "
+                         f"on {cores} threads, then the 10 smallest: {cw:.2f} s",
+               "gpu_matches_sample": bool(np.array_equal(res[0][0].cpu().numpy(), o_i))}
+    return {
+        "metric": "knn_queries_per_second", "value": 1.0 / sec, "unit": "queries/s", "ms_per_step": sec * 1e3,
+        "dtype": "f32",
+        "config": {"workload": "knn: k = 10 nearest of log-normal-length 2-D walk queries in the 10,000-curve "
+                               "serving database (seeds 5, 6), Euclidean",
+                   "queries": args.steps, "k": K, "db_points": db_points, "global_batch": args.steps},
+        "parity": {"distances_equal_full_scan": same},
+        "search": {"full_scan_ms": scan_sec * 1e3, "speedup_over_full_scan": scan_sec / sec,
+                   "effective_cells_per_s": cells / args.steps / sec, "last_query_counts": counts},
+        "cpu_baseline": cpu,
+    }
+
+
 def run_pair(args, torch, ffd, ctx, dev, stream, which):
     import workloads
     if which == "plain":
@@ -594,7 +658,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
-                                           "geo"],
+                                           "geo", "knn"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
@@ -642,14 +706,17 @@ def main():
         r = run_levenshtein(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "geo":
         r = run_geo(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "knn":
+        r = run_knn(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {
-        "metric": r.get("metric", METRIC), "value": r["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "metric": r.get("metric", METRIC), "value": r["value"], "unit": r.get("unit", "cells/s"), "n_gpus": 1,
+        "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "autotune", "serving", "roofline", "plain", "cpu_baseline"):
+    for k in ("config", "parity", "autotune", "serving", "search", "roofline", "plain", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     print(json.dumps(line), flush=True)

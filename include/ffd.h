@@ -353,6 +353,55 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
                        const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out,
                        void *workspace, size_t ws_bytes, void *stream, ffd_tuning *best);
 
+/* ------------------------------------------- decider and k-nearest search ---
+ * Early abandoning (Eq. (1): M_ij is the smallest, over monotone paths to
+ * (i, j), of the largest cell on the path, so delta is at least the smallest
+ * M over any set of cells that every full path must cross).  A wavefront
+ * sweeps one pair at a time and, every 16 columns, tests such a set -- its
+ * current anti-diagonal staircase, the cells just above it, and the rest of
+ * the band above -- against a threshold; once every cell of the set
+ * exceeds it the pair is dropped.  Float32 coordinates, FFD_EUCLIDEAN or
+ * FFD_SQEUCLIDEAN (other metrics: FFD_E_UNSUPPORTED); the values that are
+ * kept have the same bits as ffd_batch's.  The calls use device scratch
+ * that the context allocates on first need and keeps until ffd_destroy;
+ * they cannot be recorded into a graph (FFD_E_UNSUPPORTED). */
+
+/* Decider: out[k] = delta(P_k, Q_k) when it is <= eps (the same value as
+ * ffd_batch), else +inf, so that out[k] <= eps answers "is delta <= eps?".
+ * Arguments as ffd_batch without the workspace; eps is a distance in the
+ * metric's units (+inf: no pair is dropped; below 0: every pair is).
+ * Asynchronous on `stream`; offsets are HOST arrays, read before return.
+ * Errors: FFD_E_INVALID (NULL, bad offsets, NaN eps, unknown metric, dim <
+ * 1), FFD_E_UNSUPPORTED (metric, dim > FFD_MAX_DIM, a column curve of 2^31
+ * or more values), FFD_E_DEVICE. */
+int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                     int64_t npairs, int32_t dim, int32_t metric, float eps, float *out, void *stream);
+
+/* The k database curves nearest to the query q (n points) under the
+ * discrete Frechet distance, exactly: out_idx[i] (int64, device) and
+ * out_dist[i] (float32, device) for i < min(k, ndb), in increasing
+ * distance, ties by the smaller index; entries past ndb get index -1 and
+ * distance +inf.  Stages: the larger of the first-point and last-point
+ * distances bounds each curve's distance from below; the 128 curves (at
+ * least k) with the smallest bounds are evaluated exactly and the k-th
+ * smallest distance becomes the threshold; every other curve whose bound
+ * does not exceed it runs through the early-abandoning sweep at that
+ * threshold.  Database layout as ffd_cross (device coordinates, HOST
+ * offsets).  Synchronises the stream.
+ * Errors: FFD_E_INVALID (NULL, k < 1, n < 1, ndb < 1, bad offsets, unknown
+ * metric), FFD_E_UNSUPPORTED (metric, dim, too many or too long curves),
+ * FFD_E_DEVICE. */
+int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
+            int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream);
+
+typedef struct ffd_search_info {
+  int64_t exact;     /* curves evaluated before the threshold was set */
+  int64_t bounded;   /* curves swept against the threshold */
+  int64_t rejected;  /* of those, curves beyond the threshold (dropped) */
+} ffd_search_info;
+/* Counts of the context's last ffd_knn call.  Errors: FFD_E_INVALID. */
+int ffd_last_search(const ffd_ctx *ctx, ffd_search_info *info);
+
 /* ------------------------------------------------------------ serving ---
  * Queries against a device-resident database of curves (the batched form
  * of Sec. 4 against one reference curve, turned around: one query against

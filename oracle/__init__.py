@@ -20,6 +20,9 @@ Contents
   sum, M_ij = min{M_{i-1,j}, M_{i-1,j-1}, M_{i,j-1}} + d_ij, in FP64, exact
   int64, and a float32 replica (``dtw_*``).
 
+* ``decide`` and ``knn``: the decider's and the k-nearest search's answers
+  from a vector of distances (a comparison, and a sort by (distance, index)).
+
 Inputs are float32 (widened exactly to FP64 inside) or int32 arrays of shape
 (n, D), row-major.  Metric 0 = Euclidean (sqrt of the sum of squares per
 cell), 1 = squared Euclidean, 2 = Manhattan (sum of |p_k - q_k|), 3 =
@@ -391,6 +394,25 @@ def lev_batch(P, p_off, Q, q_off, nthreads=1, order=None):
 def lev_cross(Qs, q_off, DB, db_off, nthreads=1, rows=None):
     ps, pl, qs, ql, nr, ndb = _cross_index(q_off, db_off, rows)
     return lev_pairs(Qs, ps, pl, DB, qs, ql, nthreads).reshape(nr, ndb)
+
+
+def decide(values, eps):
+    """The decider's answer from distances: delta if delta <= eps, else +inf
+    (the question "is delta <= eps?" with the distance kept when it is)."""
+    v = np.asarray(values)
+    return np.where(v <= eps, v, np.inf).astype(v.dtype)
+
+
+def knn(values, k):
+    """Indices and distances of the k smallest values, in increasing value,
+    ties by the smaller index; past the end: index -1 and +inf."""
+    v = np.asarray(values)
+    order = np.lexsort((np.arange(len(v)), v))[:k]
+    idx = np.full(k, -1, dtype=np.int64)
+    dist = np.full(k, np.inf, dtype=v.dtype)
+    idx[:len(order)] = order
+    dist[:len(order)] = v[order]
+    return idx, dist
 
 
 def now():

@@ -1,0 +1,33 @@
+// Arguments and launchers of the early-abandoning sweep (ffd_bounded.hip).
+#ifndef FFD_BOUNDED_H
+#define FFD_BOUNDED_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffd {
+
+struct BoundedArgs {
+  const float *X0, *X1;        // coordinates of the row curves and of the column curves
+  const int64_t *off0, *off1;  // their offsets in points (device)
+  const int32_t *order;        // work item k -> pair index (column curve and output index)
+  int32_t fixed_row;           // >= 0: row curve of every pair; -1: the pair index
+  int32_t metric;              // 0: store sqrt(delta^2) rounded once; 1: delta^2
+  int64_t npairs;              // work items
+  float eps2;                  // drop a pair once every cell of a crossing set exceeds this (squared)
+  float *out;                  // per pair: its value when delta^2 <= eps2, else +inf
+  float *rows;                 // per wave: 3 * row_cap floats (two bottom rows, suffix minima)
+  int64_t row_cap;             // > the longest column curve when some row curve has several bands
+  uint32_t *counter;           // work counter, zero at launch
+};
+
+// nwaves wavefronts (workgroups of 4) take pairs from the counter.
+hipError_t launch_bounded(int R, int D, const BoundedArgs &a, int nwaves, hipStream_t st);
+// lb[c] = larger of the squared first-point and last-point distances between
+// the query and curve c.
+hipError_t launch_endpoint_bound(int D, const float *q, int64_t n, const float *X, const int64_t *off, int64_t count,
+                                 float *lb, hipStream_t st);
+
+}  // namespace ffd
+
+#endif  // FFD_BOUNDED_H

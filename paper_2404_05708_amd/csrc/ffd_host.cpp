@@ -1078,10 +1078,10 @@ void ffd_destroy(ffd_ctx *ctx) {
     hipEventDestroy(ctx->upload_done);
   }
   if (ctx->pinned) hipHostFree(ctx->pinned);
-  if (ctx->scratch) {
-    hipDeviceSynchronize();
-    hipFree(ctx->scratch);
-  }
+  if (ctx->scratch || ctx->search) hipDeviceSynchronize();
+  if (ctx->scratch) hipFree(ctx->scratch);
+  if (ctx->search) hipFree(ctx->search);
+  if (ctx->search_done) hipEventDestroy(ctx->search_done);
   delete ctx;
 }
 

@@ -125,6 +125,11 @@ struct ffd_ctx {
   std::unordered_map<uint64_t, ffd_tuning> tuned;
   void *scratch = nullptr;    // device workspace for long single pairs (owned)
   size_t scratch_bytes = 0;
+  void *search = nullptr;     // device scratch of the decider and the k-nearest search (owned)
+  size_t search_bytes = 0;
+  hipEvent_t search_done = nullptr;  // end of the last search launch
+  bool search_used = false;
+  ffd_search_info last_search{};
   ffd_launch_info last{};
   uint64_t *last_err = nullptr; // device error word of the last launch (workspace)
   uint32_t last_epoch = 0;

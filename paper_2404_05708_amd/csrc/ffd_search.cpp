@@ -1,0 +1,289 @@
+// Decider and k-nearest-neighbour search on the early-abandoning sweep
+// (ffd_bounded.hip): host-side checks, scratch management and the two-stage
+// search.
+//
+// k nearest neighbours of a query q in a database of curves:
+//   1. a lower bound per database curve, the larger of the squared
+//      first-point and last-point distances (every coupling contains both
+//      corner cells), computed on the GPU;
+//   2. exact squared distances of the curves with the smallest bounds (at
+//      least k of them): the k-th smallest is the threshold tau;
+//   3. every other curve whose bound is at most tau runs through the sweep
+//      with threshold tau, which drops a pair as soon as a crossing set of
+//      its table exceeds tau;
+//   4. the k smallest (distance, index) pairs of stages 2 and 3.
+// Every curve at distance <= tau is evaluated exactly in stage 2 or 3 (its
+// bound is at most its distance), and at least k curves are within tau, so
+// the result is the exact k nearest, ties broken by the smaller index.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <vector>
+
+#include "ffd.h"
+#include "ffd_bounded.h"
+#include "ffd_internal.h"
+
+using namespace ffdi;
+
+namespace {
+
+constexpr int64_t kStageOne = 128;  // exact evaluations before the threshold is set (at least k)
+
+// Largest float x whose square root, taken in FP64 and rounded once to
+// float (the stored form of a Euclidean result), is at most eps: then
+// delta <= eps exactly when delta^2 <= x.
+float eps2_of(float eps, int32_t metric) {
+  if (metric == FFD_SQEUCLIDEAN || std::isinf(eps)) return eps;
+  if (eps < 0.f) return -1.f;
+  auto root = [](float x) { return (float)std::sqrt((double)x); };
+  float x = (float)((double)eps * (double)eps);
+  while (x > 0.f && root(x) > eps) x = std::nextafter(x, 0.f);
+  for (;;) {
+    float y = std::nextafter(x, std::numeric_limits<float>::infinity());
+    if (std::isinf(y) || root(y) > eps) break;
+    x = y;
+  }
+  return x;
+}
+
+// Rows per lane: the smallest R whose band holds a typical row curve.
+int rows_per_lane(int64_t n) {
+  if (n <= 64) return 1;
+  if (n <= 128) return 2;
+  if (n <= 256) return 4;
+  return 8;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_search(ffd_ctx *ctx, int32_t dim, int32_t metric) {
+  if (!ctx) return FFD_E_INVALID;
+  if (dim < 1) return fail(ctx, FFD_E_INVALID, "dim must be >= 1");
+  if (dim > FFD_MAX_DIM) return fail(ctx, FFD_E_UNSUPPORTED, "dim exceeds FFD_MAX_DIM");
+  if (metric < FFD_EUCLIDEAN || metric > FFD_HAVERSINE) return fail(ctx, FFD_E_INVALID, "unknown metric");
+  if (metric != FFD_EUCLIDEAN && metric != FFD_SQEUCLIDEAN)
+    return fail(ctx, FFD_E_UNSUPPORTED, "the search calls take the Euclidean and squared Euclidean metrics");
+  return FFD_OK;
+}
+
+// The context's search scratch, grown on demand.  Work of an earlier
+// search call on another stream is waited for on the device.
+int search_scratch(ffd_ctx *ctx, size_t bytes, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(ctx, FFD_E_UNSUPPORTED, "the search calls cannot be recorded into a graph");
+  if (!ctx->search_done) {
+    e = hipEventCreateWithFlags(&ctx->search_done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+  } else if (ctx->search_used) {
+    e = hipStreamWaitEvent(st, ctx->search_done, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+  }
+  if (ctx->search_bytes >= bytes) return FFD_OK;
+  if (ctx->search) {
+    hipDeviceSynchronize();
+    hipFree(ctx->search);
+    ctx->search = nullptr;
+    ctx->search_bytes = 0;
+  }
+  e = hipMalloc(&ctx->search, bytes);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc (search scratch)");
+  ctx->search_bytes = bytes;
+  return FFD_OK;
+}
+
+// Waves of a launch: two per SIMD, at most one per pair, whole workgroups
+// of four.
+int search_waves(ffd_ctx *ctx, int64_t npairs) {
+  int64_t w = std::min<int64_t>((int64_t)ctx->cus * 8, npairs);
+  return (int)std::max<int64_t>(4, (w + 3) / 4 * 4);
+}
+
+struct Layout {
+  size_t off0, off1, order, out, counter, lb, rows, total;
+};
+
+Layout layout(int64_t n0, int64_t n1, int64_t npairs, int64_t nout, int64_t nlb, int nwaves, int64_t row_cap) {
+  Layout L{};
+  size_t o = 0;
+  L.off0 = o; o = al256(o + (size_t)(n0 + 1) * 8);
+  L.off1 = o; o = al256(o + (size_t)(n1 + 1) * 8);
+  L.order = o; o = al256(o + (size_t)std::max<int64_t>(npairs, 1) * 4);
+  L.out = o; o = al256(o + (size_t)std::max<int64_t>(nout, 1) * 4);
+  L.counter = o; o = al256(o + 8);
+  L.lb = o; o = al256(o + (size_t)std::max<int64_t>(nlb, 1) * 4);
+  L.rows = o; o = al256(o + (size_t)nwaves * 3 * (size_t)row_cap * 4);
+  L.total = o;
+  return L;
+}
+
+int launch(ffd_ctx *ctx, ffd::BoundedArgs &a, int R, int D, int nwaves, hipStream_t st) {
+  hipError_t e = ffd::clear_words(reinterpret_cast<uint64_t *>(a.counter), 1, st);
+  if (e == hipSuccess) e = ffd::launch_bounded(R, D, a, nwaves, st);
+  if (e == hipSuccess) e = hipEventRecord(ctx->search_done, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "search launch");
+  ctx->search_used = true;
+  return FFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                     int64_t npairs, int32_t dim, int32_t metric, float eps, float *out, void *stream) {
+  int rc = check_search(ctx, dim, metric);
+  if (rc) return rc;
+  if (std::isnan(eps)) return fail(ctx, FFD_E_INVALID, "eps is NaN");
+  if (npairs < 0) return fail(ctx, FFD_E_INVALID, "npairs < 0");
+  if (npairs == 0) return FFD_OK;
+  if (npairs > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many pairs");
+  if (!P || !Q || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
+  if ((rc = check_offsets(ctx, p_off, npairs, "p_off is NULL"))) return rc;
+  if ((rc = check_offsets(ctx, q_off, npairs, "q_off is NULL"))) return rc;
+  int64_t nsum = 0, mmax = 0, nmax = 0;
+  for (int64_t k = 0; k < npairs; ++k) {
+    nsum += p_off[k + 1] - p_off[k];
+    nmax = std::max(nmax, p_off[k + 1] - p_off[k]);
+    mmax = std::max(mmax, q_off[k + 1] - q_off[k]);
+  }
+  if (mmax * dim >= ((int64_t)1 << 31)) return fail(ctx, FFD_E_UNSUPPORTED, "column curve too long");
+  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
+  hipStream_t st = (hipStream_t)stream;
+  int R = rows_per_lane(nsum / npairs);
+  int64_t row_cap = nmax > 64 * R ? mmax + 1 : 0;
+  int nwaves = search_waves(ctx, npairs);
+  Layout L = layout(npairs, npairs, npairs, 0, 0, nwaves, row_cap);
+  if ((rc = search_scratch(ctx, L.total, st))) return rc;
+  // larger pairs first, so that the work counter ends with small ones
+  std::vector<int32_t> order(npairs);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return (p_off[x + 1] - p_off[x]) * (q_off[x + 1] - q_off[x]) >
+           (p_off[y + 1] - p_off[y]) * (q_off[y + 1] - q_off[y]);
+  });
+  char *base = static_cast<char *>(ctx->search);
+  hipError_t e = hipMemcpyAsync(base + L.off0, p_off, (size_t)(npairs + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + L.off1, q_off, (size_t)(npairs + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + L.order, order.data(), (size_t)npairs * 4, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "search upload");
+  ffd::BoundedArgs a{};
+  a.X0 = P;
+  a.X1 = Q;
+  a.off0 = reinterpret_cast<const int64_t *>(base + L.off0);
+  a.off1 = reinterpret_cast<const int64_t *>(base + L.off1);
+  a.order = reinterpret_cast<const int32_t *>(base + L.order);
+  a.fixed_row = -1;
+  a.metric = metric;
+  a.npairs = npairs;
+  a.eps2 = eps2_of(eps, metric);
+  a.out = out;
+  a.rows = reinterpret_cast<float *>(base + L.rows);
+  a.row_cap = row_cap;
+  a.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+  return launch(ctx, a, R, dim, nwaves, st);
+}
+
+int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
+            int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream) {
+  int rc = check_search(ctx, dim, metric);
+  if (rc) return rc;
+  if (k < 1) return fail(ctx, FFD_E_INVALID, "k must be >= 1");
+  if (n < 1) return fail(ctx, FFD_E_INVALID, "the query must have at least one point");
+  if (ndb < 1) return fail(ctx, FFD_E_INVALID, "the database must hold at least one curve");
+  if (ndb > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many curves");
+  if (!q || !DB || !out_idx || !out_dist) return fail(ctx, FFD_E_INVALID, "NULL pointer");
+  if ((rc = check_offsets(ctx, db_off, ndb, "db_off is NULL"))) return rc;
+  int64_t mmax = 0;
+  for (int64_t c = 0; c < ndb; ++c) mmax = std::max(mmax, db_off[c + 1] - db_off[c]);
+  if (mmax * dim >= ((int64_t)1 << 31)) return fail(ctx, FFD_E_UNSUPPORTED, "database curve too long");
+  if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t kk = std::min<int64_t>(k, ndb);
+  const int R = rows_per_lane(n);
+  const int64_t row_cap = n > 64 * R ? mmax + 1 : 0;
+  const int nwaves = search_waves(ctx, ndb);
+  Layout L = layout(1, ndb, ndb, ndb, ndb, nwaves, row_cap);
+  if ((rc = search_scratch(ctx, L.total, st))) return rc;
+  char *base = static_cast<char *>(ctx->search);
+  const int64_t qoff[2] = {0, n};
+  hipError_t e = hipMemcpyAsync(base + L.off0, qoff, sizeof qoff, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + L.off1, db_off, (size_t)(ndb + 1) * 8, hipMemcpyHostToDevice, st);
+  float *lb_dev = reinterpret_cast<float *>(base + L.lb);
+  if (e == hipSuccess)
+    e = ffd::launch_endpoint_bound(dim, q, n, DB, reinterpret_cast<const int64_t *>(base + L.off1), ndb, lb_dev, st);
+  std::vector<float> lb(ndb), vals(ndb);
+  if (e == hipSuccess) e = hipMemcpyAsync(lb.data(), lb_dev, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "search bounds");
+  std::vector<int32_t> idx(ndb);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return lb[x] < lb[y]; });
+
+  ffd::BoundedArgs a{};
+  a.X0 = q;
+  a.X1 = DB;
+  a.off0 = reinterpret_cast<const int64_t *>(base + L.off0);
+  a.off1 = reinterpret_cast<const int64_t *>(base + L.off1);
+  a.order = reinterpret_cast<const int32_t *>(base + L.order);
+  a.fixed_row = 0;
+  a.metric = FFD_SQEUCLIDEAN;
+  a.out = reinterpret_cast<float *>(base + L.out);
+  a.rows = reinterpret_cast<float *>(base + L.rows);
+  a.row_cap = row_cap;
+  a.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+  // one stage: exact squared distances of idx[lo, hi) at threshold eps2
+  auto stage = [&](int64_t lo, int64_t hi, float eps2) -> int {
+    if (hi <= lo) return FFD_OK;
+    a.npairs = hi - lo;
+    a.eps2 = eps2;
+    hipError_t err = hipMemcpyAsync(base + L.order, idx.data() + lo, (size_t)(hi - lo) * 4, hipMemcpyHostToDevice, st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "search upload");
+    int r = launch(ctx, a, R, dim, search_waves(ctx, hi - lo), st);
+    if (r) return r;
+    err = hipMemcpyAsync(vals.data(), a.out, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) return hip_fail(ctx, err, "search results");
+    return FFD_OK;
+  };
+  std::vector<std::pair<float, int32_t>> pool;
+  const int64_t s1 = std::min<int64_t>(ndb, std::max<int64_t>(kk, kStageOne));
+  if ((rc = stage(0, s1, std::numeric_limits<float>::infinity()))) return rc;
+  for (int64_t i = 0; i < s1; ++i) pool.emplace_back(vals[idx[i]], idx[i]);
+  std::sort(pool.begin(), pool.end());
+  const float tau2 = pool[kk - 1].first;
+  int64_t s2 = s1;
+  while (s2 < ndb && lb[idx[s2]] <= tau2) ++s2;
+  if ((rc = stage(s1, s2, tau2))) return rc;
+  for (int64_t i = s1; i < s2; ++i)
+    if (vals[idx[i]] <= tau2) pool.emplace_back(vals[idx[i]], idx[i]);
+  std::sort(pool.begin(), pool.end());
+  ctx->last_search = ffd_search_info{(int64_t)s1, (int64_t)(s2 - s1), 0};
+  for (int64_t i = s1; i < s2; ++i) ctx->last_search.rejected += std::isinf(vals[idx[i]]) ? 1 : 0;
+  std::vector<int64_t> ri(k, -1);
+  std::vector<float> rd(k, std::numeric_limits<float>::infinity());
+  for (int64_t i = 0; i < kk; ++i) {
+    ri[i] = pool[i].second;
+    rd[i] = metric == FFD_EUCLIDEAN ? (float)std::sqrt((double)pool[i].first) : pool[i].first;
+  }
+  e = hipMemcpyAsync(out_idx, ri.data(), (size_t)k * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out_dist, rd.data(), (size_t)k * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "search output");
+  return FFD_OK;
+}
+
+int ffd_last_search(const ffd_ctx *ctx, ffd_search_info *info) {
+  if (!ctx || !info) return FFD_E_INVALID;
+  *info = ctx->last_search;
+  return FFD_OK;
+}
+
+}  // extern "C"

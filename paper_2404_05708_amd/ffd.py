@@ -46,8 +46,15 @@ EXPORTS = (
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
-    "ffd_levenshtein_cross",
+    "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_last_search",
 )
+
+
+class SearchInfo(ctypes.Structure):
+    _fields_ = [("exact", ctypes.c_int64), ("bounded", ctypes.c_int64), ("rejected", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class LaunchInfo(ctypes.Structure):
@@ -159,6 +166,12 @@ def _load():
     lib.ffd_autotune_cross.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, vp, vp, sz, vp,
                                        ctypes.POINTER(Tuning)]
     lib.ffd_autotune_cross.restype = ctypes.c_int
+    lib.ffd_decide_batch.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, ctypes.c_float, vp, vp]
+    lib.ffd_decide_batch.restype = ctypes.c_int
+    lib.ffd_knn.argtypes = [vp, vp, i64, vp, i64p, i64, i32, i32, i32, vp, vp, vp]
+    lib.ffd_knn.restype = ctypes.c_int
+    lib.ffd_last_search.argtypes = [vp, ctypes.POINTER(SearchInfo)]
+    lib.ffd_last_search.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.ffd_db_create.argtypes = [vp, vp, i64p, i64, i32, ctypes.POINTER(vp)]
     lib.ffd_db_create.restype = ctypes.c_int
@@ -260,6 +273,46 @@ def ffd_last_errors(ctx):
 
 def ffd_set_split(ctx, share=0.0):
     _check(lib.ffd_set_split(ctx, float(share)), ctx)
+
+
+def ffd_decide_batch(ctx, P, p_off, Q, q_off, eps, metric=FFD_EUCLIDEAN, out=None, stream=None):
+    """Decider (early abandoning): out[k] = delta_k if delta_k <= eps, else +inf."""
+    P, Pp = _curve(P, torch.float32, "P")
+    Q, Qp = _curve(Q, torch.float32, "Q")
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    po, pop = _offsets(p_off)
+    qo, qop = _offsets(q_off)
+    npairs = len(po) - 1
+    if len(qo) - 1 != npairs:
+        raise ValueError("p_off and q_off must describe the same number of pairs")
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=torch.float32, device=P.device)
+    _check(lib.ffd_decide_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric), float(eps),
+                                _dev_ptr(out, torch.float32, "out"), _stream(stream)), ctx)
+    return out[:npairs]
+
+
+def ffd_knn(ctx, q, DB, db_off, k, metric=FFD_EUCLIDEAN, stream=None):
+    """The k database curves nearest to q: (int64 indices, float32 distances),
+    device tensors of k entries (index -1 / +inf past the database size)."""
+    q, qp = _curve(q, torch.float32, "q")
+    DB, Dp = _curve(DB, torch.float32, "DB")
+    if q.shape[1] != DB.shape[1]:
+        raise ValueError("q and DB must have the same dimension")
+    do, dop = _offsets(db_off)
+    idx = torch.empty(max(int(k), 1), dtype=torch.int64, device=q.device)
+    dist = torch.empty(max(int(k), 1), dtype=torch.float32, device=q.device)
+    _check(lib.ffd_knn(ctx, qp, q.shape[0], Dp, dop, len(do) - 1, q.shape[1], int(metric), int(k),
+                       _dev_ptr(idx, torch.int64, "idx"), _dev_ptr(dist, torch.float32, "dist"),
+                       _stream(stream)), ctx)
+    return idx[:k], dist[:k]
+
+
+def ffd_last_search(ctx):
+    info = SearchInfo()
+    _check(lib.ffd_last_search(ctx, ctypes.byref(info)), ctx)
+    return info.as_dict()
 
 
 def ffd_last_launch(ctx):
@@ -558,6 +611,15 @@ class Context:
 
     def levenshtein(self, p, q, **kw):
         return ffd_levenshtein_distance(self.handle, p, q, **kw)
+
+    def decide_batch(self, P, p_off, Q, q_off, eps, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_decide_batch(self.handle, P, p_off, Q, q_off, eps, metric, **kw)
+
+    def knn(self, q, DB, db_off, k, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_knn(self.handle, q, DB, db_off, k, metric, **kw)
+
+    def last_search(self):
+        return ffd_last_search(self.handle)
 
     def levenshtein_batch(self, P, p_off, Q, q_off, **kw):
         return ffd_levenshtein_batch(self.handle, P, p_off, Q, q_off, **kw)
