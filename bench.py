@@ -18,6 +18,8 @@ not counted).
   levenshtein  Levenshtein distance (Appendix B) of 4096 int32 symbol pairs
   geo    4096 pairs of (latitude, longitude) walks on the sphere under the
          great-circle distance (metric FFD_HAVERSINE)
+  decide the decider (ffd_decide_batch) on the batched pairs at the median
+         distance
   knn    k = 10 nearest curves of queries in the serving database
          (ffd_knn: bounds, threshold, early-abandoning sweep) against a
          full scan
@@ -385,6 +387,53 @@ def run_geo(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_decide(args, torch, ffd, ctx, dev, stream):
+    """The decider on the batched pairs at eps = the median distance of the
+    stored sample (about half the pairs answer no): effective cells/s over
+    all cells of the workload; the same call at eps = +inf (nothing dropped)
+    gives the sweep's own roofline."""
+    import workloads
+    P, p_off, Q, q_off = workloads.batched()
+    npairs = len(p_off) - 1
+    cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
+    Pd = torch.from_numpy(P).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    out = torch.empty(npairs, dtype=torch.float32, device=dev)
+    g = golden()["batched"]
+    eps = float(np.median(g["euclidean"]))
+
+    def step(e):
+        return lambda: ctx.decide_batch(Pd, p_off, Qd, q_off, e, out=out, stream=stream)
+
+    for _ in range(args.warmup):
+        step(eps)()
+    sec = time_steps(step(eps), args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step(eps), args.steps, stream)
+    res = out.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    want = np.array(g["euclidean"])
+    dec_ok = bool(np.all((res[idx] <= eps) == (want <= eps)))
+    kept = res[idx] <= eps
+    val_ok = bool(np.all(np.abs(res[idx][kept] - want[kept]) <= TOL * want[kept]))
+    frac_no = float(np.mean(np.isinf(res)))
+    step(np.inf)()
+    sec_inf = time_steps(step(np.inf), args.steps, torch.cuda.synchronize)
+    kms_inf = kernel_ms(torch, step(np.inf), args.steps, stream)
+    full = out.cpu().numpy()
+    info = {"rows_per_lane": 8, "waves": "2 per SIMD, one pair per wave at a time"}
+    return {
+        "metric": "decider_effective_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3,
+        "dtype": "f32",
+        "config": {"workload": "decide: the batched pairs (seed 2), is delta <= eps? with eps the median "
+                               f"of the stored sample ({eps:.6g})", "npairs": npairs, "cells": cells,
+                   "global_batch": npairs},
+        "parity": {"decisions_ok": dec_ok, "kept_values_ok": val_ok, "share_answered_no": frac_no,
+                   "no_threshold_equals_batch_sample": bool(np.all(np.abs(full[idx] - want) <= TOL * want))},
+        "search": {"kernel_ms": kms, "no_threshold_ms": sec_inf * 1e3},
+        "roofline": roofline(info, cells, kms_inf, 2, False, family="bounded_kernel"),
+    }
+
+
 def run_knn(args, torch, ffd, ctx, dev, stream):
     """k = 10 nearest curves of queries in the resident 10,000-curve database
     (the serving workload) through ffd_knn (endpoint bounds, a threshold
@@ -658,7 +707,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
-                                           "geo", "knn"],
+                                           "geo", "knn", "decide"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
@@ -708,6 +757,8 @@ def main():
         r = run_geo(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "knn":
         r = run_knn(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "decide":
+        r = run_decide(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {
