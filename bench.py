@@ -331,10 +331,10 @@ def run_levenshtein(args, torch, ffd, ctx, dev, stream):
     }
 
 
-def run_geo(args, torch, ffd, ctx, dev, stream):
-    """The Frechet distance under the great-circle ground distance on 4096
-    pairs of (latitude, longitude) walks on the sphere with the batched
-    lengths; the kernel runs on FP64 unit vectors (D = 3)."""
+def run_geo(args, torch, ffd, ctx, dev, stream, dtw=False):
+    """The Frechet distance (or DTW) under the great-circle ground distance
+    on 4096 pairs of (latitude, longitude) walks on the sphere with the
+    batched lengths; the kernel runs on FP64 unit vectors (D = 3)."""
     import workloads
     P, p_off, Q, q_off = workloads.geo_pairs()
     npairs = len(p_off) - 1
@@ -344,8 +344,10 @@ def run_geo(args, torch, ffd, ctx, dev, stream):
     ws = torch.empty(ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, 2), dtype=torch.uint8, device=dev)
     out = torch.empty(npairs, dtype=torch.float32, device=dev)
 
+    fn = ctx.dtw_batch if dtw else ctx.batch
+
     def step():
-        ctx.batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_HAVERSINE, out=out, workspace=ws, stream=stream)
+        fn(Pd, p_off, Qd, q_off, metric=ffd.FFD_HAVERSINE, out=out, workspace=ws, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -353,10 +355,12 @@ def run_geo(args, torch, ffd, ctx, dev, stream):
     kms = kernel_ms(torch, step, args.steps, stream)
     info = ctx.last_launch()
     errs = ctx.last_errors()
-    g = golden()["batched_haversine"]
+    g = golden()["dtw_haversine" if dtw else "batched_haversine"]
     res = out.cpu().numpy()
     want = np.array(g["haversine"])
-    parity_ok = bool(np.all(np.abs(res[np.array(g["sample_index"])] - want) <= TOL * want + 1e-12))
+    absb = 1e-12 * (np.diff(p_off) + np.diff(q_off)) if dtw else 1e-12
+    idx = np.array(g["sample_index"])
+    parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want + (absb[idx] if dtw else absb)))
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -369,20 +373,25 @@ def run_geo(args, torch, ffd, ctx, dev, stream):
         qs, ql = q_off[:-1][sample], np.diff(q_off)[sample]
         order = np.argsort(-(pl * ql))
         t2 = time.perf_counter()
-        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.HAVERSINE, cores, order)
+        vals = oracle.dfd_pairs(P, ps, pl, Q, qs, ql, oracle.HAVERSINE, cores, order,
+                                measure="dtw" if dtw else "dfd")
         cw = time.perf_counter() - t2
+        sb = 1e-12 * (pl + ql) if dtw else 1e-12
         cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
                "sample": f"{nsample} of the 4096 pairs (seed 77), {s_cells} cells, FP64 haversine rolling-row "
-                         f"oracle, longest first on {cores} threads, {cw:.2f} s",
-               "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals + 1e-12))}
+                         f"{'DTW ' if dtw else ''}oracle, longest first on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals + sb))}
     return {
-        "metric": "geo_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f64",
+        "metric": "geo_dtw_cells_per_second" if dtw else "geo_cells_per_second", "value": cells / sec,
+        "ms_per_step": sec * 1e3, "dtype": "f64",
         "config": {"workload": "geo: 4096 pairs of (latitude, longitude) random walks on the sphere, steps "
                                "N(0, (2e-3 rad)^2), n and m uniform in [64, 2048], q = p resampled + "
-                               "N(0, (2e-4 rad)^2), great-circle distance (seed 9)",
+                               "N(0, (2e-4 rad)^2), great-circle distance" + (", DTW" if dtw else "") +
+                               " (seed 9)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
-        "parity": {"tolerance": "2e-6 relative + 1e-12 rad", "sampled_ok": parity_ok, "launch_error_flags": errs},
-        "roofline": roofline(info, cells, kms, 3, True, family="op_kernel", suffix=", 10"),
+        "parity": {"tolerance": "2e-6 relative + 1e-12 rad" + (" per cell of a coupling" if dtw else ""),
+                   "sampled_ok": parity_ok, "launch_error_flags": errs},
+        "roofline": roofline(info, cells, kms, 3, True, family="op_kernel", suffix=", 11" if dtw else ", 10"),
         "cpu_baseline": cpu,
     }
 
@@ -707,7 +716,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
-                                           "geo", "knn", "decide"],
+                                           "geo", "geo_dtw", "knn", "decide"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
     ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
@@ -753,8 +762,8 @@ def main():
         r = run_dtw(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "levenshtein":
         r = run_levenshtein(args, torch, ffd, ctx, dev, stream)
-    elif args.workload == "geo":
-        r = run_geo(args, torch, ffd, ctx, dev, stream)
+    elif args.workload in ("geo", "geo_dtw"):
+        r = run_geo(args, torch, ffd, ctx, dev, stream, dtw=args.workload == "geo_dtw")
     elif args.workload == "knn":
         r = run_knn(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "decide":

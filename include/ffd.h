@@ -76,13 +76,15 @@ extern "C" {
  * FFD_SQEUCLIDEAN.
  * FFD_HAVERSINE is the great-circle distance on the unit sphere (the
  * central angle, in radians; multiply by the sphere's radius for a length)
- * between points given as (latitude, longitude) in radians, dim = 2.  Only
- * the float32 Frechet calls (ffd_distance, ffd_batch, ffd_cross and their
- * autotuners) take it; the DTW calls return FFD_E_UNSUPPORTED.  Internally
- * each point becomes its FP64 unit vector, the sweep runs on squared chord
- * lengths (the angle 2 asin(chord / 2) increases with the chord, so Eq. (1)
- * selects the same cells) and the angle is computed once per pair in FP64;
- * ffd_last_launch then reports dim 3 and the FP64 value type. */
+ * between points given as (latitude, longitude) in radians, dim = 2.  The
+ * float32 Frechet and DTW calls take it (ffd_distance, ffd_batch, ffd_cross,
+ * their DTW forms and the autotuners; not the int32, serving or search
+ * calls).  Internally each point becomes its FP64 unit vector and the cell
+ * is its squared chord: the Frechet sweep selects on chords (the angle
+ * 2 asin(chord / 2) increases with the chord, so Eq. (1) selects the same
+ * cells) and takes the angle once per pair; DTW takes the angle in every
+ * cell (float32 square root and arcsine of the FP64 chord) and sums in FP64.  ffd_last_launch then reports dim 3 and the FP64
+ * value type. */
 #define FFD_EUCLIDEAN 0   /* ||p_i - q_j||_2                          */
 #define FFD_SQEUCLIDEAN 1 /* ||p_i - q_j||_2^2                        */
 #define FFD_MANHATTAN 2   /* sum_k |p_ik - q_jk|                      */

@@ -63,11 +63,13 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // add a square root per cell, a quarter-rate instruction (4 issue slots);
 // Manhattan and Chebyshev cells take D subtractions and D - 1 additions or
 // maxima with free absolute values, one instruction less; great-circle
-// cells (op 10) are FP64 squared chords of unit vectors (D = 3).
+// cells (ops 10, 11) are FP64 squared chords of unit vectors (D = 3), and
+// DTW adds a float square root and arcsine per cell (about 20 instructions).
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
   int cell = op >> 1;
   double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell == 2 || cell == 3 ? 1 : 0);
   if (op == 8) per_cell = 3 * D + 4;  // Levenshtein: a compare and a 64-bit select per coordinate, 4 FP64 ops
+  if (op == 11) per_cell += 20;
   double I = (double)R * per_cell + 8.0;
   double lone = 104.0 + 3.9 * I;
   double shared = 0.75 * std::max(1.0, waves_per_simd) * I * 4.0;
@@ -101,8 +103,9 @@ int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *n
   return FFD_OK;
 }
 
-// kernel op of the Frechet distance on great-circle cells
+// kernel ops of the Frechet distance and of DTW on great-circle cells
 constexpr int kOpGeo = 10;
+constexpr int kOpGeoDtw = 11;
 
 int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   if (!ctx) return FFD_E_INVALID;
@@ -110,9 +113,8 @@ int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
   if (metric < FFD_EUCLIDEAN || metric > FFD_HAVERSINE) return fail(ctx, FFD_E_INVALID, "unknown metric");
   if (dim > FFD_MAX_DIM) return fail(ctx, FFD_E_UNSUPPORTED, "dim exceeds FFD_MAX_DIM");
   // great-circle requests arrive here with the kernel's shape (geo_shape)
-  if (metric == FFD_HAVERSINE && ctx->measure != kOpGeo)
-    return fail(ctx, FFD_E_UNSUPPORTED, "the great-circle distance is available for the Frechet distance of float32 "
-                                        "curves");
+  if (metric == FFD_HAVERSINE && ctx->measure != kOpGeo && ctx->measure != kOpGeoDtw)
+    return fail(ctx, FFD_E_UNSUPPORTED, "the great-circle distance is available for float32 curves");
   if (exact && metric == FFD_EUCLIDEAN)
     return fail(ctx, FFD_E_UNSUPPORTED, "int32 coordinates take the squared Euclidean, Manhattan or Chebyshev metric");
   return FFD_OK;
@@ -557,6 +559,9 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
   double best_cost = -1;
   for (int R : kRs) {
     if (ctx->tune_R && R != ctx->tune_R) continue;
+    // great-circle DTW inlines an arcsine per cell and row: at R = 8 the
+    // kernel spills registers to scratch memory
+    if (!ctx->tune_R && ctx->measure == kOpGeoDtw && R > 4) continue;
     Resources rs = resources(ctx, R, D, exact, W);
     std::vector<Unit> units;
     make(R, W, units);
@@ -1124,10 +1129,10 @@ int ffd_set_split(ffd_ctx *ctx, float share) {
 // Kernel op of a call: measure (0 Frechet, 1 DTW) + 2 * cell, where the
 // cell is 0 squared Euclidean (the Frechet kernel also serves Euclidean: one
 // root per pair), 1 Euclidean per cell (DTW), 2 Manhattan, 3 Chebyshev.
-// Kernel op of a call; `geo` marks the float32 Frechet calls, the only ones
-// that take FFD_HAVERSINE (elsewhere check_common refuses it).
+// Kernel op of a call; `geo` marks the float32 calls, the only ones that
+// take FFD_HAVERSINE (elsewhere check_common refuses it).
 static int op_of(bool dtw, int32_t metric, bool geo = false) {
-  if (metric == FFD_HAVERSINE) return geo && !dtw ? kOpGeo : 0;
+  if (metric == FFD_HAVERSINE) return geo ? (dtw ? kOpGeoDtw : kOpGeo) : 0;
   int cell = metric == FFD_MANHATTAN ? 2 : metric == FFD_CHEBYSHEV ? 3 : (dtw && metric == FFD_EUCLIDEAN ? 1 : 0);
   return (dtw ? 1 : 0) + 2 * cell;
 }
@@ -1231,8 +1236,10 @@ int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off,
 int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m, int32_t dim,
                      int32_t metric, float *out, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(true, metric));
-  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, false);
+  MeasureScope scope(ctx, op_of(true, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
+  return pair_common(ctx, p, n, q, m, dim, metric, out, (hipStream_t)stream, exact);
 }
 
 int ffd_dtw_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
@@ -1246,9 +1253,11 @@ int ffd_dtw_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const floa
                   int64_t npairs, int32_t dim, int32_t metric, float *out, void *workspace, size_t ws_bytes,
                   void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(true, metric));
+  MeasureScope scope(ctx, op_of(true, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
-                      false);
+                      exact);
 }
 
 int ffd_dtw_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
@@ -1264,9 +1273,11 @@ int ffd_dtw_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int64_t n
                   const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out, void *workspace,
                   size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, op_of(true, metric));
+  MeasureScope scope(ctx, op_of(true, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, metric, out, workspace, ws_bytes,
-                      (hipStream_t)stream, false);
+                      (hipStream_t)stream, exact);
 }
 
 int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
@@ -1336,17 +1347,17 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
   // one size for every path: float and int32 coordinates, every measure and
-  // ground distance (kernel ops 0, 1, 3, ..., 8, and 10 for 2-D curves)
+  // ground distance (kernel ops 0, 1, 3, ..., 8, and 10, 11 for 2-D curves)
   size_t worst = 0;
-  for (int ms = 0; ms <= kOpGeo; ++ms)
+  for (int ms = 0; ms <= kOpGeoDtw; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
       if (ms == 2 || ms == 9 || (ms == 3 && ex == 1) || (ms == 8 && ex == 0)) continue;  // no such kernel
-      if (ms == kOpGeo && (ex == 0 || dim != 2)) continue;  // FP64 on (latitude, longitude) only
+      if (ms >= kOpGeo && (ex == 0 || dim != 2)) continue;  // FP64 on (latitude, longitude) only
       MeasureScope scope(ctx, ms);
       const Plan *pl;
       uint64_t key;
       PlanCache tmp;
-      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, ms == kOpGeo ? 3 : dim, ex == 1, &pl, key);
+      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, ms >= kOpGeo ? 3 : dim, ex == 1, &pl, key);
       if (rc == FFD_E_UNSUPPORTED) continue;
       if (rc) return rc;
       worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);

@@ -28,6 +28,7 @@ FFD_DECLARE_OP(6)
 FFD_DECLARE_OP(7)
 FFD_DECLARE_OP(8)
 FFD_DECLARE_OP(10)
+FFD_DECLARE_OP(11)
 #undef FFD_DECLARE_OP
 hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 
@@ -35,8 +36,8 @@ hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 // plan uses them (a.rings); every other launch takes the plain variant.
 // `op` = measure + 2 * cell (measure 0 Frechet, 1 DTW; cell 0 squared
 // Euclidean, 1 Euclidean per cell, 2 Manhattan, 3 Chebyshev); op 8 is the
-// Levenshtein distance (int32 symbols), op 10 the Frechet distance on
-// great-circle cells (FP64 unit vectors, D = 3).  Op 0 is the
+// Levenshtein distance (int32 symbols), ops 10 and 11 the Frechet distance
+// and DTW on great-circle cells (FP64 unit vectors, D = 3).  Op 0 is the
 // Frechet kernel on squared cells (with or without LDS rings); every other
 // op has its own kernel family and never uses rings.
 inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
@@ -52,6 +53,7 @@ inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, i
     case 7: return launch_op_7(exact, R, D, a, wpb, coop, st);
     case 8: return launch_op_8(exact, R, D, a, wpb, coop, st);
     case 10: return launch_op_10(exact, R, D, a, wpb, coop, st);
+    case 11: return launch_op_11(exact, R, D, a, wpb, coop, st);
   }
   return hipErrorInvalidValue;
 }
@@ -68,6 +70,7 @@ inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds
     case 7: return occupancy_op_7(exact, R, D, wpb, lds, blocks_per_cu);
     case 8: return occupancy_op_8(exact, R, D, wpb, lds, blocks_per_cu);
     case 10: return occupancy_op_10(exact, R, D, wpb, lds, blocks_per_cu);
+    case 11: return occupancy_op_11(exact, R, D, wpb, lds, blocks_per_cu);
   }
   return hipErrorInvalidValue;
 }

@@ -4,8 +4,9 @@
 // squared Euclidean cells, 3 DTW of Euclidean cells (float32 only), 4
 // Frechet on Manhattan cells, 5 DTW on Manhattan cells, 6 Frechet on
 // Chebyshev cells, 7 DTW on Chebyshev cells, 8 Levenshtein (int32 symbols
-// only), 10 Frechet on great-circle distances (float32 (latitude,
-// longitude) input, FP64 unit vectors: the value type double, D = 3).
+// only), 10 Frechet and 11 DTW on great-circle distances (float32
+// (latitude, longitude) input, FP64 unit vectors: the value type double,
+// D = 3).
 #include "ffd_launch.h"
 
 #ifndef FFD_OP
@@ -23,8 +24,8 @@ struct OpSel {
   // float32 coordinates for every op but Levenshtein; the great-circle op
   // computes in FP64 (its `exact` shape) on float32 input
   static constexpr bool kExact = FFD_OP != 3;
-  static constexpr bool kFloat = FFD_OP != 8 && FFD_OP != 10;
-  static constexpr int kOnlyD = FFD_OP == 10 ? 3 : 0;
+  static constexpr bool kFloat = FFD_OP != 8 && FFD_OP != 10 && FFD_OP != 11;
+  static constexpr int kOnlyD = FFD_OP == 10 || FFD_OP == 11 ? 3 : 0;
   template <int R, int D, typename V>
   static auto kernel() { return &op_kernel<R, D, V, FFD_OP>; }
 };

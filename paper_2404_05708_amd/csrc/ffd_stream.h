@@ -169,14 +169,15 @@ struct Stream {
   static constexpr bool LEV = OP == 8;
   // the result is taken from the lane of the curve's last row at its switch
   static constexpr bool CAP = DTW || LEV;
-  // OP 10: points are (latitude, longitude) in radians, float32, and the
-  // ground distance is the central angle between them.  Each point becomes
-  // its FP64 unit vector u = (cos lat cos lon, cos lat sin lon, sin lat)
-  // when it is staged in LDS (once per band row and once per ring entry),
-  // and the sweep runs on the squared chord |u - v|^2 with D = 3: the angle
-  // 2 asin(|u - v| / 2) is an increasing function of it, so the selections
-  // of Eq. (1) pick the same cells, and the angle is taken once per pair.
-  static constexpr bool HAV = OP == 10;
+  // OP 10 and 11 (cell 5): points are (latitude, longitude) in radians,
+  // float32, and the ground distance is the central angle between them.
+  // Each point becomes its FP64 unit vector u = (cos lat cos lon, cos lat
+  // sin lon, sin lat) when it is staged in LDS (once per band row and once
+  // per ring entry), and the cell is the squared chord |u - v|^2 with D = 3.
+  // The angle 2 asin(|u - v| / 2) is an increasing function of it, so the
+  // Frechet sweep (OP 10) selects on chords and takes the angle once per
+  // pair; DTW (OP 11) sums angles and takes one per cell.
+  static constexpr bool HAV = CELL == 5;
   static constexpr int DI = HAV ? 2 : D;  // input values per point
   using N = Num<V>;
   using C = std::conditional_t<HAV, float, typename N::Coord>;
@@ -636,6 +637,14 @@ struct Stream {
             s = N::fma(w, w, s);
           }
           if constexpr (CELL == 1) s = N::sqrt_cell(s);
+          if constexpr (HAV && DTW) {
+            // the angle per cell, from the FP64 chord through float32 (the
+            // hardware square root and the float arcsine: a few float ulps
+            // per cell, summed in FP64); separators (+inf) stay +inf, a
+            // chord rounded past the diameter is the antipode
+            float c = 0.5f * __builtin_amdgcn_sqrtf((float)s);
+            s = c <= 1.0f ? 2.0 * (double)asinf(c) : (s < N::inf() ? 3.141592653589793 : s);
+          }
         }
         if constexpr (LEV) {
           // d = [p_i != q_j] (separators: 1)
@@ -876,7 +885,10 @@ struct Stream {
     if (RINGS && hout63 == kHoutRing && lane == 0)
       __hip_atomic_store(xctr(wib), x63 + kGroup < L63 ? x63 + kGroup : L63, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    if constexpr (CAP) {
+    if constexpr (CAP && HAV) {
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
+        static_cast<float *>(a.out)[out63] = (float)cap;
+    } else if constexpr (CAP) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
     } else if constexpr (HAV) {
       // the central angle of the selected squared chord, in FP64, rounded

@@ -82,6 +82,13 @@ def main():
     gidx = sorted(set(gidx) | {int(np.argmax(gcells)), int(np.argmin(gcells))})
     gv = oracle.dfd_pairs(GP, gpo[:-1][gidx], np.diff(gpo)[gidx], GQ, gqo[:-1][gidx], np.diff(gqo)[gidx],
                           oracle.HAVERSINE, nthreads)
+    gd = oracle.dfd_pairs(GP, gpo[:-1][gidx], np.diff(gpo)[gidx], GQ, gqo[:-1][gidx], np.diff(gqo)[gidx],
+                          oracle.HAVERSINE, nthreads, measure="dtw")
+    out["dtw_haversine"] = {
+        "workload": "geo_pairs(seed=9) as below, DTW of great-circle angles (radians)",
+        "sample_index": [int(i) for i in gidx],
+        "haversine": [float(v) for v in gd],
+    }
     out["batched_haversine"] = {
         "workload": "geo_pairs(seed=9): 4096 pairs of (latitude, longitude) walks on the sphere, lengths in "
                     "[64, 2048], great-circle distance (radians)",

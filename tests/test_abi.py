@@ -183,13 +183,14 @@ def test_metric_checks(planner):
 
 def test_great_circle_checks(planner):
     """FFD_HAVERSINE: (latitude, longitude) points for the float32 Frechet
-    calls only; the workspace size covers its FP64 plan."""
+    and DTW calls only; the workspace size covers their FP64 plans."""
     L = ffd.lib
     H = ffd.FFD_HAVERSINE
     assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, H, FAKE, None) == ffd.FFD_E_DEVICE
     assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 3, H, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 1, H, FAKE, None) == ffd.FFD_E_INVALID
-    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, H, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 2, H, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_distance(planner, FAKE, 5, FAKE, 7, 3, H, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_distance_i32(planner, FAKE, 5, FAKE, 7, 2, H, FAKE, None) == ffd.FFD_E_UNSUPPORTED
     assert L.ffd_dtw_distance_i32(planner, FAKE, 5, FAKE, 7, 2, H, FAKE, None) == ffd.FFD_E_UNSUPPORTED
     P, p_off, Q, q_off = workloads.random_pairs(6, 60, 1, 9000, dim=2)
@@ -206,8 +207,12 @@ def test_great_circle_checks(planner):
     qo = np.array([0, 4, 9], dtype=np.int64)
     assert L.ffd_cross(planner, FAKE, _i64p(qo), 2, FAKE, _i64p(p_off), 60, 2, H, FAKE, FAKE, 1 << 30,
                        None) == ffd.FFD_E_DEVICE
+    assert L.ffd_dtw_batch(planner, FAKE, _i64p(p_off), FAKE, _i64p(q_off), 60, 2, H, FAKE, FAKE, need,
+                           None) == ffd.FFD_E_DEVICE
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2, metric=H, dtw=True)
+    assert sm["rows_per_lane"] <= 4
     with pytest.raises(ffd.FFDError):
-        ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2, metric=H, dtw=True)
+        ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2, metric=H, exact=True)
 
 
 def test_levenshtein_argument_checks(planner):

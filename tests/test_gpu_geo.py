@@ -1,5 +1,5 @@
-"""GPU parity of the Frechet distance under the great-circle ground
-distance (metric FFD_HAVERSINE) through the C ABI.
+"""GPU parity of the Frechet distance and DTW under the great-circle
+ground distance (metric FFD_HAVERSINE) through the C ABI.
 
 The library maps each (latitude, longitude) point to its FP64 unit vector,
 sweeps Eq. (1) on squared chords and takes the central angle once per pair;
@@ -138,6 +138,48 @@ def test_long_pairs(ctx):
         assert close(got, oracle.dfd(p, q, H, "rolling"))
 
 
+def dtw_close(got, want, n, m):
+    # each cell's angle carries a few float32 ulps (square root and arcsine
+    # of the FP64 chord), the sum is FP64, the result is rounded once
+    return abs(float(got) - want) <= 2e-6 * want + 1e-12 * (n + m)
+
+
+def test_dtw(ctx):
+    """DTW (Appendix B) on great-circle cells: one angle per cell, summed in
+    FP64, in the single-pair, batch and cross forms and across launch
+    shapes."""
+    P, p_off, Q, q_off = workloads.geo_pairs(seed=760, npairs=60, lo=1, hi=1500)
+    say("case: geo dtw batch")
+    got = ctx.dtw_batch(dev(P), p_off, dev(Q), q_off, metric=H).cpu().numpy()
+    want = oracle.dtw_batch(P, p_off, Q, q_off, H, nthreads=8)
+    n, m = np.diff(p_off), np.diff(q_off)
+    bad = [k for k in range(60) if not dtw_close(got[k], want[k], n[k], m[k])]
+    assert not bad, [(k, float(got[k]), want[k]) for k in bad[:5]]
+    for k in range(0, 60, 12):
+        p, q = P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]]
+        assert ctx.dtw_distance(dev(p), dev(q), metric=H).item() == got[k]
+    for R in (1, 2, 4, 8):
+        say(f"case: geo dtw R={R}")
+        ctx.set_tuning(R, 0)
+        try:
+            np.testing.assert_array_equal(ctx.dtw_batch(dev(P), p_off, dev(Q), q_off, metric=H).cpu().numpy(), got)
+        finally:
+            ctx.set_tuning(0, 0)
+    Qs, qo = workloads.concat([P[p_off[k]:p_off[k + 1]] for k in range(3)])
+    DB, do = workloads.concat([Q[q_off[k]:q_off[k + 1]] for k in range(20)])
+    say("case: geo dtw cross")
+    cr = ctx.dtw_cross(dev(Qs), qo, dev(DB), do, metric=H).cpu().numpy()
+    cw = oracle.dtw_cross(Qs, qo, DB, do, H, nthreads=8)
+    for i in range(3):
+        for k in range(20):
+            assert dtw_close(cr[i, k], cw[i, k], qo[i + 1] - qo[i], do[k + 1] - do[k])
+    rng = np.random.default_rng(761)
+    p, q = curve(rng, 2500, 2e-3), curve(rng, 1800, 2e-3)
+    say("case: geo dtw long pair")
+    assert dtw_close(ctx.dtw_distance(dev(p), dev(q), metric=H).item(), oracle.dtw(p, q, H), 2500, 1800)
+    assert ctx.last_errors() == 0
+
+
 def test_full_workload_sampled(ctx):
     """The 4096-pair sphere workload in the launch configuration bench.py
     times, checked on the pairs the stored values cover."""
@@ -156,10 +198,6 @@ def test_refused_forms(ctx):
     with pytest.raises(ffd.FFDError) as e:
         ctx.distance(p, p, metric=H)
     assert e.value.status == ffd.FFD_E_INVALID
-    p2 = dev(np.zeros((4, 2), np.float32))
-    with pytest.raises(ffd.FFDError) as e:
-        ctx.dtw_distance(p2, p2, metric=H)
-    assert e.value.status == ffd.FFD_E_UNSUPPORTED
     pi = torch.zeros((4, 2), dtype=torch.int32, device="cuda:0")
     with pytest.raises(ffd.FFDError) as e:
         ctx.distance_i32(pi, pi, metric=H)

@@ -10,8 +10,8 @@ formula in FP64.  It is tied here to things other than itself:
   antipodal points are pi apart;
 * an independent formula: atan2(|u x v|, u . v) on the unit vectors u, v,
   in numpy FP64 (well conditioned at every angle);
-* the Frechet distance on these cells against brute force over all
-  couplings with the independent formula's matrix;
+* the Frechet distance and DTW on these cells against brute force over
+  all couplings with the independent formula's matrix;
 * invariances: rotation about the polar axis (a longitude shift),
   reflection in the equator, swapping the curves (bit-exact);
 * the triangle inequality of the discrete Frechet distance;
@@ -99,6 +99,18 @@ def test_frechet_equals_brute_force():
         exp = brute.brute_from_matrix(angle_matrix(p, q).tolist())
         for method in ("table", "rolling", "recursive"):
             assert oracle.dfd(p, q, H, method) == pytest.approx(exp, rel=1e-12, abs=1e-15)
+
+
+def test_dtw_equals_brute_force():
+    """DTW (Appendix B) on great-circle cells: the smallest sum of angles
+    over all couplings, with the independent formula's matrix."""
+    rng = np.random.default_rng(708)
+    for _ in range(40):
+        n, m = (int(v) for v in rng.integers(1, 7, size=2))
+        p = workloads.geo_walk(rng, n, 0.05).astype(np.float32)
+        q = workloads.geo_walk(rng, m, 0.05).astype(np.float32)
+        exp = brute.brute_dtw_from_matrix(angle_matrix(p, q).tolist())
+        assert oracle.dtw(p, q, H) == pytest.approx(exp, rel=1e-12, abs=1e-15)
 
 
 def test_invariances_and_symmetry():

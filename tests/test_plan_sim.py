@@ -82,7 +82,8 @@ def test_single_pairs(planner, n, m, dim):
 
 
 @pytest.mark.parametrize("dtw,metric,lev", [(True, 1, False), (True, 0, False), (False, 2, False),
-                                            (True, 3, False), (False, 1, True), (False, 4, False)])
+                                            (True, 3, False), (False, 1, True), (False, 4, False),
+                                            (True, 4, False)])
 def test_other_kernels(planner, dtw, metric, lev):
     P, p_off, Q, q_off = workloads.random_pairs(412, 200, 1, 6000, dim=2)
     sm = batch_case(planner, p_off, q_off, dtw=dtw, metric=metric, exact=lev, levenshtein=lev)
