@@ -47,7 +47,7 @@ struct ffd_db {
 
 namespace {
 
-constexpr int kServeR = 8;       // rows per lane
+constexpr int kServeR = 8;       // rows per lane of a tick with a query longer than 256 points
 constexpr int kServeW = 2;       // LDS share of a wave: 1 / (4 kServeW) of a CU
 constexpr int kTicks = 4;        // launches in flight
 
@@ -98,8 +98,10 @@ struct ffd_server {
   ffd_db *db = nullptr;
   int device = 0;
   int dim = 0;
-  // launch shape
+  // launch shape (capacities are sized for R; a tick whose queries are all
+  // short runs with fewer rows per lane, see query_rows)
   int R = kServeR, nwaves = 0, wpb = 1, lds_per_wave = 0;
+  int lds_rows[9] = {};           // LDS per wave for 1, 2, 4, 8 rows per lane
   int64_t hcap = 0;
   // database in chunk order
   std::vector<Chunk> chunks;
@@ -171,6 +173,7 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
   s.wpb = std::min(rs.wpb, s.nwaves);
   s.hcap = rs.hand_max;
   s.lds_per_wave = lds_bytes(s.R, s.dim, false, s.hcap);
+  for (int r = 1; r <= kServeR; r *= 2) s.lds_rows[r] = lds_bytes(r, s.dim, false, s.hcap);
   s.max_query = max_query;
   s.kmax = std::max(1, (max_slots + kTicks - 1) / kTicks);
   s.qcap = (int64_t)s.kmax * max_query;
@@ -273,19 +276,36 @@ Job band_job(int32_t i, const Chunk &ch, int64_t ndb) {
   return jb;
 }
 
+// Rows per lane for a query of n points: the smallest R whose one band
+// (64 R rows) holds it, up to kServeR.  A band's rows past the query's end
+// are computed and dropped, so a short query in a 512-row band wastes most
+// of it; ticks group queries of one class.
+int query_rows(int64_t n) {
+  int R = 1;
+  while (R < kServeR && n > (int64_t)ffd::kWave * R) R *= 2;
+  return R;
+}
+
 // Admit queued requests into tick t and launch it.  Called with the lock held.
 int launch_tick(ffd_server &s, Tick &t) {
   const TickLayout &L = s.lay;
   const int64_t ndb = s.db->ndb;
-  // requests: FIFO, same metric, within the tick's capacity
+  // requests: the oldest one, then, from the next few in arrival order,
+  // those with the same metric and rows-per-lane class, within the tick's
+  // capacity (no request is passed over by more than 4 kmax later ones)
   int32_t metric = s.pending.front()->metric;
+  const int Rt = query_rows(s.pending.front()->n);
   int64_t pts = 0;
-  while (!s.pending.empty() && (int)t.reqs.size() < s.kmax) {
-    Request *r = s.pending.front();
-    if (r->metric != metric || pts + r->n > s.qcap) break;
+  const size_t window = (size_t)4 * s.kmax;
+  for (size_t i = 0; i < s.pending.size() && i < window && (int)t.reqs.size() < s.kmax;) {
+    Request *r = s.pending[i];
+    if (r->metric != metric || query_rows(r->n) != Rt || pts + r->n > s.qcap) {
+      ++i;
+      continue;
+    }
     pts += r->n;
     t.reqs.push_back(r);
-    s.pending.pop_front();
+    s.pending.erase(s.pending.begin() + (std::ptrdiff_t)i);
     r->state = 1;
   }
   const int k = (int)t.reqs.size();
@@ -309,7 +329,7 @@ int launch_tick(ffd_server &s, Tick &t) {
     const Chunk &ch = s.chunks[w];
     int64_t steps = 0;
     for (int i = 0; i < k; ++i) {
-      int64_t nb = ffd::bands_for(t.reqs[i]->n, s.R);
+      int64_t nb = ffd::bands_for(t.reqs[i]->n, Rt);
       Job jb = band_job(i, ch, ndb);
       int64_t sumL = ch.sumL[nb > 1 ? 1 : 0];
       if (nb == 1 || ch.maxL <= s.hcap) {
@@ -364,13 +384,13 @@ int launch_tick(ffd_server &s, Tick &t) {
   a.nwaves = s.nwaves;
   a.metric = metric;
   a.hcap = (int32_t)s.hcap;
-  a.lds_per_wave = s.lds_per_wave;
+  a.lds_per_wave = s.lds_rows[Rt];
   a.max_steps = (int32_t)(max_steps + 4 * ffd::kRing);
   a.epoch = t.epoch;
   a.links = t.dev + L.links;
   a.flags = reinterpret_cast<uint64_t *>(t.dev + L.flags);
   a.err = reinterpret_cast<uint64_t *>(t.dev + L.err);
-  e = ffd::launch_stream(false, s.R, s.dim, a, s.wpb, false, t.stream);
+  e = ffd::launch_stream(false, Rt, s.dim, a, s.wpb, false, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
   e = hipMemcpyAsync(t.pin_out, t.dev + L.out, (size_t)k * ndb * sizeof(float), hipMemcpyDeviceToHost, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
