@@ -63,8 +63,8 @@ struct Bounded {
   }
 
   // Column points of the group starting at t0 for this lane (columns
-  // t0 + u - lane, clamped; columns before 0 are flagged by the caller) and
-  // lane 0's row-above values.
+  // t0 + u - lane, clamped to the last; columns before the first are +inf
+  // points, so their cells are +inf) and lane 0's row-above values.
   // (The host keeps m * D below 2^31, so 32-bit offsets from the curve's
   // first point address every column.)
   __device__ __forceinline__ void load_group(int32_t t0, const float *qb, int32_t m, bool above,
@@ -72,9 +72,10 @@ struct Bounded {
 #pragma unroll
     for (int u = 0; u < kGroupB; ++u) {
       int32_t j = t0 + u - lane;
-      j = j < 0 ? 0 : (j > m - 1 ? m - 1 : j);
+      const bool sep = j < 0;
+      j = sep ? 0 : (j > m - 1 ? m - 1 : j);
 #pragma unroll
-      for (int k2 = 0; k2 < D; ++k2) q[u][k2] = qb[j * D + k2];
+      for (int k2 = 0; k2 < D; ++k2) q[u][k2] = sep ? __builtin_huge_valf() : qb[j * D + k2];
       int32_t c = t0 + u;
       h[u] = above && c < m ? load_l2(hin + c) : __builtin_huge_valf();
     }
@@ -152,7 +153,7 @@ struct Bounded {
 #pragma unroll
         for (int u = 0; u < kGroupB; ++u) {
           const int32_t t = t0 + u;
-          const bool sep = t - lane < 0;  // columns before the first: +inf cells
+          const bool sep = t - lane < 0;  // columns before the first
           float up = shift_in(h[u], Mp[R - 1]);
           float above_v = up, diag = upPrev;
 #pragma unroll
@@ -164,7 +165,6 @@ struct Bounded {
               float w = p[r][k2] - q[u][k2];
               s = __builtin_fmaf(w, w, s);
             }
-            s = sep ? inf : s;
             float v = __builtin_fmaxf(__builtin_fminf(__builtin_fminf(above_v, diag), Mp[r]), s);
             diag = Mp[r];
             above_v = v;

@@ -97,11 +97,23 @@ int search_scratch(ffd_ctx *ctx, size_t bytes, hipStream_t st) {
   return FFD_OK;
 }
 
-// Waves of a launch: two per SIMD, at most one per pair, whole workgroups
-// of four.
-int search_waves(ffd_ctx *ctx, int64_t npairs) {
-  int64_t w = std::min<int64_t>((int64_t)ctx->cus * 8, npairs);
+// Waves of a launch, in whole workgroups of four: at most one per pair,
+// and between one and two per SIMD -- as many as keep the average wave's
+// steps (total / waves) above the longest pair's, since one wave sweeps a
+// whole pair and the longest one would otherwise set the launch time.
+int search_waves(ffd_ctx *ctx, int64_t npairs, double total_steps = 0, double longest = 0) {
+  int64_t lo = (int64_t)ctx->cus * 4, hi = (int64_t)ctx->cus * 8;
+  int64_t w = hi;
+  if (longest > 0) w = std::max<int64_t>(lo, std::min<int64_t>(hi, (int64_t)(total_steps / longest)));
+  w = std::min<int64_t>(w, npairs);
   return (int)std::max<int64_t>(4, (w + 3) / 4 * 4);
+}
+
+// Steps of one pair on a wave: its bands, each a ramp of 64 steps and the
+// column curve, in groups of 16.
+double pair_steps(int64_t n, int64_t m, int R) {
+  int64_t nb = (n + 64 * R - 1) / (64 * R);
+  return (double)nb * (double)((m + 63 + 15) / 16 * 16);
 }
 
 struct Layout {
@@ -157,7 +169,13 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
   hipStream_t st = (hipStream_t)stream;
   int R = rows_per_lane(nsum / npairs);
   int64_t row_cap = nmax > 64 * R ? mmax + 1 : 0;
-  int nwaves = search_waves(ctx, npairs);
+  double total = 0, longest = 0;
+  for (int64_t k = 0; k < npairs; ++k) {
+    double st = pair_steps(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], R);
+    total += st;
+    longest = std::max(longest, st);
+  }
+  int nwaves = search_waves(ctx, npairs, total, longest);
   Layout L = layout(npairs, npairs, npairs, 0, 0, nwaves, row_cap);
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
   // larger pairs first, so that the work counter ends with small ones
