@@ -186,11 +186,13 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
  * (ffd_workspace_size covers both) and errors.  The ground distance is
  * summed per cell, so FFD_EUCLIDEAN takes the hardware float32 square root
  * (within 1 ulp) in every cell, FFD_SQEUCLIDEAN sums squared distances and
- * FFD_MANHATTAN / FFD_CHEBYSHEV their cell distances; the result is the sum
+ * FFD_MANHATTAN / FFD_CHEBYSHEV their cell distances, FFD_HAVERSINE the
+ * angles (float32 in every cell, summed in FP64); the result is the sum
  * itself.  Float32 results agree with the exact result to a relative error
  * of (n + m + 2 D + 2) 2^-24 (each cell carries at most 2 D + 1 rounding
  * errors, the sum along the selected coupling one per addition), for
- * Euclidean cells whose squared distance is not below 2^-126.  Int32 calls
+ * Euclidean cells whose squared distance is not below 2^-126; great-circle
+ * results to 2e-6 relative.  Int32 calls
  * (every metric but FFD_EUCLIDEAN) are exact while the sums stay below 2^53
  * (for example |x| < 2^15 and n + m < 2^19). */
 int ffd_dtw_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
