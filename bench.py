@@ -321,12 +321,12 @@ def run_levenshtein(args, torch, ffd, ctx, dev, stream):
                          f"Levenshtein oracle, longest first on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": bool(np.array_equal(vals, res[sample]))}
     return {
-        "metric": "levenshtein_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f64",
+        "metric": "levenshtein_cells_per_second", "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
         "config": {"workload": "levenshtein: 4096 pairs of int32 symbol sequences over 4 letters, lengths "
                                "uniform in [64, 2048], q = p resampled with 10% redrawn (seed 8)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"exact": True, "sampled_ok": parity_ok, "launch_error_flags": errs},
-        "roofline": roofline(info, cells, kms, 1, True, family="op_kernel", suffix=", 8", cell="levenshtein"),
+        "roofline": roofline(info, cells, kms, 1, False, family="op_kernel", suffix=", 8", cell="levenshtein"),
         "cpu_baseline": cpu,
     }
 

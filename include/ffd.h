@@ -222,7 +222,9 @@ int ffd_dtw_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int
  * algorithm's index vectors read 0-based), result M_PQ, exact int64.  The
  * calls take the arguments of ffd_distance_i32, ffd_batch_i32 and
  * ffd_cross_i32 without the metric, with the same layouts, workspace sizes
- * and errors. */
+ * and errors, and FFD_E_UNSUPPORTED when a pair's lengths reach n + m >=
+ * 2^24 (the table's values are held as float32 integers, exact below 2^24;
+ * any int32 symbol values are allowed). */
 int ffd_levenshtein_distance(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q,
                              int64_t m, int32_t dim, int64_t *out, void *stream);
 int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off,

@@ -68,7 +68,7 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
   int cell = op >> 1;
   double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell == 2 || cell == 3 ? 1 : 0);
-  if (op == 8) per_cell = 3 * D + 4;  // Levenshtein: a compare and a 64-bit select per coordinate, 4 FP64 ops
+  if (op == 8) per_cell = 2 * D + 5;  // Levenshtein: a compare per coordinate, the flag, a select, 4 ops
   if (op == 11) per_cell += 20;
   double I = (double)R * per_cell + 8.0;
   double lone = 104.0 + 3.9 * I;
@@ -121,7 +121,7 @@ int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
 }
 
 int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings, int measure) {
-  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, (measure & 1) != 0).total;
+  return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, measure == 8 ? ffd::lev_dim(D) : 0).total;
 }
 
 const int kRs[4] = {1, 2, 4, 8};
@@ -1206,11 +1206,23 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
 
 // Levenshtein distance (Appendix B, Algorithm B.2) of int32 symbol
 // sequences: the same calls with the Levenshtein kernels (kernel op 8).
+// The kernels hold the table's values in float32, exact below 2^24: every
+// value is at most n + m.
+constexpr int64_t kLevMax = (int64_t)1 << 24;
+
+static int64_t longest(const int64_t *off, int64_t count) {
+  int64_t l = 0;
+  if (!off) return 0;
+  for (int64_t k = 0; k < count; ++k) l = std::max(l, off[k + 1] - off[k]);
+  return l;
+}
+
 int ffd_levenshtein_distance(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
                              int64_t *out, void *stream) {
   if (!ctx) return FFD_E_INVALID;
+  if (n + m >= kLevMax) return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
   MeasureScope scope(ctx, 8);
-  return pair_common(ctx, p, n, q, m, dim, FFD_SQEUCLIDEAN, out, (hipStream_t)stream, true);
+  return pair_common(ctx, p, n, q, m, dim, FFD_SQEUCLIDEAN, out, (hipStream_t)stream, false);
 }
 
 int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,
@@ -1218,8 +1230,12 @@ int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, 
                           size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
   MeasureScope scope(ctx, 8);
+  if (npairs > 0 && check_offsets(ctx, p_off, npairs, "p_off is NULL") == FFD_OK &&
+      check_offsets(ctx, q_off, npairs, "q_off is NULL") == FFD_OK &&
+      longest(p_off, npairs) + longest(q_off, npairs) >= kLevMax)
+    return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
-                      (hipStream_t)stream, true);
+                      (hipStream_t)stream, false);
 }
 
 int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t nq, const int32_t *DB,
@@ -1227,8 +1243,12 @@ int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off,
                           size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
   MeasureScope scope(ctx, 8);
+  if (nq > 0 && ndb > 0 && check_offsets(ctx, q_off, nq, "q_off is NULL") == FFD_OK &&
+      check_offsets(ctx, db_off, ndb, "db_off is NULL") == FFD_OK &&
+      longest(q_off, nq) + longest(db_off, ndb) >= kLevMax)
+    return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
-                      (hipStream_t)stream, true);
+                      (hipStream_t)stream, false);
 }
 
 // Dynamic time warping (Appendix B): the same calls with the DTW kernels.
@@ -1298,7 +1318,7 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   if (measure < 0 || measure > 2) return fail(ctx, FFD_E_INVALID, "unknown measure");
   if (measure == 2 && !exact) return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein takes int32 symbols");
   MeasureScope scope(ctx, measure == 2 ? 8 : op_of(measure == 1, metric, exact == 0));
-  bool ex = exact != 0;
+  bool ex = exact != 0 && measure != 2;  // Levenshtein: int32 symbols, float32 values
   int rc = geo_shape(ctx, metric, dim, ex);
   if (rc) return rc;
   if ((rc = check_common(ctx, dim, metric, ex))) return rc;
@@ -1351,7 +1371,7 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   size_t worst = 0;
   for (int ms = 0; ms <= kOpGeoDtw; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
-      if (ms == 2 || ms == 9 || (ms == 3 && ex == 1) || (ms == 8 && ex == 0)) continue;  // no such kernel
+      if (ms == 2 || ms == 9 || (ms == 3 && ex == 1) || (ms == 8 && ex == 1)) continue;  // no such kernel
       if (ms >= kOpGeo && (ex == 0 || dim != 2)) continue;  // FP64 on (latitude, longitude) only
       MeasureScope scope(ctx, ms);
       const Plan *pl;

@@ -3,8 +3,8 @@
 // This unit is compiled once per OP (-DFFD_OP=...), in parallel: 1 DTW of
 // squared Euclidean cells, 3 DTW of Euclidean cells (float32 only), 4
 // Frechet on Manhattan cells, 5 DTW on Manhattan cells, 6 Frechet on
-// Chebyshev cells, 7 DTW on Chebyshev cells, 8 Levenshtein (int32 symbols
-// only), 10 Frechet and 11 DTW on great-circle distances (float32
+// Chebyshev cells, 7 DTW on Chebyshev cells, 8 Levenshtein (int32 symbols,
+// float32 values), 10 Frechet and 11 DTW on great-circle distances (float32
 // (latitude, longitude) input, FP64 unit vectors: the value type double,
 // D = 3).
 #include "ffd_launch.h"
@@ -20,11 +20,12 @@ namespace ffd {
 
 namespace {
 struct OpSel {
-  // int32 coordinates (exact FP64 values) for every op but Euclidean cells;
-  // float32 coordinates for every op but Levenshtein; the great-circle op
-  // computes in FP64 (its `exact` shape) on float32 input
-  static constexpr bool kExact = FFD_OP != 3;
-  static constexpr bool kFloat = FFD_OP != 8 && FFD_OP != 10 && FFD_OP != 11;
+  // int32 coordinates (exact FP64 values) for every op but Euclidean cells
+  // and Levenshtein; float32 coordinates for every op but the great-circle
+  // ones, which compute in FP64 (their `exact` shape) on float32 input;
+  // Levenshtein runs on float32 values with int32 symbols as bit patterns
+  static constexpr bool kExact = FFD_OP != 3 && FFD_OP != 8;
+  static constexpr bool kFloat = FFD_OP != 10 && FFD_OP != 11;
   static constexpr int kOnlyD = FFD_OP == 10 || FFD_OP == 11 ? 3 : 0;
   template <int R, int D, typename V>
   static auto kernel() { return &op_kernel<R, D, V, FFD_OP>; }

@@ -97,16 +97,19 @@ struct LdsLayout {
 };
 
 FFD_HD int align16(int x) { return (x + 15) & ~15; }
-FFD_HD int pad_dim(int D) { return D == 3 ? 4 : D; }
+FFD_HD constexpr int pad_dim(int D) { return D == 3 ? 4 : D; }
+// Levenshtein ring entries: the D symbol values and a separator flag, padded
+// to a power of two.
+FFD_HD constexpr int lev_dim(int D) { return D == 1 ? 2 : (D <= 3 ? 4 : 8); }
 
 // rings: the wave also owns a ring that hands its bottom row to another
 // wave of its workgroup.  dtw: the layout of the DTW kernels.
-FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings, bool dtw = false) {
+// dp: values per ring entry (0: pad_dim(D)).
+FFD_HD LdsLayout lds_layout(int R, int D, int vsize, int hcap, bool rings, int dp = 0) {
   LdsLayout L;
   int o = 0;
-  L.ring = o;  o += (kRing + kGroup) * pad_dim(D) * vsize;
+  L.ring = o;  o += (kRing + kGroup) * (dp ? dp : pad_dim(D)) * vsize;
   L.ghost = o; o += (2 * kGroup + 1) * vsize;
-  (void)dtw;
   L.sink = o;  o += (kWave + kGroup) * vsize;
   o = align16(o); L.hand = o; o += hcap * vsize;
   o = align16(o); L.lring = o; o += kLinkRing * vsize;

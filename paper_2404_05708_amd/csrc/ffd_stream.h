@@ -47,7 +47,9 @@
 // column of the old one.  Levenshtein also sets the new task's first
 // (separator) column to its boundary M_{i,-1} = i + 1 at that moment; the
 // recurrence keeps it through the other separators, and lane 0's top
-// boundary is the ramp M_{-1,j} = j + 1 after a 0 corner.
+// boundary is the ramp M_{-1,j} = j + 1 after a 0 corner.  The separators of
+// a Levenshtein task carry a flag in an extra slot of the ring entry, since
+// every int32 value is a possible symbol.
 //
 // The squared distance is evaluated as d2 = dx*dx, then d2 = fma(dk, dk, d2)
 // for k >= 1, in the value type; the recurrence runs on d2 and the Euclidean
@@ -165,7 +167,10 @@ struct Stream {
   static constexpr bool DTW = (OP & 1) != 0;
   static constexpr int CELL = OP >> 1;
   // OP 8: Levenshtein distance of int32 symbol sequences (cell 4:
-  // [p_i != q_j]; M_ij = min{M_{i-1,j} + 1, M_{i,j-1} + 1, M_{i-1,j-1} + d_ij})
+  // [p_i != q_j]; M_ij = min{M_{i-1,j} + 1, M_{i,j-1} + 1, M_{i-1,j-1} + d_ij}),
+  // instantiated with V = float: the symbols travel as their bit patterns
+  // (compared, never computed with) and the values are integers below 2^24,
+  // exact in float32 (the host limits n + m)
   static constexpr bool LEV = OP == 8;
   // the result is taken from the lane of the curve's last row at its switch
   static constexpr bool CAP = DTW || LEV;
@@ -182,7 +187,8 @@ struct Stream {
   using N = Num<V>;
   using C = std::conditional_t<HAV, float, typename N::Coord>;
   static_assert(!HAV || (D == 3 && sizeof(V) == 8), "great-circle sweeps run on FP64 unit vectors");
-  static constexpr int DP = D == 3 ? 4 : D;
+  // values per ring entry; Levenshtein keeps a separator flag in slot D
+  static constexpr int DP = LEV ? lev_dim(D) : pad_dim(D);
   struct alignas(sizeof(V) * DP) Pt {
     V c[DP];
   };
@@ -510,6 +516,10 @@ struct Stream {
       stage(qbuf, u);
 #pragma unroll
       for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : u[k2]) : V(0);
+    } else if constexpr (LEV) {
+      // symbols as they are (int32 bit patterns), the flag set on separators
+#pragma unroll
+      for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? N::cvt(qbuf[k2]) : (k2 == D && qsep ? V(1) : V(0));
     } else {
 #pragma unroll
       for (int k2 = 0; k2 < DP; ++k2) e.c[k2] = k2 < D ? (qsep ? N::inf() : N::cvt(qbuf[k2])) : V(0);
@@ -647,10 +657,13 @@ struct Stream {
           }
         }
         if constexpr (LEV) {
-          // d = [p_i != q_j] (separators: 1)
-          s = V(0);
+          // d = [p_i != q_j], symbols compared as bit patterns; a separator
+          // (flag slot set) differs from every symbol
+          bool ne = __builtin_bit_cast(uint32_t, g.q[u].c[D]) != 0u;
 #pragma unroll
-          for (int k2 = 0; k2 < D; ++k2) s = p[r][k2] != g.q[u].c[k2] ? V(1) : s;
+          for (int k2 = 0; k2 < D; ++k2)
+            ne = ne || __builtin_bit_cast(uint32_t, p[r][k2]) != __builtin_bit_cast(uint32_t, g.q[u].c[k2]);
+          s = ne ? V(1) : V(0);
         }
         dd[r] = s;
       }
@@ -885,7 +898,10 @@ struct Stream {
     if (RINGS && hout63 == kHoutRing && lane == 0)
       __hip_atomic_store(xctr(wib), x63 + kGroup < L63 ? x63 + kGroup : L63, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    if constexpr (CAP && HAV) {
+    if constexpr (LEV) {
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
+        static_cast<int64_t *>(a.out)[out63] = (int64_t)cap;
+    } else if constexpr (CAP && HAV) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
         static_cast<float *>(a.out)[out63] = (float)cap;
     } else if constexpr (CAP) {
@@ -913,7 +929,7 @@ struct Stream {
 #ifdef FFD_DEBUG_HIN
     dbg_wave = wave;
 #endif
-    lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS, DTW);
+    lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS, DP);
     int32_t j0, j1;
     if (a.jobs) {
       j0 = uni(a.wave_jobs[wave]);

@@ -221,6 +221,11 @@ def test_levenshtein_argument_checks(planner):
     assert L.ffd_levenshtein_distance(planner, None, 5, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_levenshtein_distance(planner, FAKE, 0, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 5, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    # values are float32 integers: n + m must stay below 2^24
+    assert L.ffd_levenshtein_distance(planner, FAKE, 1 << 23, FAKE, 1 << 23, 1, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    big = np.array([0, 1 << 23], dtype=np.int64)
+    assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(big), FAKE, _i64p(big), 1, 1, FAKE, FAKE, 1 << 20,
+                                   None) == ffd.FFD_E_UNSUPPORTED
     good = np.array([0, 3, 5, 9], dtype=np.int64)
     assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(good), FAKE, _i64p(good), 3, 1, FAKE, FAKE, 1 << 20,
                                    None) == ffd.FFD_E_DEVICE

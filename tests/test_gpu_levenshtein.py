@@ -67,6 +67,23 @@ def test_edge_cases(ctx):
     assert ctx.levenshtein(dev(a), dev(b)).item() == 450
 
 
+def test_extreme_symbol_values(ctx):
+    """Symbols whose bit patterns are float specials (+-0, infinities, NaNs,
+    denormals) stay distinct: the kernel compares bit patterns, never floats,
+    and marks separators outside the symbol values."""
+    special = np.array([0, -2 ** 31, 2 ** 31 - 1, -1, 0x7F800000, -0x00800000, 0x7FC00000, 0x7FC00001,
+                        1, 0x00000001, 0x3F800000, 2 ** 24, 2 ** 24 + 1], dtype=np.int64).astype(np.int32)
+    rng = np.random.default_rng(512)
+    for n, m, D in [(40, 33, 1), (700, 650, 1), (90, 120, 2), (300, 200, 3), (130, 140, 4)]:
+        p = special[rng.integers(0, len(special), size=(n, D))]
+        q = special[rng.integers(0, len(special), size=(m, D))]
+        say(f"case: levenshtein special symbols n={n} m={m} D={D}")
+        assert ctx.levenshtein(dev(p), dev(q)).item() == oracle.lev(p, q)
+    # +0 and -0 as float are the same value; as symbols they differ
+    z, nz = np.zeros((5, 1), np.int32), np.full((5, 1), -2 ** 31, np.int32)
+    assert ctx.levenshtein(dev(z), dev(nz)).item() == 5
+
+
 def test_batch_cross_pairs_split_and_long(ctx):
     P, p_off, Q, q_off = workloads.symbol_pairs(seed=511, npairs=150, lo=1, hi=2500)
     say("case: levenshtein batch of 150 pairs")
