@@ -44,14 +44,28 @@ def _compile(item):
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+# A debug variant for the stress tests: the streaming kernels pause for a
+# pseudo-random time before each progress publication (FFD_DEBUG_JITTER);
+# everything else is the release objects.
+JITTER_LIB = os.path.join(HERE, "libffd_jitter.so")
+JITTER_SOURCES = [("ffd_kernels.hip", {"FFD_DEBUG_JITTER": 1}), ("ffd_kernels_rings.hip", {"FFD_DEBUG_JITTER": 1})]
+
+
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True, capture_output=not verbose)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    items = SOURCES + JITTER_SOURCES
+    with ThreadPoolExecutor(min(len(items), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, items))
+    release, jitter = objs[:len(SOURCES)], objs[len(SOURCES):]
+    _link(release, LIB, verbose)
+    _link(jitter + release[len(JITTER_SOURCES):], JITTER_LIB, verbose)
     return LIB
 
 

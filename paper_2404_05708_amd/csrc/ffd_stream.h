@@ -38,9 +38,9 @@
 // cell 0 squared Euclidean, 1 Euclidean (the hardware square root per cell,
 // DTW only: the Frechet kernel takes one root per pair), 2 Manhattan
 // (sum of |dk|), 3 Chebyshev (max of |dk|); OP 8 is the Levenshtein
-// distance of int32 symbol sequences (Appendix B, Algorithm B.2); OP 10 is
-// the Frechet distance of curves on the sphere under the great-circle
-// distance (see Stream::HAV).  Sums are
+// distance of int32 symbol sequences (Appendix B, Algorithm B.2); OP 10
+// and 11 are the Frechet distance and DTW of curves on the sphere under the
+// great-circle distance (see Stream::HAV).  Sums are
 // not selections, so row padding is no longer exact: the DTW corner is 0,
 // and the result M_{n-1,m-1} is taken from the lane holding row n-1 at the
 // moment it enters the next task, when its registers still hold the last
@@ -764,11 +764,25 @@ struct Stream {
   // flush are published at the next one (kFill steps later, when every
   // older memory operation of the wave has long completed), or at once at
   // the end of the stream (`last`).
+#ifdef FFD_DEBUG_JITTER
+  // Debug builds only: a pause of 0 to 7 short sleeps before a progress
+  // publication, varying with the wave and a stream quantity, so that tests
+  // see the waits on it resolve in many orders.
+  __device__ __forceinline__ void jitter(uint32_t x) const {
+    uint32_t h = ((uint32_t)blockIdx.x * 0x9E3779B1u) ^ ((uint32_t)wib * 0x85EBCA77u) ^ (x * 0xC2B2AE3Du);
+    h ^= h >> 15;
+    for (uint32_t i = 0; i < (h & 7u); ++i) __builtin_amdgcn_s_sleep(2);
+  }
+#else
+  __device__ __forceinline__ void jitter(uint32_t) const {}
+#endif
+
   __device__ void publish_pending(FillState &f) {
     if (f.pub_flag[0] >= 0 || f.pub_flag[1] >= 0) {
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      jitter(f.pub_count[0] + f.pub_count[1]);
       if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -875,6 +889,7 @@ struct Stream {
       int32_t x0 = t0 - S0;
       wait_ctr(xctr(src0), x0 + kGroup < L0 ? x0 + kGroup : L0);
       load_group(t0, hin_at(t0), g);
+      jitter((uint32_t)t0);
       if (lane == 0) __hip_atomic_store(xctr(src0) + 1, x0 + kGroup, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
       load_group(t0, hin_at(t0), g);
@@ -895,6 +910,7 @@ struct Stream {
     bool window = CAP && t0 < win0 + kWave;
     if (!window) group<true>(t0, win0, false, g, hout, res, rc63);
     else group<false>(t0, win0, window, g, hout, res, rc63);
+    if (RINGS && hout63 == kHoutRing) jitter((uint32_t)x63);
     if (RINGS && hout63 == kHoutRing && lane == 0)
       __hip_atomic_store(xctr(wib), x63 + kGroup < L63 ? x63 + kGroup : L63, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_WORKGROUP);

@@ -109,10 +109,11 @@ class FFDError(RuntimeError):
         self.status = status
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
-    lib = ctypes.CDLL(LIB_PATH)
+def _load(path=None):
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     i64 = ctypes.c_int64
     i32 = ctypes.c_int32
@@ -199,6 +200,13 @@ def _load():
 
 
 lib = _load()
+
+
+def load_library(path):
+    """Another build of the library (for example the debug variant the
+    stress tests use), loaded beside the default one with the same
+    signatures; its functions are called directly."""
+    return _load(path)
 
 
 def _check(rc, ctx=None):
