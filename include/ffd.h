@@ -388,8 +388,9 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
  * out_dist[i] (float32, device) for i < min(k, ndb), in increasing
  * distance, ties by the smaller index; entries past ndb get index -1 and
  * distance +inf.  Stages: the larger of the first-point and last-point
- * distances bounds each curve's distance from below; the 128 curves (at
- * least k) with the smallest bounds are evaluated exactly and the k-th
+ * distances bounds each curve's distance from below; 128 curves (at least
+ * k) with the smallest bounds, taken from those at most four times the
+ * median length when there are enough, are evaluated exactly and the k-th
  * smallest distance becomes the threshold; every other curve whose bound
  * does not exceed it runs through the early-abandoning sweep at that
  * threshold.  Database layout as ffd_cross (device coordinates, HOST

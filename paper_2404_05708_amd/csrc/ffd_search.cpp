@@ -6,8 +6,9 @@
 //   1. a lower bound per database curve, the larger of the squared
 //      first-point and last-point distances (every coupling contains both
 //      corner cells), computed on the GPU;
-//   2. exact squared distances of the curves with the smallest bounds (at
-//      least k of them): the k-th smallest is the threshold tau;
+//   2. exact squared distances of 128 curves (at least k) with the smallest
+//      bounds, among curves of moderate length: the k-th smallest is the
+//      threshold tau;
 //   3. every other curve whose bound is at most tau runs through the sweep
 //      with threshold tau, which drops a pair as soon as a crossing set of
 //      its table exceeds tau;
@@ -241,9 +242,11 @@ int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int6
   if (e == hipSuccess) e = hipMemcpyAsync(lb.data(), lb_dev, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(ctx, e, "search bounds");
+  // the curves with the smallest bounds first (ties by index); the rest is
+  // only split by the threshold later, so no full sort is needed
   std::vector<int32_t> idx(ndb);
   std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return lb[x] < lb[y]; });
+  auto by_bound = [&](int32_t x, int32_t y) { return lb[x] < lb[y] || (lb[x] == lb[y] && x < y); };
 
   ffd::BoundedArgs a{};
   a.X0 = q;
@@ -273,12 +276,26 @@ int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int6
   };
   std::vector<std::pair<float, int32_t>> pool;
   const int64_t s1 = std::min<int64_t>(ndb, std::max<int64_t>(kk, kStageOne));
+  if (s1 < ndb) {
+    // one wave sweeps one curve, so the longest curve of the first stage
+    // sets its time: take its curves from those no longer than four times
+    // the median length when enough of them exist (any k curves give a
+    // valid threshold; shorter ones give it sooner)
+    std::vector<int64_t> lens(ndb);
+    for (int64_t c = 0; c < ndb; ++c) lens[c] = db_off[c + 1] - db_off[c];
+    std::vector<int64_t> tmp(lens);
+    std::nth_element(tmp.begin(), tmp.begin() + ndb / 2, tmp.end());
+    const int64_t cap = 4 * tmp[ndb / 2];
+    auto mid = std::partition(idx.begin(), idx.end(), [&](int32_t c) { return lens[c] <= cap; });
+    if (mid - idx.begin() >= s1) std::nth_element(idx.begin(), idx.begin() + s1, mid, by_bound);
+    else std::nth_element(idx.begin(), idx.begin() + s1, idx.end(), by_bound);
+  }
   if ((rc = stage(0, s1, std::numeric_limits<float>::infinity()))) return rc;
   for (int64_t i = 0; i < s1; ++i) pool.emplace_back(vals[idx[i]], idx[i]);
   std::sort(pool.begin(), pool.end());
   const float tau2 = pool[kk - 1].first;
-  int64_t s2 = s1;
-  while (s2 < ndb && lb[idx[s2]] <= tau2) ++s2;
+  const int64_t s2 =
+      std::partition(idx.begin() + s1, idx.end(), [&](int32_t c) { return lb[c] <= tau2; }) - idx.begin();
   if ((rc = stage(s1, s2, tau2))) return rc;
   for (int64_t i = s1; i < s2; ++i)
     if (vals[idx[i]] <= tau2) pool.emplace_back(vals[idx[i]], idx[i]);
