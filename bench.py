@@ -688,7 +688,8 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
     srv.close()
     db.close()
     cells_open = st["cells_per_s"]
-    info = {"rows_per_lane": 8, "waves": st["waves"], "requests_per_launch": st["requests_per_launch"]}
+    info = {"rows_per_lane": "1 to 8, chosen per launch for its queries", "waves": st["waves"],
+            "requests_per_launch": st["requests_per_launch"]}
     return {
         "value": cells_open, "ms_per_step": st["mean_ms"], "dtype": "f32",
         "config": {"workload": "serving: Poisson arrivals, each a query against a resident database of 10,000 "
@@ -704,7 +705,7 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
                     "max_slots": args.slots},
         "roofline": {"bound": "alu", "achieved": sat_cells * imin(2) / 1e12, "peak": PEAK_VALU / 1e12,
                      "unit": "TVALUop/s", "frac": sat_cells * imin(2) / PEAK_VALU, "traffic": None,
-                     "kernel": "ffd::stream_kernel<8, 2, float>", "kernel_ms": None, "launch": info,
+                     "kernel": "ffd::stream_kernel<R, 2, float>", "kernel_ms": None, "launch": info,
                      "basis": "saturation cells/s over the closed-loop burst (host overhead included)"},
         "cpu_baseline": cpu,
     }

@@ -65,7 +65,7 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // maxima with free absolute values, one instruction less; great-circle
 // cells (ops 10, 11) are FP64 squared chords of unit vectors (D = 3), and
 // DTW adds a float square root and arcsine per cell (about 20 instructions).
-double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0) {
+double step_clocks(int R, int D, bool exact, double waves_per_simd, int op) {
   int cell = op >> 1;
   double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell == 2 || cell == 3 ? 1 : 0);
   if (op == 8) per_cell = 2 * D + 5;  // Levenshtein: a compare per coordinate, the flag, a select, 4 ops

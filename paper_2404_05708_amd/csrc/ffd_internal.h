@@ -17,6 +17,8 @@ hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, in
 hipError_t launch_stream_rings(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);
 hipError_t occupancy_stream_plain(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
 hipError_t occupancy_stream_rings(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
+// Float Frechet launches (no rings, not cooperative) with R in {3, 5, 6, 7}.
+hipError_t launch_stream_serve(int R, int D, const KernelArgs &a, int wpb, hipStream_t st);
 #define FFD_DECLARE_OP(n)                                                                                   \
   hipError_t launch_op_##n(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st); \
   hipError_t occupancy_op_##n(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu);
@@ -39,9 +41,15 @@ hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
 // Levenshtein distance (int32 symbols), ops 10 and 11 the Frechet distance
 // and DTW on great-circle cells (FP64 unit vectors, D = 3).  Op 0 is the
 // Frechet kernel on squared cells (with or without LDS rings); every other
-// op has its own kernel family and never uses rings.
+// op has its own kernel family and never uses rings.  R is 1, 2, 4 or 8,
+// or for op 0 with float coordinates, no rings and no cooperative launch
+// also 3, 5, 6 or 7 (the serving shapes).
 inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
                                 int op = 0) {
+  if ((R & (R - 1)) != 0) {
+    if (op != 0 || exact || a.rings || coop) return hipErrorInvalidValue;
+    return launch_stream_serve(R, D, a, wpb, st);
+  }
   switch (op) {
     case 0: return a.rings ? launch_stream_rings(exact, R, D, a, wpb, coop, st)
                            : launch_stream_plain(exact, R, D, a, wpb, coop, st);
@@ -156,6 +164,9 @@ struct Resources {
   int64_t hand_max; // longest LDS hand-off row
 };
 Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W);
+// Modelled clocks of one stream step of a wave (R rows per lane, D
+// coordinates, kernel op) with `waves_per_simd` waves sharing its SIMD.
+double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0);
 
 int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
                bool exact, Plan &pl);

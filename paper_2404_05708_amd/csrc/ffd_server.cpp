@@ -47,7 +47,8 @@ struct ffd_db {
 
 namespace {
 
-constexpr int kServeR = 8;       // rows per lane of a tick with a query longer than 256 points
+constexpr int kServeR = 8;       // most rows per lane of a tick
+constexpr int kServeRMulti = 3;  // fewest rows per lane of a tick whose queries span several bands
 constexpr int kServeW = 2;       // LDS share of a wave: 1 / (4 kServeW) of a CU
 constexpr int kTicks = 4;        // launches in flight
 
@@ -98,10 +99,10 @@ struct ffd_server {
   ffd_db *db = nullptr;
   int device = 0;
   int dim = 0;
-  // launch shape (capacities are sized for R; a tick whose queries are all
-  // short runs with fewer rows per lane, see query_rows)
+  // launch shape (LDS is sized for R = kServeR; a tick runs the rows per
+  // lane that fit its queries, see query_rows)
   int R = kServeR, nwaves = 0, wpb = 1, lds_per_wave = 0;
-  int lds_rows[9] = {};           // LDS per wave for 1, 2, 4, 8 rows per lane
+  int lds_rows[kServeR + 1] = {}; // LDS per wave for 1 ... kServeR rows per lane
   int64_t hcap = 0;
   // database in chunk order
   std::vector<Chunk> chunks;
@@ -137,7 +138,7 @@ struct ffd_server {
 namespace {
 
 int64_t job_count_bound(const ffd_server &s) {
-  int64_t max_nb = ffd::bands_for(s.max_query, s.R);
+  int64_t max_nb = ffd::bands_for(s.max_query, kServeRMulti);
   // per request: one job per chunk, or for a self-chained chunk a band job
   // and an idle job per band
   return (int64_t)s.chunks.size() + (int64_t)s.long_chunks.size() * (2 * max_nb);
@@ -173,7 +174,7 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
   s.wpb = std::min(rs.wpb, s.nwaves);
   s.hcap = rs.hand_max;
   s.lds_per_wave = lds_bytes(s.R, s.dim, false, s.hcap);
-  for (int r = 1; r <= kServeR; r *= 2) s.lds_rows[r] = lds_bytes(r, s.dim, false, s.hcap);
+  for (int r = 1; r <= kServeR; ++r) s.lds_rows[r] = lds_bytes(r, s.dim, false, s.hcap);
   s.max_query = max_query;
   s.kmax = std::max(1, (max_slots + kTicks - 1) / kTicks);
   s.qcap = (int64_t)s.kmax * max_query;
@@ -214,7 +215,7 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
       s.long_sumL += ch.sumL[1];
     }
   }
-  int64_t max_nb = ffd::bands_for(max_query, s.R);
+  int64_t max_nb = ffd::bands_for(max_query, kServeRMulti);
   s.jobs_cap = (size_t)s.kmax * (size_t)job_count_bound(s);
   s.flags_cap = (size_t)s.kmax * s.long_chunks.size() * (size_t)std::max<int64_t>(max_nb - 1, 0);
   s.links_cap = (size_t)s.kmax * (size_t)s.long_sumL;
@@ -276,30 +277,51 @@ Job band_job(int32_t i, const Chunk &ch, int64_t ndb) {
   return jb;
 }
 
-// Rows per lane for a query of n points: the smallest R whose one band
-// (64 R rows) holds it, up to kServeR.  A band's rows past the query's end
-// are computed and dropped, so a short query in a 512-row band wastes most
-// of it; ticks group queries of one class.
-int query_rows(int64_t n) {
-  int R = 1;
-  while (R < kServeR && n > (int64_t)ffd::kWave * R) R *= 2;
-  return R;
+// Modelled cost of a query of n points at R rows per lane: its bands times
+// the clocks of a stream step (the database side is the same for every R),
+// or +inf where R is not allowed (several bands below kServeRMulti rows per
+// lane: the tick's job and flag capacities are sized for that).
+double query_cost(const ffd_server &s, int64_t n, int R) {
+  int64_t nb = ffd::bands_for(n, R);
+  if (nb > 1 && R < kServeRMulti) return HUGE_VAL;
+  return (double)nb * step_clocks(R, s.dim, false, kServeW);
 }
+
+// Rows per lane for a query of n points: the R in 1 ... kServeR of least
+// modelled cost.  A band's rows past the query's end are computed and
+// dropped (a 300-point query uses 59 % of a 512-row band, 94 % of a 320-row
+// one), while fewer rows per lane cost more clocks per row; ticks group
+// queries that suit one R.
+int query_rows(const ffd_server &s, int64_t n) {
+  int best = kServeR;
+  double bc = query_cost(s, n, kServeR);
+  for (int R = kServeR - 1; R >= 1; --R) {
+    double c = query_cost(s, n, R);
+    if (c < bc) best = R, bc = c;
+  }
+  return best;
+}
+
+// A query joins a tick of Rt rows per lane when that costs at most this
+// factor more than its own best R.
+constexpr double kServeSlack = 1.10;
 
 // Admit queued requests into tick t and launch it.  Called with the lock held.
 int launch_tick(ffd_server &s, Tick &t) {
   const TickLayout &L = s.lay;
   const int64_t ndb = s.db->ndb;
   // requests: the oldest one, then, from the next few in arrival order,
-  // those with the same metric and rows-per-lane class, within the tick's
-  // capacity (no request is passed over by more than 4 kmax later ones)
+  // those with the same metric that suit its rows per lane, within the
+  // tick's capacity (no request is passed over by more than 4 kmax later
+  // ones)
   int32_t metric = s.pending.front()->metric;
-  const int Rt = query_rows(s.pending.front()->n);
+  const int Rt = query_rows(s, s.pending.front()->n);
   int64_t pts = 0;
   const size_t window = (size_t)4 * s.kmax;
   for (size_t i = 0; i < s.pending.size() && i < window && (int)t.reqs.size() < s.kmax;) {
     Request *r = s.pending[i];
-    if (r->metric != metric || query_rows(r->n) != Rt || pts + r->n > s.qcap) {
+    if (r->metric != metric || pts + r->n > s.qcap ||
+        query_cost(s, r->n, Rt) > kServeSlack * query_cost(s, r->n, query_rows(s, r->n))) {
       ++i;
       continue;
     }

@@ -93,6 +93,31 @@ def test_alone_equals_mix_equals_cross(served):
         assert np.all(np.abs(got - want[r]) <= TOL * np.abs(want[r]))
 
 
+def test_rows_per_lane_shapes(served):
+    """Query lengths for which the server picks each of 1 ... 8 rows per
+    lane (including 3, 5, 6 and 7, and those over several bands): alone, in
+    a mix, against ffd_cross bit for bit and the oracle within 2e-6."""
+    ffd, ctx, DB, dbo, DBd, srv = served
+    rng = np.random.default_rng(55)
+    lens = [40, 100, 150, 220, 300, 360, 420, 480, 600, 700, 1200, 2600]
+    qs = [workloads.walk(rng, L, 2) for L in lens]
+    say(f"case: serving shapes, lengths {lens}")
+    alone = [srv.wait(srv.submit(q)).copy() for q in qs]
+    tickets = [srv.submit(q) for q in qs]
+    mix = [srv.wait(t).copy() for t in tickets]
+    Qs, qo = workloads.concat(qs)
+    cross = ctx.cross(torch.from_numpy(Qs).to("cuda:0"), qo, DBd, dbo).cpu().numpy()
+    for i in range(len(qs)):
+        np.testing.assert_array_equal(alone[i], mix[i])
+        np.testing.assert_array_equal(alone[i], cross[i])
+    pick = [lens.index(L) for L in (150, 300, 600, 1200)]
+    sq, so = workloads.concat([qs[i] for i in pick])
+    want = oracle.dfd_cross(sq, so, DB, dbo, oracle.EUCLIDEAN, nthreads=8)
+    for r, i in enumerate(pick):
+        got = alone[i].astype(np.float64)
+        assert np.all(np.abs(got - want[r]) <= TOL * np.abs(want[r])), lens[i]
+
+
 def test_metrics_and_stats(served):
     ffd, ctx, DB, dbo, DBd, srv = served
     q = queries()[3]
