@@ -689,7 +689,8 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
     db.close()
     cells_open = st["cells_per_s"]
     info = {"rows_per_lane": "1 to 8, chosen per launch for its queries", "waves": st["waves"],
-            "requests_per_launch": st["requests_per_launch"]}
+            "requests_per_launch": st["requests_per_launch"],
+            "open_loop_launches_by_rows_per_lane": dict(zip(range(1, 9), st["launches_by_rows"]))}
     return {
         "value": cells_open, "ms_per_step": st["mean_ms"], "dtype": "f32",
         "config": {"workload": "serving: Poisson arrivals, each a query against a resident database of 10,000 "

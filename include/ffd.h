@@ -472,6 +472,7 @@ typedef struct ffd_server_stats {
   double qps;           /* completed requests per second, first submit to last result */
   double cells_per_s;   /* DP cells of completed requests per second, same span */
   int32_t requests_per_launch, waves;
+  int64_t launches_by_rows[8];  /* launches run with r + 1 rows per lane (r = 0 ... 7) */
 } ffd_server_stats;
 
 /* Statistics since creation or the last reset.  Thread-safe. */

@@ -131,6 +131,7 @@ struct ffd_server {
   // statistics
   std::vector<double> lat;
   int64_t submitted = 0, completed = 0, deferred = 0, failed = 0;
+  int64_t launches_by_rows[kServeR] = {};
   double cells = 0, t_first = 0, t_last = 0;
   std::string last_error;
 };
@@ -414,6 +415,7 @@ int launch_tick(ffd_server &s, Tick &t) {
   a.err = reinterpret_cast<uint64_t *>(t.dev + L.err);
   e = ffd::launch_stream(false, Rt, s.dim, a, s.wpb, false, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
+  s.launches_by_rows[Rt - 1]++;
   e = hipMemcpyAsync(t.pin_out, t.dev + L.out, (size_t)k * ndb * sizeof(float), hipMemcpyDeviceToHost, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
   e = hipMemcpyAsync(t.pin_err, t.dev + L.err, sizeof(uint64_t), hipMemcpyDeviceToHost, t.stream);
@@ -700,6 +702,7 @@ int ffd_server_get_stats(ffd_server *s, ffd_server_stats *out) {
   }
   out->requests_per_launch = s->kmax;
   out->waves = s->nwaves;
+  for (int r = 0; r < kServeR; ++r) out->launches_by_rows[r] = s->launches_by_rows[r];
   return FFD_OK;
 }
 
@@ -710,6 +713,7 @@ int ffd_server_reset_stats(ffd_server *s) {
   s->submitted = s->completed = s->deferred = s->failed = 0;
   s->cells = 0;
   s->t_first = s->t_last = 0;
+  for (int64_t &c : s->launches_by_rows) c = 0;
   return FFD_OK;
 }
 

@@ -97,10 +97,13 @@ class ServerStats(ctypes.Structure):
                 ("deferred", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("qps", ctypes.c_double), ("cells_per_s", ctypes.c_double),
-                ("requests_per_launch", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("requests_per_launch", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("launches_by_rows", ctypes.c_int64 * 8)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["launches_by_rows"] = list(d["launches_by_rows"])
+        return d
 
 
 class FFDError(RuntimeError):

@@ -102,7 +102,11 @@ def test_rows_per_lane_shapes(served):
     lens = [40, 100, 150, 220, 300, 360, 420, 480, 600, 700, 1200, 2600]
     qs = [workloads.walk(rng, L, 2) for L in lens]
     say(f"case: serving shapes, lengths {lens}")
+    srv.reset_stats()
     alone = [srv.wait(srv.submit(q)).copy() for q in qs]
+    by_rows = srv.stats()["launches_by_rows"]
+    say(f"launches by rows per lane: {by_rows}")
+    assert sum(by_rows) == len(qs) and all(by_rows[r - 1] > 0 for r in (3, 5, 6, 7)), by_rows
     tickets = [srv.submit(q) for q in qs]
     mix = [srv.wait(t).copy() for t in tickets]
     Qs, qo = workloads.concat(qs)
