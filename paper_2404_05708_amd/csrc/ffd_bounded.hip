@@ -69,6 +69,23 @@ struct Bounded {
   // first point address every column.)
   __device__ __forceinline__ void load_group(int32_t t0, const float *qb, int32_t m, bool above,
                                              const float *hin, float (&q)[kGroupB][D], float (&h)[kGroupB]) {
+    if (t0 >= kWaveB - 1 && t0 + kGroupB <= m) {
+      // every lane's 16 columns lie inside the curve: no separators and no
+      // clamping, one base address and immediate offsets
+      const float *qc = qb + (t0 - lane) * D;
+#pragma unroll
+      for (int u = 0; u < kGroupB; ++u)
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) q[u][k2] = qc[u * D + k2];
+      if (above) {
+#pragma unroll
+        for (int u = 0; u < kGroupB; ++u) h[u] = load_l2(hin + t0 + u);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kGroupB; ++u) h[u] = __builtin_huge_valf();
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < kGroupB; ++u) {
       int32_t j = t0 + u - lane;
@@ -153,7 +170,6 @@ struct Bounded {
 #pragma unroll
         for (int u = 0; u < kGroupB; ++u) {
           const int32_t t = t0 + u;
-          const bool sep = t - lane < 0;  // columns before the first
           float up = shift_in(h[u], Mp[R - 1]);
           float above_v = up, diag = upPrev;
 #pragma unroll
@@ -172,12 +188,22 @@ struct Bounded {
           }
           upPrev = up;
           hb[u] = Mp[R - 1];
-          if (store) bmin = __builtin_fminf(bmin, sep ? inf : Mp[R - 1]);
           if (last_band && t == m - 1 + ln) {
             float sel = Mp[0];
 #pragma unroll
             for (int r = 1; r < R; ++r) sel = rn == r ? Mp[r] : sel;
             res = lane == ln ? sel : res;
+          }
+        }
+        if (store) {
+          // this band's bottom row so far (lane 63's value is the one used;
+          // columns before the first are not cells)
+          if (t0 >= kWaveB - 1) {
+#pragma unroll
+            for (int u = 0; u < kGroupB; u += 2) bmin = __builtin_fminf(bmin, __builtin_fminf(hb[u], hb[u + 1]));
+          } else {
+#pragma unroll
+            for (int u = 0; u < kGroupB; ++u) bmin = __builtin_fminf(bmin, t0 + u - lane < 0 ? inf : hb[u]);
           }
         }
         if (store && lane == kWaveB - 1) {
