@@ -1087,6 +1087,7 @@ void ffd_destroy(ffd_ctx *ctx) {
   if (ctx->scratch) hipFree(ctx->scratch);
   if (ctx->search) hipFree(ctx->search);
   if (ctx->search_done) hipEventDestroy(ctx->search_done);
+  if (ctx->search_host) hipHostFree(ctx->search_host);
   delete ctx;
 }
 

@@ -140,6 +140,8 @@ struct ffd_ctx {
   size_t search_bytes = 0;
   hipEvent_t search_done = nullptr;  // end of the last search launch
   bool search_used = false;
+  void *search_host = nullptr;  // pinned host staging of the k-nearest search (owned)
+  size_t search_host_bytes = 0;
   ffd_search_info last_search{};
   ffd_launch_info last{};
   uint64_t *last_err = nullptr; // device error word of the last launch (workspace)

@@ -98,6 +98,24 @@ int search_scratch(ffd_ctx *ctx, size_t bytes, hipStream_t st) {
   return FFD_OK;
 }
 
+// Pinned host staging of the k-nearest search, grown on demand (copies
+// from and to pageable memory go through the runtime's own staging and
+// cost more per query).  Every search call ends with a stream
+// synchronisation, so no copy from an earlier call is pending when it is
+// reused or replaced.
+int search_host(ffd_ctx *ctx, size_t bytes) {
+  if (ctx->search_host_bytes >= bytes) return FFD_OK;
+  if (ctx->search_host) {
+    hipHostFree(ctx->search_host);
+    ctx->search_host = nullptr;
+    ctx->search_host_bytes = 0;
+  }
+  hipError_t e = hipHostMalloc(&ctx->search_host, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipHostMalloc (search staging)");
+  ctx->search_host_bytes = bytes;
+  return FFD_OK;
+}
+
 // Waves of a launch, in whole workgroups of four: at most one per pair,
 // and between one and two per SIMD -- as many as keep the average wave's
 // steps (total / waves) above the longest pair's, since one wave sweeps a
@@ -232,14 +250,24 @@ int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int6
   Layout L = layout(1, ndb, ndb, ndb, ndb, nwaves, row_cap);
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
   char *base = static_cast<char *>(ctx->search);
-  const int64_t qoff[2] = {0, n};
-  hipError_t e = hipMemcpyAsync(base + L.off0, qoff, sizeof qoff, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(base + L.off1, db_off, (size_t)(ndb + 1) * 8, hipMemcpyHostToDevice, st);
+  // pinned staging: both offset arrays, the bounds, the results, the order
+  const size_t h_off = 0, h_lb = al256((size_t)(ndb + 3) * 8), h_vals = h_lb + al256((size_t)ndb * 4),
+               h_order = h_vals + al256((size_t)ndb * 4), h_total = h_order + al256((size_t)ndb * 4);
+  if ((rc = search_host(ctx, h_total))) return rc;
+  char *hb = static_cast<char *>(ctx->search_host);
+  int64_t *hoff = reinterpret_cast<int64_t *>(hb + h_off);
+  float *lb = reinterpret_cast<float *>(hb + h_lb);
+  float *vals = reinterpret_cast<float *>(hb + h_vals);
+  int32_t *horder = reinterpret_cast<int32_t *>(hb + h_order);
+  hoff[0] = 0;
+  hoff[1] = n;
+  memcpy(hoff + 2, db_off, (size_t)(ndb + 1) * 8);
+  hipError_t e = hipMemcpyAsync(base + L.off0, hoff, 2 * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + L.off1, hoff + 2, (size_t)(ndb + 1) * 8, hipMemcpyHostToDevice, st);
   float *lb_dev = reinterpret_cast<float *>(base + L.lb);
   if (e == hipSuccess)
     e = ffd::launch_endpoint_bound(dim, q, n, DB, reinterpret_cast<const int64_t *>(base + L.off1), ndb, lb_dev, st);
-  std::vector<float> lb(ndb), vals(ndb);
-  if (e == hipSuccess) e = hipMemcpyAsync(lb.data(), lb_dev, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(lb, lb_dev, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(ctx, e, "search bounds");
   // the curves with the smallest bounds first (ties by index); the rest is
@@ -265,11 +293,12 @@ int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int6
     if (hi <= lo) return FFD_OK;
     a.npairs = hi - lo;
     a.eps2 = eps2;
-    hipError_t err = hipMemcpyAsync(base + L.order, idx.data() + lo, (size_t)(hi - lo) * 4, hipMemcpyHostToDevice, st);
+    memcpy(horder, idx.data() + lo, (size_t)(hi - lo) * 4);
+    hipError_t err = hipMemcpyAsync(base + L.order, horder, (size_t)(hi - lo) * 4, hipMemcpyHostToDevice, st);
     if (err != hipSuccess) return hip_fail(ctx, err, "search upload");
     int r = launch(ctx, a, R, dim, search_waves(ctx, hi - lo), st);
     if (r) return r;
-    err = hipMemcpyAsync(vals.data(), a.out, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+    err = hipMemcpyAsync(vals, a.out, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess) err = hipStreamSynchronize(st);
     if (err != hipSuccess) return hip_fail(ctx, err, "search results");
     return FFD_OK;
