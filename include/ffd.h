@@ -364,13 +364,16 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
  * (i, j), of the largest cell on the path, so delta is at least the smallest
  * M over any set of cells that every full path must cross).  A wavefront
  * sweeps one pair at a time and, every 16 columns, tests such a set -- its
- * current anti-diagonal staircase, the cells just above it, and the rest of
- * the band above -- against a threshold; once every cell of the set
- * exceeds it the pair is dropped.  Float32 coordinates, FFD_EUCLIDEAN or
+ * current anti-diagonal staircase, the cells just above it, the rest of the
+ * band above and, when bands follow, the band's own bottom row so far --
+ * against a threshold; once every cell of the set exceeds it the pair is
+ * dropped.  Float32 coordinates, FFD_EUCLIDEAN or
  * FFD_SQEUCLIDEAN (other metrics: FFD_E_UNSUPPORTED); the values that are
  * kept have the same bits as ffd_batch's.  The calls use device scratch
- * that the context allocates on first need and keeps until ffd_destroy;
- * they cannot be recorded into a graph (FFD_E_UNSUPPORTED). */
+ * (and ffd_knn pinned host staging of about 20 bytes per database curve)
+ * that the context allocates on first need, grows when a call needs more
+ * and keeps until ffd_destroy; they cannot be recorded into a graph
+ * (FFD_E_UNSUPPORTED). */
 
 /* Decider: out[k] = delta(P_k, Q_k) when it is <= eps (the same value as
  * ffd_batch), else +inf, so that out[k] <= eps answers "is delta <= eps?".
