@@ -103,6 +103,7 @@ struct ffd_server {
   // lane that fit its queries, see query_rows)
   int R = kServeR, nwaves = 0, wpb = 1, lds_per_wave = 0;
   int lds_rows[kServeR + 1] = {}; // LDS per wave for 1 ... kServeR rows per lane
+  int lds_rows1[kServeR + 1] = {};  // the same without a hand-off row (ticks of single-band queries)
   int64_t hcap = 0;
   // database in chunk order
   std::vector<Chunk> chunks;
@@ -175,7 +176,10 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
   s.wpb = std::min(rs.wpb, s.nwaves);
   s.hcap = rs.hand_max;
   s.lds_per_wave = lds_bytes(s.R, s.dim, false, s.hcap);
-  for (int r = 1; r <= kServeR; ++r) s.lds_rows[r] = lds_bytes(r, s.dim, false, s.hcap);
+  for (int r = 1; r <= kServeR; ++r) {
+    s.lds_rows[r] = lds_bytes(r, s.dim, false, s.hcap);
+    s.lds_rows1[r] = lds_bytes(r, s.dim, false, 0);
+  }
   s.max_query = max_query;
   s.kmax = std::max(1, (max_slots + kTicks - 1) / kTicks);
   s.qcap = (int64_t)s.kmax * max_query;
@@ -347,6 +351,8 @@ int launch_tick(ffd_server &s, Tick &t) {
   size_t nj = 0;
   int32_t nflags = 0;
   int64_t nlinks = 0, max_steps = 0;
+  bool multi = false;  // some query spans several bands
+  for (int i = 0; i < k; ++i) multi = multi || ffd::bands_for(t.reqs[i]->n, Rt) > 1;
   for (int w = 0; w < s.nwaves; ++w) {
     hwj[w] = (int32_t)nj;
     const Chunk &ch = s.chunks[w];
@@ -406,8 +412,12 @@ int launch_tick(ffd_server &s, Tick &t) {
   a.out = t.dev + L.out;
   a.nwaves = s.nwaves;
   a.metric = metric;
-  a.hcap = (int32_t)s.hcap;
-  a.lds_per_wave = s.lds_rows[Rt];
+  // a tick of single-band queries hands no row on inside a wave (its
+  // tasks read the ghost row and write to the sink), so its waves take no
+  // hand-off row in LDS and more of them fit a CU, also from the other
+  // launches in flight
+  a.hcap = multi ? (int32_t)s.hcap : 0;
+  a.lds_per_wave = multi ? s.lds_rows[Rt] : s.lds_rows1[Rt];
   a.max_steps = (int32_t)(max_steps + 4 * ffd::kRing);
   a.epoch = t.epoch;
   a.links = t.dev + L.links;
