@@ -127,7 +127,35 @@ def golden():
 
 
 def cpu_cores():
-    return min(16, len(os.sched_getaffinity(0)))
+    """Threads the oracle runs on: every core this process may use, within
+    the host's CPU share for one GPU where the environment states it
+    (OMP_NUM_THREADS)."""
+    n = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(share)) if share.isdigit() and int(share) > 0 else n
+
+
+def cpu_host():
+    """The host the CPU baseline ran on: nproc and the model name."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": model}
 
 
 # ------------------------------------------------------------------ workloads
@@ -781,6 +809,8 @@ def main():
     for k in ("config", "parity", "autotune", "serving", "search", "roofline", "plain", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
+    if line.get("cpu_baseline"):
+        line["cpu_baseline"].update(cpu_host())
     print(json.dumps(line), flush=True)
     ctx.close()
 

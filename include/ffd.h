@@ -22,8 +22,18 @@
  *    the context's GPU); offset arrays are HOST pointers (the host plans the
  *    work from them).  The caller owns all of them; the library never frees
  *    or keeps a caller pointer beyond the completion of the call's work on
- *    `stream`, except an ffd_db, which refers to its database until
- *    ffd_db_destroy.
+ *    `stream`, except the scratch registered with ffd_set_scratch (kept
+ *    until it is replaced or the context is destroyed) and an ffd_db, which
+ *    refers to its database until ffd_db_destroy.  The library allocates no
+ *    device memory: device scratch comes from the caller (workspaces,
+ *    ffd_set_scratch, the serving arena).
+ *  - Workspaces and the scratch: a call writes its plan (job table,
+ *    offsets, cleared progress flags) into the workspace before its kernel,
+ *    on `stream`, every time it runs outside graph capture, so nothing the
+ *    memory held before the call is trusted.  Successive calls of one
+ *    context that use the same workspace, or the scratch, on different
+ *    streams are ordered on the device (the later stream waits for the
+ *    earlier call's work).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
  *    asynchronous: results are valid once the stream has completed.
  *  - Return value: FFD_OK or a negative FFD_E_* status.  All argument checks
@@ -40,16 +50,18 @@
  *    pair and correctly rounded).  Int32 results are exact.
  *  - A context may be used by one host thread at a time.
  *  - Graph capture: ffd_distance, ffd_batch and ffd_cross (and their int32
- *    forms) may be recorded into a hipGraph by stream capture once the same
- *    call (same offsets, dimension, type, tuning and workspace) has run
- *    outside the capture: the plan is then already in the workspace, or in
- *    the context's scratch for a single long pair, and the recorded work is
- *    a small kernel that clears the launch's progress flags followed by the
- *    distance kernel.  Otherwise the call returns FFD_E_UNSUPPORTED and
- *    records nothing.  The workspace then belongs to the graph: a later call
- *    outside it with other offsets on the same workspace replaces the plan
- *    the replays read.  Replays of one graph must not overlap each other.
- *    The autotuner and the serving calls cannot be captured.
+ *    forms) may be recorded into a hipGraph by stream capture when the
+ *    context's last call outside the capture that used this workspace (or,
+ *    for a single long pair, the registered scratch) was the same call (same
+ *    offsets, dimension, type, tuning and memory): the plan is then in that
+ *    memory, and the recorded work is a small kernel that clears the
+ *    launch's progress flags followed by the distance kernel.  Otherwise the
+ *    call returns FFD_E_UNSUPPORTED and records nothing.  The memory then
+ *    belongs to the graph: the caller promises that nothing writes to it
+ *    between replays (a later eager call with other offsets on the same
+ *    workspace replaces the plan the replays read).  Replays of one graph
+ *    must not overlap each other or other work on the same memory.  The
+ *    autotuner, the search and the serving calls cannot be captured.
  */
 #ifndef FFD_H
 #define FFD_H
@@ -94,9 +106,12 @@ extern "C" {
 /* Largest supported dimension D. */
 #define FFD_MAX_DIM 4
 
-/* Operation codes for ffd_workspace_size. */
+/* Operation codes for ffd_workspace_size (and ffd_plan_describe). */
 #define FFD_OP_BATCH 0
 #define FFD_OP_CROSS 1
+#define FFD_OP_PAIR 2
+#define FFD_OP_DECIDE 3
+#define FFD_OP_KNN 4
 
 typedef struct ffd_ctx ffd_ctx;
 
@@ -126,11 +141,13 @@ const char *ffd_version(void);
  *   p   [n * dim] float32, device;  q [m * dim] float32, device;
  *   out [1] float32, device: delta_dF(p, q) under `metric`.
  * A pair short enough for one wavefront needs no device memory; a long pair
- * is split into bands over many wavefronts, using device scratch memory that
- * the context allocates on first need and keeps until ffd_destroy.
+ * is split into bands over many wavefronts, whose plan and boundary rows go
+ * into the scratch registered with ffd_set_scratch (its size from
+ * ffd_workspace_size with FFD_OP_PAIR; 0 for a pair that needs none).
  * Errors: FFD_E_INVALID for NULL pointers, n < 1, m < 1, dim < 1, an
  * unknown metric or FFD_HAVERSINE with dim != 2; FFD_E_UNSUPPORTED for
- * dim > FFD_MAX_DIM. */
+ * dim > FFD_MAX_DIM; FFD_E_NOMEM for a long pair without enough registered
+ * scratch. */
 int ffd_distance(ffd_ctx *ctx, const float *p, int64_t n, const float *q, int64_t m,
                  int32_t dim, int32_t metric, float *out, void *stream);
 
@@ -234,13 +251,28 @@ int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off,
                           const int32_t *DB, const int64_t *db_off, int64_t ndb, int32_t dim,
                           int64_t *out, void *workspace, size_t ws_bytes, void *stream);
 
-/* Device workspace needed by ffd_batch (op = FFD_OP_BATCH: a_off = p_off,
- * na = npairs, b_off = q_off, nb = npairs) or ffd_cross (op = FFD_OP_CROSS:
- * a_off = q_off, na = nq, b_off = db_off, nb = ndb), and by their int32 and
- * DTW and Levenshtein forms: the size covers all of them.  Writes *bytes.
+/* Device memory needed by a call.  Workspaces: ffd_batch (op =
+ * FFD_OP_BATCH: a_off = p_off, na = npairs, b_off = q_off, nb = npairs) or
+ * ffd_cross (op = FFD_OP_CROSS: a_off = q_off, na = nq, b_off = db_off, nb =
+ * ndb), and their int32, DTW and Levenshtein forms: the size covers all of
+ * them.  Scratch (ffd_set_scratch): ffd_distance of a pair (op =
+ * FFD_OP_PAIR: a_off = {0, n}, b_off = {0, m}, na = nb = 1; every form and
+ * metric), ffd_decide_batch (op = FFD_OP_DECIDE, arguments as FFD_OP_BATCH)
+ * and ffd_knn (op = FFD_OP_KNN: a_off = {0, n}, na = 1, b_off = db_off, nb =
+ * ndb).  Writes *bytes (0: the call needs none).
  * Errors: FFD_E_INVALID for a bad op, NULL or bad offsets. */
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                        const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);
+
+/* Register device memory of `bytes` bytes (caller-owned; NULL and 0
+ * unregister) as the context's scratch for ffd_distance of long pairs and
+ * for the search calls (ffd_decide_batch, ffd_knn).  The context keeps the
+ * pointer until it is replaced or the context is destroyed; the caller
+ * keeps the memory alive that long and, before freeing memory it replaces,
+ * waits for the calls that used it.  Calls that need more than the
+ * registered size return FFD_E_NOMEM and launch nothing.
+ * Errors: FFD_E_INVALID (NULL ctx, NULL scratch with bytes > 0). */
+int ffd_set_scratch(ffd_ctx *ctx, void *scratch, size_t bytes);
 
 /* Introspection (tests and tools): the plan that a call would launch.
  *   op: FFD_OP_BATCH (a_off = p_off, b_off = q_off, na = nb = npairs),
@@ -259,7 +291,6 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
  *   at least 80; an idle job (row_sel 2) lasts col_count steps.
  * Errors: as ffd_batch / ffd_cross / ffd_distance; FFD_E_NOMEM when jobs_cap
  * or the wave_jobs array is too small (the summary is filled first). */
-#define FFD_OP_PAIR 2
 typedef struct ffd_plan_summary {
   int32_t rows_per_lane;   /* R                                              */
   int32_t waves;           /* wavefronts                                     */
@@ -369,11 +400,12 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
  * against a threshold; once every cell of the set exceeds it the pair is
  * dropped.  Float32 coordinates, FFD_EUCLIDEAN or
  * FFD_SQEUCLIDEAN (other metrics: FFD_E_UNSUPPORTED); the values that are
- * kept have the same bits as ffd_batch's.  The calls use device scratch
- * (and ffd_knn pinned host staging of about 20 bytes per database curve)
- * that the context allocates on first need, grows when a call needs more
- * and keeps until ffd_destroy; they cannot be recorded into a graph
- * (FFD_E_UNSUPPORTED). */
+ * kept have the same bits as ffd_batch's.  The calls use the scratch
+ * registered with ffd_set_scratch (sizes from ffd_workspace_size with
+ * FFD_OP_DECIDE or FFD_OP_KNN; FFD_E_NOMEM without it); ffd_knn also uses
+ * pinned host staging of about 20 bytes per database curve that the context
+ * allocates on first need and keeps until ffd_destroy.  They cannot be
+ * recorded into a graph (FFD_E_UNSUPPORTED). */
 
 /* Decider: out[k] = delta(P_k, Q_k) when it is <= eps (the same value as
  * ffd_batch), else +inf, so that out[k] <= eps answers "is delta <= eps?".
@@ -382,7 +414,7 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
  * Asynchronous on `stream`; offsets are HOST arrays, read before return.
  * Errors: FFD_E_INVALID (NULL, bad offsets, NaN eps, unknown metric, dim <
  * 1), FFD_E_UNSUPPORTED (metric, dim > FFD_MAX_DIM, a column curve of 2^31
- * or more values), FFD_E_DEVICE. */
+ * or more values), FFD_E_NOMEM (registered scratch too small), FFD_E_DEVICE. */
 int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
                      int64_t npairs, int32_t dim, int32_t metric, float eps, float *out, void *stream);
 
@@ -400,6 +432,7 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
  * offsets).  Synchronises the stream.
  * Errors: FFD_E_INVALID (NULL, k < 1, n < 1, ndb < 1, bad offsets, unknown
  * metric), FFD_E_UNSUPPORTED (metric, dim, too many or too long curves),
+ * FFD_E_NOMEM (registered scratch too small),
  * FFD_E_DEVICE. */
 int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
             int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream);

@@ -86,11 +86,13 @@ double step_clocks(int R, int D, bool exact, double waves_per_simd, int op) {
 // own position.
 constexpr double kLinkLag = 5.0 * ffd::kFill;
 
-uint64_t fnv(uint64_t h, const void *p, size_t n) {
-  const unsigned char *b = (const unsigned char *)p;
+// Hash of 64-bit words (a multiply-xorshift mix per word): only used to
+// tell requests apart quickly; equality is always decided on the words.
+uint64_t mix_words(uint64_t h, const int64_t *w, size_t n) {
   for (size_t i = 0; i < n; ++i) {
-    h ^= b[i];
-    h *= 1099511628211ull;
+    h ^= (uint64_t)w[i] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    h *= 0xFF51AFD7ED558CCDull;
+    h ^= h >> 33;
   }
   return h;
 }
@@ -660,14 +662,16 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
   return w;
 }
 
+// The staging buffer for plan uploads, at least `bytes` long.  Replacing
+// its contents first waits until the last upload has read it.
 int ensure_pinned(ffd_ctx *ctx, size_t bytes) {
-  if (ctx->pinned_bytes >= bytes) {
-    // the previous upload must have finished reading the staging buffer
-    if (ctx->upload_done) hipEventSynchronize(ctx->upload_done);
-    return FFD_OK;
+  if (ctx->upload_done) {
+    hipError_t e = hipEventSynchronize(ctx->upload_done);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize (plan upload)");
   }
+  ctx->staged_gen = 0;
+  if (ctx->pinned_bytes >= bytes) return FFD_OK;
   if (ctx->pinned) {
-    if (ctx->upload_done) hipEventSynchronize(ctx->upload_done);
     hipHostFree(ctx->pinned);
     ctx->pinned = nullptr;
     ctx->pinned_bytes = 0;
@@ -686,13 +690,38 @@ hipError_t capturing_on(hipStream_t st, bool &capturing) {
   return e;
 }
 
-// Run a planned launch: upload the plan (jobs, job ranges, offsets, zeroed
-// flags and error word) into the workspace unless the same plan is already
-// there, then launch.  Flags carry the launch epoch, so a reused plan needs
-// no clearing.
-int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const int64_t *off0, int64_t n0,
+int use_begin(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool capturing) {
+  if (capturing || !u.pending || u.ptr != ptr || u.stream == st) return FFD_OK;
+  hipError_t e = hipStreamWaitEvent(st, u.done, 0);
+  return e == hipSuccess ? FFD_OK : hip_fail(ctx, e, "hipStreamWaitEvent");
+}
+
+int use_end(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool capturing) {
+  if (capturing) return FFD_OK;
+  if (!u.done) {
+    hipError_t e = hipEventCreateWithFlags(&u.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+  }
+  hipError_t e = hipEventRecord(u.done, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+  u.ptr = ptr;
+  u.stream = st;
+  u.pending = true;
+  return FFD_OK;
+}
+
+// Run a planned launch.  Outside graph capture the plan (jobs, job ranges,
+// offsets, zeroed flags and error word) is uploaded into the workspace on
+// every call: the library never trusts what device memory it does not own
+// held between calls.  The staging copy in pinned host memory is rebuilt
+// only when the plan changes.  A launch recorded into a graph cannot
+// upload (each replay would read the staging buffer as it is then); it
+// requires the plan that the context's last eager upload put into this
+// workspace, and the recorded work clears the flags and the error word
+// first, since every replay reuses the recorded epoch.
+int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const int64_t *off0, int64_t n0,
              const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
-             size_t ws_bytes, hipStream_t st) {
+             size_t ws_bytes, hipStream_t st, UseOrder &use) {
   WsLayout wl = ws_layout(pl, n0, n1, exact);
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings, ctx->measure),
                               exact ? 1 : 0, D, pl.max_steps};
@@ -705,32 +734,34 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   e = capturing_on(st, capturing);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
   unsigned char *w = (unsigned char *)ws;
-  if (!(ctx->plan_ws == ws && ctx->plan_ws_key == key)) {
-    if (capturing)
-      return fail(ctx, FFD_E_UNSUPPORTED,
-                  "a launch recorded into a graph needs its plan in the workspace: make the same call once "
-                  "outside the capture first");
-    int rc = ensure_pinned(ctx, wl.links);
-    if (rc) return rc;
-    unsigned char *h = (unsigned char *)ctx->pinned;
-    memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
-    memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
-    memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
-    memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
-    memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
-    e = hipMemcpyAsync(w, h, wl.links, hipMemcpyHostToDevice, st);
+  int rc = use_begin(ctx, use, ws, st, capturing);
+  if (rc) return rc;
+  if (!capturing) {
+    if (ctx->staged_gen != gen) {
+      if ((rc = ensure_pinned(ctx, wl.links))) return rc;
+      unsigned char *h = (unsigned char *)ctx->pinned;
+      memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
+      memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
+      memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
+      memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
+      memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
+      ctx->staged_gen = gen;
+    }
+    e = hipMemcpyAsync(w, ctx->pinned, wl.links, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync (plan)");
     if (!ctx->upload_done) {
       e = hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming);
       if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
     }
-    hipEventRecord(ctx->upload_done, st);
+    e = hipEventRecord(ctx->upload_done, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
     ctx->plan_ws = ws;
-    ctx->plan_ws_key = key;
-  }
-  if (capturing) {
-    // every replay runs with the epoch recorded here: clear the flags and
-    // the error word at the start of each replay instead
+    ctx->plan_ws_gen = gen;
+  } else {
+    if (!(ctx->plan_ws == ws && ctx->plan_ws_gen == gen))
+      return fail(ctx, FFD_E_UNSUPPORTED,
+                  "a launch recorded into a graph needs its plan in the workspace: make the same call on the same "
+                  "workspace outside the capture just before");
     e = ffd::clear_words((uint64_t *)(w + wl.flags), (int64_t)((wl.links - wl.flags) / sizeof(uint64_t)), st);
     if (e != hipSuccess) return hip_fail(ctx, e, "flag clearing launch");
   }
@@ -759,23 +790,49 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t key, const void *X0, const i
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
   ctx->last_stream = st;
-  return FFD_OK;
+  return use_end(ctx, use, ws, st, capturing);
 }
 
-// Key of a request: offsets, op, dim, type and, unless `base`, the tuning
-// and split settings (a plan depends on all of them).
-uint64_t key_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b,
-                int64_t nb, bool base = false) {
-  uint64_t h = 1469598103934665603ull;
-  int hdr[6] = {op, D, exact ? 1 : 0, base ? 0 : ctx->tune_R, base ? 0 : ctx->tune_W, ctx->measure};
+// A request: op, dim, type, measure and, unless `base`, the tuning and
+// split settings (a plan depends on all of them), then both offset arrays.
+struct Req {
+  static constexpr int kHdr = 9;
+  int64_t hdr[kHdr];
+  const int64_t *a, *b;
+  int64_t na, nb;
+};
+
+Req req_of(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb,
+           bool base = false) {
+  Req r;
   float sp = base ? 0.f : ctx->split;
-  h = fnv(h, hdr, sizeof hdr);
-  h = fnv(h, &sp, sizeof sp);
-  h = fnv(h, &na, sizeof na);
-  h = fnv(h, &nb, sizeof nb);
-  h = fnv(h, a, (size_t)(na + 1) * sizeof(int64_t));
-  h = fnv(h, b, (size_t)(nb + 1) * sizeof(int64_t));
-  return h;
+  int32_t spb;
+  memcpy(&spb, &sp, sizeof spb);
+  int64_t h[Req::kHdr] = {op, D, exact ? 1 : 0, base ? 0 : ctx->tune_R, base ? 0 : ctx->tune_W, ctx->measure,
+                          spb, na, nb};
+  memcpy(r.hdr, h, sizeof h);
+  r.a = a;
+  r.b = b;
+  r.na = na;
+  r.nb = nb;
+  return r;
+}
+
+bool req_matches(const ReqKey &k, const Req &r) {
+  const size_t nh = Req::kHdr, na = (size_t)r.na + 1, nb = (size_t)r.nb + 1;
+  if (k.words.size() != nh + na + nb) return false;
+  const int64_t *w = k.words.data();
+  return memcmp(w, r.hdr, nh * 8) == 0 && memcmp(w + nh, r.a, na * 8) == 0 && memcmp(w + nh + na, r.b, nb * 8) == 0;
+}
+
+ReqKey req_key(const Req &r) {
+  ReqKey k;
+  k.words.reserve(Req::kHdr + r.na + r.nb + 2);
+  k.words.insert(k.words.end(), r.hdr, r.hdr + Req::kHdr);
+  k.words.insert(k.words.end(), r.a, r.a + r.na + 1);
+  k.words.insert(k.words.end(), r.b, r.b + r.nb + 1);
+  k.hash = mix_words(1469598103934665603ull, k.words.data(), k.words.size());
+  return k;
 }
 
 constexpr int kOpPair = 100;  // internal plan kind of ffd_distance
@@ -799,11 +856,12 @@ struct TunedScope {
   TunedScope(ffd_ctx *c, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb)
       : ctx(c), R(c->tune_R), W(c->tune_W), split(c->split) {
     if (c->tune_R || c->tune_W || c->split != 0.f || c->tuned.empty()) return;
-    auto it = c->tuned.find(key_of(c, op, D, exact, a, na, b, nb, true));
-    if (it == c->tuned.end()) return;
-    c->tune_R = it->second.rows_per_lane;
-    c->tune_W = it->second.waves_per_simd;
-    c->split = it->second.split;
+    ReqKey k = req_key(req_of(c, op, D, exact, a, na, b, nb, true));
+    auto it = c->tuned.find(k.hash);
+    if (it == c->tuned.end() || it->second.first.words != k.words) return;
+    c->tune_R = it->second.second.rows_per_lane;
+    c->tune_W = it->second.second.waves_per_simd;
+    c->split = it->second.second.split;
     active = true;
   }
   ~TunedScope() {
@@ -816,10 +874,11 @@ struct TunedScope {
 };
 
 int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na, const int64_t *b_off,
-                int64_t nb, int D, bool exact, const Plan **out, uint64_t &key) {
-  key = key_of(ctx, op, D, exact, a_off, na, b_off, nb);
-  if (pc.valid && pc.key == key) {
+                int64_t nb, int D, bool exact, const Plan **out, uint64_t &gen) {
+  Req r = req_of(ctx, op, D, exact, a_off, na, b_off, nb);
+  if (pc.valid && req_matches(pc.key, r)) {
     *out = &pc.plan;
+    gen = pc.gen;
     return FFD_OK;
   }
   Plan pl;
@@ -829,9 +888,11 @@ int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64
   else rc = plan_pair(ctx, a_off[1], b_off[1], D, exact, pl);
   if (rc) return rc;
   pc.plan = std::move(pl);
-  pc.key = key;
+  pc.key = req_key(r);
+  pc.gen = ++ctx->plan_gen;
   pc.valid = true;
   *out = &pc.plan;
+  gen = pc.gen;
   return FFD_OK;
 }
 
@@ -877,29 +938,15 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
     ctx->last_err = nullptr;
     return FFD_OK;
   }
-  // bands split over waves: the plan and the links live in the context's scratch
+  // bands split over waves: the plan and the links live in the scratch the
+  // caller registered with ffd_set_scratch
   WsLayout wl = ws_layout(*pl, 1, 1, exact);
-  if (ctx->scratch_bytes < wl.total) {
-    bool capturing = false;
-    e = capturing_on(st, capturing);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
-    if (capturing)
-      return fail(ctx, FFD_E_UNSUPPORTED,
-                  "a long pair recorded into a graph needs the context's scratch: make the same call once "
-                  "outside the capture first");
-    if (ctx->scratch) {
-      hipDeviceSynchronize();  // launches on any stream may still use it
-      hipFree(ctx->scratch);
-      ctx->scratch = nullptr;
-      ctx->scratch_bytes = 0;
-      ctx->plan_ws = nullptr;
-    }
-    e = hipMalloc(&ctx->scratch, wl.total);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc (scratch for a long pair)");
-    ctx->scratch_bytes = wl.total;
-  }
+  if (ctx->scratch_bytes < wl.total)
+    return fail(ctx, FFD_E_NOMEM,
+                "a pair this long runs on many wavefronts and needs device scratch: register at least "
+                "ffd_workspace_size(FFD_OP_PAIR) bytes with ffd_set_scratch");
   return run_plan(ctx, *pl, key, p, off0, 1, q, off1, 1, dim, exact, metric, out, ctx->scratch,
-                  ctx->scratch_bytes, st);
+                  ctx->scratch_bytes, st, ctx->scratch_use);
 }
 
 int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *Q, const int64_t *q_off,
@@ -918,7 +965,8 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   uint64_t key;
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
   if (rc) return rc;
-  return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st);
+  return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st,
+                  ctx->ws_use);
 }
 
 int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq, const void *DB,
@@ -938,7 +986,8 @@ int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq,
   uint64_t key;
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key);
   if (rc) return rc;
-  return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st);
+  return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st,
+                  ctx->ws_use);
 }
 
 // Time one launch of `call` (already planned and uploaded by a first call)
@@ -979,8 +1028,8 @@ int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t 
   if (capturing) return fail(ctx, FFD_E_UNSUPPORTED, "the autotuner times launches and cannot be captured");
   int R0 = ctx->tune_R, W0 = ctx->tune_W;
   float S0 = ctx->split;
-  uint64_t base = key_of(ctx, op, D, exact, a, na, b, nb, true);
-  ctx->tuned.erase(base);
+  ReqKey base = req_key(req_of(ctx, op, D, exact, a, na, b, nb, true));
+  ctx->tuned.erase(base.hash);
   ffd_tuning best{0, 0, 0.f, -1.f, -1.f, 0};
   ctx->tune_R = ctx->tune_W = 0;
   ctx->split = 0.f;
@@ -1013,7 +1062,7 @@ int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t 
     best.split = 0.f;
     best.ms = best.ms_planner;
   } else {
-    ctx->tuned[base] = best;
+    ctx->tuned[base.hash] = std::make_pair(base, best);
   }
   if (best_out) *best_out = best;
   return FFD_OK;
@@ -1083,12 +1132,24 @@ void ffd_destroy(ffd_ctx *ctx) {
     hipEventDestroy(ctx->upload_done);
   }
   if (ctx->pinned) hipHostFree(ctx->pinned);
-  if (ctx->scratch || ctx->search) hipDeviceSynchronize();
-  if (ctx->scratch) hipFree(ctx->scratch);
-  if (ctx->search) hipFree(ctx->search);
-  if (ctx->search_done) hipEventDestroy(ctx->search_done);
+  for (UseOrder *u : {&ctx->scratch_use, &ctx->ws_use})
+    if (u->done) {
+      hipEventSynchronize(u->done);
+      hipEventDestroy(u->done);
+    }
   if (ctx->search_host) hipHostFree(ctx->search_host);
   delete ctx;
+}
+
+int ffd_set_scratch(ffd_ctx *ctx, void *scratch, size_t bytes) {
+  if (!ctx) return FFD_E_INVALID;
+  if (!scratch && bytes) return fail(ctx, FFD_E_INVALID, "NULL scratch with a nonzero size");
+  if (ctx->plan_ws == ctx->scratch) ctx->plan_ws = nullptr;
+  ctx->scratch = bytes ? scratch : nullptr;
+  ctx->scratch_bytes = bytes ? bytes : 0;
+  ctx->scratch_use.pending = false;  // the caller orders work on the memory it replaces
+  ctx->scratch_use.ptr = ctx->scratch;
+  return FFD_OK;
 }
 
 int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info) {
@@ -1357,16 +1418,19 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off, int64_t nb,
                        int32_t dim, size_t *bytes) {
   if (!ctx || !bytes) return FFD_E_INVALID;
-  if (op != FFD_OP_BATCH && op != FFD_OP_CROSS) return fail(ctx, FFD_E_INVALID, "unknown op");
+  if (op != FFD_OP_BATCH && op != FFD_OP_CROSS && op != FFD_OP_PAIR && op != FFD_OP_DECIDE && op != FFD_OP_KNN)
+    return fail(ctx, FFD_E_INVALID, "unknown op");
   if (dim < 1) return fail(ctx, FFD_E_INVALID, "dim must be >= 1");
   if (dim > FFD_MAX_DIM) return fail(ctx, FFD_E_UNSUPPORTED, "dim exceeds FFD_MAX_DIM");
   if (na < 0 || nb < 0) return fail(ctx, FFD_E_INVALID, "negative count");
-  if (op == FFD_OP_BATCH && na != nb) return fail(ctx, FFD_E_INVALID, "batch needs na == nb");
+  if ((op == FFD_OP_BATCH || op == FFD_OP_PAIR) && na != nb) return fail(ctx, FFD_E_INVALID, "needs na == nb");
+  if (op == FFD_OP_PAIR && na > 1) return fail(ctx, FFD_E_INVALID, "a pair has one curve per side");
   *bytes = 0;
   if (na == 0 || nb == 0) return FFD_OK;
   int rc;
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
+  if (op == FFD_OP_DECIDE || op == FFD_OP_KNN) return search_scratch_size(ctx, op, a_off, na, b_off, nb, dim, bytes);
   // one size for every path: float and int32 coordinates, every measure and
   // ground distance (kernel ops 0, 1, 3, ..., 8, and 10, 11 for 2-D curves)
   size_t worst = 0;
@@ -1376,14 +1440,17 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
       if (ms >= kOpGeo && (ex == 0 || dim != 2)) continue;  // FP64 on (latitude, longitude) only
       MeasureScope scope(ctx, ms);
       const Plan *pl;
-      uint64_t key;
+      uint64_t gen;
       PlanCache tmp;
-      rc = cached_plan(ctx, tmp, op, a_off, na, b_off, nb, ms >= kOpGeo ? 3 : dim, ex == 1, &pl, key);
+      rc = cached_plan(ctx, tmp, op == FFD_OP_PAIR ? kOpPair : op, a_off, na, b_off, nb, ms >= kOpGeo ? 3 : dim,
+                       ex == 1, &pl, gen);
       if (rc == FFD_E_UNSUPPORTED) continue;
       if (rc) return rc;
+      // a single pair on one wavefront needs no device memory
+      if (op == FFD_OP_PAIR && pl->nwaves == 1 && pl->link_elems == 0) continue;
       worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
     }
-  if (worst == 0) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
+  if (worst == 0 && op != FFD_OP_PAIR) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;
   return FFD_OK;
 }

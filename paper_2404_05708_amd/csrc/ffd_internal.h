@@ -106,10 +106,29 @@ struct Plan {
   std::vector<int32_t> wave_jobs;
 };
 
+// A request as the planner sees it: header words (operation, dimension,
+// value type, measure, tuning) and both offset arrays, compared in full
+// (the hash only speeds up mismatches).
+struct ReqKey {
+  uint64_t hash = 0;
+  std::vector<int64_t> words;
+};
+
 struct PlanCache {
-  uint64_t key = 0;
+  ReqKey key;
+  uint64_t gen = 0;            // unique id of the cached (request, plan), never reused by a context
   Plan plan;
   bool valid = false;
+};
+
+// Device memory used by successive calls of a context (the caller's scratch
+// or a workspace): the end of the last use, so that a use on another stream
+// waits for it on the device.
+struct UseOrder {
+  const void *ptr = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool pending = false;
 };
 
 }  // namespace ffdi
@@ -125,21 +144,22 @@ struct ffd_ctx {
   int measure = 0;            // kernel op of the call in progress (measure + 2 * cell, see launch_stream)
   uint32_t epoch = 0;
   std::string last_error;
-  // plan most recently written to a workspace (skip the upload if unchanged)
-  void *plan_ws = nullptr;
-  uint64_t plan_ws_key = 0;
-  void *pinned = nullptr;     // staging buffer for plan uploads
+  uint64_t plan_gen = 0;      // last generation id handed out to a cached plan
+  // plan most recently uploaded to device memory (a recorded launch needs it there)
+  const void *plan_ws = nullptr;
+  uint64_t plan_ws_gen = 0;
+  void *pinned = nullptr;     // host staging buffer for plan uploads (pinned)
   size_t pinned_bytes = 0;
+  uint64_t staged_gen = 0;    // plan whose bytes the staging buffer holds (0: none)
   hipEvent_t upload_done = nullptr;
   ffdi::PlanCache batch_plans, pair_plans;
   // launch shapes chosen by the autotuner, by request (offsets, op, dim, type)
-  std::unordered_map<uint64_t, ffd_tuning> tuned;
-  void *scratch = nullptr;    // device workspace for long single pairs (owned)
+  std::unordered_map<uint64_t, std::pair<ffdi::ReqKey, ffd_tuning>> tuned;
+  // device scratch registered by the caller (ffd_set_scratch): long single
+  // pairs and the search calls; not owned
+  void *scratch = nullptr;
   size_t scratch_bytes = 0;
-  void *search = nullptr;     // device scratch of the decider and the k-nearest search (owned)
-  size_t search_bytes = 0;
-  hipEvent_t search_done = nullptr;  // end of the last search launch
-  bool search_used = false;
+  ffdi::UseOrder scratch_use, ws_use;
   void *search_host = nullptr;  // pinned host staging of the k-nearest search (owned)
   size_t search_host_bytes = 0;
   ffd_search_info last_search{};
@@ -169,6 +189,15 @@ Resources resources(ffd_ctx *ctx, int R, int D, bool exact, int W);
 // Modelled clocks of one stream step of a wave (R rows per lane, D
 // coordinates, kernel op) with `waves_per_simd` waves sharing its SIMD.
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op = 0);
+
+// Make work on `st` that uses `ptr` wait for the previous use of the same
+// memory on another stream (eager calls only: a recorded launch must not
+// overlap other users of that memory), and record the end of this use.
+int use_begin(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool capturing);
+int use_end(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool capturing);
+// Scratch bytes of the search calls (FFD_OP_DECIDE, FFD_OP_KNN; ffd_search.cpp).
+int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off,
+                        int64_t nb, int32_t dim, size_t *bytes);
 
 int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
                bool exact, Plan &pl);

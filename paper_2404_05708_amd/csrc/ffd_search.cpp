@@ -70,32 +70,20 @@ int check_search(ffd_ctx *ctx, int32_t dim, int32_t metric) {
   return FFD_OK;
 }
 
-// The context's search scratch, grown on demand.  Work of an earlier
-// search call on another stream is waited for on the device.
+// The scratch the caller registered (ffd_set_scratch), at least `bytes`
+// long; work of an earlier call that used it on another stream is waited
+// for on the device.
 int search_scratch(ffd_ctx *ctx, size_t bytes, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(st, &cs);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
   if (cs != hipStreamCaptureStatusNone)
     return fail(ctx, FFD_E_UNSUPPORTED, "the search calls cannot be recorded into a graph");
-  if (!ctx->search_done) {
-    e = hipEventCreateWithFlags(&ctx->search_done, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
-  } else if (ctx->search_used) {
-    e = hipStreamWaitEvent(st, ctx->search_done, 0);
-    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
-  }
-  if (ctx->search_bytes >= bytes) return FFD_OK;
-  if (ctx->search) {
-    hipDeviceSynchronize();
-    hipFree(ctx->search);
-    ctx->search = nullptr;
-    ctx->search_bytes = 0;
-  }
-  e = hipMalloc(&ctx->search, bytes);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc (search scratch)");
-  ctx->search_bytes = bytes;
-  return FFD_OK;
+  if (ctx->scratch_bytes < bytes)
+    return fail(ctx, FFD_E_NOMEM,
+                "the search calls need device scratch: register at least ffd_workspace_size(FFD_OP_DECIDE or "
+                "FFD_OP_KNN) bytes with ffd_set_scratch");
+  return use_begin(ctx, ctx->scratch_use, ctx->scratch, st, false);
 }
 
 // Pinned host staging of the k-nearest search, grown on demand (copies
@@ -156,13 +144,69 @@ Layout layout(int64_t n0, int64_t n1, int64_t npairs, int64_t nout, int64_t nlb,
 int launch(ffd_ctx *ctx, ffd::BoundedArgs &a, int R, int D, int nwaves, hipStream_t st) {
   hipError_t e = ffd::clear_words(reinterpret_cast<uint64_t *>(a.counter), 1, st);
   if (e == hipSuccess) e = ffd::launch_bounded(R, D, a, nwaves, st);
-  if (e == hipSuccess) e = hipEventRecord(ctx->search_done, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "search launch");
-  ctx->search_used = true;
-  return FFD_OK;
+  return use_end(ctx, ctx->scratch_use, ctx->scratch, st, false);
+}
+
+// Launch shape and scratch layout of a decider call.
+struct DecideShape {
+  int R, nwaves;
+  int64_t row_cap;
+  Layout L;
+};
+
+DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs) {
+  int64_t nsum = 0, mmax = 0, nmax = 0;
+  for (int64_t k = 0; k < npairs; ++k) {
+    nsum += p_off[k + 1] - p_off[k];
+    nmax = std::max(nmax, p_off[k + 1] - p_off[k]);
+    mmax = std::max(mmax, q_off[k + 1] - q_off[k]);
+  }
+  DecideShape d;
+  d.R = rows_per_lane(nsum / npairs);
+  d.row_cap = nmax > 64 * d.R ? mmax + 1 : 0;
+  double total = 0, longest = 0;
+  for (int64_t k = 0; k < npairs; ++k) {
+    double st = pair_steps(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], d.R);
+    total += st;
+    longest = std::max(longest, st);
+  }
+  d.nwaves = search_waves(ctx, npairs, total, longest);
+  d.L = layout(npairs, npairs, npairs, 0, 0, d.nwaves, d.row_cap);
+  return d;
+}
+
+// Launch shape and scratch layout of a k-nearest search (the largest
+// stage; the others launch fewer waves).
+DecideShape knn_shape(ffd_ctx *ctx, int64_t n, const int64_t *db_off, int64_t ndb) {
+  int64_t mmax = 0;
+  for (int64_t c = 0; c < ndb; ++c) mmax = std::max(mmax, db_off[c + 1] - db_off[c]);
+  DecideShape d;
+  d.R = rows_per_lane(n);
+  d.row_cap = n > 64 * d.R ? mmax + 1 : 0;
+  d.nwaves = search_waves(ctx, ndb);
+  d.L = layout(1, ndb, ndb, ndb, ndb, d.nwaves, d.row_cap);
+  return d;
 }
 
 }  // namespace
+
+namespace ffdi {
+
+int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off,
+                        int64_t nb, int32_t dim, size_t *bytes) {
+  (void)dim;
+  if (op == FFD_OP_DECIDE) {
+    if (na != nb) return fail(ctx, FFD_E_INVALID, "the decider needs na == nb");
+    *bytes = decide_shape(ctx, a_off, b_off, na).L.total;
+    return FFD_OK;
+  }
+  if (na != 1) return fail(ctx, FFD_E_INVALID, "a k-nearest search takes one query (na == 1)");
+  *bytes = knn_shape(ctx, a_off[1], b_off, nb).L.total;
+  return FFD_OK;
+}
+
+}  // namespace ffdi
 
 extern "C" {
 
@@ -177,25 +221,15 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
   if (!P || !Q || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
   if ((rc = check_offsets(ctx, p_off, npairs, "p_off is NULL"))) return rc;
   if ((rc = check_offsets(ctx, q_off, npairs, "q_off is NULL"))) return rc;
-  int64_t nsum = 0, mmax = 0, nmax = 0;
-  for (int64_t k = 0; k < npairs; ++k) {
-    nsum += p_off[k + 1] - p_off[k];
-    nmax = std::max(nmax, p_off[k + 1] - p_off[k]);
-    mmax = std::max(mmax, q_off[k + 1] - q_off[k]);
-  }
+  int64_t mmax = 0;
+  for (int64_t k = 0; k < npairs; ++k) mmax = std::max(mmax, q_off[k + 1] - q_off[k]);
   if (mmax * dim >= ((int64_t)1 << 31)) return fail(ctx, FFD_E_UNSUPPORTED, "column curve too long");
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipStream_t st = (hipStream_t)stream;
-  int R = rows_per_lane(nsum / npairs);
-  int64_t row_cap = nmax > 64 * R ? mmax + 1 : 0;
-  double total = 0, longest = 0;
-  for (int64_t k = 0; k < npairs; ++k) {
-    double st = pair_steps(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], R);
-    total += st;
-    longest = std::max(longest, st);
-  }
-  int nwaves = search_waves(ctx, npairs, total, longest);
-  Layout L = layout(npairs, npairs, npairs, 0, 0, nwaves, row_cap);
+  const DecideShape sh = decide_shape(ctx, p_off, q_off, npairs);
+  const int R = sh.R, nwaves = sh.nwaves;
+  const int64_t row_cap = sh.row_cap;
+  const Layout &L = sh.L;
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
   // larger pairs first, so that the work counter ends with small ones
   std::vector<int32_t> order(npairs);
@@ -204,7 +238,7 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
     return (p_off[x + 1] - p_off[x]) * (q_off[x + 1] - q_off[x]) >
            (p_off[y + 1] - p_off[y]) * (q_off[y + 1] - q_off[y]);
   });
-  char *base = static_cast<char *>(ctx->search);
+  char *base = static_cast<char *>(ctx->scratch);
   hipError_t e = hipMemcpyAsync(base + L.off0, p_off, (size_t)(npairs + 1) * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(base + L.off1, q_off, (size_t)(npairs + 1) * 8, hipMemcpyHostToDevice, st);
@@ -244,12 +278,12 @@ int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int6
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipStream_t st = (hipStream_t)stream;
   const int64_t kk = std::min<int64_t>(k, ndb);
-  const int R = rows_per_lane(n);
-  const int64_t row_cap = n > 64 * R ? mmax + 1 : 0;
-  const int nwaves = search_waves(ctx, ndb);
-  Layout L = layout(1, ndb, ndb, ndb, ndb, nwaves, row_cap);
+  const DecideShape sh = knn_shape(ctx, n, db_off, ndb);
+  const int R = sh.R;
+  const int64_t row_cap = sh.row_cap;
+  const Layout &L = sh.L;
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
-  char *base = static_cast<char *>(ctx->search);
+  char *base = static_cast<char *>(ctx->scratch);
   // pinned staging: both offset arrays, the bounds, the results, the order
   const size_t h_off = 0, h_lb = al256((size_t)(ndb + 3) * 8), h_vals = h_lb + al256((size_t)ndb * 4),
                h_order = h_vals + al256((size_t)ndb * 4), h_total = h_order + al256((size_t)ndb * 4);

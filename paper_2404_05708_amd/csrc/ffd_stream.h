@@ -623,9 +623,6 @@ struct Stream {
           for (int k2 = 0; k2 < D; ++k2) p[r][k2] = sw ? pn[r][k2] : p[r][k2];
       }
       V up = N::shift_in(g.h[u], bottom);
-#ifdef FFD_DEBUG_HIN
-      if (lane == 0) static_cast<float *>(a.out)[1 + dbg_wave * 4096 + ((t0 + u) & 4095)] = (float)g.h[u];
-#endif
       V dd[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -938,13 +935,7 @@ struct Stream {
     return true;
   }
 
-#ifdef FFD_DEBUG_HIN
-  int32_t dbg_wave;
-#endif
   __device__ void run(int32_t wave) {
-#ifdef FFD_DEBUG_HIN
-    dbg_wave = wave;
-#endif
     lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS, DP);
     int32_t j0, j1;
     if (a.jobs) {

@@ -7,8 +7,8 @@ binding raises: there is no fallback path.
 
 Functions keep the C names: ``ffd_distance``, ``ffd_distance_i32``,
 ``ffd_batch``, ``ffd_batch_i32``, ``ffd_cross``, ``ffd_cross_i32``,
-``ffd_workspace_size``, ``ffd_set_tuning``, ``ffd_create``,
-``ffd_destroy``.  ``Context`` is a small convenience wrapper around them.
+``ffd_workspace_size``, ``ffd_set_scratch``, ``ffd_set_tuning``,
+``ffd_create``, ``ffd_destroy``.  ``Context`` is a small convenience wrapper around them.
 """
 import ctypes
 import os
@@ -35,6 +35,8 @@ FFD_HAVERSINE = 4  # (latitude, longitude) in radians, dim 2; float32 Frechet ca
 FFD_OP_BATCH = 0
 FFD_OP_CROSS = 1
 FFD_OP_PAIR = 2
+FFD_OP_DECIDE = 3
+FFD_OP_KNN = 4
 FFD_MAX_DIM = 4
 
 EXPORTS = (
@@ -46,7 +48,7 @@ EXPORTS = (
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
-    "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_last_search",
+    "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_last_search", "ffd_set_scratch",
 )
 
 
@@ -148,6 +150,8 @@ def _load(path=None):
         fn.restype = ctypes.c_int
     lib.ffd_workspace_size.argtypes = [vp, i32, i64p, i64, i64p, i64, i32, ctypes.POINTER(sz)]
     lib.ffd_workspace_size.restype = ctypes.c_int
+    lib.ffd_set_scratch.argtypes = [vp, vp, sz]
+    lib.ffd_set_scratch.restype = ctypes.c_int
     lib.ffd_set_tuning.argtypes = [vp, i32, i32]
     lib.ffd_set_tuning.restype = ctypes.c_int
     lib.ffd_last_errors.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -270,6 +274,59 @@ def ffd_create_planner(compute_units=256, lds_per_block=160 * 1024):
 
 def ffd_destroy(ctx):
     lib.ffd_destroy(ctx)
+    _MEM.pop(_key(ctx), None)
+
+
+# Device memory the binding owns per context, for calls made without an
+# explicit workspace and for the context's scratch (long single pairs, the
+# search calls): torch tensors kept alive as long as the context, grown when
+# a call reports FFD_E_NOMEM.  A temporary per call could be handed back by
+# torch's caching allocator to other work while a kernel on another stream
+# still uses it; memory held here cannot.
+class _CtxMem:
+    def __init__(self):
+        self.ws = None
+        self.scratch = None
+
+
+_MEM = {}
+
+
+def _key(ctx):
+    return ctx.value if isinstance(ctx, ctypes.c_void_p) else int(ctx)
+
+
+def _mem(ctx):
+    return _MEM.setdefault(_key(ctx), _CtxMem())
+
+
+def _grown(old, nbytes, device):
+    """A tensor of at least nbytes on device; the old one (if any) is dropped
+    only after the device has finished the work that may use it."""
+    if old is not None:
+        torch.cuda.synchronize(old.device)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def ffd_set_scratch(ctx, scratch):
+    """Register a uint8 device tensor (or None) as the context's scratch; the
+    caller keeps it alive while it is registered."""
+    if scratch is None:
+        _check(lib.ffd_set_scratch(ctx, None, 0), ctx)
+    else:
+        _check(lib.ffd_set_scratch(ctx, _dev_ptr(scratch, torch.uint8, "scratch"), scratch.numel()), ctx)
+
+
+def _with_scratch(ctx, device, size_fn, call):
+    """Run call(); if it needs more scratch than the context has, grow the
+    binding's scratch to size_fn() bytes, register it and run it again."""
+    rc = call()
+    if rc == FFD_E_NOMEM:
+        mem = _mem(ctx)
+        mem.scratch = _grown(mem.scratch, size_fn(), device)
+        ffd_set_scratch(ctx, mem.scratch)
+        rc = call()
+    _check(rc, ctx)
 
 
 def ffd_set_tuning(ctx, rows_per_lane=0, waves_per_simd=0):
@@ -299,8 +356,10 @@ def ffd_decide_batch(ctx, P, p_off, Q, q_off, eps, metric=FFD_EUCLIDEAN, out=Non
         raise ValueError("p_off and q_off must describe the same number of pairs")
     if out is None:
         out = torch.empty(max(npairs, 1), dtype=torch.float32, device=P.device)
-    _check(lib.ffd_decide_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric), float(eps),
-                                _dev_ptr(out, torch.float32, "out"), _stream(stream)), ctx)
+    outp = _dev_ptr(out, torch.float32, "out")
+    _with_scratch(ctx, P.device, lambda: ffd_workspace_size(ctx, FFD_OP_DECIDE, po, qo, P.shape[1]),
+                  lambda: lib.ffd_decide_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric), float(eps),
+                                               outp, _stream(stream)))
     return out[:npairs]
 
 
@@ -314,9 +373,10 @@ def ffd_knn(ctx, q, DB, db_off, k, metric=FFD_EUCLIDEAN, stream=None):
     do, dop = _offsets(db_off)
     idx = torch.empty(max(int(k), 1), dtype=torch.int64, device=q.device)
     dist = torch.empty(max(int(k), 1), dtype=torch.float32, device=q.device)
-    _check(lib.ffd_knn(ctx, qp, q.shape[0], Dp, dop, len(do) - 1, q.shape[1], int(metric), int(k),
-                       _dev_ptr(idx, torch.int64, "idx"), _dev_ptr(dist, torch.float32, "dist"),
-                       _stream(stream)), ctx)
+    ip, dp = _dev_ptr(idx, torch.int64, "idx"), _dev_ptr(dist, torch.float32, "dist")
+    _with_scratch(ctx, q.device, lambda: ffd_workspace_size(ctx, FFD_OP_KNN, [0, q.shape[0]], do, q.shape[1]),
+                  lambda: lib.ffd_knn(ctx, qp, q.shape[0], Dp, dop, len(do) - 1, q.shape[1], int(metric), int(k),
+                                      ip, dp, _stream(stream)))
     return idx[:k], dist[:k]
 
 
@@ -339,8 +399,10 @@ def _pair(fn, dtype, odtype, ctx, p, q, metric, out, stream):
         raise ValueError("p and q must have the same dimension")
     if out is None:
         out = torch.empty(1, dtype=odtype, device=p.device)
-    _check(fn(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric),
-              _dev_ptr(out, odtype, "out"), _stream(stream)), ctx)
+    outp = _dev_ptr(out, odtype, "out")
+    _with_scratch(ctx, p.device, lambda: ffd_workspace_size(ctx, FFD_OP_PAIR, [0, p.shape[0]], [0, q.shape[0]],
+                                                            p.shape[1]),
+                  lambda: fn(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], int(metric), outp, _stream(stream)))
     return out
 
 
@@ -367,8 +429,11 @@ def ffd_levenshtein_distance(ctx, p, q, out=None, stream=None):
         raise ValueError("p and q must have the same dimension")
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=p.device)
-    _check(lib.ffd_levenshtein_distance(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1],
-                                        _dev_ptr(out, torch.int64, "out"), _stream(stream)), ctx)
+    outp = _dev_ptr(out, torch.int64, "out")
+    _with_scratch(ctx, p.device, lambda: ffd_workspace_size(ctx, FFD_OP_PAIR, [0, p.shape[0]], [0, q.shape[0]],
+                                                            p.shape[1]),
+                  lambda: lib.ffd_levenshtein_distance(ctx, pp, p.shape[0], qp, q.shape[0], p.shape[1], outp,
+                                                       _stream(stream)))
     return out
 
 
@@ -384,9 +449,10 @@ def ffd_levenshtein_batch(ctx, P, p_off, Q, q_off, out=None, workspace=None, str
         raise ValueError("p_off and q_off must describe the same number of pairs")
     if out is None:
         out = torch.empty(max(npairs, 1), dtype=torch.int64, device=P.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
-    _check(lib.ffd_levenshtein_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], _dev_ptr(out, torch.int64, "out"),
-                                     wsp, wsn, _stream(stream)), ctx)
+    _run_ws(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace,
+            lambda wsp, wsn: lib.ffd_levenshtein_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1],
+                                                       _dev_ptr(out, torch.int64, "out"), wsp, wsn,
+                                                       _stream(stream)))
     return out[:npairs]
 
 
@@ -400,9 +466,10 @@ def ffd_levenshtein_cross(ctx, Qs, q_off, DB, db_off, out=None, workspace=None, 
     nq, ndb = len(qo) - 1, len(do) - 1
     if out is None:
         out = torch.empty(max(nq * ndb, 1), dtype=torch.int64, device=Qs.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
-    _check(lib.ffd_levenshtein_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1],
-                                     _dev_ptr(out, torch.int64, "out"), wsp, wsn, _stream(stream)), ctx)
+    _run_ws(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace,
+            lambda wsp, wsn: lib.ffd_levenshtein_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1],
+                                                       _dev_ptr(out, torch.int64, "out"), wsp, wsn,
+                                                       _stream(stream)))
     return out[:nq * ndb].reshape(nq, ndb)
 
 
@@ -433,11 +500,23 @@ def ffd_workspace_size(ctx, op, a_off, b_off, dim):
     return n.value
 
 
-def _workspace(ctx, op, a_off, b_off, dim, device, workspace):
-    if workspace is None:
-        nbytes = ffd_workspace_size(ctx, op, a_off, b_off, dim)
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
-    return workspace, ctypes.c_void_p(workspace.data_ptr()), workspace.numel()
+def _run_ws(ctx, op, a_off, b_off, dim, device, workspace, call, presize=False):
+    """call(workspace pointer, bytes) with the caller's workspace, or with
+    the context's own one (grown to ffd_workspace_size when the call reports
+    FFD_E_NOMEM, or before the call with `presize`) when the caller gives
+    none."""
+    if workspace is not None:
+        _check(call(_dev_ptr(workspace, workspace.dtype, "workspace"),
+                    workspace.numel() * workspace.element_size()), ctx)
+        return
+    mem = _mem(ctx)
+    if mem.ws is not None and mem.ws.device == device and not presize:
+        rc = call(ctypes.c_void_p(mem.ws.data_ptr()), mem.ws.numel())
+        if rc != FFD_E_NOMEM:
+            _check(rc, ctx)
+            return
+    mem.ws = _grown(mem.ws, ffd_workspace_size(ctx, op, a_off, b_off, dim), device)
+    _check(call(ctypes.c_void_p(mem.ws.data_ptr()), mem.ws.numel()), ctx)
 
 
 def _batch(fn, dtype, odtype, ctx, P, p_off, Q, q_off, metric, out, workspace, stream):
@@ -452,9 +531,9 @@ def _batch(fn, dtype, odtype, ctx, P, p_off, Q, q_off, metric, out, workspace, s
         raise ValueError("p_off and q_off must describe the same number of pairs")
     if out is None:
         out = torch.empty(max(npairs, 1), dtype=odtype, device=P.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
-    _check(fn(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
-              _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)), ctx)
+    _run_ws(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace,
+            lambda wsp, wsn: fn(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
+                                _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)))
     return out[:npairs]
 
 
@@ -490,9 +569,9 @@ def _cross(fn, dtype, odtype, ctx, Qs, q_off, DB, db_off, metric, out, workspace
     nq, ndb = len(qo) - 1, len(do) - 1
     if out is None:
         out = torch.empty(max(nq * ndb, 1), dtype=odtype, device=Qs.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
-    _check(fn(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
-              _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)), ctx)
+    _run_ws(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace,
+            lambda wsp, wsn: fn(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
+                                _dev_ptr(out, odtype, "out"), wsp, wsn, _stream(stream)))
     return out[:nq * ndb].reshape(nq, ndb)
 
 
@@ -529,11 +608,12 @@ def ffd_autotune_batch(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, 
     npairs = len(po) - 1
     if out is None:
         out = torch.empty(max(npairs, 1), dtype=torch.float32, device=P.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace)
     t = Tuning()
-    _check(lib.ffd_autotune_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
-                                  _dev_ptr(out, torch.float32, "out"), wsp, wsn, _stream(stream),
-                                  ctypes.byref(t)), ctx)
+    _run_ws(ctx, FFD_OP_BATCH, po, qo, P.shape[1], P.device, workspace,
+            lambda wsp, wsn: lib.ffd_autotune_batch(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
+                                                    _dev_ptr(out, torch.float32, "out"), wsp, wsn,
+                                                    _stream(stream), ctypes.byref(t)),
+            presize=True)
     return t.as_dict()
 
 
@@ -546,11 +626,12 @@ def ffd_autotune_cross(ctx, Qs, q_off, DB, db_off, metric=FFD_EUCLIDEAN, out=Non
     nq, ndb = len(qo) - 1, len(do) - 1
     if out is None:
         out = torch.empty(max(nq * ndb, 1), dtype=torch.float32, device=Qs.device)
-    ws, wsp, wsn = _workspace(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace)
     t = Tuning()
-    _check(lib.ffd_autotune_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
-                                  _dev_ptr(out, torch.float32, "out"), wsp, wsn, _stream(stream),
-                                  ctypes.byref(t)), ctx)
+    _run_ws(ctx, FFD_OP_CROSS, qo, do, Qs.shape[1], Qs.device, workspace,
+            lambda wsp, wsn: lib.ffd_autotune_cross(ctx, Qp, qop, nq, Dp, dop, ndb, Qs.shape[1], int(metric),
+                                                    _dev_ptr(out, torch.float32, "out"), wsp, wsn,
+                                                    _stream(stream), ctypes.byref(t)),
+            presize=True)
     return t.as_dict()
 
 
@@ -646,6 +727,13 @@ class Context:
 
     def workspace_size(self, op, a_off, b_off, dim):
         return ffd_workspace_size(self.handle, op, a_off, b_off, dim)
+
+    def set_scratch(self, scratch):
+        """Register caller device memory (uint8 tensor, kept alive by the
+        caller) as the scratch; None returns to the binding's own."""
+        ffd_set_scratch(self.handle, scratch)
+        if scratch is None:
+            _mem(self.handle).scratch = None
 
 
 # ------------------------------------------------------------------ serving

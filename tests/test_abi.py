@@ -276,3 +276,30 @@ def test_serving_database_and_arena(planner):
         assert L.ffd_server_submit(None, FAKE, 5, 0, FAKE, ctypes.byref(t)) == ffd.FFD_E_INVALID
     finally:
         L.ffd_db_destroy(db)
+
+
+def test_scratch_sizes_and_registration(planner):
+    """Scratch sizes (ffd_workspace_size with FFD_OP_PAIR, FFD_OP_DECIDE,
+    FFD_OP_KNN) and ffd_set_scratch argument checks; the library allocates
+    no device memory, so long pairs and the search calls size their scratch
+    through these."""
+    # a pair that fits one wavefront needs none, a long one some
+    assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_PAIR, [0, 100], [0, 90], 2) == 0
+    long_need = ffd.ffd_workspace_size(planner, ffd.FFD_OP_PAIR, [0, 6000], [0, 5000], 2)
+    assert long_need > 0
+    # more rows need more boundary rows
+    assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_PAIR, [0, 60000], [0, 5000], 2) > long_need
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_workspace_size(planner, ffd.FFD_OP_PAIR, [0, 10, 20], [0, 5, 9], 2)  # two curves
+    P, p_off, Q, q_off = workloads.random_pairs(5, 40, 1, 900, dim=2)
+    assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_DECIDE, p_off, q_off, 2) > 2 * 41 * 8
+    _, db_off = workloads.concat([np.zeros((int(k), 2), np.float32) for k in np.arange(20, 220)])
+    knn = ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0, 300], db_off, 2)
+    assert knn > 200 * 8
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0, 30, 60], db_off, 2)  # one query only
+    L = ffd.lib
+    assert L.ffd_set_scratch(None, None, 0) == ffd.FFD_E_INVALID
+    assert L.ffd_set_scratch(planner, None, 64) == ffd.FFD_E_INVALID
+    assert L.ffd_set_scratch(planner, FAKE, 64) == ffd.FFD_OK
+    assert L.ffd_set_scratch(planner, None, 0) == ffd.FFD_OK

@@ -58,6 +58,12 @@ def test_jitter_build_matches_release(gpu):
         pd, qd = torch.from_numpy(p).to(dev), torch.from_numpy(q).to(dev)
         want = ctx.distance(pd, qd).item()
         one = torch.empty(1, dtype=torch.float32, device=dev)
+        # the pipelined pair runs in scratch the caller registers
+        pair_off = [np.array([0, 24000], dtype=np.int64), np.array([0, 20000], dtype=np.int64)]
+        assert jl.ffd_workspace_size(h, ffd.FFD_OP_PAIR, pair_off[0].ctypes.data_as(i64p), 1,
+                                     pair_off[1].ctypes.data_as(i64p), 1, 3, ctypes.byref(nbytes)) == ffd.FFD_OK
+        scratch = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        assert jl.ffd_set_scratch(h, ctypes.c_void_p(scratch.data_ptr()), nbytes.value) == ffd.FFD_OK
         for rep in range(3):
             print(f"case: jitter long pair, repeat {rep}", flush=True)
             assert jl.ffd_distance(h, ctypes.c_void_p(pd.data_ptr()), 24000, ctypes.c_void_p(qd.data_ptr()), 20000,

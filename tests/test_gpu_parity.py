@@ -198,25 +198,50 @@ def test_cross_small(ctx):
     np.testing.assert_array_equal(got, oracle.dfd_cross_i32(Qi, qoi, Di, doi, nthreads=8))
 
 
-def test_batched_workload_full_size_sampled(ctx):
-    """All 4096 pairs in the launch configuration the benchmark times;
-    sampled outputs against stored oracle values, all outputs against the
-    properties that hold at any size."""
+def test_batched_workload_full_size(ctx):
+    """All 4096 pairs in the launch configuration the benchmark times, every
+    output against the FP64 oracle (the rolling form on 16 threads), plus
+    the stored sample and the end-point lower bound."""
     say("case: batched workload 4096 pairs")
     g = json.load(open(os.path.join(HERE, "golden", "expected.json")))["batched"]
     P, p_off, Q, q_off = workloads.batched()
     got = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    assert ctx.last_errors() == 0
     idx = np.array(g["sample_index"])
     assert rel_ok(got[idx], np.array(g["euclidean"]))
-    assert np.all(np.isfinite(got)) and np.all(got >= 0)
+    want = oracle.dfd_batch(P, p_off, Q, q_off, nthreads=16)
+    bad = np.flatnonzero(np.abs(got.astype(np.float64) - want) > TOL * want)
+    assert bad.size == 0, f"{bad.size} pairs outside 2e-6, first {bad[:5]}"
     # end-point lower bound holds for every pair
-    for k in range(0, 4096, 7):
-        p0, p1 = P[p_off[k]], P[p_off[k + 1] - 1]
-        q0, q1 = Q[q_off[k]], Q[q_off[k + 1] - 1]
-        lb = max(np.linalg.norm(p0.astype(np.float64) - q0), np.linalg.norm(p1.astype(np.float64) - q1))
-        assert got[k] >= lb * (1 - TOL)
+    p0, p1 = P[p_off[:-1]].astype(np.float64), P[p_off[1:] - 1].astype(np.float64)
+    q0, q1 = Q[q_off[:-1]].astype(np.float64), Q[q_off[1:] - 1].astype(np.float64)
+    lb = np.maximum(np.linalg.norm(p0 - q0, axis=1), np.linalg.norm(p1 - q1, axis=1))
+    assert np.all(got >= lb * (1 - TOL))
     again = ctx.batch(dev(P), p_off, dev(Q), q_off).cpu().numpy()
     np.testing.assert_array_equal(got, again)
+
+
+def test_large_pair_full_size(ctx):
+    """The single large pair (131072 x 131072 points, 3-D) in the launch the
+    benchmark times: bands pipelined over every wavefront with boundary rows
+    through LDS rings and global links; against the stored FP64 oracle value
+    (rolling form, single thread) within 2e-6, with no device error flags."""
+    say("case: large pair 131072 x 131072, 3-D")
+    want = json.load(open(os.path.join(HERE, "golden", "expected.json")))["large_pair"]["euclidean"]
+    p, q = workloads.large_pair()
+    pd, qd = dev(p), dev(q)
+    got = ctx.distance(pd, qd).item()
+    assert ctx.last_errors() == 0
+    info = ctx.last_launch()
+    say(f"launch: {info}")
+    assert info["waves"] > 1
+    assert abs(got - want) <= TOL * want, (got, want)
+    lb = max(np.linalg.norm(p[0].astype(np.float64) - q[0]), np.linalg.norm(p[-1].astype(np.float64) - q[-1]))
+    assert got >= lb * (1 - TOL)
+    # the squared form selects the same cell
+    got_sq = ctx.distance(pd, qd, metric=1).item()
+    assert ctx.last_errors() == 0
+    assert abs(got_sq - want * want) <= 2 * TOL * want * want
 
 
 def test_cross_int_workload_full_size_sampled(ctx):
