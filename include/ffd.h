@@ -172,6 +172,24 @@ int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q
               const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, float *out,
               void *workspace, size_t ws_bytes, void *stream);
 
+/* ffd_batch for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launch and results, with no workspace argument.  Its workspace is a
+ * static device array of the library, 32 MiB on each GPU, held until the
+ * process ends; the call allocates no device or pinned memory and creates
+ * no runtime objects (its events and the array's device address are set up
+ * by ffd_create).  The plan is copied from pageable host memory of the
+ * context.  Every call on one GPU shares that GPU's array, from any
+ * context: calls that overlap on one GPU race (calls of one context on
+ * different streams are ordered by the library; calls of different contexts
+ * are not).  Results are valid once the stream has completed.
+ * Errors: as ffd_batch; FFD_E_NOMEM when the request needs more than the
+ * 32 MiB (the message gives the size it needs), checked before any launch;
+ * FFD_E_DEVICE when the array could not be resolved on the device. */
+int ffd_batch_noalloc(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q,
+                      const int64_t *q_off, int64_t npairs, int32_t dim, int32_t metric, float *out,
+                      void *stream);
+
 /* Int32 version of ffd_batch: exact int64 out[npairs]; metrics as
  * ffd_distance_i32. */
 int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q,

@@ -663,12 +663,19 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
 }
 
 // The staging buffer for plan uploads, at least `bytes` long.  Replacing
-// its contents first waits until the last upload has read it.
+// its contents first waits until every upload has read it: the last one
+// (the event), or, when uploads since the last rewrite went to several
+// streams, all work on the device.
 int ensure_pinned(ffd_ctx *ctx, size_t bytes) {
-  if (ctx->upload_done) {
+  if (ctx->upload_streams_mixed) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize (plan upload)");
+  } else if (ctx->upload_done) {
     hipError_t e = hipEventSynchronize(ctx->upload_done);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize (plan upload)");
   }
+  ctx->upload_streams_mixed = false;
+  ctx->upload_stream = nullptr;
   ctx->staged_gen = 0;
   if (ctx->pinned_bytes >= bytes) return FFD_OK;
   if (ctx->pinned) {
@@ -719,12 +726,29 @@ int use_end(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool cap
 // requires the plan that the context's last eager upload put into this
 // workspace, and the recorded work clears the flags and the error word
 // first, since every replay reuses the recorded epoch.
+// Copy the plan image of a launch (jobs, job ranges, offsets, zeroed flags
+// and error word) into host memory at h.
+void plan_image(const Plan &pl, const WsLayout &wl, const int64_t *off0, int64_t n0, const int64_t *off1,
+                int64_t n1, unsigned char *h) {
+  memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
+  memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
+  memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
+  memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
+  memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
+}
+
 int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const int64_t *off0, int64_t n0,
              const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
-             size_t ws_bytes, hipStream_t st, UseOrder &use) {
+             size_t ws_bytes, hipStream_t st, UseOrder &use, bool noalloc = false) {
   WsLayout wl = ws_layout(pl, n0, n1, exact);
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings, ctx->measure),
                               exact ? 1 : 0, D, pl.max_steps};
+  if (noalloc && ws_bytes < wl.total) {
+    std::string msg = "the request needs " + std::to_string(wl.total) +
+                      " bytes of device scratch; ffd_batch_noalloc has " + std::to_string(ws_bytes);
+    return fail(ctx, FFD_E_NOMEM, msg.c_str());
+  }
+  if (noalloc && ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   if (!ws || ws_bytes < wl.total) return fail(ctx, FFD_E_NOMEM, "workspace too small (see ffd_workspace_size)");
   if (pl.max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
@@ -736,15 +760,22 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   unsigned char *w = (unsigned char *)ws;
   int rc = use_begin(ctx, use, ws, st, capturing);
   if (rc) return rc;
-  if (!capturing) {
+  if (noalloc && !capturing) {
+    // pageable host memory, copied by the runtime's own staging before the
+    // copy call returns, so the image may change again afterwards
+    if (ctx->noalloc_gen != gen || ctx->noalloc_img.size() < wl.links) {
+      ctx->noalloc_img.resize(wl.links);
+      plan_image(pl, wl, off0, n0, off1, n1, ctx->noalloc_img.data());
+      ctx->noalloc_gen = gen;
+    }
+    e = hipMemcpyAsync(w, ctx->noalloc_img.data(), wl.links, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync (plan)");
+    ctx->plan_ws = ws;
+    ctx->plan_ws_gen = gen;
+  } else if (!capturing) {
     if (ctx->staged_gen != gen) {
       if ((rc = ensure_pinned(ctx, wl.links))) return rc;
-      unsigned char *h = (unsigned char *)ctx->pinned;
-      memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
-      memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
-      memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
-      memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
-      memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
+      plan_image(pl, wl, off0, n0, off1, n1, (unsigned char *)ctx->pinned);
       ctx->staged_gen = gen;
     }
     e = hipMemcpyAsync(w, ctx->pinned, wl.links, hipMemcpyHostToDevice, st);
@@ -755,6 +786,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     }
     e = hipEventRecord(ctx->upload_done, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    if (ctx->upload_stream && ctx->upload_stream != st) ctx->upload_streams_mixed = true;
+    ctx->upload_stream = st;
     ctx->plan_ws = ws;
     ctx->plan_ws_gen = gen;
   } else {
@@ -951,7 +984,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
 
 int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *Q, const int64_t *q_off,
                  int64_t npairs, int32_t dim, int32_t metric, void *out, void *ws, size_t ws_bytes, hipStream_t st,
-                 bool exact) {
+                 bool exact, bool noalloc = false) {
   int rc = check_common(ctx, dim, metric, exact);
   if (rc) return rc;
   if (npairs < 0) return fail(ctx, FFD_E_INVALID, "npairs < 0");
@@ -966,7 +999,7 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
   if (rc) return rc;
   return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st,
-                  ctx->ws_use);
+                  ctx->ws_use, noalloc);
 }
 
 int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq, const void *DB,
@@ -1106,6 +1139,17 @@ int ffd_create(int device, ffd_ctx **out) {
   c->lds_block_max = prop.sharedMemPerBlock < 65536 ? prop.sharedMemPerBlock : 65536;
   c->lds_cu = prop.maxSharedMemoryPerMultiProcessor > 0 ? prop.maxSharedMemoryPerMultiProcessor : 65536;
   c->epoch = (uint32_t)std::chrono::steady_clock::now().time_since_epoch().count() | 1u;
+  // events and the no-allocation scratch are set up here, so that no later
+  // call needs to create or allocate anything on the device
+  int prev = 0;
+  bool ok = hipGetDevice(&prev) == hipSuccess && hipSetDevice(device) == hipSuccess;
+  for (hipEvent_t *ev : {&c->upload_done, &c->ws_use.done, &c->scratch_use.done})
+    ok = ok && hipEventCreateWithFlags(ev, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipSetDevice(prev) == hipSuccess;
+  if (!ok || noalloc_setup(c, device) != FFD_OK) {
+    ffd_destroy(c);
+    return FFD_E_DEVICE;
+  }
   *out = c;
   return FFD_OK;
 }
@@ -1236,6 +1280,22 @@ int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, workspace, ws_bytes, (hipStream_t)stream,
                       exact);
 }
+
+}  // extern "C"
+
+namespace ffdi {
+
+int batch_noalloc(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                  int64_t npairs, int32_t dim, int32_t metric, float *out, void *ws, size_t ws_bytes, hipStream_t st) {
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  bool exact = false;
+  if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, ws, ws_bytes, st, exact, true);
+}
+
+}  // namespace ffdi
+
+extern "C" {
 
 int ffd_batch_i32(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, const int32_t *Q, const int64_t *q_off,
                   int64_t npairs, int32_t dim, int32_t metric, int64_t *out, void *workspace, size_t ws_bytes,

@@ -151,7 +151,12 @@ struct ffd_ctx {
   void *pinned = nullptr;     // host staging buffer for plan uploads (pinned)
   size_t pinned_bytes = 0;
   uint64_t staged_gen = 0;    // plan whose bytes the staging buffer holds (0: none)
-  hipEvent_t upload_done = nullptr;
+  hipEvent_t upload_done = nullptr;   // end of the last plan upload
+  hipStream_t upload_stream = nullptr;
+  bool upload_streams_mixed = false;  // uploads on more than one stream since the staging was written
+  // plan image of the no-allocation entry point (pageable host memory)
+  std::vector<unsigned char> noalloc_img;
+  uint64_t noalloc_gen = 0;
   ffdi::PlanCache batch_plans, pair_plans;
   // launch shapes chosen by the autotuner, by request (offsets, op, dim, type)
   std::unordered_map<uint64_t, std::pair<ffdi::ReqKey, ffd_tuning>> tuned;
@@ -198,6 +203,14 @@ int use_end(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool cap
 // Scratch bytes of the search calls (FFD_OP_DECIDE, FFD_OP_KNN; ffd_search.cpp).
 int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off,
                         int64_t nb, int32_t dim, size_t *bytes);
+
+// The no-allocation entry point (ffd_noalloc.hip): resolve the device
+// address of its static scratch on `device` (ffd_create), and run a batch
+// with it as the workspace (ffd_host.cpp).
+int noalloc_setup(ffd_ctx *ctx, int device);
+size_t noalloc_bytes();
+int batch_noalloc(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                  int64_t npairs, int32_t dim, int32_t metric, float *out, void *ws, size_t ws_bytes, hipStream_t st);
 
 int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
                bool exact, Plan &pl);

@@ -49,6 +49,7 @@ EXPORTS = (
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
     "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_last_search", "ffd_set_scratch",
+    "ffd_batch_noalloc",
 )
 
 
@@ -150,6 +151,8 @@ def _load(path=None):
         fn.restype = ctypes.c_int
     lib.ffd_workspace_size.argtypes = [vp, i32, i64p, i64, i64p, i64, i32, ctypes.POINTER(sz)]
     lib.ffd_workspace_size.restype = ctypes.c_int
+    lib.ffd_batch_noalloc.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, i32, vp, vp]
+    lib.ffd_batch_noalloc.restype = ctypes.c_int
     lib.ffd_set_scratch.argtypes = [vp, vp, sz]
     lib.ffd_set_scratch.restype = ctypes.c_int
     lib.ffd_set_tuning.argtypes = [vp, i32, i32]
@@ -542,6 +545,25 @@ def ffd_batch(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, workspace
                   out, workspace, stream)
 
 
+def ffd_batch_noalloc(ctx, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, out=None, stream=None):
+    """ffd_batch with the library's static device scratch: no workspace, no
+    device allocation by the library (out is allocated here when not given)."""
+    P, Pp = _curve(P, torch.float32, "P")
+    Q, Qp = _curve(Q, torch.float32, "Q")
+    if P.shape[1] != Q.shape[1]:
+        raise ValueError("P and Q must have the same dimension")
+    po, pop = _offsets(p_off)
+    qo, qop = _offsets(q_off)
+    npairs = len(po) - 1
+    if len(qo) - 1 != npairs:
+        raise ValueError("p_off and q_off must describe the same number of pairs")
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=torch.float32, device=P.device)
+    _check(lib.ffd_batch_noalloc(ctx, Pp, pop, Qp, qop, npairs, P.shape[1], int(metric),
+                                 _dev_ptr(out, torch.float32, "out"), _stream(stream)), ctx)
+    return out[:npairs]
+
+
 def ffd_batch_i32(ctx, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, out=None, workspace=None,
                   stream=None):
     return _batch(lib.ffd_batch_i32, torch.int32, torch.int64, ctx, P, p_off, Q, q_off, metric,
@@ -673,6 +695,9 @@ class Context:
 
     def batch(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
         return ffd_batch(self.handle, P, p_off, Q, q_off, metric, **kw)
+
+    def batch_noalloc(self, P, p_off, Q, q_off, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_batch_noalloc(self.handle, P, p_off, Q, q_off, metric, **kw)
 
     def batch_i32(self, P, p_off, Q, q_off, metric=FFD_SQEUCLIDEAN, **kw):
         return ffd_batch_i32(self.handle, P, p_off, Q, q_off, metric, **kw)

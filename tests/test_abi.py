@@ -303,3 +303,21 @@ def test_scratch_sizes_and_registration(planner):
     assert L.ffd_set_scratch(planner, None, 64) == ffd.FFD_E_INVALID
     assert L.ffd_set_scratch(planner, FAKE, 64) == ffd.FFD_OK
     assert L.ffd_set_scratch(planner, None, 0) == ffd.FFD_OK
+
+
+def test_noalloc_size_limit_checked_on_the_host(planner):
+    """ffd_batch_noalloc refuses a request larger than its static scratch
+    before anything is launched (FFD_E_NOMEM, with the size it needs); a
+    request that fits passes the checks (a planning-only context then
+    reports FFD_E_DEVICE)."""
+    L = ffd.lib
+    P, p_off, Q, q_off = workloads.batched()
+    po, qo = np.asarray(p_off, np.int64), np.asarray(q_off, np.int64)
+    assert L.ffd_batch_noalloc(planner, FAKE, _i64p(po), FAKE, _i64p(qo), 4096, 2, 0, FAKE, None) == ffd.FFD_E_DEVICE
+    big = np.arange(5, dtype=np.int64) * 32768
+    assert L.ffd_batch_noalloc(planner, FAKE, _i64p(big), FAKE, _i64p(big), 4, 2, 0, FAKE, None) == ffd.FFD_E_NOMEM
+    assert b"ffd_batch_noalloc has 33554432" in L.ffd_last_error(planner)
+    # argument checks come first
+    bad = np.array([0, 5, 5], dtype=np.int64)
+    assert L.ffd_batch_noalloc(planner, FAKE, _i64p(bad), FAKE, _i64p(bad), 2, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
+    assert L.ffd_batch_noalloc(None, FAKE, _i64p(po), FAKE, _i64p(qo), 4096, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
