@@ -319,6 +319,10 @@ typedef struct ffd_plan_summary {
   int64_t link_elems;      /* elements of all link buffers                   */
   int64_t stream_steps;    /* longest stream of any wave                     */
   int64_t jobs;            /* entries of the job table                       */
+  int32_t pipelined;       /* 1: a single long pair on the pipelined kernel:
+                              no job table; waves = 4 x workgroups, one band
+                              of 64 R rows per wave and pass, link_elems
+                              values of boundary rows between workgroups   */
 } ffd_plan_summary;
 typedef struct ffd_plan_job { /* 64 bytes */
   int64_t out_base;   /* output index of the first column curve              */

@@ -557,7 +557,8 @@ bool build_pipeline(ffd_ctx *ctx, const Unit &u, int R, int D, bool exact, Plan 
 }
 
 template <typename MakeUnits>
-int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single, MakeUnits make, Plan &best) {
+int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single, MakeUnits make, Plan &best,
+               double *best_cost_out = nullptr) {
   double best_cost = -1;
   for (int R : kRs) {
     if (ctx->tune_R && R != ctx->tune_R) continue;
@@ -603,7 +604,100 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
     }
   }
   if (best_cost < 0) return fail(ctx, FFD_E_UNSUPPORTED, "no feasible launch shape");
+  if (best_cost_out) *best_cost_out = best_cost;
   return FFD_OK;
+}
+
+// ------------------------------------------------------ pipelined single pair
+//
+// A single long pair on the pipelined kernel (ffd_pipe.h): one band of 64 R
+// rows per wave, four waves per workgroup in lockstep (kPipeLag groups of
+// 16 steps apart), workgroups chained through link rows in global memory.
+// Modelled stream steps: the last band starts about 108 steps per band
+// after the first (6 groups inside a workgroup, about 9 between
+// workgroups), or, with several passes, when its wave has swept its
+// earlier bands; each band sweeps the columns plus the lanes' ramp and
+// the link flush.  Clocks per step: one instruction per 4 clocks (one wave
+// per SIMD issues alone), R cells of 2 D + 2 instructions (FP64: 2 D + 3)
+// and about 7 per step of lane shift, LDS traffic and bookkeeping.
+constexpr double kPipeBandLag = (3 * ffd::kPipeLag * ffd::kPipeGroup + 144) / 4.0;
+
+double pipe_step_clocks(int R, int D, bool exact) {
+  return 4.0 * (R * (2 * D + 2 + (exact ? 1 : 0)) + 7 + (exact ? 2 : 0));
+}
+
+// A pipelined plan for rows x cols with R rows per lane; false when the
+// kernel cannot run it.
+bool build_pipe(ffd_ctx *ctx, int64_t rows, int64_t cols, int R, int D, bool exact, Plan &pl, double &cost) {
+  if (R != 2 && R != 4) return false;
+  const int64_t nb = ffd::bands_for(rows, R);
+  if (nb < 2 || nb > INT32_MAX / 2 || cols < 2) return false;
+  size_t lds = ffd::pipe_lds(exact, D);
+  if (lds > ctx->lds_block_hw) return false;
+  // one workgroup (four waves, one per SIMD) per compute unit: request more
+  // than half of a compute unit's LDS where a workgroup may, so that the
+  // hardware cannot place two workgroups on one compute unit (two waves
+  // sharing a SIMD would halve the pace of the whole chain)
+  if (ctx->lds_cu / 2 + 4096 <= ctx->lds_block_hw) lds = std::max(lds, ctx->lds_cu / 2 + 4096);
+  int64_t nwg = (nb + ffd::kPipeWaves - 1) / ffd::kPipeWaves;
+  int64_t cap = ctx->cus;
+  if (ctx->device >= 0) {
+    int blocks = 0;
+    if (ffd::occupancy_pipe(exact, R, D, lds, &blocks) != hipSuccess || blocks < 1) return false;
+  }
+  if (nwg > cap) nwg = cap;
+  int32_t xcd = 0;
+  if (nwg >= 8) {
+    int64_t up = (nwg + 7) / 8 * 8;
+    if (up > cap) up = cap / 8 * 8;
+    if (up >= nwg || up >= 8) {
+      nwg = up;
+      xcd = (int32_t)(nwg / 8);
+    }
+  }
+  const int64_t W = nwg * ffd::kPipeWaves;
+  const int64_t passes = (nb + W - 1) / W;
+  const double sweep = (double)cols + 64.0 + 5.0 * ffd::kPipeGroup;
+  const double chain = (double)(nb - 1) * kPipeBandLag;
+  const double wrap = (double)(passes - 1) * sweep + (double)((nb - 1) % W) * kPipeBandLag;
+  const double steps = std::max(chain, wrap) + sweep;
+  if (steps + 64 > (double)INT32_MAX) return false;
+  pl = Plan();
+  pl.R = R;
+  pl.nwaves = (int)W;
+  pl.wpb = ffd::kPipeWaves;
+  pl.coop = true;
+  pl.pipe = true;
+  pl.pipe_nb = (int32_t)nb;
+  pl.pipe_nwg = (int32_t)nwg;
+  pl.pipe_xcd = xcd;
+  pl.pipe_rows = rows;
+  pl.pipe_cols = cols;
+  pl.pipe_stride = (cols + 63) / 64 * 64;
+  // one link row per band that hands its bottom row to another workgroup
+  pl.pipe_nlinks = (nb - 1) / ffd::kPipeWaves;
+  pl.pipe_lds = lds;
+  pl.link_elems = pl.pipe_nlinks * pl.pipe_stride;
+  pl.max_steps = (int64_t)steps;
+  pl.makespan = steps;
+  cost = steps * pipe_step_clocks(R, D, exact);
+  return true;
+}
+
+// Scratch of a pipelined launch: the error word, then the link rows (none
+// for a pair inside one workgroup, which then needs no scratch at all).
+struct PipeLayout {
+  size_t err, links, total;
+};
+
+PipeLayout pipe_layout(const Plan &pl, bool exact) {
+  PipeLayout L{0, 0, 0};
+  if (pl.pipe_nlinks == 0) return L;
+  L.err = 0;
+  L.links = 256;
+  L.total = L.links + (size_t)pl.link_elems * (exact ? 8 : 4);
+  L.total = (L.total + 255) & ~(size_t)255;
+  return L;
 }
 
 int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
@@ -636,8 +730,27 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
   CurveSet P{off0, 1}, Q{off1, 1};
   int W = ctx->tune_W > 0 ? ctx->tune_W : 1;
   double share = ctx->split < 0.f ? -1.0 : 0.0;
-  return plan_units(ctx, D, exact, W, share, true,
-                    [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl);
+  double cost = -1;
+  int rc = plan_units(ctx, D, exact, W, share, true,
+                      [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl, &cost);
+  if (rc) return rc;
+  // the Frechet distance on squared cells may run on the pipelined kernel,
+  // either curve holding the rows, when the model says it is faster
+  if (ctx->measure != 0 || share < 0 || ctx->tune_W > 0) return FFD_OK;
+  for (int R : {2, 4}) {
+    if (ctx->tune_R && R != ctx->tune_R) continue;
+    for (int swap = 0; swap < 2; ++swap) {
+      Plan pp;
+      double pc = 0;
+      if (!build_pipe(ctx, swap ? m : n, swap ? n : m, R, D, exact, pp, pc)) continue;
+      pp.pipe_swap = swap != 0;
+      if (pc < cost) {
+        cost = pc;
+        pl = std::move(pp);
+      }
+    }
+  }
+  return FFD_OK;
 }
 
 // ---------------------------------------------------------------- workspace
@@ -929,6 +1042,62 @@ int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64
   return FFD_OK;
 }
 
+// Device scratch a single-pair plan needs (0: none).
+size_t pair_scratch_bytes(const Plan &pl, bool exact) {
+  if (pl.pipe) return pipe_layout(pl, exact).total;
+  if (pl.nwaves == 1 && pl.link_elems == 0) return 0;
+  return ws_layout(pl, 1, 1, exact).total;
+}
+
+// Launch a pipelined single-pair plan.
+int run_pipe(ffd_ctx *ctx, const Plan &pl, const void *p, const void *q, int D, bool exact, int metric, void *out,
+             hipStream_t st) {
+  PipeLayout L = pipe_layout(pl, exact);
+  size_t lds = pl.pipe_lds;
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, ffd::kPipeWaves, (int32_t)(lds / ffd::kPipeWaves), exact ? 1 : 0, D,
+                              pl.max_steps};
+  if (ctx->scratch_bytes < L.total)
+    return fail(ctx, FFD_E_NOMEM,
+                "a pair this long runs on many wavefronts and needs device scratch: register at least "
+                "ffd_workspace_size(FFD_OP_PAIR) bytes with ffd_set_scratch");
+  bool capturing = false;
+  hipError_t e = capturing_on(st, capturing);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamIsCapturing");
+  unsigned char *w = (unsigned char *)ctx->scratch;
+  int rc;
+  if (L.total > 0 && (rc = use_begin(ctx, ctx->scratch_use, w, st, capturing))) return rc;
+  ffd::PipeArgs a;
+  memset(&a, 0, sizeof a);
+  a.X = pl.pipe_swap ? q : p;
+  a.Y = pl.pipe_swap ? p : q;
+  a.n = pl.pipe_rows;
+  a.m = pl.pipe_cols;
+  a.nb = pl.pipe_nb;
+  a.nwg = pl.pipe_nwg;
+  a.xcd_span = pl.pipe_xcd;
+  a.metric = metric;
+  a.links = L.total ? w + L.links : nullptr;
+  a.link_stride = pl.pipe_stride;
+  a.err = L.total ? (uint64_t *)(w + L.err) : nullptr;
+  a.epoch = ++ctx->epoch;
+  a.out = out;
+  // a link wait may last ten times the modelled run time at 1 GHz, and at
+  // least a second (real-time counter at 100 MHz)
+  a.patience = (uint64_t)std::max(1e8, 10.0 * pl.makespan * pipe_step_clocks(pl.R, D, exact) / 1e9 * 1e8);
+  if (L.total) {
+    // every launch (and every graph replay) starts from unwritten link rows
+    e = ffd::pipe_init(a.links, (int64_t)((L.total - L.links) / 4), a.err, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "link initialisation launch");
+  }
+  e = ffd::launch_pipe(exact, pl.R, D, a, lds, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "pipelined kernel launch");
+  ctx->last_err = a.err;
+  ctx->last_epoch = a.epoch;
+  ctx->last_stream = st;
+  if (L.total) return use_end(ctx, ctx->scratch_use, w, st, capturing);
+  return FFD_OK;
+}
+
 int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m, int32_t dim, int32_t metric,
                 void *out, hipStream_t st, bool exact) {
   int rc = check_common(ctx, dim, metric, exact);
@@ -947,6 +1116,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (pl->pipe) return run_pipe(ctx, *pl, p, q, dim, exact, metric, out, st);
   if (pl->nwaves == 1 && pl->link_elems == 0) {
     // one stream: the job travels in the kernel arguments, no device memory
     KernelArgs a;
@@ -1137,6 +1307,7 @@ int ffd_create(int device, ffd_ctx **out) {
   c->device = device;
   c->cus = prop.multiProcessorCount;
   c->lds_block_max = prop.sharedMemPerBlock < 65536 ? prop.sharedMemPerBlock : 65536;
+  c->lds_block_hw = prop.sharedMemPerBlock;
   c->lds_cu = prop.maxSharedMemoryPerMultiProcessor > 0 ? prop.maxSharedMemoryPerMultiProcessor : 65536;
   c->epoch = (uint32_t)std::chrono::steady_clock::now().time_since_epoch().count() | 1u;
   // events and the no-allocation scratch are set up here, so that no later
@@ -1163,6 +1334,7 @@ int ffd_create_planner(int32_t compute_units, int64_t lds_per_block, ffd_ctx **o
   c->device = -1;
   c->cus = compute_units;
   c->lds_block_max = (size_t)std::min<int64_t>(lds_per_block, 65536);
+  c->lds_block_hw = (size_t)lds_per_block;
   c->lds_cu = (size_t)lds_per_block;
   c->epoch = 1;
   *out = c;
@@ -1464,6 +1636,7 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   summary->link_elems = pl.link_elems;
   summary->stream_steps = pl.max_steps;
   summary->jobs = (int64_t)pl.jobs.size();
+  summary->pipelined = pl.pipe ? 1 : 0;
   if (jobs) {
     if (jobs_cap < (int64_t)pl.jobs.size()) return fail(ctx, FFD_E_NOMEM, "jobs_cap too small");
     memcpy(jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
@@ -1506,9 +1679,8 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
                        ex == 1, &pl, gen);
       if (rc == FFD_E_UNSUPPORTED) continue;
       if (rc) return rc;
-      // a single pair on one wavefront needs no device memory
-      if (op == FFD_OP_PAIR && pl->nwaves == 1 && pl->link_elems == 0) continue;
-      worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
+      if (op == FFD_OP_PAIR) worst = std::max(worst, pair_scratch_bytes(*pl, ex == 1));
+      else worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
     }
   if (worst == 0 && op != FFD_OP_PAIR) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;

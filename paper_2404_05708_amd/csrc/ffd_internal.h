@@ -33,6 +33,11 @@ FFD_DECLARE_OP(10)
 FFD_DECLARE_OP(11)
 #undef FFD_DECLARE_OP
 hipError_t clear_words(uint64_t *p, int64_t n, hipStream_t st);
+// The pipelined single-pair kernel (ffd_kernels_pipe.hip): R in {2, 4}.
+hipError_t launch_pipe(bool exact, int R, int D, const PipeArgs &a, size_t lds, hipStream_t st);
+hipError_t occupancy_pipe(bool exact, int R, int D, size_t lds, int *blocks);
+hipError_t pipe_init(void *links, int64_t nwords32, uint64_t *err, hipStream_t st);
+size_t pipe_lds(bool exact, int D);  // LDS of a workgroup
 
 // The kernel variant with LDS rings between waves serves launches whose
 // plan uses them (a.rings); every other launch takes the plain variant.
@@ -104,6 +109,15 @@ struct Plan {
   double makespan = 0;         // modelled, in steps
   std::vector<Job> jobs;       // grouped by wave, in placement order
   std::vector<int32_t> wave_jobs;
+  // a single long pair on the pipelined kernel (no jobs): bands, workgroups,
+  // XCD span of the chain order, orientation and link rows
+  bool pipe = false;
+  int32_t pipe_nb = 0, pipe_nwg = 0, pipe_xcd = 0;
+  bool pipe_swap = false;      // the second curve holds the rows
+  int64_t pipe_rows = 0, pipe_cols = 0;
+  int64_t pipe_stride = 0;     // values per link row
+  int64_t pipe_nlinks = 0;     // link rows
+  size_t pipe_lds = 0;         // LDS requested per workgroup
 };
 
 // A request as the planner sees it: header words (operation, dimension,
@@ -137,6 +151,7 @@ struct ffd_ctx {
   int device = 0;
   int cus = 0;
   size_t lds_block_max = 0;   // LDS per workgroup the planner uses
+  size_t lds_block_hw = 0;    // LDS a workgroup may request (device limit)
   size_t lds_cu = 0;          // LDS per compute unit
   int tune_R = 0;
   int tune_W = 0;

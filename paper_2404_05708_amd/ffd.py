@@ -74,7 +74,8 @@ class PlanSummary(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("cooperative", ctypes.c_int32),
                 ("rings", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("link_elems", ctypes.c_int64), ("stream_steps", ctypes.c_int64), ("jobs", ctypes.c_int64)]
+                ("link_elems", ctypes.c_int64), ("stream_steps", ctypes.c_int64), ("jobs", ctypes.c_int64),
+                ("pipelined", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

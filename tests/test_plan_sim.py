@@ -75,10 +75,27 @@ def test_cross_plans(planner):
 
 @pytest.mark.parametrize("n,m,dim", [(131072, 131072, 3), (512, 384, 2), (5000, 5000, 2), (64 * 4 * 7, 2500, 2)])
 def test_single_pairs(planner, n, m, dim):
+    """Long single Frechet pairs go to the pipelined kernel (no job table):
+    one band of 64 R rows per wave, four waves per workgroup, one link row
+    per workgroup boundary; the job-table planner's own pair plans (R = 1,
+    where the pipelined kernel does not run) still pass the simulator."""
     sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, n], [0, m], dim)
-    plan_sim.check(sm, jobs, wj, (np.array([0, n]), np.array([0, m])), [0])
+    assert sm["pipelined"] == 1 and sm["jobs"] == 0
+    R = sm["rows_per_lane"]
+    shapes = []  # (bands, link values) with either curve holding the rows
+    for rows, cols in ((n, m), (m, n)):
+        bands = -(-rows // (64 * R))
+        shapes.append((bands, ((bands - 1) // 4) * (-(-cols // 64) * 64)))
+    assert any(sm["link_elems"] == le and (sm["waves"] >= nb or sm["waves"] == 1024) for nb, le in shapes)
     if n == 131072:
-        assert sm["rings"] == 1 and sm["waves"] == 512
+        assert R == 2 and sm["waves"] == 1024
+    ffd.ffd_set_tuning(planner, 1, 0)
+    try:
+        sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, n], [0, m], dim)
+    finally:
+        ffd.ffd_set_tuning(planner, 0, 0)
+    assert sm["pipelined"] == 0
+    plan_sim.check(sm, jobs, wj, (np.array([0, n]), np.array([0, m])), [0])
 
 
 @pytest.mark.parametrize("dtw,metric,lev", [(True, 1, False), (True, 0, False), (False, 2, False),
