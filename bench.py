@@ -639,39 +639,17 @@ def run_cross(args, torch, ffd, ctx, dev, stream):
     }
 
 
-def run_serving(args, torch, ffd, ctx, dev, stream):
-    """Queries against the resident 10,000-curve database: a closed-loop
-    burst measures the saturation rate S, then Poisson arrivals at a fixed
-    rate (default 0.5 S) give the latency percentiles and cells/s."""
+def serve_open_loop(srv, queries, rate, nwarm, nmeas, seed=7):
+    """Poisson arrivals at `rate`: nwarm requests, then the statistics are
+    reset and nmeas more follow; returns the server's statistics of the
+    requests completed after the reset (latency from submission to result
+    inside the server) and the wall time of the measured part."""
     import queue
     import threading
 
     import workloads
-    DB, dbo = workloads.serving_db()
-    db_points = int(dbo[-1])
-    DBd = torch.from_numpy(DB).to(dev)
-    db = ffd.Database(ctx, DBd, dbo)
-    srv = ffd.Server(db, max_slots=args.slots, max_query=8192)
-    nwarm, nsat, nopen = 16, args.sat_requests, args.requests
-    qs = workloads.serving_queries(count=nwarm + nsat + nopen)
-    for q in qs[:nwarm]:
-        srv.wait(srv.submit(q))
-    # saturation: every request submitted at once
-    sat = qs[nwarm:nwarm + nsat]
-    srv.reset_stats()
-    t0 = time.perf_counter()
-    tickets = [srv.submit(q) for q in sat]
-    for t in tickets:
-        srv.wait(t)
-    sat_s = time.perf_counter() - t0
-    sat_qps = nsat / sat_s
-    sat_cells = sum(len(q) for q in sat) * db_points / sat_s
-    sat_stats = srv.stats()
-    # open loop at a fixed rate
-    rate = args.qps if args.qps > 0 else 0.5 * sat_qps
-    arrivals = workloads.poisson_arrivals(count=nopen, rate=rate)
-    load = qs[nwarm + nsat:]
-    results = {}
+    total = nwarm + nmeas
+    arrivals = workloads.poisson_arrivals(seed=seed, count=total, rate=rate)
     pend = queue.Queue()
 
     def collect():
@@ -679,62 +657,116 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
             item = pend.get()
             if item is None:
                 return
-            i, t = item
-            results[i] = srv.wait(t)
+            srv.wait(item)
 
     th = threading.Thread(target=collect)
     th.start()
-    srv.reset_stats()
     t0 = time.perf_counter()
+    tm = None
     for i, ta in enumerate(arrivals):
+        if i == nwarm:
+            srv.reset_stats()
+            tm = time.perf_counter()
         while True:
             dt = t0 + ta - time.perf_counter()
             if dt <= 0:
                 break
             time.sleep(min(dt, 0.0005))
-        pend.put((i, srv.submit(load[i])))
+        pend.put(srv.submit(queries[i % len(queries)]))
     pend.put(None)
     th.join()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    errs = st["failed"]
+    wall = time.perf_counter() - (tm if tm is not None else t0)
+    return srv.stats(), wall
 
-    # parity of two served results against the oracle
+
+def serve_saturation(srv, queries, count):
+    """Closed loop: every request submitted at once; requests per second and
+    DP cells per second until the last result."""
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    tickets = [srv.submit(queries[i % len(queries)]) for i in range(count)]
+    for t in tickets:
+        srv.wait(t)
+    sec = time.perf_counter() - t0
+    return count / sec, srv.stats()
+
+
+def serving_session(torch, ffd, ctx, dev, slots, nsat, nwarm, nmeas, fractions, qps=0.0):
+    """The serving workload: a resident 10,000-curve database, a saturation
+    run, then open-loop runs at the given fractions of the saturation rate
+    (or at the absolute rate qps)."""
+    import workloads
+    DB, dbo = workloads.serving_db()
+    db_points = int(dbo[-1])
+    DBd = torch.from_numpy(DB).to(dev)
+    db = ffd.Database(ctx, DBd, dbo)
+    srv = ffd.Server(db, max_slots=slots, max_query=8192)
+    qs = workloads.serving_queries(count=4096)
+    for q in qs[:16]:
+        srv.wait(srv.submit(q))
+    sat_qps, sat_stats = serve_saturation(srv, qs, nsat)
+    print(f"serving: saturation {sat_qps:.0f} requests/s", file=sys.stderr, flush=True)
+    runs = []
+    rates = [qps] if qps > 0 else [f * sat_qps for f in fractions]
+    for k, rate in enumerate(rates):
+        st, wall = serve_open_loop(srv, qs, rate, nwarm, nmeas, seed=7 + k)
+        runs.append({"qps_target": rate, "fraction_of_saturation": rate / sat_qps, "qps_achieved": st["qps"],
+                     "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                     "max_ms": st["max_ms"], "completed": st["completed"], "failed": st["failed"],
+                     "deferred": st["deferred"], "cells_per_s": st["cells_per_s"], "wall_s": wall,
+                     "launches_by_rows_per_lane": dict(zip(range(1, 9), st["launches_by_rows"]))})
+        print(f"serving: {rate:.0f} requests/s: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+    info = {"saturation_qps": sat_qps, "saturation_cells_per_s": sat_stats["cells_per_s"],
+            "saturation_requests": nsat, "warmup_requests": nwarm, "measured_requests": nmeas,
+            "max_slots": slots, "waves": sat_stats["waves"], "requests_per_launch": sat_stats["requests_per_launch"],
+            "db_points": db_points, "runs": runs}
+    return info, srv, db, DB, dbo, qs
+
+
+def run_serving(args, torch, ffd, ctx, dev, stream):
+    """Queries against the resident 10,000-curve database: a closed-loop
+    burst measures the saturation rate S, then Poisson arrivals at 0.25 S,
+    0.5 S and 0.8 S (or at --qps) give the latency percentiles and cells/s,
+    each over --requests requests after --serving-warmup warm-up ones."""
     import oracle
+    import workloads
+    fr = [float(x) for x in args.fractions.split(",")]
+    info, srv, db, DB, dbo, qs = serving_session(torch, ffd, ctx, dev, args.slots, args.sat_requests,
+                                                 args.serving_warmup, args.requests, fr, args.qps)
+    # parity of two served results against the oracle
     pick = [0, 1]
-    sq, so = workloads.concat([load[i] for i in pick])
+    res = [srv.wait(srv.submit(qs[i])).copy() for i in pick]
+    sq, so = workloads.concat([qs[i] for i in pick])
     cores = cpu_cores()
     t2 = time.perf_counter()
     want = oracle.dfd_cross(sq, so, DB, dbo, oracle.EUCLIDEAN, nthreads=cores)
     cw = time.perf_counter() - t2
-    parity_ok = bool(all(np.all(np.abs(results[i] - want[r]) <= TOL * want[r]) for r, i in enumerate(pick)))
+    parity_ok = bool(all(np.all(np.abs(res[r] - want[r]) <= TOL * want[r]) for r in range(len(pick))))
+    db_points = info["db_points"]
     s_cells = int(np.sum(np.diff(so))) * db_points
     cpu = None if args.no_cpu else {
         "value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
-        "sample": f"2 of the open-loop queries ({int(np.sum(np.diff(so)))} points) against all 10,000 "
-                  f"database curves ({s_cells} cells), FP64 rolling-row oracle on {cores} threads, {cw:.2f} s"}
+        "sample": f"2 queries ({int(np.sum(np.diff(so)))} points) against all 10,000 database curves "
+                  f"({s_cells} cells), FP64 rolling-row oracle on {cores} threads, {cw:.2f} s"}
     srv.close()
     db.close()
-    cells_open = st["cells_per_s"]
-    info = {"rows_per_lane": "1 to 8, chosen per launch for its queries", "waves": st["waves"],
-            "requests_per_launch": st["requests_per_launch"],
-            "open_loop_launches_by_rows_per_lane": dict(zip(range(1, 9), st["launches_by_rows"]))}
+    head = min(info["runs"], key=lambda r: abs(r["fraction_of_saturation"] - 0.5))
+    sat = info["saturation_cells_per_s"]
+    launch = {"rows_per_lane": "1 to 8, chosen per request", "waves": info["waves"],
+              "requests_per_launch": info["requests_per_launch"]}
     return {
-        "value": cells_open, "ms_per_step": st["mean_ms"], "dtype": "f32",
+        "value": head["cells_per_s"], "ms_per_step": head["mean_ms"], "dtype": "f32",
         "config": {"workload": "serving: Poisson arrivals, each a query against a resident database of 10,000 "
                                "curves; lengths log-normal (median 300, sigma 1, clipped to [32, 8192]), 2-D "
                                "float32 random walks, Euclidean (seeds 5, 6, 7)",
-                   "requests": nopen, "db_points": db_points, "global_batch": nopen},
-        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "failed_requests": errs},
-        "serving": {"qps_target": rate, "qps_achieved": st["qps"], "p50_ms": st["p50_ms"],
-                    "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
-                    "deferred": st["deferred"], "open_loop_wall_s": wall,
-                    "saturation": {"requests": nsat, "qps": sat_qps, "cells_per_s": sat_cells,
-                                   "p50_ms": sat_stats["p50_ms"], "p99_ms": sat_stats["p99_ms"]},
-                    "max_slots": args.slots},
-        "roofline": {"bound": "alu", "achieved": sat_cells * imin(2) / 1e12, "peak": PEAK_VALU / 1e12,
-                     "unit": "TVALUop/s", "frac": sat_cells * imin(2) / PEAK_VALU, "traffic": None,
-                     "kernel": "ffd::stream_kernel<R, 2, float>", "kernel_ms": None, "launch": info,
+                   "requests": args.requests, "db_points": db_points, "global_batch": args.requests},
+        "parity": {"tolerance": TOL, "sampled_ok": parity_ok,
+                   "failed_requests": sum(r["failed"] for r in info["runs"])},
+        "serving": info,
+        "roofline": {"bound": "alu", "achieved": sat * imin(2) / 1e12, "peak": PEAK_VALU / 1e12,
+                     "unit": "TVALUop/s", "frac": sat * imin(2) / PEAK_VALU, "traffic": None,
+                     "kernel": "ffd::stream_kernel<R, 2, float>", "kernel_ms": None, "launch": launch,
                      "basis": "saturation cells/s over the closed-loop burst (host overhead included)"},
         "cpu_baseline": cpu,
     }
@@ -748,9 +780,14 @@ def main():
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
                                            "geo", "geo_dtw", "knn", "decide"],
                     default="batched")
-    ap.add_argument("--requests", type=int, default=2000, help="open-loop requests (serving)")
-    ap.add_argument("--sat-requests", type=int, default=256, help="closed-loop burst size (serving)")
-    ap.add_argument("--qps", type=float, default=0.0, help="open-loop arrival rate; 0 = half the saturation rate")
+    ap.add_argument("--requests", type=int, default=20000, help="measured open-loop requests per rate (serving)")
+    ap.add_argument("--serving-warmup", type=int, default=2000, help="open-loop warm-up requests per rate (serving)")
+    ap.add_argument("--sat-requests", type=int, default=2000, help="closed-loop burst size (serving)")
+    ap.add_argument("--fractions", default="0.25,0.5,0.8",
+                    help="open-loop rates as fractions of the saturation rate (serving workload)")
+    ap.add_argument("--qps", type=float, default=0.0, help="open-loop arrival rate; 0 = the fractions above")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="batched workload: skip the serving block (saturation and p50/p99 at half of it)")
     ap.add_argument("--slots", type=int, default=16, help="requests in flight (serving)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-pair comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -784,6 +821,21 @@ def main():
     stream = torch.cuda.current_stream()
     if args.workload == "batched":
         r = run_batched(args, torch, ffd, ctx, dev, stream)
+        if not args.no_serving:
+            # the latency half of the metric: p50/p99 at half the saturation rate
+            info, srv, db, _, _, _ = serving_session(torch, ffd, ctx, dev, args.slots, args.sat_requests,
+                                                     args.serving_warmup, args.requests, [0.5])
+            srv.close()
+            db.close()
+            run = info["runs"][0]
+            r["serving"] = {"workload": "10,000-curve resident database, log-normal query lengths (median 300, "
+                                        "sigma 1, [32, 8192]), Poisson arrivals at half the saturation rate",
+                            "saturation_qps": info["saturation_qps"],
+                            "saturation_cells_per_s": info["saturation_cells_per_s"],
+                            "qps": run["qps_achieved"], "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"],
+                            "mean_ms": run["mean_ms"], "cells_per_s": run["cells_per_s"],
+                            "requests": run["completed"], "warmup_requests": info["warmup_requests"],
+                            "failed": run["failed"]}
     elif args.workload == "cross":
         r = run_cross(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "serving":

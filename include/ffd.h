@@ -371,7 +371,9 @@ int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info);
  * a wavefront gave up waiting for a boundary row from another wavefront
  * (possible only when other work occupies the GPU so long that the
  * producing wavefront cannot start).  Results of such a launch are not
- * valid.  0 for launches that use no workspace.
+ * valid: a wavefront that abandons a wait stores every later result as NaN
+ * (float results) or -1 (int64 results), and waits no more.  0 for
+ * launches that use no workspace.
  * Errors: FFD_E_INVALID (NULL), FFD_E_DEVICE. */
 int ffd_last_errors(ffd_ctx *ctx, int32_t *flags);
 

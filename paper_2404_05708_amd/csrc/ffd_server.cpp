@@ -11,12 +11,25 @@
 // ("tick") runs the jobs of every request admitted with it, one chunk per
 // wave, with no planning beyond filling in the job table.
 //
-// A worker thread admits queued requests into free ticks as soon as a tick
-// and its arena region are free, uploads the queries and jobs, launches on
-// the tick's own stream, and collects results when the tick's event
-// completes; ticks on different streams overlap on the device.  The arena
-// (caller device memory) holds the reordered database and the regions of
-// the ticks; the library allocates no device memory for serving.
+// A request is swept in "items" of at most a few bands of its query rows
+// (about four bands of 512 rows' worth of work), so that no launch holds
+// the GPU for the whole of a long query and short queries that arrive
+// meanwhile run between its items.  Between two items the bottom rows of
+// the last band swept (one row per database curve) wait in a pair of
+// boundary-row buffers of the request in the arena; a request needs them,
+// and is admitted, only when a buffer pair is free (admission by the
+// device memory the request needs; requests that fit one item need none).
+// The next item of a request keeps the request's arrival position, so a
+// long query is not passed over by later ones.
+//
+// A worker thread admits queued requests as soon as a slot and the memory
+// they need are free, forms a tick from the items of admitted requests
+// when a tick is free, uploads the queries and jobs, launches on the
+// tick's own stream, and collects results when the tick's event completes;
+// ticks on different streams overlap on the device.  The arena (caller
+// device memory) holds the reordered database, the regions of the ticks
+// and the boundary-row buffers; the library allocates no device memory for
+// serving.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -50,7 +63,13 @@ namespace {
 constexpr int kServeR = 8;       // most rows per lane of a tick
 constexpr int kServeRMulti = 3;  // fewest rows per lane of a tick whose queries span several bands
 constexpr int kServeW = 2;       // LDS share of a wave: 1 / (4 kServeW) of a CU
-constexpr int kTicks = 4;        // launches in flight
+#ifndef FFD_SERVE_TICKS
+#define FFD_SERVE_TICKS 4
+#endif
+#ifndef FFD_SERVE_ITEM_BANDS
+#define FFD_SERVE_ITEM_BANDS 4
+#endif
+constexpr int kTicks = FFD_SERVE_TICKS;  // launches in flight
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -71,7 +90,19 @@ struct Request {
   int32_t metric = 0;
   float *out = nullptr;
   double t_submit = 0, t_done = 0;
-  int state = 0;  // 0 queued, 1 running, 2 done, < 0 error status
+  int state = 0;      // 0 queued, 1 ready for its next item, 3 item in flight, 2 done, < 0 error status
+  int R = 0;          // rows per lane of its items (fixed once an item ran)
+  int64_t nb = 0;     // bands at R
+  int64_t next_band = 0;
+  int32_t link = -1;  // boundary-row buffer pair (multi-item requests)
+  int link_cur = 0;   // which buffer of the pair holds the rows of band next_band - 1
+};
+
+// One item of a tick: bands [b0, b0 + c) of a request's query.
+struct Item {
+  Request *r = nullptr;
+  int64_t b0 = 0, c = 0;
+  bool last = false;  // the query's last band is in this item (results)
 };
 
 // Byte layout of one tick's region; the same offsets are used in its pinned
@@ -88,9 +119,13 @@ struct Tick {
   unsigned char *pin = nullptr;   // pinned upload mirror
   float *pin_out = nullptr;       // pinned results
   uint64_t *pin_err = nullptr;
-  std::vector<Request *> reqs;
+  std::vector<Item> items;
   uint32_t epoch = 0;
 };
+
+constexpr int kFlagDone = 0;   // flag of every link written by an earlier launch: preset complete
+constexpr int kFlagSink = 1;   // flag the last band of an item publishes to (nobody waits on it)
+constexpr int kFlagFirst = 2;  // flags of links inside a launch
 
 }  // namespace
 
@@ -110,6 +145,12 @@ struct ffd_server {
   std::vector<int32_t> perm;      // chunk-order position -> original curve index
   std::vector<int32_t> long_chunks;  // chunks whose longest task exceeds hcap
   int64_t long_sumL = 0;          // sum of their chained band lengths
+  std::vector<int64_t> chunk_link;  // offset of each chunk's boundary rows in a row buffer
+  int64_t link_row = 0;           // values of a boundary-row buffer (all chunks, chained lengths)
+  int link_pairs = 0;             // boundary-row buffer pairs in the arena
+  std::vector<int32_t> free_links;
+  unsigned char *arena = nullptr;
+  size_t links_at = 0;            // arena offset of the boundary-row buffers
   int64_t db_points = 0;
   const float *dbx = nullptr;     // reordered coordinates (arena)
   const int64_t *dbo = nullptr;   // their offsets (arena)
@@ -124,7 +165,9 @@ struct ffd_server {
   // requests
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Request *> pending;
+  int max_slots = 1;
+  std::deque<Request *> pending;  // submitted, not admitted (arrival order)
+  std::deque<Request *> active;   // admitted, not finished (arrival order)
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -164,6 +207,12 @@ TickLayout tick_layout(const ffd_server &s) {
 
 size_t db_bytes(const ffd_server &s) {
   return al256((size_t)s.db_points * s.dim * sizeof(float)) + al256((size_t)(s.db->ndb + 1) * sizeof(int64_t));
+}
+
+size_t link_pair_bytes(const ffd_server &s) { return al256((size_t)2 * s.link_row * sizeof(float)); }
+
+size_t arena_total(const ffd_server &s) {
+  return db_bytes(s) + (size_t)kTicks * s.lay.total + (size_t)s.link_pairs * link_pair_bytes(s);
 }
 
 // Shape of the launches and the chunk order of the database.
@@ -222,10 +271,31 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
   }
   int64_t max_nb = ffd::bands_for(max_query, kServeRMulti);
   s.jobs_cap = (size_t)s.kmax * (size_t)job_count_bound(s);
-  s.flags_cap = (size_t)s.kmax * s.long_chunks.size() * (size_t)std::max<int64_t>(max_nb - 1, 0);
+  s.flags_cap = kFlagFirst + (size_t)s.kmax * s.long_chunks.size() * (size_t)std::max<int64_t>(max_nb - 1, 0);
   s.links_cap = (size_t)s.kmax * (size_t)s.long_sumL;
   s.lay = tick_layout(s);
+  // boundary-row buffers of multi-item requests: one row per database curve
+  // (chained task lengths), chunk after chunk; a pair per request
+  s.chunk_link.assign(s.nwaves, 0);
+  int64_t o = 0;
+  for (int32_t c = 0; c < s.nwaves; ++c) {
+    s.chunk_link[c] = o;
+    o += s.chunks[c].sumL[1];
+  }
+  s.link_row = (o + 63) / 64 * 64;
+  s.max_slots = max_slots;
+  s.link_pairs = std::max(1, std::min(max_slots, 64));
   return FFD_OK;
+}
+
+void release_link(ffd_server &s, Request *r) {
+  if (r->link >= 0) s.free_links.push_back(r->link);
+  r->link = -1;
+}
+
+void drop_active(ffd_server &s, Request *r) {
+  auto it = std::find(s.active.begin(), s.active.end(), r);
+  if (it != s.active.end()) s.active.erase(it);
 }
 
 void finish_tick(ffd_server &s, Tick &t) {
@@ -234,11 +304,18 @@ void finish_tick(ffd_server &s, Tick &t) {
   uint64_t e = *t.pin_err;
   if (e != 0 && (uint32_t)(e >> 32) == t.epoch) bad = true;
   double tn = now_s();
-  for (size_t i = 0; i < t.reqs.size(); ++i) {
-    Request *r = t.reqs[i];
+  for (size_t i = 0; i < t.items.size(); ++i) {
+    const Item &it = t.items[i];
+    Request *r = it.r;
     if (bad) {
       r->state = FFD_E_DEVICE;
       s.failed++;
+    } else if (!it.last) {
+      // more bands to sweep: the rows just written are in the other buffer
+      r->next_band = it.b0 + it.c;
+      r->link_cur ^= 1;
+      r->state = 1;
+      continue;
     } else {
       const float *src = t.pin_out + i * (size_t)ndb;
       for (int64_t p = 0; p < ndb; ++p) r->out[s.perm[p]] = src[p];
@@ -249,18 +326,22 @@ void finish_tick(ffd_server &s, Tick &t) {
       s.t_last = tn;
     }
     r->t_done = tn;
+    release_link(s, r);
+    drop_active(s, r);
   }
-  t.reqs.clear();
+  t.items.clear();
   t.busy = false;
   s.cv_done.notify_all();
 }
 
 void fail_tick(ffd_server &s, Tick &t, int code) {
-  for (Request *r : t.reqs) {
-    r->state = code;
+  for (const Item &it : t.items) {
+    it.r->state = code;
     s.failed++;
+    release_link(s, it.r);
+    drop_active(s, it.r);
   }
-  t.reqs.clear();
+  t.items.clear();
   t.busy = false;
   s.cv_done.notify_all();
 }
@@ -311,66 +392,118 @@ int query_rows(const ffd_server &s, int64_t n) {
 // factor more than its own best R.
 constexpr double kServeSlack = 1.10;
 
-// Admit queued requests into tick t and launch it.  Called with the lock held.
+// Bands of one item at R rows per lane: about four bands of kServeR rows'
+// worth of work (a band sweeps every database curve once).
+int64_t item_bands(const ffd_server &s, int R) {
+  double cap = (double)FFD_SERVE_ITEM_BANDS * step_clocks(kServeR, s.dim, false, kServeW);
+  return std::max<int64_t>(1, (int64_t)(cap / step_clocks(R, s.dim, false, kServeW)));
+}
+
+// Whether request r needs boundary-row buffers (more than one item).
+bool multi_item(const ffd_server &s, const Request &r) { return r.nb > item_bands(s, r.R); }
+
+// Form tick t from the items of ready requests and launch it.  Called with
+// the lock held; at least one admitted request is ready.
 int launch_tick(ffd_server &s, Tick &t) {
   const TickLayout &L = s.lay;
   const int64_t ndb = s.db->ndb;
-  // requests: the oldest one, then, from the next few in arrival order,
-  // those with the same metric that suit its rows per lane, within the
-  // tick's capacity (no request is passed over by more than 4 kmax later
-  // ones)
-  int32_t metric = s.pending.front()->metric;
-  const int Rt = query_rows(s, s.pending.front()->n);
-  int64_t pts = 0;
-  const size_t window = (size_t)4 * s.kmax;
-  for (size_t i = 0; i < s.pending.size() && i < window && (int)t.reqs.size() < s.kmax;) {
-    Request *r = s.pending[i];
-    if (r->metric != metric || pts + r->n > s.qcap ||
-        query_cost(s, r->n, Rt) > kServeSlack * query_cost(s, r->n, query_rows(s, r->n))) {
-      ++i;
-      continue;
+  // the oldest ready request sets the metric and the rows per lane; later
+  // ones join if they suit them (a request with bands already swept only
+  // at its own R; a fresh one at another R within the slack when all its
+  // bands fit this item)
+  Request *first = nullptr;
+  for (Request *r : s.active)
+    if (r->state == 1) {
+      first = r;
+      break;
     }
+  if (!first) return FFD_OK;
+  const int32_t metric = first->metric;
+  const int Rt = first->R;
+  const int64_t cap = item_bands(s, Rt);
+  int64_t pts = 0;
+  for (Request *r : s.active) {
+    if ((int)t.items.size() >= s.kmax) break;
+    if (r->state != 1 || r->metric != metric || pts + r->n > s.qcap) continue;
+    Item it;
+    it.r = r;
+    if (r->R == Rt) {
+      it.b0 = r->next_band;
+      it.c = std::min(r->nb - r->next_band, cap);
+    } else {
+      int64_t nbt = ffd::bands_for(r->n, Rt);
+      if (r->next_band > 0 || nbt > cap ||
+          query_cost(s, r->n, Rt) > kServeSlack * query_cost(s, r->n, r->R))
+        continue;
+      r->R = Rt;  // runs whole in this tick
+      r->nb = nbt;
+      it.b0 = 0;
+      it.c = nbt;
+    }
+    it.last = it.b0 + it.c == r->nb;
     pts += r->n;
-    t.reqs.push_back(r);
-    s.pending.erase(s.pending.begin() + (std::ptrdiff_t)i);
-    r->state = 1;
+    r->state = 3;
+    t.items.push_back(it);
   }
-  const int k = (int)t.reqs.size();
+  const int k = (int)t.items.size();
   unsigned char *h = t.pin;
   // queries and their offsets
   float *hq = reinterpret_cast<float *>(h + L.q);
   int64_t *hqo = reinterpret_cast<int64_t *>(h + L.qo);
   hqo[0] = 0;
   for (int i = 0; i < k; ++i) {
-    memcpy(hq + hqo[i] * s.dim, t.reqs[i]->q.data(), t.reqs[i]->q.size() * sizeof(float));
-    hqo[i + 1] = hqo[i] + t.reqs[i]->n;
+    const Request *r = t.items[i].r;
+    memcpy(hq + hqo[i] * s.dim, r->q.data(), r->q.size() * sizeof(float));
+    hqo[i + 1] = hqo[i] + r->n;
   }
-  // jobs, wave by wave: the chunk of wave w against every query of the tick
+  // jobs, wave by wave: the chunk of wave w against every item of the tick.
+  // Link offsets count floats from the arena's start (a.links is the arena).
+  const int64_t tick_links = (int64_t)((t.dev + L.links - s.arena) / sizeof(float));
   Job *hj = reinterpret_cast<Job *>(h + L.jobs);
   int32_t *hwj = reinterpret_cast<int32_t *>(h + L.wj);
   size_t nj = 0;
-  int32_t nflags = 0;
+  int32_t nflags = kFlagFirst;
   int64_t nlinks = 0, max_steps = 0;
-  bool multi = false;  // some query spans several bands
-  for (int i = 0; i < k; ++i) multi = multi || ffd::bands_for(t.reqs[i]->n, Rt) > 1;
+  bool chained = false;  // some item hands a band's bottom row on inside a wave
+  for (int i = 0; i < k; ++i) chained = chained || t.items[i].c > 1;
   for (int w = 0; w < s.nwaves; ++w) {
     hwj[w] = (int32_t)nj;
     const Chunk &ch = s.chunks[w];
     int64_t steps = 0;
     for (int i = 0; i < k; ++i) {
-      int64_t nb = ffd::bands_for(t.reqs[i]->n, Rt);
+      const Item &it = t.items[i];
+      const Request *r = it.r;
+      // the request's boundary rows: read from buffer link_cur, written to the other
+      int64_t lin = -1, lout = -1;
+      if (r->link >= 0) {
+        int64_t pair = (int64_t)((s.links_at + (size_t)r->link * link_pair_bytes(s)) / sizeof(float));
+        lin = pair + (int64_t)r->link_cur * s.link_row + s.chunk_link[w];
+        lout = pair + (int64_t)(r->link_cur ^ 1) * s.link_row + s.chunk_link[w];
+      }
+      const bool from_link = it.b0 > 0, to_link = !it.last;
       Job jb = band_job(i, ch, ndb);
-      int64_t sumL = ch.sumL[nb > 1 ? 1 : 0];
-      if (nb == 1 || ch.maxL <= s.hcap) {
+      int64_t sumL = ch.sumL[r->nb > 1 ? 1 : 0];
+      if (it.c == 1 || ch.maxL <= s.hcap) {
+        // the item's bands chained through LDS on this wave
+        jb.band_first = (int32_t)it.b0;
+        jb.band_count = (int32_t)it.c;
+        if (from_link) {
+          jb.link_in = lin;
+          jb.flag_in = kFlagDone;
+        }
+        if (to_link) {
+          jb.link_out = lout;
+          jb.flag_out = kFlagSink;
+        }
         hj[nj++] = jb;
-        steps += nb * sumL;
+        steps += it.c * sumL;
         continue;
       }
-      // the chunk's boundary row does not fit LDS: the query's bands run in
-      // order on this wave and pass the row on in place in the arena
+      // the chunk's boundary row does not fit LDS: the item's bands run in
+      // order on this wave and pass the row on in place in the tick's region
       int64_t gap = self_gap(sumL);
-      for (int64_t b = 0; b < nb; ++b) {
-        if (b > 0 && gap > 0) {
+      for (int64_t b = it.b0; b < it.b0 + it.c; ++b) {
+        if (b > it.b0 && gap > 0) {
           Job idle;
           memset(&idle, 0, sizeof idle);
           idle.row_sel = ffd::kRowIdle;
@@ -383,14 +516,25 @@ int launch_tick(ffd_server &s, Tick &t) {
         Job bj = jb;
         bj.band_first = (int32_t)b;
         bj.band_count = 1;
-        bj.link_in = b > 0 ? nlinks : -1;
-        bj.flag_in = b > 0 ? nflags + (int32_t)b - 1 : -1;
-        bj.link_out = b + 1 < nb ? nlinks : -1;
-        bj.flag_out = b + 1 < nb ? nflags + (int32_t)b : -1;
+        int32_t fl = nflags + (int32_t)(b - it.b0);
+        if (b > it.b0) {
+          bj.link_in = tick_links + nlinks;
+          bj.flag_in = fl - 1;
+        } else if (from_link) {
+          bj.link_in = lin;
+          bj.flag_in = kFlagDone;
+        }
+        if (b + 1 < it.b0 + it.c) {
+          bj.link_out = tick_links + nlinks;
+          bj.flag_out = fl;
+        } else if (to_link) {
+          bj.link_out = lout;
+          bj.flag_out = kFlagSink;
+        }
         hj[nj++] = bj;
         steps += sumL;
       }
-      nflags += (int32_t)(nb - 1);
+      nflags += (int32_t)(it.c - 1);
       nlinks += sumL;
     }
     max_steps = std::max(max_steps, steps);
@@ -398,6 +542,8 @@ int launch_tick(ffd_server &s, Tick &t) {
   hwj[s.nwaves] = (int32_t)nj;
   memset(h + L.flags, 0, L.upload - L.flags);  // flags and error word
   t.epoch = ++s.epoch;
+  // links written by an earlier launch are complete: their flag says so
+  reinterpret_cast<uint64_t *>(h + L.flags)[kFlagDone] = ffd::flag_word(t.epoch, 0xFFFFFFFFu);
 
   hipError_t e = hipMemcpyAsync(t.dev, h, L.upload, hipMemcpyHostToDevice, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
@@ -412,15 +558,15 @@ int launch_tick(ffd_server &s, Tick &t) {
   a.out = t.dev + L.out;
   a.nwaves = s.nwaves;
   a.metric = metric;
-  // a tick of single-band queries hands no row on inside a wave (its
-  // tasks read the ghost row and write to the sink), so its waves take no
-  // hand-off row in LDS and more of them fit a CU, also from the other
-  // launches in flight
-  a.hcap = multi ? (int32_t)s.hcap : 0;
-  a.lds_per_wave = multi ? s.lds_rows[Rt] : s.lds_rows1[Rt];
+  // a tick whose items sweep one band each hands no row on inside a wave
+  // (its tasks read the ghost row or a link and write to the sink or a
+  // link), so its waves take no hand-off row in LDS and more of them fit a
+  // CU, also from the other launches in flight
+  a.hcap = chained ? (int32_t)s.hcap : 0;
+  a.lds_per_wave = chained ? s.lds_rows[Rt] : s.lds_rows1[Rt];
   a.max_steps = (int32_t)(max_steps + 4 * ffd::kRing);
   a.epoch = t.epoch;
-  a.links = t.dev + L.links;
+  a.links = s.arena;
   a.flags = reinterpret_cast<uint64_t *>(t.dev + L.flags);
   a.err = reinterpret_cast<uint64_t *>(t.dev + L.err);
   e = ffd::launch_stream(false, Rt, s.dim, a, s.wpb, false, t.stream);
@@ -434,6 +580,33 @@ int launch_tick(ffd_server &s, Tick &t) {
   if (e != hipSuccess) return FFD_E_DEVICE;
   t.busy = true;
   return FFD_OK;
+}
+
+// Admit queued requests in arrival order while slots are free; a request
+// that needs boundary-row buffers waits for a free pair (later requests
+// that need none may pass it).  Called with the lock held.
+void admit(ffd_server &s) {
+  for (auto it = s.pending.begin(); it != s.pending.end() && (int)s.active.size() < s.max_slots;) {
+    Request *r = *it;
+    if (multi_item(s, *r)) {
+      if (s.free_links.empty()) {
+        ++it;
+        continue;
+      }
+      r->link = s.free_links.back();
+      s.free_links.pop_back();
+      r->link_cur = 0;
+    }
+    r->state = 1;
+    s.active.push_back(r);
+    it = s.pending.erase(it);
+  }
+}
+
+bool any_ready(const ffd_server &s) {
+  for (const Request *r : s.active)
+    if (r->state == 1) return true;
+  return false;
 }
 
 void worker_loop(ffd_server *s) {
@@ -454,10 +627,11 @@ void worker_loop(ffd_server *s) {
         busy = true;
       }
     }
-    while (!s->pending.empty()) {
+    admit(*s);
+    while (any_ready(*s)) {
       Tick *free_tick = nullptr;
       for (Tick &t : s->ticks)
-        if (!t.busy && t.reqs.empty()) {
+        if (!t.busy && t.items.empty()) {
           free_tick = &t;
           break;
         }
@@ -467,7 +641,7 @@ void worker_loop(ffd_server *s) {
       progressed = true;
       busy = true;
     }
-    if (s->stop && s->pending.empty() && !busy) break;
+    if (s->stop && s->pending.empty() && s->active.empty() && !busy) break;
     if (!progressed) {
       if (busy) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
       else s->cv_work.wait(lk);
@@ -542,7 +716,7 @@ int ffd_server_arena_size(ffd_db *db, int32_t max_slots, int64_t max_query, size
   ffd_server s;
   int rc = make_server(db, max_slots, max_query, &s);
   if (rc) return rc;
-  *bytes = db_bytes(s) + (size_t)kTicks * s.lay.total;
+  *bytes = arena_total(s);
   return FFD_OK;
 }
 
@@ -592,6 +766,9 @@ int ffd_server_create(ffd_db *db, void *arena, size_t arena_bytes, int32_t max_s
   }
   s->dbx = dbx;
   s->dbo = dbo;
+  s->arena = A;
+  s->links_at = db_bytes(*s) + (size_t)kTicks * s->lay.total;
+  for (int i = s->link_pairs - 1; i >= 0; --i) s->free_links.push_back(i);
   // ticks
   size_t base = db_bytes(*s);
   for (int i = 0; i < kTicks; ++i) {
@@ -631,6 +808,8 @@ int ffd_server_submit(ffd_server *s, const float *q, int64_t n, int32_t metric, 
   r->q.assign(q, q + n * s->dim);
   r->n = n;
   r->metric = metric;
+  r->R = query_rows(*s, n);
+  r->nb = ffd::bands_for(n, r->R);
   r->out = out;
   r->t_submit = now_s();
   {
@@ -641,7 +820,7 @@ int ffd_server_submit(ffd_server *s, const float *q, int64_t n, int32_t metric, 
     if (slot_free) {
       slot_free = false;
       for (Tick &t : s->ticks)
-        if (!t.busy && t.reqs.empty()) slot_free = true;
+        if (!t.busy && t.items.empty()) slot_free = true;
     }
     if (!slot_free) s->deferred++;
     if (s->submitted == 0) s->t_first = r->t_submit;

@@ -96,6 +96,8 @@ struct Num<float> {
   __device__ static __forceinline__ void store_value(void *out, int64_t idx, float v) {
     static_cast<float *>(out)[idx] = v;
   }
+  // the result of a pair whose wave abandoned a wait: NaN
+  __device__ static __forceinline__ float poison() { return __builtin_nanf(""); }
 };
 
 template <>
@@ -121,6 +123,8 @@ struct Num<double> {
   __device__ static __forceinline__ void store_value(void *out, int64_t idx, double v) {
     static_cast<int64_t *>(out)[idx] = (int64_t)v;
   }
+  // the result of a pair whose wave abandoned a wait: -1 (no distance is negative)
+  __device__ static __forceinline__ double poison() { return -1.0; }
 };
 
 // Task descriptor kept in LDS (64 bytes).
@@ -414,6 +418,7 @@ struct Stream {
   // Agent-scope polling of the count; the row itself is then read with
   // agent-scope loads (see flush_links).
   __device__ void wait_link(int32_t flag, uint32_t need) {
+    if (err) return;  // after an abandoned wait the wave waits no more (its results are poisoned)
     uint64_t want = flag_word(a.epoch, need);
     uint64_t *fl = a.flags + flag;
     for (int it = 0;; ++it) {
@@ -735,6 +740,7 @@ struct Stream {
 
   // Spin (bounded) until *c >= need; workgroup-scope acquire.
   __device__ void wait_ctr(int32_t *c, int32_t need) {
+    if (err) return;
     for (int it = 0;; ++it) {
       if (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= need) break;
       if (it == kSpinLimit) {
@@ -913,24 +919,26 @@ struct Stream {
                          __HIP_MEMORY_SCOPE_WORKGROUP);
     if constexpr (LEV) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
-        static_cast<int64_t *>(a.out)[out63] = (int64_t)cap;
+        static_cast<int64_t *>(a.out)[out63] = err ? (int64_t)-1 : (int64_t)cap;
     } else if constexpr (CAP && HAV) {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
-        static_cast<float *>(a.out)[out63] = (float)cap;
+        static_cast<float *>(a.out)[out63] = err ? __builtin_nanf("") : (float)cap;
     } else if constexpr (CAP) {
-      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63) N::store_value(a.out, out63, cap);
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == ls63)
+        N::store_value(a.out, out63, err ? N::poison() : cap);
     } else if constexpr (HAV) {
       // the central angle of the selected squared chord, in FP64, rounded
       // once to FP32 (the chord is clamped at the diameter)
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) {
         double h = 0.5 * __builtin_sqrt((double)res);
-        static_cast<float *>(a.out)[out63] = (float)(2.0 * asin(h < 1.0 ? h : 1.0));
+        static_cast<float *>(a.out)[out63] = err ? __builtin_nanf("") : (float)(2.0 * asin(h < 1.0 ? h : 1.0));
       }
     } else if constexpr (CELL != 0) {
-      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1) N::store_value(a.out, out63, res);
+      if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
+        N::store_value(a.out, out63, err ? N::poison() : res);
     } else {
       if (t0 + kGroup - kWave == S63 + L63 && out63 >= 0 && lane == kWave - 1)
-        N::store(a.out, out63, res, a.metric);
+        N::store(a.out, out63, err ? N::poison() : res, a.metric);
     }
     return true;
   }
