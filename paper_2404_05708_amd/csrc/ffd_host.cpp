@@ -613,14 +613,16 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
 // A single long pair on the pipelined kernel (ffd_pipe.h): one band of 64 R
 // rows per wave, four waves per workgroup in lockstep (kPipeLag groups of
 // 16 steps apart), workgroups chained through link rows in global memory.
-// Modelled stream steps: the last band starts about 108 steps per band
-// after the first (6 groups inside a workgroup, about 9 between
-// workgroups), or, with several passes, when its wave has swept its
-// earlier bands; each band sweeps the columns plus the lanes' ramp and
-// the link flush.  Clocks per step: one instruction per 4 clocks (one wave
-// per SIMD issues alone), R cells of 2 D + 2 instructions (FP64: 2 D + 3)
-// and about 7 per step of lane shift, LDS traffic and bookkeeping.
-constexpr double kPipeBandLag = (3 * ffd::kPipeLag * ffd::kPipeGroup + 144) / 4.0;
+// Modelled stream steps: the last band starts about 84 steps per band
+// after the first (5 groups inside a workgroup, about 6 between
+// workgroups: lane 63 stores a column by 3 steps after it computes it, and
+// the next workgroup polls a group's link values one group before it
+// needs them), or, with several passes, when its wave has swept its
+// earlier bands; each band sweeps the columns plus the lanes' ramp.
+// Clocks per step: one instruction per 4 clocks (one wave per SIMD issues
+// alone), R cells of 2 D + 2 instructions (FP64: 2 D + 3) and about 7 per
+// step of lane shift, LDS traffic and bookkeeping.
+constexpr double kPipeBandLag = (3 * ffd::kPipeLag * ffd::kPipeGroup + 6 * ffd::kPipeGroup) / 4.0;
 
 double pipe_step_clocks(int R, int D, bool exact) {
   return 4.0 * (R * (2 * D + 2 + (exact ? 1 : 0)) + 7 + (exact ? 2 : 0));
@@ -657,7 +659,7 @@ bool build_pipe(ffd_ctx *ctx, int64_t rows, int64_t cols, int R, int D, bool exa
   }
   const int64_t W = nwg * ffd::kPipeWaves;
   const int64_t passes = (nb + W - 1) / W;
-  const double sweep = (double)cols + 64.0 + 5.0 * ffd::kPipeGroup;
+  const double sweep = (double)((cols + 66 + ffd::kPipeGroup - 1) / ffd::kPipeGroup * ffd::kPipeGroup);
   const double chain = (double)(nb - 1) * kPipeBandLag;
   const double wrap = (double)(passes - 1) * sweep + (double)((nb - 1) % W) * kPipeBandLag;
   const double steps = std::max(chain, wrap) + sweep;
@@ -736,7 +738,10 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
   if (rc) return rc;
   // the Frechet distance on squared cells may run on the pipelined kernel,
   // either curve holding the rows, when the model says it is faster
+  // (waves_per_simd = -1 asks for it whenever it can run the pair)
   if (ctx->measure != 0 || share < 0 || ctx->tune_W > 0) return FFD_OK;
+  const bool force = ctx->tune_W < 0;
+  double best_pipe = -1;
   for (int R : {2, 4}) {
     if (ctx->tune_R && R != ctx->tune_R) continue;
     for (int swap = 0; swap < 2; ++swap) {
@@ -744,8 +749,8 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
       double pc = 0;
       if (!build_pipe(ctx, swap ? m : n, swap ? n : m, R, D, exact, pp, pc)) continue;
       pp.pipe_swap = swap != 0;
-      if (pc < cost) {
-        cost = pc;
+      if ((force && (best_pipe < 0 || pc < best_pipe)) || (!force && pc < cost)) {
+        best_pipe = cost = pc;
         pl = std::move(pp);
       }
     }
@@ -1391,7 +1396,8 @@ int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd) 
   if (!ctx) return FFD_E_INVALID;
   if (rows_per_lane != 0 && rows_per_lane != 1 && rows_per_lane != 2 && rows_per_lane != 4 && rows_per_lane != 8)
     return fail(ctx, FFD_E_INVALID, "rows_per_lane must be 0, 1, 2, 4 or 8");
-  if (waves_per_simd < 0 || waves_per_simd > 8) return fail(ctx, FFD_E_INVALID, "waves_per_simd must be 0..8");
+  if (waves_per_simd < -1 || waves_per_simd > 8)
+    return fail(ctx, FFD_E_INVALID, "waves_per_simd must be -1 .. 8");
   ctx->tune_R = rows_per_lane;
   ctx->tune_W = waves_per_simd;
   return FFD_OK;

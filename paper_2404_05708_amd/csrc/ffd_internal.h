@@ -11,6 +11,7 @@
 
 #include "ffd.h"
 #include "ffd_plan.h"
+#include "ffd_pipe_args.h"
 
 namespace ffd {
 hipError_t launch_stream_plain(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st);

@@ -9,25 +9,29 @@
 // wave sweeps its band once, from the first column to the last.
 //
 // Bands follow each other down the rows.  Band b + 1 needs band b's bottom
-// row; lane 63 of band b produces column j at step j + 63.  Four waves of a
+// row; lane 63 of band b produces column j at step j + 63 and writes it, in
+// batches of four columns, to a ring in LDS by step j + 66.  Four waves of a
 // workgroup (one per SIMD of the compute unit) hold four consecutive bands
 // and run in lockstep, one 16-step group per barrier phase, each wave
-// kPipeLag groups behind the one above it; the bottom row goes from one
-// wave to the next through a ring in LDS, written in batches of four
-// columns.  The column points go through one ring of the workgroup, filled
-// by the first wave (the one furthest ahead) 16 columns per group, so that
-// the other waves issue no global loads at all and every global load is
-// waited for a whole group after it was issued.  The bottom row of a workgroup's last band goes to global
-// memory ("link" rows, one value per column, initialised to the all-ones
-// pattern, a NaN that no table value takes: every value of the table is a
-// squared distance or +inf); the first wave of the next workgroup polls the
-// values themselves, so neither side needs a flag or a fence.  Workgroups
-// form one chain in an order that keeps consecutive workgroups on the same
-// XCD (the hardware deals workgroups to the eight XCDs in turn), so a link
-// stays inside one L2 except at the seven XCD boundaries.  A pair with more
-// bands than waves runs in passes: the wave of chain position c takes bands
-// c, c + W, c + 2 W, ...; the band after a pass's last one reads its link
-// like any other.
+// kPipeLag groups behind the one above it: the 16 values above a group are
+// then all written in an earlier phase, and the wave reads them at the start
+// of the group.  The column points go through one ring of the workgroup,
+// filled by the second wave 16 columns per group, ahead of the first wave
+// (the one furthest ahead), so that the computing waves issue no global
+// loads of their own and every global load is waited for a whole group after
+// it was issued; the first wave takes the incoming link values instead, so
+// that the extra work is split between two waves.  The bottom row of a
+// workgroup's last band goes to global memory ("link" rows, one value per
+// column, initialised to the all-ones pattern, a NaN that no table value
+// takes: every value of the table is a squared distance or +inf), stored by
+// lane 63 straight from its registers with each LDS batch; the first wave of
+// the next workgroup polls the values themselves, so neither side needs a
+// flag or a fence.  Workgroups form one chain in an order that keeps
+// consecutive workgroups on the same XCD (the hardware deals workgroups to
+// the eight XCDs in turn), so a link stays inside one L2 except at the seven
+// XCD boundaries.  A pair with more bands than waves runs in passes: the wave
+// of chain position c takes bands c, c + W, c + 2 W, ...; the band after a
+// pass's last one reads its link like any other.
 //
 // Boundaries (reading c11 of the paper's recurrence): columns before the
 // first hold +inf points, so every lane's left neighbour starts at +inf
@@ -38,6 +42,7 @@
 #ifndef FFD_PIPE_H
 #define FFD_PIPE_H
 
+#include "ffd_pipe_args.h"
 #include "ffd_stream.h"
 
 namespace ffd {
@@ -45,7 +50,8 @@ namespace ffd {
 
 // LDS of a workgroup, byte offsets: the column ring, then per wave the
 // hand-off ring (its bottom row, read by the next wave), the sink of the
-// other lanes' batched writes and the ring of incoming link values.
+// other lanes' batched writes (four values per lane at a 16-byte stride, so
+// that a batch touches every bank once) and the ring of incoming link values.
 template <int D, typename V>
 struct PipeLds {
   static constexpr int DP = pad_dim(D);
@@ -53,8 +59,8 @@ struct PipeLds {
   static constexpr int kQ = 0;                                                       // (kQRing + 16) points
   static constexpr int kWave0 = kQ + (kQRing + kPipeGroup) * DP * (int)sizeof(V);
   static constexpr int kH = 0;                                                       // hand-off ring
-  static constexpr int kSink = kH + kPipeRing * (int)sizeof(V);                      // 64 lanes x 16 values
-  static constexpr int kIn = kSink + kWave * kPipeGroup * (int)sizeof(V);            // incoming link values
+  static constexpr int kSink = kH + kPipeRing * (int)sizeof(V);                      // 4 per lane + 16
+  static constexpr int kIn = kSink + (4 * kWave + kPipeGroup) * (int)sizeof(V);      // incoming link values
   static constexpr int kWaveBytes = kIn + kPipeRing * (int)sizeof(V);
   static constexpr int kTotal = kWave0 + kPipeWaves * kWaveBytes;                    // per workgroup
 };
@@ -94,10 +100,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const Bits kUnset = ~(Bits)0;
   int32_t err = 0;
 
-  // groups a wave computes per pass: steps 0 .. m + 62 (lane 63 reaches the
-  // last column at step m + 62), plus 5 groups so that the last columns of
-  // a link row are stored
-  const int32_t gwork = (int32_t)((a.m + 63 + kPipeGroup - 1) / kPipeGroup) + 5;
+  // groups a wave computes per pass: lane 63 reaches the last column at
+  // step m + 62 and has written it (to its ring and its link row) by step
+  // m + 65
+  const int32_t gwork = (int32_t)((a.m + 66 + kPipeGroup - 1) / kPipeGroup);
   const int32_t phases = gwork + (kPipeWaves - 1) * kPipeLag;
   const int32_t passes = (a.nb + W - 1) / W;
 
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int32_t b0 = pass * W + chain * kPipeWaves;  // the workgroup's first band
     const int32_t b = b0 + wib;                        // this wave's band (>= nb: none)
     const bool active = b < a.nb;
-    const bool lead = wib == 0 && b0 < a.nb;           // fills the column ring for the workgroup
+    const bool filler = wib == 1 && b0 < a.nb;         // fills the column ring for the workgroup
     const bool link_in = active && b > 0 && wib == 0;
     const bool link_out = active && b + 1 < a.nb && wib == kPipeWaves - 1;
     const int64_t lrow_in = (int64_t)(b - 1) / kPipeWaves, lrow_out = (int64_t)b / kPipeWaves;
@@ -127,13 +133,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     V upPrev = (b == 0 && lane == 0) ? -inf : inf;
     V bprev = inf;  // lane 63's bottom value of the previous step
 
-    // The lead wave's global loads, both issued in one group and waited for
-    // in the next: the 16 column points of group h (lanes 0 .. 15 own one
-    // each; every lane loads a valid address, so the loaded registers are
-    // never merged with other values and nothing waits for them early) and
-    // the 16 link values of group h.  Column group h goes to the ring at the
-    // lead wave's group h - 2, link group h to inring at group h - 2: the
-    // group before reads both as its prefetch.
+    // Global loads are issued in one group and waited for in the next.  The
+    // filler wave loads the 16 column points of group h (lanes 0 .. 15 own
+    // one each; every lane loads a valid address, so the loaded registers
+    // are never merged with other values and nothing waits for them early)
+    // and puts them in the ring at phase h - 2: the first wave reads a group
+    // one phase ahead.  The first wave loads the 16 link values of group h
+    // and puts them in its incoming ring at its group h - 1.
     C qload[D];
     bool qmine = false;
     auto col_issue = [&](int64_t h) {
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       }
       if (lane < kPipeGroup) inring[(int)((h * kPipeGroup + lane) & (kPipeRing - 1))] = lmine ? lval : inf;
     };
-    if (lead) {
+    if (filler) {
       // columns -64 .. -1 are +inf points; groups 0 and 1 go in now, group 2 is loaded
       {
         C none[D];
@@ -195,66 +201,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         col_take(h);
       }
       col_issue(2);
-      if (link_in) {
-        for (int h = 0; h < 2; ++h) {
-          link_issue(h);
-          link_take(h);
-        }
-        link_issue(2);
-      } else {
-        // the first band: +inf above every column
-        for (int i = lane; i < kPipeRing; i += kWave) inring[i] = inf;
-      }
+    }
+    if (link_in) {
+      link_issue(0);
+      link_take(0);
+      link_issue(1);
+    } else if (wib == 0) {
+      // the first band: +inf above every column
+      for (int i = lane; i < kPipeRing; i += kWave) inring[i] = inf;
     }
     // every global load so far has returned (the rows, the first columns
     // and link values): the waits in the loop then only ever concern the
-    // lead wave's loads of the group before
+    // loads of the group before
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
 
-    // a group's inputs, read one group ahead; two buffers used in turn
+    // a group's column points, read one group ahead; two buffers used in turn
     Pt qa[kPipeGroup], qb[kPipeGroup];
-    V ha[kPipeGroup], hb[kPipeGroup];
-    auto load_group = [&](int64_t g, Pt *q, V *h) {
+    auto load_q = [&](int64_t g, Pt *q) {
       const Pt *qr = qring + (int)((g * kPipeGroup - lane) & (QR - 1));
-      const V *hr = hin + (int)((g * kPipeGroup) & (kPipeRing - 1));
 #pragma unroll
-      for (int u = 0; u < kPipeGroup; ++u) {
-        q[u] = qr[u];
-        h[u] = hr[u];
-      }
+      for (int u = 0; u < kPipeGroup; ++u) q[u] = qr[u];
     };
-    const int32_t start = wib * kPipeLag;  // even: group 0 always takes the first buffer
-    // one barrier phase: this wave's group g (if any) from (qc, hc), with
-    // the next group's inputs read into (qn, hn)
-    auto phase = [&](int32_t ph, Pt *qc, V *hc, Pt *qn, V *hn) {
+    const int32_t start = wib * kPipeLag;
+    // one barrier phase: the filler's ring work, then this wave's group g
+    // (if any) from qc, with the next group's points read into qn
+    auto phase = [&](int32_t ph, Pt *qc, Pt *qn) {
+      if (filler && ph < gwork) {
+        col_take(ph + 2);
+        col_issue(ph + 3);
+      }
       const int32_t g = ph - start;
       if (active && g >= 0 && g < gwork) {
         const int64_t t0 = (int64_t)g * kPipeGroup;
-        if (g == 0) load_group(0, qc, hc);
-        // link out: columns [t0 - 80, t0 - 64), completed by the last
-        // group; lanes 0 .. 15 store one each
-        if (link_out) {
-          int64_t col = t0 - kWave - kPipeGroup + lane;
-          if (lane < kPipeGroup && col >= 0 && col < a.m) {
-            V v = hring[(int)(col & (kPipeRing - 1))];
-            __hip_atomic_store(links + lrow_out * a.link_stride + col, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
+        if (link_in) {
+          link_take(g + 1);
+          link_issue(g + 2);
         }
-        // the lead wave: columns and link values of group g + 2 (loaded
-        // during the last group) into the rings, then the loads of group g + 3
-        if (wib == 0) {
-          col_take(g + 2);
-          if (link_in) link_take(g + 2);
-          col_issue(g + 3);
-          if (link_in) link_issue(g + 3);
+        if (g == 0) load_q(0, qc);
+        load_q(g + 1, qn);
+        // the values above this group's columns (written in earlier phases)
+        V hc[kPipeGroup];
+        {
+          const V *hr = hin + (int)(t0 & (kPipeRing - 1));
+#pragma unroll
+          for (int u = 0; u < kPipeGroup; ++u) hc[u] = hr[u];
         }
-        load_group(g + 1, qn, hn);
         // lane 63 writes its bottom values of columns [t0 - 64, t0 - 48) in
         // four batches of four; the other lanes write to their own sink
-        int32_t hidx = lane == kWave - 1 ? (int32_t)((t0 - kWave) & (kPipeRing - 1))
-                                         : kPipeRing + lane * kPipeGroup;
+        int32_t hidx = lane == kWave - 1 ? (int32_t)((t0 - kWave) & (kPipeRing - 1)) : kPipeRing + 4 * lane;
         V *hout = hring + hidx;
+        V *lout = links + lrow_out * a.link_stride;
         V bots[4];
         bots[0] = bprev;
 #pragma unroll
@@ -280,24 +277,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
           // Mp[R - 1] is now column t0 + u - 63 of the bottom row (lane 63)
           if ((u & 3) == 2) {
             bots[3] = Mp[R - 1];
-            hout[u - 2 + 0] = bots[0];
-            hout[u - 2 + 1] = bots[1];
-            hout[u - 2 + 2] = bots[2];
-            hout[u - 2 + 3] = bots[3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) hout[u - 2 + k] = bots[k];
+            // the same four columns, t0 + u - 66 .. t0 + u - 63, to the link
+            // row (a multiple of 4 below m: the row's stride, a multiple of
+            // 64 not below m, holds all four)
+            const int64_t col = t0 + u - 66;
+            if (link_out && lane == kWave - 1 && col >= 0 && col < a.m) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                __hip_atomic_store(lout + col + k, bots[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
           } else {
             bots[(u + 1) & 3] = Mp[R - 1];
           }
         }
         bprev = Mp[R - 1];
       }
-      // (the lead wave's last groups have written every column group the
-      // waves below it read: column group h is read at the earliest by the
-      // group before it, and the 512-entry ring keeps 32 groups)
+      // (the filler's last phases have written every column group the
+      // waves read: column group h is read at the earliest by the first
+      // wave's group h - 1, and the 512-entry ring keeps 32 groups)
       __syncthreads();
     };
     for (int32_t ph = 0; ph < phases; ph += 2) {
-      phase(ph, qa, ha, qb, hb);
-      if (ph + 1 < phases) phase(ph + 1, qb, hb, qa, ha);
+      phase(ph, qa, qb);
+      if (ph + 1 < phases) phase(ph + 1, qb, qa);
     }
     // the result: the last band's bottom value at the last column, which
     // lane 63 wrote to this wave's ring (the ring is not overwritten before

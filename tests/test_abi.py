@@ -245,6 +245,10 @@ def test_set_tuning_validation(planner):
         ffd.ffd_set_tuning(planner, 3, 1)
     with pytest.raises(ffd.FFDError):
         ffd.ffd_set_tuning(planner, 4, 99)
+    ffd.ffd_set_tuning(planner, 2, -1)  # single pairs: the pipelined kernel whenever it can run them
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_set_tuning(planner, 2, -2)
+    ffd.ffd_set_tuning(planner, 0, 0)
 
 
 def test_serving_database_and_arena(planner):

@@ -98,6 +98,25 @@ def test_single_pairs(planner, n, m, dim):
     plan_sim.check(sm, jobs, wj, (np.array([0, n]), np.array([0, m])), [0])
 
 
+def test_forced_pipeline(planner):
+    """waves_per_simd = -1 puts a pair on the pipelined kernel whenever that
+    kernel can run it, in the orientation of least modelled time; one that
+    it cannot run (a single band) stays on the job-table plan."""
+    ffd.ffd_set_tuning(planner, 2, -1)
+    try:
+        sm, jobs, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 5000], [0, 3], 2)
+        assert sm["pipelined"] == 1 and sm["rows_per_lane"] == 2 and sm["jobs"] == 0
+        bands = -(-5000 // 128)
+        assert sm["link_elems"] == ((bands - 1) // 4) * 64
+        sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 300], [0, 20000], 2)
+        assert sm["pipelined"] == 1 and sm["link_elems"] == ((-(-20000 // 128) - 1) // 4) * 320
+        sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 100], [0, 90], 2)
+        assert sm["pipelined"] == 0
+        plan_sim.check(sm, jobs, wj, (np.array([0, 100]), np.array([0, 90])), [0])
+    finally:
+        ffd.ffd_set_tuning(planner, 0, 0)
+
+
 @pytest.mark.parametrize("dtw,metric,lev", [(True, 1, False), (True, 0, False), (False, 2, False),
                                             (True, 3, False), (False, 1, True), (False, 4, False),
                                             (True, 4, False)])
