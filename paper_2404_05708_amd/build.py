@@ -31,11 +31,18 @@ SOURCES = [("ffd_kernels.hip", {}), ("ffd_kernels_rings.hip", {}), ("ffd_kernels
           [("ffd_kernels_serve.hip", {}), ("ffd_bounded.hip", {}), ("ffd_noalloc.hip", {}), ("ffd_host.cpp", {}), ("ffd_server.cpp", {}), ("ffd_search.cpp", {})]
 
 
+# Extra flags per source.  The pipelined single-pair kernel runs one wave per
+# SIMD, so nothing hides an instruction's latency but the instruction order:
+# the scheduler that maximises instruction-level parallelism suits it
+# (measured: 5 % faster on the 131072 x 131072 pair).
+EXTRA = {"ffd_kernels_pipe.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
 def _compile(item):
     src, defs = item
     tag = "".join(f"_{k}{v}" for k, v in defs.items())
     obj = os.path.join(BUILD, src + tag + ".o")
-    cmd = [HIPCC] + COMMON + [f"-D{k}={v}" for k, v in defs.items()] + \
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + [f"-D{k}={v}" for k, v in defs.items()] + \
         ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -613,16 +613,17 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
 // A single long pair on the pipelined kernel (ffd_pipe.h): one band of 64 R
 // rows per wave, four waves per workgroup in lockstep (kPipeLag groups of
 // 16 steps apart), workgroups chained through link rows in global memory.
-// Modelled stream steps: the last band starts about 84 steps per band
-// after the first (5 groups inside a workgroup, about 6 between
-// workgroups: lane 63 stores a column by 3 steps after it computes it, and
-// the next workgroup polls a group's link values one group before it
-// needs them), or, with several passes, when its wave has swept its
-// earlier bands; each band sweeps the columns plus the lanes' ramp.
+// Modelled stream steps: the last band starts about 88 steps per band
+// after the first (5 groups inside a workgroup, about 7 between
+// workgroups: the last wave stores a group's link values when it starts
+// its fifth group after it, and the next workgroup needs them one group
+// before their own group), or, with several passes, when its wave has
+// swept its earlier bands; each band sweeps the columns plus the lanes'
+// ramp and the link flush.
 // Clocks per step: one instruction per 4 clocks (one wave per SIMD issues
 // alone), R cells of 2 D + 2 instructions (FP64: 2 D + 3) and about 7 per
 // step of lane shift, LDS traffic and bookkeeping.
-constexpr double kPipeBandLag = (3 * ffd::kPipeLag * ffd::kPipeGroup + 6 * ffd::kPipeGroup) / 4.0;
+constexpr double kPipeBandLag = (3 * ffd::kPipeLag * ffd::kPipeGroup + 7 * ffd::kPipeGroup) / 4.0;
 
 double pipe_step_clocks(int R, int D, bool exact) {
   return 4.0 * (R * (2 * D + 2 + (exact ? 1 : 0)) + 7 + (exact ? 2 : 0));
@@ -659,7 +660,7 @@ bool build_pipe(ffd_ctx *ctx, int64_t rows, int64_t cols, int R, int D, bool exa
   }
   const int64_t W = nwg * ffd::kPipeWaves;
   const int64_t passes = (nb + W - 1) / W;
-  const double sweep = (double)((cols + 66 + ffd::kPipeGroup - 1) / ffd::kPipeGroup * ffd::kPipeGroup);
+  const double sweep = (double)(((cols - 1) / ffd::kPipeGroup + 6) * ffd::kPipeGroup);
   const double chain = (double)(nb - 1) * kPipeBandLag;
   const double wrap = (double)(passes - 1) * sweep + (double)((nb - 1) % W) * kPipeBandLag;
   const double steps = std::max(chain, wrap) + sweep;

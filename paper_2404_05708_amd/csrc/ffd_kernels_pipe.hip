@@ -17,12 +17,12 @@ hipError_t pipe_one(const PipeArgs &a, size_t lds, hipStream_t st) {
   }
   PipeArgs copy = a;
   void *args[] = {&copy};
-  return hipLaunchCooperativeKernel(k, dim3((unsigned)a.nwg), dim3(kPipeWaves * kWave), args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel(k, dim3((unsigned)a.nwg), dim3(kPipeThreads), args, (unsigned)lds, st);
 }
 
 template <int R, int D, typename V>
 hipError_t pipe_occ(size_t lds, int *blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, &pipe_kernel<R, D, V>, kPipeWaves * kWave, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, &pipe_kernel<R, D, V>, kPipeThreads, lds);
 }
 
 template <typename V>

@@ -10,28 +10,31 @@
 //
 // Bands follow each other down the rows.  Band b + 1 needs band b's bottom
 // row; lane 63 of band b produces column j at step j + 63 and writes it, in
-// batches of four columns, to a ring in LDS by step j + 66.  Four waves of a
-// workgroup (one per SIMD of the compute unit) hold four consecutive bands
-// and run in lockstep, one 16-step group per barrier phase, each wave
-// kPipeLag groups behind the one above it: the 16 values above a group are
-// then all written in an earlier phase, and the wave reads them at the start
-// of the group.  The column points go through one ring of the workgroup,
-// filled by the second wave 16 columns per group, ahead of the first wave
-// (the one furthest ahead), so that the computing waves issue no global
-// loads of their own and every global load is waited for a whole group after
-// it was issued; the first wave takes the incoming link values instead, so
-// that the extra work is split between two waves.  The bottom row of a
-// workgroup's last band goes to global memory ("link" rows, one value per
-// column, initialised to the all-ones pattern, a NaN that no table value
-// takes: every value of the table is a squared distance or +inf), stored by
-// lane 63 straight from its registers with each LDS batch; the first wave of
-// the next workgroup polls the values themselves, so neither side needs a
-// flag or a fence.  Workgroups form one chain in an order that keeps
-// consecutive workgroups on the same XCD (the hardware deals workgroups to
-// the eight XCDs in turn), so a link stays inside one L2 except at the seven
-// XCD boundaries.  A pair with more bands than waves runs in passes: the wave
-// of chain position c takes bands c, c + W, c + 2 W, ...; the band after a
-// pass's last one reads its link like any other.
+// batches of four columns, to a ring in LDS by step j + 66.  Four computing
+// waves of a workgroup (one per SIMD of the compute unit) hold four
+// consecutive bands and run in lockstep, one 16-step group per barrier
+// phase, each wave kPipeLag groups behind the one above it: the 16 values
+// above a group are then all written in an earlier phase, and the wave reads
+// them at the start of the group.
+//
+// A fifth wave of the workgroup computes nothing: it keeps the computing
+// waves supplied, so that they issue no global memory instruction and carry
+// no work but their band's (with one wave per SIMD, every instruction a
+// computing wave issues lengthens the phase of the whole workgroup).  It
+// loads the column points 16 per phase into a ring of the workgroup (a
+// group's points two phases before the first wave reads them), polls the
+// incoming link values (two groups ahead) into the first wave's ring, and
+// stores the last wave's bottom row from its ring to the outgoing link.
+// Link rows live in global memory, one value per column, initialised to the
+// all-ones pattern, a NaN that no table value takes (every value of the
+// table is a squared distance or +inf); the next workgroup polls the values
+// themselves, so neither side needs a flag or a fence.  Workgroups form one
+// chain in an order that keeps consecutive workgroups on the same XCD (the
+// hardware deals workgroups to the eight XCDs in turn), so a link stays
+// inside one L2 except at the seven XCD boundaries.  A pair with more bands
+// than computing waves runs in passes: the wave of chain position c takes
+// bands c, c + W, c + 2 W, ...; the band after a pass's last one reads its
+// link like any other.
 //
 // Boundaries (reading c11 of the paper's recurrence): columns before the
 // first hold +inf points, so every lane's left neighbour starts at +inf
@@ -46,7 +49,6 @@
 #include "ffd_stream.h"
 
 namespace ffd {
-
 
 // LDS of a workgroup, byte offsets: the column ring, then per wave the
 // hand-off ring (its bottom row, read by the next wave), the sink of the
@@ -66,7 +68,7 @@ struct PipeLds {
 };
 
 template <int R, int D, typename V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void pipe_kernel(PipeArgs a) {
+__global__ __launch_bounds__(kPipeThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void pipe_kernel(PipeArgs a) {
   using N = Num<V>;
   using C = typename N::Coord;
   using L = PipeLds<D, V>;
@@ -77,21 +79,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   };
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wib = threadIdx.x / kWave;
+  const int wib = threadIdx.x / kWave;  // kPipeWaves: the helper wave
+  const bool helper = wib == kPipeWaves;
   Pt *qring = reinterpret_cast<Pt *>(smem + L::kQ);
-  unsigned char *base = smem + L::kWave0 + wib * L::kWaveBytes;
-  V *hring = reinterpret_cast<V *>(base + L::kH);
-  V *inring = reinterpret_cast<V *>(base + L::kIn);
+  auto wave_base = [&](int w) { return smem + L::kWave0 + w * L::kWaveBytes; };
+  V *hring = reinterpret_cast<V *>(wave_base(helper ? 0 : wib) + L::kH);
   // the top row of this wave's band: the ring of the wave above, or (first
-  // wave of the workgroup) the values it copies in from its link
-  const V *hin = wib > 0 ? reinterpret_cast<const V *>(smem + L::kWave0 + (wib - 1) * L::kWaveBytes + L::kH)
-                         : inring;
+  // wave of the workgroup) the incoming link values
+  const V *hin = wib > 0 && !helper ? reinterpret_cast<const V *>(wave_base(wib - 1) + L::kH)
+                                    : reinterpret_cast<const V *>(wave_base(0) + L::kIn);
+  V *inring = reinterpret_cast<V *>(wave_base(0) + L::kIn);                   // written by the helper
+  const V *lastring = reinterpret_cast<const V *>(wave_base(kPipeWaves - 1) + L::kH);  // read by the helper
 
   // chain position of this workgroup
   const int32_t blk = blockIdx.x;
   const int32_t chain = a.xcd_span > 0 ? (blk % 8) * a.xcd_span + blk / 8 : blk;
   const int32_t W = a.nwg * kPipeWaves;
-  const int32_t cpos = chain * kPipeWaves + wib;
   const C *X = static_cast<const C *>(a.X);
   const C *Y = static_cast<const C *>(a.Y);
   V *links = static_cast<V *>(a.links);
@@ -101,20 +104,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   int32_t err = 0;
 
   // groups a wave computes per pass: lane 63 reaches the last column at
-  // step m + 62 and has written it (to its ring and its link row) by step
-  // m + 65
-  const int32_t gwork = (int32_t)((a.m + 66 + kPipeGroup - 1) / kPipeGroup);
+  // step m + 62 and has written it to its ring by step m + 65; the helper
+  // stores column j of the last wave's row to the link at that wave's group
+  // j / 16 + 5
+  const int32_t gwork = (int32_t)((a.m - 1) / kPipeGroup) + 6;
   const int32_t phases = gwork + (kPipeWaves - 1) * kPipeLag;
   const int32_t passes = (a.nb + W - 1) / W;
 
   for (int32_t pass = 0; pass < passes; ++pass) {
     const int32_t b0 = pass * W + chain * kPipeWaves;  // the workgroup's first band
-    const int32_t b = b0 + wib;                        // this wave's band (>= nb: none)
+    const int32_t b = helper ? a.nb : b0 + wib;        // this wave's band (>= nb: none)
     const bool active = b < a.nb;
-    const bool filler = wib == 1 && b0 < a.nb;         // fills the column ring for the workgroup
-    const bool link_in = active && b > 0 && wib == 0;
-    const bool link_out = active && b + 1 < a.nb && wib == kPipeWaves - 1;
-    const int64_t lrow_in = (int64_t)(b - 1) / kPipeWaves, lrow_out = (int64_t)b / kPipeWaves;
+    const bool fill = helper && b0 < a.nb;             // the helper has work in this pass
+    const bool link_in = fill && b0 > 0;               // the first band reads a link
+    const bool link_out = fill && b0 + kPipeWaves < a.nb;  // the last band writes one
+    const int64_t lrow_in = (int64_t)(b0 - 1) / kPipeWaves, lrow_out = (int64_t)b0 / kPipeWaves;
 
     // rows of this lane, the last point repeated past the curve's end
     V p[R][D], Mp[R];
@@ -133,13 +137,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     V upPrev = (b == 0 && lane == 0) ? -inf : inf;
     V bprev = inf;  // lane 63's bottom value of the previous step
 
-    // Global loads are issued in one group and waited for in the next.  The
-    // filler wave loads the 16 column points of group h (lanes 0 .. 15 own
-    // one each; every lane loads a valid address, so the loaded registers
-    // are never merged with other values and nothing waits for them early)
-    // and puts them in the ring at phase h - 2: the first wave reads a group
-    // one phase ahead.  The first wave loads the 16 link values of group h
-    // and puts them in its incoming ring at its group h - 1.
+    // The helper's global loads are issued at least one phase before they
+    // are waited for: the 16 column points of group h (lanes 0 .. 15 own one
+    // each; every lane loads a valid address, so the loaded registers are
+    // never merged with other values and nothing waits for them early), put
+    // in the ring at phase h - 2 (the first wave reads a group one phase
+    // ahead), and the 16 link values of group h, loaded at phase h - 3 and
+    // put in the first wave's ring at phase h - 1, polled again while any is
+    // still unset.
     C qload[D];
     bool qmine = false;
     auto col_issue = [&](int64_t h) {
@@ -160,9 +165,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     auto col_take = [&](int64_t h) {
       if (lane < kPipeGroup) col_put(h * kPipeGroup + lane, qmine, qload);
     };
-    V lval = inf;
-    bool lmine = false;
-    auto link_issue = [&](int64_t h) {
+    // two link loads in flight (groups h and h + 1), in two register sets
+    V lval0 = inf, lval1 = inf;
+    bool lmine0 = false, lmine1 = false;
+    auto link_issue = [&](int64_t h, V &lval, bool &lmine) {
       int64_t col = h * kPipeGroup + (lane & (kPipeGroup - 1));
       lmine = lane < kPipeGroup && col < a.m;
       int64_t cc = col < a.m ? col : a.m - 1;
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // a wait lasts at most a.patience ticks of the real-time counter (the
     // host sizes it far above the modelled run time); once one wait has
     // been abandoned the wave waits no more, so a launch always ends
-    auto link_take = [&](int64_t h) {
+    auto link_take = [&](int64_t h, V &lval, bool &lmine) {
       uint64_t t_begin = 0;
       for (int it = 0;; ++it) {
         bool ok = !lmine || __builtin_bit_cast(Bits, lval) != kUnset;
@@ -184,11 +190,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
           break;
         }
         __builtin_amdgcn_s_sleep(2);
-        link_issue(h);
+        link_issue(h, lval, lmine);
       }
       if (lane < kPipeGroup) inring[(int)((h * kPipeGroup + lane) & (kPipeRing - 1))] = lmine ? lval : inf;
     };
-    if (filler) {
+    if (fill) {
       // columns -64 .. -1 are +inf points; groups 0 and 1 go in now, group 2 is loaded
       {
         C none[D];
@@ -201,22 +207,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         col_take(h);
       }
       col_issue(2);
-    }
-    if (link_in) {
-      link_issue(0);
-      link_take(0);
-      link_issue(1);
-    } else if (wib == 0) {
-      // the first band: +inf above every column
-      for (int i = lane; i < kPipeRing; i += kWave) inring[i] = inf;
+      if (link_in) {
+        link_issue(0, lval0, lmine0);
+        link_issue(1, lval1, lmine1);
+        link_take(0, lval0, lmine0);
+        link_issue(2, lval0, lmine0);
+      } else {
+        // the first band: +inf above every column
+        for (int i = lane; i < kPipeRing; i += kWave) inring[i] = inf;
+      }
     }
     // every global load so far has returned (the rows, the first columns
     // and link values): the waits in the loop then only ever concern the
-    // loads of the group before
+    // helper's loads of the phases before
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
 
-    // a group's column points, read one group ahead; two buffers used in turn
+    // a group's column points, read one group ahead from two buffers used in
+    // turn (FP64 values: read at the start of the group into one buffer, so
+    // that a wave's registers fit two waves on one SIMD)
+    constexpr bool kAhead = sizeof(V) == 4;
     Pt qa[kPipeGroup], qb[kPipeGroup];
     auto load_q = [&](int64_t g, Pt *q) {
       const Pt *qr = qring + (int)((g * kPipeGroup - lane) & (QR - 1));
@@ -224,22 +234,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       for (int u = 0; u < kPipeGroup; ++u) q[u] = qr[u];
     };
     const int32_t start = wib * kPipeLag;
-    // one barrier phase: the filler's ring work, then this wave's group g
-    // (if any) from qc, with the next group's points read into qn
-    auto phase = [&](int32_t ph, Pt *qc, Pt *qn) {
-      if (filler && ph < gwork) {
-        col_take(ph + 2);
-        col_issue(ph + 3);
+    // one barrier phase: the helper's ring and link work, or this wave's
+    // group g (if any) from qc, with the next group's points read into qn;
+    // (lv, lm) is the link register set of group ph + 1
+    auto phase = [&](int32_t ph, Pt *qc, Pt *qn, V &lv, bool &lm) {
+      if (fill) {
+        if (ph < gwork) {
+          col_take(ph + 2);
+          col_issue(ph + 3);
+          if (link_in) {
+            link_take(ph + 1, lv, lm);
+            link_issue(ph + 3, lv, lm);
+          }
+        }
+        // link out: columns [t0 - 80, t0 - 64) of the last wave's row at
+        // its group t0 / 16 = ph - 3 kPipeLag, all in its ring since its
+        // group before; lanes 0 .. 15 store one each
+        if (link_out) {
+          int64_t col = (int64_t)(ph - (kPipeWaves - 1) * kPipeLag) * kPipeGroup - kWave - kPipeGroup + lane;
+          if (lane < kPipeGroup && col >= 0 && col < a.m)
+            __hip_atomic_store(links + lrow_out * a.link_stride + col, lastring[(int)(col & (kPipeRing - 1))],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
       const int32_t g = ph - start;
       if (active && g >= 0 && g < gwork) {
         const int64_t t0 = (int64_t)g * kPipeGroup;
-        if (link_in) {
-          link_take(g + 1);
-          link_issue(g + 2);
+        if (kAhead) {
+          if (g == 0) load_q(0, qc);
+          load_q(g + 1, qn);
+        } else {
+          load_q(g, qc);
         }
-        if (g == 0) load_q(0, qc);
-        load_q(g + 1, qn);
         // the values above this group's columns (written in earlier phases)
         V hc[kPipeGroup];
         {
@@ -251,7 +277,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         // four batches of four; the other lanes write to their own sink
         int32_t hidx = lane == kWave - 1 ? (int32_t)((t0 - kWave) & (kPipeRing - 1)) : kPipeRing + 4 * lane;
         V *hout = hring + hidx;
-        V *lout = links + lrow_out * a.link_stride;
         V bots[4];
         bots[0] = bprev;
 #pragma unroll
@@ -279,29 +304,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             bots[3] = Mp[R - 1];
 #pragma unroll
             for (int k = 0; k < 4; ++k) hout[u - 2 + k] = bots[k];
-            // the same four columns, t0 + u - 66 .. t0 + u - 63, to the link
-            // row (a multiple of 4 below m: the row's stride, a multiple of
-            // 64 not below m, holds all four)
-            const int64_t col = t0 + u - 66;
-            if (link_out && lane == kWave - 1 && col >= 0 && col < a.m) {
-#pragma unroll
-              for (int k = 0; k < 4; ++k)
-                __hip_atomic_store(lout + col + k, bots[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
           } else {
             bots[(u + 1) & 3] = Mp[R - 1];
           }
         }
         bprev = Mp[R - 1];
       }
-      // (the filler's last phases have written every column group the
+      // (the helper's last phases have written every column group the
       // waves read: column group h is read at the earliest by the first
       // wave's group h - 1, and the 512-entry ring keeps 32 groups)
       __syncthreads();
     };
     for (int32_t ph = 0; ph < phases; ph += 2) {
-      phase(ph, qa, qb);
-      if (ph + 1 < phases) phase(ph + 1, qb, qa);
+      phase(ph, qa, kAhead ? qb : qa, lval1, lmine1);
+      if (ph + 1 < phases) phase(ph + 1, kAhead ? qb : qa, qa, lval0, lmine0);
     }
     // the result: the last band's bottom value at the last column, which
     // lane 63 wrote to this wave's ring (the ring is not overwritten before

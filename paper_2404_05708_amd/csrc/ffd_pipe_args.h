@@ -7,7 +7,8 @@
 
 namespace ffd {
 
-constexpr int kPipeWaves = 4;   // waves per workgroup, one per SIMD
+constexpr int kPipeWaves = 4;   // computing waves per workgroup, one per SIMD
+constexpr int kPipeThreads = (kPipeWaves + 1) * 64;  // and a helper wave (loads and links)
 constexpr int kPipeLag = 5;     // groups a wave runs behind the wave above it in the workgroup
 constexpr int kPipeRing = 256;  // column ring and hand-off ring entries (power of two, multiple of 16)
 constexpr int kPipeGroup = 16;  // steps per phase
@@ -17,7 +18,7 @@ struct PipeArgs {
   const void *Y;        // column curve, m points
   int64_t n, m;
   int32_t nb;           // bands of 64 R rows
-  int32_t nwg;          // workgroups launched (kPipeWaves waves each)
+  int32_t nwg;          // workgroups launched (kPipeWaves computing waves and a helper each)
   int32_t xcd_span;     // > 0: workgroups per XCD in the chain order (nwg is a multiple of 8)
   int32_t metric;       // float: 0 Euclidean (one root of the result), 1 squared
   void *links;          // link rows of link_stride values (value bits; all ones = not written yet)
