@@ -585,7 +585,9 @@ def run_pair(args, torch, ffd, ctx, dev, stream, which):
         "config": {"workload": desc, "npairs": 1, "cells": cells, "global_batch": 1},
         "parity": {"tolerance": TOL, "ok": bool(parity_ok), "got": got, "oracle": want,
                    "launch_error_flags": errs},
-        "roofline": roofline(info, cells, kms, dim, False), "cpu_baseline": cpu,
+        "roofline": roofline(info, cells, kms, dim, False,
+                             family="pipe_kernel" if info.get("pipelined") else "stream_kernel"),
+        "cpu_baseline": cpu,
     }
 
 

@@ -363,6 +363,8 @@ typedef struct ffd_launch_info {
   int32_t lds_per_wave;    /* bytes of LDS per wavefront                    */
   int32_t exact;           /* 1: int32 path with FP64-exact values          */
   int32_t dim;             /* D                                             */
+  int32_t pipelined;       /* 1: the pipelined single-pair kernel           */
+  int32_t helper_waves;    /* waves per workgroup that compute no band      */
   int64_t stream_steps;    /* longest per-wave stream (steps)               */
 } ffd_launch_info;
 

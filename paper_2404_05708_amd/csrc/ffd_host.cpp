@@ -861,7 +861,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
              size_t ws_bytes, hipStream_t st, UseOrder &use, bool noalloc = false) {
   WsLayout wl = ws_layout(pl, n0, n1, exact);
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, lds_bytes(pl.R, D, exact, pl.hcap, pl.rings, ctx->measure),
-                              exact ? 1 : 0, D, pl.max_steps};
+                              exact ? 1 : 0, D, 0, 0, pl.max_steps};
   if (noalloc && ws_bytes < wl.total) {
     std::string msg = "the request needs " + std::to_string(wl.total) +
                       " bytes of device scratch; ffd_batch_noalloc has " + std::to_string(ws_bytes);
@@ -936,7 +936,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   a.flags = pl.nflags > 0 ? (uint64_t *)(w + wl.flags) : nullptr;
   a.err = (uint64_t *)(w + wl.err);
   a.rings = pl.rings ? 1 : 0;
-  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, pl.max_steps};
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, 0, 0, pl.max_steps};
   e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st, ctx->measure);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->last_err = a.err;
@@ -1061,7 +1061,7 @@ int run_pipe(ffd_ctx *ctx, const Plan &pl, const void *p, const void *q, int D, 
   PipeLayout L = pipe_layout(pl, exact);
   size_t lds = pl.pipe_lds;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, ffd::kPipeWaves, (int32_t)(lds / ffd::kPipeWaves), exact ? 1 : 0, D,
-                              pl.max_steps};
+                              1, 1, pl.max_steps};
   if (ctx->scratch_bytes < L.total)
     return fail(ctx, FFD_E_NOMEM,
                 "a pair this long runs on many wavefronts and needs device scratch: register at least "
@@ -1117,8 +1117,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
   if (rc) return rc;
   if (pl->max_steps + 4 * ffd::kRing > INT32_MAX) return fail(ctx, FFD_E_UNSUPPORTED, "stream too long");
   ctx->last = ffd_launch_info{pl->R, pl->nwaves, pl->wpb, lds_bytes(pl->R, dim, exact, pl->hcap, false, ctx->measure),
-                              exact ? 1 : 0,
-                              dim, pl->max_steps};
+                              exact ? 1 : 0, dim, 0, 0, pl->max_steps};
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");

@@ -64,6 +64,7 @@ class LaunchInfo(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("lds_per_wave", ctypes.c_int32),
                 ("exact", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("pipelined", ctypes.c_int32), ("helper_waves", ctypes.c_int32),
                 ("stream_steps", ctypes.c_int64)]
 
     def as_dict(self):
