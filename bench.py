@@ -86,10 +86,15 @@ def kernel_ms(torch, step, steps, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def profiled_traffic(profile):
+def launch_signature(info):
+    return f"R{info['rows_per_lane']}/W{info['waves']}/S{info['stream_steps']}"
+
+
+def profiled_traffic(profile, info):
     """HBM bytes per launch recorded in a committed rocprofv3 summary
     (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
-    kernel source differs from the one the counters were taken on."""
+    kernel source differs from the one the counters were taken on or the
+    planner chose another launch (rows per lane, waves, longest stream)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -97,7 +102,7 @@ def profiled_traffic(profile):
     fields = {}
     for line in open(path):
         if ":" in line and line.split(":", 1)[0].strip() in (
-                "kernel_source_sha256", "plan_header_sha256", "* traffic_bytes_per_launch"):
+                "kernel_source_sha256", "plan_header_sha256", "launch_signature", "* traffic_bytes_per_launch"):
             k, v = line.split(":", 1)
             fields[k.strip().lstrip("* ")] = v.split()[0]
     src = {"kernel_source_sha256": "paper_2404_05708_amd/csrc/ffd_stream.h",
@@ -106,6 +111,8 @@ def profiled_traffic(profile):
         digest = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
         if fields.get(key) != digest:
             return None
+    if fields.get("launch_signature") != launch_signature(info):
+        return None
     return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
 
 
@@ -116,7 +123,7 @@ def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel",
     return {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
         "unit": "TVALUop/s", "frac": achieved / PEAK_VALU,
-        "traffic": profiled_traffic(profile) if profile else None,
+        "traffic": profiled_traffic(profile, info) if profile else None,
         "kernel": f"ffd::{family}<{info['rows_per_lane']}, {dim}, {vt}{suffix}>", "kernel_ms": kms,
         "launch": info, "ops_per_cell": imin(dim, exact, cell), "cells_per_launch": cells,
     }
