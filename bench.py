@@ -480,61 +480,83 @@ def run_decide(args, torch, ffd, ctx, dev, stream):
 
 def run_knn(args, torch, ffd, ctx, dev, stream):
     """k = 10 nearest curves of queries in the resident 10,000-curve database
-    (the serving workload) through ffd_knn (endpoint bounds, a threshold
-    from 128 exact distances, early-abandoning sweep), against a full scan
-    (ffd_cross of the query with every curve, then the 10 smallest)."""
+    (the serving workload) through ffd_knn_batch (endpoint bounds, a
+    threshold from 128 exact distances per query, early-abandoning sweep;
+    --knn-batch queries per call), against ffd_knn one query at a time and a
+    full scan (ffd_cross of the query with every curve, then the 10
+    smallest)."""
     import workloads
     K = 10
+    B = max(1, args.knn_batch)
     DB, dbo = workloads.serving_db()
     db_points = int(dbo[-1])
     DBd = torch.from_numpy(DB).to(dev)
-    qs = workloads.serving_queries(count=args.warmup + args.steps)
-    qd = [torch.from_numpy(q).to(dev) for q in qs]
-    ws = torch.empty(max(ctx.workspace_size(ffd.FFD_OP_CROSS, [0, len(q)], dbo, 2) for q in qs),
-                     dtype=torch.uint8, device=dev)
-    full = torch.empty(len(dbo) - 1, dtype=torch.float32, device=dev)
-    for i in range(args.warmup):
-        ctx.knn(qd[i], DBd, dbo, K, stream=stream)
-        ctx.cross(qd[i], [0, len(qs[i])], DBd, dbo, out=full, workspace=ws, stream=stream)
+    nq = (args.warmup + args.steps) * B
+    qs = workloads.serving_queries(count=nq)
+    batches = []
+    for b in range(args.warmup + args.steps):
+        Qs, q_off = workloads.concat(qs[b * B:(b + 1) * B])
+        batches.append((torch.from_numpy(Qs).to(dev), q_off))
+    for b in range(args.warmup):
+        ctx.knn_batch(batches[b][0], batches[b][1], DBd, dbo, K, stream=stream)
     torch.cuda.synchronize()
     timed = range(args.warmup, args.warmup + args.steps)
-    cells = sum(len(qs[i]) for i in timed) * db_points
     t0 = time.perf_counter()
-    res = [ctx.knn(qd[i], DBd, dbo, K, stream=stream) for i in timed]
+    res = [ctx.knn_batch(batches[b][0], batches[b][1], DBd, dbo, K, stream=stream) for b in timed]
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = (time.perf_counter() - t0) / (args.steps * B)
     counts = ctx.last_search()
+    # the same queries one call each (a sample of 20), and a full scan of them
+    sample = list(range(args.warmup * B, args.warmup * B + min(20, args.steps * B)))
+    qd = {i: torch.from_numpy(qs[i]).to(dev) for i in sample}
+    ws = torch.empty(max(ctx.workspace_size(ffd.FFD_OP_CROSS, [0, len(qs[i])], dbo, 2) for i in sample),
+                     dtype=torch.uint8, device=dev)
+    full = torch.empty(len(dbo) - 1, dtype=torch.float32, device=dev)
+    ctx.knn(qd[sample[0]], DBd, dbo, K, stream=stream)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
+    single = [ctx.knn(qd[i], DBd, dbo, K, stream=stream) for i in sample]
+    torch.cuda.synchronize()
+    single_sec = (time.perf_counter() - t1) / len(sample)
+    t2 = time.perf_counter()
     scans = []
-    for i in timed:
+    for i in sample:
         ctx.cross(qd[i], [0, len(qs[i])], DBd, dbo, out=full, workspace=ws, stream=stream)
         d = full.cpu()
         scans.append(torch.topk(d, K, largest=False, sorted=True))
     torch.cuda.synchronize()
-    scan_sec = (time.perf_counter() - t1) / args.steps
-    same = all(torch.equal(r[1].cpu(), s.values) for r, s in zip(res, scans))
+    scan_sec = (time.perf_counter() - t2) / len(sample)
+    flat_i = torch.cat([r[0].cpu() for r in res]).reshape(-1, K)
+    flat_d = torch.cat([r[1].cpu() for r in res]).reshape(-1, K)
+    base = args.warmup * B
+    same = all(torch.equal(flat_d[i - base], s.values) for i, s in zip(sample, scans))
+    same_single = all(torch.equal(flat_i[i - base], r[0].cpu()) and torch.equal(flat_d[i - base], r[1].cpu())
+                      for i, r in zip(sample, single))
+    cells = sum(len(qs[i]) for i in range(base, base + args.steps * B)) * db_points
     cpu = None
     if not args.no_cpu:
         import oracle
         cores = cpu_cores()
-        i = args.warmup
-        t2 = time.perf_counter()
+        i = sample[0]
+        t3 = time.perf_counter()
         vals = oracle.dfd_cross(qs[i], [0, len(qs[i])], DB, dbo, oracle.EUCLIDEAN, cores)[0]
-        cw = time.perf_counter() - t2
+        cw = time.perf_counter() - t3
         o_i, o_d = oracle.knn(vals, K)
         cpu = {"value": 1.0 / cw, "unit": "queries/s", "cores": cores, "kind": "oracle",
                "sample": f"one query ({len(qs[i])} points) against all 10,000 curves, FP64 rolling-row oracle "
                          f"on {cores} threads, then the 10 smallest: {cw:.2f} s",
-               "gpu_matches_sample": bool(np.array_equal(res[0][0].cpu().numpy(), o_i))}
+               "gpu_matches_sample": bool(np.array_equal(flat_i[i - base].numpy(), o_i))}
     return {
-        "metric": "knn_queries_per_second", "value": 1.0 / sec, "unit": "queries/s", "ms_per_step": sec * 1e3,
+        "metric": "knn_queries_per_second", "value": 1.0 / sec, "unit": "queries/s", "ms_per_step": sec * B * 1e3,
         "dtype": "f32",
         "config": {"workload": "knn: k = 10 nearest of log-normal-length 2-D walk queries in the 10,000-curve "
                                "serving database (seeds 5, 6), Euclidean",
-                   "queries": args.steps, "k": K, "db_points": db_points, "global_batch": args.steps},
-        "parity": {"distances_equal_full_scan": same},
-        "search": {"full_scan_ms": scan_sec * 1e3, "speedup_over_full_scan": scan_sec / sec,
-                   "effective_cells_per_s": cells / args.steps / sec, "last_query_counts": counts},
+                   "queries": args.steps * B, "queries_per_call": B, "k": K, "db_points": db_points,
+                   "global_batch": B},
+        "parity": {"distances_equal_full_scan": same, "batch_equals_single_query_calls": same_single},
+        "search": {"single_query_ms": single_sec * 1e3, "full_scan_ms": scan_sec * 1e3,
+                   "speedup_over_full_scan": scan_sec / sec, "effective_cells_per_s": cells / (sec * args.steps * B),
+                   "last_call_counts": counts},
         "cpu_baseline": cpu,
     }
 
@@ -804,6 +826,7 @@ def main():
     ap.add_argument("--cpu-block", type=int, default=32768,
                     help="leading points per curve timed on the CPU (large)")
     ap.add_argument("--cpu-queries", type=int, default=64, help="queries in the CPU oracle sample (cross)")
+    ap.add_argument("--knn-batch", type=int, default=64, help="queries per ffd_knn_batch call (knn workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--metric", choices=["euclidean", "manhattan", "chebyshev"], default="euclidean",

@@ -276,8 +276,9 @@ int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off,
  * them.  Scratch (ffd_set_scratch): ffd_distance of a pair (op =
  * FFD_OP_PAIR: a_off = {0, n}, b_off = {0, m}, na = nb = 1; every form and
  * metric), ffd_decide_batch (op = FFD_OP_DECIDE, arguments as FFD_OP_BATCH)
- * and ffd_knn (op = FFD_OP_KNN: a_off = {0, n}, na = 1, b_off = db_off, nb =
- * ndb).  Writes *bytes (0: the call needs none).
+ * and ffd_knn / ffd_knn_batch (op = FFD_OP_KNN: a_off = the queries'
+ * offsets ({0, n} for one), na = nq, b_off = db_off, nb = ndb).  Writes
+ * *bytes (0: the call needs none).
  * Errors: FFD_E_INVALID for a bad op, NULL or bad offsets. */
 int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na,
                        const int64_t *b_off, int64_t nb, int32_t dim, size_t *bytes);
@@ -430,10 +431,10 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
  * FFD_SQEUCLIDEAN (other metrics: FFD_E_UNSUPPORTED); the values that are
  * kept have the same bits as ffd_batch's.  The calls use the scratch
  * registered with ffd_set_scratch (sizes from ffd_workspace_size with
- * FFD_OP_DECIDE or FFD_OP_KNN; FFD_E_NOMEM without it); ffd_knn also uses
- * pinned host staging of about 20 bytes per database curve that the context
- * allocates on first need and keeps until ffd_destroy.  They cannot be
- * recorded into a graph (FFD_E_UNSUPPORTED). */
+ * FFD_OP_DECIDE or FFD_OP_KNN; FFD_E_NOMEM without it); the k-nearest
+ * calls also use pinned host staging of about 12 bytes per (query, database
+ * curve) pair that the context allocates on first need and keeps until
+ * ffd_destroy.  They cannot be recorded into a graph (FFD_E_UNSUPPORTED). */
 
 /* Decider: out[k] = delta(P_k, Q_k) when it is <= eps (the same value as
  * ffd_batch), else +inf, so that out[k] <= eps answers "is delta <= eps?".
@@ -464,6 +465,18 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
  * FFD_E_DEVICE. */
 int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
             int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream);
+
+/* ffd_knn for nq queries in one call (CSR: Q device coordinates, q_off HOST
+ * offsets, every query at least one point): the results of query i are
+ * out_idx[i * k + j] and out_dist[i * k + j], each query's exactly as
+ * ffd_knn gives them.  The stages run for all queries at once: one launch
+ * of the bounds, one of the 128-curve first stages, one of the thresholded
+ * sweeps, so the host work and the GPU's fill are shared.
+ * Errors: as ffd_knn; FFD_E_INVALID for nq < 1 or an empty query,
+ * FFD_E_UNSUPPORTED when nq * ndb exceeds 2^30. */
+int ffd_knn_batch(ffd_ctx *ctx, const float *Q, const int64_t *q_off, int64_t nq, const float *DB,
+                  const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int32_t k, int64_t *out_idx,
+                  float *out_dist, void *stream);
 
 typedef struct ffd_search_info {
   int64_t exact;     /* curves evaluated before the threshold was set */

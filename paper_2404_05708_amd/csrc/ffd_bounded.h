@@ -10,8 +10,12 @@ namespace ffd {
 struct BoundedArgs {
   const float *X0, *X1;        // coordinates of the row curves and of the column curves
   const int64_t *off0, *off1;  // their offsets in points (device)
-  const int32_t *order;        // work item k -> pair index (column curve and output index)
-  int32_t fixed_row;           // >= 0: row curve of every pair; -1: the pair index
+  const int32_t *order;        // work item k -> pair index (the output index)
+  int32_t fixed_row;           // >= 0: row curve of every pair; -1: the pair index (or, with
+                               // col_count > 0, pair / col_count)
+  int64_t col_count;           // > 0: pair p is row curve p / col_count against column curve
+                               // p % col_count; 0: column curve = pair index
+  const float *row_eps2;       // non-null: the threshold of each row curve (replaces eps2)
   int32_t metric;              // 0: store sqrt(delta^2) rounded once; 1: delta^2
   int64_t npairs;              // work items
   float eps2;                  // drop a pair once every cell of a crossing set exceeds this (squared)
@@ -27,6 +31,10 @@ hipError_t launch_bounded(int R, int D, const BoundedArgs &a, int nwaves, hipStr
 // the query and curve c.
 hipError_t launch_endpoint_bound(int D, const float *q, int64_t n, const float *X, const int64_t *off, int64_t count,
                                  float *lb, hipStream_t st);
+// The same for nq queries (CSR offsets q_off, device) against every curve:
+// lb[i * count + c].
+hipError_t launch_endpoint_bound_batch(int D, const float *Q, const int64_t *q_off, int64_t nq, const float *X,
+                                       const int64_t *off, int64_t count, float *lb, hipStream_t st);
 
 }  // namespace ffd
 

@@ -122,7 +122,7 @@ struct Bounded {
 
   // One pair; returns the value lane `ln` holds for M_{n-1,m-1} (squared),
   // or +inf on every lane when the pair was abandoned.
-  __device__ float pair(int32_t ri, int32_t ci, int &ln_out) {
+  __device__ float pair(int32_t ri, int32_t ci, float eps2, int &ln_out) {
     const float inf = __builtin_huge_valf();
     const int64_t ro = a.off0[ri], n = a.off0[ri + 1] - ro;
     const int64_t co = a.off1[ci];
@@ -219,7 +219,7 @@ struct Bounded {
           for (int r = 0; r < R; ++r) f = __builtin_fminf(f, Mp[r]);
           if (above && lane == 0) f = __builtin_fminf(f, load_l2(smin + t0 + kGroupB));
           if (store && lane == kWaveB - 1) f = __builtin_fminf(f, bmin);
-          if (__ballot(!(f > a.eps2)) == 0) {
+          if (__ballot(!(f > eps2)) == 0) {
             dead = true;
             break;
           }
@@ -247,12 +247,18 @@ __global__ __launch_bounds__(256, 2) void bounded_kernel(BoundedArgs a) {
     k = __builtin_amdgcn_readfirstlane(k);
     if ((int64_t)k >= a.npairs) break;
     const int32_t idx = a.order[k];
-    const int32_t ri = a.fixed_row >= 0 ? a.fixed_row : idx;
+    int32_t ri = a.fixed_row >= 0 ? a.fixed_row : idx, ci = idx;
+    if (a.col_count > 0) {
+      const int32_t row = idx / (int32_t)a.col_count;
+      ci = idx - row * (int32_t)a.col_count;
+      if (a.fixed_row < 0) ri = row;
+    }
+    const float eps2 = a.row_eps2 ? a.row_eps2[ri] : a.eps2;
     int ln = 0;
-    float v = s.pair(ri, idx, ln);
+    float v = s.pair(ri, ci, eps2, ln);
     if (lane == ln) {
       float o = __builtin_huge_valf();
-      if (v <= a.eps2) o = a.metric == 0 ? (float)__builtin_sqrt((double)v) : v;
+      if (v <= eps2) o = a.metric == 0 ? (float)__builtin_sqrt((double)v) : v;
       a.out[idx] = o;
     }
   }
@@ -278,6 +284,28 @@ __global__ void endpoint_bound_kernel(const float *q, int64_t n, const float *X,
     s1 = __builtin_fmaf(z, z, s1);
   }
   lb[c] = __builtin_fmaxf(s0, s1);
+}
+
+// The same bound for nq queries (CSR offsets q_off) against every curve:
+// lb[i * count + c].
+template <int D>
+__global__ void endpoint_bound_batch_kernel(const float *Q, const int64_t *q_off, int64_t nq, const float *X,
+                                            const int64_t *off, int64_t count, float *lb) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nq * count) return;
+  const int64_t i = g / count, c = g - i * count;
+  const float *q0 = Q + q_off[i] * D, *q1 = Q + (q_off[i + 1] - 1) * D;
+  const float *a0 = X + off[c] * D, *a1 = X + (off[c + 1] - 1) * D;
+  float dx = q0[0] - a0[0], s0 = dx * dx;
+  float ex = q1[0] - a1[0], s1 = ex * ex;
+#pragma unroll
+  for (int k2 = 1; k2 < D; ++k2) {
+    float w = q0[k2] - a0[k2];
+    s0 = __builtin_fmaf(w, w, s0);
+    float z = q1[k2] - a1[k2];
+    s1 = __builtin_fmaf(z, z, s1);
+  }
+  lb[g] = __builtin_fmaxf(s0, s1);
 }
 
 template <int R>
@@ -313,6 +341,22 @@ hipError_t launch_endpoint_bound(int D, const float *q, int64_t n, const float *
     case 2: hipLaunchKernelGGL(endpoint_bound_kernel<2>, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, lb); break;
     case 3: hipLaunchKernelGGL(endpoint_bound_kernel<3>, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, lb); break;
     case 4: hipLaunchKernelGGL(endpoint_bound_kernel<4>, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, lb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_endpoint_bound_batch(int D, const float *Q, const int64_t *q_off, int64_t nq, const float *X,
+                                       const int64_t *off, int64_t count, float *lb, hipStream_t st) {
+  unsigned blocks = (unsigned)((nq * count + 255) / 256);
+  switch (D) {
+#define FFD_EPB_CASE(d)                                                                                           \
+  case d:                                                                                                         \
+    hipLaunchKernelGGL(endpoint_bound_batch_kernel<d>, dim3(blocks), dim3(256), 0, st, Q, q_off, nq, X, off, count, \
+                       lb);                                                                                       \
+    break;
+    FFD_EPB_CASE(1) FFD_EPB_CASE(2) FFD_EPB_CASE(3) FFD_EPB_CASE(4)
+#undef FFD_EPB_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -124,10 +124,11 @@ double pair_steps(int64_t n, int64_t m, int R) {
 }
 
 struct Layout {
-  size_t off0, off1, order, out, counter, lb, rows, total;
+  size_t off0, off1, order, out, counter, lb, eps, rows, total;
 };
 
-Layout layout(int64_t n0, int64_t n1, int64_t npairs, int64_t nout, int64_t nlb, int nwaves, int64_t row_cap) {
+Layout layout(int64_t n0, int64_t n1, int64_t npairs, int64_t nout, int64_t nlb, int nwaves, int64_t row_cap,
+              int64_t neps = 0) {
   Layout L{};
   size_t o = 0;
   L.off0 = o; o = al256(o + (size_t)(n0 + 1) * 8);
@@ -136,6 +137,7 @@ Layout layout(int64_t n0, int64_t n1, int64_t npairs, int64_t nout, int64_t nlb,
   L.out = o; o = al256(o + (size_t)std::max<int64_t>(nout, 1) * 4);
   L.counter = o; o = al256(o + 8);
   L.lb = o; o = al256(o + (size_t)std::max<int64_t>(nlb, 1) * 4);
+  L.eps = o; o = al256(o + (size_t)std::max<int64_t>(neps, 1) * 4);
   L.rows = o; o = al256(o + (size_t)nwaves * 3 * (size_t)row_cap * 4);
   L.total = o;
   return L;
@@ -176,16 +178,24 @@ DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_of
   return d;
 }
 
-// Launch shape and scratch layout of a k-nearest search (the largest
-// stage; the others launch fewer waves).
-DecideShape knn_shape(ffd_ctx *ctx, int64_t n, const int64_t *db_off, int64_t ndb) {
-  int64_t mmax = 0;
+// Launch shape and scratch layout of a k-nearest search of nq queries (the
+// largest stage; the others launch fewer waves): rows per lane for the
+// median query length, the bound, value and order arrays for every
+// (query, curve) pair, one threshold per query.
+DecideShape knn_shape(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb) {
+  int64_t mmax = 0, nmax = 0;
   for (int64_t c = 0; c < ndb; ++c) mmax = std::max(mmax, db_off[c + 1] - db_off[c]);
+  std::vector<int64_t> lens(nq);
+  for (int64_t i = 0; i < nq; ++i) {
+    lens[i] = q_off[i + 1] - q_off[i];
+    nmax = std::max(nmax, lens[i]);
+  }
+  std::nth_element(lens.begin(), lens.begin() + nq / 2, lens.end());
   DecideShape d;
-  d.R = rows_per_lane(n);
-  d.row_cap = n > 64 * d.R ? mmax + 1 : 0;
-  d.nwaves = search_waves(ctx, ndb);
-  d.L = layout(1, ndb, ndb, ndb, ndb, d.nwaves, d.row_cap);
+  d.R = rows_per_lane(lens[nq / 2]);
+  d.row_cap = nmax > 64 * d.R ? mmax + 1 : 0;
+  d.nwaves = search_waves(ctx, nq * ndb);
+  d.L = layout(nq, ndb, nq * ndb, nq * ndb, nq * ndb, d.nwaves, d.row_cap, nq);
   return d;
 }
 
@@ -201,8 +211,8 @@ int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t 
     *bytes = decide_shape(ctx, a_off, b_off, na).L.total;
     return FFD_OK;
   }
-  if (na != 1) return fail(ctx, FFD_E_INVALID, "a k-nearest search takes one query (na == 1)");
-  *bytes = knn_shape(ctx, a_off[1], b_off, nb).L.total;
+  if (na < 1) return fail(ctx, FFD_E_INVALID, "a k-nearest search takes at least one query");
+  *bytes = knn_shape(ctx, a_off, na, b_off, nb).L.total;
   return FFD_OK;
 }
 
@@ -262,120 +272,164 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
   return launch(ctx, a, R, dim, nwaves, st);
 }
 
-int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
-            int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream) {
+int ffd_knn_batch(ffd_ctx *ctx, const float *Q, const int64_t *q_off, int64_t nq, const float *DB,
+                  const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, int32_t k, int64_t *out_idx,
+                  float *out_dist, void *stream) {
   int rc = check_search(ctx, dim, metric);
   if (rc) return rc;
   if (k < 1) return fail(ctx, FFD_E_INVALID, "k must be >= 1");
-  if (n < 1) return fail(ctx, FFD_E_INVALID, "the query must have at least one point");
+  if (nq < 1) return fail(ctx, FFD_E_INVALID, "nq must be >= 1");
   if (ndb < 1) return fail(ctx, FFD_E_INVALID, "the database must hold at least one curve");
-  if (ndb > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many curves");
-  if (!q || !DB || !out_idx || !out_dist) return fail(ctx, FFD_E_INVALID, "NULL pointer");
+  if (nq * ndb > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many (query, curve) pairs");
+  if (!Q || !DB || !out_idx || !out_dist) return fail(ctx, FFD_E_INVALID, "NULL pointer");
+  if ((rc = check_offsets(ctx, q_off, nq, "q_off is NULL"))) return rc;
   if ((rc = check_offsets(ctx, db_off, ndb, "db_off is NULL"))) return rc;
+  for (int64_t i = 0; i < nq; ++i)
+    if (q_off[i + 1] - q_off[i] < 1) return fail(ctx, FFD_E_INVALID, "every query must have at least one point");
   int64_t mmax = 0;
   for (int64_t c = 0; c < ndb; ++c) mmax = std::max(mmax, db_off[c + 1] - db_off[c]);
   if (mmax * dim >= ((int64_t)1 << 31)) return fail(ctx, FFD_E_UNSUPPORTED, "database curve too long");
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipStream_t st = (hipStream_t)stream;
   const int64_t kk = std::min<int64_t>(k, ndb);
-  const DecideShape sh = knn_shape(ctx, n, db_off, ndb);
+  const int64_t np = nq * ndb;
+  const DecideShape sh = knn_shape(ctx, q_off, nq, db_off, ndb);
   const int R = sh.R;
-  const int64_t row_cap = sh.row_cap;
   const Layout &L = sh.L;
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
   char *base = static_cast<char *>(ctx->scratch);
-  // pinned staging: both offset arrays, the bounds, the results, the order
-  const size_t h_off = 0, h_lb = al256((size_t)(ndb + 3) * 8), h_vals = h_lb + al256((size_t)ndb * 4),
-               h_order = h_vals + al256((size_t)ndb * 4), h_total = h_order + al256((size_t)ndb * 4);
+  // pinned staging: both offset arrays, the bounds, the values, the order,
+  // the thresholds
+  const size_t h_off = 0, h_lb = al256((size_t)(nq + ndb + 2) * 8), h_vals = h_lb + al256((size_t)np * 4),
+               h_order = h_vals + al256((size_t)np * 4), h_eps = h_order + al256((size_t)np * 4),
+               h_total = h_eps + al256((size_t)nq * 4);
   if ((rc = search_host(ctx, h_total))) return rc;
   char *hb = static_cast<char *>(ctx->search_host);
   int64_t *hoff = reinterpret_cast<int64_t *>(hb + h_off);
   float *lb = reinterpret_cast<float *>(hb + h_lb);
   float *vals = reinterpret_cast<float *>(hb + h_vals);
   int32_t *horder = reinterpret_cast<int32_t *>(hb + h_order);
-  hoff[0] = 0;
-  hoff[1] = n;
-  memcpy(hoff + 2, db_off, (size_t)(ndb + 1) * 8);
-  hipError_t e = hipMemcpyAsync(base + L.off0, hoff, 2 * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(base + L.off1, hoff + 2, (size_t)(ndb + 1) * 8, hipMemcpyHostToDevice, st);
+  float *heps = reinterpret_cast<float *>(hb + h_eps);
+  memcpy(hoff, q_off, (size_t)(nq + 1) * 8);
+  memcpy(hoff + nq + 1, db_off, (size_t)(ndb + 1) * 8);
+  hipError_t e = hipMemcpyAsync(base + L.off0, hoff, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + L.off1, hoff + nq + 1, (size_t)(ndb + 1) * 8, hipMemcpyHostToDevice, st);
   float *lb_dev = reinterpret_cast<float *>(base + L.lb);
   if (e == hipSuccess)
-    e = ffd::launch_endpoint_bound(dim, q, n, DB, reinterpret_cast<const int64_t *>(base + L.off1), ndb, lb_dev, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(lb, lb_dev, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+    e = ffd::launch_endpoint_bound_batch(dim, Q, reinterpret_cast<const int64_t *>(base + L.off0), nq, DB,
+                                         reinterpret_cast<const int64_t *>(base + L.off1), ndb, lb_dev, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(lb, lb_dev, (size_t)np * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(ctx, e, "search bounds");
-  // the curves with the smallest bounds first (ties by index); the rest is
-  // only split by the threshold later, so no full sort is needed
-  std::vector<int32_t> idx(ndb);
-  std::iota(idx.begin(), idx.end(), 0);
-  auto by_bound = [&](int32_t x, int32_t y) { return lb[x] < lb[y] || (lb[x] == lb[y] && x < y); };
 
   ffd::BoundedArgs a{};
-  a.X0 = q;
+  a.X0 = Q;
   a.X1 = DB;
   a.off0 = reinterpret_cast<const int64_t *>(base + L.off0);
   a.off1 = reinterpret_cast<const int64_t *>(base + L.off1);
   a.order = reinterpret_cast<const int32_t *>(base + L.order);
-  a.fixed_row = 0;
+  a.fixed_row = -1;
+  a.col_count = ndb;
   a.metric = FFD_SQEUCLIDEAN;
   a.out = reinterpret_cast<float *>(base + L.out);
   a.rows = reinterpret_cast<float *>(base + L.rows);
-  a.row_cap = row_cap;
+  a.row_cap = sh.row_cap;
   a.counter = reinterpret_cast<uint32_t *>(base + L.counter);
-  // one stage: exact squared distances of idx[lo, hi) at threshold eps2
-  auto stage = [&](int64_t lo, int64_t hi, float eps2) -> int {
-    if (hi <= lo) return FFD_OK;
-    a.npairs = hi - lo;
-    a.eps2 = eps2;
-    memcpy(horder, idx.data() + lo, (size_t)(hi - lo) * 4);
-    hipError_t err = hipMemcpyAsync(base + L.order, horder, (size_t)(hi - lo) * 4, hipMemcpyHostToDevice, st);
+  // one stage: exact squared distances of the npairs (query, curve) pairs in
+  // horder, each at its query's threshold (heps) or at +inf
+  auto stage = [&](int64_t npairs, bool thresholds) -> int {
+    if (npairs == 0) return FFD_OK;
+    a.npairs = npairs;
+    a.eps2 = std::numeric_limits<float>::infinity();
+    a.row_eps2 = thresholds ? reinterpret_cast<const float *>(base + L.eps) : nullptr;
+    hipError_t err = hipMemcpyAsync(base + L.order, horder, (size_t)npairs * 4, hipMemcpyHostToDevice, st);
+    if (err == hipSuccess && thresholds)
+      err = hipMemcpyAsync(base + L.eps, heps, (size_t)nq * 4, hipMemcpyHostToDevice, st);
     if (err != hipSuccess) return hip_fail(ctx, err, "search upload");
-    int r = launch(ctx, a, R, dim, search_waves(ctx, hi - lo), st);
+    int r = launch(ctx, a, R, dim, search_waves(ctx, npairs), st);
     if (r) return r;
-    err = hipMemcpyAsync(vals, a.out, (size_t)ndb * 4, hipMemcpyDeviceToHost, st);
+    err = hipMemcpyAsync(vals, a.out, (size_t)np * 4, hipMemcpyDeviceToHost, st);
     if (err == hipSuccess) err = hipStreamSynchronize(st);
     if (err != hipSuccess) return hip_fail(ctx, err, "search results");
     return FFD_OK;
   };
-  std::vector<std::pair<float, int32_t>> pool;
-  const int64_t s1 = std::min<int64_t>(ndb, std::max<int64_t>(kk, kStageOne));
-  if (s1 < ndb) {
-    // one wave sweeps one curve, so the longest curve of the first stage
-    // sets its time: take its curves from those no longer than four times
-    // the median length when enough of them exist (any k curves give a
-    // valid threshold; shorter ones give it sooner)
-    std::vector<int64_t> lens(ndb);
-    for (int64_t c = 0; c < ndb; ++c) lens[c] = db_off[c + 1] - db_off[c];
+
+  // per query: the curves with the smallest bounds first (ties by index);
+  // the rest is only split by the threshold later, so no full sort is needed
+  std::vector<int64_t> lens(ndb);
+  for (int64_t c = 0; c < ndb; ++c) lens[c] = db_off[c + 1] - db_off[c];
+  int64_t cap = 0;
+  {
     std::vector<int64_t> tmp(lens);
     std::nth_element(tmp.begin(), tmp.begin() + ndb / 2, tmp.end());
-    const int64_t cap = 4 * tmp[ndb / 2];
-    auto mid = std::partition(idx.begin(), idx.end(), [&](int32_t c) { return lens[c] <= cap; });
-    if (mid - idx.begin() >= s1) std::nth_element(idx.begin(), idx.begin() + s1, mid, by_bound);
-    else std::nth_element(idx.begin(), idx.begin() + s1, idx.end(), by_bound);
+    cap = 4 * tmp[ndb / 2];
   }
-  if ((rc = stage(0, s1, std::numeric_limits<float>::infinity()))) return rc;
-  for (int64_t i = 0; i < s1; ++i) pool.emplace_back(vals[idx[i]], idx[i]);
-  std::sort(pool.begin(), pool.end());
-  const float tau2 = pool[kk - 1].first;
-  const int64_t s2 =
-      std::partition(idx.begin() + s1, idx.end(), [&](int32_t c) { return lb[c] <= tau2; }) - idx.begin();
-  if ((rc = stage(s1, s2, tau2))) return rc;
-  for (int64_t i = s1; i < s2; ++i)
-    if (vals[idx[i]] <= tau2) pool.emplace_back(vals[idx[i]], idx[i]);
-  std::sort(pool.begin(), pool.end());
-  ctx->last_search = ffd_search_info{(int64_t)s1, (int64_t)(s2 - s1), 0};
-  for (int64_t i = s1; i < s2; ++i) ctx->last_search.rejected += std::isinf(vals[idx[i]]) ? 1 : 0;
-  std::vector<int64_t> ri(k, -1);
-  std::vector<float> rd(k, std::numeric_limits<float>::infinity());
-  for (int64_t i = 0; i < kk; ++i) {
-    ri[i] = pool[i].second;
-    rd[i] = metric == FFD_EUCLIDEAN ? (float)std::sqrt((double)pool[i].first) : pool[i].first;
+  const int64_t s1 = std::min<int64_t>(ndb, std::max<int64_t>(kk, kStageOne));
+  std::vector<std::vector<int32_t>> idx(nq);
+  int64_t n1 = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    const float *lbi = lb + i * ndb;
+    std::vector<int32_t> &ix = idx[i];
+    ix.resize(ndb);
+    std::iota(ix.begin(), ix.end(), 0);
+    if (s1 < ndb) {
+      // one wave sweeps one curve, so the longest curve of the first stage
+      // sets its time: take its curves from those no longer than four times
+      // the median length when enough of them exist (any k curves give a
+      // valid threshold; shorter ones give it sooner)
+      auto by_bound = [&](int32_t x, int32_t y) { return lbi[x] < lbi[y] || (lbi[x] == lbi[y] && x < y); };
+      auto mid = std::partition(ix.begin(), ix.end(), [&](int32_t c) { return lens[c] <= cap; });
+      if (mid - ix.begin() >= s1) std::nth_element(ix.begin(), ix.begin() + s1, mid, by_bound);
+      else std::nth_element(ix.begin(), ix.begin() + s1, ix.end(), by_bound);
+    }
+    for (int64_t j = 0; j < s1; ++j) horder[n1++] = (int32_t)(i * ndb + ix[j]);
   }
-  e = hipMemcpyAsync(out_idx, ri.data(), (size_t)k * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(out_dist, rd.data(), (size_t)k * 4, hipMemcpyHostToDevice, st);
+  if ((rc = stage(n1, false))) return rc;
+  std::vector<std::vector<std::pair<float, int32_t>>> pool(nq);
+  std::vector<int64_t> s2(nq);
+  int64_t n2 = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    const float *lbi = lb + i * ndb, *vi = vals + i * ndb;
+    std::vector<int32_t> &ix = idx[i];
+    auto &pl = pool[i];
+    for (int64_t j = 0; j < s1; ++j) pl.emplace_back(vi[ix[j]], ix[j]);
+    std::nth_element(pl.begin(), pl.begin() + (kk - 1), pl.end());
+    const float tau2 = pl[kk - 1].first;
+    heps[i] = tau2;
+    s2[i] = std::partition(ix.begin() + s1, ix.end(), [&](int32_t c) { return lbi[c] <= tau2; }) - ix.begin();
+    for (int64_t j = s1; j < s2[i]; ++j) horder[n2++] = (int32_t)(i * ndb + ix[j]);
+  }
+  if ((rc = stage(n2, true))) return rc;
+  ctx->last_search = ffd_search_info{s1 * nq, n2, 0};
+  std::vector<int64_t> ri((size_t)nq * k, -1);
+  std::vector<float> rd((size_t)nq * k, std::numeric_limits<float>::infinity());
+  for (int64_t i = 0; i < nq; ++i) {
+    const float *vi = vals + i * ndb;
+    std::vector<int32_t> &ix = idx[i];
+    auto &pl = pool[i];
+    for (int64_t j = s1; j < s2[i]; ++j) {
+      if (vi[ix[j]] <= heps[i]) pl.emplace_back(vi[ix[j]], ix[j]);
+      else ctx->last_search.rejected += 1;
+    }
+    std::partial_sort(pl.begin(), pl.begin() + kk, pl.end());
+    for (int64_t j = 0; j < kk; ++j) {
+      ri[i * k + j] = pl[j].second;
+      rd[i * k + j] = metric == FFD_EUCLIDEAN ? (float)std::sqrt((double)pl[j].first) : pl[j].first;
+    }
+  }
+  e = hipMemcpyAsync(out_idx, ri.data(), (size_t)nq * k * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out_dist, rd.data(), (size_t)nq * k * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(ctx, e, "search output");
   return FFD_OK;
+}
+
+int ffd_knn(ffd_ctx *ctx, const float *q, int64_t n, const float *DB, const int64_t *db_off, int64_t ndb,
+            int32_t dim, int32_t metric, int32_t k, int64_t *out_idx, float *out_dist, void *stream) {
+  if (ctx && n < 1) return fail(ctx, FFD_E_INVALID, "the query must have at least one point");
+  const int64_t q_off[2] = {0, n};
+  return ffd_knn_batch(ctx, q, q_off, 1, DB, db_off, ndb, dim, metric, k, out_idx, out_dist, stream);
 }
 
 int ffd_last_search(const ffd_ctx *ctx, ffd_search_info *info) {

@@ -48,7 +48,7 @@ EXPORTS = (
     "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
-    "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_last_search", "ffd_set_scratch",
+    "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_knn_batch", "ffd_last_search", "ffd_set_scratch",
     "ffd_batch_noalloc",
 )
 
@@ -183,6 +183,8 @@ def _load(path=None):
     lib.ffd_decide_batch.restype = ctypes.c_int
     lib.ffd_knn.argtypes = [vp, vp, i64, vp, i64p, i64, i32, i32, i32, vp, vp, vp]
     lib.ffd_knn.restype = ctypes.c_int
+    lib.ffd_knn_batch.argtypes = [vp, vp, i64p, i64, vp, i64p, i64, i32, i32, i32, vp, vp, vp]
+    lib.ffd_knn_batch.restype = ctypes.c_int
     lib.ffd_last_search.argtypes = [vp, ctypes.POINTER(SearchInfo)]
     lib.ffd_last_search.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -383,6 +385,25 @@ def ffd_knn(ctx, q, DB, db_off, k, metric=FFD_EUCLIDEAN, stream=None):
                   lambda: lib.ffd_knn(ctx, qp, q.shape[0], Dp, dop, len(do) - 1, q.shape[1], int(metric), int(k),
                                       ip, dp, _stream(stream)))
     return idx[:k], dist[:k]
+
+
+def ffd_knn_batch(ctx, Q, q_off, DB, db_off, k, metric=FFD_EUCLIDEAN, stream=None):
+    """k nearest database curves of each of nq queries (CSR): (int64
+    indices, float32 distances), device tensors of shape (nq, k)."""
+    Q, Qp = _curve(Q, torch.float32, "Q")
+    DB, Dp = _curve(DB, torch.float32, "DB")
+    if Q.shape[1] != DB.shape[1]:
+        raise ValueError("Q and DB must have the same dimension")
+    qo, qop = _offsets(q_off)
+    do, dop = _offsets(db_off)
+    nq, k = len(qo) - 1, int(k)
+    idx = torch.empty((max(nq, 1), max(k, 1)), dtype=torch.int64, device=Q.device)
+    dist = torch.empty((max(nq, 1), max(k, 1)), dtype=torch.float32, device=Q.device)
+    ip, dp = _dev_ptr(idx, torch.int64, "idx"), _dev_ptr(dist, torch.float32, "dist")
+    _with_scratch(ctx, Q.device, lambda: ffd_workspace_size(ctx, FFD_OP_KNN, qo, do, Q.shape[1]),
+                  lambda: lib.ffd_knn_batch(ctx, Qp, qop, nq, Dp, dop, len(do) - 1, Q.shape[1], int(metric), k,
+                                            ip, dp, _stream(stream)))
+    return idx[:nq, :k], dist[:nq, :k]
 
 
 def ffd_last_search(ctx):
@@ -736,6 +757,9 @@ class Context:
 
     def knn(self, q, DB, db_off, k, metric=FFD_EUCLIDEAN, **kw):
         return ffd_knn(self.handle, q, DB, db_off, k, metric, **kw)
+
+    def knn_batch(self, Q, q_off, DB, db_off, k, metric=FFD_EUCLIDEAN, **kw):
+        return ffd_knn_batch(self.handle, Q, q_off, DB, db_off, k, metric, **kw)
 
     def last_search(self):
         return ffd_last_search(self.handle)

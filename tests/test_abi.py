@@ -300,8 +300,10 @@ def test_scratch_sizes_and_registration(planner):
     _, db_off = workloads.concat([np.zeros((int(k), 2), np.float32) for k in np.arange(20, 220)])
     knn = ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0, 300], db_off, 2)
     assert knn > 200 * 8
-    with pytest.raises(ffd.FFDError):
-        ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0, 30, 60], db_off, 2)  # one query only
+    # several queries (ffd_knn_batch): per-(query, curve) arrays grow with nq
+    knn3 = ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0, 30, 60, 400], db_off, 2)
+    assert knn3 > knn + 2 * 3 * 200 * 4
+    assert ffd.ffd_workspace_size(planner, ffd.FFD_OP_KNN, [0], db_off, 2) == 0  # no query: nothing
     L = ffd.lib
     assert L.ffd_set_scratch(None, None, 0) == ffd.FFD_E_INVALID
     assert L.ffd_set_scratch(planner, None, 64) == ffd.FFD_E_INVALID

@@ -98,6 +98,30 @@ def test_knn_matches_replica(ctx, k):
         assert info["exact"] + info["bounded"] <= 300 and info["rejected"] <= info["bounded"]
 
 
+@pytest.mark.parametrize("k,metric", [(1, 0), (10, 0), (40, 1), (400, 0)])
+def test_knn_batch_matches_replica(ctx, k, metric):
+    """Several queries in one ffd_knn_batch call (lengths spanning one to
+    several bands, so the per-pair row mapping and the per-query thresholds
+    are both exercised): each query's k nearest equal the replica's, and
+    equal ffd_knn of that query alone."""
+    DB, db_off = workloads.serving_db(seed=860 + k, count=300, lo=8, hi=1500)
+    queries = workloads.serving_queries(seed=861 + k, count=7, lo=8, hi=1400)
+    Qs, q_off = workloads.concat(queries)
+    say(f"case: knn batch k={k} metric={metric} nq=7 lengths={[len(q) for q in queries]}")
+    gi, gd = ctx.knn_batch(dev(Qs), q_off, dev(DB), db_off, k, metric=metric)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    assert gi.shape == (7, k) and gd.shape == (7, k)
+    for i, q in enumerate(queries):
+        vals = np.array([oracle.dfd_f32_replica(q, DB[db_off[c]:db_off[c + 1]], metric) for c in range(300)],
+                        dtype=np.float32)
+        want_i, want_d = oracle.knn(vals, k)
+        np.testing.assert_array_equal(gd[i], want_d)
+        np.testing.assert_array_equal(gi[i], want_i)
+        si, sd = ctx.knn(dev(q), dev(DB), db_off, k, metric=metric)
+        np.testing.assert_array_equal(si.cpu().numpy(), gi[i])
+        np.testing.assert_array_equal(sd.cpu().numpy(), gd[i])
+
+
 def test_knn_prunes_and_squared_metric(ctx):
     """A database of noisy copies of a few templates: the nearest curves are
     the query's own template, most others are bounded out or dropped."""
