@@ -81,6 +81,8 @@ extern "C" {
 #define FFD_E_DEVICE (-4)      /* HIP runtime error                                 */
 #define FFD_E_BUSY (-5)        /* serving: no free slot right now                   */
 #define FFD_E_TIMEOUT (-6)     /* serving: wait timed out                           */
+#define FFD_E_CANCELED (-7)    /* serving: request canceled (ffd_server_cancel)     */
+#define FFD_E_EXPIRED (-8)     /* serving: request deadline passed before it ran    */
 
 /* Ground distances (Sec. 2: f(p_i, q_j); Sec. 3: the method makes no
  * assumption about it).  int32 calls take every metric but FFD_EUCLIDEAN
@@ -541,6 +543,22 @@ int ffd_server_poll(ffd_server *s, uint64_t ticket, int32_t *done);
  * Errors: FFD_E_TIMEOUT, FFD_E_INVALID (unknown ticket), FFD_E_DEVICE. */
 int ffd_server_wait(ffd_server *s, uint64_t ticket, int64_t timeout_us);
 
+/* Cancel a submitted request.  A request that is still waiting, or that is
+ * between two of its launches (a long query swept in several), is dropped
+ * at the worker's next scheduling pass: its launch slot and boundary-row
+ * buffers are reclaimed, `out` is left untouched, and poll / wait then
+ * report FFD_E_CANCELED and collect the ticket.  A request whose last
+ * launch is already in flight completes normally.  Thread-safe.
+ * Errors: FFD_E_INVALID (unknown or collected ticket). */
+int ffd_server_cancel(ffd_server *s, uint64_t ticket);
+
+/* Watchdog: every request submitted after this call must have its last
+ * launch issued within timeout_us of its submission (0: no limit, the
+ * default).  One that has not is dropped as ffd_server_cancel drops it and
+ * reports FFD_E_EXPIRED.  Thread-safe.  Errors: FFD_E_INVALID (NULL,
+ * timeout_us < 0). */
+int ffd_server_set_deadline(ffd_server *s, int64_t timeout_us);
+
 typedef struct ffd_server_stats {
   int64_t submitted, completed, failed;
   int64_t deferred;     /* submissions that found no free launch slot */
@@ -550,6 +568,7 @@ typedef struct ffd_server_stats {
   double cells_per_s;   /* DP cells of completed requests per second, same span */
   int32_t requests_per_launch, waves;
   int64_t launches_by_rows[8];  /* launches run with r + 1 rows per lane (r = 0 ... 7) */
+  int64_t canceled, expired;    /* requests dropped by ffd_server_cancel / the deadline */
 } ffd_server_stats;
 
 /* Statistics since creation or the last reset.  Thread-safe. */

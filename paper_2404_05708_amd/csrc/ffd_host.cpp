@@ -1293,6 +1293,8 @@ const char *ffd_strerror(int status) {
     case FFD_E_DEVICE: return "HIP device error";
     case FFD_E_BUSY: return "busy";
     case FFD_E_TIMEOUT: return "timed out";
+    case FFD_E_CANCELED: return "canceled";
+    case FFD_E_EXPIRED: return "deadline passed before the request ran";
   }
   return "unknown status";
 }

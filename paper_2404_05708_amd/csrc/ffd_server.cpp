@@ -90,6 +90,8 @@ struct Request {
   int32_t metric = 0;
   float *out = nullptr;
   double t_submit = 0, t_done = 0;
+  double deadline = 0;  // > 0: its last launch must be issued by then (seconds, now_s clock)
+  bool cancel = false;  // ffd_server_cancel was called
   int state = 0;      // 0 queued, 1 ready for its next item, 3 item in flight, 2 done, < 0 error status
   int R = 0;          // rows per lane of its items (fixed once an item ran)
   int64_t nb = 0;     // bands at R
@@ -174,7 +176,8 @@ struct ffd_server {
   std::thread worker;
   // statistics
   std::vector<double> lat;
-  int64_t submitted = 0, completed = 0, deferred = 0, failed = 0;
+  int64_t submitted = 0, completed = 0, deferred = 0, failed = 0, canceled = 0, expired = 0;
+  int64_t deadline_us = 0;        // watchdog limit of newly submitted requests (0: none)
   int64_t launches_by_rows[kServeR] = {};
   double cells = 0, t_first = 0, t_last = 0;
   std::string last_error;
@@ -603,6 +606,49 @@ void admit(ffd_server &s) {
   }
 }
 
+// The watchdog and cancellation: drop every request that was canceled, or
+// whose deadline has passed, while it is queued or between two of its
+// items (an item in flight finishes first; a request whose last item is in
+// flight completes).  Its out array is never written.  Called with the lock
+// held.
+void expire(ffd_server &s) {
+  const double tn = now_s();
+  auto verdict = [&](const Request *r) {
+    if (r->cancel) return FFD_E_CANCELED;
+    if (r->deadline > 0 && tn > r->deadline) return FFD_E_EXPIRED;
+    return FFD_OK;
+  };
+  auto end = [&](Request *r, int v) {
+    r->state = v;
+    r->t_done = tn;
+    (v == FFD_E_CANCELED ? s.canceled : s.expired)++;
+  };
+  bool any = false;
+  for (auto it = s.pending.begin(); it != s.pending.end();) {
+    int v = verdict(*it);
+    if (v == FFD_OK) {
+      ++it;
+      continue;
+    }
+    end(*it, v);
+    it = s.pending.erase(it);
+    any = true;
+  }
+  for (auto it = s.active.begin(); it != s.active.end();) {
+    Request *r = *it;
+    int v = r->state == 1 ? verdict(r) : FFD_OK;
+    if (v == FFD_OK) {
+      ++it;
+      continue;
+    }
+    release_link(s, r);
+    end(r, v);
+    it = s.active.erase(it);
+    any = true;
+  }
+  if (any) s.cv_done.notify_all();
+}
+
 bool any_ready(const ffd_server &s) {
   for (const Request *r : s.active)
     if (r->state == 1) return true;
@@ -627,6 +673,7 @@ void worker_loop(ffd_server *s) {
         busy = true;
       }
     }
+    expire(*s);
     admit(*s);
     while (any_ready(*s)) {
       Tick *free_tick = nullptr;
@@ -814,6 +861,7 @@ int ffd_server_submit(ffd_server *s, const float *q, int64_t n, int32_t metric, 
   r->t_submit = now_s();
   {
     std::lock_guard<std::mutex> g(s->mu);
+    if (s->deadline_us > 0) r->deadline = r->t_submit + (double)s->deadline_us * 1e-6;
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     bool slot_free = s->pending.empty();
@@ -864,6 +912,26 @@ int ffd_server_wait(ffd_server *s, uint64_t ticket, int64_t timeout_us) {
   return st < 0 ? st : FFD_OK;
 }
 
+int ffd_server_cancel(ffd_server *s, uint64_t ticket) {
+  if (!s) return FFD_E_INVALID;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return sfail(s, FFD_E_INVALID, "unknown or already collected ticket");
+    it->second->cancel = true;
+  }
+  s->cv_work.notify_one();
+  return FFD_OK;
+}
+
+int ffd_server_set_deadline(ffd_server *s, int64_t timeout_us) {
+  if (!s) return FFD_E_INVALID;
+  if (timeout_us < 0) return sfail(s, FFD_E_INVALID, "timeout_us < 0");
+  std::lock_guard<std::mutex> g(s->mu);
+  s->deadline_us = timeout_us;
+  return FFD_OK;
+}
+
 int ffd_server_get_stats(ffd_server *s, ffd_server_stats *out) {
   if (!s || !out) return FFD_E_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
@@ -892,6 +960,8 @@ int ffd_server_get_stats(ffd_server *s, ffd_server_stats *out) {
   out->requests_per_launch = s->kmax;
   out->waves = s->nwaves;
   for (int r = 0; r < kServeR; ++r) out->launches_by_rows[r] = s->launches_by_rows[r];
+  out->canceled = s->canceled;
+  out->expired = s->expired;
   return FFD_OK;
 }
 
@@ -899,7 +969,7 @@ int ffd_server_reset_stats(ffd_server *s) {
   if (!s) return FFD_E_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   s->lat.clear();
-  s->submitted = s->completed = s->deferred = s->failed = 0;
+  s->submitted = s->completed = s->deferred = s->failed = s->canceled = s->expired = 0;
   s->cells = 0;
   s->t_first = s->t_last = 0;
   for (int64_t &c : s->launches_by_rows) c = 0;

@@ -27,6 +27,8 @@ FFD_E_NOMEM = -3
 FFD_E_DEVICE = -4
 FFD_E_BUSY = -5
 FFD_E_TIMEOUT = -6
+FFD_E_CANCELED = -7
+FFD_E_EXPIRED = -8
 FFD_EUCLIDEAN = 0
 FFD_SQEUCLIDEAN = 1
 FFD_MANHATTAN = 2
@@ -45,7 +47,8 @@ EXPORTS = (
     "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
     "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
-    "ffd_server_last_error", "ffd_autotune_batch", "ffd_autotune_cross",
+    "ffd_server_last_error", "ffd_server_cancel", "ffd_server_set_deadline", "ffd_autotune_batch",
+    "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
     "ffd_levenshtein_cross", "ffd_decide_batch", "ffd_knn", "ffd_knn_batch", "ffd_last_search", "ffd_set_scratch",
@@ -103,7 +106,8 @@ class ServerStats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("qps", ctypes.c_double), ("cells_per_s", ctypes.c_double),
                 ("requests_per_launch", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("launches_by_rows", ctypes.c_int64 * 8)]
+                ("launches_by_rows", ctypes.c_int64 * 8), ("canceled", ctypes.c_int64),
+                ("expired", ctypes.c_int64)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -210,6 +214,10 @@ def _load(path=None):
     lib.ffd_server_reset_stats.restype = ctypes.c_int
     lib.ffd_server_last_error.argtypes = [vp]
     lib.ffd_server_last_error.restype = ctypes.c_char_p
+    lib.ffd_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.ffd_server_cancel.restype = ctypes.c_int
+    lib.ffd_server_set_deadline.argtypes = [vp, i64]
+    lib.ffd_server_set_deadline.restype = ctypes.c_int
     return lib
 
 
@@ -832,14 +840,19 @@ class Server:
         if rc != FFD_OK:
             raise FFDError(rc, f"{lib.ffd_strerror(rc).decode()}: {lib.ffd_server_last_error(self.handle).decode()}")
 
-    def submit(self, q, metric=FFD_EUCLIDEAN):
-        """Submit a (n, dim) float32 host array; returns a ticket."""
+    def submit(self, q, metric=FFD_EUCLIDEAN, out=None):
+        """Submit a (n, dim) float32 host array; returns a ticket.  `out` (a
+        float32 array of ndb entries) receives the results, a new one if
+        None."""
         q = np.ascontiguousarray(q, dtype=np.float32)
         if q.ndim == 1:
             q = q.reshape(-1, 1)
         if q.shape[1] != self.db.dim:
             raise ValueError("query dimension differs from the database's")
-        out = np.empty(self.db.ndb, dtype=np.float32)
+        if out is None:
+            out = np.empty(self.db.ndb, dtype=np.float32)
+        elif out.dtype != np.float32 or out.shape != (self.db.ndb,) or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous float32 array of ndb entries")
         t = ctypes.c_uint64()
         self._check(lib.ffd_server_submit(self.handle, q.ctypes.data_as(ctypes.c_void_p), q.shape[0],
                                           int(metric), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
@@ -847,16 +860,30 @@ class Server:
         return t.value
 
     def poll(self, ticket):
-        """The result array once the request has finished, else None."""
+        """The result array once the request has finished, else None; a
+        failed, canceled or expired request raises FFDError (its ticket is
+        collected)."""
         done = ctypes.c_int32()
-        self._check(lib.ffd_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done)))
+        rc = lib.ffd_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done))
+        if rc != FFD_OK:
+            self._live.pop(ticket, None)
+            self._check(rc)
         if not done.value:
             return None
         return self._live.pop(ticket)[1]
 
     def wait(self, ticket, timeout_us=-1):
-        self._check(lib.ffd_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us)))
+        rc = lib.ffd_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us))
+        if rc not in (FFD_OK, FFD_E_TIMEOUT):  # a timed-out wait leaves the ticket uncollected
+            self._live.pop(ticket, None)
+        self._check(rc)
         return self._live.pop(ticket)[1]
+
+    def cancel(self, ticket):
+        self._check(lib.ffd_server_cancel(self.handle, ctypes.c_uint64(ticket)))
+
+    def set_deadline(self, timeout_us):
+        self._check(lib.ffd_server_set_deadline(self.handle, int(timeout_us)))
 
     def stats(self):
         st = ServerStats()

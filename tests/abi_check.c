@@ -33,6 +33,8 @@ int main(void) {
   FIELD(ffd_server_stats, p50_ms);
   FIELD(ffd_server_stats, requests_per_launch);
   FIELD(ffd_server_stats, launches_by_rows);
+  FIELD(ffd_server_stats, canceled);
+  FIELD(ffd_server_stats, expired);
 
   /* a planning-only context: 256 compute units, 160 KiB of LDS per block */
   ffd_ctx *ctx = NULL;

@@ -189,5 +189,65 @@ def test_long_queries_in_items(served):
     assert np.all(np.abs(got[("L", 1)].astype(np.float64) - want) <= TOL * np.abs(want))
 
 
+def test_cancel_and_deadline(served):
+    """A request canceled while it waits, or between two of its launches,
+    reports FFD_E_CANCELED and its results array is never written; the
+    watchdog drops a long query whose next launch would come after its
+    deadline (FFD_E_EXPIRED); requests around them complete with their usual
+    bits."""
+    ffd, ctx, DB, dbo, DBd, srv = served
+    rng = np.random.default_rng(57)
+    longs = [workloads.walk(rng, 8192, 2) for _ in range(10)]
+    short = workloads.walk(rng, 300, 2)
+    alone_short = srv.wait(srv.submit(short)).copy()
+    srv.reset_stats()
+    ndb = len(dbo) - 1
+    sentinel = np.float32(-7.0)
+    outs = [np.full(ndb, sentinel, dtype=np.float32) for _ in longs]
+    # 10 queries that each need a boundary-row buffer pair; the server has 8
+    say("case: serving, cancel two waiting long queries and one running")
+    tickets = [srv.submit(q, out=o) for q, o in zip(longs, outs)]
+    for t in (tickets[-1], tickets[-2], tickets[0]):
+        srv.cancel(t)
+    for j in (-1, -2):
+        with pytest.raises(ffd.FFDError) as ei:
+            srv.wait(tickets[j])
+        assert ei.value.status == ffd.FFD_E_CANCELED
+        assert np.all(outs[j] == sentinel)
+    try:
+        srv.wait(tickets[0])
+        first_canceled = False
+    except ffd.FFDError as e:
+        assert e.status == ffd.FFD_E_CANCELED
+        assert np.all(outs[0] == sentinel)
+        first_canceled = True
+    done = [srv.wait(t).copy() for t in tickets[1:-2]]
+    Qs, qo = workloads.concat(longs[1:3])
+    cross = ctx.cross(torch.from_numpy(Qs).to("cuda:0"), qo, DBd, dbo).cpu().numpy()
+    np.testing.assert_array_equal(done[0], cross[0])
+    np.testing.assert_array_equal(done[1], cross[1])
+    st = srv.stats()
+    say(f"stats after cancel: {st}")
+    assert st["canceled"] == 2 + int(first_canceled) and st["completed"] == 7 + int(not first_canceled)
+    say("case: serving, deadline of 100 us on a long query")
+    srv.set_deadline(100)
+    try:
+        out = np.full(ndb, sentinel, dtype=np.float32)
+        t = srv.submit(longs[3], out=out)
+        with pytest.raises(ffd.FFDError) as ei:
+            srv.wait(t)
+        assert ei.value.status == ffd.FFD_E_EXPIRED
+        assert np.all(out == sentinel)
+    finally:
+        srv.set_deadline(0)
+    np.testing.assert_array_equal(srv.wait(srv.submit(short)), alone_short)
+    st = srv.stats()
+    assert st["expired"] == 1
+    with pytest.raises(ffd.FFDError):
+        srv.cancel(123456789)  # unknown ticket
+    with pytest.raises(ffd.FFDError):
+        srv.set_deadline(-1)
+
+
 def srv_items_per_launch(st):
     return max(1, st["requests_per_launch"])
