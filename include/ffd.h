@@ -421,6 +421,19 @@ int ffd_autotune_cross(ffd_ctx *ctx, const float *Qs, const int64_t *q_off, int6
                        const int64_t *db_off, int64_t ndb, int32_t dim, int32_t metric, float *out,
                        void *workspace, size_t ws_bytes, void *stream, ffd_tuning *best);
 
+/* Keep autotune results on disk: `path` names a JSON file (NULL or "": none,
+ * the default; a context made by ffd_create takes the environment variable
+ * FFD_TUNE_CACHE).  Its entries are read now.  Every later autotune call
+ * adds its choice to the file, under the class of the request: gfx950 and
+ * its compute units, the operation, the kernel (measure and ground
+ * distance), the value type, D, and log2 buckets of the mean lengths and
+ * the curve counts of both sides.  A request that has no tuned shape of its
+ * own and runs with automatic settings uses the file's shape for its class;
+ * an entry of zeros keeps the model's choice.  A missing file counts as
+ * empty, and lines that do not parse are skipped.  Errors: FFD_E_INVALID
+ * (NULL ctx). */
+int ffd_set_tune_cache(ffd_ctx *ctx, const char *path);
+
 /* ------------------------------------------- decider and k-nearest search ---
  * Early abandoning (Eq. (1): M_ij is the smallest, over monotone paths to
  * (i, j), of the largest cell on the path, so delta is at least the smallest

@@ -27,6 +27,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <queue>
@@ -998,8 +999,60 @@ struct MeasureScope {
   ~MeasureScope() { ctx->measure = saved; }
 };
 
+// The class of a request in the on-disk autotune cache: the target (gfx950
+// and its compute units), the operation, the kernel (measure and ground
+// distance), the value type and D, and log2 buckets of the mean row and
+// column curve lengths and of the number of curves on each side.
+std::string tune_class(const ffd_ctx *c, int op, int D, bool exact, const int64_t *a, int64_t na,
+                       const int64_t *b, int64_t nb) {
+  auto lg = [](double x) { return x < 1 ? 0 : (int)std::lround(std::log2(x)); };
+  char buf[160];
+  snprintf(buf, sizeof buf, "gfx950/cu%d/op%d/k%d/%s/D%d/L%d/M%d/N%d/Q%d", c->cus, op, c->measure,
+           exact ? "i32" : "f32", D, lg((double)a[na] / (double)na), lg((double)b[nb] / (double)nb), lg((double)na),
+           lg((double)nb));
+  return buf;
+}
+
+// The cache file: a JSON object, one entry per line,
+//   "class": {"rows_per_lane": R, "waves_per_simd": W, "split": S},
+// R = W = S = 0 meaning that the model's own choice was the fastest.
+void load_tune_cache(ffd_ctx *c) {
+  c->tune_file.clear();
+  FILE *f = c->tune_cache_path.empty() ? nullptr : fopen(c->tune_cache_path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char key[256];
+    int R = 0, W = 0;
+    float S = 0.f;
+    if (sscanf(line, " \"%255[^\"]\": {\"rows_per_lane\": %d, \"waves_per_simd\": %d, \"split\": %f", key, &R, &W,
+               &S) == 4) {
+      if ((R == 0 || R == 1 || R == 2 || R == 4 || R == 8) && W >= 0 && W <= 8 && S == S)
+        c->tune_file[key] = ffd_tuning{R, W, S, -1.f, -1.f, 0};
+    }
+  }
+  fclose(f);
+}
+
+void save_tune_cache(const ffd_ctx *c) {
+  if (c->tune_cache_path.empty()) return;
+  std::string tmp = c->tune_cache_path + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto &kv : c->tune_file)
+    fprintf(f, "\"%s\": {\"rows_per_lane\": %d, \"waves_per_simd\": %d, \"split\": %.6g}%s\n", kv.first.c_str(),
+            kv.second.rows_per_lane, kv.second.waves_per_simd, kv.second.split,
+            ++i < c->tune_file.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  std::rename(tmp.c_str(), c->tune_cache_path.c_str());
+}
+
 // With automatic settings, a launch shape the autotuner chose for this
-// request replaces the model's choice for the duration of the call.
+// request (or, failing that, for its class in the cache file) replaces the
+// model's choice for the duration of the call.
 struct TunedScope {
   ffd_ctx *ctx;
   int R, W;
@@ -1007,13 +1060,21 @@ struct TunedScope {
   bool active = false;
   TunedScope(ffd_ctx *c, int op, int D, bool exact, const int64_t *a, int64_t na, const int64_t *b, int64_t nb)
       : ctx(c), R(c->tune_R), W(c->tune_W), split(c->split) {
-    if (c->tune_R || c->tune_W || c->split != 0.f || c->tuned.empty()) return;
-    ReqKey k = req_key(req_of(c, op, D, exact, a, na, b, nb, true));
-    auto it = c->tuned.find(k.hash);
-    if (it == c->tuned.end() || it->second.first.words != k.words) return;
-    c->tune_R = it->second.second.rows_per_lane;
-    c->tune_W = it->second.second.waves_per_simd;
-    c->split = it->second.second.split;
+    if (c->tune_R || c->tune_W || c->split != 0.f) return;
+    const ffd_tuning *t = nullptr;
+    if (!c->tuned.empty()) {
+      ReqKey k = req_key(req_of(c, op, D, exact, a, na, b, nb, true));
+      auto it = c->tuned.find(k.hash);
+      if (it != c->tuned.end() && it->second.first.words == k.words) t = &it->second.second;
+    }
+    if (!t && !c->tune_file.empty() && na > 0 && nb > 0) {
+      auto it = c->tune_file.find(tune_class(c, op, D, exact, a, na, b, nb));
+      if (it != c->tune_file.end()) t = &it->second;
+    }
+    if (!t) return;
+    c->tune_R = t->rows_per_lane;
+    c->tune_W = t->waves_per_simd;
+    c->split = t->split;
     active = true;
   }
   ~TunedScope() {
@@ -1238,6 +1299,9 @@ int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t 
   float S0 = ctx->split;
   ReqKey base = req_key(req_of(ctx, op, D, exact, a, na, b, nb, true));
   ctx->tuned.erase(base.hash);
+  // time the model's own choice, not a shape from the cache file
+  std::map<std::string, ffd_tuning> file = std::move(ctx->tune_file);
+  ctx->tune_file.clear();
   ffd_tuning best{0, 0, 0.f, -1.f, -1.f, 0};
   ctx->tune_R = ctx->tune_W = 0;
   ctx->split = 0.f;
@@ -1263,6 +1327,7 @@ int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t 
   ctx->tune_R = R0;
   ctx->tune_W = W0;
   ctx->split = S0;
+  ctx->tune_file = std::move(file);
   if (best.ms < 0) return fail(ctx, FFD_E_UNSUPPORTED, "no launch shape could run");
   if (best.ms_planner > 0 && best.ms_planner <= best.ms) {
     // the planner's own choice is as fast: keep using the model
@@ -1271,6 +1336,10 @@ int autotune(ffd_ctx *ctx, int op, int D, bool exact, const int64_t *a, int64_t 
     best.ms = best.ms_planner;
   } else {
     ctx->tuned[base.hash] = std::make_pair(base, best);
+  }
+  if (!ctx->tune_cache_path.empty()) {
+    ctx->tune_file[tune_class(ctx, op, D, exact, a, na, b, nb)] = best;
+    save_tune_cache(ctx);
   }
   if (best_out) *best_out = best;
   return FFD_OK;
@@ -1327,6 +1396,10 @@ int ffd_create(int device, ffd_ctx **out) {
   if (!ok || noalloc_setup(c, device) != FFD_OK) {
     ffd_destroy(c);
     return FFD_E_DEVICE;
+  }
+  if (const char *path = std::getenv("FFD_TUNE_CACHE")) {
+    c->tune_cache_path = path;
+    load_tune_cache(c);
   }
   *out = c;
   return FFD_OK;
@@ -1402,6 +1475,13 @@ int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd) 
     return fail(ctx, FFD_E_INVALID, "waves_per_simd must be -1 .. 8");
   ctx->tune_R = rows_per_lane;
   ctx->tune_W = waves_per_simd;
+  return FFD_OK;
+}
+
+int ffd_set_tune_cache(ffd_ctx *ctx, const char *path) {
+  if (!ctx) return FFD_E_INVALID;
+  ctx->tune_cache_path = path ? path : "";
+  load_tune_cache(ctx);
   return FFD_OK;
 }
 
@@ -1630,6 +1710,7 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   if (op == FFD_OP_PAIR && na != 1) return fail(ctx, FFD_E_INVALID, "a pair has one curve per side");
   if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
+  TunedScope tuned(ctx, op, dim, ex, a_off, na, b_off, nb);
   Plan pl;
   if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, dim, ex, pl);
   else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, dim, ex, pl);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -176,6 +177,10 @@ struct ffd_ctx {
   ffdi::PlanCache batch_plans, pair_plans;
   // launch shapes chosen by the autotuner, by request (offsets, op, dim, type)
   std::unordered_map<uint64_t, std::pair<ffdi::ReqKey, ffd_tuning>> tuned;
+  // autotune results kept on disk by request class (ffd_set_tune_cache or
+  // FFD_TUNE_CACHE): used for requests with no tuned shape of their own
+  std::string tune_cache_path;
+  std::map<std::string, ffd_tuning> tune_file;
   // device scratch registered by the caller (ffd_set_scratch): long single
   // pairs and the search calls; not owned
   void *scratch = nullptr;

@@ -47,7 +47,8 @@ EXPORTS = (
     "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
     "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
-    "ffd_server_last_error", "ffd_server_cancel", "ffd_server_set_deadline", "ffd_autotune_batch",
+    "ffd_server_last_error", "ffd_server_cancel", "ffd_server_set_deadline", "ffd_set_tune_cache",
+    "ffd_autotune_batch",
     "ffd_autotune_cross",
     "ffd_dtw_distance", "ffd_dtw_distance_i32", "ffd_dtw_batch", "ffd_dtw_batch_i32", "ffd_dtw_cross",
     "ffd_dtw_cross_i32", "ffd_plan_describe", "ffd_levenshtein_distance", "ffd_levenshtein_batch",
@@ -218,6 +219,8 @@ def _load(path=None):
     lib.ffd_server_cancel.restype = ctypes.c_int
     lib.ffd_server_set_deadline.argtypes = [vp, i64]
     lib.ffd_server_set_deadline.restype = ctypes.c_int
+    lib.ffd_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
+    lib.ffd_set_tune_cache.restype = ctypes.c_int
     return lib
 
 
@@ -352,6 +355,10 @@ def ffd_last_errors(ctx):
     v = ctypes.c_int32()
     _check(lib.ffd_last_errors(ctx, ctypes.byref(v)), ctx)
     return v.value
+
+
+def ffd_set_tune_cache(ctx, path):
+    _check(lib.ffd_set_tune_cache(ctx, None if path is None else os.fsencode(path)), ctx)
 
 
 def ffd_set_split(ctx, share=0.0):
@@ -705,6 +712,9 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tune_cache(self, path):
+        ffd_set_tune_cache(self.handle, path)
 
     def set_tuning(self, rows_per_lane=0, waves_per_simd=0):
         ffd_set_tuning(self.handle, rows_per_lane, waves_per_simd)

@@ -257,6 +257,39 @@ def test_cross_int_workload_full_size_sampled(ctx):
     np.testing.assert_array_equal(got[row], want)
 
 
+def test_autotune_cache_file(ctx, tmp_path):
+    """With a cache file, the autotuner writes its choice under the
+    request's class, and a new context reading the file runs that shape for
+    another request of the class, with the same bits."""
+    from paper_2404_05708_amd import ffd
+    P, p_off, Q, q_off = workloads.random_pairs(62, 300, 64, 1500, dim=2)
+    path = tmp_path / "tune.json"
+    say("case: autotune with a cache file")
+    other = ffd.Context(0)
+    try:
+        other.set_tune_cache(str(path))
+        t = other.autotune_batch(dev(P), p_off, dev(Q), q_off)
+        entries = json.loads(path.read_text())
+        assert len(entries) == 1
+        (cls, e), = entries.items()
+        assert cls.startswith("gfx950/") and e["rows_per_lane"] == t["rows_per_lane"]
+    finally:
+        other.close()
+    # the same pairs in reverse order: another request of the same class
+    P2, p2 = workloads.concat([P[p_off[i]:p_off[i + 1]] for i in range(299, -1, -1)])
+    Q2, q2 = workloads.concat([Q[q_off[i]:q_off[i + 1]] for i in range(299, -1, -1)])
+    base = ctx.batch(dev(P2), p2, dev(Q2), q2).cpu().numpy()
+    fresh = ffd.Context(0)
+    try:
+        fresh.set_tune_cache(str(path))
+        got = fresh.batch(dev(P2), p2, dev(Q2), q2).cpu().numpy()
+        np.testing.assert_array_equal(got, base)
+        if t["rows_per_lane"]:
+            assert fresh.last_launch()["rows_per_lane"] == t["rows_per_lane"]
+    finally:
+        fresh.close()
+
+
 def test_split_bands_bit_identical(ctx):
     """Bands split over waves (boundary rows through global links) give the
     same bits as the unsplit plan, in batch, cross and single-pair form."""
