@@ -29,6 +29,7 @@ Printed: one JSON line with the metric, the roofline of the dominant kernel
 pair), and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -65,12 +66,20 @@ def imin(dim, exact=False, cell="euclidean"):
 
 
 def time_steps(step, steps, sync):
-    sync()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    sync()
-    return (time.perf_counter() - t0) / steps
+    # Python's cyclic garbage collector can pause the host for milliseconds
+    # in the middle of the loop (each call builds a few small objects):
+    # collect before the timed region and keep it off during it
+    gc.collect()
+    gc.disable()
+    try:
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        sync()
+        return (time.perf_counter() - t0) / steps
+    finally:
+        gc.enable()
 
 
 def kernel_ms(torch, step, steps, stream):
@@ -691,6 +700,8 @@ def serve_open_loop(srv, queries, rate, nwarm, nmeas, seed=7):
             srv.wait(item)
 
     th = threading.Thread(target=collect)
+    gc.collect()
+    gc.disable()  # no collector pauses in the client's arrival schedule
     th.start()
     t0 = time.perf_counter()
     tm = None
@@ -707,6 +718,7 @@ def serve_open_loop(srv, queries, rate, nwarm, nmeas, seed=7):
     pend.put(None)
     th.join()
     wall = time.perf_counter() - (tm if tm is not None else t0)
+    gc.enable()
     return srv.stats(), wall
 
 
