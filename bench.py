@@ -818,8 +818,9 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps first (the GPU clock ramps up over the first tens of milliseconds)")
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
                                            "geo", "geo_dtw", "knn", "decide"],
                     default="batched")
