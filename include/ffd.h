@@ -454,7 +454,10 @@ int ffd_set_tune_cache(ffd_ctx *ctx, const char *path);
 /* Decider: out[k] = delta(P_k, Q_k) when it is <= eps (the same value as
  * ffd_batch), else +inf, so that out[k] <= eps answers "is delta <= eps?".
  * Arguments as ffd_batch without the workspace; eps is a distance in the
- * metric's units (+inf: no pair is dropped; below 0: every pair is).
+ * metric's units (+inf: no pair can be dropped, and the call runs ffd_batch
+ * in the registered scratch; below 0: every pair is dropped).  Each pair is
+ * swept with the curve whose bands waste fewer rows as the row curve (the
+ * distance is symmetric).
  * Asynchronous on `stream`; offsets are HOST arrays, read before return.
  * Errors: FFD_E_INVALID (NULL, bad offsets, NaN eps, unknown metric, dim <
  * 1), FFD_E_UNSUPPORTED (metric, dim > FFD_MAX_DIM, a column curve of 2^31

@@ -10,7 +10,8 @@ namespace ffd {
 struct BoundedArgs {
   const float *X0, *X1;        // coordinates of the row curves and of the column curves
   const int64_t *off0, *off1;  // their offsets in points (device)
-  const int32_t *order;        // work item k -> pair index (the output index)
+  const int32_t *order;        // work item k -> pair index (the output index); the top bit set:
+                               // the pair's curves swap roles (decider: no fixed row or mapping)
   int32_t fixed_row;           // >= 0: row curve of every pair; -1: the pair index (or, with
                                // col_count > 0, pair / col_count)
   int64_t col_count;           // > 0: pair p is row curve p / col_count against column curve

@@ -122,12 +122,21 @@ struct Bounded {
 
   // One pair; returns the value lane `ln` holds for M_{n-1,m-1} (squared),
   // or +inf on every lane when the pair was abandoned.
-  __device__ float pair(int32_t ri, int32_t ci, float eps2, int &ln_out) {
+  // (swap: the pair's curves exchange roles, row curve ci of the second set
+  // against column curve ri of the first; the distance is symmetric)
+  __device__ float pair(int32_t ri, int32_t ci, bool swap, float eps2, int &ln_out) {
     const float inf = __builtin_huge_valf();
-    const int64_t ro = a.off0[ri], n = a.off0[ri + 1] - ro;
-    const int64_t co = a.off1[ci];
-    const int32_t m = (int32_t)(a.off1[ci + 1] - co);
-    const float *qb = a.X1 + co * D;
+    const float *Xr = swap ? a.X1 : a.X0, *Xc = swap ? a.X0 : a.X1;
+    const int64_t *offr = swap ? a.off1 : a.off0, *offc = swap ? a.off0 : a.off1;
+    if (swap) {
+      const int32_t t = ri;
+      ri = ci;
+      ci = t;
+    }
+    const int64_t ro = offr[ri], n = offr[ri + 1] - ro;
+    const int64_t co = offc[ci];
+    const int32_t m = (int32_t)(offc[ci + 1] - co);
+    const float *qb = Xc + co * D;
     const int64_t band_rows = (int64_t)kWaveB * R;
     const int nb = (int)((n + band_rows - 1) / band_rows);
     const int64_t last = (n - 1) - (int64_t)(nb - 1) * band_rows;
@@ -145,7 +154,7 @@ struct Bounded {
         int64_t i = (int64_t)b * band_rows + (int64_t)lane * R + r;
         if (i > n - 1) i = n - 1;
 #pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) p[r][k2] = a.X0[(ro + i) * D + k2];
+        for (int k2 = 0; k2 < D; ++k2) p[r][k2] = Xr[(ro + i) * D + k2];
       }
       float Mp[R];
 #pragma unroll
@@ -246,7 +255,11 @@ __global__ __launch_bounds__(256, 2) void bounded_kernel(BoundedArgs a) {
     if (lane == 0) k = atomicAdd(a.counter, 1u);
     k = __builtin_amdgcn_readfirstlane(k);
     if ((int64_t)k >= a.npairs) break;
-    const int32_t idx = a.order[k];
+    // the top bit of a work item marks a pair swept with its curves' roles
+    // exchanged (decider only: no fixed row, no (row, column) mapping)
+    const int32_t raw = a.order[k];
+    const bool swap = raw < 0;
+    const int32_t idx = raw & 0x7fffffff;
     int32_t ri = a.fixed_row >= 0 ? a.fixed_row : idx, ci = idx;
     if (a.col_count > 0) {
       const int32_t row = idx / (int32_t)a.col_count;
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void bounded_kernel(BoundedArgs a) {
     }
     const float eps2 = a.row_eps2 ? a.row_eps2[ri] : a.eps2;
     int ln = 0;
-    float v = s.pair(ri, ci, eps2, ln);
+    float v = s.pair(ri, ci, swap, eps2, ln);
     if (lane == ln) {
       float o = __builtin_huge_valf();
       if (v <= eps2) o = a.metric == 0 ? (float)__builtin_sqrt((double)v) : v;

@@ -1220,7 +1220,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
 
 int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *Q, const int64_t *q_off,
                  int64_t npairs, int32_t dim, int32_t metric, void *out, void *ws, size_t ws_bytes, hipStream_t st,
-                 bool exact, bool noalloc = false) {
+                 bool exact, bool noalloc = false, UseOrder *use = nullptr) {
   int rc = check_common(ctx, dim, metric, exact);
   if (rc) return rc;
   if (npairs < 0) return fail(ctx, FFD_E_INVALID, "npairs < 0");
@@ -1235,7 +1235,7 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
   if (rc) return rc;
   return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st,
-                  ctx->ws_use, noalloc);
+                  use ? *use : ctx->ws_use, noalloc);
 }
 
 int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq, const void *DB,
@@ -1551,6 +1551,13 @@ int batch_noalloc(ffd_ctx *ctx, const float *P, const int64_t *p_off, const floa
   bool exact = false;
   if (int rc = geo_shape(ctx, metric, dim, exact)) return rc;
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, ws, ws_bytes, st, exact, true);
+}
+
+int batch_in_scratch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                     int64_t npairs, int32_t dim, int32_t metric, float *out, hipStream_t st) {
+  MeasureScope scope(ctx, op_of(false, metric, true));
+  return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, ctx->scratch, ctx->scratch_bytes, st, false,
+                      false, &ctx->scratch_use);
 }
 
 }  // namespace ffdi

@@ -233,6 +233,11 @@ size_t noalloc_bytes();
 int batch_noalloc(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
                   int64_t npairs, int32_t dim, int32_t metric, float *out, void *ws, size_t ws_bytes, hipStream_t st);
 
+// ffd_batch (float32, Euclidean or squared) with the registered scratch as
+// the workspace: the decider at eps = +inf, where no pair can be dropped.
+int batch_in_scratch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q, const int64_t *q_off,
+                     int64_t npairs, int32_t dim, int32_t metric, float *out, hipStream_t st);
+
 int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
                bool exact, Plan &pl);
 int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq, const void *DB,

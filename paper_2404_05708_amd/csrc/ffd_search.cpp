@@ -157,22 +157,31 @@ struct DecideShape {
   Layout L;
 };
 
-DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs) {
-  int64_t nsum = 0, mmax = 0, nmax = 0;
-  for (int64_t k = 0; k < npairs; ++k) {
-    nsum += p_off[k + 1] - p_off[k];
-    nmax = std::max(nmax, p_off[k + 1] - p_off[k]);
-    mmax = std::max(mmax, q_off[k + 1] - q_off[k]);
-  }
+// Each pair is swept with the curve whose bands waste the fewest rows (and
+// ramp steps) as the row curve: swap[k] when Q_k takes that role.
+DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs,
+                         std::vector<uint8_t> *swap = nullptr) {
+  int64_t nsum = 0;
+  for (int64_t k = 0; k < npairs; ++k) nsum += p_off[k + 1] - p_off[k];
   DecideShape d;
   d.R = rows_per_lane(nsum / npairs);
-  d.row_cap = nmax > 64 * d.R ? mmax + 1 : 0;
+  if (swap) swap->assign(npairs, 0);
+  int64_t cmax = 0;
+  bool banded = false;
   double total = 0, longest = 0;
   for (int64_t k = 0; k < npairs; ++k) {
-    double st = pair_steps(p_off[k + 1] - p_off[k], q_off[k + 1] - q_off[k], d.R);
+    const int64_t n = p_off[k + 1] - p_off[k], m = q_off[k + 1] - q_off[k];
+    const double a = pair_steps(n, m, d.R), b = pair_steps(m, n, d.R);
+    const bool sw = b < a;
+    if (swap) (*swap)[k] = sw ? 1 : 0;
+    const int64_t rows = sw ? m : n, cols = sw ? n : m;
+    banded = banded || rows > 64 * d.R;
+    cmax = std::max(cmax, cols);
+    const double st = sw ? b : a;
     total += st;
     longest = std::max(longest, st);
   }
+  d.row_cap = banded ? cmax + 1 : 0;
   d.nwaves = search_waves(ctx, npairs, total, longest);
   d.L = layout(npairs, npairs, npairs, 0, 0, d.nwaves, d.row_cap);
   return d;
@@ -208,7 +217,11 @@ int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t 
   (void)dim;
   if (op == FFD_OP_DECIDE) {
     if (na != nb) return fail(ctx, FFD_E_INVALID, "the decider needs na == nb");
-    *bytes = decide_shape(ctx, a_off, b_off, na).L.total;
+    // eps = +inf runs ffd_batch in the same scratch
+    size_t batch = 0;
+    int rc = ffd_workspace_size(ctx, FFD_OP_BATCH, a_off, na, b_off, nb, dim, &batch);
+    if (rc) return rc;
+    *bytes = std::max(decide_shape(ctx, a_off, b_off, na).L.total, batch);
     return FFD_OK;
   }
   if (na < 1) return fail(ctx, FFD_E_INVALID, "a k-nearest search takes at least one query");
@@ -236,18 +249,29 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
   if (mmax * dim >= ((int64_t)1 << 31)) return fail(ctx, FFD_E_UNSUPPORTED, "column curve too long");
   if (ctx->device < 0) return fail(ctx, FFD_E_DEVICE, "planning-only context cannot launch");
   hipStream_t st = (hipStream_t)stream;
-  const DecideShape sh = decide_shape(ctx, p_off, q_off, npairs);
+  if (std::isinf(eps) && eps > 0) {
+    // no pair can be dropped: the decider is a batch, and the streaming
+    // kernel computes it faster than the early-abandoning sweep (the
+    // batch's own check reports a scratch too small for its plan)
+    if ((rc = search_scratch(ctx, 0, st))) return rc;
+    return batch_in_scratch(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, st);
+  }
+  std::vector<uint8_t> swap;
+  const DecideShape sh = decide_shape(ctx, p_off, q_off, npairs, &swap);
   const int R = sh.R, nwaves = sh.nwaves;
   const int64_t row_cap = sh.row_cap;
   const Layout &L = sh.L;
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
-  // larger pairs first, so that the work counter ends with small ones
+  // larger pairs first, so that the work counter ends with small ones; the
+  // top bit marks a swapped pair
   std::vector<int32_t> order(npairs);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     return (p_off[x + 1] - p_off[x]) * (q_off[x + 1] - q_off[x]) >
            (p_off[y + 1] - p_off[y]) * (q_off[y + 1] - q_off[y]);
   });
+  for (int32_t &o : order)
+    if (swap[o]) o = (int32_t)((uint32_t)o | 0x80000000u);
   char *base = static_cast<char *>(ctx->scratch);
   hipError_t e = hipMemcpyAsync(base + L.off0, p_off, (size_t)(npairs + 1) * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
