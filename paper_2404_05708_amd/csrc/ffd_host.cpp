@@ -1735,11 +1735,11 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   summary->pipelined = pl.pipe ? 1 : 0;
   if (jobs) {
     if (jobs_cap < (int64_t)pl.jobs.size()) return fail(ctx, FFD_E_NOMEM, "jobs_cap too small");
-    memcpy(jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
+    if (!pl.jobs.empty()) memcpy(jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
   }
   if (wave_jobs) {
     if (wave_jobs_cap < (int64_t)pl.wave_jobs.size()) return fail(ctx, FFD_E_NOMEM, "wave_jobs too small");
-    memcpy(wave_jobs, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
+    if (!pl.wave_jobs.empty()) memcpy(wave_jobs, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
   }
   return FFD_OK;
 }
