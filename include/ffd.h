@@ -42,7 +42,8 @@
  *    FFD_E_DEVICE from a later call that synchronises.
  *  - Preconditions (documented, not checked): coordinates are finite; float
  *    coordinates satisfy |x| < 1e18 so that squares do not overflow; int32
- *    coordinates satisfy |x| < 2^24 so that every intermediate is exact.
+ *    coordinates satisfy |x| < 2^24 (dim <= 4) or |x| < 2^23 (dim 5 to 16)
+ *    so that every intermediate is exact.
  *  - Float32 results of the Frechet calls agree with the exact real-number
  *    result to a relative error of 2e-6 (each d_ij is evaluated in float32
  *    in a fixed order, with at most 2 D - 1 roundings; the recurrence only
@@ -105,8 +106,12 @@ extern "C" {
 #define FFD_CHEBYSHEV 3   /* max_k |p_ik - q_jk|                      */
 #define FFD_HAVERSINE 4   /* central angle of (lat, lon) points       */
 
-/* Largest supported dimension D. */
-#define FFD_MAX_DIM 4
+/* Largest supported dimension D (coordinates per point).  Curves of up to
+ * four coordinates run on kernels of their own; curves of 5 to 16 on kernels
+ * for 8 or 16 coordinates that hold zeros past the curves' own (the same
+ * results, bit for bit, at the cost of the padded coordinates' arithmetic,
+ * with 2 rows per lane and no pipelined single-pair kernel). */
+#define FFD_MAX_DIM 16
 
 /* Operation codes for ffd_workspace_size (and ffd_plan_describe). */
 #define FFD_OP_BATCH 0

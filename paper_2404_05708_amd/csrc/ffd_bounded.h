@@ -24,9 +24,11 @@ struct BoundedArgs {
   float *rows;                 // per wave: 3 * row_cap floats (two bottom rows, suffix minima)
   int64_t row_cap;             // > the longest column curve when some row curve has several bands
   uint32_t *counter;           // work counter, zero at launch
+  int32_t dim;                 // coordinates per point (the launch's D)
 };
 
-// nwaves wavefronts (workgroups of 4) take pairs from the counter.
+// nwaves wavefronts (workgroups of 4) take pairs from the counter.  D is the
+// curves' coordinates per point (a.dim); D > 4 runs with R = wide_rows(D) only.
 hipError_t launch_bounded(int R, int D, const BoundedArgs &a, int nwaves, hipStream_t st);
 // lb[c] = larger of the squared first-point and last-point distances between
 // the query and curve c.

@@ -31,6 +31,7 @@
 #include <stdint.h>
 
 #include "ffd_bounded.h"
+#include "ffd_plan.h"
 
 namespace ffd {
 
@@ -50,8 +51,15 @@ __device__ __forceinline__ float load_l2(const float *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// D = 8 and 16 are the kernels of curves with 5 to 16 coordinates (GEN): a
+// point has a.dim coordinates in memory and zeros past them in registers,
+// which leaves every cell's bits unchanged (a zero difference adds an exact
+// zero); they read each column point at its step rather than a group ahead,
+// since a group would take 8 or 16 registers per point and step.
 template <int R, int D>
 struct Bounded {
+  static constexpr bool GEN = D > 4;
+  static constexpr int QG = GEN ? 1 : kGroupB;  // column points held a group ahead
   const BoundedArgs &a;
   int lane;
   float *hand0;  // two bottom rows (this band, the band above) and suffix minima
@@ -62,14 +70,42 @@ struct Bounded {
     smin = hand0 + 2 * a.row_cap;
   }
 
+  // values per point in the input arrays, and value k of the point at pt
+  __device__ int32_t in_dim() const {
+    if constexpr (GEN) return a.dim;
+    else return D;
+  }
+  __device__ float coord(const float *pt, int k) const {
+    if constexpr (GEN) return k < a.dim ? pt[k] : 0.0f;
+    else return pt[k];
+  }
+
+  // The column point of step t for this lane (column t - lane, clamped to
+  // the last; columns before the first are +inf points).
+  __device__ __forceinline__ void load_point(int32_t t, const float *qb, int32_t m, float (&q)[D]) const {
+    int32_t j = t - lane;
+    const bool sep = j < 0;
+    j = sep ? 0 : (j > m - 1 ? m - 1 : j);
+    const float *pt = qb + (int64_t)j * in_dim();
+#pragma unroll
+    for (int k2 = 0; k2 < D; ++k2) q[k2] = sep ? __builtin_huge_valf() : coord(pt, k2);
+  }
+
   // Column points of the group starting at t0 for this lane (columns
   // t0 + u - lane, clamped to the last; columns before the first are +inf
   // points, so their cells are +inf) and lane 0's row-above values.
   // (The host keeps m * D below 2^31, so 32-bit offsets from the curve's
   // first point address every column.)
   __device__ __forceinline__ void load_group(int32_t t0, const float *qb, int32_t m, bool above,
-                                             const float *hin, float (&q)[kGroupB][D], float (&h)[kGroupB]) {
-    if (t0 >= kWaveB - 1 && t0 + kGroupB <= m) {
+                                             const float *hin, float (&q)[QG][D], float (&h)[kGroupB]) {
+    if constexpr (GEN) {
+      // the points are read at their steps (load_point)
+#pragma unroll
+      for (int u = 0; u < kGroupB; ++u) {
+        int32_t c = t0 + u;
+        h[u] = above && c < m ? load_l2(hin + c) : __builtin_huge_valf();
+      }
+    } else if (t0 >= kWaveB - 1 && t0 + kGroupB <= m) {
       // every lane's 16 columns lie inside the curve: no separators and no
       // clamping, one base address and immediate offsets
       const float *qc = qb + (t0 - lane) * D;
@@ -84,17 +120,17 @@ struct Bounded {
 #pragma unroll
         for (int u = 0; u < kGroupB; ++u) h[u] = __builtin_huge_valf();
       }
-      return;
-    }
+    } else {
 #pragma unroll
-    for (int u = 0; u < kGroupB; ++u) {
-      int32_t j = t0 + u - lane;
-      const bool sep = j < 0;
-      j = sep ? 0 : (j > m - 1 ? m - 1 : j);
+      for (int u = 0; u < kGroupB; ++u) {
+        int32_t j = t0 + u - lane;
+        const bool sep = j < 0;
+        j = sep ? 0 : (j > m - 1 ? m - 1 : j);
 #pragma unroll
-      for (int k2 = 0; k2 < D; ++k2) q[u][k2] = sep ? __builtin_huge_valf() : qb[j * D + k2];
-      int32_t c = t0 + u;
-      h[u] = above && c < m ? load_l2(hin + c) : __builtin_huge_valf();
+        for (int k2 = 0; k2 < D; ++k2) q[u][k2] = sep ? __builtin_huge_valf() : qb[j * D + k2];
+        int32_t c = t0 + u;
+        h[u] = above && c < m ? load_l2(hin + c) : __builtin_huge_valf();
+      }
     }
   }
 
@@ -136,7 +172,7 @@ struct Bounded {
     const int64_t ro = offr[ri], n = offr[ri + 1] - ro;
     const int64_t co = offc[ci];
     const int32_t m = (int32_t)(offc[ci + 1] - co);
-    const float *qb = Xc + co * D;
+    const float *qb = Xc + co * in_dim();
     const int64_t band_rows = (int64_t)kWaveB * R;
     const int nb = (int)((n + band_rows - 1) / band_rows);
     const int64_t last = (n - 1) - (int64_t)(nb - 1) * band_rows;
@@ -153,8 +189,9 @@ struct Bounded {
       for (int r = 0; r < R; ++r) {
         int64_t i = (int64_t)b * band_rows + (int64_t)lane * R + r;
         if (i > n - 1) i = n - 1;
+        const float *pt = Xr + (ro + i) * in_dim();
 #pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) p[r][k2] = Xr[(ro + i) * D + k2];
+        for (int k2 = 0; k2 < D; ++k2) p[r][k2] = coord(pt, k2);
       }
       float Mp[R];
 #pragma unroll
@@ -163,31 +200,38 @@ struct Bounded {
       // M_{i-1,-1} = +inf below it
       float upPrev = above ? inf : -inf;
       float bmin = inf;  // lane 63: smallest bottom-row value so far
-      float qn[kGroupB][D], hn[kGroupB];
+      float qn[QG][D], hn[kGroupB];
       load_group(0, qb, m, above, hin, qn, hn);
       bool dead = false;
       for (int32_t t0 = 0; t0 < T; t0 += kGroupB) {
-        float q[kGroupB][D], h[kGroupB];
+        float q[QG][D], h[kGroupB];
 #pragma unroll
-        for (int u = 0; u < kGroupB; ++u) {
-          h[u] = hn[u];
+        for (int u = 0; u < kGroupB; ++u) h[u] = hn[u];
+#pragma unroll
+        for (int u = 0; u < QG; ++u)
 #pragma unroll
           for (int k2 = 0; k2 < D; ++k2) q[u][k2] = qn[u][k2];
-        }
         if (t0 + kGroupB < T) load_group(t0 + kGroupB, qb, m, above, hin, qn, hn);
         float hb[kGroupB];
 #pragma unroll
         for (int u = 0; u < kGroupB; ++u) {
           const int32_t t = t0 + u;
+          float qv[D];
+          if constexpr (GEN) {
+            load_point(t, qb, m, qv);
+          } else {
+#pragma unroll
+            for (int k2 = 0; k2 < D; ++k2) qv[k2] = q[GEN ? 0 : u][k2];
+          }
           float up = shift_in(h[u], Mp[R - 1]);
           float above_v = up, diag = upPrev;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            float dx = p[r][0] - q[u][0];
+            float dx = p[r][0] - qv[0];
             float s = dx * dx;
 #pragma unroll
             for (int k2 = 1; k2 < D; ++k2) {
-              float w = p[r][k2] - q[u][k2];
+              float w = p[r][k2] - qv[k2];
               s = __builtin_fmaf(w, w, s);
             }
             float v = __builtin_fmaxf(__builtin_fminf(__builtin_fminf(above_v, diag), Mp[r]), s);
@@ -321,6 +365,34 @@ __global__ void endpoint_bound_batch_kernel(const float *Q, const int64_t *q_off
   lb[g] = __builtin_fmaxf(s0, s1);
 }
 
+// The bounds for curves of 5 to 16 coordinates (dim at run time).
+__device__ __forceinline__ float corner_cell(const float *x, const float *y, int dim) {
+  float dx = x[0] - y[0], s = dx * dx;
+  for (int k2 = 1; k2 < dim; ++k2) {
+    float w = x[k2] - y[k2];
+    s = __builtin_fmaf(w, w, s);
+  }
+  return s;
+}
+
+__global__ void endpoint_bound_wide_kernel(const float *q, int64_t n, const float *X, const int64_t *off,
+                                           int64_t count, int dim, float *lb) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  const float *a0 = X + off[c] * dim, *a1 = X + (off[c + 1] - 1) * dim;
+  lb[c] = __builtin_fmaxf(corner_cell(q, a0, dim), corner_cell(q + (n - 1) * dim, a1, dim));
+}
+
+__global__ void endpoint_bound_batch_wide_kernel(const float *Q, const int64_t *q_off, int64_t nq, const float *X,
+                                                 const int64_t *off, int64_t count, int dim, float *lb) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nq * count) return;
+  const int64_t i = g / count, c = g - i * count;
+  const float *q0 = Q + q_off[i] * dim, *q1 = Q + (q_off[i + 1] - 1) * dim;
+  const float *a0 = X + off[c] * dim, *a1 = X + (off[c + 1] - 1) * dim;
+  lb[g] = __builtin_fmaxf(corner_cell(q0, a0, dim), corner_cell(q1, a1, dim));
+}
+
 template <int R>
 hipError_t launch_r(int D, const BoundedArgs &a, int blocks, hipStream_t st) {
   switch (D) {
@@ -337,6 +409,13 @@ hipError_t launch_r(int D, const BoundedArgs &a, int blocks, hipStream_t st) {
 
 hipError_t launch_bounded(int R, int D, const BoundedArgs &a, int nwaves, hipStream_t st) {
   int blocks = (nwaves + 3) / 4;
+  if (D > 4) {
+    // curves of 5 to 16 coordinates: the kernels of 8 (R = 2) and 16 (R = 1)
+    if (R != wide_rows(D) || a.dim != D || D > 16) return hipErrorInvalidValue;
+    if (D <= 8) hipLaunchKernelGGL((bounded_kernel<2, 8>), dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((bounded_kernel<1, 16>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
   switch (R) {
     case 1: return launch_r<1>(D, a, blocks, st);
     case 2: return launch_r<2>(D, a, blocks, st);
@@ -349,6 +428,10 @@ hipError_t launch_bounded(int R, int D, const BoundedArgs &a, int nwaves, hipStr
 hipError_t launch_endpoint_bound(int D, const float *q, int64_t n, const float *X, const int64_t *off, int64_t count,
                                  float *lb, hipStream_t st) {
   unsigned blocks = (unsigned)((count + 255) / 256);
+  if (D > 4) {
+    hipLaunchKernelGGL(endpoint_bound_wide_kernel, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, D, lb);
+    return hipGetLastError();
+  }
   switch (D) {
     case 1: hipLaunchKernelGGL(endpoint_bound_kernel<1>, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, lb); break;
     case 2: hipLaunchKernelGGL(endpoint_bound_kernel<2>, dim3(blocks), dim3(256), 0, st, q, n, X, off, count, lb); break;
@@ -362,6 +445,11 @@ hipError_t launch_endpoint_bound(int D, const float *q, int64_t n, const float *
 hipError_t launch_endpoint_bound_batch(int D, const float *Q, const int64_t *q_off, int64_t nq, const float *X,
                                        const int64_t *off, int64_t count, float *lb, hipStream_t st) {
   unsigned blocks = (unsigned)((nq * count + 255) / 256);
+  if (D > 4) {
+    hipLaunchKernelGGL(endpoint_bound_batch_wide_kernel, dim3(blocks), dim3(256), 0, st, Q, q_off, nq, X, off, count,
+                       D, lb);
+    return hipGetLastError();
+  }
   switch (D) {
 #define FFD_EPB_CASE(d)                                                                                           \
   case d:                                                                                                         \

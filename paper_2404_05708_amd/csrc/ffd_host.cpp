@@ -67,6 +67,7 @@ int hip_fail(ffd_ctx *ctx, hipError_t e, const char *what) {
 // cells (ops 10, 11) are FP64 squared chords of unit vectors (D = 3), and
 // DTW adds a float square root and arcsine per cell (about 20 instructions).
 double step_clocks(int R, int D, bool exact, double waves_per_simd, int op) {
+  D = ffd::kernel_dim(D);  // the wide kernels compute their zero coordinates too
   int cell = op >> 1;
   double per_cell = 2 * D + (exact ? 3 : 2) + (cell == 1 ? 4 : 0) - (cell == 2 || cell == 3 ? 1 : 0);
   if (op == 8) per_cell = 2 * D + 5;  // Levenshtein: a compare per coordinate, the flag, a select, 4 ops
@@ -124,6 +125,7 @@ int check_common(ffd_ctx *ctx, int32_t dim, int32_t metric, bool exact) {
 }
 
 int lds_bytes(int R, int D, bool exact, int64_t hcap, bool rings, int measure) {
+  D = ffd::kernel_dim(D);
   return ffd::lds_layout(R, D, exact ? 8 : 4, (int)hcap, rings, measure == 8 ? ffd::lev_dim(D) : 0).total;
 }
 
@@ -563,6 +565,7 @@ int plan_units(ffd_ctx *ctx, int D, bool exact, int W, double share, bool single
   double best_cost = -1;
   for (int R : kRs) {
     if (ctx->tune_R && R != ctx->tune_R) continue;
+    if (D > 4 && R != ffd::wide_rows(D)) continue;  // the wide kernels' only shape
     // great-circle DTW inlines an arcsine per cell and row: at R = 8 the
     // kernel spills registers to scratch memory
     if (!ctx->tune_R && ctx->measure == kOpGeoDtw && R > 4) continue;
@@ -634,6 +637,7 @@ double pipe_step_clocks(int R, int D, bool exact) {
 // kernel cannot run it.
 bool build_pipe(ffd_ctx *ctx, int64_t rows, int64_t cols, int R, int D, bool exact, Plan &pl, double &cost) {
   if (R != 2 && R != 4) return false;
+  if (D > 4) return false;  // instantiated for up to four coordinates
   const int64_t nb = ffd::bands_for(rows, R);
   if (nb < 2 || nb > INT32_MAX / 2 || cols < 2) return false;
   size_t lds = ffd::pipe_lds(exact, D);
@@ -937,6 +941,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   a.flags = pl.nflags > 0 ? (uint64_t *)(w + wl.flags) : nullptr;
   a.err = (uint64_t *)(w + wl.err);
   a.rings = pl.rings ? 1 : 0;
+  a.dim = D;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, 0, 0, pl.max_steps};
   e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st, ctx->measure);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
@@ -1202,6 +1207,7 @@ int pair_common(ffd_ctx *ctx, const void *p, int64_t n, const void *q, int64_t m
     a.lds_per_wave = lds_bytes(pl->R, dim, exact, pl->hcap, false, ctx->measure);
     a.max_steps = (int32_t)(pl->max_steps + 4 * ffd::kRing);
     a.epoch = ++ctx->epoch;
+    a.dim = dim;
     e = ffd::launch_stream(exact, pl->R, dim, a, 1, false, st, ctx->measure);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     ctx->last_err = nullptr;

@@ -51,8 +51,12 @@ size_t pipe_lds(bool exact, int D);  // LDS of a workgroup
 // op has its own kernel family and never uses rings.  R is 1, 2, 4 or 8,
 // or for op 0 with float coordinates, no rings and no cooperative launch
 // also 3, 5, 6 or 7 (the serving shapes).
+// D is the curves' coordinates per point (a.dim), run on the kernel of
+// kernel_dim(D) coordinates.
 inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st,
                                 int op = 0) {
+  if (a.dim != D) return hipErrorInvalidValue;
+  D = kernel_dim(D);
   if ((R & (R - 1)) != 0) {
     if (op != 0 || exact || a.rings || coop) return hipErrorInvalidValue;
     return launch_stream_serve(R, D, a, wpb, st);
@@ -74,6 +78,7 @@ inline hipError_t launch_stream(bool exact, int R, int D, const KernelArgs &a, i
 }
 inline hipError_t occupancy_stream(bool exact, int R, int D, int wpb, size_t lds, int *blocks_per_cu,
                                    bool rings = false, int op = 0) {
+  D = kernel_dim(D);
   switch (op) {
     case 0: return rings ? occupancy_stream_rings(exact, R, D, wpb, lds, blocks_per_cu)
                          : occupancy_stream_plain(exact, R, D, wpb, lds, blocks_per_cu);

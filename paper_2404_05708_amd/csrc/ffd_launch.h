@@ -1,8 +1,9 @@
 // Launch and occupancy helpers shared by the kernel translation units.  Each
 // unit instantiates one kernel family (a selector `Sel` whose
 // `Sel::kernel<R, D, V>()` names the kernel for a launch shape) for every
-// shape R in {1, 2, 4, 8}, D in {1, ..., 4} (only D = Sel::kOnlyD when that
-// is not 0), and the value types it supports.
+// shape R in {1, 2, 4, 8}, D in {1, ..., 4}, and the wide shapes (R, D) =
+// (2, 8) and (1, 16) (curves of 5 to 16 coordinates; see kernel_dim), only D =
+// Sel::kOnlyD when that is not 0, and the value types it supports.
 #ifndef FFD_LAUNCH_H
 #define FFD_LAUNCH_H
 
@@ -10,10 +11,11 @@
 
 namespace ffd {
 
-// Every (R, D) shape: R rows per lane, D coordinates.
+// Every (R, D) shape: R rows per lane, D coordinates per point in the kernel.
 #define FFD_SHAPES(X) \
   X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 1) X(2, 2) X(2, 3) X(2, 4) \
-  X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(8, 1) X(8, 2) X(8, 3) X(8, 4)
+  X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(8, 1) X(8, 2) X(8, 3) X(8, 4) \
+  X(2, 8) X(1, 16)
 
 template <class Sel>
 struct Launcher {
@@ -48,9 +50,9 @@ struct Launcher {
 
   template <typename V>
   static hipError_t launch_v(int R, int D, const KernelArgs &a, int wpb, bool coop, hipStream_t st) {
-    switch (R * 8 + D) {
+    switch (R * 32 + D) {
 #define FFD_CASE(r, d) \
-  case r * 8 + d: return one<r, d, V>(a, wpb, coop, st);
+  case r * 32 + d: return one<r, d, V>(a, wpb, coop, st);
       FFD_SHAPES(FFD_CASE)
 #undef FFD_CASE
     }
@@ -59,9 +61,9 @@ struct Launcher {
 
   template <typename V>
   static hipError_t occ_v(int R, int D, int wpb, size_t lds, int *blocks) {
-    switch (R * 8 + D) {
+    switch (R * 32 + D) {
 #define FFD_CASE(r, d) \
-  case r * 8 + d: return occ<r, d, V>(wpb, lds, blocks);
+  case r * 32 + d: return occ<r, d, V>(wpb, lds, blocks);
       FFD_SHAPES(FFD_CASE)
 #undef FFD_CASE
     }

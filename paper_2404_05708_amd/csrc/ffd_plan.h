@@ -100,7 +100,18 @@ FFD_HD int align16(int x) { return (x + 15) & ~15; }
 FFD_HD constexpr int pad_dim(int D) { return D == 3 ? 4 : D; }
 // Levenshtein ring entries: the D symbol values and a separator flag, padded
 // to a power of two.
-FFD_HD constexpr int lev_dim(int D) { return D == 1 ? 2 : (D <= 3 ? 4 : 8); }
+FFD_HD constexpr int lev_dim(int D) { return D == 1 ? 2 : (D <= 3 ? 4 : (D <= 7 ? 8 : (D <= 15 ? 16 : 32))); }
+// Coordinates per point of the kernel that runs curves of D coordinates:
+// up to four, a kernel of their own; five to eight, the kernel of eight;
+// nine to sixteen, the kernel of sixteen.  The wider kernels read the
+// curves' own D coordinates per point and hold zeros in the others: a zero
+// difference adds nothing to a sum of squares or of absolute values,
+// changes no maximum of absolute values and no symbol comparison, so the
+// results are those of D coordinates, bit for bit.
+FFD_HD constexpr int kernel_dim(int D) { return D <= 4 ? D : (D <= 8 ? 8 : 16); }
+// The wider kernels exist for one R each (a lane's registers hold its R
+// rows twice): 2 rows per lane for the kernel of 8, 1 for the kernel of 16.
+FFD_HD constexpr int wide_rows(int D) { return D <= 8 ? 2 : 1; }
 
 // rings: the wave also owns a ring that hands its bottom row to another
 // wave of its workgroup.  dtw: the layout of the DTW kernels.
@@ -142,6 +153,7 @@ struct KernelArgs {
   uint64_t *err;             // error word (epoch << 32 | bits): bit 0 loop guard hit,
                              // bit 1 link wait abandoned; the largest word of a launch wins
   int32_t rings;             // nonzero: some jobs hand rows between waves through LDS rings
+  int32_t dim;               // coordinates per point of the curves (at most the kernel's D)
 };
 
 // A link buffer holds the boundary rows of a job's column curves back to

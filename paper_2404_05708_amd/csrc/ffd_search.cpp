@@ -50,8 +50,10 @@ float eps2_of(float eps, int32_t metric) {
   return x;
 }
 
-// Rows per lane: the smallest R whose band holds a typical row curve.
-int rows_per_lane(int64_t n) {
+// Rows per lane: the smallest R whose band holds a typical row curve
+// (curves of more than four coordinates: the wide kernels' R).
+int rows_per_lane(int64_t n, int32_t dim) {
+  if (dim > 4) return ffd::wide_rows(dim);
   if (n <= 64) return 1;
   if (n <= 128) return 2;
   if (n <= 256) return 4;
@@ -159,12 +161,12 @@ struct DecideShape {
 
 // Each pair is swept with the curve whose bands waste the fewest rows (and
 // ramp steps) as the row curve: swap[k] when Q_k takes that role.
-DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs,
+DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int32_t dim,
                          std::vector<uint8_t> *swap = nullptr) {
   int64_t nsum = 0;
   for (int64_t k = 0; k < npairs; ++k) nsum += p_off[k + 1] - p_off[k];
   DecideShape d;
-  d.R = rows_per_lane(nsum / npairs);
+  d.R = rows_per_lane(nsum / npairs, dim);
   if (swap) swap->assign(npairs, 0);
   int64_t cmax = 0;
   bool banded = false;
@@ -191,7 +193,8 @@ DecideShape decide_shape(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_of
 // largest stage; the others launch fewer waves): rows per lane for the
 // median query length, the bound, value and order arrays for every
 // (query, curve) pair, one threshold per query.
-DecideShape knn_shape(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb) {
+DecideShape knn_shape(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb,
+                      int32_t dim) {
   int64_t mmax = 0, nmax = 0;
   for (int64_t c = 0; c < ndb; ++c) mmax = std::max(mmax, db_off[c + 1] - db_off[c]);
   std::vector<int64_t> lens(nq);
@@ -201,7 +204,7 @@ DecideShape knn_shape(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int6
   }
   std::nth_element(lens.begin(), lens.begin() + nq / 2, lens.end());
   DecideShape d;
-  d.R = rows_per_lane(lens[nq / 2]);
+  d.R = rows_per_lane(lens[nq / 2], dim);
   d.row_cap = nmax > 64 * d.R ? mmax + 1 : 0;
   d.nwaves = search_waves(ctx, nq * ndb);
   d.L = layout(nq, ndb, nq * ndb, nq * ndb, nq * ndb, d.nwaves, d.row_cap, nq);
@@ -214,18 +217,17 @@ namespace ffdi {
 
 int search_scratch_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na, const int64_t *b_off,
                         int64_t nb, int32_t dim, size_t *bytes) {
-  (void)dim;
   if (op == FFD_OP_DECIDE) {
     if (na != nb) return fail(ctx, FFD_E_INVALID, "the decider needs na == nb");
     // eps = +inf runs ffd_batch in the same scratch
     size_t batch = 0;
     int rc = ffd_workspace_size(ctx, FFD_OP_BATCH, a_off, na, b_off, nb, dim, &batch);
     if (rc) return rc;
-    *bytes = std::max(decide_shape(ctx, a_off, b_off, na).L.total, batch);
+    *bytes = std::max(decide_shape(ctx, a_off, b_off, na, dim).L.total, batch);
     return FFD_OK;
   }
   if (na < 1) return fail(ctx, FFD_E_INVALID, "a k-nearest search takes at least one query");
-  *bytes = knn_shape(ctx, a_off, na, b_off, nb).L.total;
+  *bytes = knn_shape(ctx, a_off, na, b_off, nb, dim).L.total;
   return FFD_OK;
 }
 
@@ -257,7 +259,7 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
     return batch_in_scratch(ctx, P, p_off, Q, q_off, npairs, dim, metric, out, st);
   }
   std::vector<uint8_t> swap;
-  const DecideShape sh = decide_shape(ctx, p_off, q_off, npairs, &swap);
+  const DecideShape sh = decide_shape(ctx, p_off, q_off, npairs, dim, &swap);
   const int R = sh.R, nwaves = sh.nwaves;
   const int64_t row_cap = sh.row_cap;
   const Layout &L = sh.L;
@@ -293,6 +295,7 @@ int ffd_decide_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const f
   a.rows = reinterpret_cast<float *>(base + L.rows);
   a.row_cap = row_cap;
   a.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+  a.dim = dim;
   return launch(ctx, a, R, dim, nwaves, st);
 }
 
@@ -317,7 +320,7 @@ int ffd_knn_batch(ffd_ctx *ctx, const float *Q, const int64_t *q_off, int64_t nq
   hipStream_t st = (hipStream_t)stream;
   const int64_t kk = std::min<int64_t>(k, ndb);
   const int64_t np = nq * ndb;
-  const DecideShape sh = knn_shape(ctx, q_off, nq, db_off, ndb);
+  const DecideShape sh = knn_shape(ctx, q_off, nq, db_off, ndb, dim);
   const int R = sh.R;
   const Layout &L = sh.L;
   if ((rc = search_scratch(ctx, L.total, st))) return rc;
@@ -360,6 +363,7 @@ int ffd_knn_batch(ffd_ctx *ctx, const float *Q, const int64_t *q_off, int64_t nq
   a.rows = reinterpret_cast<float *>(base + L.rows);
   a.row_cap = sh.row_cap;
   a.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+  a.dim = dim;
   // one stage: exact squared distances of the npairs (query, curve) pairs in
   // horder, each at its query's threshold (heps) or at +inf
   auto stage = [&](int64_t npairs, bool thresholds) -> int {

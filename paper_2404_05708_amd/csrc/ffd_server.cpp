@@ -185,8 +185,12 @@ struct ffd_server {
 
 namespace {
 
+// Fewest rows per lane of a tick whose queries span several bands: curves of
+// more than four coordinates run on the wide kernels' R only.
+int multi_rows(const ffd_server &s) { return s.dim > 4 ? ffd::wide_rows(s.dim) : kServeRMulti; }
+
 int64_t job_count_bound(const ffd_server &s) {
-  int64_t max_nb = ffd::bands_for(s.max_query, kServeRMulti);
+  int64_t max_nb = ffd::bands_for(s.max_query, multi_rows(s));
   // per request: one job per chunk, or for a self-chained chunk a band job
   // and an idle job per band
   return (int64_t)s.chunks.size() + (int64_t)s.long_chunks.size() * (2 * max_nb);
@@ -272,7 +276,7 @@ int plan_server(ffd_server &s, int32_t max_slots, int64_t max_query) {
       s.long_sumL += ch.sumL[1];
     }
   }
-  int64_t max_nb = ffd::bands_for(max_query, kServeRMulti);
+  int64_t max_nb = ffd::bands_for(max_query, multi_rows(s));
   s.jobs_cap = (size_t)s.kmax * (size_t)job_count_bound(s);
   s.flags_cap = kFlagFirst + (size_t)s.kmax * s.long_chunks.size() * (size_t)std::max<int64_t>(max_nb - 1, 0);
   s.links_cap = (size_t)s.kmax * (size_t)s.long_sumL;
@@ -372,7 +376,8 @@ Job band_job(int32_t i, const Chunk &ch, int64_t ndb) {
 // lane: the tick's job and flag capacities are sized for that).
 double query_cost(const ffd_server &s, int64_t n, int R) {
   int64_t nb = ffd::bands_for(n, R);
-  if (nb > 1 && R < kServeRMulti) return HUGE_VAL;
+  if (s.dim > 4 && R != ffd::wide_rows(s.dim)) return HUGE_VAL;
+  if (nb > 1 && R < multi_rows(s)) return HUGE_VAL;
   return (double)nb * step_clocks(R, s.dim, false, kServeW);
 }
 
@@ -572,6 +577,7 @@ int launch_tick(ffd_server &s, Tick &t) {
   a.links = s.arena;
   a.flags = reinterpret_cast<uint64_t *>(t.dev + L.flags);
   a.err = reinterpret_cast<uint64_t *>(t.dev + L.err);
+  a.dim = s.dim;
   e = ffd::launch_stream(false, Rt, s.dim, a, s.wpb, false, t.stream);
   if (e != hipSuccess) return FFD_E_DEVICE;
   s.launches_by_rows[Rt - 1]++;
@@ -727,6 +733,7 @@ int make_server(ffd_db *db, int32_t max_slots, int64_t max_query, ffd_server *s)
   s->db = db;
   s->device = db->ctx->device;
   s->dim = db->dim;
+  if (s->dim > 4) s->R = ffd::wide_rows(s->dim);  // LDS sized for the wide kernels' only shape
   return plan_server(*s, max_slots, max_query);
 }
 

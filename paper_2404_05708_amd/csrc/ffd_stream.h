@@ -187,7 +187,10 @@ struct Stream {
   // Frechet sweep (OP 10) selects on chords and takes the angle once per
   // pair; DTW (OP 11) sums angles and takes one per cell.
   static constexpr bool HAV = CELL == 5;
-  static constexpr int DI = HAV ? 2 : D;  // input values per point
+  static constexpr int DI = HAV ? 2 : D;  // values per point in registers
+  // D = 8 and 16: the kernels of curves with 5 to 16 coordinates; a point
+  // has a.dim coordinates in memory and zeros past them in registers
+  static constexpr bool GEN = D > 4;
   using N = Num<V>;
   using C = std::conditional_t<HAV, float, typename N::Coord>;
   static_assert(!HAV || (D == 3 && sizeof(V) == 8), "great-circle sweeps run on FP64 unit vectors");
@@ -257,6 +260,17 @@ struct Stream {
     return (sel ? a.off[1] : a.off[0])[idx];
   }
 
+  // values per point in the input arrays
+  __device__ int32_t in_dim() const {
+    if constexpr (GEN) return a.dim;
+    else return DI;
+  }
+  // value k of the point at pt (k < DI); zero past the curves' coordinates
+  __device__ C coord(const C *pt, int k) const {
+    if constexpr (GEN) return k < a.dim ? pt[k] : C(0);
+    else return pt[k];
+  }
+
   __device__ static void uni_task(FillTask &t) {
     t.S = uni(t.S); t.L = uni(t.L); t.drain = uni(t.drain); t.col_sel = uni(t.col_sel);
     t.hin = uni(t.hin); t.flag_in = uni(t.flag_in); t.rel = uni(t.rel);
@@ -267,7 +281,7 @@ struct Stream {
   // Read the refill state from LDS.  Every lane reads the same values;
   // only the fields that steer control flow are made scalar (the rest stay
   // in vector registers, which keeps the scalar register file from spilling).
-  __device__ void load_state(FillState &f) const {
+  __device__ __forceinline__ void load_state(FillState &f) const {
     f = *fstate();
     f.exhausted = uni(f.exhausted); f.has_next = uni(f.has_next); f.idle = uni(f.idle);
     f.ptmp_pending = uni(f.ptmp_pending);
@@ -276,11 +290,11 @@ struct Stream {
     f.nxt.S = uni(f.nxt.S); f.nxt.L = uni(f.nxt.L); f.nxt.hin = uni(f.nxt.hin);
   }
 
-  __device__ void store_state(const FillState &f) const {
+  __device__ __forceinline__ void store_state(const FillState &f) const {
     if (lane == 0) *fstate() = f;
   }
 
-  __device__ void load_job(FillState &f, int32_t jj) const {
+  __device__ __forceinline__ void load_job(FillState &f, int32_t jj) const {
     int32_t ri, bf, bc;
     if (a.jobs) {
       const Job *jb = a.jobs + jj;
@@ -334,7 +348,7 @@ struct Stream {
   // Create the next task in stream order starting at position S: write its
   // descriptor, issue the loads of its band rows into ptmp, return its
   // stream parameters.
-  __device__ void make_task(FillState &f, int32_t S, FillTask &t) {
+  __device__ __forceinline__ void make_task(FillState &f, int32_t S, FillTask &t) {
     int32_t id = f.next_id++;
     Desc d;
     d.S = S;
@@ -395,9 +409,9 @@ struct Stream {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int64_t ri = r0 + r < f.n ? r0 + r : f.n - 1;
-        const C *pt = X + (f.row_off + ri) * DI;
+        const C *pt = X + (f.row_off + ri) * in_dim();
 #pragma unroll
-        for (int k2 = 0; k2 < DI; ++k2) ptmp[r][k2] = pt[k2];
+        for (int k2 = 0; k2 < DI; ++k2) ptmp[r][k2] = coord(pt, k2);
       }
       f.ptmp_pending = 1;
       f.ptmp_slot = id & 1;
@@ -437,7 +451,7 @@ struct Stream {
 
   // Make f.cur the task containing stream position t, and f.nxt the one
   // after it if f.cur ends before t + kFill.
-  __device__ void advance(FillState &f, int32_t t) {
+  __device__ __forceinline__ void advance(FillState &f, int32_t t) {
     while (f.cur.S + f.cur.L <= t) {
       if (!f.has_next) make_task(f, f.cur.S + f.cur.L, f.nxt);
       f.cur = f.nxt;
@@ -451,7 +465,7 @@ struct Stream {
 
   // Issue the global loads of ring entries [t, t + 64), one per lane; f
   // describes that chunk (advance(f, t)).
-  __device__ void ring_load(const FillState &f, int32_t t) {
+  __device__ __forceinline__ void ring_load(const FillState &f, int32_t t) {
     const FillTask &cur = f.cur, &nxt = f.nxt;
     int32_t tau = t + lane;
     bool in_next = tau >= cur.S + cur.L;
@@ -467,16 +481,16 @@ struct Stream {
     if (idx < 0) idx = 0;
     if (drain) { co = 0; idx = 0; sel = 0; }
     const C *X = coords(sel);
-    const C *pt = X + (co + idx) * DI;
+    const C *pt = X + (co + idx) * in_dim();
 #pragma unroll
-    for (int k2 = 0; k2 < DI; ++k2) qbuf[k2] = pt[k2];
+    for (int k2 = 0; k2 < DI; ++k2) qbuf[k2] = coord(pt, k2);
   }
 
   // Issue the loads of the incoming boundary values of positions
   // [t, t + 64) for tasks whose band above ran on another wave, after
   // waiting for them to be published; f describes that chunk.  They are
   // written to LDS at the refill of step t, just before their first use.
-  __device__ void link_load(const FillState &f, int32_t t) {
+  __device__ __forceinline__ void link_load(const FillState &f, int32_t t) {
     const FillTask &cur = f.cur, &nxt = f.nxt;
     if (cur.hin == kHinLink) {
       int32_t hi = t + kFill - cur.S;
@@ -514,7 +528,7 @@ struct Stream {
     out[2] = sf;
   }
 
-  __device__ void fill_write(FillState &f, int32_t t) {
+  __device__ __forceinline__ void fill_write(FillState &f, int32_t t) {
     Pt e;
     if constexpr (HAV) {
       V u[D];
@@ -567,19 +581,29 @@ struct Stream {
   }
 
   // Column points and top-boundary values of one group of kGroup steps,
-  // read from LDS one group ahead of their use.
+  // read from LDS one group ahead of their use.  The wide kernels (GEN)
+  // would need 8 or 16 registers per point and step: they keep the group's
+  // ring address and read each point at its step (the ring chunk of a group
+  // is only rewritten at a later refill).
   struct GroupIn {
-    Pt q[kGroup];
+    Pt q[GEN ? 1 : kGroup];
+    const Pt *qp;
     V h[kGroup];
   };
 
   __device__ __forceinline__ void load_group(int32_t t, const V *hin, GroupIn &g) const {
     const Pt *qr = ring() + ((t - lane) & (kRing - 1));
+    g.qp = qr;
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
-      g.q[u] = qr[u];
+      if constexpr (!GEN) g.q[u] = qr[u];
       g.h[u] = hin[u];
     }
+  }
+
+  __device__ __forceinline__ static const Pt &entry(const GroupIn &g, int u) {
+    if constexpr (GEN) return g.qp[u];
+    else return g.q[u];
   }
 
   // Row state of the lane: the R rows it holds, the rows of the next task,
@@ -628,24 +652,25 @@ struct Stream {
           for (int k2 = 0; k2 < D; ++k2) p[r][k2] = sw ? pn[r][k2] : p[r][k2];
       }
       V up = N::shift_in(g.h[u], bottom);
+      const Pt &qe = entry(g, u);
       V dd[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        V t = p[r][0] - g.q[u].c[0];
+        V t = p[r][0] - qe.c[0];
         V s;
         if constexpr (CELL >= 2 && !HAV) {
           // Manhattan: s = |d0| + |d1| + ...; Chebyshev: max of |dk|
           s = N::abs(t);
 #pragma unroll
           for (int k2 = 1; k2 < D; ++k2) {
-            V w = N::abs(p[r][k2] - g.q[u].c[k2]);
+            V w = N::abs(p[r][k2] - qe.c[k2]);
             s = CELL == 2 ? s + w : N::mx(s, w);
           }
         } else {
           s = t * t;
 #pragma unroll
           for (int k2 = 1; k2 < D; ++k2) {
-            V w = p[r][k2] - g.q[u].c[k2];
+            V w = p[r][k2] - qe.c[k2];
             s = N::fma(w, w, s);
           }
           if constexpr (CELL == 1) s = N::sqrt_cell(s);
@@ -661,10 +686,10 @@ struct Stream {
         if constexpr (LEV) {
           // d = [p_i != q_j], symbols compared as bit patterns; a separator
           // (flag slot set) differs from every symbol
-          bool ne = __builtin_bit_cast(uint32_t, g.q[u].c[D]) != 0u;
+          bool ne = __builtin_bit_cast(uint32_t, qe.c[D]) != 0u;
 #pragma unroll
           for (int k2 = 0; k2 < D; ++k2)
-            ne = ne || __builtin_bit_cast(uint32_t, p[r][k2]) != __builtin_bit_cast(uint32_t, g.q[u].c[k2]);
+            ne = ne || __builtin_bit_cast(uint32_t, p[r][k2]) != __builtin_bit_cast(uint32_t, qe.c[k2]);
           s = ne ? V(1) : V(0);
         }
         dd[r] = s;
@@ -943,7 +968,7 @@ struct Stream {
     return true;
   }
 
-  __device__ void run(int32_t wave) {
+  __device__ __forceinline__ void run(int32_t wave) {
     lay = lds_layout(R, D, (int)sizeof(V), a.hcap, RINGS, DP);
     int32_t j0, j1;
     if (a.jobs) {

@@ -39,7 +39,7 @@ FFD_OP_CROSS = 1
 FFD_OP_PAIR = 2
 FFD_OP_DECIDE = 3
 FFD_OP_KNN = 4
-FFD_MAX_DIM = 4
+FFD_MAX_DIM = 16
 
 EXPORTS = (
     "ffd_create", "ffd_create_planner", "ffd_destroy", "ffd_strerror", "ffd_last_error", "ffd_version",

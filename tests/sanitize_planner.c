@@ -71,6 +71,15 @@ int main(void) {
       }
   ffd_set_tuning(c, 0, 0);
   ffd_set_split(c, 0.f);
+  /* curves of 5 to 16 coordinates: the wide kernels' one rows-per-lane each */
+  for (int dim = 5; dim <= 16; dim += 11) {
+    EXPECT(describe(c, FFD_OP_BATCH, p, NP, q, NP, dim, 0, 0, 0) == FFD_OK, "wide batch plan");
+    EXPECT(describe(c, FFD_OP_BATCH, p, NP, q, NP, dim, 1, 0, 1) == FFD_OK, "wide exact batch plan");
+    EXPECT(describe(c, FFD_OP_CROSS, p, 30, q, 400, dim, 0, 1, 0) == FFD_OK, "wide dtw cross plan");
+  }
+  ffd_set_tuning(c, 4, 0);
+  EXPECT(describe(c, FFD_OP_BATCH, p, NP, q, NP, 6, 0, 0, 0) == FFD_E_UNSUPPORTED, "wide shape other than its R");
+  ffd_set_tuning(c, 0, 0);
   /* cross: 30 queries x 400 curves, float and exact */
   EXPECT(describe(c, FFD_OP_CROSS, p, 30, q, 400, 2, 0, 0, 0) == FFD_OK, "cross plan");
   EXPECT(describe(c, FFD_OP_CROSS, p, 30, q, 400, 2, 1, 0, 1) == FFD_OK, "exact cross plan");
@@ -82,6 +91,7 @@ int main(void) {
       ffd_set_tuning(c, 0, w);
       EXPECT(describe(c, FFD_OP_PAIR, a, 1, b, 1, 3, 0, 0, 0) == FFD_OK, "pair plan");
       EXPECT(describe(c, FFD_OP_PAIR, a, 1, b, 1, 2, 1, 0, 1) == FFD_OK, "exact pair plan");
+      EXPECT(describe(c, FFD_OP_PAIR, a, 1, b, 1, 11, 0, 0, 0) == FFD_OK, "wide pair plan");
     }
   }
   ffd_set_tuning(c, 0, 0);
@@ -95,7 +105,7 @@ int main(void) {
   /* refused requests */
   EXPECT(describe(c, FFD_OP_BATCH, p, 0, q, 0, 2, 0, 0, 0) == FFD_E_INVALID, "empty batch refused");
   EXPECT(describe(c, 99, p, 2, q, 2, 2, 0, 0, 0) == FFD_E_INVALID, "unknown op refused");
-  EXPECT(describe(c, FFD_OP_BATCH, p, 2, q, 2, 9, 0, 0, 0) == FFD_E_UNSUPPORTED, "dim 9 refused");
+  EXPECT(describe(c, FFD_OP_BATCH, p, 2, q, 2, 17, 0, 0, 0) == FFD_E_UNSUPPORTED, "dim 17 refused");
   /* sizes of every op */
   size_t bytes = 0;
   const int ops[] = {FFD_OP_BATCH, FFD_OP_CROSS, FFD_OP_DECIDE, FFD_OP_KNN};

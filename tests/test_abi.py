@@ -77,7 +77,11 @@ def test_distance_argument_checks(planner):
     assert L.ffd_distance(planner, FAKE, 5, FAKE, -1, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 0, 0, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 2, 9, FAKE, None) == ffd.FFD_E_INVALID
-    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 5, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    # up to 16 coordinates per point
+    assert ffd.FFD_MAX_DIM == 16
+    for dim in (5, 8, 9, 16):
+        assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, dim, 0, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_distance(planner, FAKE, 5, FAKE, 7, 17, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
     assert L.ffd_distance(None, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_INVALID
     # int32 coordinates: squared Euclidean only
     assert L.ffd_distance_i32(planner, FAKE, 5, FAKE, 7, 2, 0, FAKE, None) == ffd.FFD_E_UNSUPPORTED
@@ -97,7 +101,8 @@ def test_batch_argument_checks(planner):
     assert args(good, empty) == ffd.FFD_E_INVALID
     assert args(shifted, good) == ffd.FFD_E_INVALID
     assert args(good, good, metric=7) == ffd.FFD_E_INVALID
-    assert args(good, good, dim=9) == ffd.FFD_E_UNSUPPORTED
+    assert args(good, good, dim=9) == ffd.FFD_E_DEVICE
+    assert args(good, good, dim=17) == ffd.FFD_E_UNSUPPORTED
     assert args(good, good, out=None) == ffd.FFD_E_INVALID
     assert args(good, good, n=-1) == ffd.FFD_E_INVALID
     assert args(good, good, n=0) == ffd.FFD_OK  # no-op
@@ -220,7 +225,8 @@ def test_levenshtein_argument_checks(planner):
     assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_DEVICE
     assert L.ffd_levenshtein_distance(planner, None, 5, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
     assert L.ffd_levenshtein_distance(planner, FAKE, 0, FAKE, 7, 1, FAKE, None) == ffd.FFD_E_INVALID
-    assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 5, FAKE, None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 5, FAKE, None) == ffd.FFD_E_DEVICE
+    assert L.ffd_levenshtein_distance(planner, FAKE, 5, FAKE, 7, 17, FAKE, None) == ffd.FFD_E_UNSUPPORTED
     # values are float32 integers: n + m must stay below 2^24
     assert L.ffd_levenshtein_distance(planner, FAKE, 1 << 23, FAKE, 1 << 23, 1, FAKE, None) == ffd.FFD_E_UNSUPPORTED
     big = np.array([0, 1 << 23], dtype=np.int64)
@@ -262,7 +268,9 @@ def test_serving_database_and_arena(planner):
         h = ctypes.c_void_p()
         assert L.ffd_db_create(planner, FAKE, _i64p(bad), 300, 2, ctypes.byref(h)) == ffd.FFD_E_INVALID
         assert L.ffd_db_create(planner, None, _i64p(dbo), 300, 2, ctypes.byref(h)) == ffd.FFD_E_INVALID
-        assert L.ffd_db_create(planner, FAKE, _i64p(dbo), 300, 9, ctypes.byref(h)) == ffd.FFD_E_UNSUPPORTED
+        assert L.ffd_db_create(planner, FAKE, _i64p(dbo), 300, 17, ctypes.byref(h)) == ffd.FFD_E_UNSUPPORTED
+        assert L.ffd_db_create(planner, FAKE, _i64p(dbo), 300, 9, ctypes.byref(h)) == ffd.FFD_OK
+        ffd.lib.ffd_db_destroy(h)
         n = ctypes.c_size_t()
         assert L.ffd_server_arena_size(db, 8, 8192, ctypes.byref(n)) == ffd.FFD_OK
         # the reordered database, the queries of 8 requests and their results at least

@@ -167,3 +167,35 @@ def test_simulator_catches_a_broken_plan(planner):
     bad["out_base"][writers[1]] = bad["out_base"][writers[0]]
     with pytest.raises(AssertionError):
         plan_sim.check(sm, bad, wj, offs, range(len(p_off) - 1))
+
+
+@pytest.mark.parametrize("dim,R", [(5, 2), (8, 2), (9, 1), (16, 1)])
+def test_wide_dimensions(planner, dim, R):
+    """Curves of 5 to 16 coordinates run on the kernels of 8 (R = 2) or 16
+    (R = 1) coordinates: batch, cross and single-pair plans take that R, pass
+    the simulator, and a long pair stays on the job-table plan (the pipelined
+    kernel has no wide form), also when the pipeline is asked for."""
+    P, p_off, Q, q_off = workloads.random_pairs(300, 300, 1, 2500, dim=2)
+    sm = batch_case(planner, p_off, q_off, dim=dim)
+    assert sm["rows_per_lane"] == R
+    sm = batch_case(planner, p_off, q_off, dim=dim, exact=True, metric=ffd.FFD_SQEUCLIDEAN)
+    assert sm["rows_per_lane"] == R
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, p_off[:21], q_off, dim, dtw=True)
+    assert sm["rows_per_lane"] == R
+    plan_sim.check(sm, jobs, wj, (np.asarray(p_off[:21]), np.asarray(q_off)), range(20 * 300))
+    for w in (0, -1):
+        ffd.ffd_set_tuning(planner, 0, w)
+        try:
+            sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_PAIR, [0, 20000], [0, 20000], dim)
+        finally:
+            ffd.ffd_set_tuning(planner, 0, 0)
+        assert sm["pipelined"] == 0 and sm["rows_per_lane"] == R
+        plan_sim.check(sm, jobs, wj, (np.array([0, 20000]), np.array([0, 20000])), [0])
+    # a forced rows-per-lane other than the wide kernel's is refused
+    ffd.ffd_set_tuning(planner, 4 if R != 4 else 8, 0)
+    try:
+        with pytest.raises(ffd.FFDError) as e:
+            ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, dim)
+        assert e.value.status == ffd.FFD_E_UNSUPPORTED
+    finally:
+        ffd.ffd_set_tuning(planner, 0, 0)
