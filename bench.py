@@ -125,6 +125,11 @@ def profiled_traffic(profile, info):
     return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
 
 
+def kernel_dim(dim):
+    """Coordinates per point of the kernel that runs curves of `dim`."""
+    return dim if dim <= 4 else (8 if dim <= 8 else 16)
+
+
 def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel", suffix="", cell="euclidean"):
     ops = cells * imin(dim, exact, cell)
     achieved = ops / (kms / 1e3)
@@ -133,7 +138,7 @@ def roofline(info, cells, kms, dim, exact, profile=None, family="stream_kernel",
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
         "unit": "TVALUop/s", "frac": achieved / PEAK_VALU,
         "traffic": profiled_traffic(profile, info) if profile else None,
-        "kernel": f"ffd::{family}<{info['rows_per_lane']}, {dim}, {vt}{suffix}>", "kernel_ms": kms,
+        "kernel": f"ffd::{family}<{info['rows_per_lane']}, {kernel_dim(dim)}, {vt}{suffix}>", "kernel_ms": kms,
         "launch": info, "ops_per_cell": imin(dim, exact, cell), "cells_per_launch": cells,
     }
 
@@ -178,10 +183,11 @@ def cpu_host():
 
 def run_batched(args, torch, ffd, ctx, dev, stream):
     import workloads
-    P, p_off, Q, q_off = workloads.batched()
+    P, p_off, Q, q_off = workloads.batched(dim=args.dim)
     npairs = len(p_off) - 1
     cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
     dim = P.shape[1]
+    wide = dim != 2  # the same lengths with other dimensions: no stored values, no profile
     Pd = torch.from_numpy(P).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
@@ -208,14 +214,21 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     kms = kernel_ms(torch, step, args.steps, stream)
     info = ctx.last_launch()
     errs = ctx.last_errors()
-    g = golden()["batched" if args.metric == "euclidean" else "batched_" + args.metric]
     res = out.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    want = np.array(g[args.metric])
+    if wide:
+        # 64 pairs of the batch against the FP64 oracle, computed here
+        import oracle
+        idx = np.sort(np.random.default_rng(78).choice(npairs, size=64, replace=False))
+        want = oracle.dfd_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
+                                metric, cpu_cores())
+    else:
+        g = golden()["batched" if args.metric == "euclidean" else "batched_" + args.metric]
+        idx = np.array(g["sample_index"])
+        want = np.array(g[args.metric])
     parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
 
     plain = None
-    if not args.no_plain and args.metric == "euclidean":
+    if not args.no_plain and args.metric == "euclidean" and not wide:
         pp = [(Pd[p_off[k]:p_off[k + 1]], Qd[q_off[k]:q_off[k + 1]]) for k in range(npairs)]
         outs = torch.empty(npairs, dtype=torch.float32, device=dev)
         for k in range(8):
@@ -249,12 +262,12 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
                "gpu_matches_sample": agree}
     return {
         "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
-        "config": {"workload": "batched: 4096 pairs, n and m uniform in [64, 2048], 2-D float32 "
+        "config": {"workload": f"batched: 4096 pairs, n and m uniform in [64, 2048], {dim}-D float32 "
                                f"random walks, q = p resampled + N(0, 0.1^2), {args.metric.capitalize()} (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": errs},
         "autotune": tuning,
-        "roofline": (roofline(info, cells, kms, dim, False, "stream_kernel_batched_4096pairs.md")
+        "roofline": (roofline(info, cells, kms, dim, False, None if wide else "stream_kernel_batched_4096pairs.md")
                      if args.metric == "euclidean" else
                      roofline(info, cells, kms, dim, False, family="op_kernel",
                               suffix=", 4" if args.metric == "manhattan" else ", 6", cell=args.metric)),
@@ -854,6 +867,8 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--metric", choices=["euclidean", "manhattan", "chebyshev"], default="euclidean",
                     help="ground distance of the batched workload")
+    ap.add_argument("--dim", type=int, default=2,
+                    help="coordinates per point of the batched workload (its headline form is 2-D)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
