@@ -359,7 +359,10 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
  * row curve each GPU lane holds; waves_per_simd: resident waves per SIMD the
  * batch planner targets, or -1: a single Frechet pair (ffd_distance) runs on
  * the pipelined single-pair kernel whenever that kernel can run it, whatever
- * the cost model prefers.  Returns FFD_E_INVALID for values out of range. */
+ * the cost model prefers.  Curves of 5 to 16 coordinates run with one rows
+ * per lane only (2 up to 8 coordinates, 1 above): a forced other value makes
+ * their calls return FFD_E_UNSUPPORTED.  Returns FFD_E_INVALID for values out
+ * of range. */
 int ffd_set_tuning(ffd_ctx *ctx, int32_t rows_per_lane, int32_t waves_per_simd);
 
 /* Shape of the most recent launch on this context, for reporting and tuning.
