@@ -74,3 +74,45 @@ def test_jitter_build_matches_release(gpu):
         torch.cuda.synchronize()
         jl.ffd_destroy(h)
         ctx.close()
+
+
+@pytest.mark.parametrize("dim", [6, 12])
+def test_jitter_wide_split_batch(gpu, dim):
+    """The kernels of 8 and 16 coordinates (curves of 5 to 16) under the
+    same pauses: a batch split into bands over waves gives the release
+    bits, repeatedly, with no error flags."""
+    from paper_2404_05708_amd import ffd
+    path = os.path.join(ROOT, "paper_2404_05708_amd", "libffd_jitter.so")
+    jl = ffd.load_library(path)
+    dev = torch.device("cuda:0")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ctx = ffd.Context(0)
+    h = ctypes.c_void_p()
+    assert jl.ffd_create(0, ctypes.byref(h)) == ffd.FFD_OK
+    flags = ctypes.c_int32()
+    try:
+        P, p_off, Q, q_off = workloads.random_pairs(910 + dim, 80, 1, 1500, dim=dim)
+        Pd, Qd = torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev)
+        base = ctx.batch(Pd, p_off, Qd, q_off).cpu().numpy()
+        po = np.ascontiguousarray(p_off, dtype=np.int64)
+        qo = np.ascontiguousarray(q_off, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        pop, qop = po.ctypes.data_as(i64p), qo.ctypes.data_as(i64p)
+        npairs = len(po) - 1
+        assert jl.ffd_set_split(h, 1e-9) == ffd.FFD_OK
+        nbytes = ctypes.c_size_t()
+        assert jl.ffd_workspace_size(h, ffd.FFD_OP_BATCH, pop, npairs, qop, npairs, dim,
+                                     ctypes.byref(nbytes)) == ffd.FFD_OK
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        out = torch.empty(npairs, dtype=torch.float32, device=dev)
+        for rep in range(3):
+            print(f"case: jitter wide split batch dim={dim}, repeat {rep}", flush=True)
+            assert jl.ffd_batch(h, ctypes.c_void_p(Pd.data_ptr()), pop, ctypes.c_void_p(Qd.data_ptr()), qop,
+                                npairs, dim, ffd.FFD_EUCLIDEAN, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(ws.data_ptr()), nbytes.value, stream) == ffd.FFD_OK
+            assert jl.ffd_last_errors(h, ctypes.byref(flags)) == ffd.FFD_OK and flags.value == 0
+            np.testing.assert_array_equal(out.cpu().numpy(), base)
+    finally:
+        torch.cuda.synchronize()
+        jl.ffd_destroy(h)
+        ctx.close()
