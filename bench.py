@@ -275,6 +275,74 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     }
 
 
+def run_short(args, torch, ffd, ctx, dev, stream):
+    """Many short pairs: the one-pair-per-lane kernel, with the streaming
+    kernel's job-table plan timed on the same pairs beside it."""
+    import workloads
+    P, p_off, Q, q_off = workloads.short_pairs()
+    npairs = len(p_off) - 1
+    cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
+    dim = P.shape[1]
+    Pd = torch.from_numpy(P).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.empty(npairs, dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sec = time_steps(step, args.steps, torch.cuda.synchronize)
+    kms = kernel_ms(torch, step, args.steps, stream)
+    info = ctx.last_launch()
+    res = out.cpu().numpy()
+    import oracle
+    idx = np.sort(np.random.default_rng(79).choice(npairs, size=256, replace=False))
+    want = oracle.dfd_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
+                            oracle.EUCLIDEAN, cpu_cores())
+    parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
+    # the streaming kernel on the same pairs: any forced setting keeps the job-table plan
+    ctx.set_tuning(0, 2)
+    try:
+        for _ in range(2):
+            step()
+        ssec = time_steps(step, args.steps, torch.cuda.synchronize)
+        skms = kernel_ms(torch, step, args.steps, stream)
+        sinfo = ctx.last_launch()
+        same = bool(np.array_equal(out.cpu().numpy(), res))
+    finally:
+        ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
+    cpu = None
+    if not args.no_cpu:
+        cores = cpu_cores()
+        rng = np.random.default_rng(80)
+        sample = np.sort(rng.choice(npairs, size=min(npairs, 65536), replace=False))
+        s_cells = int(np.sum((np.diff(p_off) * np.diff(q_off))[sample]))
+        t2 = time.perf_counter()
+        vals = oracle.dfd_pairs(P, p_off[:-1][sample], np.diff(p_off)[sample], Q, q_off[:-1][sample],
+                                np.diff(q_off)[sample], oracle.EUCLIDEAN, cores)
+        cw = time.perf_counter() - t2
+        cpu = {"value": s_cells / cw, "unit": "cells/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(sample)} of the {npairs} pairs (seed 80), {s_cells} cells, FP64 rolling-row oracle "
+                         f"on {cores} threads, {cw:.2f} s",
+               "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))}
+    rl = roofline(info, cells, kms, dim, False, family="lane_kernel")
+    rl["kernel"] = "ffd::lane_kernel<16|32|64, 2, float> (one launch per column class)"
+    return {
+        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
+        "config": {"workload": f"short pairs: {npairs} pairs, n and m uniform in [8, 64], 2-D float32 random walks, "
+                               "Euclidean (seed 11)", "npairs": npairs, "cells": cells, "global_batch": npairs},
+        "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": ctx.last_errors(),
+                   "streaming_kernel_bit_identical": same},
+        "roofline": rl,
+        "streaming_kernel": {"cells_per_s": cells / ssec, "ms_per_step": ssec * 1e3, "kernel_ms": skms,
+                             "frac": cells * imin(dim) / (skms / 1e3) / PEAK_VALU, "launch": sinfo},
+        "cpu_baseline": cpu,
+    }
+
+
 def run_dtw(args, torch, ffd, ctx, dev, stream):
     """DTW (Appendix B) with squared Euclidean cells on the batched workload."""
     import workloads
@@ -845,7 +913,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20,
                     help="untimed steps first (the GPU clock ramps up over the first tens of milliseconds)")
     ap.add_argument("--workload", choices=["batched", "plain", "large", "cross", "serving", "dtw", "levenshtein",
-                                           "geo", "geo_dtw", "knn", "decide"],
+                                           "geo", "geo_dtw", "knn", "decide", "short"],
                     default="batched")
     ap.add_argument("--requests", type=int, default=20000, help="measured open-loop requests per rate (serving)")
     ap.add_argument("--serving-warmup", type=int, default=2000, help="open-loop warm-up requests per rate (serving)")
@@ -920,6 +988,8 @@ def main():
         r = run_knn(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "decide":
         r = run_decide(args, torch, ffd, ctx, dev, stream)
+    elif args.workload == "short":
+        r = run_short(args, torch, ffd, ctx, dev, stream)
     else:
         r = run_pair(args, torch, ffd, ctx, dev, stream, args.workload)
     line = {
@@ -928,7 +998,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "autotune", "serving", "search", "roofline", "plain", "cpu_baseline"):
+    for k in ("config", "parity", "autotune", "serving", "search", "roofline", "plain", "streaming_kernel",
+              "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     if line.get("cpu_baseline"):

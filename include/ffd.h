@@ -331,6 +331,10 @@ typedef struct ffd_plan_summary {
                               no job table; waves = 4 x workgroups, one band
                               of 64 R rows per wave and pass, link_elems
                               values of boundary rows between workgroups   */
+  int32_t per_lane;        /* 1: a batch of short pairs, one pair per lane
+                              (rows_per_lane 0, no job table; waves = pairs
+                              / 64 rounded up per class of column count,
+                              stream_steps = the most rows of any lane)    */
 } ffd_plan_summary;
 typedef struct ffd_plan_job { /* 64 bytes */
   int64_t out_base;   /* output index of the first column curve              */
@@ -377,6 +381,7 @@ typedef struct ffd_launch_info {
   int32_t pipelined;       /* 1: the pipelined single-pair kernel           */
   int32_t helper_waves;    /* waves per workgroup that compute no band      */
   int64_t stream_steps;    /* longest per-wave stream (steps)               */
+  int32_t per_lane;        /* 1: short pairs, one per lane (rows_per_lane 0) */
 } ffd_launch_info;
 
 int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info);

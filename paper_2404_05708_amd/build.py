@@ -28,7 +28,7 @@ COMMON = [
 # per measure / ground distance (OP = measure + 2 * cell)
 SOURCES = [("ffd_kernels.hip", {}), ("ffd_kernels_rings.hip", {}), ("ffd_kernels_pipe.hip", {})] + \
           [("ffd_kernels_op.hip", {"FFD_OP": op}) for op in (1, 3, 4, 5, 6, 7, 8, 10, 11)] + \
-          [("ffd_kernels_serve.hip", {}), ("ffd_bounded.hip", {}), ("ffd_noalloc.hip", {}), ("ffd_host.cpp", {}), ("ffd_server.cpp", {}), ("ffd_search.cpp", {})]
+          [("ffd_kernels_serve.hip", {}), ("ffd_bounded.hip", {}), ("ffd_lanes.hip", {}), ("ffd_noalloc.hip", {}), ("ffd_host.cpp", {}), ("ffd_server.cpp", {}), ("ffd_search.cpp", {})]
 
 
 # Extra flags per source.  The pipelined single-pair kernel runs one wave per

@@ -708,12 +708,80 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
   return L;
 }
 
+// ------------------------------------------------------ short pairs per lane
+//
+// A batch whose pairs all have a curve of at most lane_cols_max points runs
+// on the one-pair-per-lane kernel (ffd_lanes.hip) when the model says it is
+// faster: each lane sweeps the longer curve's rows against the shorter
+// curve held in registers, 16, 32 or 64 columns (one launch per class of
+// column count), the pairs of a class in decreasing row count so that the
+// lanes of a wavefront sweep about as many rows.  Modelled clocks: per row
+// of a lane, M cells of 2 D + 2 instructions (FP64: 2 D + 3) and about 8 of
+// loop and load work; a wavefront takes its longest lane's rows; the
+// wavefronts share the SIMDs at about one instruction per 4.5 clocks, and
+// no wavefront can finish before its own rows at one per 5 clocks (alone on
+// a SIMD).
+bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
+                 Plan &pl, double &cost) {
+  if (ctx->measure != 0 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
+  const int cmax = ffd::lane_cols_max(exact, D);
+  const int classes[3] = {16, 32, 64};
+  struct Item {
+    int64_t rows;
+    int32_t key;
+  };
+  std::vector<Item> cls[3];
+  for (int64_t k = 0; k < npairs; ++k) {
+    const int64_t n = p_off[k + 1] - p_off[k], m = q_off[k + 1] - q_off[k];
+    const bool swap = n < m;  // the shorter curve holds the columns
+    const int64_t cols = swap ? n : m, rows = swap ? m : n;
+    if (cols > cmax) return false;
+    int c = 0;
+    while (classes[c] < cols) ++c;
+    cls[c].push_back({rows, (int32_t)((uint32_t)k | (swap ? 0x80000000u : 0u))});
+  }
+  pl = Plan();
+  pl.lanes = true;
+  pl.R = 0;
+  pl.wpb = 4;
+  double total = 0, longest = 0;
+  for (int c = 0; c < 3; ++c) {
+    if (cls[c].empty()) continue;
+    std::stable_sort(cls[c].begin(), cls[c].end(), [](const Item &a, const Item &b) { return a.rows > b.rows; });
+    const int i = pl.lane_classes++;
+    pl.lane_cols[i] = classes[c];
+    pl.lane_first[i] = (int64_t)pl.lane_order.size();
+    const double per_row = (double)classes[c] * (2 * D + (exact ? 3 : 2)) + 8.0;
+    for (size_t w = 0; w < cls[c].size(); w += ffd::kWave) {
+      const double v = (double)cls[c][w].rows * per_row;  // the wavefront's longest lane
+      total += v;
+      longest = std::max(longest, v);
+      pl.max_steps = std::max<int64_t>(pl.max_steps, cls[c][w].rows);
+    }
+    for (const Item &it : cls[c]) pl.lane_order.push_back(it.key);
+    pl.lane_first[i + 1] = (int64_t)pl.lane_order.size();
+    pl.nwaves += (int)((cls[c].size() + ffd::kWave - 1) / ffd::kWave);
+  }
+  pl.makespan = (double)pl.max_steps;
+  cost = std::max(total * 4.5 / (4.0 * ctx->cus), longest * 5.0);
+  return true;
+}
+
 int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                Plan &pl) {
   CurveSet P{p_off, npairs}, Q{q_off, npairs};
   int W = ctx->tune_W > 0 ? ctx->tune_W : 2;
-  return plan_units(ctx, D, exact, W, split_share(ctx), false,
-                    [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl);
+  double cost = -1;
+  int rc = plan_units(ctx, D, exact, W, split_share(ctx), false,
+                      [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl, &cost);
+  if (rc) return rc;
+  // short pairs, one per lane, when no launch shape is forced and the model prefers it
+  if (ctx->tune_R == 0 && ctx->tune_W == 0 && ctx->split == 0.f) {
+    Plan lanes;
+    double lc = 0;
+    if (build_lanes(ctx, p_off, q_off, npairs, D, exact, lanes, lc) && lc < cost) pl = std::move(lanes);
+  }
+  return FFD_OK;
 }
 
 int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db_off, int64_t ndb, int D,
@@ -769,7 +837,7 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t jobs, wj, off0, off1, flags, err, links, total;
+  size_t jobs, wj, off0, off1, order, flags, err, links, total;
 };
 
 WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
@@ -779,6 +847,7 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
   w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
   w.off0 = o;  o = al256(o + (size_t)(n0 + 1) * sizeof(int64_t));
   w.off1 = o;  o = al256(o + (size_t)(n1 + 1) * sizeof(int64_t));
+  w.order = o; o = al256(o + pl.lane_order.size() * sizeof(int32_t));
   w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
   w.err = o;   o = al256(o + sizeof(uint64_t));
   w.links = o; o = al256(o + (size_t)pl.link_elems * (exact ? 8 : 4));
@@ -854,10 +923,11 @@ int use_end(ffd_ctx *ctx, UseOrder &u, const void *ptr, hipStream_t st, bool cap
 // and error word) into host memory at h.
 void plan_image(const Plan &pl, const WsLayout &wl, const int64_t *off0, int64_t n0, const int64_t *off1,
                 int64_t n1, unsigned char *h) {
-  memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
-  memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
+  if (!pl.jobs.empty()) memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
+  if (!pl.wave_jobs.empty()) memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
   memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
   memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
+  if (!pl.lane_order.empty()) memcpy(h + wl.order, pl.lane_order.data(), pl.lane_order.size() * sizeof(int32_t));
   memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
 }
 
@@ -921,6 +991,26 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
                   "workspace outside the capture just before");
     e = ffd::clear_words((uint64_t *)(w + wl.flags), (int64_t)((wl.links - wl.flags) / sizeof(uint64_t)), st);
     if (e != hipSuccess) return hip_fail(ctx, e, "flag clearing launch");
+  }
+  if (pl.lanes) {
+    // short pairs, one per lane: a launch per class of column count
+    ffd::LaneArgs la;
+    la.X[0] = X0;
+    la.X[1] = X1;
+    la.off[0] = (const int64_t *)(w + wl.off0);
+    la.off[1] = (const int64_t *)(w + wl.off1);
+    la.out = out;
+    la.metric = metric;
+    for (int c = 0; c < pl.lane_classes; ++c) {
+      la.order = (const int32_t *)(w + wl.order) + pl.lane_first[c];
+      la.npairs = pl.lane_first[c + 1] - pl.lane_first[c];
+      e = ffd::launch_lanes(exact, pl.lane_cols[c], D, la, st);
+      if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+    }
+    ctx->last = ffd_launch_info{0, pl.nwaves, pl.wpb, 0, exact ? 1 : 0, D, 0, 0, pl.max_steps, 1};
+    ctx->last_err = nullptr;  // the kernel waits on nothing and raises no error bits
+    ctx->last_stream = st;
+    return use_end(ctx, use, ws, st, capturing);
   }
   KernelArgs a;
   memset(&a, 0, sizeof a);
@@ -1739,6 +1829,7 @@ int ffd_plan_describe(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t na
   summary->stream_steps = pl.max_steps;
   summary->jobs = (int64_t)pl.jobs.size();
   summary->pipelined = pl.pipe ? 1 : 0;
+  summary->per_lane = pl.lanes ? 1 : 0;
   if (jobs) {
     if (jobs_cap < (int64_t)pl.jobs.size()) return fail(ctx, FFD_E_NOMEM, "jobs_cap too small");
     if (!pl.jobs.empty()) memcpy(jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));

@@ -69,7 +69,7 @@ class LaunchInfo(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("lds_per_wave", ctypes.c_int32),
                 ("exact", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("pipelined", ctypes.c_int32), ("helper_waves", ctypes.c_int32),
-                ("stream_steps", ctypes.c_int64)]
+                ("stream_steps", ctypes.c_int64), ("per_lane", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -80,7 +80,7 @@ class PlanSummary(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("cooperative", ctypes.c_int32),
                 ("rings", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("link_elems", ctypes.c_int64), ("stream_steps", ctypes.c_int64), ("jobs", ctypes.c_int64),
-                ("pipelined", ctypes.c_int32)]
+                ("pipelined", ctypes.c_int32), ("per_lane", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

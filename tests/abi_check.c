@@ -18,6 +18,7 @@ int main(void) {
   FIELD(ffd_plan_summary, stream_steps);
   FIELD(ffd_plan_summary, jobs);
   FIELD(ffd_plan_summary, pipelined);
+  FIELD(ffd_plan_summary, per_lane);
   SIZE(ffd_plan_job);
   FIELD(ffd_plan_job, row_sel);
   FIELD(ffd_plan_job, band_count);
@@ -26,6 +27,7 @@ int main(void) {
   FIELD(ffd_launch_info, pipelined);
   FIELD(ffd_launch_info, helper_waves);
   FIELD(ffd_launch_info, stream_steps);
+  FIELD(ffd_launch_info, per_lane);
   SIZE(ffd_tuning);
   FIELD(ffd_tuning, tried);
   SIZE(ffd_search_info);

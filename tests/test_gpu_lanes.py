@@ -1,0 +1,136 @@
+"""GPU parity of the one-pair-per-lane kernel (batches of short pairs).
+
+The lane kernel evaluates every cell as the streaming kernels do and takes
+the Euclidean root once per pair, so its results must equal the streaming
+kernel's (forced with a rows-per-lane setting, which keeps the job-table
+plan) bit for bit, for every pair; a sample is also checked against the
+oracle's float32 replica and the FP64 oracle (2e-6), and the int32 path
+against the int64 oracle for every pair.  Lengths cover the three column
+classes (16, 32, 64), their boundaries, single points and both orientations.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ffdmod(gpu):
+    from paper_2404_05708_amd import ffd
+    return ffd
+
+
+@pytest.fixture(scope="module")
+def ctx(ffdmod):
+    c = ffdmod.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def short_pairs(seed, count, lo, hi, dim, kind="walk"):
+    """count pairs with lengths uniform in [lo, hi], plus the class
+    boundaries and single points; random walks (float32) or int32 in
+    [-2^15, 2^15).  Returns P, p_off, Q, q_off."""
+    rng = np.random.default_rng(seed)
+    edge = [(1, 1), (1, hi), (hi, 1), (16, 16), (17, 16), (16, 17), (32, 33), (33, 32), (64, 64), (63, 64),
+            (5, 64), (64, 5)]
+    edge = [(a, b) for a, b in edge if a <= hi and b <= hi]
+    n = np.concatenate([rng.integers(lo, hi + 1, size=count), [e[0] for e in edge]]).astype(np.int64)
+    m = np.concatenate([rng.integers(lo, hi + 1, size=count), [e[1] for e in edge]]).astype(np.int64)
+    p_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+
+    def curves(off):
+        total = int(off[-1])
+        if kind == "int":
+            return rng.integers(-(1 << 15), 1 << 15, size=(total, dim), dtype=np.int32)
+        x = np.cumsum(rng.standard_normal((total, dim)), axis=0)
+        starts = np.repeat(x[off[:-1]] - rng.standard_normal((len(off) - 1, dim)), np.diff(off), axis=0)
+        return (x - starts).astype(np.float32)  # a walk per curve, starting near 0
+
+    return curves(p_off), p_off, curves(q_off), q_off
+
+
+@pytest.mark.parametrize("dim,hi", [(1, 64), (2, 64), (3, 32), (4, 32), (2, 16)])
+def test_lanes_equal_streaming_kernel(ctx, dim, hi):
+    P, p_off, Q, q_off = short_pairs(500 + dim + hi, 150000, 1, hi, dim)
+    Pd, Qd = dev(P), dev(Q)
+    npairs = len(p_off) - 1
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(npairs, size=300, replace=False))
+    sample = np.unique(np.concatenate([sample, np.arange(npairs - 12, npairs)]))  # the edge cases
+    for metric in (0, 1):
+        say(f"case: lanes dim={dim} hi={hi} metric={metric}")
+        got = ctx.batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+        info = ctx.last_launch()
+        assert info["per_lane"] == 1 and info["rows_per_lane"] == 0, info
+        assert ctx.last_errors() == 0
+        ctx.set_tuning(1, 0)  # the job-table plan of the streaming kernel
+        try:
+            say(f"case: streaming kernel on the same pairs dim={dim} metric={metric}")
+            ref = ctx.batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+            assert ctx.last_launch()["per_lane"] == 0
+        finally:
+            ctx.set_tuning(0, 0)
+        np.testing.assert_array_equal(got, ref)
+        for k in sample:
+            p, q = P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]]
+            assert got[k] == oracle.dfd_f32_replica(p, q, metric), (k, len(p), len(q))
+        if metric == 0:
+            want = oracle.dfd_pairs(P, p_off[:-1][sample], np.diff(p_off)[sample], Q, q_off[:-1][sample],
+                                    np.diff(q_off)[sample], 0, 8)
+            assert np.all(np.abs(got[sample] - want) <= TOL * want)
+
+
+@pytest.mark.parametrize("dim,hi", [(2, 32), (4, 16)])
+def test_lanes_int_exact(ctx, dim, hi):
+    P, p_off, Q, q_off = short_pairs(600 + dim, 150000, 1, hi, dim, kind="int")
+    say(f"case: lanes int32 dim={dim} hi={hi}")
+    got = ctx.batch_i32(dev(P), p_off, dev(Q), q_off).cpu().numpy()
+    assert ctx.last_launch()["per_lane"] == 1
+    np.testing.assert_array_equal(got, oracle.dfd_batch_i32(P, p_off, Q, q_off, nthreads=8))
+
+
+def test_lanes_graph_replay_and_noalloc(ctx, ffdmod):
+    """A batch on the lane kernel recorded into a graph replays the eager
+    bits; the no-allocation entry point gives them too."""
+    P, p_off, Q, q_off = short_pairs(700, 150000, 1, 64, 2)
+    Pd, Qd = dev(P), dev(Q)
+    out = torch.empty(len(p_off) - 1, dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(ctx.workspace_size(ffdmod.FFD_OP_BATCH, p_off, q_off, 2), dtype=torch.uint8, device="cuda:0")
+    say("case: lanes, eager call")
+    ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    assert ctx.last_launch()["per_lane"] == 1
+    eager = out.clone()
+    g = torch.cuda.CUDAGraph()
+    say("case: lanes, capture")
+    with torch.cuda.graph(g):
+        ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws)
+    for k in range(3):
+        say(f"case: lanes, replay {k}")
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+    say("case: lanes, no-allocation entry point")
+    got = ctx.batch_noalloc(Pd, p_off, Qd, q_off)
+    torch.cuda.synchronize()
+    assert torch.equal(got, eager)

@@ -199,3 +199,55 @@ def test_wide_dimensions(planner, dim, R):
         assert e.value.status == ffd.FFD_E_UNSUPPORTED
     finally:
         ffd.ffd_set_tuning(planner, 0, 0)
+
+
+def test_short_pairs_per_lane(planner):
+    """A batch whose pairs all have a curve of at most 64 points (32 for
+    3-D and 4-D, half that for the exact path) runs one pair per lane when
+    the model prefers it; a batch with one longer pair, a forced launch
+    shape, another measure or a split setting keeps the job-table plan."""
+    def offsets(seed, count, lo, hi):
+        rng = np.random.default_rng(seed)
+        a = np.concatenate([[0], np.cumsum(rng.integers(lo, hi + 1, size=count))]).astype(np.int64)
+        b = np.concatenate([[0], np.cumsum(rng.integers(lo, hi + 1, size=count))]).astype(np.int64)
+        return a, b
+
+    # a few thousand pairs: a lane sweeps its whole pair alone, so the
+    # streaming kernel (64 rows of a pair in parallel) finishes first
+    p_off, q_off = offsets(69, 5000, 1, 64)
+    assert batch_case(planner, p_off, q_off)["per_lane"] == 0
+    # many pairs: one per lane
+    p_off, q_off = offsets(70, 200000, 1, 64)
+    sm, jobs, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2)
+    assert sm["per_lane"] == 1 and sm["jobs"] == 0 and sm["rows_per_lane"] == 0
+    lens = np.maximum(np.diff(p_off), np.diff(q_off))
+    assert sm["stream_steps"] == lens.max()
+    # classes of 16, 32 and 64 columns: waves = pairs per class / 64, rounded up
+    short = np.minimum(np.diff(p_off), np.diff(q_off))
+    per = [np.sum(short <= 16), np.sum((short > 16) & (short <= 32)), np.sum(short > 32)]
+    assert sm["waves"] == sum(-(-int(c) // 64) for c in per)
+    # one long pair anywhere: the streaming kernel
+    p2 = np.concatenate([p_off, [p_off[-1] + 500]])
+    q2 = np.concatenate([q_off, [q_off[-1] + 500]])
+    sm = batch_case(planner, p2, q2)
+    assert sm["per_lane"] == 0
+    # 3-D curves hold at most 32 columns per lane, the exact path 32 (2-D)
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 3)
+    assert sm["per_lane"] == 0
+    pb, qb = offsets(71, 200000, 1, 32)
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 3)
+    assert sm["per_lane"] == 1
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 2, exact=True, metric=ffd.FFD_SQEUCLIDEAN)
+    assert sm["per_lane"] == 1
+    for kw in ({"dtw": True}, {"metric": ffd.FFD_MANHATTAN}):
+        assert batch_case(planner, pb, qb, dim=2, **kw)["per_lane"] == 0
+    ffd.ffd_set_tuning(planner, 1, 0)
+    try:
+        assert batch_case(planner, pb, qb, dim=2)["per_lane"] == 0
+    finally:
+        ffd.ffd_set_tuning(planner, 0, 0)
+    ffd.ffd_set_split(planner, 1.5)
+    try:
+        assert batch_case(planner, pb, qb, dim=2)["per_lane"] == 0
+    finally:
+        ffd.ffd_set_split(planner, 0.0)

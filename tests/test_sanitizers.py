@@ -48,7 +48,7 @@ def test_planner_under_sanitizers(tmp_path):
     from paper_2404_05708_amd import build as B
     kernels = [os.path.join(B.BUILD, n) for n in
                ("ffd_kernels.hip.o", "ffd_kernels_rings.hip.o", "ffd_kernels_pipe.hip.o", "ffd_kernels_serve.hip.o",
-                "ffd_bounded.hip.o", "ffd_noalloc.hip.o")]
+                "ffd_bounded.hip.o", "ffd_lanes.hip.o", "ffd_noalloc.hip.o")]
     kernels += sorted(glob.glob(os.path.join(B.BUILD, "ffd_kernels_op.hip_FFD_OP*.o")))
     if not all(os.path.exists(k) for k in kernels):
         pytest.skip("kernel objects of the in-tree build are missing: run the build first")

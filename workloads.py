@@ -141,6 +141,27 @@ def poisson_arrivals(seed=7, count=1000, rate=1000.0):
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
+def short_pairs(seed=11, npairs=262144, lo=8, hi=64, dim=2):
+    """Many short pairs.  Draw order: n[npairs], m[npairs] uniform in [lo, hi];
+    then the N(0,1) steps of every p point (sum n x dim) and of every q point
+    (sum m x dim); each curve is the FP64 cumulative sum of its own steps,
+    cast once.  Returns P, p_off, Q, q_off."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(lo, hi + 1, size=npairs)
+    m = rng.integers(lo, hi + 1, size=npairs)
+
+    def curves(lens):
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        steps = rng.standard_normal((int(off[-1]), dim))
+        total = np.cumsum(steps, axis=0)
+        before = np.concatenate([np.zeros((1, dim)), total[off[1:-1] - 1]])  # sum of earlier curves' steps
+        return (total - np.repeat(before, lens, axis=0)).astype(np.float32), off
+
+    P, p_off = curves(n)
+    Q, q_off = curves(m)
+    return P, p_off, Q, q_off
+
+
 def random_pairs(seed, npairs, lo, hi, dim=2, kind="walk"):
     """Independent pairs with lengths uniform in [lo, hi] (tests).
 
