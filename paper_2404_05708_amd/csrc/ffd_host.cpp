@@ -102,8 +102,9 @@ uint64_t mix_words(uint64_t h, const int64_t *w, size_t n) {
 int check_offsets(ffd_ctx *ctx, const int64_t *off, int64_t count, const char *name) {
   if (!off) return fail(ctx, FFD_E_INVALID, name);
   if (off[0] != 0) return fail(ctx, FFD_E_INVALID, "offsets must start at 0");
-  for (int64_t k = 0; k < count; ++k)
-    if (off[k + 1] <= off[k]) return fail(ctx, FFD_E_INVALID, "offsets must be strictly increasing (empty curve)");
+  bool bad = false;  // one pass without an early exit, which the compiler vectorises
+  for (int64_t k = 0; k < count; ++k) bad |= off[k + 1] <= off[k];
+  if (bad) return fail(ctx, FFD_E_INVALID, "offsets must be strictly increasing (empty curve)");
   return FFD_OK;
 }
 
@@ -713,17 +714,19 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // A batch whose pairs all have a curve of at most lane_cols_max points runs
 // on the one-pair-per-lane kernel (ffd_lanes.hip) when the model says it is
 // faster: each lane sweeps the longer curve's rows against the shorter
-// curve held in registers, 16, 32 or 64 columns (one launch per class of
-// column count), the pairs of a class in decreasing row count so that the
-// lanes of a wavefront sweep about as many rows.  Modelled clocks: per row
-// of a lane, M cells of 2 D + 2 instructions (FP64: 2 D + 3) and about 8 of
-// loop and load work; a wavefront takes its longest lane's rows; the
-// wavefronts share the SIMDs at about one instruction per 4.5 clocks, and
-// no wavefront can finish before its own rows at one per 5 clocks (alone on
-// a SIMD).
+// curve held in registers, 16, 32 or 64 columns (classes of column count,
+// the widest first, in one launch), the pairs of a class in decreasing row
+// count so that the lanes of a wavefront sweep about as many rows.
+// Modelled clocks: per row of a lane, M cells of 2 D + 2 instructions
+// (FP64: 2 D + 3) and about 8 of loop and load work; a wavefront takes its
+// longest lane's rows; the wavefronts share the SIMDs at about one
+// instruction per 4.5 clocks, and no wavefront can finish before its own
+// rows at one per 5 clocks (alone on a SIMD).
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                  Plan &pl, double &cost) {
   if (ctx->measure != 0 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
+  // the kernel reads 32-bit offsets (half the upload of every call)
+  if (p_off[npairs] > INT32_MAX || q_off[npairs] > INT32_MAX) return false;
   const int cmax = ffd::lane_cols_max(exact, D);
   const int classes[3] = {16, 32, 64};
   struct Item {
@@ -745,7 +748,7 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   pl.R = 0;
   pl.wpb = 4;
   double total = 0, longest = 0;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 2; c >= 0; --c) {
     if (cls[c].empty()) continue;
     std::stable_sort(cls[c].begin(), cls[c].end(), [](const Item &a, const Item &b) { return a.rows > b.rows; });
     const int i = pl.lane_classes++;
@@ -845,8 +848,9 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
   size_t o = 0;
   w.jobs = o;  o = al256(o + pl.jobs.size() * sizeof(Job));
   w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
-  w.off0 = o;  o = al256(o + (size_t)(n0 + 1) * sizeof(int64_t));
-  w.off1 = o;  o = al256(o + (size_t)(n1 + 1) * sizeof(int64_t));
+  const size_t osz = pl.lanes ? sizeof(int32_t) : sizeof(int64_t);  // offsets as the kernel reads them
+  w.off0 = o;  o = al256(o + (size_t)(n0 + 1) * osz);
+  w.off1 = o;  o = al256(o + (size_t)(n1 + 1) * osz);
   w.order = o; o = al256(o + pl.lane_order.size() * sizeof(int32_t));
   w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
   w.err = o;   o = al256(o + sizeof(uint64_t));
@@ -925,8 +929,15 @@ void plan_image(const Plan &pl, const WsLayout &wl, const int64_t *off0, int64_t
                 int64_t n1, unsigned char *h) {
   if (!pl.jobs.empty()) memcpy(h + wl.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(Job));
   if (!pl.wave_jobs.empty()) memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
-  memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
-  memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
+  if (pl.lanes) {
+    // 32-bit offsets (the planner checked that they fit)
+    int32_t *o0 = reinterpret_cast<int32_t *>(h + wl.off0), *o1 = reinterpret_cast<int32_t *>(h + wl.off1);
+    for (int64_t k = 0; k <= n0; ++k) o0[k] = (int32_t)off0[k];
+    for (int64_t k = 0; k <= n1; ++k) o1[k] = (int32_t)off1[k];
+  } else {
+    memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
+    memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
+  }
   if (!pl.lane_order.empty()) memcpy(h + wl.order, pl.lane_order.data(), pl.lane_order.size() * sizeof(int32_t));
   memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
 }
@@ -995,18 +1006,24 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   if (pl.lanes) {
     // short pairs, one per lane: a launch per class of column count
     ffd::LaneArgs la;
+    memset(&la, 0, sizeof la);
     la.X[0] = X0;
     la.X[1] = X1;
-    la.off[0] = (const int64_t *)(w + wl.off0);
-    la.off[1] = (const int64_t *)(w + wl.off1);
+    la.off[0] = (const int32_t *)(w + wl.off0);
+    la.off[1] = (const int32_t *)(w + wl.off1);
+    la.order = (const int32_t *)(w + wl.order);
     la.out = out;
     la.metric = metric;
+    la.classes = pl.lane_classes;
     for (int c = 0; c < pl.lane_classes; ++c) {
-      la.order = (const int32_t *)(w + wl.order) + pl.lane_first[c];
-      la.npairs = pl.lane_first[c + 1] - pl.lane_first[c];
-      e = ffd::launch_lanes(exact, pl.lane_cols[c], D, la, st);
-      if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+      la.cols[c] = pl.lane_cols[c];
+      la.first[c] = pl.lane_first[c];
+      la.first[c + 1] = pl.lane_first[c + 1];
+      la.block_first[c + 1] = la.block_first[c] + (pl.lane_first[c + 1] - pl.lane_first[c] + ffd::kLaneBlock - 1) /
+                                                      ffd::kLaneBlock;
     }
+    e = ffd::launch_lanes(exact, D, la, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     ctx->last = ffd_launch_info{0, pl.nwaves, pl.wpb, 0, exact ? 1 : 0, D, 0, 0, pl.max_steps, 1};
     ctx->last_err = nullptr;  // the kernel waits on nothing and raises no error bits
     ctx->last_stream = st;
@@ -1181,8 +1198,10 @@ struct TunedScope {
   }
 };
 
+// (validate: check both offset arrays, unless they equal those of the
+// cached plan, which were checked when it was made)
 int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na, const int64_t *b_off,
-                int64_t nb, int D, bool exact, const Plan **out, uint64_t &gen) {
+                int64_t nb, int D, bool exact, const Plan **out, uint64_t &gen, bool validate = false) {
   Req r = req_of(ctx, op, D, exact, a_off, na, b_off, nb);
   if (pc.valid && req_matches(pc.key, r)) {
     *out = &pc.plan;
@@ -1191,6 +1210,10 @@ int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64
   }
   Plan pl;
   int rc;
+  if (validate) {
+    if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
+    if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
+  }
   if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, D, exact, pl);
   else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, D, exact, pl);
   else rc = plan_pair(ctx, a_off[1], b_off[1], D, exact, pl);
@@ -1323,12 +1346,12 @@ int batch_common(ffd_ctx *ctx, const void *P, const int64_t *p_off, const void *
   if (npairs == 0) return FFD_OK;
   if (npairs > INT32_MAX / 2) return fail(ctx, FFD_E_UNSUPPORTED, "too many pairs");
   if (!P || !Q || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
-  if ((rc = check_offsets(ctx, p_off, npairs, "p_off is NULL"))) return rc;
-  if ((rc = check_offsets(ctx, q_off, npairs, "q_off is NULL"))) return rc;
+  if (!p_off) return fail(ctx, FFD_E_INVALID, "p_off is NULL");
+  if (!q_off) return fail(ctx, FFD_E_INVALID, "q_off is NULL");
   TunedScope tuned(ctx, FFD_OP_BATCH, dim, exact, p_off, npairs, q_off, npairs);
   const Plan *pl;
   uint64_t key;
-  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key);
+  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_BATCH, p_off, npairs, q_off, npairs, dim, exact, &pl, key, true);
   if (rc) return rc;
   return run_plan(ctx, *pl, key, P, p_off, npairs, Q, q_off, npairs, dim, exact, metric, out, ws, ws_bytes, st,
                   use ? *use : ctx->ws_use, noalloc);
@@ -1344,12 +1367,12 @@ int cross_common(ffd_ctx *ctx, const void *Qs, const int64_t *q_off, int64_t nq,
   if (nq > INT32_MAX / 2 || ndb > INT32_MAX / 2 || nq * ndb > ((int64_t)1 << 40))
     return fail(ctx, FFD_E_UNSUPPORTED, "too many curves");
   if (!Qs || !DB || !out) return fail(ctx, FFD_E_INVALID, "NULL pointer");
-  if ((rc = check_offsets(ctx, q_off, nq, "q_off is NULL"))) return rc;
-  if ((rc = check_offsets(ctx, db_off, ndb, "db_off is NULL"))) return rc;
+  if (!q_off) return fail(ctx, FFD_E_INVALID, "q_off is NULL");
+  if (!db_off) return fail(ctx, FFD_E_INVALID, "db_off is NULL");
   TunedScope tuned(ctx, FFD_OP_CROSS, dim, exact, q_off, nq, db_off, ndb);
   const Plan *pl;
   uint64_t key;
-  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key);
+  rc = cached_plan(ctx, ctx->batch_plans, FFD_OP_CROSS, q_off, nq, db_off, ndb, dim, exact, &pl, key, true);
   if (rc) return rc;
   return run_plan(ctx, *pl, key, Qs, q_off, nq, DB, db_off, ndb, dim, exact, metric, out, ws, ws_bytes, st,
                   ctx->ws_use);

@@ -10,11 +10,14 @@ namespace ffd {
 
 struct LaneArgs {
   const void *X[2];       // coordinate arrays of the two curve sets (float32, or int32 for the exact path)
-  const int64_t *off[2];  // their curve offsets in points (device)
+  const int32_t *off[2];  // their curve offsets in points (device; each set below 2^31 points)
   const int32_t *order;   // lane k -> pair index; the top bit set: the second set's curve holds the rows
   void *out;              // float32 or int64 results, indexed by pair
-  int64_t npairs;         // lanes of this launch
   int32_t metric;         // 0 Euclidean (the root taken once per pair), 1 squared Euclidean
+  int32_t classes;        // classes of column count, 1 ... 3, most columns first
+  int32_t cols[3];        // columns a lane of class c holds (64, 32 or 16)
+  int64_t first[4];       // class c: lanes [first[c], first[c + 1]) of order
+  int64_t block_first[4]; // class c: workgroups [block_first[c], block_first[c + 1]) of the launch
 };
 
 // The largest column curve a lane holds in registers for D coordinates (16,
@@ -23,9 +26,12 @@ constexpr int lane_cols_max(bool exact, int D) {
   return exact ? (D <= 2 ? 32 : 16) : (D <= 2 ? 64 : 32);
 }
 
-// One launch of a shape: M columns (16, 32 or 64, at most lane_cols_max),
-// D coordinates (1 ... 4).
-hipError_t launch_lanes(bool exact, int M, int D, const LaneArgs &a, hipStream_t st);
+// Workgroups (of 256 lanes) of a launch.
+constexpr int kLaneBlock = 256;
+
+// One launch for every class (their workgroups in a.block_first), D
+// coordinates (1 ... 4); every class's column count at most lane_cols_max.
+hipError_t launch_lanes(bool exact, int D, const LaneArgs &a, hipStream_t st);
 
 }  // namespace ffd
 

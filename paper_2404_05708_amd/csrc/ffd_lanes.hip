@@ -21,8 +21,17 @@
 // int32 coordinates) and the Euclidean root is taken once per pair, so the
 // results equal the streaming kernels' bit for bit.
 //
-// The host sorts the pairs of a launch by row count, so that the lanes of a
-// wavefront sweep about as many rows each.
+// A lane sweeps its rows two at a time, both rows' cells of a column
+// together: the second row's cell takes the first row's as its value above,
+// so the two chains of selections (one per row, through the left
+// neighbours) overlap in the instruction stream.  A curve of odd length has
+// its last point repeated once more (exact, as above).
+//
+// One launch covers every class of column count (16, 32, 64 columns; the
+// registers are those of the widest class), its workgroups of the widest
+// class first; the host sorts the pairs of a class by row count, so that the
+// lanes of a wavefront sweep about as many rows each and the longest
+// wavefronts start first.
 #include "ffd_lanes.h"
 
 #include "ffd_stream.h"
@@ -32,18 +41,16 @@ namespace ffd {
 namespace {
 
 template <int M, int D, typename V>
-__global__ __launch_bounds__(256) void lane_kernel(LaneArgs a) {
+__device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   using N = Num<V>;
   using C = typename N::Coord;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.npairs) return;
   const int32_t raw = a.order[k];
   const bool swap = raw < 0;
   const int32_t idx = raw & 0x7fffffff;
   const C *Xr = static_cast<const C *>(swap ? a.X[1] : a.X[0]);
   const C *Xc = static_cast<const C *>(swap ? a.X[0] : a.X[1]);
-  const int64_t *offr = swap ? a.off[1] : a.off[0];
-  const int64_t *offc = swap ? a.off[0] : a.off[1];
+  const int32_t *offr = swap ? a.off[1] : a.off[0];
+  const int32_t *offc = swap ? a.off[0] : a.off[1];
   const int64_t ro = offr[idx], n = offr[idx + 1] - ro;
   const int64_t co = offc[idx], m = offc[idx + 1] - co;
 
@@ -58,43 +65,53 @@ __global__ __launch_bounds__(256) void lane_kernel(LaneArgs a) {
 #pragma unroll
   for (int j = 0; j < M; ++j) row[j] = N::inf();
 
-  // the points of the rows, loaded kAhead rows before they are swept (a
-  // lane's loads are gathers from its own curve; a row of 16 columns is
-  // shorter than their latency)
-  constexpr int kAhead = 8;
-  C nxt[kAhead][D];
+  // the points of the rows, loaded kAhead row pairs before they are swept
+  // (a lane's loads are gathers from its own curve)
+  constexpr int kAhead = 4;
+  C nxt[kAhead][2][D];
+  auto load_pair = [&](int64_t i, C (&dst)[2][D]) {
 #pragma unroll
-  for (int r = 0; r < kAhead; ++r) {
-    const int64_t ir = r < n ? r : n - 1;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t ir = i + h < n ? i + h : n - 1;
 #pragma unroll
-    for (int c = 0; c < D; ++c) nxt[r][c] = Xr[(ro + ir) * D + c];
-  }
-  for (int64_t i0 = 0; i0 < n; i0 += kAhead) {
+      for (int c = 0; c < D; ++c) dst[h][c] = Xr[(ro + ir) * D + c];
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < kAhead; ++r) load_pair(2 * r, nxt[r]);
+  for (int64_t i0 = 0; i0 < n; i0 += 2 * kAhead) {
 #pragma unroll
     for (int r = 0; r < kAhead; ++r) {
-      const int64_t i = i0 + r;
+      const int64_t i = i0 + 2 * r;
       if (i < n) {
-        V p[D];
+        V pa[D], pb[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) p[c] = N::cvt(nxt[r][c]);
-        const int64_t in = i + kAhead < n ? i + kAhead : n - 1;
-#pragma unroll
-        for (int c = 0; c < D; ++c) nxt[r][c] = Xr[(ro + in) * D + c];
-        V diag = i == 0 ? -N::inf() : N::inf();  // M_{i-1,-1}: the corner above the first row
-        V left = N::inf();                       // M_{i,-1}
+        for (int c = 0; c < D; ++c) {
+          pa[c] = N::cvt(nxt[r][0][c]);
+          pb[c] = N::cvt(nxt[r][1][c]);  // row i + 1, or row n - 1 again
+        }
+        load_pair(i + 2 * kAhead, nxt[r]);
+        V diag_a = i == 0 ? -N::inf() : N::inf();  // M_{i-1,-1}: the corner above the first row
+        V left_a = N::inf();                       // M_{i,-1}
+        V diag_b = N::inf();                       // M_{i,-1}
+        V left_b = N::inf();                       // M_{i+1,-1}
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          V t = p[0] - q[j][0];
-          V d = t * t;
+          V t = pa[0] - q[j][0], u = pb[0] - q[j][0];
+          V da = t * t, db = u * u;
 #pragma unroll
           for (int c = 1; c < D; ++c) {
-            V w = p[c] - q[j][c];
-            d = N::fma(w, w, d);
+            V w = pa[c] - q[j][c], z = pb[c] - q[j][c];
+            da = N::fma(w, w, da);
+            db = N::fma(z, z, db);
           }
-          const V v = N::mx(N::mn(N::mn(row[j], diag), left), d);
-          diag = row[j];
-          row[j] = v;
-          left = v;
+          const V va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
+          const V vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
+          diag_a = row[j];
+          left_a = va;
+          diag_b = va;
+          left_b = vb;
+          row[j] = vb;
         }
       }
     }
@@ -102,47 +119,45 @@ __global__ __launch_bounds__(256) void lane_kernel(LaneArgs a) {
   N::store(a.out, idx, row[M - 1], a.metric);
 }
 
-template <int M, typename V>
-hipError_t launch_m(int D, const LaneArgs &a, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.npairs + 255) / 256);
+template <int M, int D, typename V>
+__device__ __forceinline__ void lane_class(const LaneArgs &a, int64_t k) {
+  if constexpr (M <= lane_cols_max(sizeof(V) == 8, D)) lane_pair<M, D, V>(a, k);
+}
+
+template <int D, typename V>
+__global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
+  const int64_t b = blockIdx.x;
+  int c = 0;
+  while (c + 1 < a.classes && b >= a.block_first[c + 1]) ++c;
+  const int64_t k = a.first[c] + (b - a.block_first[c]) * kLaneBlock + threadIdx.x;
+  if (k >= a.first[c + 1]) return;
+  switch (a.cols[c]) {
+    case 64: lane_class<64, D, V>(a, k); break;
+    case 32: lane_class<32, D, V>(a, k); break;
+    default: lane_class<16, D, V>(a, k); break;
+  }
+}
+
+template <typename V>
+hipError_t launch_v(int D, const LaneArgs &a, hipStream_t st) {
+  for (int c = 0; c < a.classes; ++c)
+    if (a.cols[c] > lane_cols_max(sizeof(V) == 8, D)) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)a.block_first[a.classes];
   switch (D) {
-    case 1: hipLaunchKernelGGL((lane_kernel<M, 1, V>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((lane_kernel<M, 2, V>), dim3(blocks), dim3(256), 0, st, a); break;
-    case 3:
-      if constexpr (M <= lane_cols_max(sizeof(V) == 8, 3)) {
-        hipLaunchKernelGGL((lane_kernel<M, 3, V>), dim3(blocks), dim3(256), 0, st, a);
-        break;
-      }
-      return hipErrorInvalidValue;
-    case 4:
-      if constexpr (M <= lane_cols_max(sizeof(V) == 8, 4)) {
-        hipLaunchKernelGGL((lane_kernel<M, 4, V>), dim3(blocks), dim3(256), 0, st, a);
-        break;
-      }
-      return hipErrorInvalidValue;
+    case 1: hipLaunchKernelGGL((lane_kernel<1, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((lane_kernel<2, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((lane_kernel<3, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((lane_kernel<4, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename V>
-hipError_t launch_v(int M, int D, const LaneArgs &a, hipStream_t st) {
-  if (M > lane_cols_max(sizeof(V) == 8, D)) return hipErrorInvalidValue;
-  switch (M) {
-    case 16: return launch_m<16, V>(D, a, st);
-    case 32: return launch_m<32, V>(D, a, st);
-    case 64:
-      if constexpr (sizeof(V) == 4) return launch_m<64, V>(D, a, st);
-      return hipErrorInvalidValue;
-  }
-  return hipErrorInvalidValue;
-}
-
 }  // namespace
 
-hipError_t launch_lanes(bool exact, int M, int D, const LaneArgs &a, hipStream_t st) {
-  if (a.npairs <= 0) return hipSuccess;
-  return exact ? launch_v<double>(M, D, a, st) : launch_v<float>(M, D, a, st);
+hipError_t launch_lanes(bool exact, int D, const LaneArgs &a, hipStream_t st) {
+  if (a.classes < 1 || a.classes > 3 || a.block_first[a.classes] <= 0) return hipSuccess;
+  return exact ? launch_v<double>(D, a, st) : launch_v<float>(D, a, st);
 }
 
 }  // namespace ffd
