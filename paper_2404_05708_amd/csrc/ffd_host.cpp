@@ -714,8 +714,8 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // A batch whose pairs all have a curve of at most lane_cols_max points runs
 // on the one-pair-per-lane kernel (ffd_lanes.hip) when the model says it is
 // faster: each lane sweeps the longer curve's rows against the shorter
-// curve held in registers, 16, 32 or 64 columns (classes of column count,
-// the widest first, in one launch), the pairs of a class in decreasing row
+// curve held in registers, padded to a multiple of 8 columns (classes of
+// column count, the widest first, in one launch), the pairs of a class in decreasing row
 // count so that the lanes of a wavefront sweep about as many rows.
 // Modelled clocks: per row of a lane, M cells of 2 D + 2 instructions
 // (FP64: 2 D + 3) and about 8 of loop and load work; a wavefront takes its
@@ -728,19 +728,17 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   // the kernel reads 32-bit offsets (half the upload of every call)
   if (p_off[npairs] > INT32_MAX || q_off[npairs] > INT32_MAX) return false;
   const int cmax = ffd::lane_cols_max(exact, D);
-  const int classes[3] = {16, 32, 64};
   struct Item {
     int64_t rows;
     int32_t key;
   };
-  std::vector<Item> cls[3];
+  std::vector<Item> cls[ffd::kLaneClasses];
   for (int64_t k = 0; k < npairs; ++k) {
     const int64_t n = p_off[k + 1] - p_off[k], m = q_off[k + 1] - q_off[k];
     const bool swap = n < m;  // the shorter curve holds the columns
     const int64_t cols = swap ? n : m, rows = swap ? m : n;
     if (cols > cmax) return false;
-    int c = 0;
-    while (classes[c] < cols) ++c;
+    const int c = (int)((cols - 1) / ffd::kLaneColStep);  // columns padded to (c + 1) * kLaneColStep
     cls[c].push_back({rows, (int32_t)((uint32_t)k | (swap ? 0x80000000u : 0u))});
   }
   pl = Plan();
@@ -748,13 +746,13 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   pl.R = 0;
   pl.wpb = 4;
   double total = 0, longest = 0;
-  for (int c = 2; c >= 0; --c) {
+  for (int c = ffd::kLaneClasses - 1; c >= 0; --c) {
     if (cls[c].empty()) continue;
     std::stable_sort(cls[c].begin(), cls[c].end(), [](const Item &a, const Item &b) { return a.rows > b.rows; });
     const int i = pl.lane_classes++;
-    pl.lane_cols[i] = classes[c];
+    pl.lane_cols[i] = (c + 1) * ffd::kLaneColStep;
     pl.lane_first[i] = (int64_t)pl.lane_order.size();
-    const double per_row = (double)classes[c] * (2 * D + (exact ? 3 : 2)) + 8.0;
+    const double per_row = (double)((c + 1) * ffd::kLaneColStep) * (2 * D + (exact ? 3 : 2)) + 8.0;
     for (size_t w = 0; w < cls[c].size(); w += ffd::kWave) {
       const double v = (double)cls[c][w].rows * per_row;  // the wavefront's longest lane
       total += v;

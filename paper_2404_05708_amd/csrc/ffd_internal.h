@@ -126,13 +126,13 @@ struct Plan {
   int64_t pipe_stride = 0;     // values per link row
   int64_t pipe_nlinks = 0;     // link rows
   size_t pipe_lds = 0;         // LDS requested per workgroup
-  // a batch of short pairs on the one-pair-per-lane kernel (no jobs): up to
-  // three launches, class c holding lane_order[lane_first[c], lane_first[c + 1])
-  // with column curves of at most lane_cols[c] points
+  // a batch of short pairs on the one-pair-per-lane kernel (no jobs): class
+  // c holds lane_order[lane_first[c], lane_first[c + 1]), column curves of at
+  // most lane_cols[c] points, the widest class first
   bool lanes = false;
   int32_t lane_classes = 0;
-  int32_t lane_cols[3] = {0, 0, 0};
-  int64_t lane_first[4] = {0, 0, 0, 0};
+  int32_t lane_cols[ffd::kLaneClasses] = {};
+  int64_t lane_first[ffd::kLaneClasses + 1] = {};
   std::vector<int32_t> lane_order;  // pair index; the top bit: the second set holds the rows
 };
 

@@ -14,14 +14,20 @@ struct LaneArgs {
   const int32_t *order;   // lane k -> pair index; the top bit set: the second set's curve holds the rows
   void *out;              // float32 or int64 results, indexed by pair
   int32_t metric;         // 0 Euclidean (the root taken once per pair), 1 squared Euclidean
-  int32_t classes;        // classes of column count, 1 ... 3, most columns first
-  int32_t cols[3];        // columns a lane of class c holds (64, 32 or 16)
-  int64_t first[4];       // class c: lanes [first[c], first[c + 1]) of order
-  int64_t block_first[4]; // class c: workgroups [block_first[c], block_first[c + 1]) of the launch
+  int32_t classes;        // classes of column count, 1 ... kLaneClasses, most columns first
+  int32_t cols[8];        // columns a lane of class c holds (a multiple of 8, at most 64)
+  int64_t first[9];       // class c: lanes [first[c], first[c + 1]) of order
+  int64_t block_first[9]; // class c: workgroups [block_first[c], block_first[c + 1]) of the launch
 };
 
+// Classes of column count: a lane holds its column curve padded to the next
+// multiple of kLaneColStep columns.
+constexpr int kLaneClasses = 8;
+constexpr int kLaneColStep = 8;
+
 // The largest column curve a lane holds in registers for D coordinates (16,
-// 32 or 64), by value type.
+// 32 or 64), by value type.  (A lane holds M x D coordinates and M table
+// values: at most about 192 registers' worth.)
 constexpr int lane_cols_max(bool exact, int D) {
   return exact ? (D <= 2 ? 32 : 16) : (D <= 2 ? 64 : 32);
 }

@@ -27,9 +27,9 @@
 // neighbours) overlap in the instruction stream.  A curve of odd length has
 // its last point repeated once more (exact, as above).
 //
-// One launch covers every class of column count (16, 32, 64 columns; the
-// registers are those of the widest class), its workgroups of the widest
-// class first; the host sorts the pairs of a class by row count, so that the
+// One launch covers every class of column count (multiples of 8 up to 64
+// columns; the registers are those of the widest class), its workgroups of
+// the widest class first; the host sorts the pairs of a class by row count, so that the
 // lanes of a wavefront sweep about as many rows each and the longest
 // wavefronts start first.
 #include "ffd_lanes.h"
@@ -133,8 +133,13 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
   if (k >= a.first[c + 1]) return;
   switch (a.cols[c]) {
     case 64: lane_class<64, D, V>(a, k); break;
+    case 56: lane_class<56, D, V>(a, k); break;
+    case 48: lane_class<48, D, V>(a, k); break;
+    case 40: lane_class<40, D, V>(a, k); break;
     case 32: lane_class<32, D, V>(a, k); break;
-    default: lane_class<16, D, V>(a, k); break;
+    case 24: lane_class<24, D, V>(a, k); break;
+    case 16: lane_class<16, D, V>(a, k); break;
+    default: lane_class<8, D, V>(a, k); break;
   }
 }
 
@@ -156,7 +161,7 @@ hipError_t launch_v(int D, const LaneArgs &a, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_lanes(bool exact, int D, const LaneArgs &a, hipStream_t st) {
-  if (a.classes < 1 || a.classes > 3 || a.block_first[a.classes] <= 0) return hipSuccess;
+  if (a.classes < 1 || a.classes > kLaneClasses || a.block_first[a.classes] <= 0) return hipSuccess;
   return exact ? launch_v<double>(D, a, st) : launch_v<float>(D, a, st);
 }
 

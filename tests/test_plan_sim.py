@@ -222,9 +222,9 @@ def test_short_pairs_per_lane(planner):
     assert sm["per_lane"] == 1 and sm["jobs"] == 0 and sm["rows_per_lane"] == 0
     lens = np.maximum(np.diff(p_off), np.diff(q_off))
     assert sm["stream_steps"] == lens.max()
-    # classes of 16, 32 and 64 columns: waves = pairs per class / 64, rounded up
+    # classes of column count, multiples of 8: waves = pairs per class / 64, rounded up
     short = np.minimum(np.diff(p_off), np.diff(q_off))
-    per = [np.sum(short <= 16), np.sum((short > 16) & (short <= 32)), np.sum(short > 32)]
+    per = np.bincount((short - 1) // 8, minlength=8)
     assert sm["waves"] == sum(-(-int(c) // 64) for c in per)
     # one long pair anywhere: the streaming kernel
     p2 = np.concatenate([p_off, [p_off[-1] + 500]])
