@@ -724,7 +724,9 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // rows at one per 5 clocks (alone on a SIMD).
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                  Plan &pl, double &cost) {
-  if (ctx->measure != 0 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
+  // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells
+  const int op = ctx->measure;
+  if ((op != 0 && op != 4 && op != 6) || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
   // the kernel reads 32-bit offsets (half the upload of every call)
   if (p_off[npairs] > INT32_MAX || q_off[npairs] > INT32_MAX) return false;
   const int cmax = ffd::lane_cols_max(exact, D);
@@ -1012,6 +1014,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     la.order = (const int32_t *)(w + wl.order);
     la.out = out;
     la.metric = metric;
+    la.cell = ctx->measure >> 1;  // the planner took only Frechet ops 0, 4, 6
     la.classes = pl.lane_classes;
     for (int c = 0; c < pl.lane_classes; ++c) {
       la.cols[c] = pl.lane_cols[c];

@@ -17,9 +17,10 @@
 // first row starts from the corner M_{-1,-1} = -inf with +inf elsewhere
 // around the table (the boundary reading of the streaming kernels), so Eq.
 // (1) itself produces the first row and column.  Each cell is evaluated as
-// everywhere else in the library (d2 = dx*dx, then fma(dk, dk, d2), FP64 for
-// int32 coordinates) and the Euclidean root is taken once per pair, so the
-// results equal the streaming kernels' bit for bit.
+// everywhere else in the library (d2 = dx*dx, then fma(dk, dk, d2); for
+// Manhattan and Chebyshev cells |d0|, then the sum or maximum with |dk|;
+// FP64 for int32 coordinates) and the Euclidean root is taken once per
+// pair, so the results equal the streaming kernels' bit for bit.
 //
 // A lane sweeps its rows two at a time, both rows' cells of a column
 // together: the second row's cell takes the first row's as its value above,
@@ -40,7 +41,32 @@ namespace ffd {
 
 namespace {
 
-template <int M, int D, typename V>
+// The ground distance of a cell (CELL 0 squared Euclidean, 2 Manhattan, 3
+// Chebyshev), in the streaming kernels' order of operations.
+template <int D, typename V, int CELL>
+__device__ __forceinline__ V cell_value(const V (&p)[D], const V (&q)[D]) {
+  using N = Num<V>;
+  if constexpr (CELL >= 2) {
+    V s = N::abs(p[0] - q[0]);
+#pragma unroll
+    for (int c = 1; c < D; ++c) {
+      V w = N::abs(p[c] - q[c]);
+      s = CELL == 2 ? s + w : N::mx(s, w);
+    }
+    return s;
+  } else {
+    V t = p[0] - q[0];
+    V s = t * t;
+#pragma unroll
+    for (int c = 1; c < D; ++c) {
+      V w = p[c] - q[c];
+      s = N::fma(w, w, s);
+    }
+    return s;
+  }
+}
+
+template <int M, int D, typename V, int CELL>
 __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   using N = Num<V>;
   using C = typename N::Coord;
@@ -97,14 +123,8 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
         V left_b = N::inf();                       // M_{i+1,-1}
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          V t = pa[0] - q[j][0], u = pb[0] - q[j][0];
-          V da = t * t, db = u * u;
-#pragma unroll
-          for (int c = 1; c < D; ++c) {
-            V w = pa[c] - q[j][c], z = pb[c] - q[j][c];
-            da = N::fma(w, w, da);
-            db = N::fma(z, z, db);
-          }
+          const V da = cell_value<D, V, CELL>(pa, q[j]);
+          const V db = cell_value<D, V, CELL>(pb, q[j]);
           const V va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
           const V vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
           diag_a = row[j];
@@ -116,15 +136,16 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
       }
     }
   }
-  N::store(a.out, idx, row[M - 1], a.metric);
+  if constexpr (CELL == 0) N::store(a.out, idx, row[M - 1], a.metric);
+  else N::store_value(a.out, idx, row[M - 1]);
 }
 
-template <int M, int D, typename V>
+template <int M, int D, typename V, int CELL>
 __device__ __forceinline__ void lane_class(const LaneArgs &a, int64_t k) {
-  if constexpr (M <= lane_cols_max(sizeof(V) == 8, D)) lane_pair<M, D, V>(a, k);
+  if constexpr (M <= lane_cols_max(sizeof(V) == 8, D)) lane_pair<M, D, V, CELL>(a, k);
 }
 
-template <int D, typename V>
+template <int D, typename V, int CELL>
 __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
   const int64_t b = blockIdx.x;
   int c = 0;
@@ -132,30 +153,40 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
   const int64_t k = a.first[c] + (b - a.block_first[c]) * kLaneBlock + threadIdx.x;
   if (k >= a.first[c + 1]) return;
   switch (a.cols[c]) {
-    case 64: lane_class<64, D, V>(a, k); break;
-    case 56: lane_class<56, D, V>(a, k); break;
-    case 48: lane_class<48, D, V>(a, k); break;
-    case 40: lane_class<40, D, V>(a, k); break;
-    case 32: lane_class<32, D, V>(a, k); break;
-    case 24: lane_class<24, D, V>(a, k); break;
-    case 16: lane_class<16, D, V>(a, k); break;
-    default: lane_class<8, D, V>(a, k); break;
+    case 64: lane_class<64, D, V, CELL>(a, k); break;
+    case 56: lane_class<56, D, V, CELL>(a, k); break;
+    case 48: lane_class<48, D, V, CELL>(a, k); break;
+    case 40: lane_class<40, D, V, CELL>(a, k); break;
+    case 32: lane_class<32, D, V, CELL>(a, k); break;
+    case 24: lane_class<24, D, V, CELL>(a, k); break;
+    case 16: lane_class<16, D, V, CELL>(a, k); break;
+    default: lane_class<8, D, V, CELL>(a, k); break;
   }
+}
+
+template <typename V, int CELL>
+hipError_t launch_c(int D, const LaneArgs &a, hipStream_t st) {
+  const unsigned blocks = (unsigned)a.block_first[a.classes];
+  switch (D) {
+    case 1: hipLaunchKernelGGL((lane_kernel<1, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((lane_kernel<2, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((lane_kernel<3, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((lane_kernel<4, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <typename V>
 hipError_t launch_v(int D, const LaneArgs &a, hipStream_t st) {
   for (int c = 0; c < a.classes; ++c)
     if (a.cols[c] > lane_cols_max(sizeof(V) == 8, D)) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)a.block_first[a.classes];
-  switch (D) {
-    case 1: hipLaunchKernelGGL((lane_kernel<1, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((lane_kernel<2, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((lane_kernel<3, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((lane_kernel<4, V>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+  switch (a.cell) {
+    case 0: return launch_c<V, 0>(D, a, st);
+    case 2: return launch_c<V, 2>(D, a, st);
+    case 3: return launch_c<V, 3>(D, a, st);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace

@@ -5,8 +5,9 @@ the Euclidean root once per pair, so its results must equal the streaming
 kernel's (forced with a rows-per-lane setting, which keeps the job-table
 plan) bit for bit, for every pair; a sample is also checked against the
 oracle's float32 replica and the FP64 oracle (2e-6), and the int32 path
-against the int64 oracle for every pair.  Lengths cover the three column
-classes (16, 32, 64), their boundaries, single points and both orientations.
+against the int64 oracle for every pair.  Lengths cover the column classes
+(multiples of 8 up to 64), their boundaries, single points and both
+orientations.
 """
 import sys
 
@@ -96,6 +97,35 @@ def test_lanes_equal_streaming_kernel(ctx, dim, hi):
             want = oracle.dfd_pairs(P, p_off[:-1][sample], np.diff(p_off)[sample], Q, q_off[:-1][sample],
                                     np.diff(q_off)[sample], 0, 8)
             assert np.all(np.abs(got[sample] - want) <= TOL * want)
+
+
+@pytest.mark.parametrize("dim,hi", [(1, 64), (3, 32)])
+def test_lanes_manhattan_chebyshev(ctx, ffdmod, dim, hi):
+    """The Frechet distance on Manhattan and Chebyshev cells, one pair per
+    lane: the streaming kernel's bits for every pair, the replica's on a
+    sample."""
+    P, p_off, Q, q_off = short_pairs(550 + dim, 150000, 1, hi, dim)
+    Pd, Qd = dev(P), dev(Q)
+    sample = np.arange(0, len(p_off) - 1, 997)
+    for metric in (ffdmod.FFD_MANHATTAN, ffdmod.FFD_CHEBYSHEV):
+        say(f"case: lanes dim={dim} metric={metric}")
+        got = ctx.batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 1
+        ctx.set_tuning(1, 0)
+        try:
+            ref = ctx.batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+        finally:
+            ctx.set_tuning(0, 0)
+        np.testing.assert_array_equal(got, ref)
+        for k in sample:
+            p, q = P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]]
+            assert got[k] == oracle.dfd_f32_replica(p, q, metric), k
+    Pi, pio, Qi, qio = short_pairs(560 + dim, 150000, 1, 16, dim, kind="int")
+    for metric in (ffdmod.FFD_MANHATTAN, ffdmod.FFD_CHEBYSHEV):
+        say(f"case: lanes int32 dim={dim} metric={metric}")
+        got = ctx.batch_i32(dev(Pi), pio, dev(Qi), qio, metric=metric).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 1
+        np.testing.assert_array_equal(got, oracle.dfd_batch_i32(Pi, pio, Qi, qio, nthreads=8, metric=metric))
 
 
 @pytest.mark.parametrize("dim,hi", [(2, 32), (4, 16)])
