@@ -173,6 +173,10 @@ int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q
  *   workspace: device memory of ws_bytes >= ffd_workspace_size(FFD_OP_BATCH).
  *   Contents of the workspace are overwritten; it may be reused across calls
  *   once the previous call on it has completed.
+ *   A batch of many short pairs (every pair with a curve of at most 64
+ *   points; 32 for dim 3 and 4) may run one pair per GPU lane when that is
+ *   modelled faster (ffd_last_launch reports per_lane = 1): the same results,
+ *   bit for bit.
  * npairs == 0 is a no-op.  Errors: FFD_E_INVALID (bad offsets, NULL, metric),
  * FFD_E_UNSUPPORTED (dim), FFD_E_NOMEM (workspace too small). */
 int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q,
