@@ -724,9 +724,10 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // rows at one per 5 clocks (alone on a SIMD).
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                  Plan &pl, double &cost) {
-  // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells
+  // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells,
+  // DTW on those or on Euclidean cells (ops 0 ... 7)
   const int op = ctx->measure;
-  if ((op != 0 && op != 4 && op != 6) || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
+  if (op < 0 || op > 7 || op == 2 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
   // the kernel reads 32-bit offsets (half the upload of every call)
   if (p_off[npairs] > INT32_MAX || q_off[npairs] > INT32_MAX) return false;
   const int cmax = ffd::lane_cols_max(exact, D);
@@ -754,7 +755,8 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
     const int i = pl.lane_classes++;
     pl.lane_cols[i] = (c + 1) * ffd::kLaneColStep;
     pl.lane_first[i] = (int64_t)pl.lane_order.size();
-    const double per_row = (double)((c + 1) * ffd::kLaneColStep) * (2 * D + (exact ? 3 : 2)) + 8.0;
+    const double per_row =
+        (double)((c + 1) * ffd::kLaneColStep) * (2 * D + (exact ? 3 : 2) + ((op >> 1) == 1 ? 4 : 0)) + 8.0;
     for (size_t w = 0; w < cls[c].size(); w += ffd::kWave) {
       const double v = (double)cls[c][w].rows * per_row;  // the wavefront's longest lane
       total += v;
@@ -1014,7 +1016,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     la.order = (const int32_t *)(w + wl.order);
     la.out = out;
     la.metric = metric;
-    la.cell = ctx->measure >> 1;  // the planner took only Frechet ops 0, 4, 6
+    la.cell = ctx->measure >> 1;  // the planner took only ops 0 ... 7 but 2
+    la.dtw = ctx->measure & 1;
     la.classes = pl.lane_classes;
     for (int c = 0; c < pl.lane_classes; ++c) {
       la.cols[c] = pl.lane_cols[c];

@@ -14,7 +14,8 @@ struct LaneArgs {
   const int32_t *order;   // lane k -> pair index; the top bit set: the second set's curve holds the rows
   void *out;              // float32 or int64 results, indexed by pair
   int32_t metric;         // squared cells: 0 Euclidean (the root taken once per pair), 1 squared Euclidean
-  int32_t cell;           // ground distance: 0 squared Euclidean, 2 Manhattan, 3 Chebyshev
+  int32_t cell;           // ground distance: 0 squared Euclidean, 1 Euclidean (DTW), 2 Manhattan, 3 Chebyshev
+  int32_t dtw;            // 1: dynamic time warping (Appendix B), 0: the Frechet distance
   int32_t classes;        // classes of column count, 1 ... kLaneClasses, most columns first
   int32_t cols[8];        // columns a lane of class c holds (a multiple of 8, at most 64)
   int64_t first[9];       // class c: lanes [first[c], first[c + 1]) of order

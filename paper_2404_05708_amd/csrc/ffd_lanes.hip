@@ -28,6 +28,12 @@
 // neighbours) overlap in the instruction stream.  A curve of odd length has
 // its last point repeated once more (exact, as above).
 //
+// Dynamic time warping (Appendix B, Algorithm B.1: the outer max becomes a
+// sum, the corner 0) runs on the same sweep; sums are not selections, so
+// there the padding is not exact: the result is read at the column curve's
+// own last column (columns to its right never feed it), and the second row
+// of a pair is dropped when the row curve has no row left.
+//
 // One launch covers every class of column count (multiples of 8 up to 64
 // columns; the registers are those of the widest class), its workgroups of
 // the widest class first; the host sorts the pairs of a class by row count, so that the
@@ -46,7 +52,9 @@ namespace {
 template <int D, typename V, int CELL>
 __device__ __forceinline__ V cell_value(const V (&p)[D], const V (&q)[D]) {
   using N = Num<V>;
-  if constexpr (CELL >= 2) {
+  if constexpr (CELL == 1) {
+    return N::sqrt_cell(cell_value<D, V, 0>(p, q));  // DTW of Euclidean cells: a root per cell
+  } else if constexpr (CELL >= 2) {
     V s = N::abs(p[0] - q[0]);
 #pragma unroll
     for (int c = 1; c < D; ++c) {
@@ -66,7 +74,7 @@ __device__ __forceinline__ V cell_value(const V (&p)[D], const V (&q)[D]) {
   }
 }
 
-template <int M, int D, typename V, int CELL>
+template <int M, int D, typename V, int CELL, bool DTW>
 __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   using N = Num<V>;
   using C = typename N::Coord;
@@ -117,35 +125,53 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
           pb[c] = N::cvt(nxt[r][1][c]);  // row i + 1, or row n - 1 again
         }
         load_pair(i + 2 * kAhead, nxt[r]);
-        V diag_a = i == 0 ? -N::inf() : N::inf();  // M_{i-1,-1}: the corner above the first row
+        // M_{i-1,-1}: the corner above the first row (-inf for the Frechet
+        // distance, 0 for DTW), +inf below it
+        V diag_a = i == 0 ? (DTW ? V(0) : -N::inf()) : N::inf();
         V left_a = N::inf();                       // M_{i,-1}
         V diag_b = N::inf();                       // M_{i,-1}
         V left_b = N::inf();                       // M_{i+1,-1}
+        const bool two = !DTW || i + 1 < n;        // DTW: no repeated row
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           const V da = cell_value<D, V, CELL>(pa, q[j]);
           const V db = cell_value<D, V, CELL>(pb, q[j]);
-          const V va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
-          const V vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
+          V va, vb;
+          if constexpr (DTW) {
+            va = N::mn(N::mn(row[j], diag_a), left_a) + da;
+            vb = N::mn(N::mn(va, diag_b), left_b) + db;
+          } else {
+            va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
+            vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
+          }
           diag_a = row[j];
           left_a = va;
           diag_b = va;
           left_b = vb;
-          row[j] = vb;
+          row[j] = DTW ? (two ? vb : va) : vb;
         }
       }
     }
   }
-  if constexpr (CELL == 0) N::store(a.out, idx, row[M - 1], a.metric);
-  else N::store_value(a.out, idx, row[M - 1]);
+  if constexpr (DTW) {
+    // the value at the column curve's own last column
+    V res = row[0];
+#pragma unroll
+    for (int j = 1; j < M; ++j) res = j == m - 1 ? row[j] : res;
+    N::store_value(a.out, idx, res);
+  } else if constexpr (CELL == 0) {
+    N::store(a.out, idx, row[M - 1], a.metric);
+  } else {
+    N::store_value(a.out, idx, row[M - 1]);
+  }
 }
 
-template <int M, int D, typename V, int CELL>
+template <int M, int D, typename V, int CELL, bool DTW>
 __device__ __forceinline__ void lane_class(const LaneArgs &a, int64_t k) {
-  if constexpr (M <= lane_cols_max(sizeof(V) == 8, D)) lane_pair<M, D, V, CELL>(a, k);
+  if constexpr (M <= lane_cols_max(sizeof(V) == 8, D)) lane_pair<M, D, V, CELL, DTW>(a, k);
 }
 
-template <int D, typename V, int CELL>
+template <int D, typename V, int CELL, bool DTW>
 __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
   const int64_t b = blockIdx.x;
   int c = 0;
@@ -153,25 +179,25 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a) {
   const int64_t k = a.first[c] + (b - a.block_first[c]) * kLaneBlock + threadIdx.x;
   if (k >= a.first[c + 1]) return;
   switch (a.cols[c]) {
-    case 64: lane_class<64, D, V, CELL>(a, k); break;
-    case 56: lane_class<56, D, V, CELL>(a, k); break;
-    case 48: lane_class<48, D, V, CELL>(a, k); break;
-    case 40: lane_class<40, D, V, CELL>(a, k); break;
-    case 32: lane_class<32, D, V, CELL>(a, k); break;
-    case 24: lane_class<24, D, V, CELL>(a, k); break;
-    case 16: lane_class<16, D, V, CELL>(a, k); break;
-    default: lane_class<8, D, V, CELL>(a, k); break;
+    case 64: lane_class<64, D, V, CELL, DTW>(a, k); break;
+    case 56: lane_class<56, D, V, CELL, DTW>(a, k); break;
+    case 48: lane_class<48, D, V, CELL, DTW>(a, k); break;
+    case 40: lane_class<40, D, V, CELL, DTW>(a, k); break;
+    case 32: lane_class<32, D, V, CELL, DTW>(a, k); break;
+    case 24: lane_class<24, D, V, CELL, DTW>(a, k); break;
+    case 16: lane_class<16, D, V, CELL, DTW>(a, k); break;
+    default: lane_class<8, D, V, CELL, DTW>(a, k); break;
   }
 }
 
-template <typename V, int CELL>
+template <typename V, int CELL, bool DTW>
 hipError_t launch_c(int D, const LaneArgs &a, hipStream_t st) {
   const unsigned blocks = (unsigned)a.block_first[a.classes];
   switch (D) {
-    case 1: hipLaunchKernelGGL((lane_kernel<1, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((lane_kernel<2, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((lane_kernel<3, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((lane_kernel<4, V, CELL>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((lane_kernel<1, V, CELL, DTW>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((lane_kernel<2, V, CELL, DTW>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((lane_kernel<3, V, CELL, DTW>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((lane_kernel<4, V, CELL, DTW>), dim3(blocks), dim3(kLaneBlock), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -181,10 +207,21 @@ template <typename V>
 hipError_t launch_v(int D, const LaneArgs &a, hipStream_t st) {
   for (int c = 0; c < a.classes; ++c)
     if (a.cols[c] > lane_cols_max(sizeof(V) == 8, D)) return hipErrorInvalidValue;
+  if (a.dtw) {
+    switch (a.cell) {
+      case 0: return launch_c<V, 0, true>(D, a, st);
+      case 1:
+        if constexpr (sizeof(V) == 4) return launch_c<V, 1, true>(D, a, st);  // float32 coordinates only
+        return hipErrorInvalidValue;
+      case 2: return launch_c<V, 2, true>(D, a, st);
+      case 3: return launch_c<V, 3, true>(D, a, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (a.cell) {
-    case 0: return launch_c<V, 0>(D, a, st);
-    case 2: return launch_c<V, 2>(D, a, st);
-    case 3: return launch_c<V, 3>(D, a, st);
+    case 0: return launch_c<V, 0, false>(D, a, st);
+    case 2: return launch_c<V, 2, false>(D, a, st);
+    case 3: return launch_c<V, 3, false>(D, a, st);
   }
   return hipErrorInvalidValue;
 }

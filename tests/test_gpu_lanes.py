@@ -128,6 +128,37 @@ def test_lanes_manhattan_chebyshev(ctx, ffdmod, dim, hi):
         np.testing.assert_array_equal(got, oracle.dfd_batch_i32(Pi, pio, Qi, qio, nthreads=8, metric=metric))
 
 
+@pytest.mark.parametrize("dim,hi", [(1, 64), (2, 64), (3, 32)])
+def test_lanes_dtw(ctx, ffdmod, dim, hi):
+    """DTW one pair per lane (sums: the result read at the column curve's own
+    last column, no repeated row): the streaming kernel's bits for every pair
+    on every cell, the replica's on a sample; int32 exact."""
+    P, p_off, Q, q_off = short_pairs(570 + dim, 150000, 1, hi, dim)
+    Pd, Qd = dev(P), dev(Q)
+    sample = np.arange(0, len(p_off) - 1, 1499)
+    sample = np.unique(np.concatenate([sample, np.arange(len(p_off) - 13, len(p_off) - 1)]))
+    for metric in (ffdmod.FFD_SQEUCLIDEAN, ffdmod.FFD_EUCLIDEAN, ffdmod.FFD_MANHATTAN, ffdmod.FFD_CHEBYSHEV):
+        say(f"case: lanes dtw dim={dim} metric={metric}")
+        got = ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 1
+        ctx.set_tuning(1, 0)
+        try:
+            ref = ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=metric).cpu().numpy()
+            assert ctx.last_launch()["per_lane"] == 0
+        finally:
+            ctx.set_tuning(0, 0)
+        np.testing.assert_array_equal(got, ref)
+        if metric != ffdmod.FFD_EUCLIDEAN:  # the replica takes the correctly rounded root per cell
+            for k in sample:
+                p, q = P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]]
+                assert got[k] == oracle.dtw_f32_replica(p, q, metric), (k, len(p), len(q))
+    Pi, pio, Qi, qio = short_pairs(580 + dim, 150000, 1, 16, dim, kind="int")
+    say(f"case: lanes dtw int32 dim={dim}")
+    got = ctx.dtw_batch_i32(dev(Pi), pio, dev(Qi), qio).cpu().numpy()
+    assert ctx.last_launch()["per_lane"] == 1
+    np.testing.assert_array_equal(got, oracle.dtw_batch_i32(Pi, pio, Qi, qio, nthreads=8))
+
+
 @pytest.mark.parametrize("dim,hi", [(2, 32), (4, 16)])
 def test_lanes_int_exact(ctx, dim, hi):
     P, p_off, Q, q_off = short_pairs(600 + dim, 150000, 1, hi, dim, kind="int")

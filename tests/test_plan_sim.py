@@ -204,9 +204,10 @@ def test_wide_dimensions(planner, dim, R):
 def test_short_pairs_per_lane(planner):
     """A batch whose pairs all have a curve of at most 64 points (32 for
     3-D and 4-D, half that for the exact path) runs one pair per lane when
-    the model prefers it (the Frechet distance on squared Euclidean,
-    Manhattan or Chebyshev cells); a batch with one longer pair, a forced
-    launch shape, DTW or a split setting keeps the job-table plan."""
+    the model prefers it (the Frechet distance and DTW on squared Euclidean,
+    Manhattan or Chebyshev cells, DTW also on Euclidean cells); a batch with
+    one longer pair, a forced launch shape, Levenshtein or a split setting
+    keeps the job-table plan."""
     def offsets(seed, count, lo, hi):
         rng = np.random.default_rng(seed)
         a = np.concatenate([[0], np.cumsum(rng.integers(lo, hi + 1, size=count))]).astype(np.int64)
@@ -243,7 +244,9 @@ def test_short_pairs_per_lane(planner):
     for metric in (ffd.FFD_MANHATTAN, ffd.FFD_CHEBYSHEV):  # the Frechet distance on other cells
         sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 2, metric=metric)
         assert sm["per_lane"] == 1
-    assert batch_case(planner, pb, qb, dim=2, dtw=True)["per_lane"] == 0
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 2, dtw=True)
+    assert sm["per_lane"] == 1  # DTW too
+    assert batch_case(planner, pb, qb, dim=2, levenshtein=True, exact=True)["per_lane"] == 0
     ffd.ffd_set_tuning(planner, 1, 0)
     try:
         assert batch_case(planner, pb, qb, dim=2)["per_lane"] == 0
