@@ -288,9 +288,13 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     out = torch.empty(npairs, dtype=torch.float32, device=dev)
+    dtw = args.dtw  # DTW of squared Euclidean cells instead of the Frechet distance
 
     def step():
-        ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+        if dtw:
+            ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_SQEUCLIDEAN, out=out, workspace=ws, stream=stream)
+        else:
+            ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -300,9 +304,17 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     res = out.cpu().numpy()
     import oracle
     idx = np.sort(np.random.default_rng(79).choice(npairs, size=256, replace=False))
-    want = oracle.dfd_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
-                            oracle.EUCLIDEAN, cpu_cores())
-    parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
+    if dtw:
+        want = np.array([oracle.dtw(P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]], oracle.SQEUCLIDEAN)
+                         for k in idx])
+    else:
+        want = oracle.dfd_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
+                                oracle.EUCLIDEAN, cpu_cores())
+    if dtw:  # float32 sums: within (n + m + 2 D + 2) roundings
+        tol = (np.diff(p_off)[idx] + np.diff(q_off)[idx] + 2 * dim + 2) * 2.0 ** -24 * 1.01
+        parity_ok = bool(np.all(np.abs(res[idx] - want) <= tol * want))
+    else:
+        parity_ok = bool(np.all(np.abs(res[idx] - want) <= TOL * want))
     # the streaming kernel on the same pairs: any forced setting keeps the job-table plan
     ctx.set_tuning(0, 2)
     try:
@@ -315,7 +327,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     finally:
         ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not dtw:
         cores = cpu_cores()
         rng = np.random.default_rng(80)
         sample = np.sort(rng.choice(npairs, size=min(npairs, 65536), replace=False))
@@ -329,11 +341,12 @@ def run_short(args, torch, ffd, ctx, dev, stream):
                          f"on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))}
     rl = roofline(info, cells, kms, dim, False, family="lane_kernel")
-    rl["kernel"] = "ffd::lane_kernel<16|32|64, 2, float> (one launch per column class)"
+    rl["kernel"] = f"ffd::lane_kernel<2, float, 0, {'true' if dtw else 'false'}> (one launch, column classes 8 .. 64)"
     return {
         "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
         "config": {"workload": f"short pairs: {npairs} pairs, n and m uniform in [8, 64], 2-D float32 random walks, "
-                               "Euclidean (seed 11)", "npairs": npairs, "cells": cells, "global_batch": npairs},
+                               + ("DTW of squared Euclidean cells" if dtw else "Euclidean") + " (seed 11)",
+                   "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": ctx.last_errors(),
                    "streaming_kernel_bit_identical": same},
         "roofline": rl,
@@ -935,6 +948,7 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--metric", choices=["euclidean", "manhattan", "chebyshev"], default="euclidean",
                     help="ground distance of the batched workload")
+    ap.add_argument("--dtw", action="store_true", help="short workload: DTW of squared cells")
     ap.add_argument("--dim", type=int, default=2,
                     help="coordinates per point of the batched workload (its headline form is 2-D)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
