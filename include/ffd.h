@@ -173,10 +173,10 @@ int ffd_distance_i32(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q
  *   workspace: device memory of ws_bytes >= ffd_workspace_size(FFD_OP_BATCH).
  *   Contents of the workspace are overwritten; it may be reused across calls
  *   once the previous call on it has completed.
- *   A batch of many short pairs (every pair with a curve of at most 64
- *   points; 32 for dim 3 and 4) may run one pair per GPU lane when that is
- *   modelled faster (ffd_last_launch reports per_lane = 1): the same results,
- *   bit for bit.
+ *   Many short pairs (a curve of at most 64 points; 32 for dim 3 and 4) may
+ *   run one pair per GPU lane, alone or in a launch before the streaming
+ *   kernel's for the batch's other pairs, when that is modelled faster
+ *   (ffd_last_launch reports per_lane = 1): the same results, bit for bit.
  * npairs == 0 is a no-op.  Errors: FFD_E_INVALID (bad offsets, NULL, metric),
  * FFD_E_UNSUPPORTED (dim), FFD_E_NOMEM (workspace too small). */
 int ffd_batch(ffd_ctx *ctx, const float *P, const int64_t *p_off, const float *Q,
@@ -335,10 +335,12 @@ typedef struct ffd_plan_summary {
                               no job table; waves = 4 x workgroups, one band
                               of 64 R rows per wave and pass, link_elems
                               values of boundary rows between workgroups   */
-  int32_t per_lane;        /* 1: a batch of short pairs, one pair per lane
-                              (rows_per_lane 0, no job table; waves = pairs
-                              / 64 rounded up per class of column count,
-                              stream_steps = the most rows of any lane)    */
+  int32_t per_lane;        /* 1: short pairs one per lane.  With no job table
+                              the whole batch (rows_per_lane 0; waves =
+                              pairs / 64 rounded up per class of column
+                              count, stream_steps = the most rows of any
+                              lane); with one, the batch's short pairs, in a
+                              launch before the job table's for the rest  */
 } ffd_plan_summary;
 typedef struct ffd_plan_job { /* 64 bytes */
   int64_t out_base;   /* output index of the first column curve              */
@@ -385,7 +387,9 @@ typedef struct ffd_launch_info {
   int32_t pipelined;       /* 1: the pipelined single-pair kernel           */
   int32_t helper_waves;    /* waves per workgroup that compute no band      */
   int64_t stream_steps;    /* longest per-wave stream (steps)               */
-  int32_t per_lane;        /* 1: short pairs, one per lane (rows_per_lane 0) */
+  int32_t per_lane;        /* 1: short pairs one per lane: the whole batch
+                              (rows_per_lane 0) or, before this streaming
+                              launch, the batch's short pairs             */
 } ffd_launch_info;
 
 int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info);

@@ -172,6 +172,23 @@ void batch_units(const CurveSet &P, const CurveSet &Q, int R, std::vector<Unit> 
   }
 }
 
+// Units of the pairs listed in idx only (the rest of a batch runs elsewhere).
+void batch_units_of(const CurveSet &P, const CurveSet &Q, int R, const std::vector<int32_t> &idx,
+                    std::vector<Unit> &units) {
+  std::vector<Unit> all;
+  units.clear();
+  units.reserve(idx.size());
+  for (int32_t k : idx) {
+    int64_t off_p[2] = {0, P.len(k)}, off_q[2] = {0, Q.len(k)};
+    CurveSet p1{off_p, 1}, q1{off_q, 1};
+    batch_units(p1, q1, R, all);
+    Unit u = all[0];
+    u.row_idx = u.col_first = k;
+    u.out_base = k;
+    units.push_back(u);
+  }
+}
+
 // Units of queries x database: query i against runs of consecutive database
 // curves of about `target` steps each.
 void cross_units(const CurveSet &Qs, const CurveSet &DB, int R, double target, std::vector<Unit> &units) {
@@ -722,8 +739,10 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // longest lane's rows; the wavefronts share the SIMDs at about one
 // instruction per 4.5 clocks, and no wavefront can finish before its own
 // rows at one per 5 clocks (alone on a SIMD).
+// With `rest`, pairs whose curves are both longer than a lane holds are
+// listed there instead of making the batch ineligible (false: no pair fits).
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
-                 Plan &pl, double &cost) {
+                 Plan &pl, double &cost, std::vector<int32_t> *rest = nullptr) {
   // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells,
   // DTW on those or on Euclidean cells (ops 0 ... 7)
   const int op = ctx->measure;
@@ -740,10 +759,15 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
     const int64_t n = p_off[k + 1] - p_off[k], m = q_off[k + 1] - q_off[k];
     const bool swap = n < m;  // the shorter curve holds the columns
     const int64_t cols = swap ? n : m, rows = swap ? m : n;
-    if (cols > cmax) return false;
+    if (cols > cmax) {
+      if (!rest) return false;
+      rest->push_back((int32_t)k);
+      continue;
+    }
     const int c = (int)((cols - 1) / ffd::kLaneColStep);  // columns padded to (c + 1) * kLaneColStep
     cls[c].push_back({rows, (int32_t)((uint32_t)k | (swap ? 0x80000000u : 0u))});
   }
+  if (rest && rest->size() == (size_t)npairs) return false;
   pl = Plan();
   pl.lanes = true;
   pl.R = 0;
@@ -780,11 +804,32 @@ int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t
   int rc = plan_units(ctx, D, exact, W, split_share(ctx), false,
                       [&](int R, int, std::vector<Unit> &u) { batch_units(P, Q, R, u); }, pl, &cost);
   if (rc) return rc;
-  // short pairs, one per lane, when no launch shape is forced and the model prefers it
+  // short pairs, one per lane, when no launch shape is forced and the model
+  // prefers it: the whole batch, or its short pairs in a launch before the
+  // streaming kernel's for the rest
   if (ctx->tune_R == 0 && ctx->tune_W == 0 && ctx->split == 0.f) {
     Plan lanes;
     double lc = 0;
-    if (build_lanes(ctx, p_off, q_off, npairs, D, exact, lanes, lc) && lc < cost) pl = std::move(lanes);
+    std::vector<int32_t> rest;
+    if (build_lanes(ctx, p_off, q_off, npairs, D, exact, lanes, lc, &rest) && lc < cost) {
+      if (rest.empty()) {
+        pl = std::move(lanes);
+      } else {
+        Plan longp;
+        double sc = -1;
+        rc = plan_units(ctx, D, exact, W, split_share(ctx), false,
+                        [&](int R, int, std::vector<Unit> &u) { batch_units_of(P, Q, R, rest, u); }, longp, &sc);
+        if (rc == FFD_OK && lc + sc < cost) {
+          longp.lanes = true;
+          longp.lane_classes = lanes.lane_classes;
+          std::copy(lanes.lane_cols, lanes.lane_cols + ffd::kLaneClasses, longp.lane_cols);
+          std::copy(lanes.lane_first, lanes.lane_first + ffd::kLaneClasses + 1, longp.lane_first);
+          longp.lane_order = std::move(lanes.lane_order);
+          longp.lane_waves = lanes.nwaves;
+          pl = std::move(longp);
+        }
+      }
+    }
   }
   return FFD_OK;
 }
@@ -842,7 +887,7 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-  size_t jobs, wj, off0, off1, order, flags, err, links, total;
+  size_t jobs, wj, off0, off1, lo0, lo1, order, flags, err, links, total;
 };
 
 WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
@@ -850,9 +895,12 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
   size_t o = 0;
   w.jobs = o;  o = al256(o + pl.jobs.size() * sizeof(Job));
   w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
-  const size_t osz = pl.lanes ? sizeof(int32_t) : sizeof(int64_t);  // offsets as the kernel reads them
-  w.off0 = o;  o = al256(o + (size_t)(n0 + 1) * osz);
-  w.off1 = o;  o = al256(o + (size_t)(n1 + 1) * osz);
+  // 64-bit offsets for the streaming kernel, 32-bit ones for the lane kernel
+  const bool stream = !pl.lanes || !pl.jobs.empty();
+  w.off0 = o;  o = al256(o + (stream ? (size_t)(n0 + 1) * sizeof(int64_t) : 0));
+  w.off1 = o;  o = al256(o + (stream ? (size_t)(n1 + 1) * sizeof(int64_t) : 0));
+  w.lo0 = o;   o = al256(o + (pl.lanes ? (size_t)(n0 + 1) * sizeof(int32_t) : 0));
+  w.lo1 = o;   o = al256(o + (pl.lanes ? (size_t)(n1 + 1) * sizeof(int32_t) : 0));
   w.order = o; o = al256(o + pl.lane_order.size() * sizeof(int32_t));
   w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
   w.err = o;   o = al256(o + sizeof(uint64_t));
@@ -933,10 +981,11 @@ void plan_image(const Plan &pl, const WsLayout &wl, const int64_t *off0, int64_t
   if (!pl.wave_jobs.empty()) memcpy(h + wl.wj, pl.wave_jobs.data(), pl.wave_jobs.size() * sizeof(int32_t));
   if (pl.lanes) {
     // 32-bit offsets (the planner checked that they fit)
-    int32_t *o0 = reinterpret_cast<int32_t *>(h + wl.off0), *o1 = reinterpret_cast<int32_t *>(h + wl.off1);
+    int32_t *o0 = reinterpret_cast<int32_t *>(h + wl.lo0), *o1 = reinterpret_cast<int32_t *>(h + wl.lo1);
     for (int64_t k = 0; k <= n0; ++k) o0[k] = (int32_t)off0[k];
     for (int64_t k = 0; k <= n1; ++k) o1[k] = (int32_t)off1[k];
-  } else {
+  }
+  if (!pl.lanes || !pl.jobs.empty()) {
     memcpy(h + wl.off0, off0, (size_t)(n0 + 1) * sizeof(int64_t));
     memcpy(h + wl.off1, off1, (size_t)(n1 + 1) * sizeof(int64_t));
   }
@@ -1011,8 +1060,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     memset(&la, 0, sizeof la);
     la.X[0] = X0;
     la.X[1] = X1;
-    la.off[0] = (const int32_t *)(w + wl.off0);
-    la.off[1] = (const int32_t *)(w + wl.off1);
+    la.off[0] = (const int32_t *)(w + wl.lo0);
+    la.off[1] = (const int32_t *)(w + wl.lo1);
     la.order = (const int32_t *)(w + wl.order);
     la.out = out;
     la.metric = metric;
@@ -1028,10 +1077,13 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     }
     e = ffd::launch_lanes(exact, D, la, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
-    ctx->last = ffd_launch_info{0, pl.nwaves, pl.wpb, 0, exact ? 1 : 0, D, 0, 0, pl.max_steps, 1};
-    ctx->last_err = nullptr;  // the kernel waits on nothing and raises no error bits
-    ctx->last_stream = st;
-    return use_end(ctx, use, ws, st, capturing);
+    if (pl.jobs.empty()) {
+      ctx->last = ffd_launch_info{0, pl.nwaves, pl.wpb, 0, exact ? 1 : 0, D, 0, 0, pl.max_steps, 1};
+      ctx->last_err = nullptr;  // the kernel waits on nothing and raises no error bits
+      ctx->last_stream = st;
+      return use_end(ctx, use, ws, st, capturing);
+    }
+    // the rest of the batch on the streaming kernel, after the lanes on the same stream
   }
   KernelArgs a;
   memset(&a, 0, sizeof a);
@@ -1053,7 +1105,8 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   a.err = (uint64_t *)(w + wl.err);
   a.rings = pl.rings ? 1 : 0;
   a.dim = D;
-  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, 0, 0, pl.max_steps};
+  ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, 0, 0, pl.max_steps,
+                              pl.lanes ? 1 : 0};
   e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st, ctx->measure);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   ctx->last_err = a.err;

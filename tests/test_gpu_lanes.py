@@ -195,3 +195,56 @@ def test_lanes_graph_replay_and_noalloc(ctx, ffdmod):
     got = ctx.batch_noalloc(Pd, p_off, Qd, q_off)
     torch.cuda.synchronize()
     assert torch.equal(got, eager)
+
+
+def test_lanes_with_long_pairs(ctx, ffdmod):
+    """Short and long pairs in one batch: the short ones one per lane, the
+    long ones on the streaming kernel in a launch after them; every result
+    equals the streaming kernel's for the whole batch, a sample the
+    replica's; graph replay gives the eager bits."""
+    rng = np.random.default_rng(710)
+    n = np.concatenate([rng.integers(1, 65, size=150000), rng.integers(300, 1501, size=800)])
+    m = np.concatenate([rng.integers(1, 65, size=150000), rng.integers(300, 1501, size=800)])
+    perm = rng.permutation(len(n))
+    n, m = n[perm], m[perm]
+    p_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    P = np.cumsum(rng.standard_normal((int(p_off[-1]), 2)), axis=0).astype(np.float32)
+    Q = (P[np.minimum(np.arange(int(q_off[-1])), len(P) - 1)] + rng.standard_normal((int(q_off[-1]), 2))
+         ).astype(np.float32)
+    Pd, Qd = dev(P), dev(Q)
+    out = torch.empty(len(n), dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(ctx.workspace_size(ffdmod.FFD_OP_BATCH, p_off, q_off, 2), dtype=torch.uint8, device="cuda:0")
+    say("case: lanes with long pairs, eager call")
+    ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    info = ctx.last_launch()
+    assert info["per_lane"] == 1 and info["rows_per_lane"] > 0, info
+    assert ctx.last_errors() == 0
+    got = out.cpu().numpy()
+    ctx.set_tuning(2, 0)
+    try:
+        say("case: the whole batch on the streaming kernel")
+        ref = ctx.batch(Pd, p_off, Qd, q_off).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 0
+    finally:
+        ctx.set_tuning(0, 0)
+    np.testing.assert_array_equal(got, ref)
+    longs = np.nonzero(np.minimum(n, m) > 64)[0]
+    for k in np.concatenate([longs[:20], np.arange(0, len(n), 5003)]):
+        p, q = P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]]
+        assert got[k] == oracle.dfd_f32_replica(p, q, 0), (k, len(p), len(q))
+    # a capture needs the same call's plan in the workspace: the eager call again
+    ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("case: lanes with long pairs, capture and replays")
+    with torch.cuda.graph(g):
+        ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws)
+    for k in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert ctx.last_errors() == 0
+        np.testing.assert_array_equal(out.cpu().numpy(), got)

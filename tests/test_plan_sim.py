@@ -205,9 +205,9 @@ def test_short_pairs_per_lane(planner):
     """A batch whose pairs all have a curve of at most 64 points (32 for
     3-D and 4-D, half that for the exact path) runs one pair per lane when
     the model prefers it (the Frechet distance and DTW on squared Euclidean,
-    Manhattan or Chebyshev cells, DTW also on Euclidean cells); a batch with
-    one longer pair, a forced launch shape, Levenshtein or a split setting
-    keeps the job-table plan."""
+    Manhattan or Chebyshev cells, DTW also on Euclidean cells); a long pair
+    among them goes to the job-table plan alone; a forced launch shape,
+    Levenshtein or a split setting keeps the job-table plan for all."""
     def offsets(seed, count, lo, hi):
         rng = np.random.default_rng(seed)
         a = np.concatenate([[0], np.cumsum(rng.integers(lo, hi + 1, size=count))]).astype(np.int64)
@@ -228,14 +228,19 @@ def test_short_pairs_per_lane(planner):
     short = np.minimum(np.diff(p_off), np.diff(q_off))
     per = np.bincount((short - 1) // 8, minlength=8)
     assert sm["waves"] == sum(-(-int(c) // 64) for c in per)
-    # one long pair anywhere: the streaming kernel
+    # one long pair as well: it alone goes to the streaming kernel
     p2 = np.concatenate([p_off, [p_off[-1] + 500]])
     q2 = np.concatenate([q_off, [q_off[-1] + 500]])
-    sm = batch_case(planner, p2, q2)
-    assert sm["per_lane"] == 0
-    # 3-D curves hold at most 32 columns per lane, the exact path 32 (2-D)
-    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 3)
-    assert sm["per_lane"] == 0
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p2, q2, 2)
+    assert sm["per_lane"] == 1 and sm["jobs"] > 0
+    plan_sim.check(sm, jobs, wj, (p2, q2), [len(p2) - 2])
+    # 3-D curves hold at most 32 columns per lane, the exact path 32 (2-D):
+    # the pairs with a curve of at most 32 points per lane, the rest on the
+    # job-table plan
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 3)
+    assert sm["per_lane"] == 1 and sm["jobs"] > 0
+    short = np.minimum(np.diff(p_off), np.diff(q_off))
+    plan_sim.check(sm, jobs, wj, (p_off, q_off), np.nonzero(short > 32)[0])
     pb, qb = offsets(71, 200000, 1, 32)
     sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 3)
     assert sm["per_lane"] == 1
@@ -257,3 +262,24 @@ def test_short_pairs_per_lane(planner):
         assert batch_case(planner, pb, qb, dim=2)["per_lane"] == 0
     finally:
         ffd.ffd_set_split(planner, 0.0)
+
+
+def test_short_and_long_pairs(planner):
+    """A batch of many short pairs and some long ones: the short ones run one
+    per lane, the rest on the streaming kernel's job-table plan (which the
+    simulator checks for exactly the long pairs' outputs); a batch of few
+    short pairs keeps one job-table plan for all."""
+    rng = np.random.default_rng(72)
+    n = np.concatenate([rng.integers(1, 65, size=200000), rng.integers(500, 2001, size=3000)])
+    m = np.concatenate([rng.integers(1, 65, size=200000), rng.integers(500, 2001, size=3000)])
+    perm = rng.permutation(len(n))
+    n, m = n[perm], m[perm]
+    p_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 2)
+    assert sm["per_lane"] == 1 and sm["jobs"] > 0
+    long_pairs = np.nonzero(np.minimum(n, m) > 64)[0]
+    assert len(long_pairs) == 3000
+    plan_sim.check(sm, jobs, wj, (p_off, q_off), long_pairs)
+    few = np.concatenate([[0], np.cumsum(np.concatenate([rng.integers(1, 65, size=300), [1500]]))]).astype(np.int64)
+    assert batch_case(planner, few, few)["per_lane"] == 0
