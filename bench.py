@@ -960,7 +960,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(this build measures one GPU's share: batches would shard by pairs across GPUs)", file=sys.stderr)
+              "(it measures one GPU's share; batches shard by pairs across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
