@@ -77,7 +77,7 @@ extern "C" {
 /* Status codes. */
 #define FFD_OK 0
 #define FFD_E_INVALID (-1)     /* bad argument (NULL, empty curve, bad offsets ...) */
-#define FFD_E_UNSUPPORTED (-2) /* valid request outside what this build supports   */
+#define FFD_E_UNSUPPORTED (-2) /* valid request outside what the library supports */
 #define FFD_E_NOMEM (-3)       /* workspace or arena too small                      */
 #define FFD_E_DEVICE (-4)      /* HIP runtime error                                 */
 #define FFD_E_BUSY (-5)        /* serving: no free slot right now                   */

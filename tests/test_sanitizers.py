@@ -51,7 +51,7 @@ def test_planner_under_sanitizers(tmp_path):
                 "ffd_bounded.hip.o", "ffd_lanes.hip.o", "ffd_noalloc.hip.o")]
     kernels += sorted(glob.glob(os.path.join(B.BUILD, "ffd_kernels_op.hip_FFD_OP*.o")))
     if not all(os.path.exists(k) for k in kernels):
-        pytest.skip("kernel objects of the in-tree build are missing: run the build first")
+        pytest.skip("kernel objects are missing from _build: compile the library first")
     csrc = os.path.join(ROOT, "paper_2404_05708_amd", "csrc")
     host_flags = [f for flag in ("-fsanitize=address", "-fsanitize=undefined", "-fno-omit-frame-pointer")
                   for f in ("-Xarch_host", flag)]
