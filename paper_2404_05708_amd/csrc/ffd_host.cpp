@@ -741,14 +741,18 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 // rows at one per 5 clocks (alone on a SIMD).
 // With `rest`, pairs whose curves are both longer than a lane holds are
 // listed there instead of making the batch ineligible (false: no pair fits).
+// With col_count > 0, the pairs are (query, database curve): p_off holds
+// the npairs / col_count queries, q_off the col_count database curves, pair
+// i * col_count + c.
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
-                 Plan &pl, double &cost, std::vector<int32_t> *rest = nullptr) {
+                 Plan &pl, double &cost, std::vector<int32_t> *rest = nullptr, int64_t col_count = 0) {
   // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells,
   // DTW on those or on Euclidean cells (ops 0 ... 7)
   const int op = ctx->measure;
   if (op < 0 || op > 7 || op == 2 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
   // the kernel reads 32-bit offsets (half the upload of every call)
-  if (p_off[npairs] > INT32_MAX || q_off[npairs] > INT32_MAX) return false;
+  const int64_t n0 = col_count > 0 ? npairs / col_count : npairs, n1 = col_count > 0 ? col_count : npairs;
+  if (p_off[n0] > INT32_MAX || q_off[n1] > INT32_MAX) return false;
   const int cmax = ffd::lane_cols_max(exact, D);
   struct Item {
     int64_t rows;
@@ -756,7 +760,8 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   };
   std::vector<Item> cls[ffd::kLaneClasses];
   for (int64_t k = 0; k < npairs; ++k) {
-    const int64_t n = p_off[k + 1] - p_off[k], m = q_off[k + 1] - q_off[k];
+    const int64_t i0 = col_count > 0 ? k / col_count : k, i1 = col_count > 0 ? k % col_count : k;
+    const int64_t n = p_off[i0 + 1] - p_off[i0], m = q_off[i1 + 1] - q_off[i1];
     const bool swap = n < m;  // the shorter curve holds the columns
     const int64_t cols = swap ? n : m, rows = swap ? m : n;
     if (cols > cmax) {
@@ -770,6 +775,7 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   if (rest && rest->size() == (size_t)npairs) return false;
   pl = Plan();
   pl.lanes = true;
+  pl.lane_cross = col_count;
   pl.R = 0;
   pl.wpb = 4;
   double total = 0, longest = 0;
@@ -838,16 +844,27 @@ int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db
                bool exact, Plan &pl) {
   CurveSet Qs{q_off, nq}, DB{db_off, ndb};
   int W = ctx->tune_W > 0 ? ctx->tune_W : 2;
-  return plan_units(ctx, D, exact, W, split_share(ctx), false,
-                    [&](int R, int Wv, std::vector<Unit> &u) {
-                      // about eight units per wave
-                      double total = 0, cols = 0;
-                      for (int64_t k = 0; k < ndb; ++k) cols += (double)ffd::task_len(DB.len(k), false);
-                      for (int64_t i = 0; i < nq; ++i) total += (double)ffd::bands_for(Qs.len(i), R) * cols;
-                      double target = total / ((double)ctx->cus * 4 * Wv * 8.0);
-                      cross_units(Qs, DB, R, std::max(target, 1.0), u);
-                    },
-                    pl);
+  double cost = -1;
+  int rc = plan_units(ctx, D, exact, W, split_share(ctx), false,
+                      [&](int R, int Wv, std::vector<Unit> &u) {
+                        // about eight units per wave
+                        double total = 0, cols = 0;
+                        for (int64_t k = 0; k < ndb; ++k) cols += (double)ffd::task_len(DB.len(k), false);
+                        for (int64_t i = 0; i < nq; ++i) total += (double)ffd::bands_for(Qs.len(i), R) * cols;
+                        double target = total / ((double)ctx->cus * 4 * Wv * 8.0);
+                        cross_units(Qs, DB, R, std::max(target, 1.0), u);
+                      },
+                      pl, &cost);
+  if (rc) return rc;
+  // every (query, database curve) pair short: one pair per lane, when no
+  // launch shape is forced and the model prefers it
+  if (ctx->tune_R == 0 && ctx->tune_W == 0 && ctx->split == 0.f && nq * ndb <= INT32_MAX) {
+    Plan lanes;
+    double lc = 0;
+    if (build_lanes(ctx, q_off, db_off, nq * ndb, D, exact, lanes, lc, nullptr, ndb) && lc < cost)
+      pl = std::move(lanes);
+  }
+  return FFD_OK;
 }
 
 // One pair; a long pair is split into bands over waves when that pays.
@@ -1064,6 +1081,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     la.off[1] = (const int32_t *)(w + wl.lo1);
     la.order = (const int32_t *)(w + wl.order);
     la.out = out;
+    la.col_count = (int32_t)pl.lane_cross;
     la.metric = metric;
     la.cell = ctx->measure >> 1;  // the planner took only ops 0 ... 7 but 2
     la.dtw = ctx->measure & 1;

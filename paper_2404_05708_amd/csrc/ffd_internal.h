@@ -135,6 +135,7 @@ struct Plan {
   int64_t lane_first[ffd::kLaneClasses + 1] = {};
   std::vector<int32_t> lane_order;  // pair index; the top bit: the second set holds the rows
   int32_t lane_waves = 0;           // with jobs as well: wavefronts of the lane launch
+  int64_t lane_cross = 0;           // > 0: (query, database curve) pairs, this many database curves
 };
 
 // A request as the planner sees it: header words (operation, dimension,

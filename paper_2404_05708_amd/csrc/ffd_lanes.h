@@ -13,6 +13,8 @@ struct LaneArgs {
   const int32_t *off[2];  // their curve offsets in points (device; each set below 2^31 points)
   const int32_t *order;   // lane k -> pair index; the top bit set: the second set's curve holds the rows
   void *out;              // float32 or int64 results, indexed by pair
+  int32_t col_count;      // 0: pair p is curve p of both sets; > 0: curve p / col_count of the first set
+                          // against curve p % col_count of the second (query set x database)
   int32_t metric;         // squared cells: 0 Euclidean (the root taken once per pair), 1 squared Euclidean
   int32_t cell;           // ground distance: 0 squared Euclidean, 1 Euclidean (DTW), 2 Manhattan, 3 Chebyshev
   int32_t dtw;            // 1: dynamic time warping (Appendix B), 0: the Frechet distance

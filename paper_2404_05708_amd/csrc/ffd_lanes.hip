@@ -81,12 +81,16 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   const int32_t raw = a.order[k];
   const bool swap = raw < 0;
   const int32_t idx = raw & 0x7fffffff;
+  // the pair's curve in each set: the same index, or (query, database curve)
+  const int32_t i0 = a.col_count > 0 ? idx / a.col_count : idx;
+  const int32_t i1 = a.col_count > 0 ? idx - i0 * a.col_count : idx;
   const C *Xr = static_cast<const C *>(swap ? a.X[1] : a.X[0]);
   const C *Xc = static_cast<const C *>(swap ? a.X[0] : a.X[1]);
   const int32_t *offr = swap ? a.off[1] : a.off[0];
   const int32_t *offc = swap ? a.off[0] : a.off[1];
-  const int64_t ro = offr[idx], n = offr[idx + 1] - ro;
-  const int64_t co = offc[idx], m = offc[idx + 1] - co;
+  const int32_t ir = swap ? i1 : i0, ic = swap ? i0 : i1;
+  const int64_t ro = offr[ir], n = offr[ir + 1] - ro;
+  const int64_t co = offc[ic], m = offc[ic + 1] - co;
 
   V q[M][D];
 #pragma unroll

@@ -248,3 +248,45 @@ def test_lanes_with_long_pairs(ctx, ffdmod):
         torch.cuda.synchronize()
         assert ctx.last_errors() == 0
         np.testing.assert_array_equal(out.cpu().numpy(), got)
+
+
+def test_lanes_cross(ctx, ffdmod):
+    """Queries x database of short curves, one (query, curve) pair per lane:
+    the streaming kernel's bits for every pair, Frechet and DTW, float32 and
+    int32 (exact against the oracle)."""
+    rng = np.random.default_rng(720)
+    qs = [np.cumsum(rng.standard_normal((int(L), 2)), axis=0).astype(np.float32) for L in rng.integers(1, 49, 400)]
+    db = [np.cumsum(rng.standard_normal((int(L), 2)), axis=0).astype(np.float32) for L in rng.integers(1, 49, 500)]
+    qo = np.concatenate([[0], np.cumsum([len(q) for q in qs])]).astype(np.int64)
+    do = np.concatenate([[0], np.cumsum([len(c) for c in db])]).astype(np.int64)
+    Qd, Dd = dev(np.concatenate(qs)), dev(np.concatenate(db))
+    for dtw in (False, True):
+        say(f"case: lanes cross dtw={dtw}")
+        call = ctx.dtw_cross if dtw else ctx.cross
+        got = call(Qd, qo, Dd, do, metric=ffdmod.FFD_SQEUCLIDEAN).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 1
+        ctx.set_tuning(1, 0)
+        try:
+            ref = call(Qd, qo, Dd, do, metric=ffdmod.FFD_SQEUCLIDEAN).cpu().numpy()
+            assert ctx.last_launch()["per_lane"] == 0
+        finally:
+            ctx.set_tuning(0, 0)
+        np.testing.assert_array_equal(got, ref)
+        f = oracle.dtw_f32_replica if dtw else oracle.dfd_f32_replica
+        for i in (0, 17, 399):
+            for c in (0, 250, 499):
+                assert got.reshape(400, 500)[i, c] == f(qs[i], db[c], ffdmod.FFD_SQEUCLIDEAN), (i, c)
+    Qi, qoi, Di, doi = workloads_cross_int(rng)
+    say("case: lanes cross int32")
+    got = ctx.cross_i32(dev(Qi), qoi, dev(Di), doi).cpu().numpy()
+    assert ctx.last_launch()["per_lane"] == 1
+    np.testing.assert_array_equal(got, oracle.dfd_cross_i32(Qi, qoi, Di, doi, nthreads=8))
+
+
+def workloads_cross_int(rng):
+    lq, ld = rng.integers(1, 33, 300), rng.integers(1, 33, 600)
+    qo = np.concatenate([[0], np.cumsum(lq)]).astype(np.int64)
+    do = np.concatenate([[0], np.cumsum(ld)]).astype(np.int64)
+    Qi = rng.integers(-(1 << 15), 1 << 15, size=(int(qo[-1]), 2), dtype=np.int32)
+    Di = rng.integers(-(1 << 15), 1 << 15, size=(int(do[-1]), 2), dtype=np.int32)
+    return Qi, qo, Di, do

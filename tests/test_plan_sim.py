@@ -283,3 +283,21 @@ def test_short_and_long_pairs(planner):
     plan_sim.check(sm, jobs, wj, (p_off, q_off), long_pairs)
     few = np.concatenate([[0], np.cumsum(np.concatenate([rng.integers(1, 65, size=300), [1500]]))]).astype(np.int64)
     assert batch_case(planner, few, few)["per_lane"] == 0
+
+
+def test_short_cross_per_lane(planner):
+    """Queries x database with every curve short: one (query, curve) pair
+    per lane when the model prefers it; one long query keeps the job-table
+    plan (a cross request is not split)."""
+    rng = np.random.default_rng(73)
+    qo = np.concatenate([[0], np.cumsum(rng.integers(2, 49, size=500))]).astype(np.int64)
+    do = np.concatenate([[0], np.cumsum(rng.integers(2, 49, size=400))]).astype(np.int64)
+    sm, jobs, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, qo, do, 2)
+    assert sm["per_lane"] == 1 and sm["jobs"] == 0
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, qo, do, 2, dtw=True)
+    assert sm["per_lane"] == 1
+    q2 = np.concatenate([qo, [qo[-1] + 3000]])
+    d2 = np.concatenate([do, [do[-1] + 3000]])
+    sm, jobs, wj = ffd.ffd_plan_describe(planner, ffd.FFD_OP_CROSS, q2, d2, 2)
+    assert sm["per_lane"] == 0
+    plan_sim.check(sm, jobs, wj, (q2, d2), range(501 * 401))
