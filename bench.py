@@ -279,7 +279,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     """Many short pairs: the one-pair-per-lane kernel, with the streaming
     kernel's job-table plan timed on the same pairs beside it."""
     import workloads
-    P, p_off, Q, q_off = workloads.short_pairs()
+    P, p_off, Q, q_off = workloads.short_pairs(long_pairs=800 if args.mixed else 0)
     npairs = len(p_off) - 1
     cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
     dim = P.shape[1]
@@ -341,10 +341,14 @@ def run_short(args, torch, ffd, ctx, dev, stream):
                          f"on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))}
     rl = roofline(info, cells, kms, dim, False, family="lane_kernel")
-    rl["kernel"] = f"ffd::lane_kernel<2, float, 0, {'true' if dtw else 'false'}> (one launch, column classes 8 .. 64)"
+    rl["kernel"] = f"ffd::lane_kernel<2, float, 0, {'true' if dtw else 'false'}> (one launch, column classes 8 .. 64)" + (
+        ", then the streaming kernel for the long pairs (kernel_ms covers both)" if args.mixed else "")
     return {
         "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
-        "config": {"workload": f"short pairs: {npairs} pairs, n and m uniform in [8, 64], 2-D float32 random walks, "
+        "config": {"workload": ("short and long pairs: 262144 pairs with n and m uniform in [8, 64] and 800 with "
+                                "n and m uniform in [300, 1500], shuffled" if args.mixed else
+                                f"short pairs: {npairs} pairs, n and m uniform in [8, 64]")
+                               + ", 2-D float32 random walks, "
                                + ("DTW of squared Euclidean cells" if dtw else "Euclidean") + " (seed 11)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": ctx.last_errors(),
@@ -949,6 +953,7 @@ def main():
     ap.add_argument("--metric", choices=["euclidean", "manhattan", "chebyshev"], default="euclidean",
                     help="ground distance of the batched workload")
     ap.add_argument("--dtw", action="store_true", help="short workload: DTW of squared cells")
+    ap.add_argument("--mixed", action="store_true", help="short workload: 800 long pairs among the short ones")
     ap.add_argument("--dim", type=int, default=2,
                     help="coordinates per point of the batched workload (its headline form is 2-D)")
     ap.add_argument("--rows-per-lane", type=int, default=0)

@@ -141,14 +141,21 @@ def poisson_arrivals(seed=7, count=1000, rate=1000.0):
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
-def short_pairs(seed=11, npairs=262144, lo=8, hi=64, dim=2):
+def short_pairs(seed=11, npairs=262144, lo=8, hi=64, dim=2, long_pairs=0, long_lo=300, long_hi=1500):
     """Many short pairs.  Draw order: n[npairs], m[npairs] uniform in [lo, hi];
-    then the N(0,1) steps of every p point (sum n x dim) and of every q point
-    (sum m x dim); each curve is the FP64 cumulative sum of its own steps,
-    cast once.  Returns P, p_off, Q, q_off."""
+    with long_pairs > 0, then n and m of that many more pairs uniform in
+    [long_lo, long_hi] and a permutation of all pairs; then the N(0,1) steps
+    of every p point (sum n x dim) and of every q point (sum m x dim); each
+    curve is the FP64 cumulative sum of its own steps, cast once.  Returns
+    P, p_off, Q, q_off."""
     rng = np.random.default_rng(seed)
     n = rng.integers(lo, hi + 1, size=npairs)
     m = rng.integers(lo, hi + 1, size=npairs)
+    if long_pairs > 0:
+        n = np.concatenate([n, rng.integers(long_lo, long_hi + 1, size=long_pairs)])
+        m = np.concatenate([m, rng.integers(long_lo, long_hi + 1, size=long_pairs)])
+        perm = rng.permutation(len(n))
+        n, m = n[perm], m[perm]
 
     def curves(lens):
         off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
