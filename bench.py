@@ -954,6 +954,8 @@ def main():
                     help="ground distance of the batched workload")
     ap.add_argument("--dtw", action="store_true", help="short workload: DTW of squared cells")
     ap.add_argument("--mixed", action="store_true", help="short workload: 800 long pairs among the short ones")
+    ap.add_argument("--no-short", action="store_true",
+                    help="batched workload: skip the short-pairs block (one pair per lane) of the line")
     ap.add_argument("--dim", type=int, default=2,
                     help="coordinates per point of the batched workload (its headline form is 2-D)")
     ap.add_argument("--rows-per-lane", type=int, default=0)
@@ -993,6 +995,16 @@ def main():
                             "mean_ms": run["mean_ms"], "cells_per_s": run["cells_per_s"],
                             "requests": run["completed"], "warmup_requests": info["warmup_requests"],
                             "failed": run["failed"]}
+        if not args.no_short:
+            # many short pairs (one pair per lane) beside the streaming kernel on the same pairs
+            import copy
+            sa = copy.copy(args)
+            sa.steps, sa.warmup, sa.no_cpu, sa.dtw, sa.mixed = 20, 5, True, False, False
+            sr = run_short(sa, torch, ffd, ctx, dev, stream)
+            r["short_pairs"] = {"workload": sr["config"]["workload"], "cells_per_s": sr["value"],
+                                "ms_per_step": sr["ms_per_step"], "kernel_ms": sr["roofline"]["kernel_ms"],
+                                "frac": sr["roofline"]["frac"], "parity": sr["parity"],
+                                "streaming_kernel_cells_per_s": sr["streaming_kernel"]["cells_per_s"]}
     elif args.workload == "cross":
         r = run_cross(args, torch, ffd, ctx, dev, stream)
     elif args.workload == "serving":
@@ -1017,8 +1029,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "autotune", "serving", "search", "roofline", "plain", "streaming_kernel",
-              "cpu_baseline"):
+    for k in ("config", "parity", "autotune", "serving", "short_pairs", "search", "roofline", "plain",
+              "streaming_kernel", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     if line.get("cpu_baseline"):
