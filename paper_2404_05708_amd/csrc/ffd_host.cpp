@@ -747,9 +747,9 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                  Plan &pl, double &cost, std::vector<int32_t> *rest = nullptr, int64_t col_count = 0) {
   // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells,
-  // DTW on those or on Euclidean cells (ops 0 ... 7)
+  // DTW on those or on Euclidean cells (ops 0 ... 7), Levenshtein (op 8)
   const int op = ctx->measure;
-  if (op < 0 || op > 7 || op == 2 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
+  if (op < 0 || op > 8 || op == 2 || D > 4 || npairs < 1 || npairs > INT32_MAX) return false;
   // the kernel reads 32-bit offsets (half the upload of every call)
   const int64_t n0 = col_count > 0 ? npairs / col_count : npairs, n1 = col_count > 0 ? col_count : npairs;
   if (p_off[n0] > INT32_MAX || q_off[n1] > INT32_MAX) return false;
@@ -785,8 +785,9 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
     const int i = pl.lane_classes++;
     pl.lane_cols[i] = (c + 1) * ffd::kLaneColStep;
     pl.lane_first[i] = (int64_t)pl.lane_order.size();
-    const double per_row =
-        (double)((c + 1) * ffd::kLaneColStep) * (2 * D + (exact ? 3 : 2) + ((op >> 1) == 1 ? 4 : 0)) + 8.0;
+    const double per_cell =
+        op == 8 ? 2 * D + 5 : 2 * D + (exact ? 3 : 2) + ((op >> 1) == 1 ? 4 : 0);  // Levenshtein: 2 D + 5
+    const double per_row = (double)((c + 1) * ffd::kLaneColStep) * per_cell + 8.0;
     for (size_t w = 0; w < cls[c].size(); w += ffd::kWave) {
       const double v = (double)cls[c][w].rows * per_row;  // the wavefront's longest lane
       total += v;
@@ -1083,7 +1084,7 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
     la.out = out;
     la.col_count = (int32_t)pl.lane_cross;
     la.metric = metric;
-    la.cell = ctx->measure >> 1;  // the planner took only ops 0 ... 7 but 2
+    la.cell = ctx->measure >> 1;  // the planner took only ops 0 ... 8 but 2 (op 8: cell 4, Levenshtein)
     la.dtw = ctx->measure & 1;
     la.classes = pl.lane_classes;
     for (int c = 0; c < pl.lane_classes; ++c) {

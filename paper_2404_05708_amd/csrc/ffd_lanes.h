@@ -16,7 +16,8 @@ struct LaneArgs {
   int32_t col_count;      // 0: pair p is curve p of both sets; > 0: curve p / col_count of the first set
                           // against curve p % col_count of the second (query set x database)
   int32_t metric;         // squared cells: 0 Euclidean (the root taken once per pair), 1 squared Euclidean
-  int32_t cell;           // ground distance: 0 squared Euclidean, 1 Euclidean (DTW), 2 Manhattan, 3 Chebyshev
+  int32_t cell;           // ground distance: 0 squared Euclidean, 1 Euclidean (DTW), 2 Manhattan, 3 Chebyshev,
+                          // 4 Levenshtein (int32 symbols, float32 values, int64 results)
   int32_t dtw;            // 1: dynamic time warping (Appendix B), 0: the Frechet distance
   int32_t classes;        // classes of column count, 1 ... kLaneClasses, most columns first
   int32_t cols[8];        // columns a lane of class c holds (a multiple of 8, at most 64)

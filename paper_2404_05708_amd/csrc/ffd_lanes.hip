@@ -32,7 +32,12 @@
 // sum, the corner 0) runs on the same sweep; sums are not selections, so
 // there the padding is not exact: the result is read at the column curve's
 // own last column (columns to its right never feed it), and the second row
-// of a pair is dropped when the row curve has no row left.
+// of a pair is dropped when the row curve has no row left.  The Levenshtein
+// distance (Appendix B, Algorithm B.2; CELL 4) likewise: int32 symbol
+// vectors compared as bit patterns, integer table values in float32 (exact
+// below 2^24), M_ij = min(min(M_{i-1,j}, M_{i,j-1}) + 1, M_{i-1,j-1} + d_ij)
+// with the ramps M_{-1,j} = j + 1, M_{i,-1} = i + 1 and a 0 corner, as the
+// streaming kernel evaluates it.
 //
 // One launch covers every class of column count (multiples of 8 up to 64
 // columns; the registers are those of the widest class), its workgroups of
@@ -48,11 +53,17 @@ namespace ffd {
 namespace {
 
 // The ground distance of a cell (CELL 0 squared Euclidean, 2 Manhattan, 3
-// Chebyshev), in the streaming kernels' order of operations.
+// Chebyshev, 4 the Levenshtein symbol mismatch), in the streaming kernels'
+// order of operations.
 template <int D, typename V, int CELL>
 __device__ __forceinline__ V cell_value(const V (&p)[D], const V (&q)[D]) {
   using N = Num<V>;
-  if constexpr (CELL == 1) {
+  if constexpr (CELL == 4) {
+    bool ne = false;
+#pragma unroll
+    for (int c = 0; c < D; ++c) ne = ne || __builtin_bit_cast(uint32_t, p[c]) != __builtin_bit_cast(uint32_t, q[c]);
+    return ne ? V(1) : V(0);
+  } else if constexpr (CELL == 1) {
     return N::sqrt_cell(cell_value<D, V, 0>(p, q));  // DTW of Euclidean cells: a root per cell
   } else if constexpr (CELL >= 2) {
     V s = N::abs(p[0] - q[0]);
@@ -77,7 +88,9 @@ __device__ __forceinline__ V cell_value(const V (&p)[D], const V (&q)[D]) {
 template <int M, int D, typename V, int CELL, bool DTW>
 __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   using N = Num<V>;
-  using C = typename N::Coord;
+  using C = typename N::Coord;  // float for Levenshtein: the int32 symbols travel as bit patterns
+  constexpr bool LEV = CELL == 4;
+  constexpr bool SUM = DTW || LEV;  // not a selection: no exact padding
   const int32_t raw = a.order[k];
   const bool swap = raw < 0;
   const int32_t idx = raw & 0x7fffffff;
@@ -99,9 +112,9 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
 #pragma unroll
     for (int c = 0; c < D; ++c) q[j][c] = N::cvt(Xc[(co + jj) * D + c]);
   }
-  V row[M];
+  V row[M];  // M_{-1,j}: +inf (Frechet, DTW), j + 1 (Levenshtein)
 #pragma unroll
-  for (int j = 0; j < M; ++j) row[j] = N::inf();
+  for (int j = 0; j < M; ++j) row[j] = LEV ? V(j + 1) : N::inf();
 
   // the points of the rows, loaded kAhead row pairs before they are swept
   // (a lane's loads are gathers from its own curve)
@@ -130,18 +143,21 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
         }
         load_pair(i + 2 * kAhead, nxt[r]);
         // M_{i-1,-1}: the corner above the first row (-inf for the Frechet
-        // distance, 0 for DTW), +inf below it
-        V diag_a = i == 0 ? (DTW ? V(0) : -N::inf()) : N::inf();
-        V left_a = N::inf();                       // M_{i,-1}
-        V diag_b = N::inf();                       // M_{i,-1}
-        V left_b = N::inf();                       // M_{i+1,-1}
-        const bool two = !DTW || i + 1 < n;        // DTW: no repeated row
+        // distance, 0 for DTW), +inf below it; Levenshtein: the ramp i
+        V diag_a = LEV ? V(i) : (i == 0 ? (DTW ? V(0) : -N::inf()) : N::inf());
+        V left_a = LEV ? V(i + 1) : N::inf();      // M_{i,-1}
+        V diag_b = LEV ? V(i + 1) : N::inf();      // M_{i,-1}
+        V left_b = LEV ? V(i + 2) : N::inf();      // M_{i+1,-1}
+        const bool two = !SUM || i + 1 < n;        // sums: no repeated row
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           const V da = cell_value<D, V, CELL>(pa, q[j]);
           const V db = cell_value<D, V, CELL>(pb, q[j]);
           V va, vb;
-          if constexpr (DTW) {
+          if constexpr (LEV) {
+            va = N::mn(N::mn(row[j], left_a) + V(1), diag_a + da);
+            vb = N::mn(N::mn(va, left_b) + V(1), diag_b + db);
+          } else if constexpr (DTW) {
             va = N::mn(N::mn(row[j], diag_a), left_a) + da;
             vb = N::mn(N::mn(va, diag_b), left_b) + db;
           } else {
@@ -152,17 +168,18 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
           left_a = va;
           diag_b = va;
           left_b = vb;
-          row[j] = DTW ? (two ? vb : va) : vb;
+          row[j] = SUM ? (two ? vb : va) : vb;
         }
       }
     }
   }
-  if constexpr (DTW) {
+  if constexpr (SUM) {
     // the value at the column curve's own last column
     V res = row[0];
 #pragma unroll
     for (int j = 1; j < M; ++j) res = j == m - 1 ? row[j] : res;
-    N::store_value(a.out, idx, res);
+    if constexpr (LEV) static_cast<int64_t *>(a.out)[idx] = (int64_t)res;
+    else N::store_value(a.out, idx, res);
   } else if constexpr (CELL == 0) {
     N::store(a.out, idx, row[M - 1], a.metric);
   } else {
@@ -226,6 +243,9 @@ hipError_t launch_v(int D, const LaneArgs &a, hipStream_t st) {
     case 0: return launch_c<V, 0, false>(D, a, st);
     case 2: return launch_c<V, 2, false>(D, a, st);
     case 3: return launch_c<V, 3, false>(D, a, st);
+    case 4:
+      if constexpr (sizeof(V) == 4) return launch_c<V, 4, false>(D, a, st);  // Levenshtein: float32 values
+      return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }

@@ -159,6 +159,39 @@ def test_lanes_dtw(ctx, ffdmod, dim, hi):
     np.testing.assert_array_equal(got, oracle.dtw_batch_i32(Pi, pio, Qi, qio, nthreads=8))
 
 
+@pytest.mark.parametrize("dim,alphabet", [(1, 4), (1, 26), (2, 3)])
+def test_lanes_levenshtein(ctx, dim, alphabet):
+    """Levenshtein on short symbol sequences, one pair per lane (and query
+    set x database): the streaming kernel's values for every pair, and the
+    int64 oracle's."""
+    rng = np.random.default_rng(590 + alphabet)
+    count = 150000
+    n = np.concatenate([rng.integers(1, 65, size=count), [1, 64, 64, 1, 63]])
+    m = np.concatenate([rng.integers(1, 65, size=count), [1, 64, 1, 64, 64]])
+    p_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    P = rng.integers(0, alphabet, size=(int(p_off[-1]), dim)).astype(np.int32)
+    Q = rng.integers(0, alphabet, size=(int(q_off[-1]), dim)).astype(np.int32)
+    Pd, Qd = dev(P), dev(Q)
+    say(f"case: lanes levenshtein dim={dim} alphabet={alphabet}")
+    got = ctx.levenshtein_batch(Pd, p_off, Qd, q_off).cpu().numpy()
+    assert ctx.last_launch()["per_lane"] == 1
+    ctx.set_tuning(1, 0)
+    try:
+        ref = ctx.levenshtein_batch(Pd, p_off, Qd, q_off).cpu().numpy()
+        assert ctx.last_launch()["per_lane"] == 0
+    finally:
+        ctx.set_tuning(0, 0)
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_array_equal(got, oracle.lev_batch(P, p_off, Q, q_off, nthreads=8))
+    say(f"case: lanes levenshtein cross dim={dim}")
+    Qs, qo = P[:p_off[300]], p_off[:301]
+    DB, do = Q[:q_off[500]], q_off[:501]
+    cr = ctx.levenshtein_cross(dev(Qs), qo, dev(DB), do).cpu().numpy()
+    assert ctx.last_launch()["per_lane"] == 1
+    np.testing.assert_array_equal(cr, oracle.lev_cross(Qs, qo, DB, do, nthreads=8))
+
+
 @pytest.mark.parametrize("dim,hi", [(2, 32), (4, 16)])
 def test_lanes_int_exact(ctx, dim, hi):
     P, p_off, Q, q_off = short_pairs(600 + dim, 150000, 1, hi, dim, kind="int")

@@ -205,9 +205,10 @@ def test_short_pairs_per_lane(planner):
     """A batch whose pairs all have a curve of at most 64 points (32 for
     3-D and 4-D, half that for the exact path) runs one pair per lane when
     the model prefers it (the Frechet distance and DTW on squared Euclidean,
-    Manhattan or Chebyshev cells, DTW also on Euclidean cells); a long pair
-    among them goes to the job-table plan alone; a forced launch shape,
-    Levenshtein or a split setting keeps the job-table plan for all."""
+    Manhattan or Chebyshev cells, DTW also on Euclidean cells, Levenshtein);
+    a long pair among them goes to the job-table plan alone; a forced launch
+    shape, the great-circle distance or a split setting keeps the job-table
+    plan for all."""
     def offsets(seed, count, lo, hi):
         rng = np.random.default_rng(seed)
         a = np.concatenate([[0], np.cumsum(rng.integers(lo, hi + 1, size=count))]).astype(np.int64)
@@ -251,7 +252,9 @@ def test_short_pairs_per_lane(planner):
         assert sm["per_lane"] == 1
     sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 2, dtw=True)
     assert sm["per_lane"] == 1  # DTW too
-    assert batch_case(planner, pb, qb, dim=2, levenshtein=True, exact=True)["per_lane"] == 0
+    sm, _, _ = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, pb, qb, 1, levenshtein=True, exact=True)
+    assert sm["per_lane"] == 1  # Levenshtein too
+    assert batch_case(planner, pb, qb, dim=2, metric=ffd.FFD_HAVERSINE)["per_lane"] == 0
     ffd.ffd_set_tuning(planner, 1, 0)
     try:
         assert batch_case(planner, pb, qb, dim=2)["per_lane"] == 0
