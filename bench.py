@@ -279,7 +279,11 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     """Many short pairs: the one-pair-per-lane kernel, with the streaming
     kernel's job-table plan timed on the same pairs beside it."""
     import workloads
-    P, p_off, Q, q_off = workloads.short_pairs(long_pairs=800 if args.mixed else 0)
+    lev = args.levenshtein  # the Levenshtein distance of short symbol sequences instead
+    if lev:
+        P, p_off, Q, q_off = workloads.short_symbol_pairs()
+    else:
+        P, p_off, Q, q_off = workloads.short_pairs(long_pairs=800 if args.mixed else 0)
     npairs = len(p_off) - 1
     cells = int(np.sum(np.diff(p_off) * np.diff(q_off)))
     dim = P.shape[1]
@@ -287,11 +291,13 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     Qd = torch.from_numpy(Q).to(dev)
     nbytes = ctx.workspace_size(ffd.FFD_OP_BATCH, p_off, q_off, dim)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    out = torch.empty(npairs, dtype=torch.float32, device=dev)
+    out = torch.empty(npairs, dtype=torch.int64 if lev else torch.float32, device=dev)
     dtw = args.dtw  # DTW of squared Euclidean cells instead of the Frechet distance
 
     def step():
-        if dtw:
+        if lev:
+            ctx.levenshtein_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+        elif dtw:
             ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_SQEUCLIDEAN, out=out, workspace=ws, stream=stream)
         else:
             ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
@@ -304,13 +310,18 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     res = out.cpu().numpy()
     import oracle
     idx = np.sort(np.random.default_rng(79).choice(npairs, size=256, replace=False))
-    if dtw:
+    if lev:
+        want = oracle.lev_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
+                                cpu_cores())
+    elif dtw:
         want = np.array([oracle.dtw(P[p_off[k]:p_off[k + 1]], Q[q_off[k]:q_off[k + 1]], oracle.SQEUCLIDEAN)
                          for k in idx])
     else:
         want = oracle.dfd_pairs(P, p_off[:-1][idx], np.diff(p_off)[idx], Q, q_off[:-1][idx], np.diff(q_off)[idx],
                                 oracle.EUCLIDEAN, cpu_cores())
-    if dtw:  # float32 sums: within (n + m + 2 D + 2) roundings
+    if lev:  # exact
+        parity_ok = bool(np.array_equal(res[idx], want))
+    elif dtw:  # float32 sums: within (n + m + 2 D + 2) roundings
         tol = (np.diff(p_off)[idx] + np.diff(q_off)[idx] + 2 * dim + 2) * 2.0 ** -24 * 1.01
         parity_ok = bool(np.all(np.abs(res[idx] - want) <= tol * want))
     else:
@@ -327,7 +338,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     finally:
         ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
     cpu = None
-    if not args.no_cpu and not dtw:
+    if not args.no_cpu and not dtw and not lev:
         cores = cpu_cores()
         rng = np.random.default_rng(80)
         sample = np.sort(rng.choice(npairs, size=min(npairs, 65536), replace=False))
@@ -340,22 +351,27 @@ def run_short(args, torch, ffd, ctx, dev, stream):
                "sample": f"{len(sample)} of the {npairs} pairs (seed 80), {s_cells} cells, FP64 rolling-row oracle "
                          f"on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": bool(np.all(np.abs(res[sample] - vals) <= TOL * vals))}
-    rl = roofline(info, cells, kms, dim, False, family="lane_kernel")
-    rl["kernel"] = f"ffd::lane_kernel<2, float, 0, {'true' if dtw else 'false'}> (one launch, column classes 8 .. 64)" + (
+    rl = roofline(info, cells, kms, dim, False, family="lane_kernel", cell="levenshtein" if lev else "euclidean")
+    rl["kernel"] = (f"ffd::lane_kernel<1, float, 4, false>" if lev else
+                    f"ffd::lane_kernel<2, float, 0, {'true' if dtw else 'false'}>") + " (one launch, column classes 8 .. 64)" + (
         ", then the streaming kernel for the long pairs (kernel_ms covers both)" if args.mixed else "")
     return {
+        "metric": "levenshtein_cells_per_second" if lev else METRIC,
         "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
-        "config": {"workload": ("short and long pairs: 262144 pairs with n and m uniform in [8, 64] and 800 with "
-                                "n and m uniform in [300, 1500], shuffled" if args.mixed else
-                                f"short pairs: {npairs} pairs, n and m uniform in [8, 64]")
-                               + ", 2-D float32 random walks, "
-                               + ("DTW of squared Euclidean cells" if dtw else "Euclidean") + " (seed 11)",
+        "config": {"workload": (f"short symbol sequences: {npairs} pairs, n and m uniform in [8, 64], int32 symbols "
+                                "uniform in [0, 4), Levenshtein (seed 12)") if lev else
+                               (("short and long pairs: 262144 pairs with n and m uniform in [8, 64] and 800 with "
+                                 "n and m uniform in [300, 1500], shuffled" if args.mixed else
+                                 f"short pairs: {npairs} pairs, n and m uniform in [8, 64]")
+                                + ", 2-D float32 random walks, "
+                                + ("DTW of squared Euclidean cells" if dtw else "Euclidean") + " (seed 11)"),
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": ctx.last_errors(),
                    "streaming_kernel_bit_identical": same},
         "roofline": rl,
         "streaming_kernel": {"cells_per_s": cells / ssec, "ms_per_step": ssec * 1e3, "kernel_ms": skms,
-                             "frac": cells * imin(dim) / (skms / 1e3) / PEAK_VALU, "launch": sinfo},
+                             "frac": cells * imin(dim, cell="levenshtein" if lev else "euclidean") / (skms / 1e3) / PEAK_VALU,
+                             "launch": sinfo},
         "cpu_baseline": cpu,
     }
 
@@ -954,6 +970,8 @@ def main():
                     help="ground distance of the batched workload")
     ap.add_argument("--dtw", action="store_true", help="short workload: DTW of squared cells")
     ap.add_argument("--mixed", action="store_true", help="short workload: 800 long pairs among the short ones")
+    ap.add_argument("--levenshtein", action="store_true",
+                    help="short workload: the Levenshtein distance of short symbol sequences")
     ap.add_argument("--no-short", action="store_true",
                     help="batched workload: skip the short-pairs block (one pair per lane) of the line")
     ap.add_argument("--dim", type=int, default=2,
@@ -999,7 +1017,7 @@ def main():
             # many short pairs (one pair per lane) beside the streaming kernel on the same pairs
             import copy
             sa = copy.copy(args)
-            sa.steps, sa.warmup, sa.no_cpu, sa.dtw, sa.mixed = 20, 5, True, False, False
+            sa.steps, sa.warmup, sa.no_cpu, sa.dtw, sa.mixed, sa.levenshtein = 20, 5, True, False, False, False
             sr = run_short(sa, torch, ffd, ctx, dev, stream)
             r["short_pairs"] = {"workload": sr["config"]["workload"], "cells_per_s": sr["value"],
                                 "ms_per_step": sr["ms_per_step"], "kernel_ms": sr["roofline"]["kernel_ms"],

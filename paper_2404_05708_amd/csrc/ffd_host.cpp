@@ -726,6 +726,31 @@ PipeLayout pipe_layout(const Plan &pl, bool exact) {
   return L;
 }
 
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t jobs, wj, off0, off1, lo0, lo1, order, flags, err, links, total;
+};
+
+WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
+  WsLayout w;
+  size_t o = 0;
+  w.jobs = o;  o = al256(o + pl.jobs.size() * sizeof(Job));
+  w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
+  // 64-bit offsets for the streaming kernel, 32-bit ones for the lane kernel
+  const bool stream = !pl.lanes || !pl.jobs.empty();
+  w.off0 = o;  o = al256(o + (stream ? (size_t)(n0 + 1) * sizeof(int64_t) : 0));
+  w.off1 = o;  o = al256(o + (stream ? (size_t)(n1 + 1) * sizeof(int64_t) : 0));
+  w.lo0 = o;   o = al256(o + (pl.lanes ? (size_t)(n0 + 1) * sizeof(int32_t) : 0));
+  w.lo1 = o;   o = al256(o + (pl.lanes ? (size_t)(n1 + 1) * sizeof(int32_t) : 0));
+  w.order = o; o = al256(o + pl.lane_order.size() * sizeof(int32_t));
+  w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
+  w.err = o;   o = al256(o + sizeof(uint64_t));
+  w.links = o; o = al256(o + (size_t)pl.link_elems * (exact ? 8 : 4));
+  w.total = o;
+  return w;
+}
+
 // ------------------------------------------------------ short pairs per lane
 //
 // A batch whose pairs all have a curve of at most lane_cols_max points runs
@@ -819,8 +844,10 @@ int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t
     double lc = 0;
     std::vector<int32_t> rest;
     if (build_lanes(ctx, p_off, q_off, npairs, D, exact, lanes, lc, &rest) && lc < cost) {
+      const size_t alt = ws_layout(pl, npairs, npairs, exact).total;  // the job-table plan for all
       if (rest.empty()) {
         pl = std::move(lanes);
+        pl.alt_ws = alt;
       } else {
         Plan longp;
         double sc = -1;
@@ -834,6 +861,7 @@ int plan_batch(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t
           longp.lane_order = std::move(lanes.lane_order);
           longp.lane_waves = lanes.nwaves;
           pl = std::move(longp);
+          pl.alt_ws = alt;
         }
       }
     }
@@ -862,8 +890,11 @@ int plan_cross(ffd_ctx *ctx, const int64_t *q_off, int64_t nq, const int64_t *db
   if (ctx->tune_R == 0 && ctx->tune_W == 0 && ctx->split == 0.f && nq * ndb <= INT32_MAX) {
     Plan lanes;
     double lc = 0;
-    if (build_lanes(ctx, q_off, db_off, nq * ndb, D, exact, lanes, lc, nullptr, ndb) && lc < cost)
+    if (build_lanes(ctx, q_off, db_off, nq * ndb, D, exact, lanes, lc, nullptr, ndb) && lc < cost) {
+      const size_t alt = ws_layout(pl, nq, ndb, exact).total;  // the job-table plan
       pl = std::move(lanes);
+      pl.alt_ws = alt;
+    }
   }
   return FFD_OK;
 }
@@ -902,30 +933,7 @@ int plan_pair(ffd_ctx *ctx, int64_t n, int64_t m, int D, bool exact, Plan &pl) {
 
 // ---------------------------------------------------------------- workspace
 
-size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct WsLayout {
-  size_t jobs, wj, off0, off1, lo0, lo1, order, flags, err, links, total;
-};
-
-WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
-  WsLayout w;
-  size_t o = 0;
-  w.jobs = o;  o = al256(o + pl.jobs.size() * sizeof(Job));
-  w.wj = o;    o = al256(o + (size_t)(pl.nwaves + 1) * sizeof(int32_t));
-  // 64-bit offsets for the streaming kernel, 32-bit ones for the lane kernel
-  const bool stream = !pl.lanes || !pl.jobs.empty();
-  w.off0 = o;  o = al256(o + (stream ? (size_t)(n0 + 1) * sizeof(int64_t) : 0));
-  w.off1 = o;  o = al256(o + (stream ? (size_t)(n1 + 1) * sizeof(int64_t) : 0));
-  w.lo0 = o;   o = al256(o + (pl.lanes ? (size_t)(n0 + 1) * sizeof(int32_t) : 0));
-  w.lo1 = o;   o = al256(o + (pl.lanes ? (size_t)(n1 + 1) * sizeof(int32_t) : 0));
-  w.order = o; o = al256(o + pl.lane_order.size() * sizeof(int32_t));
-  w.flags = o; o = al256(o + (size_t)pl.nflags * sizeof(uint64_t));
-  w.err = o;   o = al256(o + sizeof(uint64_t));
-  w.links = o; o = al256(o + (size_t)pl.link_elems * (exact ? 8 : 4));
-  w.total = o;
-  return w;
-}
 
 // The staging buffer for plan uploads, at least `bytes` long.  Replacing
 // its contents first waits until every upload has read it: the last one
@@ -1957,7 +1965,9 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
   if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
   if (op == FFD_OP_DECIDE || op == FFD_OP_KNN) return search_scratch_size(ctx, op, a_off, na, b_off, nb, dim, bytes);
   // one size for every path: float and int32 coordinates, every measure and
-  // ground distance (kernel ops 0, 1, 3, ..., 8, and 10, 11 for 2-D curves)
+  // ground distance (kernel ops 0, 1, 3, ..., 8, and 10, 11 for 2-D curves),
+  // and for requests that run one pair per lane the job-table plan they were
+  // weighed against as well (a forced launch shape or the autotuner uses it)
   size_t worst = 0;
   for (int ms = 0; ms <= kOpGeoDtw; ++ms)
     for (int ex = 0; ex < 2; ++ex) {
@@ -1972,7 +1982,7 @@ int ffd_workspace_size(ffd_ctx *ctx, int32_t op, const int64_t *a_off, int64_t n
       if (rc == FFD_E_UNSUPPORTED) continue;
       if (rc) return rc;
       if (op == FFD_OP_PAIR) worst = std::max(worst, pair_scratch_bytes(*pl, ex == 1));
-      else worst = std::max(worst, ws_layout(*pl, na, nb, ex == 1).total);
+      else worst = std::max({worst, ws_layout(*pl, na, nb, ex == 1).total, pl->alt_ws});
     }
   if (worst == 0 && op != FFD_OP_PAIR) return fail(ctx, FFD_E_UNSUPPORTED, "request not supported by any path");
   *bytes = worst;

@@ -136,6 +136,7 @@ struct Plan {
   std::vector<int32_t> lane_order;  // pair index; the top bit: the second set holds the rows
   int32_t lane_waves = 0;           // with jobs as well: wavefronts of the lane launch
   int64_t lane_cross = 0;           // > 0: (query, database curve) pairs, this many database curves
+  size_t alt_ws = 0;                // workspace of the job-table plan this one was chosen over
 };
 
 // A request as the planner sees it: header words (operation, dimension,

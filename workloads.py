@@ -141,6 +141,20 @@ def poisson_arrivals(seed=7, count=1000, rate=1000.0):
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
+def short_symbol_pairs(seed=12, npairs=262144, lo=8, hi=64, alphabet=4):
+    """Many short symbol sequences (one int32 coordinate per symbol).  Draw
+    order: n[npairs], m[npairs] uniform in [lo, hi]; then every p symbol and
+    every q symbol uniform in [0, alphabet).  Returns P, p_off, Q, q_off."""
+    rng = np.random.default_rng(seed)
+    n = rng.integers(lo, hi + 1, size=npairs)
+    m = rng.integers(lo, hi + 1, size=npairs)
+    p_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(m)]).astype(np.int64)
+    P = rng.integers(0, alphabet, size=(int(p_off[-1]), 1)).astype(np.int32)
+    Q = rng.integers(0, alphabet, size=(int(q_off[-1]), 1)).astype(np.int32)
+    return P, p_off, Q, q_off
+
+
 def short_pairs(seed=11, npairs=262144, lo=8, hi=64, dim=2, long_pairs=0, long_lo=300, long_hi=1500):
     """Many short pairs.  Draw order: n[npairs], m[npairs] uniform in [lo, hi];
     with long_pairs > 0, then n and m of that many more pairs uniform in
