@@ -82,9 +82,23 @@ def time_steps(step, steps, sync):
         gc.enable()
 
 
-def kernel_ms(torch, step, steps, stream):
-    """Average duration of one step's launch, from HIP events recorded on the
-    stream the kernel runs on."""
+def kernel_ms(torch, step, steps, stream, ctx=None):
+    """Average duration of one step's launch.  The library's own event pair
+    on the launch stream when it records one per step (its kernels alone,
+    without the plan upload); otherwise HIP events recorded on the stream
+    around each step."""
+    if ctx is not None:
+        torch.cuda.synchronize()
+        ctx.set_kernel_timing(True)
+        try:
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            ms, n = ctx.kernel_time()
+        finally:
+            ctx.set_kernel_timing(False)
+        if n == steps:
+            return ms / n
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     for a, b in evs:
@@ -211,7 +225,7 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
         torch.cuda.synchronize()
         del src, dst
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     res = out.cpu().numpy()
@@ -305,7 +319,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     res = out.cpu().numpy()
     import oracle
@@ -332,7 +346,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
         for _ in range(2):
             step()
         ssec = time_steps(step, args.steps, torch.cuda.synchronize)
-        skms = kernel_ms(torch, step, args.steps, stream)
+        skms = kernel_ms(torch, step, args.steps, stream, ctx)
         sinfo = ctx.last_launch()
         same = bool(np.array_equal(out.cpu().numpy(), res))
     finally:
@@ -396,7 +410,7 @@ def run_dtw(args, torch, ffd, ctx, dev, stream):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     g = golden()["dtw_batched"]
@@ -455,7 +469,7 @@ def run_levenshtein(args, torch, ffd, ctx, dev, stream):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     g = golden()["levenshtein"]
@@ -510,7 +524,7 @@ def run_geo(args, torch, ffd, ctx, dev, stream, dtw=False):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     g = golden()["dtw_haversine" if dtw else "batched_haversine"]
@@ -579,7 +593,7 @@ def run_decide(args, torch, ffd, ctx, dev, stream):
     for _ in range(args.warmup):
         step(eps)()
     sec = time_steps(step(eps), args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step(eps), args.steps, stream)
+    kms = kernel_ms(torch, step(eps), args.steps, stream, ctx)
     res = out.cpu().numpy()
     idx = np.array(g["sample_index"])
     want = np.array(g["euclidean"])
@@ -588,11 +602,11 @@ def run_decide(args, torch, ffd, ctx, dev, stream):
     val_ok = bool(np.all(np.abs(res[idx][kept] - want[kept]) <= TOL * want[kept]))
     frac_no = float(np.mean(np.isinf(res)))
     step(big)()
-    kms_all = kernel_ms(torch, step(big), args.steps, stream)
+    kms_all = kernel_ms(torch, step(big), args.steps, stream, ctx)
     swept = out.cpu().numpy()
     step(np.inf)()
     sec_inf = time_steps(step(np.inf), args.steps, torch.cuda.synchronize)
-    kms_inf = kernel_ms(torch, step(np.inf), args.steps, stream)
+    kms_inf = kernel_ms(torch, step(np.inf), args.steps, stream, ctx)
     full = out.cpu().numpy()
     info = {"rows_per_lane": 8, "waves": "1 to 2 per SIMD, one pair per wave at a time"}
     inf_line = roofline(ctx.last_launch(), cells, kms_inf, 2, False)
@@ -716,7 +730,7 @@ def run_pair(args, torch, ffd, ctx, dev, stream, which):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     got = out.item()
@@ -770,7 +784,7 @@ def run_cross(args, torch, ffd, ctx, dev, stream):
     for _ in range(args.warmup):
         step()
     sec = time_steps(step, args.steps, torch.cuda.synchronize)
-    kms = kernel_ms(torch, step, args.steps, stream)
+    kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     errs = ctx.last_errors()
     g = golden()["cross_int"]

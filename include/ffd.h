@@ -394,6 +394,23 @@ typedef struct ffd_launch_info {
 
 int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info);
 
+/* Kernel timing, for measurement.  While enabled, every ffd_batch,
+ * ffd_cross (all their variants, eager calls only) and ffd_distance that
+ * runs on many wavefronts records a HIP event on its stream just before its
+ * first kernel and one just after its last: the time between them leaves
+ * out the plan upload.  The first time a launch is timed the context
+ * creates the events it needs (kept until ffd_destroy); at most 65536
+ * launches are recorded between two reads, later ones are not.  Enabling
+ * or disabling clears the record.
+ * Errors: FFD_E_INVALID (NULL, or a planning-only context). */
+int ffd_set_kernel_timing(ffd_ctx *ctx, int32_t enable);
+
+/* Waits for the launches recorded since the last read or ffd_set_kernel_timing
+ * and returns their summed kernel time (milliseconds, `*total_ms`) and their
+ * number (`*launches`, 0 when none), then clears the record.
+ * Errors: FFD_E_INVALID (NULL), FFD_E_DEVICE. */
+int ffd_kernel_time(ffd_ctx *ctx, double *total_ms, int64_t *launches);
+
 /* Error bits the most recent launch on this context raised on the device
  * (waits for it to finish): bit 0 = a wavefront hit its step bound, bit 1 =
  * a wavefront gave up waiting for a boundary row from another wavefront

@@ -1019,6 +1019,24 @@ void plan_image(const Plan &pl, const WsLayout &wl, const int64_t *off0, int64_t
   memset(h + wl.flags, 0, wl.links - wl.flags);  // flags and error word
 }
 
+// Kernel timing: an event on the launch stream before the first kernel and
+// after the last one of a launch (never inside a graph capture).
+constexpr size_t kMaxTimedLaunches = 1 << 16;
+
+int time_mark(ffd_ctx *ctx, hipStream_t st, bool capturing) {
+  if (!ctx->timing || capturing || ctx->tev_used >= 2 * kMaxTimedLaunches) return FFD_OK;
+  if (ctx->tev_used == ctx->tev.size()) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate (timing)");
+    ctx->tev.push_back(ev);
+  }
+  hipError_t e = hipEventRecord(ctx->tev[ctx->tev_used], st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord (timing)");
+  ++ctx->tev_used;
+  return FFD_OK;
+}
+
 int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const int64_t *off0, int64_t n0,
              const void *X1, const int64_t *off1, int64_t n1, int D, bool exact, int metric, void *out, void *ws,
              size_t ws_bytes, hipStream_t st, UseOrder &use, bool noalloc = false) {
@@ -1102,9 +1120,11 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
       la.block_first[c + 1] = la.block_first[c] + (pl.lane_first[c + 1] - pl.lane_first[c] + ffd::kLaneBlock - 1) /
                                                       ffd::kLaneBlock;
     }
+    if (int rc = time_mark(ctx, st, capturing)) return rc;
     e = ffd::launch_lanes(exact, D, la, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
     if (pl.jobs.empty()) {
+      if (int rc = time_mark(ctx, st, capturing)) return rc;
       ctx->last = ffd_launch_info{0, pl.nwaves, pl.wpb, 0, exact ? 1 : 0, D, 0, 0, pl.max_steps, 1};
       ctx->last_err = nullptr;  // the kernel waits on nothing and raises no error bits
       ctx->last_stream = st;
@@ -1134,8 +1154,11 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
   a.dim = D;
   ctx->last = ffd_launch_info{pl.R, pl.nwaves, pl.wpb, a.lds_per_wave, exact ? 1 : 0, D, 0, 0, pl.max_steps,
                               pl.lanes ? 1 : 0};
+  if (!pl.lanes)
+    if (int rc = time_mark(ctx, st, capturing)) return rc;
   e = ffd::launch_stream(exact, pl.R, D, a, pl.wpb, pl.coop, st, ctx->measure);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+  if (int rc = time_mark(ctx, st, capturing)) return rc;
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
   ctx->last_stream = st;
@@ -1282,8 +1305,20 @@ struct TunedScope {
   }
 };
 
+// The Levenshtein kernels hold the table's values in float32, exact below
+// 2^24: every value is at most n + m.
+constexpr int64_t kLevMax = (int64_t)1 << 24;
+
+static int64_t longest(const int64_t *off, int64_t count) {
+  int64_t l = 0;
+  if (!off) return 0;
+  for (int64_t k = 0; k < count; ++k) l = std::max(l, off[k + 1] - off[k]);
+  return l;
+}
+
 // (validate: check both offset arrays, unless they equal those of the
-// cached plan, which were checked when it was made)
+// cached plan, which were checked when it was made; a Levenshtein request's
+// sequence lengths are checked against the float32 bound on the same terms)
 int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64_t na, const int64_t *b_off,
                 int64_t nb, int D, bool exact, const Plan **out, uint64_t &gen, bool validate = false) {
   Req r = req_of(ctx, op, D, exact, a_off, na, b_off, nb);
@@ -1298,6 +1333,8 @@ int cached_plan(ffd_ctx *ctx, PlanCache &pc, int op, const int64_t *a_off, int64
     if ((rc = check_offsets(ctx, a_off, na, "offsets are NULL"))) return rc;
     if ((rc = check_offsets(ctx, b_off, nb, "offsets are NULL"))) return rc;
   }
+  if (ctx->measure == 8 && op != kOpPair && longest(a_off, na) + longest(b_off, nb) >= kLevMax)
+    return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
   if (op == FFD_OP_BATCH) rc = plan_batch(ctx, a_off, b_off, na, D, exact, pl);
   else if (op == FFD_OP_CROSS) rc = plan_cross(ctx, a_off, na, b_off, nb, D, exact, pl);
   else rc = plan_pair(ctx, a_off[1], b_off[1], D, exact, pl);
@@ -1358,8 +1395,10 @@ int run_pipe(ffd_ctx *ctx, const Plan &pl, const void *p, const void *q, int D, 
     e = ffd::pipe_init(a.links, (int64_t)((L.total - L.links) / 4), a.err, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "link initialisation launch");
   }
+  if (int rc2 = time_mark(ctx, st, capturing)) return rc2;
   e = ffd::launch_pipe(exact, pl.R, D, a, lds, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "pipelined kernel launch");
+  if (int rc2 = time_mark(ctx, st, capturing)) return rc2;
   ctx->last_err = a.err;
   ctx->last_epoch = a.epoch;
   ctx->last_stream = st;
@@ -1626,6 +1665,10 @@ int ffd_create_planner(int32_t compute_units, int64_t lds_per_block, ffd_ctx **o
 
 void ffd_destroy(ffd_ctx *ctx) {
   if (!ctx) return;
+  for (hipEvent_t ev : ctx->tev) {
+    hipEventSynchronize(ev);
+    hipEventDestroy(ev);
+  }
   if (ctx->upload_done) {
     hipEventSynchronize(ctx->upload_done);
     hipEventDestroy(ctx->upload_done);
@@ -1654,6 +1697,33 @@ int ffd_set_scratch(ffd_ctx *ctx, void *scratch, size_t bytes) {
 int ffd_last_launch(const ffd_ctx *ctx, ffd_launch_info *info) {
   if (!ctx || !info) return FFD_E_INVALID;
   *info = ctx->last;
+  return FFD_OK;
+}
+
+int ffd_set_kernel_timing(ffd_ctx *ctx, int32_t enable) {
+  if (!ctx) return FFD_E_INVALID;
+  if (enable && ctx->device < 0) return fail(ctx, FFD_E_INVALID, "a planning-only context launches nothing");
+  ctx->timing = enable != 0;
+  ctx->tev_used = 0;
+  return FFD_OK;
+}
+
+int ffd_kernel_time(ffd_ctx *ctx, double *total_ms, int64_t *launches) {
+  if (!ctx || !total_ms || !launches) return FFD_E_INVALID;
+  *total_ms = 0;
+  *launches = 0;
+  double sum = 0;
+  for (size_t k = 0; k + 1 < ctx->tev_used; k += 2) {
+    hipError_t e = hipEventSynchronize(ctx->tev[k + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize (timing)");
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, ctx->tev[k], ctx->tev[k + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)(ctx->tev_used / 2);
+  ctx->tev_used = 0;
   return FFD_OK;
 }
 
@@ -1800,14 +1870,6 @@ int ffd_cross_i32(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off, int64_t
 // sequences: the same calls with the Levenshtein kernels (kernel op 8).
 // The kernels hold the table's values in float32, exact below 2^24: every
 // value is at most n + m.
-constexpr int64_t kLevMax = (int64_t)1 << 24;
-
-static int64_t longest(const int64_t *off, int64_t count) {
-  int64_t l = 0;
-  if (!off) return 0;
-  for (int64_t k = 0; k < count; ++k) l = std::max(l, off[k + 1] - off[k]);
-  return l;
-}
 
 int ffd_levenshtein_distance(ffd_ctx *ctx, const int32_t *p, int64_t n, const int32_t *q, int64_t m, int32_t dim,
                              int64_t *out, void *stream) {
@@ -1821,11 +1883,7 @@ int ffd_levenshtein_batch(ffd_ctx *ctx, const int32_t *P, const int64_t *p_off, 
                           const int64_t *q_off, int64_t npairs, int32_t dim, int64_t *out, void *workspace,
                           size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, 8);
-  if (npairs > 0 && check_offsets(ctx, p_off, npairs, "p_off is NULL") == FFD_OK &&
-      check_offsets(ctx, q_off, npairs, "q_off is NULL") == FFD_OK &&
-      longest(p_off, npairs) + longest(q_off, npairs) >= kLevMax)
-    return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
+  MeasureScope scope(ctx, 8);  // the sequence lengths are checked with the offsets, when planned
   return batch_common(ctx, P, p_off, Q, q_off, npairs, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
                       (hipStream_t)stream, false);
 }
@@ -1834,11 +1892,7 @@ int ffd_levenshtein_cross(ffd_ctx *ctx, const int32_t *Qs, const int64_t *q_off,
                           const int64_t *db_off, int64_t ndb, int32_t dim, int64_t *out, void *workspace,
                           size_t ws_bytes, void *stream) {
   if (!ctx) return FFD_E_INVALID;
-  MeasureScope scope(ctx, 8);
-  if (nq > 0 && ndb > 0 && check_offsets(ctx, q_off, nq, "q_off is NULL") == FFD_OK &&
-      check_offsets(ctx, db_off, ndb, "db_off is NULL") == FFD_OK &&
-      longest(q_off, nq) + longest(db_off, ndb) >= kLevMax)
-    return fail(ctx, FFD_E_UNSUPPORTED, "Levenshtein sequences must have n + m < 2^24");
+  MeasureScope scope(ctx, 8);  // the sequence lengths are checked with the offsets, when planned
   return cross_common(ctx, Qs, q_off, nq, DB, db_off, ndb, dim, FFD_SQEUCLIDEAN, out, workspace, ws_bytes,
                       (hipStream_t)stream, false);
 }

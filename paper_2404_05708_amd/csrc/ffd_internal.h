@@ -186,6 +186,10 @@ struct ffd_ctx {
   size_t pinned_bytes = 0;
   uint64_t staged_gen = 0;    // plan whose bytes the staging buffer holds (0: none)
   hipEvent_t upload_done = nullptr;   // end of the last plan upload
+  // kernel timing (ffd_set_kernel_timing): an event pair per launch around its kernels
+  bool timing = false;
+  std::vector<hipEvent_t> tev;  // pool, two per recorded launch
+  size_t tev_used = 0;          // events recorded since the last ffd_kernel_time
   hipStream_t upload_stream = nullptr;
   bool upload_streams_mixed = false;  // uploads on more than one stream since the staging was written
   // plan image of the no-allocation entry point (pageable host memory)

@@ -45,6 +45,7 @@ EXPORTS = (
     "ffd_create", "ffd_create_planner", "ffd_destroy", "ffd_strerror", "ffd_last_error", "ffd_version",
     "ffd_distance", "ffd_distance_i32", "ffd_batch", "ffd_batch_i32", "ffd_cross",
     "ffd_cross_i32", "ffd_workspace_size", "ffd_set_tuning", "ffd_last_launch", "ffd_set_split", "ffd_last_errors",
+    "ffd_set_kernel_timing", "ffd_kernel_time",
     "ffd_db_create", "ffd_db_destroy", "ffd_server_arena_size", "ffd_server_create", "ffd_server_destroy",
     "ffd_server_submit", "ffd_server_poll", "ffd_server_wait", "ffd_server_get_stats", "ffd_server_reset_stats",
     "ffd_server_last_error", "ffd_server_cancel", "ffd_server_set_deadline", "ffd_set_tune_cache",
@@ -170,6 +171,10 @@ def _load(path=None):
     lib.ffd_set_split.restype = ctypes.c_int
     lib.ffd_last_launch.argtypes = [vp, ctypes.POINTER(LaunchInfo)]
     lib.ffd_last_launch.restype = ctypes.c_int
+    lib.ffd_set_kernel_timing.argtypes = [vp, i32]
+    lib.ffd_set_kernel_timing.restype = ctypes.c_int
+    lib.ffd_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ffd_kernel_time.restype = ctypes.c_int
     lib.ffd_levenshtein_distance.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
     lib.ffd_levenshtein_distance.restype = ctypes.c_int
     lib.ffd_levenshtein_batch.argtypes = [vp, vp, i64p, vp, i64p, i64, i32, vp, vp, sz, vp]
@@ -431,6 +436,17 @@ def ffd_last_launch(ctx):
     info = LaunchInfo()
     _check(lib.ffd_last_launch(ctx, ctypes.byref(info)), ctx)
     return info.as_dict()
+
+
+def ffd_set_kernel_timing(ctx, enable):
+    _check(lib.ffd_set_kernel_timing(ctx, 1 if enable else 0), ctx)
+
+
+def ffd_kernel_time(ctx):
+    """(summed kernel milliseconds, launches) recorded since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.ffd_kernel_time(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
 
 
 def _pair(fn, dtype, odtype, ctx, p, q, metric, out, stream):
@@ -727,6 +743,12 @@ class Context:
 
     def last_launch(self):
         return ffd_last_launch(self.handle)
+
+    def set_kernel_timing(self, enable):
+        ffd_set_kernel_timing(self.handle, enable)
+
+    def kernel_time(self):
+        return ffd_kernel_time(self.handle)
 
     def distance(self, p, q, metric=FFD_EUCLIDEAN, **kw):
         return ffd_distance(self.handle, p, q, metric, **kw)

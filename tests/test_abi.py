@@ -232,6 +232,11 @@ def test_levenshtein_argument_checks(planner):
     big = np.array([0, 1 << 23], dtype=np.int64)
     assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(big), FAKE, _i64p(big), 1, 1, FAKE, FAKE, 1 << 20,
                                    None) == ffd.FFD_E_UNSUPPORTED
+    one = np.array([0, 1], dtype=np.int64)
+    assert L.ffd_levenshtein_cross(planner, FAKE, _i64p(big), 1, FAKE, _i64p(big), 1, 1, FAKE, FAKE, 1 << 20,
+                                   None) == ffd.FFD_E_UNSUPPORTED
+    assert L.ffd_levenshtein_cross(planner, FAKE, _i64p(one), 1, FAKE, _i64p(big), 1, 1, FAKE, FAKE, 1 << 20,
+                                   None) == ffd.FFD_E_DEVICE  # 1 + 2^23 is within the bound
     good = np.array([0, 3, 5, 9], dtype=np.int64)
     assert L.ffd_levenshtein_batch(planner, FAKE, _i64p(good), FAKE, _i64p(good), 3, 1, FAKE, FAKE, 1 << 20,
                                    None) == ffd.FFD_E_DEVICE
@@ -255,6 +260,14 @@ def test_set_tuning_validation(planner):
     with pytest.raises(ffd.FFDError):
         ffd.ffd_set_tuning(planner, 2, -2)
     ffd.ffd_set_tuning(planner, 0, 0)
+
+
+def test_kernel_timing_checks(planner):
+    # a planning-only context launches nothing, so it has nothing to time
+    with pytest.raises(ffd.FFDError):
+        ffd.ffd_set_kernel_timing(planner, True)
+    ffd.ffd_set_kernel_timing(planner, False)
+    assert ffd.ffd_kernel_time(planner) == (0.0, 0)
 
 
 def test_serving_database_and_arena(planner):

@@ -323,3 +323,36 @@ def workloads_cross_int(rng):
     Qi = rng.integers(-(1 << 15), 1 << 15, size=(int(qo[-1]), 2), dtype=np.int32)
     Di = rng.integers(-(1 << 15), 1 << 15, size=(int(do[-1]), 2), dtype=np.int32)
     return Qi, qo, Di, do
+
+
+def test_kernel_timing(ctx):
+    # the library's event pair brackets the kernels alone: no longer than the
+    # whole call on the same stream, one record per launch, none when off
+    P, p_off, Q, q_off = short_pairs(611, 60000, 8, 64, 2)
+    Pd, Qd = dev(P), dev(Q)
+    out = torch.empty(len(p_off) - 1, dtype=torch.float32, device="cuda:0")
+    ctx.batch(Pd, p_off, Qd, q_off, out=out)  # plan cached
+    for forced in (False, True):
+        if forced:
+            ctx.set_tuning(1, 0)  # the streaming kernel's job-table plan
+        try:
+            say(f"case: kernel timing forced_stream={forced}")
+            ctx.batch(Pd, p_off, Qd, q_off, out=out)
+            torch.cuda.synchronize()
+            ctx.set_kernel_timing(True)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                ctx.batch(Pd, p_off, Qd, q_off, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            ms, n = ctx.kernel_time()
+            assert n == 5 and ctx.last_launch()["per_lane"] == (0 if forced else 1)
+            assert 0 < ms <= a.elapsed_time(b) * 1.001 + 0.01, (ms, a.elapsed_time(b))
+            assert ctx.kernel_time() == (0.0, 0)  # read clears the record
+            ctx.set_kernel_timing(False)
+            ctx.batch(Pd, p_off, Qd, q_off, out=out)
+            assert ctx.kernel_time() == (0.0, 0)
+        finally:
+            ctx.set_kernel_timing(False)
+            ctx.set_tuning(0, 0)
