@@ -56,8 +56,10 @@ def imin(dim, exact=False, cell="euclidean"):
     three-input maxima.  DTW replaces the max by an add (same count)."""
     sel = 3 if exact else 2
     if cell == "levenshtein":
-        # a compare and a select per symbol value, then min, +1, +d, min
-        return 2 * dim + 4
+        # a compare per symbol coordinate, then the least of the three
+        # neighbours (three-input min), +1, and the select of the diagonal
+        # on a match (neighbouring values differ by at most one)
+        return dim + 3
     if cell == "manhattan":
         return 2 * dim - 1 + sel
     if cell == "chebyshev":

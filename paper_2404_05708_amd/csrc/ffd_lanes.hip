@@ -151,18 +151,23 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
         const bool two = !SUM || i + 1 < n;        // sums: no repeated row
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-          const V da = cell_value<D, V, CELL>(pa, q[j]);
-          const V db = cell_value<D, V, CELL>(pb, q[j]);
           V va, vb;
           if constexpr (LEV) {
-            va = N::mn(N::mn(row[j], left_a) + V(1), diag_a + da);
-            vb = N::mn(N::mn(va, left_b) + V(1), diag_b + db);
-          } else if constexpr (DTW) {
-            va = N::mn(N::mn(row[j], diag_a), left_a) + da;
-            vb = N::mn(N::mn(va, diag_b), left_b) + db;
+            // neighbouring values of the table differ by at most one: on a
+            // match the diagonal is the least candidate, otherwise the
+            // three candidates share the + 1 (the streaming kernel's form)
+            va = cell_value<D, V, CELL>(pa, q[j]) == V(0) ? diag_a : N::mn(N::mn(row[j], left_a), diag_a) + V(1);
+            vb = cell_value<D, V, CELL>(pb, q[j]) == V(0) ? diag_b : N::mn(N::mn(va, left_b), diag_b) + V(1);
           } else {
-            va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
-            vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
+            const V da = cell_value<D, V, CELL>(pa, q[j]);
+            const V db = cell_value<D, V, CELL>(pb, q[j]);
+            if constexpr (DTW) {
+              va = N::mn(N::mn(row[j], diag_a), left_a) + da;
+              vb = N::mn(N::mn(va, diag_b), left_b) + db;
+            } else {
+              va = N::mx(N::mn(N::mn(row[j], diag_a), left_a), da);
+              vb = N::mx(N::mn(N::mn(va, diag_b), left_b), db);
+            }
           }
           diag_a = row[j];
           left_a = va;

@@ -654,6 +654,7 @@ struct Stream {
       V up = N::shift_in(g.h[u], bottom);
       const Pt &qe = entry(g, u);
       V dd[R];
+      bool same[R];  // Levenshtein: p_i = q_j (a separator matches nothing)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         V t = p[r][0] - qe.c[0];
@@ -684,13 +685,13 @@ struct Stream {
           }
         }
         if constexpr (LEV) {
-          // d = [p_i != q_j], symbols compared as bit patterns; a separator
-          // (flag slot set) differs from every symbol
+          // symbols compared as bit patterns; a separator (flag slot set)
+          // differs from every symbol
           bool ne = __builtin_bit_cast(uint32_t, qe.c[D]) != 0u;
 #pragma unroll
           for (int k2 = 0; k2 < D; ++k2)
             ne = ne || __builtin_bit_cast(uint32_t, p[r][k2]) != __builtin_bit_cast(uint32_t, qe.c[k2]);
-          s = ne ? V(1) : V(0);
+          same[r] = !ne;
         }
         dd[r] = s;
       }
@@ -698,7 +699,12 @@ struct Stream {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         V v;
-        if constexpr (LEV) v = N::mn(N::mn(above, Mp[r]) + V(1), diag + dd[r]);
+        // Levenshtein: M_{i,j} = min(M_{i-1,j} + 1, M_{i,j-1} + 1,
+        // M_{i-1,j-1} + [p_i != q_j]).  Neighbouring values of the table
+        // differ by at most one, so on a match the diagonal is the least of
+        // the three, and otherwise the three candidates share the + 1; the
+        // separator columns take the second form, as before
+        if constexpr (LEV) v = same[r] ? diag : N::mn(N::mn(above, Mp[r]), diag) + V(1);
         else if constexpr (DTW) v = N::mn(N::mn(above, diag), Mp[r]) + dd[r];
         else v = N::mx(N::mn(N::mn(above, diag), Mp[r]), dd[r]);
         diag = Mp[r];

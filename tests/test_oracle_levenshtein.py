@@ -70,6 +70,30 @@ def test_equals_recursive_definition():
         assert oracle.lev(p, q) == recursive(p, q)
 
 
+def match_form(p, q):
+    """The cell form the kernels evaluate: on a symbol match the diagonal
+    value, otherwise one more than the least of the three neighbours, with
+    the boundary row j + 1 and column i + 1 (float32 integers, as on the
+    device).  Equal to the recurrence because neighbouring values of the
+    table differ by at most one."""
+    P = [tuple(r) for r in np.asarray(p).reshape(len(p), -1).tolist()]
+    Q = [tuple(r) for r in np.asarray(q).reshape(len(q), -1).tolist()]
+    row = [np.float32(j + 1) for j in range(len(Q))]
+    for i in range(len(P)):
+        diag, left = np.float32(i), np.float32(i + 1)
+        for j in range(len(Q)):
+            v = diag if P[i] == Q[j] else min(row[j], left, diag) + np.float32(1)
+            diag, left, row[j] = row[j], v, v
+    return int(row[-1])
+
+
+def test_kernel_match_form_equals_the_recurrence():
+    cases = _cases(130, 400) + _cases(131, 150, D=2, alphabet=2) + _cases(132, 100, maxlen=30, alphabet=2)
+    cases += [(seq([1] * 9), seq([1] * 5)), (seq([0, 1] * 6), seq([1, 0] * 6)), (seq([2]), seq([3] * 7))]
+    for p, q in cases:
+        assert match_form(p, q) == oracle.lev(p, q)
+
+
 def test_paper_algorithm_zero_based_reading():
     differ = 0
     for p, q in _cases(122, 200, maxlen=9):
