@@ -24,6 +24,11 @@ not counted).
          (ffd_knn: bounds, threshold, early-abandoning sweep) against a
          full scan
 
+The batched and short-pairs lines time HIP graph replays of the call
+(inputs and the call's plan resident in device memory, the replays' bits
+checked against the eager call's); the eager calls' rate, with the plan
+uploaded from host memory on every call, is printed beside it ("eager").
+
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (VALU issue rate: the path has no contraction and moves O(n+m) bytes per
 pair), and the CPU oracle timed on a bounded sample of the same workload.
@@ -109,6 +114,43 @@ def kernel_ms(torch, step, steps, stream, ctx=None):
         b.record(stream)
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def graph_replay(torch, call, steps, out):
+    """Time one call recorded into a HIP graph: (seconds per replay, whether
+    every replay's results equal the eager call's bits).  The eager call
+    just before the capture leaves the call's plan (the job table and the
+    offsets, from host memory) in the workspace, so a replay runs the
+    kernels on inputs and plan already resident in device memory: no
+    transfer from host memory inside the timed region."""
+    call(None)  # eager, on the current stream
+    torch.cuda.synchronize()
+    eager = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call(None)  # torch's capture stream is current inside the block
+    same = True
+    for _ in range(2):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same = same and torch.equal(out, eager)
+    sec = time_steps(g.replay, steps, torch.cuda.synchronize)
+    same = same and torch.equal(out, eager)
+    del g
+    return sec, same
+
+
+def resident(cells, sec, gsec, same):
+    """The line's rate: graph replays (inputs and plan resident) when their
+    bits equal the eager call's, with the eager call's rate beside it."""
+    use = gsec if same else sec
+    return use, {"ms_per_step": sec * 1e3, "cells_per_s": cells / sec,
+                 "note": "one eager call per step: the plan (job table and offsets from host memory) is uploaded "
+                         "on every call, inside the timed region"}, \
+        {"timing": "HIP graph replay of one call (plan resident in the workspace)" if same else
+                   "eager calls (graph replays differed from the eager bits)", "replay_bit_identical": same}
 
 
 def launch_signature(info):
@@ -212,8 +254,11 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     metric = {"euclidean": ffd.FFD_EUCLIDEAN, "manhattan": ffd.FFD_MANHATTAN,
               "chebyshev": ffd.FFD_CHEBYSHEV}[args.metric]
 
+    def call(st):
+        ctx.batch(Pd, p_off, Qd, q_off, metric=metric, out=out, workspace=ws, stream=st)
+
     def step():
-        ctx.batch(Pd, p_off, Qd, q_off, metric=metric, out=out, workspace=ws, stream=stream)
+        call(stream)
 
     tuning = None
     if args.autotune:
@@ -231,6 +276,8 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
     info = ctx.last_launch()
     errs = ctx.last_errors()
     res = out.cpu().numpy()
+    gsec, gsame = graph_replay(torch, call, args.steps, out)
+    use, eager, timing = resident(cells, sec, gsec, gsame)
     if wide:
         # 64 pairs of the batch against the FP64 oracle, computed here
         import oracle
@@ -277,7 +324,7 @@ def run_batched(args, torch, ffd, ctx, dev, stream):
                          f"oracle, longest first on {cores} threads, {cw:.2f} s",
                "gpu_matches_sample": agree}
     return {
-        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
+        "value": cells / use, "ms_per_step": use * 1e3, "dtype": "f32", "timing": timing, "eager": eager,
         "config": {"workload": f"batched: 4096 pairs, n and m uniform in [64, 2048], {dim}-D float32 "
                                f"random walks, q = p resampled + N(0, 0.1^2), {args.metric.capitalize()} (seed 2)",
                    "npairs": npairs, "cells": cells, "global_batch": npairs},
@@ -310,13 +357,16 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     out = torch.empty(npairs, dtype=torch.int64 if lev else torch.float32, device=dev)
     dtw = args.dtw  # DTW of squared Euclidean cells instead of the Frechet distance
 
-    def step():
+    def call(st):
         if lev:
-            ctx.levenshtein_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+            ctx.levenshtein_batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=st)
         elif dtw:
-            ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_SQEUCLIDEAN, out=out, workspace=ws, stream=stream)
+            ctx.dtw_batch(Pd, p_off, Qd, q_off, metric=ffd.FFD_SQEUCLIDEAN, out=out, workspace=ws, stream=st)
         else:
-            ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=stream)
+            ctx.batch(Pd, p_off, Qd, q_off, out=out, workspace=ws, stream=st)
+
+    def step():
+        call(stream)
 
     for _ in range(args.warmup):
         step()
@@ -324,6 +374,8 @@ def run_short(args, torch, ffd, ctx, dev, stream):
     kms = kernel_ms(torch, step, args.steps, stream, ctx)
     info = ctx.last_launch()
     res = out.cpu().numpy()
+    gsec, gsame = graph_replay(torch, call, args.steps, out)
+    use, eager, timing = resident(cells, sec, gsec, gsame)
     import oracle
     idx = np.sort(np.random.default_rng(79).choice(npairs, size=256, replace=False))
     if lev:
@@ -351,6 +403,9 @@ def run_short(args, torch, ffd, ctx, dev, stream):
         skms = kernel_ms(torch, step, args.steps, stream, ctx)
         sinfo = ctx.last_launch()
         same = bool(np.array_equal(out.cpu().numpy(), res))
+        sgsec, sgsame = graph_replay(torch, call, args.steps, out)
+        same = same and bool(np.array_equal(out.cpu().numpy(), res))
+        suse = sgsec if sgsame else ssec
     finally:
         ctx.set_tuning(args.rows_per_lane, args.waves_per_simd)
     cpu = None
@@ -373,7 +428,7 @@ def run_short(args, torch, ffd, ctx, dev, stream):
         ", then the streaming kernel for the long pairs (kernel_ms covers both)" if args.mixed else "")
     return {
         "metric": "levenshtein_cells_per_second" if lev else METRIC,
-        "value": cells / sec, "ms_per_step": sec * 1e3, "dtype": "f32",
+        "value": cells / use, "ms_per_step": use * 1e3, "dtype": "f32", "timing": timing, "eager": eager,
         "config": {"workload": (f"short symbol sequences: {npairs} pairs, n and m uniform in [8, 64], int32 symbols "
                                 "uniform in [0, 4), Levenshtein (seed 12)") if lev else
                                (("short and long pairs: 262144 pairs with n and m uniform in [8, 64] and 800 with "
@@ -385,7 +440,8 @@ def run_short(args, torch, ffd, ctx, dev, stream):
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok, "launch_error_flags": ctx.last_errors(),
                    "streaming_kernel_bit_identical": same},
         "roofline": rl,
-        "streaming_kernel": {"cells_per_s": cells / ssec, "ms_per_step": ssec * 1e3, "kernel_ms": skms,
+        "streaming_kernel": {"cells_per_s": cells / suse, "ms_per_step": suse * 1e3, "kernel_ms": skms,
+                             "eager_ms_per_step": ssec * 1e3,
                              "frac": cells * imin(dim, cell="levenshtein" if lev else "euclidean") / (skms / 1e3) / PEAK_VALU,
                              "launch": sinfo},
         "cpu_baseline": cpu,
@@ -1038,6 +1094,7 @@ def main():
             r["short_pairs"] = {"workload": sr["config"]["workload"], "cells_per_s": sr["value"],
                                 "ms_per_step": sr["ms_per_step"], "kernel_ms": sr["roofline"]["kernel_ms"],
                                 "frac": sr["roofline"]["frac"], "parity": sr["parity"],
+                                "eager_ms_per_step": sr["eager"]["ms_per_step"], "timing": sr["timing"]["timing"],
                                 "streaming_kernel_cells_per_s": sr["streaming_kernel"]["cells_per_s"]}
     elif args.workload == "cross":
         r = run_cross(args, torch, ffd, ctx, dev, stream)
@@ -1063,8 +1120,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": r["dtype"], "data": "synthetic",
     }
-    for k in ("config", "parity", "autotune", "serving", "short_pairs", "search", "roofline", "plain",
-              "streaming_kernel", "cpu_baseline"):
+    for k in ("timing", "eager", "config", "parity", "autotune", "serving", "short_pairs", "search", "roofline",
+              "plain", "streaming_kernel", "cpu_baseline"):
         if k in r:
             line[k] = r[k]
     if line.get("cpu_baseline"):
