@@ -769,6 +769,12 @@ WsLayout ws_layout(const Plan &pl, int64_t n0, int64_t n1, bool exact) {
 // With col_count > 0, the pairs are (query, database curve): p_off holds
 // the npairs / col_count queries, q_off the col_count database curves, pair
 // i * col_count + c.
+// Cells a lane sweeps for rows x cols: the rows two at a time, the columns
+// padded to the next multiple of kLaneColStep.
+int64_t lane_padded(int64_t rows, int64_t cols) {
+  return (rows + 1) / 2 * 2 * ((cols + ffd::kLaneColStep - 1) / ffd::kLaneColStep * ffd::kLaneColStep);
+}
+
 bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64_t npairs, int D, bool exact,
                  Plan &pl, double &cost, std::vector<int32_t> *rest = nullptr, int64_t col_count = 0) {
   // the Frechet distance on squared Euclidean, Manhattan or Chebyshev cells,
@@ -787,7 +793,17 @@ bool build_lanes(ffd_ctx *ctx, const int64_t *p_off, const int64_t *q_off, int64
   for (int64_t k = 0; k < npairs; ++k) {
     const int64_t i0 = col_count > 0 ? k / col_count : k, i1 = col_count > 0 ? k % col_count : k;
     const int64_t n = p_off[i0 + 1] - p_off[i0], m = q_off[i1 + 1] - q_off[i1];
-    const bool swap = n < m;  // the shorter curve holds the columns
+    // the shorter curve holds the columns.  Levenshtein: when both fit, the
+    // curve that leaves less padded work (rows go two at a time, columns to
+    // a multiple of kLaneColStep); the table's values are the same either
+    // way.  (Measured on 262,144 pairs of 8 ... 64: 3 % faster for
+    // Levenshtein, 6 % slower for the Frechet distance of 2-D float curves,
+    // whose longer column curve is a longer burst of loads before the sweep)
+    bool swap = n < m;
+    if (op == 8 && n <= cmax && m <= cmax) {
+      const int64_t keep = lane_padded(n, m), turn = lane_padded(m, n);
+      swap = turn < keep || (turn == keep && n < m);
+    }
     const int64_t cols = swap ? n : m, rows = swap ? m : n;
     if (cols > cmax) {
       if (!rest) return false;

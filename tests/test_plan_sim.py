@@ -229,6 +229,17 @@ def test_short_pairs_per_lane(planner):
     short = np.minimum(np.diff(p_off), np.diff(q_off))
     per = np.bincount((short - 1) // 8, minlength=8)
     assert sm["waves"] == sum(-(-int(c) // 64) for c in per)
+    # Levenshtein: the column curve is the one leaving less padded work
+    # (rows two at a time, columns to a multiple of 8), the shorter on a tie
+    sm = ffd.ffd_plan_describe(planner, ffd.FFD_OP_BATCH, p_off, q_off, 1, exact=True, levenshtein=True)[0]
+    n, m = np.diff(p_off), np.diff(q_off)
+    padded = lambda r, c: (r + 1) // 2 * 2 * ((c + 7) // 8 * 8)
+    turn, keep = padded(m, n), padded(n, m)
+    swap = (turn < keep) | ((turn == keep) & (n < m))
+    cols, rows = np.where(swap, n, m), np.where(swap, m, n)
+    assert np.sum(padded(rows, cols)) < np.sum(padded(np.maximum(n, m), np.minimum(n, m)))
+    assert sm["per_lane"] == 1 and sm["stream_steps"] == rows.max()
+    assert sm["waves"] == sum(-(-int(c) // 64) for c in np.bincount((cols - 1) // 8, minlength=8))
     # one long pair as well: it alone goes to the streaming kernel
     p2 = np.concatenate([p_off, [p_off[-1] + 500]])
     q2 = np.concatenate([q_off, [q_off[-1] + 500]])
