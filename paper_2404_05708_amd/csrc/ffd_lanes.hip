@@ -119,6 +119,10 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
   // the points of the rows, loaded kAhead row pairs before they are swept
   // (a lane's loads are gathers from its own curve)
   constexpr int kAhead = 4;
+  // where a slot's next points are loaded: after the row step's branch for
+  // the float kernels (measured 2-3 % faster on 262,144 short pairs), inside
+  // it for Levenshtein (3 % faster there: one int32 coordinate per point)
+  constexpr bool kLoadAfter = !LEV;
   C nxt[kAhead][2][D];
   auto load_pair = [&](int64_t i, C (&dst)[2][D]) {
 #pragma unroll
@@ -141,7 +145,7 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
           pa[c] = N::cvt(nxt[r][0][c]);
           pb[c] = N::cvt(nxt[r][1][c]);  // row i + 1, or row n - 1 again
         }
-        load_pair(i + 2 * kAhead, nxt[r]);
+        if constexpr (!kLoadAfter) load_pair(i + 2 * kAhead, nxt[r]);
         // M_{i-1,-1}: the corner above the first row (-inf for the Frechet
         // distance, 0 for DTW), +inf below it; Levenshtein: the ramp i
         V diag_a = LEV ? V(i) : (i == 0 ? (DTW ? V(0) : -N::inf()) : N::inf());
@@ -176,6 +180,11 @@ __device__ __forceinline__ void lane_pair(const LaneArgs &a, int64_t k) {
           row[j] = SUM ? (two ? vb : va) : vb;
         }
       }
+      // the next points into this slot, on every lane (the index is clamped
+      // to the curve): a load inside the branch above has to land before
+      // the branch ends, where its registers merge with the lanes that
+      // skipped it
+      if constexpr (kLoadAfter) load_pair(i + 2 * kAhead, nxt[r]);
     }
   }
   if constexpr (SUM) {
