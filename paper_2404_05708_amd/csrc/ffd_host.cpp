@@ -1111,8 +1111,10 @@ int run_plan(ffd_ctx *ctx, const Plan &pl, uint64_t gen, const void *X0, const i
       return fail(ctx, FFD_E_UNSUPPORTED,
                   "a launch recorded into a graph needs its plan in the workspace: make the same call on the same "
                   "workspace outside the capture just before");
-    e = ffd::clear_words((uint64_t *)(w + wl.flags), (int64_t)((wl.links - wl.flags) / sizeof(uint64_t)), st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "flag clearing launch");
+    if (!(pl.lanes && pl.jobs.empty())) {  // the per-lane kernel alone reads no flags
+      e = ffd::clear_words((uint64_t *)(w + wl.flags), (int64_t)((wl.links - wl.flags) / sizeof(uint64_t)), st);
+      if (e != hipSuccess) return hip_fail(ctx, e, "flag clearing launch");
+    }
   }
   if (pl.lanes) {
     // short pairs, one per lane: a launch per class of column count
