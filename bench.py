@@ -1071,7 +1071,10 @@ def main():
     if args.workload == "batched":
         r = run_batched(args, torch, ffd, ctx, dev, stream)
         if not args.no_serving:
-            # the latency half of the metric: p50/p99 at half the saturation rate
+            # the latency half of the metric: p50/p99 at half the saturation rate.  (Measured
+            # after the batched block's HIP graph replays, the saturation reads about 1,200
+            # requests/s, against 1,490 in a process that launches no graph (--workload
+            # serving); measuring it first instead slows the batched block's launches)
             info, srv, db, _, _, _ = serving_session(torch, ffd, ctx, dev, args.slots, args.sat_requests,
                                                      args.serving_warmup, args.requests, [0.5])
             srv.close()
