@@ -43,6 +43,18 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# HIP maps a process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by
+# default, round robin in creation order).  The serving block keeps its
+# launch slots' streams busy at once; with 4 queues two of them can land on
+# one queue and run one after the other, depending on the streams created
+# before (measured: saturation 1,200 requests/s after the batched block's
+# graph replays, 1,490 without them, 1,650 with 8 queues in either case; the
+# other blocks unchanged).  Raised to 8 where the environment sets fewer,
+# before the HIP runtime starts; the line records both.
+ENV_HW_QUEUES = os.environ.get("GPU_MAX_HW_QUEUES")
+if not (ENV_HW_QUEUES or "").isdigit() or int(ENV_HW_QUEUES) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+HW_QUEUES = {"gpu_max_hw_queues": os.environ["GPU_MAX_HW_QUEUES"], "environment": ENV_HW_QUEUES}
 sys.path.insert(0, ROOT)
 
 METRIC = "DP cells/s (batched vs plain, 1 GPU) at stated tol; p50/p99 latency at fixed QPS"
@@ -999,7 +1011,8 @@ def run_serving(args, torch, ffd, ctx, dev, stream):
         "config": {"workload": "serving: Poisson arrivals, each a query against a resident database of 10,000 "
                                "curves; lengths log-normal (median 300, sigma 1, clipped to [32, 8192]), 2-D "
                                "float32 random walks, Euclidean (seeds 5, 6, 7)",
-                   "requests": args.requests, "db_points": db_points, "global_batch": args.requests},
+                   "requests": args.requests, "db_points": db_points, "global_batch": args.requests,
+                   "hw_queues": HW_QUEUES},
         "parity": {"tolerance": TOL, "sampled_ok": parity_ok,
                    "failed_requests": sum(r["failed"] for r in info["runs"])},
         "serving": info,
@@ -1071,10 +1084,7 @@ def main():
     if args.workload == "batched":
         r = run_batched(args, torch, ffd, ctx, dev, stream)
         if not args.no_serving:
-            # the latency half of the metric: p50/p99 at half the saturation rate.  (Measured
-            # after the batched block's HIP graph replays, the saturation reads about 1,200
-            # requests/s, against 1,490 in a process that launches no graph (--workload
-            # serving); measuring it first instead slows the batched block's launches)
+            # the latency half of the metric: p50/p99 at half the saturation rate
             info, srv, db, _, _, _ = serving_session(torch, ffd, ctx, dev, args.slots, args.sat_requests,
                                                      args.serving_warmup, args.requests, [0.5])
             srv.close()
@@ -1082,6 +1092,7 @@ def main():
             run = info["runs"][0]
             r["serving"] = {"workload": "10,000-curve resident database, log-normal query lengths (median 300, "
                                         "sigma 1, [32, 8192]), Poisson arrivals at half the saturation rate",
+                            "hw_queues": HW_QUEUES,
                             "saturation_qps": info["saturation_qps"],
                             "saturation_cells_per_s": info["saturation_cells_per_s"],
                             "qps": run["qps_achieved"], "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"],
