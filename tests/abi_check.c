@@ -78,6 +78,13 @@ int main(void) {
   printf("{\"strerror\": \"%s\"}\n", ffd_strerror(FFD_E_NOMEM));
   rc = ffd_set_tuning(ctx, 3, 0);
   printf("{\"bad_tuning_status\": %d}\n", rc);
+  /* kernel timing: a planning-only context launches nothing to time */
+  double ms = -1;
+  int64_t launches = -1;
+  int rc_on = ffd_set_kernel_timing(ctx, 1);
+  rc = ffd_kernel_time(ctx, &ms, &launches);
+  printf("{\"timing_on_status\": %d, \"kernel_time_status\": %d, \"ms\": %.1f, \"launches\": %lld}\n", rc_on, rc,
+         ms, (long long)launches);
   free(jobs);
   free(wave_jobs);
   ffd_destroy(ctx);

@@ -85,3 +85,5 @@ def test_status_codes_through_c(c_output):
     text = next(r["strerror"] for r in c_output if "strerror" in r)
     assert text == ffd.lib.ffd_strerror(ffd.FFD_E_NOMEM).decode()
     assert next(r["bad_tuning_status"] for r in c_output if "bad_tuning_status" in r) == ffd.FFD_E_INVALID
+    t = next(r for r in c_output if "timing_on_status" in r)
+    assert t == {"timing_on_status": ffd.FFD_E_INVALID, "kernel_time_status": ffd.FFD_OK, "ms": 0.0, "launches": 0}
