@@ -22,7 +22,7 @@ def _gpu_available():
 
 @pytest.fixture(scope="session")
 def gpu():
-    """Skip-free gate: GPU tests must run on a GPU machine; fail loudly otherwise."""
+    """Skip-free gate: GPU tests must run where a GPU is visible; fail loudly otherwise."""
     if not _gpu_available():
         pytest.fail("GPU test selected but no GPU is visible")
     import torch
